@@ -1,0 +1,155 @@
+"""FP64 CPU oracle for parallel-beam filtered backprojection.
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only callers.  The HIP library never imports,
+links or executes anything here, and nothing here imports the library.
+
+The arithmetic lives in ``fbp_oracle.c`` (plain FP64 C, OpenMP over output
+rows); this module compiles it with gcc when the shared object is missing or
+older than the source, and wraps it for NumPy arrays.  See the header of
+``fbp_oracle.c`` for the definitions and the readings of the paper
+(arXiv 2109.02174, section "Computed tomography", Eq. 2 and the filtered
+projection Q = P * H).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fbp_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile ``fbp_oracle.c`` into ``liboracle.so`` with gcc (-O2, OpenMP)."""
+    stale = (not os.path.exists(_LIB)) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)
+    if force or stale:
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
+               "-shared", "-std=c11", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def load_library(path: str):
+    """Open an oracle shared object and declare its C signatures."""
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_filter.argtypes = [dp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, dp]
+    lib.oracle_backproject.argtypes = [dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_double, dp, dp]
+    lib.oracle_fbp.argtypes = lib.oracle_backproject.argtypes
+    lib.oracle_forward_splat.argtypes = lib.oracle_backproject.argtypes
+    for fn in (lib.oracle_filter, lib.oracle_backproject, lib.oracle_fbp,
+               lib.oracle_forward_splat):
+        fn.restype = ctypes.c_int
+    lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_num_threads.restype = None
+    return lib
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            _lib = load_library(_LIB)
+        return _lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle uses."""
+    return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    _load().oracle_set_num_threads(int(n))
+
+
+def ramlak_filter(P, dt: float) -> np.ndarray:
+    """Ram-Lak filtered rows ``Q[..., n] = dt * sum_m h(n-m) P[..., m]`` (last axis = bins)."""
+    P = _f64(P)
+    D = P.shape[-1]
+    rows = int(np.prod(P.shape[:-1])) if P.ndim > 1 else 1
+    Q = np.empty_like(P)
+    rc = _load().oracle_filter(_ptr(P), rows, D, float(dt), _ptr(Q))
+    if rc != 0:
+        raise ValueError("oracle_filter rejected its arguments")
+    return Q
+
+
+def _geom(arr: np.ndarray, angles):
+    ang = _f64(angles).reshape(-1)
+    K = ang.shape[0]
+    return ang, K
+
+
+def backproject(Q, N: int, dt: float, angles) -> np.ndarray:
+    """Backprojection of filtered rows Q[B][K][D] (or [K][D]) onto N x N images."""
+    Q = _f64(Q)
+    squeeze = Q.ndim == 2
+    if squeeze:
+        Q = Q[None]
+    B, K, D = Q.shape
+    ang, Ka = _geom(Q, angles)
+    if Ka != K:
+        raise ValueError("angle count does not match the sinogram")
+    img = np.empty((B, N, N), dtype=np.float64)
+    rc = _load().oracle_backproject(_ptr(Q), B, K, D, int(N), float(dt), _ptr(ang), _ptr(img))
+    if rc != 0:
+        raise ValueError("oracle_backproject rejected its arguments")
+    return img[0] if squeeze else img
+
+
+def fbp(P, N: int, dt: float, angles) -> np.ndarray:
+    """Filter then backproject sinograms P[B][K][D] (or [K][D])."""
+    P = _f64(P)
+    squeeze = P.ndim == 2
+    if squeeze:
+        P = P[None]
+    B, K, D = P.shape
+    ang, Ka = _geom(P, angles)
+    if Ka != K:
+        raise ValueError("angle count does not match the sinogram")
+    img = np.empty((B, N, N), dtype=np.float64)
+    rc = _load().oracle_fbp(_ptr(P), B, K, D, int(N), float(dt), _ptr(ang), _ptr(img))
+    if rc != 0:
+        raise ValueError("oracle_fbp rejected its arguments")
+    return img[0] if squeeze else img
+
+
+def forward_splat(img, K: int, D: int, dt: float, angles) -> np.ndarray:
+    """Exact adjoint of :func:`backproject` (pixel-driven hat-function splat)."""
+    img = _f64(img)
+    squeeze = img.ndim == 2
+    if squeeze:
+        img = img[None]
+    B, N, N2 = img.shape
+    if N != N2:
+        raise ValueError("image must be square")
+    ang, Ka = _geom(img, angles)
+    if Ka != K:
+        raise ValueError("angle count mismatch")
+    sino = np.empty((B, K, D), dtype=np.float64)
+    rc = _load().oracle_forward_splat(_ptr(img), B, int(K), int(D), N, float(dt), _ptr(ang),
+                                      _ptr(sino))
+    if rc != 0:
+        raise ValueError("oracle_forward_splat rejected its arguments")
+    return sino[0] if squeeze else sino

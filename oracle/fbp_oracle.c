@@ -1,0 +1,203 @@
+/*
+ * FP64 CPU oracle for 2D parallel-beam filtered backprojection.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this code.  It shares no code,
+ * header, table or constant generator with the HIP library: it is the plain
+ * definition of what that library computes, written out slowly and in
+ * double precision so that a reader can check it against the paper by eye.
+ *
+ * The paper (arXiv 2109.02174, section "Computed tomography") fixes:
+ *   - each ray as the line  x cos(theta) + y sin(theta) = t;
+ *   - the filtered projection  Q_theta(t) = P_theta(t) * H(t)  (a convolution
+ *     of every projection row with a filter kernel);
+ *   - the image as  f(x,y) = sum_i Q_theta_i( x cos(theta_i) + y sin(theta_i) )
+ *     (Eq. 2).
+ * It leaves the filter, the angular weight, the interpolation rule and the
+ * grid conventions open.  The readings taken here (listed in the design
+ * notes of the repository) are:
+ *   - H is the band-limited ramp of Ramachandran & Lakshminarayanan (the
+ *     "Ram-Lak" kernel, Kak & Slaney 1988, ch. 3):
+ *         h(0) = 1/(4 dt^2),  h(d) = 0 for even d != 0,
+ *         h(d) = -1/(pi^2 d^2 dt^2) for odd d,
+ *     applied as a linear (not circular) convolution over the D detector
+ *     bins with zero samples outside the detector, times the sample width dt;
+ *   - Eq. 2 is weighted by pi/K (K angles spread over [0, pi));
+ *   - Q_theta is evaluated between bins by linear interpolation, with the
+ *     filtered row extended by zeros beyond both ends (so the value ramps to
+ *     zero over the one bin past each end);
+ *   - detector bin j sits at t_j = (j - (D-1)/2) dt; pixel (r, c) of an N x N
+ *     image sits at x = c - (N-1)/2, y = r - (N-1)/2 (unit pixels), so image
+ *     rows follow y and columns follow x.
+ *
+ * Every function returns 0 on success and -1 on invalid arguments.  Loops sum
+ * in ascending index order.  Parallelism is OpenMP over independent output
+ * rows only, so each output value is computed by one thread and the result
+ * does not depend on the thread count.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static const double kPi = 3.14159265358979323846264338327950288;
+
+/* Ram-Lak kernel value h(d) for bin offset d and bin width dt. */
+static double ramlak(int64_t d, double dt) {
+    if (d == 0) return 1.0 / (4.0 * dt * dt);
+    if (d % 2 == 0) return 0.0;
+    double dd = (double)d;
+    return -1.0 / (kPi * kPi * dd * dd * dt * dt);
+}
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/*
+ * Filtered projections (the convolution Q = P * H of the section
+ * "Computed tomography"):
+ *     Q[row][n] = dt * sum_{m=0}^{D-1} h(n - m) * P[row][m],   n = 0..D-1.
+ * P and Q are [n_rows][D], row-major.  P and Q must not overlap.
+ */
+int oracle_filter(const double* P, int64_t n_rows, int32_t D, double dt, double* Q) {
+    if (!P || !Q || n_rows < 0 || D < 1 || !(dt > 0.0) || !isfinite(dt)) return -1;
+    int64_t row;
+#pragma omp parallel for schedule(static)
+    for (row = 0; row < n_rows; ++row) {
+        const double* p = P + row * (int64_t)D;
+        double* q = Q + row * (int64_t)D;
+        for (int32_t n = 0; n < D; ++n) {
+            double acc = 0.0;
+            for (int32_t m = 0; m < D; ++m) acc += ramlak((int64_t)n - m, dt) * p[m];
+            q[n] = dt * acc;
+        }
+    }
+    return 0;
+}
+
+/* Filtered row value at bin i, zero outside the detector. */
+static double qtilde(const double* q, int32_t D, int64_t i) {
+    return (i >= 0 && i < D) ? q[i] : 0.0;
+}
+
+/*
+ * Backprojection (Eq. 2 with weight pi/K and linear interpolation):
+ *     u = (x_c cos(theta_k) + y_r sin(theta_k)) / dt + (D-1)/2
+ *     i = floor(u), alpha = u - i
+ *     img[r][c] = (pi/K) * sum_k [ (1-alpha) Q~[k][i] + alpha Q~[k][i+1] ].
+ * Q is [n_slices][K][D], img is [n_slices][N][N], angles holds K radians.
+ */
+int oracle_backproject(const double* Q, int32_t n_slices, int32_t K, int32_t D, int32_t N,
+                       double dt, const double* angles, double* img) {
+    if (!Q || !img || !angles || n_slices < 0 || K < 1 || D < 1 || N < 1 || !(dt > 0.0) ||
+        !isfinite(dt))
+        return -1;
+    double* cs = (double*)malloc(sizeof(double) * 2 * (size_t)K);
+    if (!cs) return -1;
+    for (int32_t k = 0; k < K; ++k) {
+        cs[2 * k] = cos(angles[k]);
+        cs[2 * k + 1] = sin(angles[k]);
+    }
+    const double centre_det = 0.5 * (double)(D - 1);
+    const double centre_pix = 0.5 * (double)(N - 1);
+    const double weight = kPi / (double)K;
+    int64_t sr;
+    const int64_t n_rows = (int64_t)n_slices * N;
+#pragma omp parallel for schedule(static)
+    for (sr = 0; sr < n_rows; ++sr) {
+        const int64_t s = sr / N;
+        const int32_t r = (int32_t)(sr % N);
+        const double y = (double)r - centre_pix;
+        const double* qs = Q + s * (int64_t)K * D;
+        double* out = img + s * (int64_t)N * N + (int64_t)r * N;
+        for (int32_t c = 0; c < N; ++c) {
+            const double x = (double)c - centre_pix;
+            double acc = 0.0;
+            for (int32_t k = 0; k < K; ++k) {
+                const double u = (x * cs[2 * k] + y * cs[2 * k + 1]) / dt + centre_det;
+                const double fi = floor(u);
+                const double alpha = u - fi;
+                const int64_t i = (int64_t)fi;
+                const double* q = qs + (int64_t)k * D;
+                acc += (1.0 - alpha) * qtilde(q, D, i) + alpha * qtilde(q, D, i + 1);
+            }
+            out[c] = weight * acc;
+        }
+    }
+    free(cs);
+    return 0;
+}
+
+/*
+ * Whole reconstruction: filter every row, then backproject.  The filtered
+ * intermediate is allocated here.  P is [n_slices][K][D].
+ */
+int oracle_fbp(const double* P, int32_t n_slices, int32_t K, int32_t D, int32_t N, double dt,
+               const double* angles, double* img) {
+    if (!P || !img || !angles || n_slices < 0 || K < 1 || D < 1 || N < 1) return -1;
+    const size_t count = (size_t)n_slices * (size_t)K * (size_t)D;
+    double* Q = (double*)malloc(sizeof(double) * (count ? count : 1));
+    if (!Q) return -1;
+    int rc = oracle_filter(P, (int64_t)n_slices * K, D, dt, Q);
+    if (rc == 0) rc = oracle_backproject(Q, n_slices, K, D, N, dt, angles, img);
+    free(Q);
+    return rc;
+}
+
+/*
+ * Splat (pixel-driven forward) projector, written from its own definition as
+ * the exact adjoint of oracle_backproject, for the brute-force adjoint test:
+ *     sino[k][j] = (pi/K) * sum_{r,c} img[r][c] * max(0, 1 - |u_k(x_c, y_r) - j|)
+ * with u_k as in oracle_backproject.  Every detector bin j is visited for
+ * every pixel (O(N^2 K D)); it is meant for tiny grids.
+ * img is [n_slices][N][N], sino is [n_slices][K][D].
+ */
+int oracle_forward_splat(const double* img, int32_t n_slices, int32_t K, int32_t D, int32_t N,
+                         double dt, const double* angles, double* sino) {
+    if (!img || !sino || !angles || n_slices < 0 || K < 1 || D < 1 || N < 1 || !(dt > 0.0) ||
+        !isfinite(dt))
+        return -1;
+    const double centre_det = 0.5 * (double)(D - 1);
+    const double centre_pix = 0.5 * (double)(N - 1);
+    const double weight = kPi / (double)K;
+    int64_t sk;
+    const int64_t n_rows = (int64_t)n_slices * K;
+#pragma omp parallel for schedule(static)
+    for (sk = 0; sk < n_rows; ++sk) {
+        const int64_t s = sk / K;
+        const int32_t k = (int32_t)(sk % K);
+        const double ck = cos(angles[k]);
+        const double sn = sin(angles[k]);
+        const double* im = img + s * (int64_t)N * N;
+        double* row = sino + sk * (int64_t)D;
+        for (int32_t j = 0; j < D; ++j) {
+            double acc = 0.0;
+            for (int32_t r = 0; r < N; ++r) {
+                const double y = (double)r - centre_pix;
+                for (int32_t c = 0; c < N; ++c) {
+                    const double x = (double)c - centre_pix;
+                    const double u = (x * ck + y * sn) / dt + centre_det;
+                    const double w = 1.0 - fabs(u - (double)j);
+                    if (w > 0.0) acc += w * im[(int64_t)r * N + c];
+                }
+            }
+            row[j] = weight * acc;
+        }
+    }
+    return 0;
+}

@@ -1,0 +1,179 @@
+"""Seeded synthetic inputs: analytic sinograms of ellipse phantoms and test objects.
+
+This module is the one input generator shared by the tests, the benchmark and
+the serving demo.  It holds none of the reconstruction arithmetic (no filter,
+no backprojection): it only evaluates exact line integrals of simple objects
+along the rays  x cos(theta) + y sin(theta) = t  (arXiv 2109.02174, section
+"Computed tomography") and draws noise.
+
+Conventions (shared with the library and the oracle by specification only):
+  * detector bin j sits at t_j = (j - (D-1)/2) * dt, in pixel units;
+  * pixel (r, c) of an N x N image sits at x = c - (N-1)/2, y = r - (N-1)/2;
+  * ellipse parameters are drawn in normalised units (the image spans
+    [-1, 1]^2) and scaled by N/2 to pixel units.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+# Integer tags standing for the string seeds 'geom' and 'arr' of the workload recipes.
+SEED_TAG_GEOM = 0x67656F6D
+SEED_TAG_ARRIVALS = 0x617272
+
+
+def rng_for(*key: int) -> np.random.Generator:
+    """PCG64 generator seeded by SeedSequence(key), e.g. rng_for(config_id, slice_id)."""
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(k) for k in key])))
+
+
+def uniform_angles(K: int) -> np.ndarray:
+    """theta_k = k*pi/K, k = 0..K-1, in FP64."""
+    return np.arange(K, dtype=np.float64) * (math.pi / K)
+
+
+@dataclass(frozen=True)
+class Ellipse:
+    """One ellipse in normalised units: centre, semi-axes, rotation, density."""
+    cx: float
+    cy: float
+    a: float
+    b: float
+    phi: float
+    rho: float
+
+
+def draw_ellipses(rng: np.random.Generator, n: int) -> list:
+    """Draw n ellipses; per ellipse the draw order is cx, cy, a, b, phi, rho."""
+    out = []
+    for _ in range(n):
+        cx = rng.uniform(-0.7, 0.7)
+        cy = rng.uniform(-0.7, 0.7)
+        a = rng.uniform(0.05, 0.5)
+        b = rng.uniform(0.05, 0.5)
+        phi = rng.uniform(0.0, math.pi)
+        rho = rng.uniform(-0.5, 1.0)
+        out.append(Ellipse(cx, cy, a, b, phi, rho))
+    return out
+
+
+def detector_coords(D: int, dt: float) -> np.ndarray:
+    return (np.arange(D, dtype=np.float64) - 0.5 * (D - 1)) * dt
+
+
+def ellipse_sinogram(ellipses, N: int, D: int, dt: float, angles) -> np.ndarray:
+    """Exact parallel-beam projections [K][D] (pixel units) of a sum of ellipses.
+
+    For an ellipse with semi-axes A, B (pixels), rotation phi, centre (x0, y0)
+    and density rho, the line integral at (theta, t) is
+        2 rho A B sqrt(s^2 - tau^2) / s^2   for |tau| <= s, else 0,
+    with s^2 = A^2 cos^2(theta-phi) + B^2 sin^2(theta-phi) and
+    tau = t - x0 cos(theta) - y0 sin(theta)  (Kak & Slaney 1988, ch. 3).
+    """
+    ang = np.asarray(angles, dtype=np.float64).reshape(-1, 1)
+    t = detector_coords(D, dt).reshape(1, -1)
+    half = 0.5 * N
+    sino = np.zeros((ang.shape[0], D), dtype=np.float64)
+    ct, st = np.cos(ang), np.sin(ang)
+    for e in ellipses:
+        A, B = e.a * half, e.b * half
+        x0, y0 = e.cx * half, e.cy * half
+        s2 = (A * np.cos(ang - e.phi)) ** 2 + (B * np.sin(ang - e.phi)) ** 2
+        tau = t - x0 * ct - y0 * st
+        rad = s2 - tau * tau
+        inside = rad > 0.0
+        contrib = np.where(inside, 2.0 * e.rho * A * B * np.sqrt(np.where(inside, rad, 0.0)) / s2,
+                           0.0)
+        sino += contrib
+    return sino
+
+
+def rasterise(ellipses, N: int) -> np.ndarray:
+    """Pixel-centre point samples [N][N] of the phantom (rows = y, columns = x)."""
+    half = 0.5 * N
+    coord = np.arange(N, dtype=np.float64) - 0.5 * (N - 1)
+    x = coord.reshape(1, -1)
+    y = coord.reshape(-1, 1)
+    img = np.zeros((N, N), dtype=np.float64)
+    for e in ellipses:
+        A, B = e.a * half, e.b * half
+        dx, dy = x - e.cx * half, y - e.cy * half
+        u = dx * math.cos(e.phi) + dy * math.sin(e.phi)
+        v = -dx * math.sin(e.phi) + dy * math.cos(e.phi)
+        img += np.where((u / A) ** 2 + (v / B) ** 2 <= 1.0, e.rho, 0.0)
+    return img
+
+
+def gaussian_sinogram(sigma: float, D: int, dt: float, angles, x0: float = 0.0,
+                      y0: float = 0.0) -> np.ndarray:
+    """Projections of f = exp(-((x-x0)^2 + (y-y0)^2) / (2 sigma^2)) (peak 1, pixel units)."""
+    ang = np.asarray(angles, dtype=np.float64).reshape(-1, 1)
+    t = detector_coords(D, dt).reshape(1, -1)
+    tau = t - x0 * np.cos(ang) - y0 * np.sin(ang)
+    return math.sqrt(2.0 * math.pi) * sigma * np.exp(-tau * tau / (2.0 * sigma * sigma))
+
+
+def disk_sinogram(radius: float, rho: float, D: int, dt: float, angles, x0: float = 0.0,
+                  y0: float = 0.0) -> np.ndarray:
+    """Projections of a uniform disk: 2 rho sqrt(R^2 - tau^2) for |tau| <= R."""
+    ang = np.asarray(angles, dtype=np.float64).reshape(-1, 1)
+    t = detector_coords(D, dt).reshape(1, -1)
+    tau = t - x0 * np.cos(ang) - y0 * np.sin(ang)
+    rad = radius * radius - tau * tau
+    return np.where(rad > 0.0, 2.0 * rho * np.sqrt(np.maximum(rad, 0.0)), 0.0)
+
+
+def add_gaussian_noise(sino: np.ndarray, rng: np.random.Generator, rel_sigma: float) -> np.ndarray:
+    """i.i.d. N(0, (rel_sigma * max(sino))^2) on every bin."""
+    sigma = rel_sigma * float(np.max(sino))
+    return sino + rng.normal(0.0, sigma, size=sino.shape)
+
+
+def add_poisson_noise(sino: np.ndarray, rng: np.random.Generator, I0: float, N: int) -> np.ndarray:
+    """Photon-count noise on the Lambert-Beer model I = I0 exp(-mu d).
+
+    Line integrals are taken in normalised length units (image half-width 1):
+    counts n ~ Poisson(I0 exp(-p/(N/2))), n <- max(n, 1), and the noisy line
+    integral is -ln(n/I0) * (N/2) in pixel units.
+    """
+    half = 0.5 * N
+    lam = I0 * np.exp(-sino / half)
+    counts = np.maximum(rng.poisson(lam), 1).astype(np.float64)
+    return -np.log(counts / I0) * half
+
+
+@dataclass(frozen=True)
+class SliceInput:
+    sino: np.ndarray        # FP64 [K][D]
+    phantom: np.ndarray     # FP64 [N][N] pixel-centre raster
+    ellipses: tuple
+    N: int
+    K: int
+    D: int
+    dt: float
+    angles: np.ndarray
+
+    @property
+    def value_range(self) -> float:
+        """Phantom range R = max - min of the raster (1.0 if the raster is flat)."""
+        r = float(self.phantom.max() - self.phantom.min())
+        return r if r > 0 else 1.0
+
+
+def ellipse_slice(config_id: int, slice_id: int, N: int, K: int, D: int, dt: float = 1.0,
+                  n_ellipses: int = 20, noise: str | None = None, angles=None,
+                  gauss_rel_sigma: float = 0.01, I0: float = 1e5) -> SliceInput:
+    """One seeded ellipse-phantom slice: ellipses first, then noise, from one generator."""
+    rng = rng_for(config_id, slice_id)
+    ells = draw_ellipses(rng, n_ellipses)
+    ang = uniform_angles(K) if angles is None else np.asarray(angles, dtype=np.float64)
+    sino = ellipse_sinogram(ells, N, D, dt, ang)
+    if noise == "gauss":
+        sino = add_gaussian_noise(sino, rng, gauss_rel_sigma)
+    elif noise == "poisson":
+        sino = add_poisson_noise(sino, rng, I0, N)
+    elif noise is not None:
+        raise ValueError(f"unknown noise model {noise!r}")
+    return SliceInput(sino, rasterise(ells, N), tuple(ells), N, K, D, dt, ang)

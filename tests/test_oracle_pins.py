@@ -1,0 +1,315 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Nothing here retypes the oracle's formulas: each check compares the oracle
+with a closed form, a library routine or a second, differently written
+definition, chosen so that a dropped term, a wrong sign or index, a swapped
+axis or a transposed operand fails at least one of them.
+
+Paper: arXiv 2109.02174, section "Computed tomography" (ray equation
+x cos(theta) + y sin(theta) = t, filtered projection Q = P * H, Eq. 2) and
+section "Benchmark" (PSNR, Eq. 3).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.signal import fftconvolve
+from scipy.special import polygamma
+
+import oracle
+from paper_2109_02174_amd import metrics
+from paper_2109_02174_amd import phantom as ph
+
+
+# ---------------------------------------------------------------- filter (Q = P * H)
+
+def _impulse_response(D, dt):
+    """Oracle response to a unit impulse in the middle of an odd-length detector."""
+    P = np.zeros(D)
+    P[D // 2] = 1.0
+    return oracle.ramlak_filter(P, dt)
+
+
+@pytest.mark.parametrize("dt", [1.0, 0.5, 2.0])
+def test_ramlak_frequency_response_is_ramp(dt):
+    """The impulse response's DTFT equals |w| / (2 pi dt) up to the series tail.
+
+    The Fourier series |w| = pi/2 - (4/pi) sum_{odd d} cos(d w)/d^2 on [-pi, pi]
+    makes the full Ram-Lak series exactly the ramp; truncation at |d| <= M leaves
+    an error bounded by (2/(pi^2 dt)) sum_{odd d > M} 1/d^2, which equals
+    (2/(pi^2 dt)) psi'(M/2 + 1/2)/4 for even M and is attained at w = 0.
+    """
+    D = 2001
+    M = D // 2
+    q = _impulse_response(D, dt)
+    d = np.arange(D) - M
+    tail = polygamma(1, M / 2 + 0.5) / 4.0
+    bound = 2.0 / (math.pi ** 2 * dt) * tail
+    assert abs(q.sum() - bound) <= 1e-12 * max(1.0, 1.0 / dt)
+    w = np.linspace(-math.pi, math.pi, 257)
+    H = (q[None, :] * np.cos(w[:, None] * d[None, :])).sum(axis=1)
+    Hs = (q[None, :] * np.sin(w[:, None] * d[None, :])).sum(axis=1)
+    assert np.max(np.abs(Hs)) < 1e-13  # even (real, zero-phase) kernel
+    assert np.max(np.abs(H - np.abs(w) / (2 * math.pi * dt))) <= bound * (1 + 1e-9) + 1e-14
+    # at w = pi the ramp is 1/(2 dt): the taps are neither halved nor doubled
+    assert abs(H[-1] - 1.0 / (2 * dt)) <= bound * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("D,dt", [(257, 1.0), (100, 0.7)])
+def test_filter_is_linear_zero_padded_convolution(D, dt):
+    """Rows are filtered by one shift-invariant kernel with zeros past both detector ends.
+
+    The kernel is read off the oracle's impulse response on a detector of 2D-1 bins;
+    the comparison is scipy's FFT convolution (padded, so not circular).
+    """
+    rng = ph.rng_for(900, D)
+    P = rng.normal(size=(3, D))
+    Q = oracle.ramlak_filter(P, dt)
+    kern = _impulse_response(2 * D - 1, dt)
+    for row in range(3):
+        ref = fftconvolve(P[row], kern)[D - 1: 2 * D - 1]
+        assert np.max(np.abs(Q[row] - ref)) <= 1e-12 * np.max(np.abs(P[row])) * D
+
+
+def test_filter_is_symmetric_operator():
+    """<H p, q> = <p, H q> (the Ram-Lak kernel is even)."""
+    rng = ph.rng_for(901, 0)
+    p, q = rng.normal(size=(2, 313))
+    lhs = np.dot(oracle.ramlak_filter(p, 0.9), q)
+    rhs = np.dot(p, oracle.ramlak_filter(q, 0.9))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+# ---------------------------------------------------------------- whole reconstruction
+
+@pytest.mark.parametrize("sigma,dt,uniform", [(3.0, 1.0, True), (4.0, 0.75, True), (4.0, 1.0, False)])
+def test_gaussian_blob_centre_is_exact(sigma, dt, uniform):
+    """A centred Gaussian of peak 1 reconstructs to 1 at the centre pixel.
+
+    Odd N and odd D put the centre pixel on a bin for every angle, and for a
+    band-limited projection the discrete Ram-Lak sum equals the continuous
+    ramp filter, so the centre is 1 to rounding for any angle set.
+    """
+    K = 180
+    ang = ph.uniform_angles(K) if uniform else np.sort(ph.rng_for(902, 1).uniform(0, math.pi, K))
+    N, D = 65, 129
+    S = ph.gaussian_sinogram(sigma, D, dt, ang)
+    img = oracle.fbp(S, N, dt, ang)
+    assert abs(img[32, 32] - 1.0) < 1e-12
+
+
+def test_offcentre_gaussian_lands_on_its_pixel():
+    """Orientation: a blob at (x0, y0) peaks at column x0 + (N-1)/2, row y0 + (N-1)/2."""
+    K, N, D, sigma = 180, 65, 129, 3.0
+    ang = ph.uniform_angles(K)
+    x0, y0 = 10.0, -7.0
+    S = ph.gaussian_sinogram(sigma, D, 1.0, ang, x0=x0, y0=y0)
+    img = oracle.fbp(S, N, 1.0, ang)
+    r, c = np.unravel_index(np.argmax(img), img.shape)
+    assert (r, c) == (25, 42)
+    assert abs(img[r, c] - 1.0) < 0.02
+    # and the true image exp(-r^2/2s^2) is matched to the blur of linear interpolation
+    coord = np.arange(N) - 32.0
+    truth = np.exp(-((coord[None, :] - x0) ** 2 + (coord[:, None] - y0) ** 2) / (2 * sigma ** 2))
+    assert np.max(np.abs(img - truth)) < 0.03
+
+
+def test_uniform_disk_centre_converges_as_r_to_minus_3_halves():
+    """A centred disk of density rho: the centre value tends to rho with error ~ R^-3/2."""
+    errs = []
+    for R in (16, 32, 64, 128):
+        N, D = 2 * R + 33, 2 * R + 41
+        ang = ph.uniform_angles(4)
+        img = oracle.fbp(ph.disk_sinogram(R, 2.5, D, 1.0, ang), N, 1.0, ang)
+        c = (N - 1) // 2
+        e = img[c, c] / 2.5 - 1.0
+        assert -0.2 * R ** -1.5 < e < 0.0
+        errs.append(e)
+    ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    for q in ratios:
+        assert abs(q - 2 ** 1.5) < 0.1
+
+
+def test_uniform_disk_interior_is_flat():
+    """Away from the rim the reconstruction of a disk stays within 1% of its density."""
+    R, N, D, K = 40, 101, 145, 360
+    ang = ph.uniform_angles(K)
+    img = oracle.fbp(ph.disk_sinogram(R, 1.0, D, 1.0, ang), N, 1.0, ang)
+    coord = np.arange(N) - 50.0
+    rr = np.hypot(coord[None, :], coord[:, None])
+    assert np.max(np.abs(img[rr <= 0.8 * R] - 1.0)) < 0.01
+    assert np.max(np.abs(img[rr >= 1.25 * R])) < 0.02
+
+
+# ---------------------------------------------------------------- backprojection alone
+
+@pytest.mark.parametrize("theta", [0.0, math.pi / 2, 1.1])
+@pytest.mark.parametrize("dt", [1.0, 1.7])
+def test_single_angle_is_linear_interpolation(theta, dt):
+    """K = 1: every pixel takes pi * (filtered row linearly interpolated at its ray).
+
+    Reference: numpy.interp over the row padded with one zero bin at each end,
+    which is linear interpolation with the continuous zero extension.
+    """
+    N, D = 33, 31
+    rng = ph.rng_for(903, int(10 * theta + dt))
+    Q = rng.normal(size=(1, D))
+    img = oracle.backproject(Q, N, dt, [theta])
+    coord = np.arange(N) - (N - 1) / 2
+    x, y = coord[None, :], coord[:, None]
+    u = (x * math.cos(theta) + y * math.sin(theta)) / dt + (D - 1) / 2
+    ref = math.pi * np.interp(u, np.arange(-1, D + 1), np.concatenate([[0.0], Q[0], [0.0]]))
+    assert np.max(np.abs(img - ref)) < 1e-12
+    if theta == 0.0:
+        assert np.all(img == img[0:1, :])   # constant down each column (x follows columns)
+    if dt == 1.0 and theta == 0.0:
+        # odd N <= odd D with unit bins: every pixel centre sits exactly on a bin
+        n_small = 21
+        img_s = oracle.backproject(Q, n_small, dt, [theta])
+        off = (D - n_small) // 2
+        assert np.allclose(img_s[0], math.pi * Q[0, off:off + n_small], rtol=0, atol=1e-13)
+
+
+def test_rotation_by_90_degrees():
+    """Rotating the sinogram by half the angle set rotates the image by +90 degrees.
+
+    With theta_k = k pi / K and K even, the object f'(x, y) = f(y, -x) has
+    projections S'[k] = S[k - K/2] for k >= K/2 and S'[k][j] = S[k + K/2][D-1-j]
+    for k < K/2; its image is f'[r][c] = f[N-1-c][r].  A transposed image, a
+    flipped row axis or a sign error in sin(theta) breaks this.
+    """
+    K, N, D, dt = 64, 21, 35, 0.8
+    ang = ph.uniform_angles(K)
+    S = ph.rng_for(904, 0).normal(size=(K, D))
+    S2 = np.empty_like(S)
+    S2[K // 2:] = S[:K // 2]
+    S2[:K // 2] = S[K // 2:, ::-1]
+    f = oracle.fbp(S, N, dt, ang)
+    f2 = oracle.fbp(S2, N, dt, ang)
+    rot = np.empty_like(f)
+    for r in range(N):
+        for c in range(N):
+            rot[r, c] = f[N - 1 - c, r]
+    assert np.max(np.abs(f2 - rot)) < 1e-11 * np.max(np.abs(f))
+    assert np.max(np.abs(f2 - f.T)) > 1e-3 * np.max(np.abs(f))   # the check has teeth
+
+
+@pytest.mark.parametrize("dt", [0.8, 1.3])
+def test_backprojection_is_adjoint_of_splat_projector(dt):
+    """Dense brute force on a tiny grid: splat projector == transpose of backprojection.
+
+    The splat projector sums every pixel into every bin with the hat weight
+    max(0, 1 - |u - j|), a definition written separately from the gather
+    (floor, fraction, two taps, zero extension) of the backprojector.
+    dt = 0.8 sends corner rays past the detector ends.
+    """
+    N, K, D = 8, 6, 13
+    ang = ph.rng_for(905, 0).uniform(0, math.pi, K)
+    B = np.zeros((N * N, K * D))
+    for idx in range(K * D):
+        e = np.zeros(K * D)
+        e[idx] = 1.0
+        B[:, idx] = oracle.backproject(e.reshape(K, D), N, dt, ang).reshape(-1)
+    Rd = np.zeros((K * D, N * N))
+    for idx in range(N * N):
+        e = np.zeros(N * N)
+        e[idx] = 1.0
+        Rd[:, idx] = oracle.forward_splat(e.reshape(N, N), K, D, dt, ang).reshape(-1)
+    assert np.max(np.abs(Rd - B.T)) < 1e-13
+    rng = ph.rng_for(905, 1)
+    x, y = rng.normal(size=N * N), rng.normal(size=K * D)
+    lhs = np.dot(Rd @ x, y)
+    rhs = np.dot(x, B @ y)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+    # every pixel with its ray inside the detector spreads weight pi/K per angle
+    assert np.all(np.abs(B.sum(axis=1) - math.pi) < 1e-12) or dt < 1.0
+
+
+def test_batch_slices_are_independent():
+    """A stack reconstructs slice by slice: [B][K][D] equals B separate calls."""
+    K, N, D = 12, 9, 15
+    ang = ph.uniform_angles(K)
+    S = ph.rng_for(906, 0).normal(size=(3, K, D))
+    stack = oracle.fbp(S, N, 1.0, ang)
+    for b in range(3):
+        assert np.array_equal(stack[b], oracle.fbp(S[b], N, 1.0, ang))
+
+
+def test_oracle_rejects_bad_arguments():
+    with pytest.raises(ValueError):
+        oracle.ramlak_filter(np.zeros((2, 5)), 0.0)
+    with pytest.raises(ValueError):
+        oracle.backproject(np.zeros((2, 5)), 4, 1.0, [0.0, 1.0, 2.0])
+
+
+# ---------------------------------------------------------------- test data
+
+def test_ellipse_sinogram_matches_brute_force_line_integrals():
+    """Analytic ellipse projections agree with dense sampling along each ray."""
+    rng = ph.rng_for(907, 0)
+    ells = ph.draw_ellipses(rng, 3)
+    N, D, dt = 64, 91, 1.0
+    ang = rng.uniform(0, math.pi, 5)
+    S = ph.ellipse_sinogram(ells, N, D, dt, ang)
+    t = ph.detector_coords(D, dt)
+    s = np.linspace(-80.0, 80.0, 400001)
+    ds = s[1] - s[0]
+    half = N / 2
+    for k, th in enumerate(ang):
+        for j in rng.integers(0, D, size=6):
+            px = t[j] * math.cos(th) - s * math.sin(th)
+            py = t[j] * math.sin(th) + s * math.cos(th)
+            val = np.zeros_like(s)
+            for e in ells:
+                dx, dy = px - e.cx * half, py - e.cy * half
+                u = dx * math.cos(e.phi) + dy * math.sin(e.phi)
+                v = -dx * math.sin(e.phi) + dy * math.cos(e.phi)
+                val += np.where((u / (e.a * half)) ** 2 + (v / (e.b * half)) ** 2 <= 1, e.rho, 0.0)
+            assert abs(val.sum() * ds - S[k, j]) < 2e-3 * (1 + abs(S[k, j]))
+
+
+def test_ellipse_sinogram_conserves_mass():
+    """dt * sum_j p(theta, t_j) -> sum rho pi A B as dt -> 0 (ellipses inside the field of view).
+
+    The chord profile has square-root edges, so the sampled sum converges like dt^1.5.
+    """
+    ells = [ph.Ellipse(0.1, -0.2, 0.3, 0.15, 0.4, 0.8), ph.Ellipse(-0.3, 0.25, 0.2, 0.35, 2.0, -0.4)]
+    N = 128
+    ang = ph.uniform_angles(7)
+    mass = sum(e.rho * math.pi * (e.a * N / 2) * (e.b * N / 2) for e in ells)
+    errs = []
+    for dt in (0.5, 0.05):
+        D = int(200 / dt)
+        S = ph.ellipse_sinogram(ells, N, D, dt, ang)
+        errs.append(np.max(np.abs(dt * S.sum(axis=1) - mass)) / abs(mass))
+    assert errs[0] < 1e-2 and errs[1] < 5e-4 and errs[1] < errs[0] / 10
+
+
+def test_phantom_reconstruction_sanity():
+    """FBP of a noise-free phantom follows the raster 4+ pixels away from ellipse edges."""
+    ells = [ph.Ellipse(0.0, 0.0, 0.6, 0.45, 0.3, 1.0), ph.Ellipse(0.15, 0.1, 0.2, 0.12, 1.0, -0.5)]
+    N, K, D = 96, 180, 137
+    ang = ph.uniform_angles(K)
+    img = oracle.fbp(ph.ellipse_sinogram(ells, N, D, 1.0, ang), N, 1.0, ang)
+    ras = ph.rasterise(ells, N)
+    # distance to the nearest raster edge >= 3 px
+    edge = np.zeros_like(ras, dtype=bool)
+    edge[:-1, :] |= ras[:-1, :] != ras[1:, :]
+    edge[1:, :] |= ras[:-1, :] != ras[1:, :]
+    edge[:, :-1] |= ras[:, :-1] != ras[:, 1:]
+    edge[:, 1:] |= ras[:, :-1] != ras[:, 1:]
+    from scipy.ndimage import binary_dilation
+    near = binary_dilation(edge, iterations=4)
+    err = np.abs(img - ras)[~near]
+    assert np.median(err) < 0.01 and np.max(err) < 0.1   # ringing off edges decays slowly
+
+
+# ---------------------------------------------------------------- metrics (Eq. 3)
+
+def test_psnr_worked_values():
+    a = np.zeros((4, 4))
+    assert metrics.psnr(a, a, 1.0) == math.inf        # identical images: infinite PSNR
+    b = a + 1.0                                       # MSE = 1 with MAX = 255
+    assert abs(metrics.psnr(a, b, 255.0) - 20 * math.log10(255.0)) < 1e-12
+    assert abs(metrics.psnr(a, b, 255.0) - 48.13080360867910) < 1e-9
+    assert metrics.ssim(np.ones((16, 16)), np.ones((16, 16)), 1.0) == pytest.approx(1.0)
