@@ -1,0 +1,168 @@
+/*
+ * fbp.h - C ABI of the MI355X (gfx950) parallel-beam filtered backprojection library.
+ *
+ * The library reconstructs 2D slices from parallel-beam sinograms as in
+ * arXiv 2109.02174, section "Computed tomography": every projection row
+ * P_theta(t) is convolved with a filter kernel H to give Q_theta = P_theta * H,
+ * and the image is the sum over angles of Q_theta_i evaluated on each pixel's
+ * ray x cos(theta_i) + y sin(theta_i) = t (Eq. 2).
+ *
+ * Conventions (the paper leaves them open; these are the readings adopted):
+ *   - H is the Ram-Lak band-limited ramp: h(0) = 1/(4 dt^2), h(d) = 0 for even
+ *     d != 0, h(d) = -1/(pi^2 d^2 dt^2) for odd d, applied as a linear
+ *     convolution over the D bins (zeros beyond both ends), times dt.
+ *   - Eq. 2 is weighted by pi/K and evaluates Q between bins by linear
+ *     interpolation; beyond the detector Q is zero and the interpolation ramps
+ *     to it over one bin.
+ *   - Detector bin j sits at t_j = (j - (D-1)/2) * det_spacing.  Pixel (r, c)
+ *     of the N x N image sits at x = c - (N-1)/2, y = r - (N-1)/2 (unit pixel
+ *     pitch): rows follow y, columns follow x.  Angles are radians from +x.
+ *
+ * Layouts: all device arrays are row-major, contiguous, FP32 and 4-byte
+ * aligned.  A sinogram stack is [n_slices][n_angles][n_det]; an image stack is
+ * [n_slices][N][N].
+ *
+ * Ownership: the caller owns every device buffer and keeps it alive until the
+ * work queued on `hip_stream` has finished.  The library owns only per-geometry
+ * plan state (FP64 cos/sin tables, the filter kernel table, the tile choice),
+ * created on the first call for a geometry and kept until process exit.  Once a
+ * geometry's plan exists, fbp_filter, fbp_backproject, fbp_reconstruct and
+ * fbp_reconstruct_batch allocate no device memory.
+ *
+ * Errors: arguments are validated on the host before any HIP call; a rejected
+ * call has queued no work.  Launch failures are reported as FBP_EHIP.  Work is
+ * asynchronous on `hip_stream` (NULL = the null stream): faults during
+ * execution surface at the caller's next synchronisation.  No function aborts,
+ * throws or prints on the hot path.  All functions are thread-safe.
+ *
+ * Determinism: every output value is written once, by one GPU lane, with a
+ * summation order fixed by the geometry alone (no atomics).  Repeated calls,
+ * and a slice reconstructed alone or inside a batch, give bitwise-equal
+ * results.
+ */
+#ifndef FBP_H
+#define FBP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FBP_OK = 0,
+    FBP_EINVAL = -1,        /* invalid argument (null pointer, bad size, aliasing, misalignment) */
+    FBP_ENOMEM = -2,        /* plan creation could not allocate device or host memory */
+    FBP_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
+    FBP_EUNSUPPORTED = -4,  /* valid but outside the supported range (e.g. geometry too large) */
+    FBP_EWORKSPACE = -5     /* workspace missing or smaller than the *_workspace_bytes query */
+} fbp_status;
+
+/* Operand precision of the ramp-filter GEMM; accumulation is always FP32. */
+typedef enum {
+    FBP_PREC_FP32 = 0,
+    FBP_PREC_BF16 = 1,      /* sinogram rows and kernel taps rounded to bfloat16 (RNE) */
+    FBP_PREC_FP16 = 2       /* rounded to binary16 (RNE); taps pre-scaled by 2^s to stay normal */
+} fbp_precision;
+
+/* One parallel-beam geometry. */
+typedef struct {
+    int32_t n_angles;        /* K >= 1 */
+    int32_t n_det;           /* D >= 1 */
+    int32_t image_size;      /* N >= 1: the image is N x N */
+    double det_spacing;      /* dt > 0 and finite, in pixel units */
+    const double* angles;    /* host array of K finite radians; copied into the plan, never kept */
+} fbp_geom;
+
+/* One slice of a mixed batch. */
+typedef struct {
+    fbp_geom geom;
+    const float* sino;       /* device [K][D] */
+    float* image;            /* device [N][N] */
+} fbp_job;
+
+/*
+ * Ramp filter (the convolution Q = P * H, section "Computed tomography"):
+ *   d_filtered[b][k][n] = dt * sum_{m<D} h(n - m) * d_sino[b][k][m].
+ * Runs as a GEMM on the matrix cores: rows of the sinogram times the Toeplitz
+ * matrix of the kernel, operands in `precision`, FP32 accumulation.
+ * d_sino and d_filtered are [n_slices][K][D] and must not overlap.
+ * n_slices == 0 is a valid no-op.
+ */
+int fbp_filter(const fbp_geom* geom, int32_t n_slices, const float* d_sino, float* d_filtered,
+               int32_t precision, void* hip_stream);
+
+/*
+ * Backprojection (Eq. 2 with weight pi/K and linear interpolation):
+ *   d_image[b][r][c] = (pi/K) * sum_k Q~_k(u_k(x_c, y_r)),
+ *   u_k(x, y) = (x cos(theta_k) + y sin(theta_k)) / dt + (D-1)/2.
+ * d_filtered is [n_slices][K][D], d_image is [n_slices][N][N]; no overlap.
+ * Every image pixel is written.  With d_filtered = the raw sinogram this is
+ * the exact adjoint of the linear-interpolation (hat) projector.
+ */
+int fbp_backproject(const fbp_geom* geom, int32_t n_slices, const float* d_filtered,
+                    float* d_image, void* hip_stream);
+
+/*
+ * fbp_backproject(fbp_filter(d_sino)) with the filtered rows kept in the
+ * caller's workspace (at least fbp_workspace_bytes(geom, n_slices, precision)
+ * bytes of device memory, 256-byte aligned).  Bitwise equal to the two calls.
+ */
+int fbp_reconstruct(const fbp_geom* geom, int32_t n_slices, const float* d_sino, float* d_image,
+                    void* d_workspace, size_t workspace_bytes, int32_t precision,
+                    void* hip_stream);
+
+/* Workspace bytes fbp_reconstruct needs (0 on invalid arguments). */
+size_t fbp_workspace_bytes(const fbp_geom* geom, int32_t n_slices, int32_t precision);
+
+/*
+ * Mixed-size batch (one slice per job, geometries may all differ): grouped
+ * filter GEMMs and a persistent, cost-ordered backprojection launch per tile
+ * shape, replayed from a captured HIP graph.  Each job's image is bitwise equal
+ * to reconstructing that slice alone with fbp_reconstruct.  The workspace
+ * (fbp_batch_workspace_bytes) holds the filtered rows and the tile list; calls
+ * that share a workspace must be ordered on one stream.
+ */
+int fbp_reconstruct_batch(const fbp_job* jobs, int32_t n_jobs, void* d_workspace,
+                          size_t workspace_bytes, int32_t precision, void* hip_stream);
+
+/* Workspace bytes fbp_reconstruct_batch needs for these jobs (0 on invalid arguments). */
+size_t fbp_batch_workspace_bytes(const fbp_job* jobs, int32_t n_jobs, int32_t precision);
+
+/*
+ * Tile-shape autotuning for one geometry: times each compiled backprojection
+ * tile shape on synthetic data on `hip_stream` (allocates and frees scratch
+ * memory, synchronises the stream) and records the fastest for this geometry.
+ * Later plans of the geometry use it; a plan that already exists keeps its
+ * shape, so results never depend on when tuning ran relative to a call.
+ * `out_config` (may be NULL) receives the chosen tile id.
+ */
+int fbp_autotune(const fbp_geom* geom, void* hip_stream, int32_t* out_config);
+
+/* Tile id the plan of this geometry uses, or a negative fbp_status. */
+int fbp_plan_config(const fbp_geom* geom);
+
+/*
+ * fbp_backproject with an explicit tile id instead of the plan's (for tests and
+ * tuning).  Different tile ids may differ in the last bits (per-tile FP32
+ * coordinates); each is deterministic.
+ */
+int fbp_backproject_with_config(const fbp_geom* geom, int32_t n_slices, const float* d_filtered,
+                                float* d_image, int32_t config, void* hip_stream);
+
+/* Number of compiled backprojection tile shapes and a description of one. */
+int32_t fbp_num_tile_configs(void);
+const char* fbp_tile_config_name(int32_t id);
+
+/* Static text for a status code (never NULL). */
+const char* fbp_status_string(int status);
+
+/* Library version string. */
+const char* fbp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FBP_H */

@@ -1,0 +1,21 @@
+"""MI355X (gfx950) parallel-beam filtered backprojection.
+
+The reconstruction runs in libfbp.so (hand-written HIP kernels behind the C ABI
+of include/fbp.h); this package holds the thin ctypes binding with the same
+function names, the seeded synthetic-input generator, image metrics and the
+continuous-batching serving loop.
+"""
+from ._binding import (FBP_EHIP, FBP_EINVAL, FBP_ENOMEM, FBP_EUNSUPPORTED, FBP_EWORKSPACE, FBP_OK,
+                       FbpError, Geometry, alloc_workspace, fbp_autotune, fbp_backproject,
+                       fbp_backproject_with_config, fbp_batch_workspace_bytes, fbp_filter,
+                       fbp_num_tile_configs, fbp_plan_config, fbp_reconstruct,
+                       fbp_reconstruct_batch, fbp_status_string, fbp_tile_config_name, fbp_version,
+                       fbp_workspace_bytes, load)
+
+__all__ = [
+    "FBP_OK", "FBP_EINVAL", "FBP_ENOMEM", "FBP_EHIP", "FBP_EUNSUPPORTED", "FBP_EWORKSPACE",
+    "FbpError", "Geometry", "alloc_workspace", "fbp_autotune", "fbp_backproject",
+    "fbp_backproject_with_config", "fbp_batch_workspace_bytes", "fbp_filter",
+    "fbp_num_tile_configs", "fbp_plan_config", "fbp_reconstruct", "fbp_reconstruct_batch",
+    "fbp_status_string", "fbp_tile_config_name", "fbp_version", "fbp_workspace_bytes", "load",
+]

@@ -1,0 +1,272 @@
+"""ctypes binding of libfbp (include/fbp.h): argument marshalling only.
+
+Every function here has the name of the C entry point it wraps and does no
+arithmetic of the method: it checks tensor dtype/device/shape, passes device
+pointers and the current HIP stream, and raises FbpError on a nonzero status.
+All reconstruction work runs in the library's HIP kernels; there is no
+fallback of any kind when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfbp.so")
+
+FBP_OK = 0
+FBP_EINVAL = -1
+FBP_ENOMEM = -2
+FBP_EHIP = -3
+FBP_EUNSUPPORTED = -4
+FBP_EWORKSPACE = -5
+
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
+
+
+class FbpError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {fbp_status_string(status)} ({status})")
+        self.status = status
+
+
+class c_geom(ctypes.Structure):
+    _fields_ = [("n_angles", ctypes.c_int32), ("n_det", ctypes.c_int32),
+                ("image_size", ctypes.c_int32), ("det_spacing", ctypes.c_double),
+                ("angles", ctypes.POINTER(ctypes.c_double))]
+
+
+class c_job(ctypes.Structure):
+    _fields_ = [("geom", c_geom), ("sino", ctypes.c_void_p), ("image", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Open libfbp.so (built in-tree by __graft_entry__.build or paper_2109_02174_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libfbp.so is not built ({LIB_PATH}); run "
+                          "`python -m paper_2109_02174_amd.build` first")
+    lib = ctypes.CDLL(LIB_PATH)
+    G = ctypes.POINTER(c_geom)
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    sig = {
+        "fbp_filter": (ctypes.c_int, [G, i32, vp, vp, i32, vp]),
+        "fbp_backproject": (ctypes.c_int, [G, i32, vp, vp, vp]),
+        "fbp_reconstruct": (ctypes.c_int, [G, i32, vp, vp, vp, sz, i32, vp]),
+        "fbp_workspace_bytes": (sz, [G, i32, i32]),
+        "fbp_reconstruct_batch": (ctypes.c_int, [ctypes.POINTER(c_job), i32, vp, sz, i32, vp]),
+        "fbp_batch_workspace_bytes": (sz, [ctypes.POINTER(c_job), i32, i32]),
+        "fbp_autotune": (ctypes.c_int, [G, vp, ctypes.POINTER(i32)]),
+        "fbp_plan_config": (ctypes.c_int, [G]),
+        "fbp_backproject_with_config": (ctypes.c_int, [G, i32, vp, vp, i32, vp]),
+        "fbp_num_tile_configs": (i32, []),
+        "fbp_tile_config_name": (ctypes.c_char_p, [i32]),
+        "fbp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "fbp_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+@dataclass
+class Geometry:
+    """Parallel-beam geometry: K angles (radians), D bins of width dt, N x N image."""
+    n_angles: int
+    n_det: int
+    image_size: int
+    det_spacing: float = 1.0
+    angles: np.ndarray = field(default=None)
+
+    def __post_init__(self):
+        if self.angles is None:
+            self.angles = np.arange(self.n_angles, dtype=np.float64) * (np.pi / self.n_angles)
+        self.angles = np.ascontiguousarray(self.angles, dtype=np.float64)
+
+    def as_c(self) -> c_geom:
+        g = c_geom(int(self.n_angles), int(self.n_det), int(self.image_size), float(self.det_spacing),
+                   self.angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        g._keep = self.angles   # keep the host array alive with the struct
+        return g
+
+
+def _stream_ptr(stream=None) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _check_tensor(t, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 tensor on the GPU")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _prec(p) -> int:
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def _raise(rc, where):
+    if rc != FBP_OK:
+        raise FbpError(rc, where)
+
+
+def fbp_status_string(status: int) -> str:
+    return load().fbp_status_string(int(status)).decode()
+
+
+def fbp_version() -> str:
+    return load().fbp_version().decode()
+
+
+def fbp_num_tile_configs() -> int:
+    return int(load().fbp_num_tile_configs())
+
+
+def fbp_tile_config_name(i: int) -> str:
+    return load().fbp_tile_config_name(int(i)).decode()
+
+
+def fbp_workspace_bytes(geom: Geometry, n_slices: int, precision="fp32") -> int:
+    g = geom.as_c()
+    return int(load().fbp_workspace_bytes(ctypes.byref(g), int(n_slices), _prec(precision)))
+
+
+def _shapes(geom: Geometry, n: int):
+    return (n, geom.n_angles, geom.n_det), (n, geom.image_size, geom.image_size)
+
+
+def fbp_filter(geom: Geometry, sino, out=None, precision="fp32", stream=None):
+    """Ramp-filter every row of sino[B][K][D] (device, float32) into out."""
+    import torch
+    n = sino.shape[0]
+    sshape, _ = _shapes(geom, n)
+    _check_tensor(sino, sshape, "sino")
+    if out is None:
+        out = torch.empty_like(sino)
+    _check_tensor(out, sshape, "out")
+    g = geom.as_c()
+    rc = load().fbp_filter(ctypes.byref(g), n, sino.data_ptr(), out.data_ptr(), _prec(precision),
+                           _stream_ptr(stream))
+    _raise(rc, "fbp_filter")
+    return out
+
+
+def fbp_backproject(geom: Geometry, filtered, out=None, stream=None):
+    """Backproject filtered[B][K][D] onto out[B][N][N] (weight pi/K)."""
+    import torch
+    n = filtered.shape[0]
+    sshape, ishape = _shapes(geom, n)
+    _check_tensor(filtered, sshape, "filtered")
+    if out is None:
+        out = torch.empty(ishape, dtype=torch.float32, device=filtered.device)
+    _check_tensor(out, ishape, "out")
+    g = geom.as_c()
+    rc = load().fbp_backproject(ctypes.byref(g), n, filtered.data_ptr(), out.data_ptr(),
+                                _stream_ptr(stream))
+    _raise(rc, "fbp_backproject")
+    return out
+
+
+def fbp_backproject_with_config(geom: Geometry, filtered, config: int, out=None, stream=None):
+    import torch
+    n = filtered.shape[0]
+    sshape, ishape = _shapes(geom, n)
+    _check_tensor(filtered, sshape, "filtered")
+    if out is None:
+        out = torch.empty(ishape, dtype=torch.float32, device=filtered.device)
+    _check_tensor(out, ishape, "out")
+    g = geom.as_c()
+    rc = load().fbp_backproject_with_config(ctypes.byref(g), n, filtered.data_ptr(), out.data_ptr(),
+                                            int(config), _stream_ptr(stream))
+    _raise(rc, "fbp_backproject_with_config")
+    return out
+
+
+def alloc_workspace(nbytes: int, device=None):
+    """A 256-byte aligned device buffer of at least nbytes (torch allocations are aligned)."""
+    import torch
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device or "cuda")
+
+
+def fbp_reconstruct(geom: Geometry, sino, out=None, workspace=None, precision="fp32", stream=None):
+    """Filter + backproject sino[B][K][D] into out[B][N][N]."""
+    import torch
+    n = sino.shape[0]
+    sshape, ishape = _shapes(geom, n)
+    _check_tensor(sino, sshape, "sino")
+    if out is None:
+        out = torch.empty(ishape, dtype=torch.float32, device=sino.device)
+    _check_tensor(out, ishape, "out")
+    if workspace is None:
+        workspace = alloc_workspace(fbp_workspace_bytes(geom, n, precision), sino.device)
+    g = geom.as_c()
+    rc = load().fbp_reconstruct(ctypes.byref(g), n, sino.data_ptr(), out.data_ptr(),
+                                workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                _prec(precision), _stream_ptr(stream))
+    _raise(rc, "fbp_reconstruct")
+    return out
+
+
+def _jobs_array(jobs):
+    """jobs: sequence of (Geometry, sino[K][D] tensor, image[N][N] tensor)."""
+    arr = (c_job * max(len(jobs), 1))()
+    keep = []
+    for i, (geom, sino, img) in enumerate(jobs):
+        _check_tensor(sino, (geom.n_angles, geom.n_det), f"jobs[{i}].sino")
+        _check_tensor(img, (geom.image_size, geom.image_size), f"jobs[{i}].image")
+        g = geom.as_c()
+        keep.append(g)
+        arr[i].geom = g
+        arr[i].sino = sino.data_ptr()
+        arr[i].image = img.data_ptr()
+    return arr, keep
+
+
+def fbp_batch_workspace_bytes(jobs, precision="fp32") -> int:
+    arr, _keep = _jobs_array(jobs)
+    return int(load().fbp_batch_workspace_bytes(arr, len(jobs), _prec(precision)))
+
+
+def fbp_reconstruct_batch(jobs, workspace=None, precision="fp32", stream=None):
+    """Reconstruct a mixed list of (Geometry, sino, image) slices in one batch."""
+    arr, _keep = _jobs_array(jobs)
+    nbytes = int(load().fbp_batch_workspace_bytes(arr, len(jobs), _prec(precision)))
+    if workspace is None:
+        workspace = alloc_workspace(nbytes, jobs[0][1].device if jobs else None)
+    rc = load().fbp_reconstruct_batch(arr, len(jobs), workspace.data_ptr(),
+                                      workspace.numel() * workspace.element_size(), _prec(precision),
+                                      _stream_ptr(stream))
+    _raise(rc, "fbp_reconstruct_batch")
+    return workspace
+
+
+def fbp_autotune(geom: Geometry, stream=None) -> int:
+    g = geom.as_c()
+    out = ctypes.c_int32(-1)
+    rc = load().fbp_autotune(ctypes.byref(g), _stream_ptr(stream), ctypes.byref(out))
+    _raise(rc, "fbp_autotune")
+    return int(out.value)
+
+
+def fbp_plan_config(geom: Geometry) -> int:
+    g = geom.as_c()
+    rc = int(load().fbp_plan_config(ctypes.byref(g)))
+    if rc < 0:
+        raise FbpError(rc, "fbp_plan_config")
+    return rc

@@ -1,0 +1,100 @@
+// Internal types shared by the HIP kernels and the host runtime of libfbp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fbp {
+
+// ------------------------------------------------------------------ backprojection
+
+// Everything one slice's backprojection needs, as the kernels see it.
+struct BpJob {
+    const float* q;       // filtered rows [K][D]
+    float* img;           // image [N][N]
+    const double* cs;     // [K][2]: cos(theta_k)/dt, sin(theta_k)/dt in FP64
+    double half_pix;      // (N-1)/2
+    double centre_det;    // (D-1)/2
+    int32_t N, K, D;
+    int32_t WL;           // window length (bins) staged per angle for this job's tile shape
+    int32_t KB;           // angles staged per LDS block
+    int32_t tiles_x;      // tile columns of the half image
+    float scale;          // pi/K
+    int32_t pad;
+};
+static_assert(sizeof(BpJob) % 8 == 0, "BpJob layout");
+
+// Compile-time tile shapes of the backprojector.  256 lanes; lane t owns column
+// t % TW and P consecutive rows starting at (t / TW) * P, for its pixel and the
+// pixel's point reflection through the image centre.
+struct TileShape {
+    int32_t tw, p, th;
+    const char* name;
+};
+
+constexpr int kBpThreads = 256;
+constexpr int kNumTileConfigs = 5;
+constexpr int kMaxKB = 64;
+// Dynamic LDS budget of one backprojection workgroup (bytes).
+constexpr int kBpLdsBudget = 32 * 1024;
+
+const TileShape& tile_shape(int cfg);
+
+// Window length for a tile shape: bins covering every pixel centre of a TW x TH
+// tile at any angle, plus interpolation and rounding margin.  span_max is the
+// largest (TW-1)|cos|/dt + (TH-1)|sin|/dt over the angles.
+inline int window_length(double span_max) { return (int)span_max + 5; }
+
+// Backprojection of n_slices slices of one geometry (tile grid from blockIdx).
+hipError_t launch_bp_grid(int cfg, const BpJob& job, int n_slices, size_t q_stride,
+                          size_t img_stride, int tiles_per_slice, hipStream_t stream);
+
+// Persistent backprojection over a mixed list: tile index -> job by binary search in
+// tile_prefix (n_jobs + 1 entries, device); jobs and prefix live in device memory,
+// counts are read on the device (so a captured graph serves any batch).
+struct BpListArgs {
+    const BpJob* jobs;          // device [n_jobs]
+    const int32_t* job_index;   // device [n_sel]: jobs of this tile shape, cost-ordered
+    const int32_t* tile_prefix; // device [n_sel + 1]: exclusive prefix of tile counts
+    const int32_t* counts;      // device: counts[0] = n_sel
+};
+// `args` is a DEVICE pointer (the batch header in the workspace).
+hipError_t launch_bp_list(int cfg, const BpListArgs* args, int grid, size_t lds_bytes,
+                          hipStream_t stream);
+int bp_lds_bytes(int WL, int KB);
+int bp_occupancy(int cfg, size_t lds_bytes);   // resident workgroups per CU
+
+// ------------------------------------------------------------------ ramp filter GEMM
+
+enum Prec : int32_t { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
+
+// One ramp-filter GEMM problem: Q[R][D] = P[R][D] x T, T[m][n] = tap(n - m).
+struct GemmJob {
+    const float* p;       // [R][D]
+    float* q;             // [R][D]
+    const void* taps;     // tap(d) at index d + Dp, d in [-Dp, Dp); element type by precision
+    int32_t R, D, Dp;
+    float out_scale;      // undoes the FP16 tap pre-scale (1 otherwise)
+    int32_t tiles_n;      // ceil(D / 64)
+    int32_t pad[3];
+};
+static_assert(sizeof(GemmJob) % 8 == 0, "GemmJob layout");
+
+constexpr int kGemmBM = 64;
+constexpr int kGemmBN = 64;
+
+hipError_t launch_gemm_grid(int prec, const GemmJob& job, hipStream_t stream);
+
+struct GemmListArgs {
+    const GemmJob* jobs;        // device [n_jobs]
+    const int32_t* tile_prefix; // device [n_jobs + 1]
+    const int32_t* counts;      // device: counts[0] = n_jobs
+};
+// `args` is a DEVICE pointer (the batch header in the workspace).
+hipError_t launch_gemm_list(int prec, const GemmListArgs* args, int grid, size_t lds_bytes,
+                            hipStream_t stream);
+int gemm_lds_bytes(int prec, int Dp);
+int gemm_occupancy(int prec, size_t lds_bytes);
+
+}  // namespace fbp

@@ -1,0 +1,923 @@
+// Host runtime of libfbp: argument validation, per-geometry plans, launches,
+// the mixed-size batch path with captured HIP graphs, and tile autotuning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/fbp.h"
+#include "fbp_internal.hpp"
+
+namespace fbp {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr int32_t kMaxDet = 8192;
+constexpr int32_t kMaxImage = 16384;
+constexpr int32_t kMaxAngles = 1 << 16;
+
+// ------------------------------------------------------------------ validation
+
+bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    if (!a || !b || na == 0 || nb == 0) return false;
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+    return a0 < b0 + nb && b0 < a0 + na;
+}
+
+int check_geom(const fbp_geom* g) {
+    if (!g) return FBP_EINVAL;
+    if (g->n_angles < 1 || g->n_det < 1 || g->image_size < 1) return FBP_EINVAL;
+    if (!std::isfinite(g->det_spacing) || !(g->det_spacing > 0.0)) return FBP_EINVAL;
+    if (!g->angles) return FBP_EINVAL;
+    for (int32_t k = 0; k < g->n_angles; ++k)
+        if (!std::isfinite(g->angles[k])) return FBP_EINVAL;
+    if (g->n_det > kMaxDet || g->image_size > kMaxImage || g->n_angles > kMaxAngles)
+        return FBP_EUNSUPPORTED;
+    return FBP_OK;
+}
+
+int check_prec(int32_t p) { return (p == kFP32 || p == kBF16 || p == kFP16) ? FBP_OK : FBP_EINVAL; }
+
+size_t sino_bytes(const fbp_geom* g, int64_t n) {
+    return (size_t)n * (size_t)g->n_angles * (size_t)g->n_det * sizeof(float);
+}
+size_t image_bytes(const fbp_geom* g, int64_t n) {
+    return (size_t)n * (size_t)g->image_size * (size_t)g->image_size * sizeof(float);
+}
+
+int check_slices(const fbp_geom* g, int32_t n_slices) {
+    if (n_slices < 0) return FBP_EINVAL;
+    if ((int64_t)n_slices * g->n_angles > INT32_MAX) return FBP_EUNSUPPORTED;
+    return FBP_OK;
+}
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ------------------------------------------------------------------ plans
+
+struct GeomKey {
+    int device, K, D, N;
+    uint64_t dt_bits;
+    uint64_t angle_hash;
+    bool operator<(const GeomKey& o) const {
+        return std::tie(device, K, D, N, dt_bits, angle_hash) <
+               std::tie(o.device, o.K, o.D, o.N, o.dt_bits, o.angle_hash);
+    }
+};
+
+uint64_t hash_angles(const double* a, int32_t K) {
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the bytes
+    const unsigned char* p = reinterpret_cast<const unsigned char*>(a);
+    for (size_t i = 0; i < (size_t)K * sizeof(double); ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+GeomKey make_key(int device, const fbp_geom* g) {
+    GeomKey k;
+    k.device = device;
+    k.K = g->n_angles;
+    k.D = g->n_det;
+    k.N = g->image_size;
+    std::memcpy(&k.dt_bits, &g->det_spacing, 8);
+    k.angle_hash = hash_angles(g->angles, g->n_angles);
+    return k;
+}
+
+struct Plan {
+    int device = 0;
+    int K = 0, D = 0, N = 0;
+    double dt = 1.0;
+    std::vector<double> angles;
+    std::vector<double> cs;          // host copy of the device table
+    int Dp = 0;                      // D rounded up to the GEMM tile width
+    double* d_cs = nullptr;
+    void* d_taps[3] = {nullptr, nullptr, nullptr};
+    float out_scale[3] = {1.0f, 1.0f, 1.0f};
+    int cfg = 0;
+    int WL = 0, KB = 0;
+    int tiles_x = 0, tiles_y = 0;
+    std::mutex mu;
+};
+
+struct Registry {
+    std::mutex mu;
+    std::map<GeomKey, std::unique_ptr<Plan>> plans;
+    std::map<GeomKey, int> tuned;       // tile id chosen by fbp_autotune or the tune cache
+    bool tune_cache_loaded = false;
+};
+
+Registry& registry() {
+    static Registry* r = new Registry();  // never destroyed: plans live until process exit
+    return *r;
+}
+
+bool angles_equal(const Plan& p, const fbp_geom* g) {
+    return (int)p.angles.size() == g->n_angles &&
+           std::memcmp(p.angles.data(), g->angles, sizeof(double) * (size_t)g->n_angles) == 0 &&
+           p.dt == g->det_spacing;
+}
+
+double span_for(const TileShape& s, const std::vector<double>& cs) {
+    double span = 0.0;
+    for (size_t k = 0; k + 1 < cs.size(); k += 2)
+        span = std::max(span, (s.tw - 1) * std::fabs(cs[k]) + (s.th - 1) * std::fabs(cs[k + 1]));
+    return span;
+}
+
+// Tile shape, window length and angle block of a tile id for a geometry.
+bool shape_params(int cfg, const std::vector<double>& cs, int N, int* WL, int* KB, int* tx, int* ty) {
+    const TileShape& s = tile_shape(cfg);
+    const double span = span_for(s, cs);
+    if (!(span < 1e6)) return false;
+    *WL = window_length(span);
+    const int kb = (kBpLdsBudget / 16 - kMaxKB) / *WL;
+    if (kb < 1) return false;
+    *KB = std::min(kMaxKB, kb);
+    *tx = (N + s.tw - 1) / s.tw;
+    const int half_rows = (N + 1) / 2;
+    *ty = (half_rows + s.th - 1) / s.th;
+    return true;
+}
+
+int default_config(int N) {
+    // Enough tile pairs to give every CU work for a single slice.
+    if (N >= 1024) return 0;
+    if (N >= 384) return 1;
+    return 3;
+}
+
+std::string tune_cache_path() {
+    const char* p = std::getenv("FBP_TUNE_CACHE");
+    return p ? std::string(p) : std::string();
+}
+
+std::string arch_name(int device) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+void load_tune_cache_locked(Registry& R, int device) {
+    if (R.tune_cache_loaded) return;
+    R.tune_cache_loaded = true;
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    std::ifstream in(path);
+    if (!in) return;
+    const std::string arch = arch_name(device);
+    std::string line;
+    while (std::getline(in, line)) {
+        // one entry per line: arch K D N dt_bits angle_hash cfg
+        std::istringstream ss(line);
+        std::string a;
+        GeomKey k;
+        int cfg;
+        unsigned long long dtb, ah;
+        if (!(ss >> a >> k.K >> k.D >> k.N >> dtb >> ah >> cfg)) continue;
+        if (a != arch || cfg < 0 || cfg >= kNumTileConfigs) continue;
+        k.device = device;
+        k.dt_bits = dtb;
+        k.angle_hash = ah;
+        R.tuned[k] = cfg;
+    }
+}
+
+int env_forced_config() {
+    const char* f = std::getenv("FBP_FORCE_CONFIG");
+    if (!f || !*f) return -1;
+    const int c = std::atoi(f);
+    return (c >= 0 && c < kNumTileConfigs) ? c : -1;
+}
+
+// Look up or create the plan of a validated geometry on the current device.
+int get_plan(const fbp_geom* g, Plan** out) {
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return FBP_EHIP;
+    const GeomKey key = make_key(device, g);
+    Registry& R = registry();
+    std::lock_guard<std::mutex> lock(R.mu);
+    auto it = R.plans.find(key);
+    if (it != R.plans.end() && angles_equal(*it->second, g)) {
+        *out = it->second.get();
+        return FBP_OK;
+    }
+    if (it != R.plans.end()) return FBP_EUNSUPPORTED;  // 64-bit hash collision: refuse, never mix
+    load_tune_cache_locked(R, device);
+
+    auto p = std::make_unique<Plan>();
+    p->device = device;
+    p->K = g->n_angles;
+    p->D = g->n_det;
+    p->N = g->image_size;
+    p->dt = g->det_spacing;
+    p->angles.assign(g->angles, g->angles + g->n_angles);
+    p->cs.resize(2 * (size_t)p->K);
+    for (int k = 0; k < p->K; ++k) {
+        p->cs[2 * k] = std::cos(p->angles[k]) / p->dt;
+        p->cs[2 * k + 1] = std::sin(p->angles[k]) / p->dt;
+    }
+    p->Dp = (int)round_up((size_t)p->D, kGemmBN);
+    int cfg = env_forced_config();
+    if (cfg < 0) {
+        auto t = R.tuned.find(key);
+        cfg = (t != R.tuned.end()) ? t->second : default_config(p->N);
+    }
+    if (!shape_params(cfg, p->cs, p->N, &p->WL, &p->KB, &p->tiles_x, &p->tiles_y)) {
+        // fall back to the shape with the smallest window, else refuse
+        bool ok = false;
+        for (int c = kNumTileConfigs - 1; c >= 0 && !ok; --c)
+            if (shape_params(c, p->cs, p->N, &p->WL, &p->KB, &p->tiles_x, &p->tiles_y)) {
+                cfg = c;
+                ok = true;
+            }
+        if (!ok) return FBP_EUNSUPPORTED;
+    }
+    p->cfg = cfg;
+    if (hipMalloc(&p->d_cs, sizeof(double) * p->cs.size()) != hipSuccess) return FBP_ENOMEM;
+    if (hipMemcpy(p->d_cs, p->cs.data(), sizeof(double) * p->cs.size(), hipMemcpyHostToDevice) !=
+        hipSuccess) {
+        (void)hipFree(p->d_cs);
+        return FBP_EHIP;
+    }
+    *out = p.get();
+    R.plans[key] = std::move(p);
+    return FBP_OK;
+}
+
+// ------------------------------------------------------------------ filter taps
+
+uint16_t bf16_bits_rne(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+uint16_t f16_bits_rne(float x) {
+    _Float16 h = (_Float16)x;
+    uint16_t b;
+    std::memcpy(&b, &h, 2);
+    return b;
+}
+
+// tap(d) = dt h(d) for |d| <= D-1 (Ram-Lak), stored at index d + Dp, d in [-Dp, Dp).
+double ramlak_tap(int d, double dt) {
+    if (d == 0) return 1.0 / (4.0 * dt);
+    if (d % 2 == 0) return 0.0;
+    const double dd = (double)d;
+    return -1.0 / (kPi * kPi * dd * dd * dt);
+}
+
+int ensure_taps(Plan* p, int prec) {
+    std::lock_guard<std::mutex> lock(p->mu);
+    if (p->d_taps[prec]) return FBP_OK;
+    const int Dp = p->Dp, D = p->D;
+    std::vector<double> taps(2 * (size_t)Dp, 0.0);
+    for (int d = -(D - 1); d <= D - 1; ++d) taps[(size_t)(d + Dp)] = ramlak_tap(d, p->dt);
+    void* dev = nullptr;
+    size_t bytes = 0;
+    std::vector<float> f32;
+    std::vector<uint16_t> h16;
+    float out_scale = 1.0f;
+    if (prec == kFP32) {
+        f32.resize(taps.size());
+        for (size_t i = 0; i < taps.size(); ++i) f32[i] = (float)taps[i];
+        bytes = f32.size() * 4;
+    } else {
+        double scale = 1.0;
+        if (prec == kFP16) {
+            // Pre-scale by 2^s so the smallest nonzero tap is a normal binary16 number
+            // (>= 2^-14) while the largest stays below 2^15.
+            double tmax = 0.0, tmin = 1e300;
+            for (double v : taps)
+                if (v != 0.0) {
+                    tmax = std::max(tmax, std::fabs(v));
+                    tmin = std::min(tmin, std::fabs(v));
+                }
+            int s = 0;
+            if (tmax > 0.0) {
+                s = (int)std::ceil(-14.0 - std::log2(tmin));
+                s = std::min(s, (int)std::floor(15.0 - std::log2(tmax)));
+            }
+            scale = std::ldexp(1.0, s);
+            out_scale = (float)std::ldexp(1.0, -s);
+        }
+        h16.resize(taps.size());
+        for (size_t i = 0; i < taps.size(); ++i) {
+            const float v = (float)(taps[i] * scale);
+            h16[i] = (prec == kBF16) ? bf16_bits_rne(v) : f16_bits_rne(v);
+        }
+        bytes = h16.size() * 2;
+    }
+    if (hipMalloc(&dev, bytes) != hipSuccess) return FBP_ENOMEM;
+    const void* src = (prec == kFP32) ? (const void*)f32.data() : (const void*)h16.data();
+    if (hipMemcpy(dev, src, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(dev);
+        return FBP_EHIP;
+    }
+    p->out_scale[prec] = out_scale;
+    p->d_taps[prec] = dev;
+    return FBP_OK;
+}
+
+// ------------------------------------------------------------------ launch helpers
+
+GemmJob gemm_job(const Plan& p, int prec, const float* sino, float* filt, int rows) {
+    GemmJob j{};
+    j.p = sino;
+    j.q = filt;
+    j.taps = p.d_taps[prec];
+    j.R = rows;
+    j.D = p.D;
+    j.Dp = p.Dp;
+    j.out_scale = p.out_scale[prec];
+    j.tiles_n = (p.D + kGemmBN - 1) / kGemmBN;
+    return j;
+}
+
+BpJob bp_job(const Plan& p, const float* filt, float* img) {
+    BpJob j{};
+    j.q = filt;
+    j.img = img;
+    j.cs = p.d_cs;
+    j.half_pix = 0.5 * (double)(p.N - 1);
+    j.centre_det = 0.5 * (double)(p.D - 1);
+    j.N = p.N;
+    j.K = p.K;
+    j.D = p.D;
+    j.WL = p.WL;
+    j.KB = p.KB;
+    j.tiles_x = p.tiles_x;
+    j.scale = (float)(kPi / (double)p.K);
+    return j;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? FBP_OK : FBP_EHIP; }
+
+int run_filter(const Plan& p, int prec, int32_t n, const float* sino, float* filt, hipStream_t s) {
+    if (n == 0) return FBP_OK;
+    const GemmJob j = gemm_job(p, prec, sino, filt, n * p.K);
+    return hip_status(launch_gemm_grid(prec, j, s));
+}
+
+int run_backproject(const Plan& p, int32_t n, const float* filt, float* img, hipStream_t s, int cfg_override = -1,
+                    const BpJob* job_override = nullptr) {
+    if (n == 0) return FBP_OK;
+    const BpJob j = job_override ? *job_override : bp_job(p, filt, img);
+    const int cfg = cfg_override >= 0 ? cfg_override : p.cfg;
+    int tx = p.tiles_x, ty = p.tiles_y;
+    if (cfg_override >= 0) {
+        const TileShape& s2 = tile_shape(cfg);
+        tx = (p.N + s2.tw - 1) / s2.tw;
+        ty = ((p.N + 1) / 2 + s2.th - 1) / s2.th;
+    }
+    const int64_t grid = (int64_t)n * tx * ty;
+    if (grid > INT32_MAX) return FBP_EUNSUPPORTED;
+    return hip_status(launch_bp_grid(cfg, j, n, (size_t)p.K * p.D, (size_t)p.N * p.N, tx * ty, s));
+}
+
+// ------------------------------------------------------------------ batch path
+
+// Header at the start of a batch workspace.  The list kernels read their
+// arguments from here, so one captured graph per workspace serves every batch.
+struct BatchHeader {
+    GemmListArgs gemm;
+    BpListArgs bp[kNumTileConfigs];
+    int32_t counts[1 + kNumTileConfigs];
+};
+
+struct BatchLayout {
+    size_t gemm_jobs = 0, gemm_prefix = 0;
+    size_t bp_jobs = 0, bp_index = 0, bp_prefix = 0;
+    size_t desc_end = 0;          // end of the descriptor area (the uploaded bytes)
+    std::vector<size_t> q_off;    // per job: offset of its filtered rows
+    size_t total = 0;
+};
+
+BatchLayout batch_layout(const fbp_job* jobs, int32_t n) {
+    BatchLayout L;
+    size_t o = round_up(sizeof(BatchHeader), 256);
+    L.gemm_jobs = o;
+    o = round_up(o + sizeof(GemmJob) * (size_t)n, 256);
+    L.gemm_prefix = o;
+    o = round_up(o + sizeof(int32_t) * (size_t)(n + 1), 256);
+    L.bp_jobs = o;
+    o = round_up(o + sizeof(BpJob) * (size_t)n, 256);
+    L.bp_index = o;
+    o = round_up(o + sizeof(int32_t) * (size_t)n, 256);
+    L.bp_prefix = o;
+    o = round_up(o + sizeof(int32_t) * (size_t)(n + kNumTileConfigs), 256);
+    L.desc_end = o;
+    L.q_off.resize((size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        L.q_off[(size_t)i] = o;
+        o = round_up(o + sino_bytes(&jobs[i].geom, 1), 256);
+    }
+    L.total = o;
+    return L;
+}
+
+int check_jobs(const fbp_job* jobs, int32_t n) {
+    if (n < 0) return FBP_EINVAL;
+    if (n > 0 && !jobs) return FBP_EINVAL;
+    for (int32_t i = 0; i < n; ++i) {
+        const int rc = check_geom(&jobs[i].geom);
+        if (rc != FBP_OK) return rc;
+        if (!jobs[i].sino || !jobs[i].image) return FBP_EINVAL;
+        if (!aligned4(jobs[i].sino) || !aligned4(jobs[i].image)) return FBP_EINVAL;
+        if (overlaps(jobs[i].sino, sino_bytes(&jobs[i].geom, 1), jobs[i].image,
+                     image_bytes(&jobs[i].geom, 1)))
+            return FBP_EINVAL;
+    }
+    return FBP_OK;
+}
+
+// Pinned host staging buffers for descriptor uploads; one is reused once the copy
+// that last read it has completed on the device.
+struct Staging {
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    bool recorded = false;
+};
+
+struct GraphKey {
+    int device;
+    int prec;
+    uintptr_t ws;
+    uint32_t cfg_mask;
+    int gemm_lds;
+    int bp_lds;
+    bool operator<(const GraphKey& o) const {
+        return std::tie(device, prec, ws, cfg_mask, gemm_lds, bp_lds) <
+               std::tie(o.device, o.prec, o.ws, o.cfg_mask, o.gemm_lds, o.bp_lds);
+    }
+};
+
+struct BatchState {
+    std::mutex mu;
+    std::vector<std::unique_ptr<Staging>> staging;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    std::map<int, hipStream_t> capture_stream;   // per device, default priority
+    std::map<int, int> cu_count;
+};
+
+BatchState& batch_state() {
+    static BatchState* s = new BatchState();
+    return *s;
+}
+
+bool graphs_disabled() {
+    const char* e = std::getenv("FBP_DISABLE_GRAPHS");
+    return e && *e && *e != '0';
+}
+
+int cu_count(int device) {
+    BatchState& S = batch_state();
+    std::lock_guard<std::mutex> lock(S.mu);
+    auto it = S.cu_count.find(device);
+    if (it != S.cu_count.end()) return it->second;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n < 1)
+        n = 256;
+    S.cu_count[device] = n;
+    return n;
+}
+
+Staging* acquire_staging(size_t need) {
+    BatchState& S = batch_state();
+    std::lock_guard<std::mutex> lock(S.mu);
+    for (auto& st : S.staging) {
+        if (st->busy || st->cap < need) continue;
+        if (st->recorded && hipEventQuery(st->done) != hipSuccess) continue;
+        st->busy = true;
+        return st.get();
+    }
+    auto st = std::make_unique<Staging>();
+    st->cap = round_up(std::max(need, (size_t)65536), 65536);
+    if (hipHostMalloc(&st->host, st->cap, hipHostMallocDefault) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&st->done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(st->host);
+        return nullptr;
+    }
+    st->busy = true;
+    S.staging.push_back(std::move(st));
+    return S.staging.back().get();
+}
+
+void release_staging(Staging* st, bool recorded) {
+    BatchState& S = batch_state();
+    std::lock_guard<std::mutex> lock(S.mu);
+    st->recorded = recorded;
+    st->busy = false;
+}
+
+// The batch kernels: grouped GEMM over every job, then one persistent
+// backprojection launch per tile shape present, all reading the header at ws.
+hipError_t enqueue_batch_kernels(const GraphKey& key, int cus, hipStream_t s) {
+    const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(key.ws);
+    const int g_occ = gemm_occupancy(key.prec, (size_t)key.gemm_lds);
+    hipError_t e = launch_gemm_list(key.prec, &hdr->gemm, cus * g_occ, (size_t)key.gemm_lds, s);
+    if (e != hipSuccess) return e;
+    for (int c = 0; c < kNumTileConfigs; ++c) {
+        if (!(key.cfg_mask & (1u << c))) continue;
+        const int occ = bp_occupancy(c, (size_t)key.bp_lds);
+        e = launch_bp_list(c, &hdr->bp[c], cus * occ, (size_t)key.bp_lds, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int launch_batch(const GraphKey& key, int cus, hipStream_t s) {
+    if (graphs_disabled()) return hip_status(enqueue_batch_kernels(key, cus, s));
+    BatchState& S = batch_state();
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(S.mu);
+        auto it = S.graphs.find(key);
+        if (it != S.graphs.end()) exec = it->second;
+    }
+    if (!exec) {
+        hipStream_t cs = nullptr;
+        {
+            std::lock_guard<std::mutex> lock(S.mu);
+            auto it = S.capture_stream.find(key.device);
+            if (it == S.capture_stream.end()) {
+                if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return FBP_EHIP;
+                S.capture_stream[key.device] = cs;
+            } else {
+                cs = it->second;
+            }
+        }
+        std::lock_guard<std::mutex> lock(S.mu);   // one capture at a time on the shared stream
+        auto it = S.graphs.find(key);
+        if (it != S.graphs.end()) {
+            exec = it->second;
+        } else {
+            hipGraph_t graph = nullptr;
+            if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return FBP_EHIP;
+            const hipError_t le = enqueue_batch_kernels(key, cus, cs);
+            const hipError_t ce = hipStreamEndCapture(cs, &graph);
+            if (le != hipSuccess || ce != hipSuccess || !graph) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return FBP_EHIP;
+            }
+            const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) return FBP_EHIP;
+            S.graphs[key] = exec;
+        }
+    }
+    return hip_status(hipGraphLaunch(exec, s));
+}
+
+int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes, int32_t prec,
+                      hipStream_t s) {
+    int rc = check_jobs(jobs, n);
+    if (rc == FBP_OK) rc = check_prec(prec);
+    if (rc != FBP_OK) return rc;
+    if (n == 0) return FBP_OK;
+    const BatchLayout L = batch_layout(jobs, n);
+    if (!ws || ws_bytes < L.total) return FBP_EWORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return FBP_EINVAL;
+    for (int32_t i = 0; i < n; ++i) {
+        if (overlaps(ws, L.total, jobs[i].sino, sino_bytes(&jobs[i].geom, 1)) ||
+            overlaps(ws, L.total, jobs[i].image, image_bytes(&jobs[i].geom, 1)))
+            return FBP_EINVAL;
+        for (int32_t j = 0; j < i; ++j)   // images must not overlap each other
+            if (overlaps(jobs[i].image, image_bytes(&jobs[i].geom, 1), jobs[j].image,
+                         image_bytes(&jobs[j].geom, 1)))
+                return FBP_EINVAL;
+    }
+    std::vector<Plan*> plans((size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        rc = get_plan(&jobs[i].geom, &plans[(size_t)i]);
+        if (rc == FBP_OK) rc = ensure_taps(plans[(size_t)i], prec);
+        if (rc != FBP_OK) return rc;
+    }
+    char* wsc = static_cast<char*>(ws);
+    std::vector<char> img(L.desc_end, 0);
+    BatchHeader* hdr = reinterpret_cast<BatchHeader*>(img.data());
+    GemmJob* gj = reinterpret_cast<GemmJob*>(img.data() + L.gemm_jobs);
+    int32_t* gp = reinterpret_cast<int32_t*>(img.data() + L.gemm_prefix);
+    BpJob* bj = reinterpret_cast<BpJob*>(img.data() + L.bp_jobs);
+    int32_t* bidx = reinterpret_cast<int32_t*>(img.data() + L.bp_index);
+    int32_t* bpre = reinterpret_cast<int32_t*>(img.data() + L.bp_prefix);
+
+    int max_dp = 0, max_bp_lds = 0;
+    uint32_t mask = 0;
+    int64_t gemm_tiles = 0;
+    gp[0] = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const Plan& p = *plans[(size_t)i];
+        float* q = reinterpret_cast<float*>(wsc + L.q_off[(size_t)i]);
+        gj[i] = gemm_job(p, prec, jobs[i].sino, q, p.K);
+        gemm_tiles += (int64_t)((p.K + kGemmBM - 1) / kGemmBM) * gj[i].tiles_n;
+        if (gemm_tiles > INT32_MAX) return FBP_EUNSUPPORTED;
+        gp[i + 1] = (int32_t)gemm_tiles;
+        bj[i] = bp_job(p, q, jobs[i].image);
+        max_dp = std::max(max_dp, p.Dp);
+        max_bp_lds = std::max(max_bp_lds, bp_lds_bytes(p.WL, p.KB));
+        mask |= 1u << p.cfg;
+    }
+    // Per tile shape: jobs in descending cost order (angles x per-tile work), ties by index.
+    int idx_off = 0, pre_off = 0;
+    for (int c = 0; c < kNumTileConfigs; ++c) {
+        std::vector<int32_t> sel;
+        for (int32_t i = 0; i < n; ++i)
+            if (plans[(size_t)i]->cfg == c) sel.push_back(i);
+        std::stable_sort(sel.begin(), sel.end(), [&](int32_t a, int32_t b) {
+            const Plan& pa = *plans[(size_t)a];
+            const Plan& pb = *plans[(size_t)b];
+            return (int64_t)pa.K * (pa.WL + 8) > (int64_t)pb.K * (pb.WL + 8);
+        });
+        int64_t tiles = 0;
+        bpre[pre_off] = 0;
+        for (size_t j = 0; j < sel.size(); ++j) {
+            const Plan& p = *plans[(size_t)sel[j]];
+            bidx[idx_off + (int)j] = sel[j];
+            tiles += (int64_t)p.tiles_x * p.tiles_y;
+            if (tiles > INT32_MAX) return FBP_EUNSUPPORTED;
+            bpre[pre_off + (int)j + 1] = (int32_t)tiles;
+        }
+        BpListArgs& a = hdr->bp[c];
+        a.jobs = reinterpret_cast<const BpJob*>(wsc + L.bp_jobs);
+        a.job_index = reinterpret_cast<const int32_t*>(wsc + L.bp_index) + idx_off;
+        a.tile_prefix = reinterpret_cast<const int32_t*>(wsc + L.bp_prefix) + pre_off;
+        a.counts = reinterpret_cast<const int32_t*>(wsc + offsetof(BatchHeader, counts)) + 1 + c;
+        hdr->counts[1 + c] = (int32_t)sel.size();
+        idx_off += (int)sel.size();
+        pre_off += (int)sel.size() + 1;
+    }
+    hdr->gemm.jobs = reinterpret_cast<const GemmJob*>(wsc + L.gemm_jobs);
+    hdr->gemm.tile_prefix = reinterpret_cast<const int32_t*>(wsc + L.gemm_prefix);
+    hdr->gemm.counts = reinterpret_cast<const int32_t*>(wsc + offsetof(BatchHeader, counts));
+    hdr->counts[0] = n;
+
+    Staging* st = acquire_staging(L.desc_end);
+    if (!st) return FBP_ENOMEM;
+    std::memcpy(st->host, img.data(), L.desc_end);
+    hipError_t e = hipMemcpyAsync(ws, st->host, L.desc_end, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(st->done, s);
+    release_staging(st, e == hipSuccess);
+    if (e != hipSuccess) return FBP_EHIP;
+
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return FBP_EHIP;
+    GraphKey key;
+    key.device = device;
+    key.prec = prec;
+    key.ws = reinterpret_cast<uintptr_t>(ws);
+    key.cfg_mask = mask;
+    key.gemm_lds = (int)round_up((size_t)gemm_lds_bytes(prec, max_dp), 8192);
+    key.bp_lds = (int)round_up((size_t)max_bp_lds, 4096);
+    return launch_batch(key, cu_count(device), s);
+}
+
+// ------------------------------------------------------------------ autotuning
+
+int autotune(const fbp_geom* g, hipStream_t s, int32_t* out_cfg) {
+    int rc = check_geom(g);
+    if (rc != FBP_OK) return rc;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return FBP_EHIP;
+    std::vector<double> cs(2 * (size_t)g->n_angles);
+    for (int k = 0; k < g->n_angles; ++k) {
+        cs[2 * k] = std::cos(g->angles[k]) / g->det_spacing;
+        cs[2 * k + 1] = std::sin(g->angles[k]) / g->det_spacing;
+    }
+    const size_t qb = sino_bytes(g, 1), ib = image_bytes(g, 1);
+    float *q = nullptr, *im = nullptr;
+    double* dcs = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int best = -1;
+    float best_ms = 0.0f;
+    rc = FBP_OK;
+    if (hipMalloc(&q, qb) != hipSuccess || hipMalloc(&im, ib) != hipSuccess ||
+        hipMalloc(&dcs, sizeof(double) * cs.size()) != hipSuccess) {
+        rc = FBP_ENOMEM;
+    } else if (hipMemcpy(dcs, cs.data(), sizeof(double) * cs.size(), hipMemcpyHostToDevice) != hipSuccess ||
+               hipMemsetAsync(q, 0, qb, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+               hipEventCreate(&e1) != hipSuccess) {
+        rc = FBP_EHIP;
+    } else {
+        Plan p;   // scratch plan for the timing runs
+        p.K = g->n_angles;
+        p.D = g->n_det;
+        p.N = g->image_size;
+        p.dt = g->det_spacing;
+        p.cs = cs;
+        p.d_cs = dcs;
+        for (int c = 0; c < kNumTileConfigs && rc == FBP_OK; ++c) {
+            if (!shape_params(c, cs, p.N, &p.WL, &p.KB, &p.tiles_x, &p.tiles_y)) continue;
+            p.cfg = c;
+            const BpJob job = bp_job(p, q, im);
+            float ms_min = 1e30f;
+            for (int rep = 0; rep < 7 && rc == FBP_OK; ++rep) {
+                if (hipEventRecord(e0, s) != hipSuccess) { rc = FBP_EHIP; break; }
+                rc = run_backproject(p, 1, q, im, s, -1, &job);
+                if (rc != FBP_OK) break;
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                    rc = FBP_EHIP;
+                    break;
+                }
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (rep >= 2) ms_min = std::min(ms_min, ms);   // first two runs warm up
+            }
+            if (rc == FBP_OK && (best < 0 || ms_min < best_ms)) {
+                best = c;
+                best_ms = ms_min;
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    if (q) (void)hipFree(q);
+    if (im) (void)hipFree(im);
+    if (dcs) (void)hipFree(dcs);
+    if (rc != FBP_OK) return rc;
+    if (best < 0) return FBP_EUNSUPPORTED;
+    {
+        Registry& R = registry();
+        std::lock_guard<std::mutex> lock(R.mu);
+        const GeomKey key = make_key(device, g);
+        R.tuned[key] = best;
+        const std::string path = tune_cache_path();
+        if (!path.empty()) {
+            std::ofstream out(path, std::ios::app);
+            if (out)
+                out << arch_name(device) << ' ' << key.K << ' ' << key.D << ' ' << key.N << ' '
+                    << (unsigned long long)key.dt_bits << ' ' << (unsigned long long)key.angle_hash << ' '
+                    << best << '\n';
+        }
+    }
+    if (out_cfg) *out_cfg = best;
+    return FBP_OK;
+}
+
+}  // namespace
+}  // namespace fbp
+
+// ====================================================================== C ABI
+
+using namespace fbp;
+
+extern "C" {
+
+const char* fbp_status_string(int status) {
+    switch (status) {
+        case FBP_OK: return "ok";
+        case FBP_EINVAL: return "invalid argument";
+        case FBP_ENOMEM: return "out of memory";
+        case FBP_EHIP: return "HIP runtime error";
+        case FBP_EUNSUPPORTED: return "unsupported geometry or size";
+        case FBP_EWORKSPACE: return "workspace missing or too small";
+        default: return "unknown status";
+    }
+}
+
+const char* fbp_version(void) { return "fbp-mi355x 0.1 (gfx950)"; }
+
+int32_t fbp_num_tile_configs(void) { return kNumTileConfigs; }
+
+const char* fbp_tile_config_name(int32_t id) {
+    if (id < 0 || id >= kNumTileConfigs) return "invalid tile id";
+    return tile_shape(id).name;
+}
+
+size_t fbp_workspace_bytes(const fbp_geom* geom, int32_t n_slices, int32_t precision) {
+    if (check_geom(geom) != FBP_OK || check_prec(precision) != FBP_OK ||
+        check_slices(geom, n_slices) != FBP_OK)
+        return 0;
+    return round_up(sino_bytes(geom, n_slices), 256);
+}
+
+size_t fbp_batch_workspace_bytes(const fbp_job* jobs, int32_t n_jobs, int32_t precision) {
+    if (check_prec(precision) != FBP_OK || n_jobs < 0 || (n_jobs > 0 && !jobs)) return 0;
+    for (int32_t i = 0; i < n_jobs; ++i)
+        if (check_geom(&jobs[i].geom) != FBP_OK) return 0;
+    return batch_layout(jobs, n_jobs).total;
+}
+
+int fbp_filter(const fbp_geom* geom, int32_t n_slices, const float* d_sino, float* d_filtered,
+               int32_t precision, void* hip_stream) {
+    int rc = check_geom(geom);
+    if (rc == FBP_OK) rc = check_prec(precision);
+    if (rc == FBP_OK) rc = check_slices(geom, n_slices);
+    if (rc != FBP_OK) return rc;
+    if (n_slices == 0) return FBP_OK;
+    if (!d_sino || !d_filtered || !aligned4(d_sino) || !aligned4(d_filtered)) return FBP_EINVAL;
+    const size_t nb = sino_bytes(geom, n_slices);
+    if (overlaps(d_sino, nb, d_filtered, nb)) return FBP_EINVAL;
+    Plan* p = nullptr;
+    rc = get_plan(geom, &p);
+    if (rc == FBP_OK) rc = ensure_taps(p, precision);
+    if (rc != FBP_OK) return rc;
+    return run_filter(*p, precision, n_slices, d_sino, d_filtered, (hipStream_t)hip_stream);
+}
+
+int fbp_backproject(const fbp_geom* geom, int32_t n_slices, const float* d_filtered, float* d_image,
+                    void* hip_stream) {
+    int rc = check_geom(geom);
+    if (rc == FBP_OK) rc = check_slices(geom, n_slices);
+    if (rc != FBP_OK) return rc;
+    if (n_slices == 0) return FBP_OK;
+    if (!d_filtered || !d_image || !aligned4(d_filtered) || !aligned4(d_image)) return FBP_EINVAL;
+    if (overlaps(d_filtered, sino_bytes(geom, n_slices), d_image, image_bytes(geom, n_slices)))
+        return FBP_EINVAL;
+    Plan* p = nullptr;
+    rc = get_plan(geom, &p);
+    if (rc != FBP_OK) return rc;
+    return run_backproject(*p, n_slices, d_filtered, d_image, (hipStream_t)hip_stream);
+}
+
+int fbp_reconstruct(const fbp_geom* geom, int32_t n_slices, const float* d_sino, float* d_image,
+                    void* d_workspace, size_t workspace_bytes, int32_t precision, void* hip_stream) {
+    int rc = check_geom(geom);
+    if (rc == FBP_OK) rc = check_prec(precision);
+    if (rc == FBP_OK) rc = check_slices(geom, n_slices);
+    if (rc != FBP_OK) return rc;
+    if (n_slices == 0) return FBP_OK;
+    if (!d_sino || !d_image || !aligned4(d_sino) || !aligned4(d_image)) return FBP_EINVAL;
+    const size_t sb = sino_bytes(geom, n_slices), ib = image_bytes(geom, n_slices);
+    if (overlaps(d_sino, sb, d_image, ib)) return FBP_EINVAL;
+    if (!d_workspace || workspace_bytes < sb) return FBP_EWORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(d_workspace) & 255u) != 0) return FBP_EINVAL;
+    if (overlaps(d_workspace, sb, d_sino, sb) || overlaps(d_workspace, sb, d_image, ib))
+        return FBP_EINVAL;
+    Plan* p = nullptr;
+    rc = get_plan(geom, &p);
+    if (rc == FBP_OK) rc = ensure_taps(p, precision);
+    if (rc != FBP_OK) return rc;
+    float* filt = static_cast<float*>(d_workspace);
+    const hipStream_t s = (hipStream_t)hip_stream;
+    rc = run_filter(*p, precision, n_slices, d_sino, filt, s);
+    if (rc == FBP_OK) rc = run_backproject(*p, n_slices, filt, d_image, s);
+    return rc;
+}
+
+int fbp_reconstruct_batch(const fbp_job* jobs, int32_t n_jobs, void* d_workspace,
+                          size_t workspace_bytes, int32_t precision, void* hip_stream) {
+    return reconstruct_batch(jobs, n_jobs, d_workspace, workspace_bytes, precision,
+                             (hipStream_t)hip_stream);
+}
+
+int fbp_autotune(const fbp_geom* geom, void* hip_stream, int32_t* out_config) {
+    return autotune(geom, (hipStream_t)hip_stream, out_config);
+}
+
+int fbp_plan_config(const fbp_geom* geom) {
+    const int rc = check_geom(geom);
+    if (rc != FBP_OK) return rc;
+    Plan* p = nullptr;
+    const int prc = get_plan(geom, &p);
+    return prc == FBP_OK ? p->cfg : prc;
+}
+
+int fbp_backproject_with_config(const fbp_geom* geom, int32_t n_slices, const float* d_filtered,
+                                float* d_image, int32_t config, void* hip_stream) {
+    int rc = check_geom(geom);
+    if (rc == FBP_OK) rc = check_slices(geom, n_slices);
+    if (rc != FBP_OK) return rc;
+    if (config < 0 || config >= kNumTileConfigs) return FBP_EINVAL;
+    if (n_slices == 0) return FBP_OK;
+    if (!d_filtered || !d_image || !aligned4(d_filtered) || !aligned4(d_image)) return FBP_EINVAL;
+    if (overlaps(d_filtered, sino_bytes(geom, n_slices), d_image, image_bytes(geom, n_slices)))
+        return FBP_EINVAL;
+    Plan* p = nullptr;
+    rc = get_plan(geom, &p);
+    if (rc != FBP_OK) return rc;
+    Plan q;   // same geometry, other tile shape
+    q.K = p->K;
+    q.D = p->D;
+    q.N = p->N;
+    q.dt = p->dt;
+    q.d_cs = p->d_cs;
+    if (!shape_params(config, p->cs, p->N, &q.WL, &q.KB, &q.tiles_x, &q.tiles_y)) return FBP_EUNSUPPORTED;
+    q.cfg = config;
+    const BpJob job = bp_job(q, d_filtered, d_image);
+    return run_backproject(q, n_slices, d_filtered, d_image, (hipStream_t)hip_stream, config, &job);
+}
+
+}  // extern "C"

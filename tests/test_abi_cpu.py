@@ -1,0 +1,169 @@
+"""Host-side checks of libfbp that need no GPU.
+
+The library loads and exports every function include/fbp.h declares, and its
+argument validation returns the documented status codes before any HIP call
+(so these run on a machine without a GPU).  Also static checks of the kernel
+sources: no atomics, no CUDA headers.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2109_02174_amd as fbp
+from paper_2109_02174_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fbp.h")
+CSRC = os.path.join(ROOT, "paper_2109_02174_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_2109_02174_amd import build
+        build.build()
+    return B.load()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fbp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_symbols_exported(lib):
+    names = _declared_functions()
+    assert "fbp_filter" in names and "fbp_backproject" in names and "fbp_reconstruct" in names
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in fbp.h but not exported"
+
+
+def test_status_strings(lib):
+    assert fbp.fbp_status_string(0) == "ok"
+    for code in (-1, -2, -3, -4, -5):
+        s = fbp.fbp_status_string(code)
+        assert s and s != "unknown status"
+    assert fbp.fbp_status_string(12345) == "unknown status"
+    assert "gfx950" in fbp.fbp_version()
+    n = fbp.fbp_num_tile_configs()
+    assert n >= 1
+    for i in range(n):
+        assert "tile" in fbp.fbp_tile_config_name(i)
+    assert fbp.fbp_tile_config_name(n) == "invalid tile id"
+
+
+def _geom(K=4, D=7, N=5, dt=1.0, angles=None):
+    g = fbp.Geometry(K, D, N, dt, angles)
+    return g, g.as_c()
+
+
+FAKE = 0x100000       # never dereferenced: validation fails before any use
+FAKE2 = 0x200000
+FAKE3 = 0x300000
+
+
+@pytest.mark.parametrize("K,D,N,dt", [(0, 7, 5, 1.0), (4, 0, 5, 1.0), (4, 7, 0, 1.0), (4, 7, 5, 0.0),
+                                      (4, 7, 5, -1.0), (4, 7, 5, float("nan")), (4, 7, 5, float("inf"))])
+def test_invalid_geometry_rejected(lib, K, D, N, dt):
+    g = B.c_geom(K, D, N, dt, (ctypes.c_double * max(K, 1))())
+    assert lib.fbp_filter(ctypes.byref(g), 1, FAKE, FAKE2, 0, None) == B.FBP_EINVAL
+    assert lib.fbp_backproject(ctypes.byref(g), 1, FAKE, FAKE2, None) == B.FBP_EINVAL
+    assert lib.fbp_reconstruct(ctypes.byref(g), 1, FAKE, FAKE2, FAKE3, 1 << 20, 0, None) == B.FBP_EINVAL
+    assert lib.fbp_workspace_bytes(ctypes.byref(g), 1, 0) == 0
+
+
+def test_null_and_nonfinite_angles_rejected(lib):
+    g = B.c_geom(4, 7, 5, 1.0, None)
+    assert lib.fbp_backproject(ctypes.byref(g), 1, FAKE, FAKE2, None) == B.FBP_EINVAL
+    ang = (ctypes.c_double * 4)(0.0, 1.0, float("nan"), 2.0)
+    g = B.c_geom(4, 7, 5, 1.0, ang)
+    assert lib.fbp_backproject(ctypes.byref(g), 1, FAKE, FAKE2, None) == B.FBP_EINVAL
+    assert lib.fbp_backproject(None, 1, FAKE, FAKE2, None) == B.FBP_EINVAL
+
+
+def test_oversized_geometry_is_unsupported(lib):
+    _, g = _geom(D=100000)
+    assert lib.fbp_backproject(ctypes.byref(g), 1, FAKE, FAKE2, None) == B.FBP_EUNSUPPORTED
+
+
+def test_pointer_checks(lib):
+    _, g = _geom()
+    gp = ctypes.byref(g)
+    assert lib.fbp_filter(gp, 1, None, FAKE2, 0, None) == B.FBP_EINVAL
+    assert lib.fbp_filter(gp, 1, FAKE, None, 0, None) == B.FBP_EINVAL
+    assert lib.fbp_filter(gp, 1, FAKE + 2, FAKE2, 0, None) == B.FBP_EINVAL       # misaligned
+    assert lib.fbp_filter(gp, 1, FAKE, FAKE + 8, 0, None) == B.FBP_EINVAL         # overlap
+    assert lib.fbp_filter(gp, 1, FAKE, FAKE2, 7, None) == B.FBP_EINVAL            # precision
+    assert lib.fbp_filter(gp, -1, FAKE, FAKE2, 0, None) == B.FBP_EINVAL
+    assert lib.fbp_backproject(gp, 1, FAKE, FAKE + 4, None) == B.FBP_EINVAL      # overlap
+    assert lib.fbp_backproject(gp, 1, FAKE, FAKE2 + 1, None) == B.FBP_EINVAL
+    # empty calls are valid no-ops that touch nothing
+    assert lib.fbp_filter(gp, 0, None, None, 0, None) == B.FBP_OK
+    assert lib.fbp_backproject(gp, 0, None, None, None) == B.FBP_OK
+    assert lib.fbp_reconstruct(gp, 0, None, None, None, 0, 0, None) == B.FBP_OK
+
+
+def test_workspace_checks(lib):
+    _, g = _geom(K=4, D=7, N=5)
+    gp = ctypes.byref(g)
+    need = lib.fbp_workspace_bytes(gp, 3, 0)
+    assert need >= 3 * 4 * 7 * 4 and need % 256 == 0
+    assert lib.fbp_reconstruct(gp, 3, FAKE, FAKE2, None, need, 0, None) == B.FBP_EWORKSPACE
+    assert lib.fbp_reconstruct(gp, 3, FAKE, FAKE2, FAKE3, need - 256, 0, None) == B.FBP_EWORKSPACE
+    assert lib.fbp_reconstruct(gp, 3, FAKE, FAKE2, FAKE3 + 16, need, 0, None) == B.FBP_EINVAL
+    assert lib.fbp_reconstruct(gp, 3, FAKE, FAKE2, FAKE, need, 0, None) == B.FBP_EINVAL  # aliases sino
+
+
+def test_batch_validation(lib):
+    ang = np.zeros(4)
+    jobs = (B.c_job * 2)()
+    for j in jobs:
+        j.geom = B.c_geom(4, 7, 5, 1.0, ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        j.sino = FAKE
+        j.image = FAKE2
+    jobs[1].sino = FAKE3
+    jobs[1].image = FAKE2 + 4096
+    need = lib.fbp_batch_workspace_bytes(jobs, 2, 0)
+    assert need > 2 * 4 * 7 * 4
+    assert lib.fbp_reconstruct_batch(jobs, 2, None, need, 0, None) == B.FBP_EWORKSPACE
+    assert lib.fbp_reconstruct_batch(jobs, 2, 0x400000, need - 1, 0, None) == B.FBP_EWORKSPACE
+    assert lib.fbp_reconstruct_batch(jobs, 2, 0x400010, need, 0, None) == B.FBP_EINVAL
+    assert lib.fbp_reconstruct_batch(jobs, -1, 0x400000, need, 0, None) == B.FBP_EINVAL
+    assert lib.fbp_reconstruct_batch(jobs, 0, None, 0, 0, None) == B.FBP_OK
+    jobs[1].image = FAKE2 + 16    # two images overlap
+    assert lib.fbp_reconstruct_batch(jobs, 2, 0x400000, need, 0, None) == B.FBP_EINVAL
+    jobs[1].image = None
+    assert lib.fbp_reconstruct_batch(jobs, 2, 0x400000, need, 0, None) == B.FBP_EINVAL
+
+
+def test_autotune_and_plan_validation(lib):
+    assert lib.fbp_autotune(None, None, None) == B.FBP_EINVAL
+    assert lib.fbp_plan_config(None) == B.FBP_EINVAL
+    _, g = _geom()
+    assert lib.fbp_backproject_with_config(ctypes.byref(g), 1, FAKE, FAKE2, 99, None) == B.FBP_EINVAL
+
+
+def _kernel_sources():
+    return [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp", ".hpp"))]
+
+
+def test_kernels_use_no_atomics_and_no_cuda():
+    for path in _kernel_sources():
+        text = open(path).read()
+        code = re.sub(r"//.*", "", re.sub(r"/\*.*?\*/", "", text, flags=re.S))
+        assert not re.search(r"atomic", code, re.I), f"atomic operation in {path}"
+        assert "cuda" not in code.lower(), f"CUDA reference in {path}"
+        assert "__HIP_PLATFORM" not in code
+
+
+def test_product_never_touches_oracle():
+    pkg = os.path.join(ROOT, "paper_2109_02174_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b|liboracle|fbp_oracle", text, re.M), \
+                    f"{f} loads the oracle"
