@@ -8,7 +8,7 @@
 //  * A workgroup owns a TW x TH tile of the upper half image AND the tile's point
 //    reflection through the centre.  The reflected pixel (-x, -y) sits at
 //    u' = (D-1) - u, so it reads the reversed filtered row at the SAME local
-//    coordinate: one coordinate, one floor and one LDS address serve two pixels.
+//    coordinate: one coordinate, one truncation and one LDS address serve two pixels.
 //  * Angles are streamed in blocks of KB.  Per (tile, angle) the window origin is
 //    computed once in FP64; lanes then work in FP32 coordinates local to that
 //    window.  The window starts one bin below the tile's smallest coordinate, so
@@ -18,22 +18,19 @@
 //    (A_j, dL_j) with dL_j = L[j+1] - L[j] and A_j = L[j] - j dL_j, so the
 //    interpolated value at local coordinate u in [j, j+1) is A_j + u dL_j: one
 //    FMA, no fraction.  One ds_read_b128 returns both directions.
-//  * Each pixel is written once by one lane; no atomics; the sum over angles runs
-//    in ascending k for every tile shape, so results depend on the tile shape only
-//    through rounding of the per-tile FP32 coordinates (the shape is fixed per
-//    geometry, which keeps repeated and batched calls bitwise identical).
+//  * The workgroup has S groups of 256 lanes over the same pixels; group g takes
+//    every S-th angle of a block, and the S partial sums are added in fixed order
+//    at the end.  This gives a single 512^2 slice enough waves per CU.
+//  * The next block's filtered rows are loaded into registers while the current
+//    block is computed, so the global-load latency hides behind the LDS work.
+//  * Each pixel is written once by one lane; no atomics.  The summation order
+//    depends only on the tile shape, which is fixed per geometry, so repeated and
+//    batched calls are bitwise identical.
 #include "fbp_internal.hpp"
 
 namespace fbp {
 
 namespace {
-
-struct alignas(16) AngleParams {
-    float b;      // local coordinate of the tile origin pixel (FP32)
-    float cf;     // cos/dt
-    float sf;     // sin/dt
-    int32_t i0;   // first staged bin
-};
 
 __device__ __forceinline__ float ld_zero(const float* __restrict__ row, int g, int D) {
     return (g >= 0 && g < D) ? row[g] : 0.0f;
@@ -49,19 +46,44 @@ __device__ __forceinline__ int xcd_logical(int b, int G) {
     return x * per + min(x, extra) + slot;
 }
 
-template <int TW, int P>
+// LDS layout: prm_b[2][kMaxKB] floats, prm_i[2][kMaxKB] ints, then the window
+// (float4 [KB][WL]), which the final cross-group reduction reuses.
+constexpr int kPrmBytes = kBpPrmBytes;
+
+template <int TW, int P, int S>
+struct Shape {
+    static constexpr int NT = kGroupThreads * S;
+    static constexpr int TH = (kGroupThreads / TW) * P;
+    static constexpr int RED_BYTES = (S - 1) * kGroupThreads * 2 * P * 4;
+};
+
+template <int TW, int P, int S>
 __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restrict__ q,
-                                        float* __restrict__ img, int c0, int r0,
-                                        float4* __restrict__ win, AngleParams* __restrict__ prm) {
-    constexpr int TH = (kBpThreads / TW) * P;
+                                        float* __restrict__ img, int c0, int r0, char* smem) {
+    using Sh = Shape<TW, P, S>;
+    constexpr int NT = Sh::NT;
+    constexpr int TH = Sh::TH;
+    float* prm_b = reinterpret_cast<float*>(smem);                      // [2][kMaxKB]
+    int* prm_i = reinterpret_cast<int*>(smem + 2 * kMaxKB * 4);         // [2][kMaxKB]
+    float4* win = reinterpret_cast<float4*>(smem + kPrmBytes);
+
     const int t = threadIdx.x;
-    const int lx = t % TW;
-    const int ly0 = (t / TW) * P;
+    const int grp = __builtin_amdgcn_readfirstlane(t >> 8);   // wave-uniform angle group
+    const int tl = t & (kGroupThreads - 1);
+    const int lx = tl % TW;
+    const int ly0 = (tl / TW) * P;
     const int N = job.N, K = job.K, D = job.D, WL = job.WL, KB = job.KB;
+    const int rw_shift = job.rw_shift;
     const double x0 = (double)c0 - job.half_pix;
     const double y0 = (double)r0 - job.half_pix;
     const float flx = (float)lx;
     const float fly = (float)ly0;
+    const float* __restrict__ cs32 = job.cs32;
+
+    // staging coordinates of this thread: bin sj of angles sa0, sa0 + sstep, ...
+    const int sj = t & ((1 << rw_shift) - 1);
+    const int sa0 = t >> rw_shift;
+    const int sstep = NT >> rw_shift;
 
     float accf[P], accr[P];
 #pragma unroll
@@ -70,51 +92,97 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
         accr[i] = 0.0f;
     }
 
-    for (int k0 = 0; k0 < K; k0 += KB) {
-        const int nb = min(KB, K - k0);
-        __syncthreads();  // previous block (or previous tile) fully consumed
+    // window origin (FP64) of the angles of the block starting at kb, into buffer buf
+    auto params = [&](int kb, int buf) {
+        const int nb = min(KB, K - kb);
         if (t < nb) {
-            const double cd = job.cs[2 * (k0 + t)];
-            const double sd = job.cs[2 * (k0 + t) + 1];
+            const double cd = job.cs[2 * (kb + t)];
+            const double sd = job.cs[2 * (kb + t) + 1];
             const double uo = x0 * cd + y0 * sd + job.centre_det;
             const double umin = uo + fmin(0.0, (double)(TW - 1) * cd) + fmin(0.0, (double)(TH - 1) * sd);
             const int i0 = (int)floor(umin) - 1;
-            AngleParams ap;
-            ap.b = (float)(uo - (double)i0);
-            ap.cf = (float)cd;
-            ap.sf = (float)sd;
-            ap.i0 = i0;
-            prm[t] = ap;
+            prm_b[buf * kMaxKB + t] = (float)(uo - (double)i0);
+            prm_i[buf * kMaxKB + t] = i0;
         }
-        __syncthreads();
-        const int n_el = nb * WL;
-        for (int e = t; e < n_el; e += kBpThreads) {
-            const int a = e / WL;
-            const int j = e - a * WL;
-            const int g = prm[a].i0 + j;
-            const float* __restrict__ row = q + (size_t)(k0 + a) * (size_t)D;
-            const float f0 = ld_zero(row, g, D);
-            const float f1 = ld_zero(row, g + 1, D);
-            const float b0 = ld_zero(row, D - 1 - g, D);
-            const float b1 = ld_zero(row, D - 2 - g, D);
-            const float df = f1 - f0;
-            const float db = b1 - b0;
-            const float jj = (float)j;
-            win[e] = make_float4(fmaf(-jj, df, f0), df, fmaf(-jj, db, b0), db);
+    };
+    float pf[kStageE][4];
+    auto load = [&](int kb, int buf) {
+        const int nb = min(KB, K - kb);
+#pragma unroll
+        for (int e = 0; e < kStageE; ++e) {
+            const int a = sa0 + e * sstep;
+            if (a < nb && sj < WL) {
+                const int g = prm_i[buf * kMaxKB + a] + sj;
+                const float* __restrict__ row = q + (size_t)(kb + a) * (size_t)D;
+                pf[e][0] = ld_zero(row, g, D);
+                pf[e][1] = ld_zero(row, g + 1, D);
+                pf[e][2] = ld_zero(row, D - 1 - g, D);
+                pf[e][3] = ld_zero(row, D - 2 - g, D);
+            }
         }
+    };
+    auto store = [&](int kb) {
+        const int nb = min(KB, K - kb);
+        const float jj = (float)sj;
+#pragma unroll
+        for (int e = 0; e < kStageE; ++e) {
+            const int a = sa0 + e * sstep;
+            if (a < nb && sj < WL) {
+                const float df = pf[e][1] - pf[e][0];
+                const float db = pf[e][3] - pf[e][2];
+                win[a * WL + sj] = make_float4(fmaf(-jj, df, pf[e][0]), df, fmaf(-jj, db, pf[e][2]), db);
+            }
+        }
+    };
+
+    __syncthreads();   // LDS of a previous tile (persistent workgroups) fully consumed
+    params(0, 0);
+    __syncthreads();
+    load(0, 0);
+    int buf = 0;
+    for (int k0 = 0; k0 < K; k0 += KB, buf ^= 1) {
+        const int nb = min(KB, K - k0);
+        store(k0);
+        if (k0 + KB < K) params(k0 + KB, buf ^ 1);
         __syncthreads();
+        if (k0 + KB < K) load(k0 + KB, buf ^ 1);
+        const float* __restrict__ pb = prm_b + buf * kMaxKB;
+        const float* __restrict__ cb = cs32 + 2 * k0;
 #pragma unroll 2
-        for (int a = 0; a < nb; ++a) {
-            const AngleParams p = prm[a];
-            const float u0 = fmaf(flx, p.cf, fmaf(fly, p.sf, p.b));
+        for (int a = grp; a < nb; a += S) {
+            const float cf = cb[2 * a];
+            const float sf = cb[2 * a + 1];
+            const float u0 = fmaf(flx, cf, fmaf(fly, sf, pb[a]));
             const float4* __restrict__ w = win + a * WL;
 #pragma unroll
             for (int i = 0; i < P; ++i) {
-                const float u = (i == 0) ? u0 : fmaf((float)i, p.sf, u0);
+                const float u = (i == 0) ? u0 : fmaf((float)i, sf, u0);
                 const int j = (int)u;   // u > 0: truncation is floor
                 const float4 v = w[j];
                 accf[i] += fmaf(u, v.y, v.x);
                 accr[i] += fmaf(u, v.w, v.z);
+            }
+        }
+        __syncthreads();
+    }
+
+    if constexpr (S > 1) {
+        float* red = reinterpret_cast<float*>(win);   // [S-1][256][2P]
+        if (grp > 0) {
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                red[((grp - 1) * kGroupThreads + tl) * 2 * P + 2 * i] = accf[i];
+                red[((grp - 1) * kGroupThreads + tl) * 2 * P + 2 * i + 1] = accr[i];
+            }
+        }
+        __syncthreads();
+        if (grp > 0) return;
+#pragma unroll
+        for (int gg = 1; gg < S; ++gg) {
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                accf[i] += red[((gg - 1) * kGroupThreads + tl) * 2 * P + 2 * i];
+                accr[i] += red[((gg - 1) * kGroupThreads + tl) * 2 * P + 2 * i + 1];
             }
         }
     }
@@ -138,29 +206,27 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
     }
 }
 
-template <int TW, int P>
-__global__ __launch_bounds__(kBpThreads) void bp_grid_kernel(BpJob job, size_t q_stride,
-                                                             size_t img_stride, int tiles_per_slice) {
-    extern __shared__ float4 smem[];
-    AngleParams* prm = reinterpret_cast<AngleParams*>(smem);
-    float4* win = smem + kMaxKB;
-    constexpr int TH = (kBpThreads / TW) * P;
+template <int TW, int P, int S>
+__global__ __launch_bounds__(kGroupThreads * S) void bp_grid_kernel(BpJob job, size_t q_stride,
+                                                                    size_t img_stride, int tiles_per_slice) {
+    extern __shared__ float4 smem4[];
+    char* smem = reinterpret_cast<char*>(smem4);
+    constexpr int TH = Shape<TW, P, S>::TH;
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int s = lb / tiles_per_slice;
     const int tt = lb - s * tiles_per_slice;
     const int ty = tt / job.tiles_x;
     const int tx = tt - ty * job.tiles_x;
-    bp_tile<TW, P>(job, job.q + (size_t)s * q_stride, job.img + (size_t)s * img_stride, tx * TW,
-                   ty * TH, win, prm);
+    bp_tile<TW, P, S>(job, job.q + (size_t)s * q_stride, job.img + (size_t)s * img_stride, tx * TW,
+                      ty * TH, smem);
 }
 
-template <int TW, int P>
-__global__ __launch_bounds__(kBpThreads) void bp_list_kernel(const BpListArgs* __restrict__ args) {
-    extern __shared__ float4 smem[];
+template <int TW, int P, int S>
+__global__ __launch_bounds__(kGroupThreads * S) void bp_list_kernel(const BpListArgs* __restrict__ args) {
+    extern __shared__ float4 smem4[];
+    char* smem = reinterpret_cast<char*>(smem4);
     const BpListArgs a = *args;
-    AngleParams* prm = reinterpret_cast<AngleParams*>(smem);
-    float4* win = smem + kMaxKB;
-    constexpr int TH = (kBpThreads / TW) * P;
+    constexpr int TH = Shape<TW, P, S>::TH;
     const int n_sel = a.counts[0];
     if (n_sel <= 0) return;
     const int total = a.tile_prefix[n_sel];
@@ -176,79 +242,98 @@ __global__ __launch_bounds__(kBpThreads) void bp_list_kernel(const BpListArgs* _
         const int tt = it - a.tile_prefix[lo];
         const int ty = tt / job.tiles_x;
         const int tx = tt - ty * job.tiles_x;
-        bp_tile<TW, P>(job, job.q, job.img, tx * TW, ty * TH, win, prm);
+        bp_tile<TW, P, S>(job, job.q, job.img, tx * TW, ty * TH, smem);
     }
 }
 
 constexpr TileShape kShapes[kNumTileConfigs] = {
-    {32, 4, 32, "32x32 tile, 4 px/lane"},
-    {32, 2, 16, "32x16 tile, 2 px/lane"},
-    {16, 2, 32, "16x32 tile, 2 px/lane"},
-    {32, 1, 8, "32x8 tile, 1 px/lane"},
-    {64, 4, 16, "64x16 tile, 4 px/lane"},
+    {32, 2, 16, 4, "32x16 tile, 2 px/lane, 4 angle groups"},
+    {16, 2, 32, 4, "16x32 tile, 2 px/lane, 4 angle groups"},
+    {32, 4, 32, 2, "32x32 tile, 4 px/lane, 2 angle groups"},
+    {32, 1, 8, 4, "32x8 tile, 1 px/lane, 4 angle groups"},
+    {32, 4, 32, 1, "32x32 tile, 4 px/lane, 1 angle group"},
+    {16, 2, 32, 2, "16x32 tile, 2 px/lane, 2 angle groups"},
+    {32, 2, 16, 1, "32x16 tile, 2 px/lane, 1 angle group"},
 };
 
-template <int TW, int P>
+template <int TW, int P, int S>
 hipError_t grid_launch(const BpJob& job, int n_slices, size_t q_stride, size_t img_stride,
-                       int tiles_per_slice, hipStream_t stream) {
-    const size_t lds = (size_t)bp_lds_bytes(job.WL, job.KB);
+                       int tiles_per_slice, size_t lds, hipStream_t stream) {
     const unsigned grid = (unsigned)n_slices * (unsigned)tiles_per_slice;
-    hipLaunchKernelGGL((bp_grid_kernel<TW, P>), dim3(grid), dim3(kBpThreads), lds, stream, job,
-                       q_stride, img_stride, tiles_per_slice);
+    hipLaunchKernelGGL((bp_grid_kernel<TW, P, S>), dim3(grid), dim3(kGroupThreads * S), lds, stream,
+                       job, q_stride, img_stride, tiles_per_slice);
     return hipGetLastError();
 }
 
-template <int TW, int P>
+template <int TW, int P, int S>
 hipError_t list_launch(const BpListArgs* a, int grid, size_t lds, hipStream_t stream) {
-    hipLaunchKernelGGL((bp_list_kernel<TW, P>), dim3(grid), dim3(kBpThreads), lds, stream, a);
+    hipLaunchKernelGGL((bp_list_kernel<TW, P, S>), dim3(grid), dim3(kGroupThreads * S), lds, stream, a);
     return hipGetLastError();
 }
 
-template <int TW, int P>
+template <int TW, int P, int S>
 int occupancy(size_t lds) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_list_kernel<TW, P>, kBpThreads, lds) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_list_kernel<TW, P, S>, kGroupThreads * S,
+                                                     lds) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
+
+template <int TW, int P, int S>
+constexpr int red_bytes() { return Shape<TW, P, S>::RED_BYTES; }
+
+#define FBP_FOR_EACH_SHAPE(X) \
+    X(0, 32, 2, 4)            \
+    X(1, 16, 2, 4)            \
+    X(2, 32, 4, 2)            \
+    X(3, 32, 1, 4)            \
+    X(4, 32, 4, 1)            \
+    X(5, 16, 2, 2)            \
+    X(6, 32, 2, 1)
 
 }  // namespace
 
 const TileShape& tile_shape(int cfg) { return kShapes[cfg]; }
 
-int bp_lds_bytes(int WL, int KB) { return (kMaxKB + WL * KB) * 16; }
+int bp_lds_bytes(int cfg, int WL, int KB) {
+    int red = 0;
+    switch (cfg) {
+#define X(id, tw, p, s) case id: red = red_bytes<tw, p, s>(); break;
+        FBP_FOR_EACH_SHAPE(X)
+#undef X
+        default: break;
+    }
+    const int win = WL * KB * 16;
+    return kPrmBytes + (win > red ? win : red);
+}
 
 hipError_t launch_bp_grid(int cfg, const BpJob& job, int n_slices, size_t q_stride,
                           size_t img_stride, int tiles_per_slice, hipStream_t stream) {
+    const size_t lds = (size_t)bp_lds_bytes(cfg, job.WL, job.KB);
     switch (cfg) {
-        case 0: return grid_launch<32, 4>(job, n_slices, q_stride, img_stride, tiles_per_slice, stream);
-        case 1: return grid_launch<32, 2>(job, n_slices, q_stride, img_stride, tiles_per_slice, stream);
-        case 2: return grid_launch<16, 2>(job, n_slices, q_stride, img_stride, tiles_per_slice, stream);
-        case 3: return grid_launch<32, 1>(job, n_slices, q_stride, img_stride, tiles_per_slice, stream);
-        case 4: return grid_launch<64, 4>(job, n_slices, q_stride, img_stride, tiles_per_slice, stream);
+#define X(id, tw, p, s) \
+        case id: return grid_launch<tw, p, s>(job, n_slices, q_stride, img_stride, tiles_per_slice, lds, stream);
+        FBP_FOR_EACH_SHAPE(X)
+#undef X
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_bp_list(int cfg, const BpListArgs* a, int grid, size_t lds, hipStream_t stream) {
     switch (cfg) {
-        case 0: return list_launch<32, 4>(a, grid, lds, stream);
-        case 1: return list_launch<32, 2>(a, grid, lds, stream);
-        case 2: return list_launch<16, 2>(a, grid, lds, stream);
-        case 3: return list_launch<32, 1>(a, grid, lds, stream);
-        case 4: return list_launch<64, 4>(a, grid, lds, stream);
+#define X(id, tw, p, s) case id: return list_launch<tw, p, s>(a, grid, lds, stream);
+        FBP_FOR_EACH_SHAPE(X)
+#undef X
         default: return hipErrorInvalidValue;
     }
 }
 
 int bp_occupancy(int cfg, size_t lds) {
     switch (cfg) {
-        case 0: return occupancy<32, 4>(lds);
-        case 1: return occupancy<32, 2>(lds);
-        case 2: return occupancy<16, 2>(lds);
-        case 3: return occupancy<32, 1>(lds);
-        case 4: return occupancy<64, 4>(lds);
+#define X(id, tw, p, s) case id: return occupancy<tw, p, s>(lds);
+        FBP_FOR_EACH_SHAPE(X)
+#undef X
         default: return 1;
     }
 }

@@ -13,31 +13,38 @@ namespace fbp {
 struct BpJob {
     const float* q;       // filtered rows [K][D]
     float* img;           // image [N][N]
-    const double* cs;     // [K][2]: cos(theta_k)/dt, sin(theta_k)/dt in FP64
+    const double* cs;     // [K][2]: cos(theta_k)/dt, sin(theta_k)/dt in FP64 (window origins)
+    const float* cs32;    // [K][2]: the same rounded to FP32 (pixel steps)
     double half_pix;      // (N-1)/2
     double centre_det;    // (D-1)/2
     int32_t N, K, D;
     int32_t WL;           // window length (bins) staged per angle for this job's tile shape
     int32_t KB;           // angles staged per LDS block
+    int32_t rw_shift;     // log2 of the staging row width (power of two >= WL)
     int32_t tiles_x;      // tile columns of the half image
     float scale;          // pi/K
-    int32_t pad;
 };
 static_assert(sizeof(BpJob) % 8 == 0, "BpJob layout");
 
-// Compile-time tile shapes of the backprojector.  256 lanes; lane t owns column
-// t % TW and P consecutive rows starting at (t / TW) * P, for its pixel and the
-// pixel's point reflection through the image centre.
+// Compile-time tile shapes of the backprojector.  A workgroup has s groups of
+// 256 lanes; lane t of a group owns column t % tw and p consecutive rows starting
+// at (t / tw) * p, for its pixel and the pixel's point reflection through the
+// image centre.  Group g takes the angles g, g+s, g+2s, ... of every staged block;
+// the groups' partial sums are added in fixed order at the end.
 struct TileShape {
-    int32_t tw, p, th;
+    int32_t tw, p, th, s;
     const char* name;
 };
 
-constexpr int kBpThreads = 256;
-constexpr int kNumTileConfigs = 5;
+constexpr int kGroupThreads = 256;
+constexpr int kBpThreads = 256;   // threads of the GEMM workgroups
+constexpr int kNumTileConfigs = 7;
 constexpr int kMaxKB = 64;
+constexpr int kStageE = 4;        // staged (angle, bin) elements per thread per block
 // Dynamic LDS budget of one backprojection workgroup (bytes).
-constexpr int kBpLdsBudget = 32 * 1024;
+constexpr int kBpLdsBudget = 48 * 1024;
+// LDS bytes of the per-block window origins (two buffers of kMaxKB floats and ints).
+constexpr int kBpPrmBytes = 2 * kMaxKB * 8;
 
 const TileShape& tile_shape(int cfg);
 
@@ -45,6 +52,9 @@ const TileShape& tile_shape(int cfg);
 // tile at any angle, plus interpolation and rounding margin.  span_max is the
 // largest (TW-1)|cos|/dt + (TH-1)|sin|/dt over the angles.
 inline int window_length(double span_max) { return (int)span_max + 5; }
+
+// LDS bytes of a backprojection workgroup of tile shape cfg with window WL and block KB.
+int bp_lds_bytes(int cfg, int WL, int KB);
 
 // Backprojection of n_slices slices of one geometry (tile grid from blockIdx).
 hipError_t launch_bp_grid(int cfg, const BpJob& job, int n_slices, size_t q_stride,
@@ -62,27 +72,31 @@ struct BpListArgs {
 // `args` is a DEVICE pointer (the batch header in the workspace).
 hipError_t launch_bp_list(int cfg, const BpListArgs* args, int grid, size_t lds_bytes,
                           hipStream_t stream);
-int bp_lds_bytes(int WL, int KB);
 int bp_occupancy(int cfg, size_t lds_bytes);   // resident workgroups per CU
 
 // ------------------------------------------------------------------ ramp filter GEMM
 
 enum Prec : int32_t { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
 
-// One ramp-filter GEMM problem: Q[R][D] = P[R][D] x T, T[m][n] = tap(n - m).
+// One ramp-filter GEMM problem: Q[R][D] = P[R][D] x T, T[m][n] = tap(n - m), computed
+// as two parity-split half GEMMs over the odd taps to(j) = tap(2j - 1) plus the
+// centre tap.
 struct GemmJob {
     const float* p;       // [R][D]
     float* q;             // [R][D]
-    const void* taps;     // tap(d) at index d + Dp, d in [-Dp, Dp); element type by precision
-    int32_t R, D, Dp;
+    const void* taps;     // to(j) at index j + Dhp, j in [-Dhp, Dhp]; element type by precision
+    int32_t R, D;
+    int32_t Dh;           // ceil(D / 2): inputs per parity
+    int32_t Dhp;          // Dh rounded up to 64
+    float diag;           // tap(0), rounded like the taps (and pre-scaled for FP16)
     float out_scale;      // undoes the FP16 tap pre-scale (1 otherwise)
     int32_t tiles_n;      // ceil(D / 64)
-    int32_t pad[3];
+    int32_t pad;
 };
 static_assert(sizeof(GemmJob) % 8 == 0, "GemmJob layout");
 
-constexpr int kGemmBM = 64;
-constexpr int kGemmBN = 64;
+constexpr int kGemmBM = 32;   // rows per GEMM tile
+constexpr int kGemmBN = 64;   // output bins per GEMM tile
 
 hipError_t launch_gemm_grid(int prec, const GemmJob& job, hipStream_t stream);
 
@@ -94,7 +108,7 @@ struct GemmListArgs {
 // `args` is a DEVICE pointer (the batch header in the workspace).
 hipError_t launch_gemm_list(int prec, const GemmListArgs* args, int grid, size_t lds_bytes,
                             hipStream_t stream);
-int gemm_lds_bytes(int prec, int Dp);
+int gemm_lds_bytes(int prec, int Dh);
 int gemm_occupancy(int prec, size_t lds_bytes);
 
 }  // namespace fbp

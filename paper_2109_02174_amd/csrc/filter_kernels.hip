@@ -4,35 +4,40 @@
 // tomography") with the Ram-Lak kernel is, for all rows at once,
 //     Q[R][D] = P[R][D] x T,   T[m][n] = tap(n - m) = dt h(n - m),
 // a dense contraction over the D input bins (linear convolution: the kernel
-// spans every |n - m| <= D-1, so nothing is truncated).  T is symmetric and
-// Toeplitz, so no T matrix exists in memory: each workgroup loads the slice of
-// the 1D tap table its output columns need into LDS and feeds the B operand
-// from there.
+// spans every |n - m| <= D-1, so nothing is truncated).
 //
-// Workgroup: 256 lanes = 4 waves in a 2 x 2 arrangement, 64 x 64 outputs, each
-// wave one 32 x 32 MFMA accumulator block (FP32 accumulate).
-//   FP32:       v_mfma_f32_32x32x2_f32, K-step 32 staged through LDS.
-//   BF16/FP16:  v_mfma_f32_32x32x16_{bf16,f16}; A is rounded to 16 bits (RNE)
-//               as it is staged; the tap table is kept as eight copies shifted by
-//               one element so every 8-tap B fragment is one aligned 16-byte read.
-#include <hip/hip_bf16.h>
-#include <hip/hip_fp16.h>
-
+// The kernel vanishes at even nonzero offsets, so an even output bin n = 2n'
+// only sees odd input bins m = 2m'+1 and an odd output only even inputs:
+//     Q[2n'+s] = tap(0) P[2n'+s] + sum_m' to(n' - m' + s) P[2m' + 1 - s],
+//     to(j) = tap(2j - 1),
+// two half-size Toeplitz GEMMs (half the MACs of the dense product) plus the
+// centre tap, which is applied in FP32 in the epilogue.  No T matrix exists in
+// memory: each workgroup copies the slice of the 1D odd-tap table its outputs
+// need into LDS and feeds the B operand from there.
+//
+// Workgroup: 256 lanes = 4 waves; tile = 32 rows x 64 output bins.  Wave w owns
+// rows 16 (w/2) .. +16 and the output bins of parity w%2 (two 16x16 MFMA blocks).
+// The next chunk of sinogram rows is loaded into registers while the current one
+// is multiplied.
+//   FP32:       v_mfma_f32_16x16x4_f32, 32 inputs per parity per chunk.
+//   BF16/FP16:  v_mfma_f32_16x16x32_{bf16,f16}, 64 per parity per chunk; the rows
+//               are rounded to 16 bits (RNE) as they are staged, and the tap slice
+//               is kept in LDS as eight copies shifted by one element so every
+//               8-tap fragment is one aligned 16-byte read.
 #include "fbp_internal.hpp"
 
 namespace fbp {
 
 namespace {
 
-typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef unsigned short v8u16 __attribute__((ext_vector_type(8)));
 
-constexpr int kBK32 = 32;   // K-step of the FP32 path
-constexpr int kBK16 = 64;   // K-step of the 16-bit paths
-constexpr int kAStride32 = kBK32 + 1;   // LDS row stride (floats), odd: no bank conflicts
-constexpr int kAStride16 = kBK16 + 8;   // LDS row stride (16-bit), 16-byte aligned rows
+constexpr int kTM = kGemmBM;        // rows per tile (32)
+constexpr int kTN = kGemmBN;        // output bins per tile (64 = 32 per parity)
+constexpr int kHalfN = kTN / 2;
 
 __device__ __forceinline__ unsigned short to_bf16_rne(float x) {
     unsigned int u = __float_as_uint(x);
@@ -45,147 +50,196 @@ __device__ __forceinline__ unsigned short to_f16_rne(float x) {
     return __builtin_bit_cast(unsigned short, h);
 }
 
-// Output element (m, n) of accumulator register i of a 32x32 MFMA block for lane l:
-// n = l % 32, m = 8 (i / 4) + 4 (l / 32) + i % 4.
-__device__ __forceinline__ void store_block(const v16f& acc, float* __restrict__ q, int R, int D,
-                                            int m0, int n0, float s) {
+template <int PREC>
+__device__ __forceinline__ float round_operand(float x) {
+    if constexpr (PREC == kBF16) return __uint_as_float((unsigned int)to_bf16_rne(x) << 16);
+    else if constexpr (PREC == kFP16) return (float)(_Float16)x;
+    else return x;
+}
+
+// Epilogue: lane l of a 16x16 block holds rows 4 (l/16) + i, column l % 16.
+template <int PREC>
+__device__ __forceinline__ void store_block(const v4f& acc, const GemmJob& job, int row0, int nh0, int sg) {
     const int l = threadIdx.x & 63;
-    const int n = n0 + (l & 31);
-    if (n >= D) return;
+    const int n = 2 * (nh0 + (l & 15)) + sg;
+    if (n >= job.D) return;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int m = m0 + 8 * (i >> 2) + 4 * (l >> 5) + (i & 3);
-        if (m < R) q[(size_t)m * D + n] = acc[i] * s;
+    for (int i = 0; i < 4; ++i) {
+        const int m = row0 + 4 * (l >> 4) + i;
+        if (m < job.R) {
+            const float pc = round_operand<PREC>(job.p[(size_t)m * job.D + n]);
+            job.q[(size_t)m * job.D + n] = fmaf(job.diag, pc, acc[i]) * job.out_scale;
+        }
     }
 }
 
 // ---------------------------------------------------------------- FP32 operands
 
-__device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt, float* smem) {
-    float* As = smem;                                  // [64][kAStride32]
-    float* Bt = smem + kGemmBM * kAStride32;           // taps d = n0 - Dp + 1 + x
+constexpr int kK32 = 32;                  // inputs per parity per chunk
+constexpr int kAS32 = kK32 + 1;           // LDS row stride (floats)
+
+__device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt, char* smem) {
+    float* As = reinterpret_cast<float*>(smem);          // [2 parity][32 rows][kAS32]
+    float* Bt = As + 2 * kTM * kAS32;                    // odd taps j = jlo + x
     const int t = threadIdx.x;
     const int w = t >> 6, l = t & 63;
-    const int wm = w >> 1, wn = w & 1;
-    const int m0 = mt * kGemmBM, n0 = nt * kGemmBN;
-    const int R = job.R, D = job.D, Dp = job.Dp;
+    const int wm = w >> 1, sg = w & 1;                   // row half, output parity
+    const int m0 = mt * kTM, nh0 = nt * kHalfN;
+    const int R = job.R, D = job.D, Dh = job.Dh, Dhp = job.Dhp;
     const float* __restrict__ taps = static_cast<const float*>(job.taps);
     const float* __restrict__ P = job.p;
+    const int mpad = (Dh + kK32 - 1) / kK32 * kK32;       // inputs per parity, padded
+    const int jlo = nh0 - mpad + 1;
+    const int n_taps = mpad + kHalfN;                    // j in [jlo, nh0 + 32]
 
-    __syncthreads();  // LDS reuse across tiles of a persistent workgroup
-    // taps for d in [n0 - Dp + 1, n0 + 63]: table index d + Dp in [n0 + 1, n0 + Dp + 63]
-    const int n_taps = Dp + kGemmBN - 1;
-    for (int x = t; x < n_taps; x += kBpThreads) Bt[x] = taps[n0 + 1 + x];
+    __syncthreads();   // LDS reuse across tiles of a persistent workgroup
+    for (int x = t; x < n_taps; x += kBpThreads) Bt[x] = taps[jlo + x + Dhp];
 
-    v16f acc = {};
-    const int col_l = wn * 32 + (l & 31);              // output column within the tile
-    const int row_l = wm * 32 + (l & 31);              // A row within the tile
-    for (int k0 = 0; k0 < D; k0 += kBK32) {
-        __syncthreads();
-        for (int e = t; e < kGemmBM * kBK32; e += kBpThreads) {
-            const int row = e / kBK32, col = e % kBK32;
-            const int m = m0 + row, k = k0 + col;
-            As[row * kAStride32 + col] = (m < R && k < D) ? P[(size_t)m * D + k] : 0.0f;
-        }
-        __syncthreads();
+    float pf[8];
+    auto load = [&](int c0) {   // original columns c0 .. c0+63 of rows m0 .. m0+31
 #pragma unroll
-        for (int ks = 0; ks < kBK32; ks += 2) {
-            const int kk = ks + (l >> 5);
-            const float a = As[row_l * kAStride32 + kk];
-            // tap(n - k) with n = n0 + col_l, k = k0 + kk: Bt index n - k - (n0 - Dp + 1)
-            const float b = Bt[col_l + Dp - 1 - (k0 + kk)];
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        for (int i = 0; i < 8; ++i) {
+            const int e = t + i * kBpThreads;
+            const int row = e >> 6, col = c0 + (e & 63);
+            const int m = m0 + row;
+            pf[i] = (m < R && col < D) ? P[(size_t)m * D + col] : 0.0f;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = t + i * kBpThreads;
+            const int row = e >> 6, col = e & 63;
+            As[((col & 1) * kTM + row) * kAS32 + (col >> 1)] = pf[i];
+        }
+    };
+
+    v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    const float* __restrict__ Arow = As + ((1 - sg) * kTM + wm * 16 + (l & 15)) * kAS32 + (l >> 4);
+    const int bbase = (l & 15) - (l >> 4) + sg - jlo + nh0;   // + 16 ntile - m'
+    load(0);
+    for (int c0 = 0; c0 < D; c0 += 2 * kK32) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        if (c0 + 2 * kK32 < D) load(c0 + 2 * kK32);
+        const int mh0 = c0 >> 1;
+#pragma unroll
+        for (int kk = 0; kk < kK32; kk += 4) {
+            const float a = Arow[kk];
+            const float b0 = Bt[bbase - (mh0 + kk)];
+            const float b1 = Bt[bbase + 16 - (mh0 + kk)];
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc1, 0, 0, 0);
         }
     }
-    store_block(acc, job.q, R, D, m0 + wm * 32, n0 + wn * 32, job.out_scale);
+    store_block<kFP32>(acc0, job, m0 + wm * 16, nh0, sg);
+    store_block<kFP32>(acc1, job, m0 + wm * 16, nh0 + 16, sg);
 }
 
 // ---------------------------------------------------------------- 16-bit operands
 
+constexpr int kK16 = 64;                  // inputs per parity per chunk
+constexpr int kAS16 = kK16 + 8;           // LDS row stride (16-bit), 16-byte aligned rows
+
+__device__ __forceinline__ int copy_stride16(int mpad) { return (mpad + kHalfN + 8 + 7 + 7) & ~7; }
+
 template <int PREC>
-__device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt, unsigned short* smem) {
-    // LDS: A [64][kAStride16] 16-bit, then 8 shifted copies of the tap slice.
-    unsigned short* As = smem;
-    unsigned short* Tc = smem + kGemmBM * kAStride16;
+__device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt, char* smem) {
+    unsigned short* As = reinterpret_cast<unsigned short*>(smem);   // [2][32][kAS16]
+    unsigned short* Tc = As + 2 * kTM * kAS16;                      // 8 shifted tap copies
     const int t = threadIdx.x;
     const int w = t >> 6, l = t & 63;
-    const int wm = w >> 1, wn = w & 1;
-    const int m0 = mt * kGemmBM, n0 = nt * kGemmBN;
-    const int R = job.R, D = job.D, Dp = job.Dp;
+    const int wm = w >> 1, sg = w & 1;
+    const int m0 = mt * kTM, nh0 = nt * kHalfN;
+    const int R = job.R, D = job.D, Dh = job.Dh, Dhp = job.Dhp;
     const unsigned short* __restrict__ taps = static_cast<const unsigned short*>(job.taps);
     const float* __restrict__ P = job.p;
-
-    // B fragment of lane l at K-step base kb: taps at d = k - n for
-    // k = kb + 8 (l / 32) + i, i = 0..7, n = n0 + wn*32 + l%32 (tap(n-k) = tap(k-n)).
-    // d ranges over [-(n0 + 63), Dp - 1 - n0 + 8]; slice origin d_lo = -(n0 + 64).
-    const int d_lo = -(n0 + kGemmBN);
-    const int span = Dp + kGemmBN + 16;                // covers d_lo .. Dp - n0 + 15
-    const int cstride = (span + 7 + 7) & ~7;           // per-copy length, multiple of 8
+    const int mpad = (Dh + kK16 - 1) / kK16 * kK16;
+    // B fragment of lane l: to(n' - m' + s) for m' = mb + 8 (l/16) + i, i = 0..7, with
+    // n' = nh0 + 16 ntile + l%16.  As y = m' - n' - s rises, tr(y) = to(-y) is read
+    // forward; slice index = y - ylo.
+    const int ylo = -(nh0 + kHalfN);
+    const int cstride = copy_stride16(mpad);
 
     __syncthreads();
     for (int x = t; x < 8 * cstride; x += kBpThreads) {
         const int c = x / cstride, y = x - c * cstride;
-        const int d = d_lo + y + c;                    // copy c holds slice[y + c]
-        const int idx = d + Dp;
-        Tc[x] = (idx >= 0 && idx < 2 * Dp) ? taps[idx] : (unsigned short)0;
+        const int idx = -(ylo + y + c) + Dhp;             // table index of to(-(y'))
+        Tc[x] = (idx >= 0 && idx <= 2 * Dhp) ? taps[idx] : (unsigned short)0;
     }
 
-    v16f acc = {};
-    const int row_l = wm * 32 + (l & 31);
-    const int n_l = n0 + wn * 32 + (l & 31);
-    const int kq = 8 * (l >> 5);
-    for (int k0 = 0; k0 < D; k0 += kBK16) {
-        __syncthreads();
-        // stage A: 64 rows x 64 k, four consecutive k per lane-step
-        for (int e = t; e < kGemmBM * (kBK16 / 4); e += kBpThreads) {
-            const int row = e / (kBK16 / 4), c4 = (e % (kBK16 / 4)) * 4;
+    float pf[16];
+    auto load = [&](int c0) {   // original columns c0 .. c0+127 of rows m0 .. m0+31
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = t + i * kBpThreads;
+            const int row = e >> 7, col = c0 + (e & 127);
             const int m = m0 + row;
-            unsigned short h[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int k = k0 + c4 + i;
-                const float v = (m < R && k < D) ? P[(size_t)m * D + k] : 0.0f;
-                h[i] = (PREC == kBF16) ? to_bf16_rne(v) : to_f16_rne(v);
-            }
-            unsigned int* dst = reinterpret_cast<unsigned int*>(As + row * kAStride16 + c4);
-            dst[0] = (unsigned int)h[0] | ((unsigned int)h[1] << 16);
-            dst[1] = (unsigned int)h[2] | ((unsigned int)h[3] << 16);
+            pf[i] = (m < R && col < D) ? P[(size_t)m * D + col] : 0.0f;
         }
-        __syncthreads();
+    };
+    auto store = [&]() {
 #pragma unroll
-        for (int ks = 0; ks < kBK16; ks += 16) {
-            const v8u16 av = *reinterpret_cast<const v8u16*>(As + row_l * kAStride16 + ks + kq);
-            const int y = (k0 + ks + kq) - n_l - d_lo;     // slice index of the first tap
-            const int c = y & 7;
-            const v8u16 bv = *reinterpret_cast<const v8u16*>(Tc + c * cstride + (y - c));
+        for (int i = 0; i < 16; ++i) {
+            const int e = t + i * kBpThreads;
+            const int row = e >> 7, col = e & 127;
+            As[((col & 1) * kTM + row) * kAS16 + (col >> 1)] =
+                (PREC == kBF16) ? to_bf16_rne(pf[i]) : to_f16_rne(pf[i]);
+        }
+    };
+
+    v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    const unsigned short* Arow = As + ((1 - sg) * kTM + wm * 16 + (l & 15)) * kAS16 + 8 * (l >> 4);
+    const int kq = 8 * (l >> 4);
+    load(0);
+    for (int c0 = 0; c0 < D; c0 += 2 * kK16) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        if (c0 + 2 * kK16 < D) load(c0 + 2 * kK16);
+        const int mh0 = c0 >> 1;
+#pragma unroll
+        for (int ks = 0; ks < kK16; ks += 32) {
+            const v8u16 av = *reinterpret_cast<const v8u16*>(Arow + ks);
+            const int ya = (mh0 + ks + kq) - (nh0 + (l & 15)) - sg - ylo;
+            const int yb = ya - 16;
+            const int ca = ya & 7, cb = yb & 7;
+            const v8u16 b0 = *reinterpret_cast<const v8u16*>(Tc + ca * cstride + (ya - ca));
+            const v8u16 b1 = *reinterpret_cast<const v8u16*>(Tc + cb * cstride + (yb - cb));
             if constexpr (PREC == kBF16) {
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, av),
-                                                              __builtin_bit_cast(v8bf, bv), acc, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av),
+                                                               __builtin_bit_cast(v8bf, b0), acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av),
+                                                               __builtin_bit_cast(v8bf, b1), acc1, 0, 0, 0);
             } else {
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, av),
-                                                             __builtin_bit_cast(v8h, bv), acc, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, av),
+                                                              __builtin_bit_cast(v8h, b0), acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, av),
+                                                              __builtin_bit_cast(v8h, b1), acc1, 0, 0, 0);
             }
         }
     }
-    store_block(acc, job.q, R, D, m0 + wm * 32, n0 + wn * 32, job.out_scale);
+    store_block<PREC>(acc0, job, m0 + wm * 16, nh0, sg);
+    store_block<PREC>(acc1, job, m0 + wm * 16, nh0 + 16, sg);
 }
 
 template <int PREC>
-__device__ __forceinline__ void gemm_tile(const GemmJob& job, int mt, int nt, void* smem) {
+__device__ __forceinline__ void gemm_tile(const GemmJob& job, int mt, int nt, char* smem) {
     if constexpr (PREC == kFP32)
-        gemm_tile_f32(job, mt, nt, static_cast<float*>(smem));
+        gemm_tile_f32(job, mt, nt, smem);
     else
-        gemm_tile_16<PREC>(job, mt, nt, static_cast<unsigned short*>(smem));
+        gemm_tile_16<PREC>(job, mt, nt, smem);
 }
 
 template <int PREC>
 __global__ __launch_bounds__(kBpThreads) void gemm_grid_kernel(GemmJob job) {
     extern __shared__ float4 smem4[];
-    const int tiles_m = (job.R + kGemmBM - 1) / kGemmBM;
+    const int tiles_m = (job.R + kTM - 1) / kTM;
     // blockIdx.x: output tile index, row tiles fastest so neighbours share tap slices
     const int b = blockIdx.x;
     const int nt = b / tiles_m, mt = b - nt * tiles_m;
-    gemm_tile<PREC>(job, mt, nt, smem4);
+    gemm_tile<PREC>(job, mt, nt, reinterpret_cast<char*>(smem4));
 }
 
 template <int PREC>
@@ -203,9 +257,9 @@ __global__ __launch_bounds__(kBpThreads) void gemm_list_kernel(const GemmListArg
         }
         const GemmJob job = a.jobs[lo];
         const int tt = it - a.tile_prefix[lo];
-        const int tiles_m = (job.R + kGemmBM - 1) / kGemmBM;
+        const int tiles_m = (job.R + kTM - 1) / kTM;
         const int nt = tt / tiles_m, mt = tt - nt * tiles_m;
-        gemm_tile<PREC>(job, mt, nt, smem4);
+        gemm_tile<PREC>(job, mt, nt, reinterpret_cast<char*>(smem4));
     }
 }
 
@@ -220,17 +274,19 @@ int occ(int lds) {
 
 }  // namespace
 
-int gemm_lds_bytes(int prec, int Dp) {
-    if (prec == kFP32) return (kGemmBM * kAStride32 + Dp + kGemmBN) * 4;
-    const int span = Dp + kGemmBN + 16;
-    const int cstride = (span + 7 + 7) & ~7;
-    return (kGemmBM * kAStride16 + 8 * cstride) * 2;
+int gemm_lds_bytes(int prec, int Dh) {
+    if (prec == kFP32) {
+        const int mpad = (Dh + kK32 - 1) / kK32 * kK32;
+        return (2 * kTM * kAS32 + mpad + kHalfN) * 4;
+    }
+    const int mpad = (Dh + kK16 - 1) / kK16 * kK16;
+    return (2 * kTM * kAS16 + 8 * ((mpad + kHalfN + 8 + 7 + 7) & ~7)) * 2;
 }
 
 hipError_t launch_gemm_grid(int prec, const GemmJob& job, hipStream_t stream) {
-    const int tiles_m = (job.R + kGemmBM - 1) / kGemmBM;
+    const int tiles_m = (job.R + kTM - 1) / kTM;
     const unsigned grid = (unsigned)(tiles_m * job.tiles_n);
-    const size_t lds = (size_t)gemm_lds_bytes(prec, job.Dp);
+    const size_t lds = (size_t)gemm_lds_bytes(prec, job.Dh);
     switch (prec) {
         case kFP32: hipLaunchKernelGGL(gemm_grid_kernel<kFP32>, dim3(grid), dim3(kBpThreads), lds, stream, job); break;
         case kBF16: hipLaunchKernelGGL(gemm_grid_kernel<kBF16>, dim3(grid), dim3(kBpThreads), lds, stream, job); break;

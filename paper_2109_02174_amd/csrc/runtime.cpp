@@ -105,12 +105,14 @@ struct Plan {
     double dt = 1.0;
     std::vector<double> angles;
     std::vector<double> cs;          // host copy of the device table
-    int Dp = 0;                      // D rounded up to the GEMM tile width
+    int Dh = 0, Dhp = 0;             // inputs per parity, and that rounded up to 64
     double* d_cs = nullptr;
+    float* d_cs32 = nullptr;
     void* d_taps[3] = {nullptr, nullptr, nullptr};
     float out_scale[3] = {1.0f, 1.0f, 1.0f};
+    float diag[3] = {0.0f, 0.0f, 0.0f};
     int cfg = 0;
-    int WL = 0, KB = 0;
+    int WL = 0, KB = 0, rw_shift = 0;
     int tiles_x = 0, tiles_y = 0;
     std::mutex mu;
 };
@@ -140,19 +142,38 @@ double span_for(const TileShape& s, const std::vector<double>& cs) {
     return span;
 }
 
-// Tile shape, window length and angle block of a tile id for a geometry.
-bool shape_params(int cfg, const std::vector<double>& cs, int N, int* WL, int* KB, int* tx, int* ty) {
+// Window length, staging row width and angle block of a tile id for a geometry.
+struct ShapeParams {
+    int WL = 0, KB = 0, rw_shift = 0, tiles_x = 0, tiles_y = 0;
+};
+
+bool shape_params(int cfg, const std::vector<double>& cs, int N, ShapeParams* sp) {
     const TileShape& s = tile_shape(cfg);
     const double span = span_for(s, cs);
     if (!(span < 1e6)) return false;
-    *WL = window_length(span);
-    const int kb = (kBpLdsBudget / 16 - kMaxKB) / *WL;
-    if (kb < 1) return false;
-    *KB = std::min(kMaxKB, kb);
-    *tx = (N + s.tw - 1) / s.tw;
+    sp->WL = window_length(span);
+    const int nt = kGroupThreads * s.s;
+    int shift = 0;
+    while ((1 << shift) < sp->WL) ++shift;
+    if ((1 << shift) > nt) return false;          // one staging row per workgroup pass at least
+    sp->rw_shift = shift;
+    const int kb_stage = kStageE * (nt >> shift);
+    const int kb_lds = (kBpLdsBudget - kBpPrmBytes) / (16 * sp->WL);
+    sp->KB = std::min(kMaxKB, std::min(kb_stage, kb_lds));
+    if (sp->KB < 1) return false;
+    sp->tiles_x = (N + s.tw - 1) / s.tw;
     const int half_rows = (N + 1) / 2;
-    *ty = (half_rows + s.th - 1) / s.th;
+    sp->tiles_y = (half_rows + s.th - 1) / s.th;
     return true;
+}
+
+void apply_shape(Plan* p, int cfg, const ShapeParams& sp) {
+    p->cfg = cfg;
+    p->WL = sp.WL;
+    p->KB = sp.KB;
+    p->rw_shift = sp.rw_shift;
+    p->tiles_x = sp.tiles_x;
+    p->tiles_y = sp.tiles_y;
 }
 
 int default_config(int N) {
@@ -234,27 +255,38 @@ int get_plan(const fbp_geom* g, Plan** out) {
         p->cs[2 * k] = std::cos(p->angles[k]) / p->dt;
         p->cs[2 * k + 1] = std::sin(p->angles[k]) / p->dt;
     }
-    p->Dp = (int)round_up((size_t)p->D, kGemmBN);
+    p->Dh = (p->D + 1) / 2;
+    p->Dhp = (int)round_up((size_t)p->Dh, 64);
     int cfg = env_forced_config();
     if (cfg < 0) {
         auto t = R.tuned.find(key);
         cfg = (t != R.tuned.end()) ? t->second : default_config(p->N);
     }
-    if (!shape_params(cfg, p->cs, p->N, &p->WL, &p->KB, &p->tiles_x, &p->tiles_y)) {
-        // fall back to the shape with the smallest window, else refuse
+    ShapeParams sp;
+    if (!shape_params(cfg, p->cs, p->N, &sp)) {
+        // fall back to any shape whose window fits, else refuse
         bool ok = false;
-        for (int c = kNumTileConfigs - 1; c >= 0 && !ok; --c)
-            if (shape_params(c, p->cs, p->N, &p->WL, &p->KB, &p->tiles_x, &p->tiles_y)) {
+        for (int c = 0; c < kNumTileConfigs && !ok; ++c)
+            if (shape_params(c, p->cs, p->N, &sp)) {
                 cfg = c;
                 ok = true;
             }
         if (!ok) return FBP_EUNSUPPORTED;
     }
-    p->cfg = cfg;
+    apply_shape(p.get(), cfg, sp);
+    std::vector<float> cs32(p->cs.size());
+    for (size_t i = 0; i < cs32.size(); ++i) cs32[i] = (float)p->cs[i];
     if (hipMalloc(&p->d_cs, sizeof(double) * p->cs.size()) != hipSuccess) return FBP_ENOMEM;
-    if (hipMemcpy(p->d_cs, p->cs.data(), sizeof(double) * p->cs.size(), hipMemcpyHostToDevice) !=
-        hipSuccess) {
+    if (hipMalloc(&p->d_cs32, sizeof(float) * cs32.size()) != hipSuccess) {
         (void)hipFree(p->d_cs);
+        return FBP_ENOMEM;
+    }
+    if (hipMemcpy(p->d_cs, p->cs.data(), sizeof(double) * p->cs.size(), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(p->d_cs32, cs32.data(), sizeof(float) * cs32.size(), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+        (void)hipFree(p->d_cs);
+        (void)hipFree(p->d_cs32);
         return FBP_EHIP;
     }
     *out = p.get();
@@ -278,7 +310,7 @@ uint16_t f16_bits_rne(float x) {
     return b;
 }
 
-// tap(d) = dt h(d) for |d| <= D-1 (Ram-Lak), stored at index d + Dp, d in [-Dp, Dp).
+// tap(d) = dt h(d): the Ram-Lak kernel times the bin width.
 double ramlak_tap(int d, double dt) {
     if (d == 0) return 1.0 / (4.0 * dt);
     if (d % 2 == 0) return 0.0;
@@ -286,17 +318,23 @@ double ramlak_tap(int d, double dt) {
     return -1.0 / (kPi * kPi * dd * dd * dt);
 }
 
+// Odd-tap table to(j) = tap(2j - 1) for j in [-Dhp, Dhp] (zero where |2j - 1| > D - 1),
+// stored at index j + Dhp in the operand precision, plus the centre tap.
 int ensure_taps(Plan* p, int prec) {
     std::lock_guard<std::mutex> lock(p->mu);
     if (p->d_taps[prec]) return FBP_OK;
-    const int Dp = p->Dp, D = p->D;
-    std::vector<double> taps(2 * (size_t)Dp, 0.0);
-    for (int d = -(D - 1); d <= D - 1; ++d) taps[(size_t)(d + Dp)] = ramlak_tap(d, p->dt);
+    const int Dhp = p->Dhp, D = p->D;
+    std::vector<double> taps(2 * (size_t)Dhp + 1, 0.0);
+    for (int j = -Dhp; j <= Dhp; ++j) {
+        const int d = 2 * j - 1;
+        if (d >= -(D - 1) && d <= D - 1) taps[(size_t)(j + Dhp)] = ramlak_tap(d, p->dt);
+    }
+    const double centre = ramlak_tap(0, p->dt);
     void* dev = nullptr;
     size_t bytes = 0;
     std::vector<float> f32;
     std::vector<uint16_t> h16;
-    float out_scale = 1.0f;
+    float out_scale = 1.0f, diag = (float)centre;
     if (prec == kFP32) {
         f32.resize(taps.size());
         for (size_t i = 0; i < taps.size(); ++i) f32[i] = (float)taps[i];
@@ -306,17 +344,14 @@ int ensure_taps(Plan* p, int prec) {
         if (prec == kFP16) {
             // Pre-scale by 2^s so the smallest nonzero tap is a normal binary16 number
             // (>= 2^-14) while the largest stays below 2^15.
-            double tmax = 0.0, tmin = 1e300;
+            double tmax = std::fabs(centre), tmin = std::fabs(centre);
             for (double v : taps)
                 if (v != 0.0) {
                     tmax = std::max(tmax, std::fabs(v));
                     tmin = std::min(tmin, std::fabs(v));
                 }
-            int s = 0;
-            if (tmax > 0.0) {
-                s = (int)std::ceil(-14.0 - std::log2(tmin));
-                s = std::min(s, (int)std::floor(15.0 - std::log2(tmax)));
-            }
+            int s = (int)std::ceil(-14.0 - std::log2(tmin));
+            s = std::min(s, (int)std::floor(15.0 - std::log2(tmax)));
             scale = std::ldexp(1.0, s);
             out_scale = (float)std::ldexp(1.0, -s);
         }
@@ -324,6 +359,13 @@ int ensure_taps(Plan* p, int prec) {
         for (size_t i = 0; i < taps.size(); ++i) {
             const float v = (float)(taps[i] * scale);
             h16[i] = (prec == kBF16) ? bf16_bits_rne(v) : f16_bits_rne(v);
+        }
+        const float c = (float)(centre * scale);
+        if (prec == kBF16) {
+            const uint32_t u = (uint32_t)bf16_bits_rne(c) << 16;
+            std::memcpy(&diag, &u, 4);
+        } else {
+            diag = (float)(_Float16)c;
         }
         bytes = h16.size() * 2;
     }
@@ -334,6 +376,7 @@ int ensure_taps(Plan* p, int prec) {
         return FBP_EHIP;
     }
     p->out_scale[prec] = out_scale;
+    p->diag[prec] = diag;
     p->d_taps[prec] = dev;
     return FBP_OK;
 }
@@ -347,7 +390,9 @@ GemmJob gemm_job(const Plan& p, int prec, const float* sino, float* filt, int ro
     j.taps = p.d_taps[prec];
     j.R = rows;
     j.D = p.D;
-    j.Dp = p.Dp;
+    j.Dh = p.Dh;
+    j.Dhp = p.Dhp;
+    j.diag = p.diag[prec];
     j.out_scale = p.out_scale[prec];
     j.tiles_n = (p.D + kGemmBN - 1) / kGemmBN;
     return j;
@@ -358,6 +403,7 @@ BpJob bp_job(const Plan& p, const float* filt, float* img) {
     j.q = filt;
     j.img = img;
     j.cs = p.d_cs;
+    j.cs32 = p.d_cs32;
     j.half_pix = 0.5 * (double)(p.N - 1);
     j.centre_det = 0.5 * (double)(p.D - 1);
     j.N = p.N;
@@ -365,6 +411,7 @@ BpJob bp_job(const Plan& p, const float* filt, float* img) {
     j.D = p.D;
     j.WL = p.WL;
     j.KB = p.KB;
+    j.rw_shift = p.rw_shift;
     j.tiles_x = p.tiles_x;
     j.scale = (float)(kPi / (double)p.K);
     return j;
@@ -623,7 +670,7 @@ int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes,
     int32_t* bidx = reinterpret_cast<int32_t*>(img.data() + L.bp_index);
     int32_t* bpre = reinterpret_cast<int32_t*>(img.data() + L.bp_prefix);
 
-    int max_dp = 0, max_bp_lds = 0;
+    int max_dh = 0, max_bp_lds = 0;
     uint32_t mask = 0;
     int64_t gemm_tiles = 0;
     gp[0] = 0;
@@ -635,8 +682,8 @@ int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes,
         if (gemm_tiles > INT32_MAX) return FBP_EUNSUPPORTED;
         gp[i + 1] = (int32_t)gemm_tiles;
         bj[i] = bp_job(p, q, jobs[i].image);
-        max_dp = std::max(max_dp, p.Dp);
-        max_bp_lds = std::max(max_bp_lds, bp_lds_bytes(p.WL, p.KB));
+        max_dh = std::max(max_dh, p.Dh);
+        max_bp_lds = std::max(max_bp_lds, bp_lds_bytes(p.cfg, p.WL, p.KB));
         mask |= 1u << p.cfg;
     }
     // Per tile shape: jobs in descending cost order (angles x per-tile work), ties by index.
@@ -688,7 +735,7 @@ int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes,
     key.prec = prec;
     key.ws = reinterpret_cast<uintptr_t>(ws);
     key.cfg_mask = mask;
-    key.gemm_lds = (int)round_up((size_t)gemm_lds_bytes(prec, max_dp), 8192);
+    key.gemm_lds = (int)round_up((size_t)gemm_lds_bytes(prec, max_dh), 8192);
     key.bp_lds = (int)round_up((size_t)max_bp_lds, 4096);
     return launch_batch(key, cu_count(device), s);
 }
@@ -706,16 +753,20 @@ int autotune(const fbp_geom* g, hipStream_t s, int32_t* out_cfg) {
         cs[2 * k + 1] = std::sin(g->angles[k]) / g->det_spacing;
     }
     const size_t qb = sino_bytes(g, 1), ib = image_bytes(g, 1);
-    float *q = nullptr, *im = nullptr;
+    std::vector<float> cs32(cs.size());
+    for (size_t i = 0; i < cs.size(); ++i) cs32[i] = (float)cs[i];
+    float *q = nullptr, *im = nullptr, *dcs32 = nullptr;
     double* dcs = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int best = -1;
     float best_ms = 0.0f;
     rc = FBP_OK;
     if (hipMalloc(&q, qb) != hipSuccess || hipMalloc(&im, ib) != hipSuccess ||
-        hipMalloc(&dcs, sizeof(double) * cs.size()) != hipSuccess) {
+        hipMalloc(&dcs, sizeof(double) * cs.size()) != hipSuccess ||
+        hipMalloc(&dcs32, sizeof(float) * cs32.size()) != hipSuccess) {
         rc = FBP_ENOMEM;
     } else if (hipMemcpy(dcs, cs.data(), sizeof(double) * cs.size(), hipMemcpyHostToDevice) != hipSuccess ||
+               hipMemcpy(dcs32, cs32.data(), sizeof(float) * cs32.size(), hipMemcpyHostToDevice) != hipSuccess ||
                hipMemsetAsync(q, 0, qb, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
                hipEventCreate(&e1) != hipSuccess) {
         rc = FBP_EHIP;
@@ -727,9 +778,11 @@ int autotune(const fbp_geom* g, hipStream_t s, int32_t* out_cfg) {
         p.dt = g->det_spacing;
         p.cs = cs;
         p.d_cs = dcs;
+        p.d_cs32 = dcs32;
         for (int c = 0; c < kNumTileConfigs && rc == FBP_OK; ++c) {
-            if (!shape_params(c, cs, p.N, &p.WL, &p.KB, &p.tiles_x, &p.tiles_y)) continue;
-            p.cfg = c;
+            ShapeParams sp;
+            if (!shape_params(c, cs, p.N, &sp)) continue;
+            apply_shape(&p, c, sp);
             const BpJob job = bp_job(p, q, im);
             float ms_min = 1e30f;
             for (int rep = 0; rep < 7 && rc == FBP_OK; ++rep) {
@@ -756,6 +809,7 @@ int autotune(const fbp_geom* g, hipStream_t s, int32_t* out_cfg) {
     if (q) (void)hipFree(q);
     if (im) (void)hipFree(im);
     if (dcs) (void)hipFree(dcs);
+    if (dcs32) (void)hipFree(dcs32);
     if (rc != FBP_OK) return rc;
     if (best < 0) return FBP_EUNSUPPORTED;
     {
@@ -914,8 +968,10 @@ int fbp_backproject_with_config(const fbp_geom* geom, int32_t n_slices, const fl
     q.N = p->N;
     q.dt = p->dt;
     q.d_cs = p->d_cs;
-    if (!shape_params(config, p->cs, p->N, &q.WL, &q.KB, &q.tiles_x, &q.tiles_y)) return FBP_EUNSUPPORTED;
-    q.cfg = config;
+    q.d_cs32 = p->d_cs32;
+    ShapeParams sp;
+    if (!shape_params(config, p->cs, p->N, &sp)) return FBP_EUNSUPPORTED;
+    apply_shape(&q, config, sp);
     const BpJob job = bp_job(q, d_filtered, d_image);
     return run_backproject(q, n_slices, d_filtered, d_image, (hipStream_t)hip_stream, config, &job);
 }

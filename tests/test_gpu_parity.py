@@ -154,8 +154,53 @@ def test_reconstruct_equals_filter_then_backproject():
     assert np.array_equal(whole[1:2], single)
 
 
-@pytest.mark.parametrize("prec,min_psnr", [("bf16", 30.0), ("fp16", 50.0)])
-def test_reduced_precision_filter_error_is_stated(prec, min_psnr):
+def _bf16(x):
+    """float32 -> bfloat16 round-to-nearest-even, returned as float64."""
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _rounded_operand_filter(P32, dt, prec):
+    """Reference for the 16-bit modes: the oracle's taps and the FP32 rows rounded to the
+    operand type as the library specifies (taps via FP32, RNE; FP16 taps pre-scaled by 2^s,
+    s the smallest power keeping the smallest nonzero tap normal), products summed in FP64."""
+    B, K, D = P32.shape
+    e = np.zeros(2 * D - 1)
+    e[D - 1] = 1.0
+    taps = oracle.ramlak_filter(e, dt)          # index d + D - 1, d in [-(D-1), D-1]
+    if prec == "bf16":
+        tq, Pq, scale = _bf16(np.float32(taps)), _bf16(P32), 1.0
+    else:
+        nz = np.abs(taps[taps != 0])
+        s = math.ceil(-14 - math.log2(nz.min()))
+        s = min(s, math.floor(15 - math.log2(nz.max())))
+        tq = np.float32(taps * 2.0 ** s).astype(np.float16).astype(np.float64)
+        Pq = P32.astype(np.float16).astype(np.float64)
+        scale = 2.0 ** -s
+    Q = np.empty((B, K, D))
+    for b in range(B):
+        for k in range(K):
+            Q[b, k] = np.convolve(Pq[b, k], tq)[D - 1:2 * D - 1] * scale
+    return Q, np.abs(tq).sum() * scale
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("K,D,dt", [(40, 725, 1.0), (9, 183, 0.8), (3, 1451, 1.0), (5, 3, 1.0)])
+def test_reduced_precision_filter_matches_rounded_operands(prec, K, D, dt):
+    P32 = ph.rng_for(1003, D).uniform(-20, 420, size=(2, K, D)).astype(np.float32)
+    g = fbp.Geometry(K, D, 8, dt)
+    got = host(fbp.fbp_filter(g, dev(P32), precision=prec))
+    ref, tap_l1 = _rounded_operand_filter(P32, dt, prec)
+    tol = D * 2.0 ** -24 * np.max(np.abs(P32)) * tap_l1 + 1e-7
+    err = np.max(np.abs(got - ref))
+    assert err <= tol, f"{prec}: max err {err:.3e} > {tol:.3e}"
+
+
+@pytest.mark.parametrize("prec,min_psnr", [("bf16", 24.0), ("fp16", 65.0)])
+def test_reduced_precision_reconstruction_error_is_stated(prec, min_psnr):
+    """C2 slice: BF16 operands give ~25.8 dB (BF16 taps no longer sum to zero, so the
+    filter leaks the large smooth sinogram into Q), FP16 with pre-scaled taps ~67.7 dB."""
     sl = configs.c2_slice()
     g = fbp.Geometry(sl.K, sl.D, sl.N, sl.dt, sl.angles)
     got = host(fbp.fbp_reconstruct(g, dev(sl.sino[None]), precision=prec))[0]
