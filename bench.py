@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="after the timed region, one device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -65,11 +67,18 @@ def recorded_traffic(updates_per_launch: int):
 
 
 def time_launches(fn, stream, n: int) -> float:
-    """Average duration (ms) of n launches of fn, timed with HIP events on `stream`."""
+    """Average device duration (ms) of n back-to-back launches of fn on `stream`.
+
+    A long blocker kernel is queued first so that all n launches are enqueued before
+    the first one starts: the events then see device time, not host launch gaps.
+    """
     import torch
+    blocker = torch.empty((4096, 4096), device="cuda")
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     with torch.cuda.stream(stream):
+        for _ in range(2):
+            blocker = blocker @ blocker.T   # ~ms of work ahead of the timed launches
         e0.record(stream)
         for _ in range(n):
             fn()
@@ -155,7 +164,7 @@ def main():
 
     # dominant kernel alone (backprojection) and the filter GEMM alone, same stream
     fbp.fbp_filter(geom, sino, out=filt, precision=args.precision)
-    n_k = max(20, args.steps)
+    n_k = 20
     bp_ms = time_launches(lambda: fbp.fbp_backproject(geom, filt, out=img), stream, n_k)
     flt_ms = time_launches(lambda: fbp.fbp_filter(geom, sino, out=filt, precision=args.precision),
                            stream, n_k)
@@ -163,7 +172,11 @@ def main():
     traffic = recorded_traffic(updates)
     gemm_flops = 2.0 * sl.K * sl.D * sl.D
 
-    result_img = None
+    if args.copy_mb > 0:
+        src = torch.empty(args.copy_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     fbp.fbp_reconstruct(geom, sino, out=img, workspace=ws, precision=args.precision)
     torch.cuda.synchronize()
     result_img = img[0].cpu().numpy().astype(np.float64)

@@ -23,6 +23,8 @@
 //    at the end.  This gives a single 512^2 slice enough waves per CU.
 //  * The next block's filtered rows are loaded into registers while the current
 //    block is computed, so the global-load latency hides behind the LDS work.
+//    The loads are buffer loads whose range check supplies the zeros beyond the
+//    detector ends, so staging has no compares or branches.
 //  * Each pixel is written once by one lane; no atomics.  The summation order
 //    depends only on the tile shape, which is fixed per geometry, so repeated and
 //    batched calls are bitwise identical.
@@ -45,6 +47,10 @@ __device__ __forceinline__ int xcd_logical(int b, int G) {
     const int extra = G & 7;
     return x * per + min(x, extra) + slot;
 }
+
+// Word 3 of a raw (stride 0) buffer resource: 32-bit data format, no swizzle; reads
+// at byte offsets >= num_records return 0.
+constexpr int kBufferWord3 = 0x00020000;
 
 // LDS layout: prm_b[2][kMaxKB] floats, prm_i[2][kMaxKB] ints, then the window
 // (float4 [KB][WL]), which the final cross-group reduction reuses.
@@ -73,17 +79,24 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
     const int lx = tl % TW;
     const int ly0 = (tl / TW) * P;
     const int N = job.N, K = job.K, D = job.D, WL = job.WL, KB = job.KB;
-    const int rw_shift = job.rw_shift;
     const double x0 = (double)c0 - job.half_pix;
     const double y0 = (double)r0 - job.half_pix;
     const float flx = (float)lx;
     const float fly = (float)ly0;
     const float* __restrict__ cs32 = job.cs32;
 
-    // staging coordinates of this thread: bin sj of angles sa0, sa0 + sstep, ...
-    const int sj = t & ((1 << rw_shift) - 1);
-    const int sa0 = t >> rw_shift;
-    const int sstep = NT >> rw_shift;
+    // Staging: one wave fills one segment of 63 window bins of one angle per pass.
+    // Lane j loads bin i0 + 63 seg + j of the forward row and the mirrored bin of the
+    // reversed row with single-dword buffer loads; a per-row buffer resource of D
+    // floats returns 0 outside the detector, which is the zero extension of the
+    // filtered row.  The value at bin + 1 comes from the next lane (ds_bpermute), so
+    // 64 lanes produce 63 (A, dL) pairs per direction.
+    constexpr int W = NT / 64;                  // waves per workgroup
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int lane = t & 63;
+    const int seg_shift = job.seg_shift;        // log2(segments per angle)
+    const int nxt = ((lane + 1) & 63) << 2;     // ds_bpermute source: lane + 1
+    const int d4 = (D - 1) * 4;
 
     float accf[P], accr[P];
 #pragma unroll
@@ -105,32 +118,39 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
             prm_i[buf * kMaxKB + t] = i0;
         }
     };
-    float pf[kStageE][4];
+    float pf[kStageE], pr[kStageE];
     auto load = [&](int kb, int buf) {
-        const int nb = min(KB, K - kb);
+        const int nslot = min(KB, K - kb) << seg_shift;
 #pragma unroll
         for (int e = 0; e < kStageE; ++e) {
-            const int a = sa0 + e * sstep;
-            if (a < nb && sj < WL) {
-                const int g = prm_i[buf * kMaxKB + a] + sj;
-                const float* __restrict__ row = q + (size_t)(kb + a) * (size_t)D;
-                pf[e][0] = ld_zero(row, g, D);
-                pf[e][1] = ld_zero(row, g + 1, D);
-                pf[e][2] = ld_zero(row, D - 1 - g, D);
-                pf[e][3] = ld_zero(row, D - 2 - g, D);
+            const int slot = wave + e * W;                       // wave-uniform
+            if (slot < nslot) {
+                const int a = slot >> seg_shift;
+                const int seg = slot & ((1 << seg_shift) - 1);
+                const __amdgpu_buffer_rsrc_t row = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<float*>(q + (size_t)(kb + a) * (size_t)D), (short)0, D * 4, kBufferWord3);
+                const int g4 = (prm_i[buf * kMaxKB + a] + 63 * seg + lane) * 4;
+                pf[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(row, g4, 0, 0));
+                pr[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(row, d4 - g4, 0, 0));
             }
         }
     };
     auto store = [&](int kb) {
-        const int nb = min(KB, K - kb);
-        const float jj = (float)sj;
+        const int nslot = min(KB, K - kb) << seg_shift;
 #pragma unroll
         for (int e = 0; e < kStageE; ++e) {
-            const int a = sa0 + e * sstep;
-            if (a < nb && sj < WL) {
-                const float df = pf[e][1] - pf[e][0];
-                const float db = pf[e][3] - pf[e][2];
-                win[a * WL + sj] = make_float4(fmaf(-jj, df, pf[e][0]), df, fmaf(-jj, db, pf[e][2]), db);
+            const int slot = wave + e * W;
+            if (slot < nslot) {
+                const int a = slot >> seg_shift;
+                const int j = 63 * (slot & ((1 << seg_shift) - 1)) + lane;
+                const float f1 = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(nxt, __builtin_bit_cast(int, pf[e])));
+                const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(nxt, __builtin_bit_cast(int, pr[e])));
+                if (lane < 63 && j < WL) {
+                    const float df = f1 - pf[e];
+                    const float db = r1 - pr[e];
+                    const float jj = (float)j;
+                    win[a * WL + j] = make_float4(fmaf(-jj, df, pf[e]), df, fmaf(-jj, db, pr[e]), db);
+                }
             }
         }
     };

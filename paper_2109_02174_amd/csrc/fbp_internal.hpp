@@ -20,7 +20,7 @@ struct BpJob {
     int32_t N, K, D;
     int32_t WL;           // window length (bins) staged per angle for this job's tile shape
     int32_t KB;           // angles staged per LDS block
-    int32_t rw_shift;     // log2 of the staging row width (power of two >= WL)
+    int32_t seg_shift;    // log2 of the 63-bin staging segments per angle (>= WL / 63)
     int32_t tiles_x;      // tile columns of the half image
     float scale;          // pi/K
 };

@@ -112,7 +112,7 @@ struct Plan {
     float out_scale[3] = {1.0f, 1.0f, 1.0f};
     float diag[3] = {0.0f, 0.0f, 0.0f};
     int cfg = 0;
-    int WL = 0, KB = 0, rw_shift = 0;
+    int WL = 0, KB = 0, seg_shift = 0;
     int tiles_x = 0, tiles_y = 0;
     std::mutex mu;
 };
@@ -144,7 +144,7 @@ double span_for(const TileShape& s, const std::vector<double>& cs) {
 
 // Window length, staging row width and angle block of a tile id for a geometry.
 struct ShapeParams {
-    int WL = 0, KB = 0, rw_shift = 0, tiles_x = 0, tiles_y = 0;
+    int WL = 0, KB = 0, seg_shift = 0, tiles_x = 0, tiles_y = 0;
 };
 
 bool shape_params(int cfg, const std::vector<double>& cs, int N, ShapeParams* sp) {
@@ -152,12 +152,12 @@ bool shape_params(int cfg, const std::vector<double>& cs, int N, ShapeParams* sp
     const double span = span_for(s, cs);
     if (!(span < 1e6)) return false;
     sp->WL = window_length(span);
-    const int nt = kGroupThreads * s.s;
+    // staging: one wave per (angle, 63-bin segment) per pass, kStageE passes per block
+    const int waves = kGroupThreads * s.s / 64;
     int shift = 0;
-    while ((1 << shift) < sp->WL) ++shift;
-    if ((1 << shift) > nt) return false;          // one staging row per workgroup pass at least
-    sp->rw_shift = shift;
-    const int kb_stage = kStageE * (nt >> shift);
+    while (63 * (1 << shift) < sp->WL) ++shift;
+    sp->seg_shift = shift;
+    const int kb_stage = (kStageE * waves) >> shift;
     const int kb_lds = (kBpLdsBudget - kBpPrmBytes) / (16 * sp->WL);
     sp->KB = std::min(kMaxKB, std::min(kb_stage, kb_lds));
     if (sp->KB < 1) return false;
@@ -171,7 +171,7 @@ void apply_shape(Plan* p, int cfg, const ShapeParams& sp) {
     p->cfg = cfg;
     p->WL = sp.WL;
     p->KB = sp.KB;
-    p->rw_shift = sp.rw_shift;
+    p->seg_shift = sp.seg_shift;
     p->tiles_x = sp.tiles_x;
     p->tiles_y = sp.tiles_y;
 }
@@ -411,7 +411,7 @@ BpJob bp_job(const Plan& p, const float* filt, float* img) {
     j.D = p.D;
     j.WL = p.WL;
     j.KB = p.KB;
-    j.rw_shift = p.rw_shift;
+    j.seg_shift = p.seg_shift;
     j.tiles_x = p.tiles_x;
     j.scale = (float)(kPi / (double)p.K);
     return j;

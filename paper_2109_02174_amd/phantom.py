@@ -90,6 +90,23 @@ def ellipse_sinogram(ellipses, N: int, D: int, dt: float, angles) -> np.ndarray:
     return sino
 
 
+def ellipse_sinogram_device(ellipses, N: int, D: int, dt: float, angles, device="cuda"):
+    """ellipse_sinogram evaluated with torch in FP64 on `device` (same formula, all
+    ellipses at once); for generating large synthetic workloads directly in HBM."""
+    import torch
+    f64 = torch.float64
+    ang = torch.as_tensor(np.asarray(angles, dtype=np.float64), dtype=f64, device=device).view(1, -1, 1)
+    t = torch.as_tensor(detector_coords(D, dt), dtype=f64, device=device).view(1, 1, -1)
+    half = 0.5 * N
+    prm = torch.tensor([[e.a * half, e.b * half, e.cx * half, e.cy * half, e.phi, e.rho] for e in ellipses],
+                       dtype=f64, device=device).view(-1, 6, 1, 1)
+    A, B, x0, y0, phi, rho = (prm[:, i] for i in range(6))
+    s2 = (A * torch.cos(ang - phi)) ** 2 + (B * torch.sin(ang - phi)) ** 2
+    tau = t - x0 * torch.cos(ang) - y0 * torch.sin(ang)
+    rad = torch.clamp(s2 - tau * tau, min=0.0)
+    return (2.0 * rho * A * B * torch.sqrt(rad) / s2).sum(dim=0)
+
+
 def rasterise(ellipses, N: int) -> np.ndarray:
     """Pixel-centre point samples [N][N] of the phantom (rows = y, columns = x)."""
     half = 0.5 * N
