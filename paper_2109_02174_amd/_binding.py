@@ -95,9 +95,16 @@ class Geometry:
         self.angles = np.ascontiguousarray(self.angles, dtype=np.float64)
 
     def as_c(self) -> c_geom:
-        g = c_geom(int(self.n_angles), int(self.n_det), int(self.image_size), float(self.det_spacing),
+        """The C struct (cached; the angle array is kept alive with it)."""
+        key = (int(self.n_angles), int(self.n_det), int(self.image_size), float(self.det_spacing),
+               self.angles.ctypes.data)
+        cached = getattr(self, "_c_cache", None)
+        if cached is not None and cached[0] == key:
+            return cached[1]
+        g = c_geom(key[0], key[1], key[2], key[3],
                    self.angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
-        g._keep = self.angles   # keep the host array alive with the struct
+        g._keep = self.angles
+        self._c_cache = (key, g)
         return g
 
 

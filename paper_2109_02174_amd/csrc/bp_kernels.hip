@@ -19,8 +19,10 @@
 //    interpolated value at local coordinate u in [j, j+1) is A_j + u dL_j: one
 //    FMA, no fraction.  One ds_read_b128 returns both directions.
 //  * The workgroup has S groups of 256 lanes over the same pixels; group g takes
-//    every S-th angle of a block, and the S partial sums are added in fixed order
-//    at the end.  This gives a single 512^2 slice enough waves per CU.
+//    the g-th contiguous quarter (for S = 4) of every staged block, and the S
+//    partial sums are added in fixed order at the end.  This gives a single 512^2
+//    slice enough waves per CU.  Per-angle constants come from LDS (not scalar
+//    loads, which would force full LDS drains inside the loop).
 //  * The next block's filtered rows are loaded into registers while the current
 //    block is computed, so the global-load latency hides behind the LDS work.
 //    The loads are buffer loads whose range check supplies the zeros beyond the
@@ -52,8 +54,9 @@ __device__ __forceinline__ int xcd_logical(int b, int G) {
 // at byte offsets >= num_records return 0.
 constexpr int kBufferWord3 = 0x00020000;
 
-// LDS layout: prm_b[2][kMaxKB] floats, prm_i[2][kMaxKB] ints, then the window
-// (float4 [KB][WL]), which the final cross-group reduction reuses.
+// LDS layout: prm[2][kMaxKB] float4 {b, cos/dt, sin/dt, i0 bits} per angle of the
+// current and next block, then the window (float4 [KB][WL]), which the final
+// cross-group reduction reuses.
 constexpr int kPrmBytes = kBpPrmBytes;
 
 template <int TW, int P, int S>
@@ -69,8 +72,7 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
     using Sh = Shape<TW, P, S>;
     constexpr int NT = Sh::NT;
     constexpr int TH = Sh::TH;
-    float* prm_b = reinterpret_cast<float*>(smem);                      // [2][kMaxKB]
-    int* prm_i = reinterpret_cast<int*>(smem + 2 * kMaxKB * 4);         // [2][kMaxKB]
+    float4* prm = reinterpret_cast<float4*>(smem);                      // [2][kMaxKB]
     float4* win = reinterpret_cast<float4*>(smem + kPrmBytes);
 
     const int t = threadIdx.x;
@@ -83,7 +85,6 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
     const double y0 = (double)r0 - job.half_pix;
     const float flx = (float)lx;
     const float fly = (float)ly0;
-    const float* __restrict__ cs32 = job.cs32;
 
     // Staging: one wave fills one segment of 63 window bins of one angle per pass.
     // Lane j loads bin i0 + 63 seg + j of the forward row and the mirrored bin of the
@@ -114,8 +115,8 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
             const double uo = x0 * cd + y0 * sd + job.centre_det;
             const double umin = uo + fmin(0.0, (double)(TW - 1) * cd) + fmin(0.0, (double)(TH - 1) * sd);
             const int i0 = (int)floor(umin) - 1;
-            prm_b[buf * kMaxKB + t] = (float)(uo - (double)i0);
-            prm_i[buf * kMaxKB + t] = i0;
+            prm[buf * kMaxKB + t] = make_float4((float)(uo - (double)i0), (float)cd, (float)sd,
+                                                __int_as_float(i0));
         }
     };
     float pf[kStageE], pr[kStageE];
@@ -129,7 +130,7 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
                 const int seg = slot & ((1 << seg_shift) - 1);
                 const __amdgpu_buffer_rsrc_t row = __builtin_amdgcn_make_buffer_rsrc(
                     const_cast<float*>(q + (size_t)(kb + a) * (size_t)D), (short)0, D * 4, kBufferWord3);
-                const int g4 = (prm_i[buf * kMaxKB + a] + 63 * seg + lane) * 4;
+                const int g4 = (__float_as_int(prm[buf * kMaxKB + a].w) + 63 * seg + lane) * 4;
                 pf[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(row, g4, 0, 0));
                 pr[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(row, d4 - g4, 0, 0));
             }
@@ -166,17 +167,19 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
         if (k0 + KB < K) params(k0 + KB, buf ^ 1);
         __syncthreads();
         if (k0 + KB < K) load(k0 + KB, buf ^ 1);
-        const float* __restrict__ pb = prm_b + buf * kMaxKB;
-        const float* __restrict__ cb = cs32 + 2 * k0;
-#pragma unroll 2
-        for (int a = grp; a < nb; a += S) {
-            const float cf = cb[2 * a];
-            const float sf = cb[2 * a + 1];
-            const float u0 = fmaf(flx, cf, fmaf(fly, sf, pb[a]));
+        // group grp takes the contiguous angles [a_lo, a_hi) of this block
+        const int per = (nb + S - 1) / S;
+        const int a_lo = min(nb, grp * per);
+        const int a_hi = min(nb, a_lo + per);
+        const float4* __restrict__ pa = prm + buf * kMaxKB;
+#pragma unroll 4
+        for (int a = a_lo; a < a_hi; ++a) {
+            const float4 p = pa[a];
+            const float u0 = fmaf(flx, p.y, fmaf(fly, p.z, p.x));
             const float4* __restrict__ w = win + a * WL;
 #pragma unroll
             for (int i = 0; i < P; ++i) {
-                const float u = (i == 0) ? u0 : fmaf((float)i, sf, u0);
+                const float u = (i == 0) ? u0 : fmaf((float)i, p.z, u0);
                 const int j = (int)u;   // u > 0: truncation is floor
                 const float4 v = w[j];
                 accf[i] += fmaf(u, v.y, v.x);

@@ -43,8 +43,8 @@ constexpr int kMaxKB = 64;
 constexpr int kStageE = 4;        // staged (angle, bin) elements per thread per block
 // Dynamic LDS budget of one backprojection workgroup (bytes).
 constexpr int kBpLdsBudget = 48 * 1024;
-// LDS bytes of the per-block window origins (two buffers of kMaxKB floats and ints).
-constexpr int kBpPrmBytes = 2 * kMaxKB * 8;
+// LDS bytes of the per-angle constants of the current and next block (float4 each).
+constexpr int kBpPrmBytes = 2 * kMaxKB * 16;
 
 const TileShape& tile_shape(int cfg);
 

@@ -17,8 +17,8 @@
 //
 // Workgroup: 256 lanes = 4 waves; tile = 32 rows x 64 output bins.  Wave w owns
 // rows 16 (w/2) .. +16 and the output bins of parity w%2 (two 16x16 MFMA blocks).
-// The next chunk of sinogram rows is loaded into registers while the current one
-// is multiplied.
+// A ring of register buffers keeps several chunks of sinogram rows in flight
+// while the current one is multiplied.
 //   FP32:       v_mfma_f32_16x16x4_f32, 32 inputs per parity per chunk.
 //   BF16/FP16:  v_mfma_f32_16x16x32_{bf16,f16}, 64 per parity per chunk; the rows
 //               are rounded to 16 bits (RNE) as they are staged, and the tap slice
@@ -76,6 +76,7 @@ __device__ __forceinline__ void store_block(const v4f& acc, const GemmJob& job, 
 // ---------------------------------------------------------------- FP32 operands
 
 constexpr int kK32 = 32;                  // inputs per parity per chunk
+constexpr int kPD = 4;                    // chunks in flight (register ring)
 constexpr int kAS32 = kK32 + 1;           // LDS row stride (floats)
 
 __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt, char* smem) {
@@ -95,42 +96,53 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
     __syncthreads();   // LDS reuse across tiles of a persistent workgroup
     for (int x = t; x < n_taps; x += kBpThreads) Bt[x] = taps[jlo + x + Dhp];
 
-    float pf[8];
-    auto load = [&](int c0) {   // original columns c0 .. c0+63 of rows m0 .. m0+31
+    // ring of kPD chunks of 64 input columns in registers: chunk c + kPD - 1 is
+    // loaded while chunk c is multiplied, hiding several chunks of load latency
+    float pf[kPD][8];
+    auto load = [&](float (&r)[8], int c0) {   // columns c0 .. c0+63 of rows m0 .. m0+31
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int e = t + i * kBpThreads;
             const int row = e >> 6, col = c0 + (e & 63);
             const int m = m0 + row;
-            pf[i] = (m < R && col < D) ? P[(size_t)m * D + col] : 0.0f;
+            r[i] = (m < R && col < D) ? P[(size_t)m * D + col] : 0.0f;
         }
     };
-    auto store = [&]() {
+    auto store = [&](const float (&r)[8]) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int e = t + i * kBpThreads;
             const int row = e >> 6, col = e & 63;
-            As[((col & 1) * kTM + row) * kAS32 + (col >> 1)] = pf[i];
+            As[((col & 1) * kTM + row) * kAS32 + (col >> 1)] = r[i];
         }
     };
 
     v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
     const float* __restrict__ Arow = As + ((1 - sg) * kTM + wm * 16 + (l & 15)) * kAS32 + (l >> 4);
     const int bbase = (l & 15) - (l >> 4) + sg - jlo + nh0;   // + 16 ntile - m'
-    load(0);
-    for (int c0 = 0; c0 < D; c0 += 2 * kK32) {
-        __syncthreads();
-        store();
-        __syncthreads();
-        if (c0 + 2 * kK32 < D) load(c0 + 2 * kK32);
-        const int mh0 = c0 >> 1;
+    const int nch = (D + 2 * kK32 - 1) / (2 * kK32);
 #pragma unroll
-        for (int kk = 0; kk < kK32; kk += 4) {
-            const float a = Arow[kk];
-            const float b0 = Bt[bbase - (mh0 + kk)];
-            const float b1 = Bt[bbase + 16 - (mh0 + kk)];
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc1, 0, 0, 0);
+    for (int c = 0; c < kPD - 1; ++c)
+        if (c < nch) load(pf[c], c * 2 * kK32);
+    for (int cb = 0; cb < nch; cb += kPD) {
+#pragma unroll
+        for (int u = 0; u < kPD; ++u) {
+            const int c = cb + u;
+            if (c < nch) {
+                if (c + kPD - 1 < nch) load(pf[(u + kPD - 1) % kPD], (c + kPD - 1) * 2 * kK32);
+                __syncthreads();
+                store(pf[u]);
+                __syncthreads();
+                const int mh0 = c * kK32;
+#pragma unroll
+                for (int kk = 0; kk < kK32; kk += 4) {
+                    const float a = Arow[kk];
+                    const float b0 = Bt[bbase - (mh0 + kk)];
+                    const float b1 = Bt[bbase + 16 - (mh0 + kk)];
+                    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc1, 0, 0, 0);
+                }
+            }
         }
     }
     store_block<kFP32>(acc0, job, m0 + wm * 16, nh0, sg);
@@ -140,6 +152,7 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
 // ---------------------------------------------------------------- 16-bit operands
 
 constexpr int kK16 = 64;                  // inputs per parity per chunk
+constexpr int kPD16 = 3;                  // chunks in flight (register ring)
 constexpr int kAS16 = kK16 + 8;           // LDS row stride (16-bit), 16-byte aligned rows
 
 __device__ __forceinline__ int copy_stride16(int mpad) { return (mpad + kHalfN + 8 + 7 + 7) & ~7; }
@@ -169,54 +182,63 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
         Tc[x] = (idx >= 0 && idx <= 2 * Dhp) ? taps[idx] : (unsigned short)0;
     }
 
-    float pf[16];
-    auto load = [&](int c0) {   // original columns c0 .. c0+127 of rows m0 .. m0+31
+    float pf[kPD16][16];
+    auto load = [&](float (&r)[16], int c0) {   // columns c0 .. c0+127 of rows m0 .. m0+31
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int e = t + i * kBpThreads;
             const int row = e >> 7, col = c0 + (e & 127);
             const int m = m0 + row;
-            pf[i] = (m < R && col < D) ? P[(size_t)m * D + col] : 0.0f;
+            r[i] = (m < R && col < D) ? P[(size_t)m * D + col] : 0.0f;
         }
     };
-    auto store = [&]() {
+    auto store = [&](const float (&r)[16]) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int e = t + i * kBpThreads;
             const int row = e >> 7, col = e & 127;
             As[((col & 1) * kTM + row) * kAS16 + (col >> 1)] =
-                (PREC == kBF16) ? to_bf16_rne(pf[i]) : to_f16_rne(pf[i]);
+                (PREC == kBF16) ? to_bf16_rne(r[i]) : to_f16_rne(r[i]);
         }
     };
 
     v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
     const unsigned short* Arow = As + ((1 - sg) * kTM + wm * 16 + (l & 15)) * kAS16 + 8 * (l >> 4);
     const int kq = 8 * (l >> 4);
-    load(0);
-    for (int c0 = 0; c0 < D; c0 += 2 * kK16) {
-        __syncthreads();
-        store();
-        __syncthreads();
-        if (c0 + 2 * kK16 < D) load(c0 + 2 * kK16);
-        const int mh0 = c0 >> 1;
+    const int nch = (D + 2 * kK16 - 1) / (2 * kK16);
 #pragma unroll
-        for (int ks = 0; ks < kK16; ks += 32) {
-            const v8u16 av = *reinterpret_cast<const v8u16*>(Arow + ks);
-            const int ya = (mh0 + ks + kq) - (nh0 + (l & 15)) - sg - ylo;
-            const int yb = ya - 16;
-            const int ca = ya & 7, cb = yb & 7;
-            const v8u16 b0 = *reinterpret_cast<const v8u16*>(Tc + ca * cstride + (ya - ca));
-            const v8u16 b1 = *reinterpret_cast<const v8u16*>(Tc + cb * cstride + (yb - cb));
-            if constexpr (PREC == kBF16) {
-                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av),
-                                                               __builtin_bit_cast(v8bf, b0), acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av),
-                                                               __builtin_bit_cast(v8bf, b1), acc1, 0, 0, 0);
-            } else {
-                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, av),
-                                                              __builtin_bit_cast(v8h, b0), acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, av),
-                                                              __builtin_bit_cast(v8h, b1), acc1, 0, 0, 0);
+    for (int c = 0; c < kPD16 - 1; ++c)
+        if (c < nch) load(pf[c], c * 2 * kK16);
+    for (int cb = 0; cb < nch; cb += kPD16) {
+#pragma unroll
+        for (int u = 0; u < kPD16; ++u) {
+            const int c = cb + u;
+            if (c < nch) {
+                if (c + kPD16 - 1 < nch) load(pf[(u + kPD16 - 1) % kPD16], (c + kPD16 - 1) * 2 * kK16);
+                __syncthreads();
+                store(pf[u]);
+                __syncthreads();
+                const int mh0 = c * kK16;
+#pragma unroll
+                for (int ks = 0; ks < kK16; ks += 32) {
+                    const v8u16 av = *reinterpret_cast<const v8u16*>(Arow + ks);
+                    const int ya = (mh0 + ks + kq) - (nh0 + (l & 15)) - sg - ylo;
+                    const int yb = ya - 16;
+                    const int ca = ya & 7, cb2 = yb & 7;
+                    const v8u16 b0 = *reinterpret_cast<const v8u16*>(Tc + ca * cstride + (ya - ca));
+                    const v8u16 b1 = *reinterpret_cast<const v8u16*>(Tc + cb2 * cstride + (yb - cb2));
+                    if constexpr (PREC == kBF16) {
+                        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av),
+                                                                       __builtin_bit_cast(v8bf, b0), acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av),
+                                                                       __builtin_bit_cast(v8bf, b1), acc1, 0, 0, 0);
+                    } else {
+                        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, av),
+                                                                      __builtin_bit_cast(v8h, b0), acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, av),
+                                                                      __builtin_bit_cast(v8h, b1), acc1, 0, 0, 0);
+                    }
+                }
             }
         }
     }

@@ -79,11 +79,14 @@ struct GeomKey {
 };
 
 uint64_t hash_angles(const double* a, int32_t K) {
-    uint64_t h = 1469598103934665603ull;  // FNV-1a over the bytes
-    const unsigned char* p = reinterpret_cast<const unsigned char*>(a);
-    for (size_t i = 0; i < (size_t)K * sizeof(double); ++i) {
-        h ^= p[i];
-        h *= 1099511628211ull;
+    // 64-bit word hash (multiply-xorshift); plans also compare the full angle list,
+    // so a collision can only make a lookup miss, never mix geometries.
+    uint64_t h = 0x9E3779B97F4A7C15ull ^ (uint64_t)K;
+    for (int32_t k = 0; k < K; ++k) {
+        uint64_t w;
+        std::memcpy(&w, a + k, 8);
+        h = (h ^ w) * 0xBF58476D1CE4E5B9ull;
+        h ^= h >> 31;
     }
     return h;
 }
