@@ -230,7 +230,7 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
 }
 
 template <int TW, int P, int S>
-__global__ __launch_bounds__(kGroupThreads * S) void bp_grid_kernel(BpJob job, size_t q_stride,
+__global__ __launch_bounds__(kGroupThreads * S, 2 * S) void bp_grid_kernel(BpJob job, size_t q_stride,
                                                                     size_t img_stride, int tiles_per_slice) {
     extern __shared__ float4 smem4[];
     char* smem = reinterpret_cast<char*>(smem4);
@@ -245,24 +245,25 @@ __global__ __launch_bounds__(kGroupThreads * S) void bp_grid_kernel(BpJob job, s
 }
 
 template <int TW, int P, int S>
-__global__ __launch_bounds__(kGroupThreads * S) void bp_list_kernel(const BpListArgs* __restrict__ args) {
+__global__ __launch_bounds__(kGroupThreads * S, 2 * S) void bp_list_kernel(const BpListArgs* __restrict__ args) {
     extern __shared__ float4 smem4[];
     char* smem = reinterpret_cast<char*>(smem4);
-    const BpListArgs a = *args;
+    const BpListArgs a = load_const(args);
     constexpr int TH = Shape<TW, P, S>::TH;
-    const int n_sel = a.counts[0];
+    const auto* __restrict__ prefix = as_const(a.tile_prefix);
+    const int n_sel = *as_const(a.counts);
     if (n_sel <= 0) return;
-    const int total = a.tile_prefix[n_sel];
+    const int total = prefix[n_sel];
     const int G = gridDim.x;
     for (int it = xcd_logical(blockIdx.x, G); it < total; it += G) {
-        // largest s with tile_prefix[s] <= it
+        // largest s with tile_prefix[s] <= it (uniform: scalar loads and branches)
         int lo = 0, hi = n_sel - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (a.tile_prefix[mid] <= it) lo = mid; else hi = mid - 1;
+            if (prefix[mid] <= it) lo = mid; else hi = mid - 1;
         }
-        const BpJob job = a.jobs[a.job_index[lo]];
-        const int tt = it - a.tile_prefix[lo];
+        const BpJob job = load_const(a.jobs + as_const(a.job_index)[lo]);
+        const int tt = it - prefix[lo];
         const int ty = tt / job.tiles_x;
         const int tx = tt - ty * job.tiles_x;
         bp_tile<TW, P, S>(job, job.q, job.img, tx * TW, ty * TH, smem);
@@ -277,6 +278,8 @@ constexpr TileShape kShapes[kNumTileConfigs] = {
     {32, 4, 32, 1, "32x32 tile, 4 px/lane, 1 angle group"},
     {16, 2, 32, 2, "16x32 tile, 2 px/lane, 2 angle groups"},
     {32, 2, 16, 1, "32x16 tile, 2 px/lane, 1 angle group"},
+    {16, 1, 16, 4, "16x16 tile, 1 px/lane, 4 angle groups"},
+    {16, 4, 64, 4, "16x64 tile, 4 px/lane, 4 angle groups"},
 };
 
 template <int TW, int P, int S>
@@ -313,7 +316,9 @@ constexpr int red_bytes() { return Shape<TW, P, S>::RED_BYTES; }
     X(3, 32, 1, 4)            \
     X(4, 32, 4, 1)            \
     X(5, 16, 2, 2)            \
-    X(6, 32, 2, 1)
+    X(6, 32, 2, 1)            \
+    X(7, 16, 1, 4)            \
+    X(8, 16, 4, 4)
 
 }  // namespace
 

@@ -7,6 +7,26 @@
 
 namespace fbp {
 
+// Read-only view of device data in the constant address space: uniform loads
+// through it compile to scalar loads (descriptor tables read by whole waves).
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* as_const(const T* p) {
+    return (const __attribute__((address_space(4))) T*)p;
+}
+
+// Copy of a descriptor struct read through the constant address space.
+template <typename T>
+__device__ __forceinline__ T load_const(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "descriptor size");
+    T v;
+    const __attribute__((address_space(4))) unsigned int* src =
+        (const __attribute__((address_space(4))) unsigned int*)p;
+    unsigned int* dst = reinterpret_cast<unsigned int*>(&v);
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(T) / 4; ++i) dst[i] = src[i];
+    return v;
+}
+
 // ------------------------------------------------------------------ backprojection
 
 // Everything one slice's backprojection needs, as the kernels see it.
@@ -38,7 +58,7 @@ struct TileShape {
 
 constexpr int kGroupThreads = 256;
 constexpr int kBpThreads = 256;   // threads of the GEMM workgroups
-constexpr int kNumTileConfigs = 7;
+constexpr int kNumTileConfigs = 9;
 constexpr int kMaxKB = 64;
 constexpr int kStageE = 4;        // staged (angle, bin) elements per thread per block
 // Dynamic LDS budget of one backprojection workgroup (bytes).

@@ -267,18 +267,19 @@ __global__ __launch_bounds__(kBpThreads) void gemm_grid_kernel(GemmJob job) {
 template <int PREC>
 __global__ __launch_bounds__(kBpThreads) void gemm_list_kernel(const GemmListArgs* __restrict__ args) {
     extern __shared__ float4 smem4[];
-    const GemmListArgs a = *args;
-    const int n_jobs = a.counts[0];
+    const GemmListArgs a = load_const(args);
+    const auto* __restrict__ prefix = as_const(a.tile_prefix);
+    const int n_jobs = *as_const(a.counts);
     if (n_jobs <= 0) return;
-    const int total = a.tile_prefix[n_jobs];
+    const int total = prefix[n_jobs];
     for (int it = blockIdx.x; it < total; it += gridDim.x) {
         int lo = 0, hi = n_jobs - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (a.tile_prefix[mid] <= it) lo = mid; else hi = mid - 1;
+            if (prefix[mid] <= it) lo = mid; else hi = mid - 1;
         }
-        const GemmJob job = a.jobs[lo];
-        const int tt = it - a.tile_prefix[lo];
+        const GemmJob job = load_const(a.jobs + lo);
+        const int tt = it - prefix[lo];
         const int tiles_m = (job.R + kTM - 1) / kTM;
         const int nt = tt / tiles_m, mt = tt - nt * tiles_m;
         gemm_tile<PREC>(job, mt, nt, reinterpret_cast<char*>(smem4));
