@@ -59,12 +59,19 @@ constexpr int kBufferWord3 = 0x00020000;
 // cross-group reduction reuses.
 constexpr int kPrmBytes = kBpPrmBytes;
 
-template <int TW, int P, int S>
+template <int TW, int P, int S, bool ROT = false>
 struct Shape {
     static constexpr int NT = kGroupThreads * S;
     static constexpr int TH = (kGroupThreads / TW) * P;
-    static constexpr int RED_BYTES = (S - 1) * kGroupThreads * 2 * P * 4;
+    static constexpr int NACC = ROT ? 4 : 2;                      // accumulators per pixel row
+    static constexpr int RED_BYTES = (S - 1) * kGroupThreads * NACC * P * 4;
+    static constexpr int XPOSE_BYTES = ROT ? 2 * TH * (TW + 1) * 4 : 0;
 };
+
+// LDS of the rotation-symmetric shapes: prm float4 {bU, bV, cos/dt, sin/dt} and
+// pri int2 {iU0, iV0} for the angle pairs of the current and next block, then the
+// windows.
+constexpr int kRotPrmBytes = kBpRotPrmBytes;
 
 template <int TW, int P, int S>
 __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restrict__ q,
@@ -229,27 +236,264 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
     }
 }
 
+
+// Rotation-symmetric variant for angle lists closed under +pi/2 (theta_{k+K/2} =
+// theta_k + pi/2) and even N.  The workgroup owns a tile T of the top-left image
+// quadrant and its three 90-degree rotations.  Rotating a pixel by +90 degrees
+// and its angle by +pi/2 leaves the ray coordinate unchanged, so for an angle
+// pair (theta, theta + pi/2) the four rotated copies of a pixel need only two
+// local coordinates, U = u_theta(p) and V = u_theta(R p):
+//     p     : theta fwd at U,   theta+pi/2 rev at V
+//     R^2 p : theta rev at U,   theta+pi/2 fwd at V
+//     R p   : theta fwd at V,   theta+pi/2 fwd at U
+//     R^3 p : theta rev at V,   theta+pi/2 rev at U
+// (R(x, y) = (-y, x); "rev" is the reversed filtered row, as for the point
+// reflection).  Each window bin holds both angles' forward and reversed (A, dL)
+// pairs in 32 bytes: 8 updates per 2 coordinates, 2 truncations, 4 ds_read_b128.
 template <int TW, int P, int S>
+__device__ __forceinline__ void bp_tile_rot4(const BpJob& job, const float* __restrict__ q,
+                                             float* __restrict__ img, int c0, int r0, char* smem) {
+    using Sh = Shape<TW, P, S, true>;
+    constexpr int NT = Sh::NT;
+    constexpr int TH = Sh::TH;
+    float4* prm = reinterpret_cast<float4*>(smem);                        // [2][kMaxKB]
+    int2* pri = reinterpret_cast<int2*>(smem + 2 * kMaxKB * 16);          // [2][kMaxKB]
+    float4* win = reinterpret_cast<float4*>(smem + kRotPrmBytes);         // [KB][2][WL][2]
+
+    const int t = threadIdx.x;
+    const int grp = __builtin_amdgcn_readfirstlane(t >> 8);
+    const int tl = t & (kGroupThreads - 1);
+    const int lx = tl % TW;
+    const int ly0 = (tl / TW) * P;
+    const int N = job.N, D = job.D, WL = job.WL, KB = job.KB;
+    const int K2 = job.K >> 1;                 // angle pairs (k, k + K/2)
+    const double x0 = (double)c0 - job.half_pix;
+    const double y0 = (double)r0 - job.half_pix;
+    const float flx = (float)lx;
+    const float fly = (float)ly0;
+    const float nfly = -fly;
+
+    constexpr int W = NT / 64;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int lane = t & 63;
+    const int seg_shift = job.seg_shift;
+    const int nxt = ((lane + 1) & 63) << 2;
+    const int d4 = (D - 1) * 4;
+
+    float acc0[P], acc1[P], acc2[P], acc3[P];   // p, R p, R^2 p, R^3 p
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        acc0[i] = 0.0f;
+        acc1[i] = 0.0f;
+        acc2[i] = 0.0f;
+        acc3[i] = 0.0f;
+    }
+
+    auto params = [&](int kb, int buf) {
+        const int nb = min(KB, K2 - kb);
+        if (t < nb) {
+            const double cd = job.cs[2 * (kb + t)];
+            const double sd = job.cs[2 * (kb + t) + 1];
+            const double uo = x0 * cd + y0 * sd + job.centre_det;
+            const double umin = uo + fmin(0.0, (double)(TW - 1) * cd) + fmin(0.0, (double)(TH - 1) * sd);
+            const double vo = x0 * sd - y0 * cd + job.centre_det;
+            const double vmin = vo + fmin(0.0, (double)(TW - 1) * sd) + fmin(0.0, -(double)(TH - 1) * cd);
+            const int iu = (int)floor(umin) - 1;
+            const int iv = (int)floor(vmin) - 1;
+            prm[buf * kMaxKB + t] = make_float4((float)(uo - (double)iu), (float)(vo - (double)iv),
+                                                (float)cd, (float)sd);
+            pri[buf * kMaxKB + t] = make_int2(iu, iv);
+        }
+    };
+    // staging slot = (pair a, window w in {U, V}, 63-bin segment): 4 single-dword
+    // buffer loads per lane (forward and reversed row of both angles)
+    float pf[kStageE][4];
+    auto load = [&](int kb, int buf) {
+        const int nslot = min(KB, K2 - kb) << (seg_shift + 1);
+#pragma unroll
+        for (int e = 0; e < kStageE; ++e) {
+            const int slot = wave + e * W;
+            if (slot < nslot) {
+                const int a = slot >> (seg_shift + 1);
+                const int w = (slot >> seg_shift) & 1;
+                const int seg = slot & ((1 << seg_shift) - 1);
+                const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<float*>(q + (size_t)(kb + a) * (size_t)D), (short)0, D * 4, kBufferWord3);
+                const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<float*>(q + (size_t)(kb + a + K2) * (size_t)D), (short)0, D * 4, kBufferWord3);
+                const int2 io = pri[buf * kMaxKB + a];
+                const int g4 = ((w ? io.y : io.x) + 63 * seg + lane) * 4;
+                pf[e][0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, g4, 0, 0));
+                pf[e][1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, d4 - g4, 0, 0));
+                pf[e][2] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, g4, 0, 0));
+                pf[e][3] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, d4 - g4, 0, 0));
+            }
+        }
+    };
+    auto store = [&](int kb) {
+        const int nslot = min(KB, K2 - kb) << (seg_shift + 1);
+#pragma unroll
+        for (int e = 0; e < kStageE; ++e) {
+            const int slot = wave + e * W;
+            if (slot < nslot) {
+                const int a = slot >> (seg_shift + 1);
+                const int w = (slot >> seg_shift) & 1;
+                const int j = 63 * (slot & ((1 << seg_shift) - 1)) + lane;
+                float nx[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    nx[c] = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(nxt, __builtin_bit_cast(int, pf[e][c])));
+                if (lane < 63 && j < WL) {
+                    const float jj = (float)j;
+                    float d[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) d[c] = nx[c] - pf[e][c];
+                    float4* dst = win + (((a * 2 + w) * WL + j) << 1);
+                    dst[0] = make_float4(fmaf(-jj, d[0], pf[e][0]), d[0], fmaf(-jj, d[1], pf[e][1]), d[1]);
+                    dst[1] = make_float4(fmaf(-jj, d[2], pf[e][2]), d[2], fmaf(-jj, d[3], pf[e][3]), d[3]);
+                }
+            }
+        }
+    };
+
+    __syncthreads();
+    params(0, 0);
+    __syncthreads();
+    load(0, 0);
+    int buf = 0;
+    for (int k0 = 0; k0 < K2; k0 += KB, buf ^= 1) {
+        const int nb = min(KB, K2 - k0);
+        store(k0);
+        if (k0 + KB < K2) params(k0 + KB, buf ^ 1);
+        __syncthreads();
+        if (k0 + KB < K2) load(k0 + KB, buf ^ 1);
+        const int per = (nb + S - 1) / S;
+        const int a_lo = min(nb, grp * per);
+        const int a_hi = min(nb, a_lo + per);
+        const float4* __restrict__ pa = prm + buf * kMaxKB;
+#pragma unroll 2
+        for (int a = a_lo; a < a_hi; ++a) {
+            const float4 p = pa[a];    // bU, bV, cos, sin
+            const float u0 = fmaf(flx, p.z, fmaf(fly, p.w, p.x));
+            const float v0 = fmaf(flx, p.w, fmaf(nfly, p.z, p.y));
+            const float4* __restrict__ wu = win + ((a * 2) * WL << 1);
+            const float4* __restrict__ wv = win + ((a * 2 + 1) * WL << 1);
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                const float u = (i == 0) ? u0 : fmaf((float)i, p.w, u0);
+                const float v = (i == 0) ? v0 : fmaf(-(float)i, p.z, v0);
+                const int ju = (int)u;   // both > 0: truncation is floor
+                const int jv = (int)v;
+                const float4 qu0 = wu[2 * ju], qu1 = wu[2 * ju + 1];
+                const float4 qv0 = wv[2 * jv], qv1 = wv[2 * jv + 1];
+                // theta term first, then theta + pi/2, for every pixel
+                acc0[i] += fmaf(u, qu0.y, qu0.x);
+                acc0[i] += fmaf(v, qv1.w, qv1.z);
+                acc2[i] += fmaf(u, qu0.w, qu0.z);
+                acc2[i] += fmaf(v, qv1.y, qv1.x);
+                acc1[i] += fmaf(v, qv0.y, qv0.x);
+                acc1[i] += fmaf(u, qu1.y, qu1.x);
+                acc3[i] += fmaf(v, qv0.w, qv0.z);
+                acc3[i] += fmaf(u, qu1.w, qu1.z);
+            }
+        }
+        __syncthreads();
+    }
+
+    float* red = reinterpret_cast<float*>(win);
+    if constexpr (S > 1) {
+        if (grp > 0) {
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                float* r = red + ((grp - 1) * kGroupThreads + tl) * 4 * P + 4 * i;
+                r[0] = acc0[i];
+                r[1] = acc1[i];
+                r[2] = acc2[i];
+                r[3] = acc3[i];
+            }
+        }
+        __syncthreads();
+        if (grp == 0) {
+#pragma unroll
+            for (int gg = 1; gg < S; ++gg) {
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    const float* r = red + ((gg - 1) * kGroupThreads + tl) * 4 * P + 4 * i;
+                    acc0[i] += r[0];
+                    acc1[i] += r[1];
+                    acc2[i] += r[2];
+                    acc3[i] += r[3];
+                }
+            }
+        }
+        __syncthreads();   // reduction buffer fully read before the transpose reuses it
+    }
+
+    // p and R^2 p store directly; R p and R^3 p go through LDS so the transposed
+    // tiles are written row-contiguously.
+    const float scale = job.scale;
+    const int half = N >> 1;
+    const int c = c0 + lx;
+    float* x1 = red;                                // [TH][TW + 1]
+    float* x3 = red + TH * (TW + 1);
+    if (grp == 0) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const int ly = ly0 + i;
+            const int r = r0 + ly;
+            if (c < half && r < half) {
+                img[(size_t)r * N + c] = acc0[i] * scale;
+                img[(size_t)(N - 1 - r) * N + (N - 1 - c)] = acc2[i] * scale;
+            }
+            x1[ly * (TW + 1) + lx] = acc1[i] * scale;
+            x3[ly * (TW + 1) + lx] = acc3[i] * scale;
+        }
+    }
+    __syncthreads();
+    if (grp == 0) {
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+            const int e = tl + m * kGroupThreads;   // e = a * TH + b: column a = lx, row b = ly
+            const int a = e / TH, b = e - (e / TH) * TH;
+            if (r0 + b < half && c0 + a < half) {
+                // R p of tile element (b, a) sits at (c0 + a, N-1-r0-b); R^3 p at (N-1-c0-a, r0 + b)
+                img[(size_t)(c0 + a) * N + (N - 1 - r0 - b)] = x1[b * (TW + 1) + a];
+                img[(size_t)(N - 1 - c0 - a) * N + (r0 + b)] = x3[b * (TW + 1) + a];
+            }
+        }
+    }
+}
+
+template <int TW, int P, int S, bool ROT>
+__device__ __forceinline__ void tile_dispatch(const BpJob& job, const float* q, float* img, int c0,
+                                              int r0, char* smem) {
+    if constexpr (ROT)
+        bp_tile_rot4<TW, P, S>(job, q, img, c0, r0, smem);
+    else
+        bp_tile<TW, P, S>(job, q, img, c0, r0, smem);
+}
+
+template <int TW, int P, int S, bool ROT>
 __global__ __launch_bounds__(kGroupThreads * S, 2 * S) void bp_grid_kernel(BpJob job, size_t q_stride,
                                                                     size_t img_stride, int tiles_per_slice) {
     extern __shared__ float4 smem4[];
     char* smem = reinterpret_cast<char*>(smem4);
-    constexpr int TH = Shape<TW, P, S>::TH;
+    constexpr int TH = Shape<TW, P, S, ROT>::TH;
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int s = lb / tiles_per_slice;
     const int tt = lb - s * tiles_per_slice;
     const int ty = tt / job.tiles_x;
     const int tx = tt - ty * job.tiles_x;
-    bp_tile<TW, P, S>(job, job.q + (size_t)s * q_stride, job.img + (size_t)s * img_stride, tx * TW,
-                      ty * TH, smem);
+    tile_dispatch<TW, P, S, ROT>(job, job.q + (size_t)s * q_stride, job.img + (size_t)s * img_stride,
+                                 tx * TW, ty * TH, smem);
 }
 
-template <int TW, int P, int S>
+template <int TW, int P, int S, bool ROT>
 __global__ __launch_bounds__(kGroupThreads * S, 2 * S) void bp_list_kernel(const BpListArgs* __restrict__ args) {
     extern __shared__ float4 smem4[];
     char* smem = reinterpret_cast<char*>(smem4);
     const BpListArgs a = load_const(args);
-    constexpr int TH = Shape<TW, P, S>::TH;
+    constexpr int TH = Shape<TW, P, S, ROT>::TH;
     const auto* __restrict__ prefix = as_const(a.tile_prefix);
     const int n_sel = *as_const(a.counts);
     if (n_sel <= 0) return;
@@ -266,7 +510,7 @@ __global__ __launch_bounds__(kGroupThreads * S, 2 * S) void bp_list_kernel(const
         const int tt = it - prefix[lo];
         const int ty = tt / job.tiles_x;
         const int tx = tt - ty * job.tiles_x;
-        bp_tile<TW, P, S>(job, job.q, job.img, tx * TW, ty * TH, smem);
+        tile_dispatch<TW, P, S, ROT>(job, job.q, job.img, tx * TW, ty * TH, smem);
     }
 }
 
@@ -280,45 +524,54 @@ constexpr TileShape kShapes[kNumTileConfigs] = {
     {32, 2, 16, 1, "32x16 tile, 2 px/lane, 1 angle group"},
     {16, 1, 16, 4, "16x16 tile, 1 px/lane, 4 angle groups"},
     {16, 4, 64, 4, "16x64 tile, 4 px/lane, 4 angle groups"},
+    {16, 2, 32, 4, "16x32 quadrant tile x 4 rotations, 2 px/lane, 4 angle groups", 1},
+    {16, 1, 16, 4, "16x16 quadrant tile x 4 rotations, 1 px/lane, 4 angle groups", 1},
+    {16, 4, 64, 4, "16x64 quadrant tile x 4 rotations, 4 px/lane, 4 angle groups", 1},
 };
 
-template <int TW, int P, int S>
+template <int TW, int P, int S, bool ROT>
 hipError_t grid_launch(const BpJob& job, int n_slices, size_t q_stride, size_t img_stride,
                        int tiles_per_slice, size_t lds, hipStream_t stream) {
     const unsigned grid = (unsigned)n_slices * (unsigned)tiles_per_slice;
-    hipLaunchKernelGGL((bp_grid_kernel<TW, P, S>), dim3(grid), dim3(kGroupThreads * S), lds, stream,
+    hipLaunchKernelGGL((bp_grid_kernel<TW, P, S, ROT>), dim3(grid), dim3(kGroupThreads * S), lds, stream,
                        job, q_stride, img_stride, tiles_per_slice);
     return hipGetLastError();
 }
 
-template <int TW, int P, int S>
+template <int TW, int P, int S, bool ROT>
 hipError_t list_launch(const BpListArgs* a, int grid, size_t lds, hipStream_t stream) {
-    hipLaunchKernelGGL((bp_list_kernel<TW, P, S>), dim3(grid), dim3(kGroupThreads * S), lds, stream, a);
+    hipLaunchKernelGGL((bp_list_kernel<TW, P, S, ROT>), dim3(grid), dim3(kGroupThreads * S), lds, stream, a);
     return hipGetLastError();
 }
 
-template <int TW, int P, int S>
+template <int TW, int P, int S, bool ROT>
 int occupancy(size_t lds) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_list_kernel<TW, P, S>, kGroupThreads * S,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_list_kernel<TW, P, S, ROT>, kGroupThreads * S,
                                                      lds) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
 
-template <int TW, int P, int S>
-constexpr int red_bytes() { return Shape<TW, P, S>::RED_BYTES; }
+template <int TW, int P, int S, bool ROT>
+constexpr int red_bytes() {
+    return Shape<TW, P, S, ROT>::RED_BYTES > Shape<TW, P, S, ROT>::XPOSE_BYTES ? Shape<TW, P, S, ROT>::RED_BYTES
+                                                                            : Shape<TW, P, S, ROT>::XPOSE_BYTES;
+}
 
 #define FBP_FOR_EACH_SHAPE(X) \
-    X(0, 32, 2, 4)            \
-    X(1, 16, 2, 4)            \
-    X(2, 32, 4, 2)            \
-    X(3, 32, 1, 4)            \
-    X(4, 32, 4, 1)            \
-    X(5, 16, 2, 2)            \
-    X(6, 32, 2, 1)            \
-    X(7, 16, 1, 4)            \
-    X(8, 16, 4, 4)
+    X(0, 32, 2, 4, false)     \
+    X(1, 16, 2, 4, false)     \
+    X(2, 32, 4, 2, false)     \
+    X(3, 32, 1, 4, false)     \
+    X(4, 32, 4, 1, false)     \
+    X(5, 16, 2, 2, false)     \
+    X(6, 32, 2, 1, false)     \
+    X(7, 16, 1, 4, false)     \
+    X(8, 16, 4, 4, false)     \
+    X(9, 16, 2, 4, true)      \
+    X(10, 16, 1, 4, true)     \
+    X(11, 16, 4, 4, true)
 
 }  // namespace
 
@@ -327,10 +580,14 @@ const TileShape& tile_shape(int cfg) { return kShapes[cfg]; }
 int bp_lds_bytes(int cfg, int WL, int KB) {
     int red = 0;
     switch (cfg) {
-#define X(id, tw, p, s) case id: red = red_bytes<tw, p, s>(); break;
+#define X(id, tw, p, s, rot) case id: red = red_bytes<tw, p, s, rot>(); break;
         FBP_FOR_EACH_SHAPE(X)
 #undef X
         default: break;
+    }
+    if (tile_shape(cfg).rot) {
+        const int win = WL * KB * 64;
+        return kRotPrmBytes + (win > red ? win : red);
     }
     const int win = WL * KB * 16;
     return kPrmBytes + (win > red ? win : red);
@@ -340,8 +597,8 @@ hipError_t launch_bp_grid(int cfg, const BpJob& job, int n_slices, size_t q_stri
                           size_t img_stride, int tiles_per_slice, hipStream_t stream) {
     const size_t lds = (size_t)bp_lds_bytes(cfg, job.WL, job.KB);
     switch (cfg) {
-#define X(id, tw, p, s) \
-        case id: return grid_launch<tw, p, s>(job, n_slices, q_stride, img_stride, tiles_per_slice, lds, stream);
+#define X(id, tw, p, s, rot) \
+        case id: return grid_launch<tw, p, s, rot>(job, n_slices, q_stride, img_stride, tiles_per_slice, lds, stream);
         FBP_FOR_EACH_SHAPE(X)
 #undef X
         default: return hipErrorInvalidValue;
@@ -350,7 +607,7 @@ hipError_t launch_bp_grid(int cfg, const BpJob& job, int n_slices, size_t q_stri
 
 hipError_t launch_bp_list(int cfg, const BpListArgs* a, int grid, size_t lds, hipStream_t stream) {
     switch (cfg) {
-#define X(id, tw, p, s) case id: return list_launch<tw, p, s>(a, grid, lds, stream);
+#define X(id, tw, p, s, rot) case id: return list_launch<tw, p, s, rot>(a, grid, lds, stream);
         FBP_FOR_EACH_SHAPE(X)
 #undef X
         default: return hipErrorInvalidValue;
@@ -359,7 +616,7 @@ hipError_t launch_bp_list(int cfg, const BpListArgs* a, int grid, size_t lds, hi
 
 int bp_occupancy(int cfg, size_t lds) {
     switch (cfg) {
-#define X(id, tw, p, s) case id: return occupancy<tw, p, s>(lds);
+#define X(id, tw, p, s, rot) case id: return occupancy<tw, p, s, rot>(lds);
         FBP_FOR_EACH_SHAPE(X)
 #undef X
         default: return 1;

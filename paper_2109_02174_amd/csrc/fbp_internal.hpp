@@ -54,17 +54,22 @@ static_assert(sizeof(BpJob) % 8 == 0, "BpJob layout");
 struct TileShape {
     int32_t tw, p, th, s;
     const char* name;
+    int32_t rot = 0;      // 1: quadrant tile and its three 90-degree rotations (angle pairs)
 };
 
 constexpr int kGroupThreads = 256;
 constexpr int kBpThreads = 256;   // threads of the GEMM workgroups
-constexpr int kNumTileConfigs = 9;
+constexpr int kNumTileConfigs = 12;
 constexpr int kMaxKB = 64;
 constexpr int kStageE = 4;        // staged (angle, bin) elements per thread per block
 // Dynamic LDS budget of one backprojection workgroup (bytes).
 constexpr int kBpLdsBudget = 48 * 1024;
 // LDS bytes of the per-angle constants of the current and next block (float4 each).
 constexpr int kBpPrmBytes = 2 * kMaxKB * 16;
+// Rotation-symmetric shapes: float4 + int2 per angle pair, two blocks.
+constexpr int kBpRotPrmBytes = 2 * kMaxKB * 24;
+// LDS budget of the rotation-symmetric shapes (two windows of 32-byte bins per pair).
+constexpr int kBpRotLdsBudget = 64 * 1024;
 
 const TileShape& tile_shape(int cfg);
 

@@ -150,13 +150,46 @@ struct ShapeParams {
     int WL = 0, KB = 0, seg_shift = 0, tiles_x = 0, tiles_y = 0;
 };
 
-bool shape_params(int cfg, const std::vector<double>& cs, int N, ShapeParams* sp) {
+// Angle list closed under +pi/2: theta_{k+K/2} = theta_k + pi/2 for every k < K/2.
+bool quarter_turn_symmetric(const std::vector<double>& angles) {
+    const size_t K = angles.size();
+    if (K < 2 || (K & 1)) return false;
+    const size_t h = K / 2;
+    for (size_t k = 0; k < h; ++k)
+        if (std::fabs(angles[k + h] - angles[k] - 0.5 * kPi) > 1e-12) return false;
+    return true;
+}
+
+bool shape_params(int cfg, const std::vector<double>& cs, const std::vector<double>& angles, int N,
+                  ShapeParams* sp) {
     const TileShape& s = tile_shape(cfg);
+    const int waves = kGroupThreads * s.s / 64;
+    if (s.rot) {
+        // quadrant tile plus its three rotations: even N, angles in quarter-turn pairs
+        if ((N & 1) || !quarter_turn_symmetric(angles)) return false;
+        double span = 0.0;
+        for (size_t k = 0; 2 * k + 1 < cs.size(); ++k) {
+            const double c = std::fabs(cs[2 * k]), sn = std::fabs(cs[2 * k + 1]);
+            span = std::max(span, std::max((s.tw - 1) * c + (s.th - 1) * sn, (s.tw - 1) * sn + (s.th - 1) * c));
+        }
+        if (!(span < 1e6)) return false;
+        sp->WL = window_length(span);
+        int shift = 0;
+        while (63 * (1 << shift) < sp->WL) ++shift;
+        sp->seg_shift = shift;
+        const int kb_stage = (kStageE * waves) >> (shift + 1);
+        const int kb_lds = (kBpRotLdsBudget - kBpRotPrmBytes) / (64 * sp->WL);
+        sp->KB = std::min(kMaxKB, std::min(kb_stage, kb_lds));
+        if (sp->KB < 1) return false;
+        const int half = N / 2;
+        sp->tiles_x = (half + s.tw - 1) / s.tw;
+        sp->tiles_y = (half + s.th - 1) / s.th;
+        return true;
+    }
     const double span = span_for(s, cs);
     if (!(span < 1e6)) return false;
     sp->WL = window_length(span);
     // staging: one wave per (angle, 63-bin segment) per pass, kStageE passes per block
-    const int waves = kGroupThreads * s.s / 64;
     int shift = 0;
     while (63 * (1 << shift) < sp->WL) ++shift;
     sp->seg_shift = shift;
@@ -266,11 +299,11 @@ int get_plan(const fbp_geom* g, Plan** out) {
         cfg = (t != R.tuned.end()) ? t->second : default_config(p->N);
     }
     ShapeParams sp;
-    if (!shape_params(cfg, p->cs, p->N, &sp)) {
+    if (!shape_params(cfg, p->cs, p->angles, p->N, &sp)) {
         // fall back to any shape whose window fits, else refuse
         bool ok = false;
         for (int c = 0; c < kNumTileConfigs && !ok; ++c)
-            if (shape_params(c, p->cs, p->N, &sp)) {
+            if (shape_params(c, p->cs, p->angles, p->N, &sp)) {
                 cfg = c;
                 ok = true;
             }
@@ -433,12 +466,7 @@ int run_backproject(const Plan& p, int32_t n, const float* filt, float* img, hip
     if (n == 0) return FBP_OK;
     const BpJob j = job_override ? *job_override : bp_job(p, filt, img);
     const int cfg = cfg_override >= 0 ? cfg_override : p.cfg;
-    int tx = p.tiles_x, ty = p.tiles_y;
-    if (cfg_override >= 0) {
-        const TileShape& s2 = tile_shape(cfg);
-        tx = (p.N + s2.tw - 1) / s2.tw;
-        ty = ((p.N + 1) / 2 + s2.th - 1) / s2.th;
-    }
+    const int tx = p.tiles_x, ty = p.tiles_y;
     const int64_t grid = (int64_t)n * tx * ty;
     if (grid > INT32_MAX) return FBP_EUNSUPPORTED;
     return hip_status(launch_bp_grid(cfg, j, n, (size_t)p.K * p.D, (size_t)p.N * p.N, tx * ty, s));
@@ -780,11 +808,12 @@ int autotune(const fbp_geom* g, hipStream_t s, int32_t* out_cfg) {
         p.N = g->image_size;
         p.dt = g->det_spacing;
         p.cs = cs;
+        p.angles.assign(g->angles, g->angles + g->n_angles);
         p.d_cs = dcs;
         p.d_cs32 = dcs32;
         for (int c = 0; c < kNumTileConfigs && rc == FBP_OK; ++c) {
             ShapeParams sp;
-            if (!shape_params(c, cs, p.N, &sp)) continue;
+            if (!shape_params(c, cs, p.angles, p.N, &sp)) continue;
             apply_shape(&p, c, sp);
             const BpJob job = bp_job(p, q, im);
             float ms_min = 1e30f;
@@ -973,7 +1002,7 @@ int fbp_backproject_with_config(const fbp_geom* geom, int32_t n_slices, const fl
     q.d_cs = p->d_cs;
     q.d_cs32 = p->d_cs32;
     ShapeParams sp;
-    if (!shape_params(config, p->cs, p->N, &sp)) return FBP_EUNSUPPORTED;
+    if (!shape_params(config, p->cs, p->angles, p->N, &sp)) return FBP_EUNSUPPORTED;
     apply_shape(&q, config, sp);
     const BpJob job = bp_job(q, d_filtered, d_image);
     return run_backproject(q, n_slices, d_filtered, d_image, (hipStream_t)hip_stream, config, &job);

@@ -48,6 +48,9 @@ GEOMS = [
     (5, 1, 3, 1.0, "random", 1),          # one bin
     (3, 4, 1, 1.0, "uniform", 2),         # one pixel
     (100, 300, 200, 1.0, "random", 1),    # angles spanning [0, 2 pi)
+    (90, 101, 70, 1.0, "uniform", 2),     # quarter-turn symmetric, ragged quadrant tiles
+    (40, 75, 50, 0.7, "uniform", 1),      # quarter-turn symmetric, dt < 1
+    (2, 3, 2, 1.0, "uniform", 1),         # smallest quarter-turn case
 ]
 
 
@@ -66,13 +69,23 @@ def test_backprojection_matches_oracle_every_tile_shape(geom):
     ref = oracle.backproject(Q32.astype(np.float64), N, dt, ang)
     tol = bp_tolerance(Q32)
     q = dev(Q32)
+    ran = []
     for cfg in range(fbp.fbp_num_tile_configs()):
         out = torch.full((B, N, N), float("nan"), device="cuda")
-        fbp.fbp_backproject_with_config(g, q, cfg, out=out)
+        try:
+            fbp.fbp_backproject_with_config(g, q, cfg, out=out)
+        except fbp.FbpError as e:
+            # quadrant-rotation shapes need even N and quarter-turn symmetric angles
+            assert e.status == fbp.FBP_EUNSUPPORTED and "rotations" in fbp.fbp_tile_config_name(cfg)
+            continue
+        ran.append(cfg)
         got = host(out)
         assert np.all(np.isfinite(got)), f"tile {cfg}: pixel left unwritten"
         err = np.max(np.abs(got - ref))
         assert err <= tol, f"tile {cfg}: max err {err:.3e} > {tol:.3e}"
+    rot_ok = N % 2 == 0 and kind == "uniform" and K % 2 == 0
+    n_rot = sum("rotations" in fbp.fbp_tile_config_name(c) for c in ran)
+    assert (n_rot > 0) == rot_ok
     out = fbp.fbp_backproject(g, q)
     assert np.max(np.abs(host(out) - ref)) <= tol
 
