@@ -473,8 +473,14 @@ __device__ __forceinline__ void tile_dispatch(const BpJob& job, const float* q, 
         bp_tile<TW, P, S>(job, q, img, c0, r0, smem);
 }
 
+// Resident waves per SIMD asked of the compiler: two workgroups per CU, except the
+// quarter-turn shapes (four accumulators per pixel row), which keep one workgroup
+// per CU rather than spill.
+template <int P, int S, bool ROT>
+constexpr int min_waves() { return ROT ? S : 2 * S; }
+
 template <int TW, int P, int S, bool ROT>
-__global__ __launch_bounds__(kGroupThreads * S, 2 * S) void bp_grid_kernel(BpJob job, size_t q_stride,
+__global__ __launch_bounds__(kGroupThreads * S, (min_waves<P, S, ROT>())) void bp_grid_kernel(BpJob job, size_t q_stride,
                                                                     size_t img_stride, int tiles_per_slice) {
     extern __shared__ float4 smem4[];
     char* smem = reinterpret_cast<char*>(smem4);
@@ -489,7 +495,7 @@ __global__ __launch_bounds__(kGroupThreads * S, 2 * S) void bp_grid_kernel(BpJob
 }
 
 template <int TW, int P, int S, bool ROT>
-__global__ __launch_bounds__(kGroupThreads * S, 2 * S) void bp_list_kernel(const BpListArgs* __restrict__ args) {
+__global__ __launch_bounds__(kGroupThreads * S, (min_waves<P, S, ROT>())) void bp_list_kernel(const BpListArgs* __restrict__ args) {
     extern __shared__ float4 smem4[];
     char* smem = reinterpret_cast<char*>(smem4);
     const BpListArgs a = load_const(args);
