@@ -19,10 +19,15 @@
 //    interpolated value at local coordinate u in [j, j+1) is A_j + u dL_j: one
 //    FMA, no fraction.  One ds_read_b128 returns both directions.
 //  * The workgroup has S groups of 256 lanes over the same pixels; group g takes
-//    the g-th contiguous quarter (for S = 4) of every staged block, and the S
-//    partial sums are added in fixed order at the end.  This gives a single 512^2
-//    slice enough waves per CU.  Per-angle constants come from LDS (not scalar
-//    loads, which would force full LDS drains inside the loop).
+//    the angles k = g (mod S), and the S partial sums are added in fixed order at
+//    the end.  This gives a single 512^2 slice enough waves per CU.  Per-angle
+//    constants come from LDS (not scalar loads, which would force full LDS drains
+//    inside the loop).
+//  * For stacks of slices with one geometry, a workgroup can take M = 4 slices of
+//    the same tile: the coordinate, its truncation and the LDS address are shared
+//    by 2 M pixels, and the window bins of the M slices sit side by side.  Each
+//    slice's arithmetic, and the order of its sums, is that of the one-slice
+//    kernel of the same tile shape, so the results are bitwise identical.
 //  * The next block's filtered rows are loaded into registers while the current
 //    block is computed, so the global-load latency hides behind the LDS work.
 //    The loads are buffer loads whose range check supplies the zeros beyond the
@@ -73,14 +78,36 @@ struct Shape {
 // windows.
 constexpr int kRotPrmBytes = kBpRotPrmBytes;
 
-template <int TW, int P, int S>
-__device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restrict__ q,
-                                        float* __restrict__ img, int c0, int r0, char* smem) {
+// The M slices a workgroup backprojects together.  They share the geometry, so one
+// coordinate, one truncation and one LDS address serve 2 M pixels.  Entries at
+// m >= n repeat slice 0's pointers; their rows are read as zeros and never stored.
+template <int M>
+struct SliceSet {
+    const float* q[M];
+    float* img[M];
+    int n;   // valid slices, 1 <= n <= M
+};
+
+// Window bins of the M slices of one angle are interleaved with a stride of ST
+// float4s; an odd stride keeps lanes at consecutive bins on distinct LDS banks.
+template <int M>
+constexpr int bin_stride() { return (M == 1) ? 1 : (M | 1); }
+
+template <int M>
+constexpr int log2_slices() { return M == 1 ? 0 : (M == 2 ? 1 : 2); }
+
+template <int TW, int P, int S, int M>
+__device__ __forceinline__ void bp_tile(const BpJob& job, const SliceSet<M>& ss, int c0, int r0,
+                                        char* smem) {
+    static_assert(M == 1 || M == 2 || M == 4, "slices per workgroup");
     using Sh = Shape<TW, P, S>;
     constexpr int NT = Sh::NT;
     constexpr int TH = Sh::TH;
+    constexpr int ST = bin_stride<M>();
+    constexpr int LM = log2_slices<M>();
+    constexpr int UB = (16 / (P * M) < 1) ? 1 : (16 / (P * M) > 4 ? 4 : 16 / (P * M));
     float4* prm = reinterpret_cast<float4*>(smem);                      // [2][kMaxKB]
-    float4* win = reinterpret_cast<float4*>(smem + kPrmBytes);
+    float4* win = reinterpret_cast<float4*>(smem + kPrmBytes);          // [KB][WL][ST]
 
     const int t = threadIdx.x;
     const int grp = __builtin_amdgcn_readfirstlane(t >> 8);   // wave-uniform angle group
@@ -93,12 +120,12 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
     const float flx = (float)lx;
     const float fly = (float)ly0;
 
-    // Staging: one wave fills one segment of 63 window bins of one angle per pass.
-    // Lane j loads bin i0 + 63 seg + j of the forward row and the mirrored bin of the
-    // reversed row with single-dword buffer loads; a per-row buffer resource of D
-    // floats returns 0 outside the detector, which is the zero extension of the
-    // filtered row.  The value at bin + 1 comes from the next lane (ds_bpermute), so
-    // 64 lanes produce 63 (A, dL) pairs per direction.
+    // Staging: one wave fills one segment of 63 window bins of one (angle, slice)
+    // per pass.  Lane j loads bin i0 + 63 seg + j of the forward row and the
+    // mirrored bin of the reversed row with single-dword buffer loads; a per-row
+    // buffer resource of D floats returns 0 outside the detector, which is the zero
+    // extension of the filtered row.  The value at bin + 1 comes from the next lane
+    // (ds_bpermute), so 64 lanes produce 63 (A, dL) pairs per direction.
     constexpr int W = NT / 64;                  // waves per workgroup
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int lane = t & 63;
@@ -106,11 +133,14 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
     const int nxt = ((lane + 1) & 63) << 2;     // ds_bpermute source: lane + 1
     const int d4 = (D - 1) * 4;
 
-    float accf[P], accr[P];
+    float accf[M][P], accr[M][P];
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
-        accf[i] = 0.0f;
-        accr[i] = 0.0f;
+    for (int m = 0; m < M; ++m) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            accf[m][i] = 0.0f;
+            accr[m][i] = 0.0f;
+        }
     }
 
     // window origin (FP64) of the angles of the block starting at kb, into buffer buf
@@ -128,15 +158,21 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
     };
     float pf[kStageE], pr[kStageE];
     auto load = [&](int kb, int buf) {
-        const int nslot = min(KB, K - kb) << seg_shift;
+        const int nslot = min(KB, K - kb) << (LM + seg_shift);
 #pragma unroll
         for (int e = 0; e < kStageE; ++e) {
             const int slot = wave + e * W;                       // wave-uniform
             if (slot < nslot) {
-                const int a = slot >> seg_shift;
+                const int a = slot >> (LM + seg_shift);
+                const int m = (slot >> seg_shift) & (M - 1);
                 const int seg = slot & ((1 << seg_shift) - 1);
+                const float* qm = ss.q[0];
+#pragma unroll
+                for (int mm = 1; mm < M; ++mm)
+                    if (m == mm) qm = ss.q[mm];
+                const int nrec = (m < ss.n) ? D * 4 : 0;
                 const __amdgpu_buffer_rsrc_t row = __builtin_amdgcn_make_buffer_rsrc(
-                    const_cast<float*>(q + (size_t)(kb + a) * (size_t)D), (short)0, D * 4, kBufferWord3);
+                    const_cast<float*>(qm + (size_t)(kb + a) * (size_t)D), (short)0, nrec, kBufferWord3);
                 const int g4 = (__float_as_int(prm[buf * kMaxKB + a].w) + 63 * seg + lane) * 4;
                 pf[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(row, g4, 0, 0));
                 pr[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(row, d4 - g4, 0, 0));
@@ -144,12 +180,13 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
         }
     };
     auto store = [&](int kb) {
-        const int nslot = min(KB, K - kb) << seg_shift;
+        const int nslot = min(KB, K - kb) << (LM + seg_shift);
 #pragma unroll
         for (int e = 0; e < kStageE; ++e) {
             const int slot = wave + e * W;
             if (slot < nslot) {
-                const int a = slot >> seg_shift;
+                const int a = slot >> (LM + seg_shift);
+                const int m = (slot >> seg_shift) & (M - 1);
                 const int j = 63 * (slot & ((1 << seg_shift) - 1)) + lane;
                 const float f1 = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(nxt, __builtin_bit_cast(int, pf[e])));
                 const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(nxt, __builtin_bit_cast(int, pr[e])));
@@ -157,7 +194,7 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
                     const float df = f1 - pf[e];
                     const float db = r1 - pr[e];
                     const float jj = (float)j;
-                    win[a * WL + j] = make_float4(fmaf(-jj, df, pf[e]), df, fmaf(-jj, db, pr[e]), db);
+                    win[(a * WL + j) * ST + m] = make_float4(fmaf(-jj, df, pf[e]), df, fmaf(-jj, db, pr[e]), db);
                 }
             }
         }
@@ -174,45 +211,85 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
         if (k0 + KB < K) params(k0 + KB, buf ^ 1);
         __syncthreads();
         if (k0 + KB < K) load(k0 + KB, buf ^ 1);
-        // group grp takes the contiguous angles [a_lo, a_hi) of this block
-        const int per = (nb + S - 1) / S;
-        const int a_lo = min(nb, grp * per);
-        const int a_hi = min(nb, a_lo + per);
+        // group grp takes the angles k = grp (mod S): the assignment and the order of
+        // each group's sum depend on neither the block length nor M
         const float4* __restrict__ pa = prm + buf * kMaxKB;
-#pragma unroll 4
-        for (int a = a_lo; a < a_hi; ++a) {
+        int a = (grp - k0 % S + S) % S;
+        // UB angles per step: every window read of the step is issued before the
+        // first is consumed, so each wave keeps P M UB LDS reads in flight
+        for (; a + (UB - 1) * S < nb; a += UB * S) {
+            float4 p[UB];
+#pragma unroll
+            for (int b = 0; b < UB; ++b) p[b] = pa[a + b * S];
+            float u[UB][P];
+            float4 v[UB][P][M];
+#pragma unroll
+            for (int b = 0; b < UB; ++b) {
+                const float u0 = fmaf(flx, p[b].y, fmaf(fly, p[b].z, p[b].x));
+                const float4* __restrict__ w = win + (a + b * S) * WL * ST;
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    u[b][i] = (i == 0) ? u0 : fmaf((float)i, p[b].z, u0);
+                    const float4* __restrict__ wj = w + (int)u[b][i] * ST;   // u > 0: truncation is floor
+#pragma unroll
+                    for (int m = 0; m < M; ++m) v[b][i][m] = wj[m];
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < UB; ++b)
+#pragma unroll
+                for (int i = 0; i < P; ++i)
+#pragma unroll
+                    for (int m = 0; m < M; ++m) {
+                        accf[m][i] += fmaf(u[b][i], v[b][i][m].y, v[b][i][m].x);
+                        accr[m][i] += fmaf(u[b][i], v[b][i][m].w, v[b][i][m].z);
+                    }
+        }
+        for (; a < nb; a += S) {
             const float4 p = pa[a];
             const float u0 = fmaf(flx, p.y, fmaf(fly, p.z, p.x));
-            const float4* __restrict__ w = win + a * WL;
+            const float4* __restrict__ w = win + a * WL * ST;
 #pragma unroll
             for (int i = 0; i < P; ++i) {
                 const float u = (i == 0) ? u0 : fmaf((float)i, p.z, u0);
-                const int j = (int)u;   // u > 0: truncation is floor
-                const float4 v = w[j];
-                accf[i] += fmaf(u, v.y, v.x);
-                accr[i] += fmaf(u, v.w, v.z);
+                const float4* __restrict__ wj = w + (int)u * ST;
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    const float4 v = wj[m];
+                    accf[m][i] += fmaf(u, v.y, v.x);
+                    accr[m][i] += fmaf(u, v.w, v.z);
+                }
             }
         }
         __syncthreads();
     }
 
     if constexpr (S > 1) {
-        float* red = reinterpret_cast<float*>(win);   // [S-1][256][2P]
+        constexpr int NV = 2 * P * M;                 // partial sums per lane
+        float* red = reinterpret_cast<float*>(win);   // [S-1][NV][256]
         if (grp > 0) {
+            float* r = red + (grp - 1) * NV * kGroupThreads + tl;
 #pragma unroll
-            for (int i = 0; i < P; ++i) {
-                red[((grp - 1) * kGroupThreads + tl) * 2 * P + 2 * i] = accf[i];
-                red[((grp - 1) * kGroupThreads + tl) * 2 * P + 2 * i + 1] = accr[i];
+            for (int m = 0; m < M; ++m) {
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    r[(2 * (m * P + i)) * kGroupThreads] = accf[m][i];
+                    r[(2 * (m * P + i) + 1) * kGroupThreads] = accr[m][i];
+                }
             }
         }
         __syncthreads();
         if (grp > 0) return;
 #pragma unroll
         for (int gg = 1; gg < S; ++gg) {
+            const float* r = red + (gg - 1) * NV * kGroupThreads + tl;
 #pragma unroll
-            for (int i = 0; i < P; ++i) {
-                accf[i] += red[((gg - 1) * kGroupThreads + tl) * 2 * P + 2 * i];
-                accr[i] += red[((gg - 1) * kGroupThreads + tl) * 2 * P + 2 * i + 1];
+            for (int m = 0; m < M; ++m) {
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    accf[m][i] += r[(2 * (m * P + i)) * kGroupThreads];
+                    accr[m][i] += r[(2 * (m * P + i) + 1) * kGroupThreads];
+                }
             }
         }
     }
@@ -228,9 +305,14 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
         if (c < N && r < half_rows) {
             const bool mid = (2 * r == N - 1);
             if (!mid || 2 * c <= N - 1) {
-                img[(size_t)r * N + c] = accf[i] * scale;
-                if (!(mid && 2 * c == N - 1))
-                    img[(size_t)(N - 1 - r) * N + (N - 1 - c)] = accr[i] * scale;
+                const bool refl = !(mid && 2 * c == N - 1);
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    if (m < ss.n) {
+                        ss.img[m][(size_t)r * N + c] = accf[m][i] * scale;
+                        if (refl) ss.img[m][(size_t)(N - 1 - r) * N + (N - 1 - c)] = accr[m][i] * scale;
+                    }
+                }
             }
         }
     }
@@ -250,12 +332,29 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const float* __restric
 // (R(x, y) = (-y, x); "rev" is the reversed filtered row, as for the point
 // reflection).  Each window bin holds both angles' forward and reversed (A, dL)
 // pairs in 32 bytes: 8 updates per 2 coordinates, 2 truncations, 4 ds_read_b128.
+// The eight updates of one angle pair (theta, theta + pi/2) for a pixel and its
+// three rotations, from the coordinates U, V and the window bins read at them;
+// the theta term first, then theta + pi/2, for every pixel.
+__device__ __forceinline__ void rot_accumulate(float u, float v, const float4& qu0, const float4& qu1,
+                                               const float4& qv0, const float4& qv1, float& acc0, float& acc1,
+                                               float& acc2, float& acc3) {
+    acc0 += fmaf(u, qu0.y, qu0.x);
+    acc0 += fmaf(v, qv1.w, qv1.z);
+    acc2 += fmaf(u, qu0.w, qu0.z);
+    acc2 += fmaf(v, qv1.y, qv1.x);
+    acc1 += fmaf(v, qv0.y, qv0.x);
+    acc1 += fmaf(u, qu1.y, qu1.x);
+    acc3 += fmaf(v, qv0.w, qv0.z);
+    acc3 += fmaf(u, qu1.w, qu1.z);
+}
+
 template <int TW, int P, int S>
 __device__ __forceinline__ void bp_tile_rot4(const BpJob& job, const float* __restrict__ q,
                                              float* __restrict__ img, int c0, int r0, char* smem) {
     using Sh = Shape<TW, P, S, true>;
     constexpr int NT = Sh::NT;
     constexpr int TH = Sh::TH;
+    constexpr int UB = (4 / P < 1) ? 1 : 4 / P;
     float4* prm = reinterpret_cast<float4*>(smem);                        // [2][kMaxKB]
     int2* pri = reinterpret_cast<int2*>(smem + 2 * kMaxKB * 16);          // [2][kMaxKB]
     float4* win = reinterpret_cast<float4*>(smem + kRotPrmBytes);         // [KB][2][WL][2]
@@ -371,30 +470,53 @@ __device__ __forceinline__ void bp_tile_rot4(const BpJob& job, const float* __re
         const int a_lo = min(nb, grp * per);
         const int a_hi = min(nb, a_lo + per);
         const float4* __restrict__ pa = prm + buf * kMaxKB;
-#pragma unroll 2
-        for (int a = a_lo; a < a_hi; ++a) {
-            const float4 p = pa[a];    // bU, bV, cos, sin
+        // UB angle pairs per step, every window read issued before the first is used
+        int a = a_lo;
+        for (; a + UB <= a_hi; a += UB) {
+            float4 p[UB];
+#pragma unroll
+            for (int b = 0; b < UB; ++b) p[b] = pa[a + b];    // bU, bV, cos, sin
+            float u[UB][P], v[UB][P];
+            float4 qu0[UB][P], qu1[UB][P], qv0[UB][P], qv1[UB][P];
+#pragma unroll
+            for (int b = 0; b < UB; ++b) {
+                const float u0 = fmaf(flx, p[b].z, fmaf(fly, p[b].w, p[b].x));
+                const float v0 = fmaf(flx, p[b].w, fmaf(nfly, p[b].z, p[b].y));
+                const float4* __restrict__ wu = win + (((a + b) * 2) * WL << 1);
+                const float4* __restrict__ wv = win + (((a + b) * 2 + 1) * WL << 1);
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    u[b][i] = (i == 0) ? u0 : fmaf((float)i, p[b].w, u0);
+                    v[b][i] = (i == 0) ? v0 : fmaf(-(float)i, p[b].z, v0);
+                    const int ju = (int)u[b][i];   // both > 0: truncation is floor
+                    const int jv = (int)v[b][i];
+                    qu0[b][i] = wu[2 * ju];
+                    qu1[b][i] = wu[2 * ju + 1];
+                    qv0[b][i] = wv[2 * jv];
+                    qv1[b][i] = wv[2 * jv + 1];
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < UB; ++b)
+#pragma unroll
+                for (int i = 0; i < P; ++i)
+                    rot_accumulate(u[b][i], v[b][i], qu0[b][i], qu1[b][i], qv0[b][i], qv1[b][i], acc0[i],
+                                   acc1[i], acc2[i], acc3[i]);
+        }
+        for (; a < a_hi; ++a) {
+            const float4 p = pa[a];
             const float u0 = fmaf(flx, p.z, fmaf(fly, p.w, p.x));
             const float v0 = fmaf(flx, p.w, fmaf(nfly, p.z, p.y));
             const float4* __restrict__ wu = win + ((a * 2) * WL << 1);
             const float4* __restrict__ wv = win + ((a * 2 + 1) * WL << 1);
 #pragma unroll
             for (int i = 0; i < P; ++i) {
-                const float u = (i == 0) ? u0 : fmaf((float)i, p.w, u0);
-                const float v = (i == 0) ? v0 : fmaf(-(float)i, p.z, v0);
-                const int ju = (int)u;   // both > 0: truncation is floor
-                const int jv = (int)v;
-                const float4 qu0 = wu[2 * ju], qu1 = wu[2 * ju + 1];
-                const float4 qv0 = wv[2 * jv], qv1 = wv[2 * jv + 1];
-                // theta term first, then theta + pi/2, for every pixel
-                acc0[i] += fmaf(u, qu0.y, qu0.x);
-                acc0[i] += fmaf(v, qv1.w, qv1.z);
-                acc2[i] += fmaf(u, qu0.w, qu0.z);
-                acc2[i] += fmaf(v, qv1.y, qv1.x);
-                acc1[i] += fmaf(v, qv0.y, qv0.x);
-                acc1[i] += fmaf(u, qu1.y, qu1.x);
-                acc3[i] += fmaf(v, qv0.w, qv0.z);
-                acc3[i] += fmaf(u, qu1.w, qu1.z);
+                const float uu = (i == 0) ? u0 : fmaf((float)i, p.w, u0);
+                const float vv = (i == 0) ? v0 : fmaf(-(float)i, p.z, v0);
+                const int ju = (int)uu;
+                const int jv = (int)vv;
+                rot_accumulate(uu, vv, wu[2 * ju], wu[2 * ju + 1], wv[2 * jv], wv[2 * jv + 1], acc0[i], acc1[i],
+                               acc2[i], acc3[i]);
             }
         }
         __syncthreads();
@@ -464,38 +586,55 @@ __device__ __forceinline__ void bp_tile_rot4(const BpJob& job, const float* __re
     }
 }
 
-template <int TW, int P, int S, bool ROT>
-__device__ __forceinline__ void tile_dispatch(const BpJob& job, const float* q, float* img, int c0,
-                                              int r0, char* smem) {
-    if constexpr (ROT)
-        bp_tile_rot4<TW, P, S>(job, q, img, c0, r0, smem);
-    else
-        bp_tile<TW, P, S>(job, q, img, c0, r0, smem);
+template <int TW, int P, int S, bool ROT, int M>
+__device__ __forceinline__ void tile_dispatch(const BpJob& job, const SliceSet<M>& ss, int c0, int r0,
+                                              char* smem) {
+    if constexpr (ROT) {
+        static_assert(M == 1, "quarter-turn shapes backproject one slice per workgroup");
+        bp_tile_rot4<TW, P, S>(job, ss.q[0], ss.img[0], c0, r0, smem);
+    } else {
+        bp_tile<TW, P, S, M>(job, ss, c0, r0, smem);
+    }
 }
 
-// Resident waves per SIMD asked of the compiler: two workgroups per CU, except the
-// quarter-turn shapes (four accumulators per pixel row), which keep one workgroup
-// per CU rather than spill.
-template <int P, int S, bool ROT>
-constexpr int min_waves() { return ROT ? S : 2 * S; }
+// Resident waves per SIMD asked of the compiler: one workgroup per CU, so the
+// batched window reads (up to 16 float4 per lane) stay in registers.
+template <int P, int S, bool ROT, int M>
+constexpr int min_waves() { return S; }
 
-template <int TW, int P, int S, bool ROT>
-__global__ __launch_bounds__(kGroupThreads * S, (min_waves<P, S, ROT>())) void bp_grid_kernel(BpJob job, size_t q_stride,
-                                                                    size_t img_stride, int tiles_per_slice) {
+// Slices s0 .. s0 + M - 1 of a strided stack (n_total slices in all).
+template <int M>
+__device__ __forceinline__ SliceSet<M> stack_slices(const BpJob& job, size_t q_stride, size_t img_stride,
+                                                    int s0, int n_total) {
+    SliceSet<M> ss;
+    ss.n = min(M, n_total - s0);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const size_t s = (size_t)(m < ss.n ? s0 + m : s0);
+        ss.q[m] = job.q + s * q_stride;
+        ss.img[m] = job.img + s * img_stride;
+    }
+    return ss;
+}
+
+template <int TW, int P, int S, bool ROT, int M>
+__global__ __launch_bounds__(kGroupThreads * S, (min_waves<P, S, ROT, M>())) void bp_grid_kernel(
+    BpJob job, size_t q_stride, size_t img_stride, int tiles_per_slice, int n_slices) {
     extern __shared__ float4 smem4[];
     char* smem = reinterpret_cast<char*>(smem4);
     constexpr int TH = Shape<TW, P, S, ROT>::TH;
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
-    const int s = lb / tiles_per_slice;
-    const int tt = lb - s * tiles_per_slice;
+    const int sg = lb / tiles_per_slice;     // slice group: slices sg M .. sg M + M - 1
+    const int tt = lb - sg * tiles_per_slice;
     const int ty = tt / job.tiles_x;
     const int tx = tt - ty * job.tiles_x;
-    tile_dispatch<TW, P, S, ROT>(job, job.q + (size_t)s * q_stride, job.img + (size_t)s * img_stride,
-                                 tx * TW, ty * TH, smem);
+    const SliceSet<M> ss = stack_slices<M>(job, q_stride, img_stride, sg * M, n_slices);
+    tile_dispatch<TW, P, S, ROT, M>(job, ss, tx * TW, ty * TH, smem);
 }
 
-template <int TW, int P, int S, bool ROT>
-__global__ __launch_bounds__(kGroupThreads * S, (min_waves<P, S, ROT>())) void bp_list_kernel(const BpListArgs* __restrict__ args) {
+template <int TW, int P, int S, bool ROT, int M>
+__global__ __launch_bounds__(kGroupThreads * S, (min_waves<P, S, ROT, M>())) void bp_list_kernel(
+    const BpListArgs* __restrict__ args) {
     extern __shared__ float4 smem4[];
     char* smem = reinterpret_cast<char*>(smem4);
     const BpListArgs a = load_const(args);
@@ -512,118 +651,144 @@ __global__ __launch_bounds__(kGroupThreads * S, (min_waves<P, S, ROT>())) void b
             const int mid = (lo + hi + 1) >> 1;
             if (prefix[mid] <= it) lo = mid; else hi = mid - 1;
         }
-        const BpJob job = load_const(a.jobs + as_const(a.job_index)[lo]);
+        const int first = as_const(a.job_index)[lo];
+        const BpJob job = load_const(a.jobs + first);
+        SliceSet<M> ss;
+        if constexpr (M == 1) {
+            ss.n = 1;
+            ss.q[0] = job.q;
+            ss.img[0] = job.img;
+        } else {
+            // a group: jobs first .. first + n - 1 share the geometry
+            ss.n = as_const(a.group_size)[lo];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const BpJob* jm = a.jobs + first + (m < ss.n ? m : 0);
+                ss.q[m] = load_const(&jm->q);
+                ss.img[m] = load_const(&jm->img);
+            }
+        }
         const int tt = it - prefix[lo];
         const int ty = tt / job.tiles_x;
         const int tx = tt - ty * job.tiles_x;
-        tile_dispatch<TW, P, S, ROT>(job, job.q, job.img, tx * TW, ty * TH, smem);
+        tile_dispatch<TW, P, S, ROT, M>(job, ss, tx * TW, ty * TH, smem);
     }
 }
 
 constexpr TileShape kShapes[kNumTileConfigs] = {
-    {32, 2, 16, 4, "32x16 tile, 2 px/lane, 4 angle groups"},
-    {16, 2, 32, 4, "16x32 tile, 2 px/lane, 4 angle groups"},
+    {32, 2, 16, 4, "32x16 tile, 2 px/lane, 4 angle groups; 4-slice stacks", 0, 4},
+    {16, 2, 32, 4, "16x32 tile, 2 px/lane, 4 angle groups; 4-slice stacks", 0, 4},
     {32, 4, 32, 2, "32x32 tile, 4 px/lane, 2 angle groups"},
-    {32, 1, 8, 4, "32x8 tile, 1 px/lane, 4 angle groups"},
+    {32, 1, 8, 4, "32x8 tile, 1 px/lane, 4 angle groups; 4-slice stacks", 0, 4},
     {32, 4, 32, 1, "32x32 tile, 4 px/lane, 1 angle group"},
     {16, 2, 32, 2, "16x32 tile, 2 px/lane, 2 angle groups"},
     {32, 2, 16, 1, "32x16 tile, 2 px/lane, 1 angle group"},
-    {16, 1, 16, 4, "16x16 tile, 1 px/lane, 4 angle groups"},
+    {16, 1, 16, 4, "16x16 tile, 1 px/lane, 4 angle groups; 4-slice stacks", 0, 4},
     {16, 4, 64, 4, "16x64 tile, 4 px/lane, 4 angle groups"},
     {16, 2, 32, 4, "16x32 quadrant tile x 4 rotations, 2 px/lane, 4 angle groups", 1},
     {16, 1, 16, 4, "16x16 quadrant tile x 4 rotations, 1 px/lane, 4 angle groups", 1},
-    {16, 4, 64, 4, "16x64 quadrant tile x 4 rotations, 4 px/lane, 4 angle groups", 1},
 };
 
-template <int TW, int P, int S, bool ROT>
+template <int TW, int P, int S, bool ROT, int M>
 hipError_t grid_launch(const BpJob& job, int n_slices, size_t q_stride, size_t img_stride,
                        int tiles_per_slice, size_t lds, hipStream_t stream) {
-    const unsigned grid = (unsigned)n_slices * (unsigned)tiles_per_slice;
-    hipLaunchKernelGGL((bp_grid_kernel<TW, P, S, ROT>), dim3(grid), dim3(kGroupThreads * S), lds, stream,
-                       job, q_stride, img_stride, tiles_per_slice);
-    return hipGetLastError();
+    const unsigned groups = (unsigned)((n_slices + M - 1) / M);
+    const unsigned grid = groups * (unsigned)tiles_per_slice;
+    return launch_kernel(bp_grid_kernel<TW, P, S, ROT, M>, dim3(grid), dim3(kGroupThreads * S), lds, stream, job,
+                         q_stride, img_stride, tiles_per_slice, n_slices);
 }
 
-template <int TW, int P, int S, bool ROT>
+template <int TW, int P, int S, bool ROT, int M>
 hipError_t list_launch(const BpListArgs* a, int grid, size_t lds, hipStream_t stream) {
-    hipLaunchKernelGGL((bp_list_kernel<TW, P, S, ROT>), dim3(grid), dim3(kGroupThreads * S), lds, stream, a);
-    return hipGetLastError();
+    return launch_kernel(bp_list_kernel<TW, P, S, ROT, M>, dim3(grid), dim3(kGroupThreads * S), lds, stream, a);
 }
 
-template <int TW, int P, int S, bool ROT>
+template <int TW, int P, int S, bool ROT, int M>
 int occupancy(size_t lds) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_list_kernel<TW, P, S, ROT>, kGroupThreads * S,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_list_kernel<TW, P, S, ROT, M>, kGroupThreads * S,
                                                      lds) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
 
-template <int TW, int P, int S, bool ROT>
+// LDS bytes of the cross-group reduction (and of the quarter-turn transpose).
+template <int TW, int P, int S, bool ROT, int M>
 constexpr int red_bytes() {
-    return Shape<TW, P, S, ROT>::RED_BYTES > Shape<TW, P, S, ROT>::XPOSE_BYTES ? Shape<TW, P, S, ROT>::RED_BYTES
-                                                                            : Shape<TW, P, S, ROT>::XPOSE_BYTES;
+    using Sh = Shape<TW, P, S, ROT>;
+    return Sh::RED_BYTES * M > Sh::XPOSE_BYTES ? Sh::RED_BYTES * M : Sh::XPOSE_BYTES;
 }
 
-#define FBP_FOR_EACH_SHAPE(X) \
-    X(0, 32, 2, 4, false)     \
-    X(1, 16, 2, 4, false)     \
-    X(2, 32, 4, 2, false)     \
-    X(3, 32, 1, 4, false)     \
-    X(4, 32, 4, 1, false)     \
-    X(5, 16, 2, 2, false)     \
-    X(6, 32, 2, 1, false)     \
-    X(7, 16, 1, 4, false)     \
-    X(8, 16, 4, 4, false)     \
-    X(9, 16, 2, 4, true)      \
-    X(10, 16, 1, 4, true)     \
-    X(11, 16, 4, 4, true)
+// Every compiled kernel: (tile id, TW, P, S, quarter-turn, slices per workgroup).
+#define FBP_FOR_EACH_KERNEL(X)   \
+    X(0, 32, 2, 4, false, 1)     \
+    X(0, 32, 2, 4, false, 4)     \
+    X(1, 16, 2, 4, false, 1)     \
+    X(1, 16, 2, 4, false, 4)     \
+    X(2, 32, 4, 2, false, 1)     \
+    X(3, 32, 1, 4, false, 1)     \
+    X(3, 32, 1, 4, false, 4)     \
+    X(4, 32, 4, 1, false, 1)     \
+    X(5, 16, 2, 2, false, 1)     \
+    X(6, 32, 2, 1, false, 1)     \
+    X(7, 16, 1, 4, false, 1)     \
+    X(7, 16, 1, 4, false, 4)     \
+    X(8, 16, 4, 4, false, 1)     \
+    X(9, 16, 2, 4, true, 1)      \
+    X(10, 16, 1, 4, true, 1)
+
+constexpr int kernel_key(int cfg, int m) { return cfg * 8 + m; }
 
 }  // namespace
 
 const TileShape& tile_shape(int cfg) { return kShapes[cfg]; }
 
-int bp_lds_bytes(int cfg, int WL, int KB) {
-    int red = 0;
-    switch (cfg) {
-#define X(id, tw, p, s, rot) case id: red = red_bytes<tw, p, s, rot>(); break;
-        FBP_FOR_EACH_SHAPE(X)
+int bp_lds_bytes(int cfg, int m, int WL, int KB) {
+    int red = -1;
+    switch (kernel_key(cfg, m)) {
+#define X(id, tw, p, s, rot, mm) case kernel_key(id, mm): red = red_bytes<tw, p, s, rot, mm>(); break;
+        FBP_FOR_EACH_KERNEL(X)
 #undef X
         default: break;
     }
+    if (red < 0) return -1;
     if (tile_shape(cfg).rot) {
         const int win = WL * KB * 64;
         return kRotPrmBytes + (win > red ? win : red);
     }
-    const int win = WL * KB * 16;
+    const int st = (m == 1) ? 1 : (m | 1);
+    const int win = WL * KB * 16 * st;
     return kPrmBytes + (win > red ? win : red);
 }
 
-hipError_t launch_bp_grid(int cfg, const BpJob& job, int n_slices, size_t q_stride,
+hipError_t launch_bp_grid(int cfg, int m, const BpJob& job, int n_slices, size_t q_stride,
                           size_t img_stride, int tiles_per_slice, hipStream_t stream) {
-    const size_t lds = (size_t)bp_lds_bytes(cfg, job.WL, job.KB);
-    switch (cfg) {
-#define X(id, tw, p, s, rot) \
-        case id: return grid_launch<tw, p, s, rot>(job, n_slices, q_stride, img_stride, tiles_per_slice, lds, stream);
-        FBP_FOR_EACH_SHAPE(X)
+    const int lds = bp_lds_bytes(cfg, m, job.WL, job.KB);
+    if (lds < 0) return hipErrorInvalidValue;
+    switch (kernel_key(cfg, m)) {
+#define X(id, tw, p, s, rot, mm)                                                                              \
+        case kernel_key(id, mm):                                                                              \
+            return grid_launch<tw, p, s, rot, mm>(job, n_slices, q_stride, img_stride, tiles_per_slice,     \
+                                                  (size_t)lds, stream);
+        FBP_FOR_EACH_KERNEL(X)
 #undef X
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_bp_list(int cfg, const BpListArgs* a, int grid, size_t lds, hipStream_t stream) {
-    switch (cfg) {
-#define X(id, tw, p, s, rot) case id: return list_launch<tw, p, s, rot>(a, grid, lds, stream);
-        FBP_FOR_EACH_SHAPE(X)
+hipError_t launch_bp_list(int cfg, int m, const BpListArgs* a, int grid, size_t lds, hipStream_t stream) {
+    switch (kernel_key(cfg, m)) {
+#define X(id, tw, p, s, rot, mm) case kernel_key(id, mm): return list_launch<tw, p, s, rot, mm>(a, grid, lds, stream);
+        FBP_FOR_EACH_KERNEL(X)
 #undef X
         default: return hipErrorInvalidValue;
     }
 }
 
-int bp_occupancy(int cfg, size_t lds) {
-    switch (cfg) {
-#define X(id, tw, p, s, rot) case id: return occupancy<tw, p, s, rot>(lds);
-        FBP_FOR_EACH_SHAPE(X)
+int bp_occupancy(int cfg, int m, size_t lds) {
+    switch (kernel_key(cfg, m)) {
+#define X(id, tw, p, s, rot, mm) case kernel_key(id, mm): return occupancy<tw, p, s, rot, mm>(lds);
+        FBP_FOR_EACH_KERNEL(X)
 #undef X
         default: return 1;
     }

@@ -27,6 +27,19 @@ __device__ __forceinline__ T load_const(const T* p) {
     return v;
 }
 
+// Launch with the error returned by the launch itself (not a thread's sticky
+// last-error state, which an unrelated earlier call may have set).
+template <typename T>
+struct nondeduced {
+    using type = T;
+};
+template <typename... A>
+inline hipError_t launch_kernel(void (*kernel)(A...), dim3 grid, dim3 block, size_t lds, hipStream_t stream,
+                                typename nondeduced<A>::type... args) {
+    void* argv[] = {static_cast<void*>(&args)..., nullptr};
+    return hipLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, argv, lds, stream);
+}
+
 // ------------------------------------------------------------------ backprojection
 
 // Everything one slice's backprojection needs, as the kernels see it.
@@ -55,15 +68,18 @@ struct TileShape {
     int32_t tw, p, th, s;
     const char* name;
     int32_t rot = 0;      // 1: quadrant tile and its three 90-degree rotations (angle pairs)
+    int32_t multi = 1;    // slices per workgroup of the stack variant (1: none)
 };
 
 constexpr int kGroupThreads = 256;
 constexpr int kBpThreads = 256;   // threads of the GEMM workgroups
-constexpr int kNumTileConfigs = 12;
+constexpr int kNumTileConfigs = 11;
 constexpr int kMaxKB = 64;
 constexpr int kStageE = 4;        // staged (angle, bin) elements per thread per block
 // Dynamic LDS budget of one backprojection workgroup (bytes).
 constexpr int kBpLdsBudget = 48 * 1024;
+// Budget of a workgroup that backprojects several slices of one geometry.
+constexpr int kBpMultiLdsBudget = 64 * 1024;
 // LDS bytes of the per-angle constants of the current and next block (float4 each).
 constexpr int kBpPrmBytes = 2 * kMaxKB * 16;
 // Rotation-symmetric shapes: float4 + int2 per angle pair, two blocks.
@@ -78,11 +94,13 @@ const TileShape& tile_shape(int cfg);
 // largest (TW-1)|cos|/dt + (TH-1)|sin|/dt over the angles.
 inline int window_length(double span_max) { return (int)span_max + 5; }
 
-// LDS bytes of a backprojection workgroup of tile shape cfg with window WL and block KB.
-int bp_lds_bytes(int cfg, int WL, int KB);
+// LDS bytes of a backprojection workgroup of tile shape cfg that backprojects m
+// slices at once, with window WL and block KB; -1 if no such kernel is compiled.
+int bp_lds_bytes(int cfg, int m, int WL, int KB);
 
-// Backprojection of n_slices slices of one geometry (tile grid from blockIdx).
-hipError_t launch_bp_grid(int cfg, const BpJob& job, int n_slices, size_t q_stride,
+// Backprojection of n_slices slices of one geometry (tile grid from blockIdx), m
+// slices per workgroup (m = 1, or tile_shape(cfg).multi).
+hipError_t launch_bp_grid(int cfg, int m, const BpJob& job, int n_slices, size_t q_stride,
                           size_t img_stride, int tiles_per_slice, hipStream_t stream);
 
 // Persistent backprojection over a mixed list: tile index -> job by binary search in
@@ -93,11 +111,15 @@ struct BpListArgs {
     const int32_t* job_index;   // device [n_sel]: jobs of this tile shape, cost-ordered
     const int32_t* tile_prefix; // device [n_sel + 1]: exclusive prefix of tile counts
     const int32_t* counts;      // device: counts[0] = n_sel
+    // Lists of the multi-slice kernels: entry s is the group of group_size[s] jobs
+    // job_index[s] .. job_index[s] + group_size[s] - 1 (one geometry).  Unused (null)
+    // by the one-slice kernels.
+    const int32_t* group_size;
 };
 // `args` is a DEVICE pointer (the batch header in the workspace).
-hipError_t launch_bp_list(int cfg, const BpListArgs* args, int grid, size_t lds_bytes,
+hipError_t launch_bp_list(int cfg, int m, const BpListArgs* args, int grid, size_t lds_bytes,
                           hipStream_t stream);
-int bp_occupancy(int cfg, size_t lds_bytes);   // resident workgroups per CU
+int bp_occupancy(int cfg, int m, size_t lds_bytes);   // resident workgroups per CU
 
 // ------------------------------------------------------------------ ramp filter GEMM
 

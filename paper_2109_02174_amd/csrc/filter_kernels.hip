@@ -311,22 +311,20 @@ hipError_t launch_gemm_grid(int prec, const GemmJob& job, hipStream_t stream) {
     const unsigned grid = (unsigned)(tiles_m * job.tiles_n);
     const size_t lds = (size_t)gemm_lds_bytes(prec, job.Dh);
     switch (prec) {
-        case kFP32: hipLaunchKernelGGL(gemm_grid_kernel<kFP32>, dim3(grid), dim3(kBpThreads), lds, stream, job); break;
-        case kBF16: hipLaunchKernelGGL(gemm_grid_kernel<kBF16>, dim3(grid), dim3(kBpThreads), lds, stream, job); break;
-        case kFP16: hipLaunchKernelGGL(gemm_grid_kernel<kFP16>, dim3(grid), dim3(kBpThreads), lds, stream, job); break;
+        case kFP32: return launch_kernel(gemm_grid_kernel<kFP32>, dim3(grid), dim3(kBpThreads), lds, stream, job);
+        case kBF16: return launch_kernel(gemm_grid_kernel<kBF16>, dim3(grid), dim3(kBpThreads), lds, stream, job);
+        case kFP16: return launch_kernel(gemm_grid_kernel<kFP16>, dim3(grid), dim3(kBpThreads), lds, stream, job);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_gemm_list(int prec, const GemmListArgs* a, int grid, size_t lds, hipStream_t stream) {
     switch (prec) {
-        case kFP32: hipLaunchKernelGGL(gemm_list_kernel<kFP32>, dim3(grid), dim3(kBpThreads), lds, stream, a); break;
-        case kBF16: hipLaunchKernelGGL(gemm_list_kernel<kBF16>, dim3(grid), dim3(kBpThreads), lds, stream, a); break;
-        case kFP16: hipLaunchKernelGGL(gemm_list_kernel<kFP16>, dim3(grid), dim3(kBpThreads), lds, stream, a); break;
+        case kFP32: return launch_kernel(gemm_list_kernel<kFP32>, dim3(grid), dim3(kBpThreads), lds, stream, a);
+        case kBF16: return launch_kernel(gemm_list_kernel<kBF16>, dim3(grid), dim3(kBpThreads), lds, stream, a);
+        case kFP16: return launch_kernel(gemm_list_kernel<kFP16>, dim3(grid), dim3(kBpThreads), lds, stream, a);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 int gemm_occupancy(int prec, size_t lds_bytes) {

@@ -116,6 +116,7 @@ struct Plan {
     float diag[3] = {0.0f, 0.0f, 0.0f};
     int cfg = 0;
     int WL = 0, KB = 0, seg_shift = 0;
+    int multi = 1, KBm = 0;          // slices per workgroup of the stack kernel, its angle block
     int tiles_x = 0, tiles_y = 0;
     std::mutex mu;
 };
@@ -148,6 +149,7 @@ double span_for(const TileShape& s, const std::vector<double>& cs) {
 // Window length, staging row width and angle block of a tile id for a geometry.
 struct ShapeParams {
     int WL = 0, KB = 0, seg_shift = 0, tiles_x = 0, tiles_y = 0;
+    int multi = 1, KBm = 0;
 };
 
 // Angle list closed under +pi/2: theta_{k+K/2} = theta_k + pi/2 for every k < K/2.
@@ -197,6 +199,20 @@ bool shape_params(int cfg, const std::vector<double>& cs, const std::vector<doub
     const int kb_lds = (kBpLdsBudget - kBpPrmBytes) / (16 * sp->WL);
     sp->KB = std::min(kMaxKB, std::min(kb_stage, kb_lds));
     if (sp->KB < 1) return false;
+    // stack kernel: M slices' windows side by side (bin stride M | 1 float4s), one
+    // staging slot per (angle, slice, segment)
+    sp->multi = 1;
+    sp->KBm = 0;
+    if (s.multi > 1) {
+        const int m = s.multi, lm = (m == 2) ? 1 : 2;
+        const int kbm_stage = (kStageE * waves) >> (shift + lm);
+        const int kbm_lds = (kBpMultiLdsBudget - kBpPrmBytes) / (16 * sp->WL * (m | 1));
+        const int kbm = std::min(kMaxKB, std::min(kbm_stage, kbm_lds));
+        if (kbm >= 1 && bp_lds_bytes(cfg, m, sp->WL, kbm) <= kBpMultiLdsBudget) {
+            sp->multi = m;
+            sp->KBm = kbm;
+        }
+    }
     sp->tiles_x = (N + s.tw - 1) / s.tw;
     const int half_rows = (N + 1) / 2;
     sp->tiles_y = (half_rows + s.th - 1) / s.th;
@@ -208,6 +224,8 @@ void apply_shape(Plan* p, int cfg, const ShapeParams& sp) {
     p->WL = sp.WL;
     p->KB = sp.KB;
     p->seg_shift = sp.seg_shift;
+    p->multi = sp.multi;
+    p->KBm = sp.KBm;
     p->tiles_x = sp.tiles_x;
     p->tiles_y = sp.tiles_y;
 }
@@ -434,7 +452,8 @@ GemmJob gemm_job(const Plan& p, int prec, const float* sino, float* filt, int ro
     return j;
 }
 
-BpJob bp_job(const Plan& p, const float* filt, float* img) {
+// Descriptor of one slice (or, with multi, of the first slice of a group).
+BpJob bp_job(const Plan& p, const float* filt, float* img, bool multi = false) {
     BpJob j{};
     j.q = filt;
     j.img = img;
@@ -446,7 +465,7 @@ BpJob bp_job(const Plan& p, const float* filt, float* img) {
     j.K = p.K;
     j.D = p.D;
     j.WL = p.WL;
-    j.KB = p.KB;
+    j.KB = multi ? p.KBm : p.KB;
     j.seg_shift = p.seg_shift;
     j.tiles_x = p.tiles_x;
     j.scale = (float)(kPi / (double)p.K);
@@ -461,30 +480,43 @@ int run_filter(const Plan& p, int prec, int32_t n, const float* sino, float* fil
     return hip_status(launch_gemm_grid(prec, j, s));
 }
 
-int run_backproject(const Plan& p, int32_t n, const float* filt, float* img, hipStream_t s, int cfg_override = -1,
-                    const BpJob* job_override = nullptr) {
+// A stack of n slices: groups of p.multi slices per workgroup, the rest (or all,
+// without a stack kernel) one slice per workgroup.  Both give bitwise the same
+// slices.
+int run_backproject(const Plan& p, int32_t n, const float* filt, float* img, hipStream_t s) {
     if (n == 0) return FBP_OK;
-    const BpJob j = job_override ? *job_override : bp_job(p, filt, img);
-    const int cfg = cfg_override >= 0 ? cfg_override : p.cfg;
-    const int tx = p.tiles_x, ty = p.tiles_y;
-    const int64_t grid = (int64_t)n * tx * ty;
-    if (grid > INT32_MAX) return FBP_EUNSUPPORTED;
-    return hip_status(launch_bp_grid(cfg, j, n, (size_t)p.K * p.D, (size_t)p.N * p.N, tx * ty, s));
+    const int tiles = p.tiles_x * p.tiles_y;
+    const size_t qs = (size_t)p.K * p.D, is = (size_t)p.N * p.N;
+    const int32_t grouped = (p.multi > 1) ? n - n % p.multi : 0;
+    if (grouped > 0) {
+        if ((int64_t)(grouped / p.multi) * tiles > INT32_MAX) return FBP_EUNSUPPORTED;
+        const BpJob j = bp_job(p, filt, img, true);
+        const int rc = hip_status(launch_bp_grid(p.cfg, p.multi, j, grouped, qs, is, tiles, s));
+        if (rc != FBP_OK) return rc;
+    }
+    const int32_t rest = n - grouped;
+    if (rest == 0) return FBP_OK;
+    if ((int64_t)rest * tiles > INT32_MAX) return FBP_EUNSUPPORTED;
+    const BpJob j = bp_job(p, filt + (size_t)grouped * qs, img + (size_t)grouped * is);
+    return hip_status(launch_bp_grid(p.cfg, 1, j, rest, qs, is, tiles, s));
 }
 
 // ------------------------------------------------------------------ batch path
 
 // Header at the start of a batch workspace.  The list kernels read their
 // arguments from here, so one captured graph per workspace serves every batch.
+// bp[c] lists single slices of tile shape c, bpm[c] groups of slices that share
+// a geometry (stack kernel of shape c).
 struct BatchHeader {
     GemmListArgs gemm;
     BpListArgs bp[kNumTileConfigs];
-    int32_t counts[1 + kNumTileConfigs];
+    BpListArgs bpm[kNumTileConfigs];
+    int32_t counts[1 + 2 * kNumTileConfigs];
 };
 
 struct BatchLayout {
     size_t gemm_jobs = 0, gemm_prefix = 0;
-    size_t bp_jobs = 0, bp_index = 0, bp_prefix = 0;
+    size_t bp_jobs = 0, bp_index = 0, bp_prefix = 0, bp_gsize = 0;
     size_t desc_end = 0;          // end of the descriptor area (the uploaded bytes)
     std::vector<size_t> q_off;    // per job: offset of its filtered rows
     size_t total = 0;
@@ -502,7 +534,9 @@ BatchLayout batch_layout(const fbp_job* jobs, int32_t n) {
     L.bp_index = o;
     o = round_up(o + sizeof(int32_t) * (size_t)n, 256);
     L.bp_prefix = o;
-    o = round_up(o + sizeof(int32_t) * (size_t)(n + kNumTileConfigs), 256);
+    o = round_up(o + sizeof(int32_t) * (size_t)(n + 2 * kNumTileConfigs), 256);
+    L.bp_gsize = o;
+    o = round_up(o + sizeof(int32_t) * (size_t)n, 256);
     L.desc_end = o;
     L.q_off.resize((size_t)n);
     for (int32_t i = 0; i < n; ++i) {
@@ -542,12 +576,14 @@ struct GraphKey {
     int device;
     int prec;
     uintptr_t ws;
-    uint32_t cfg_mask;
+    uint32_t cfg_mask;     // tile shapes with single-slice entries
+    uint32_t multi_mask;   // tile shapes with slice groups
     int gemm_lds;
     int bp_lds;
+    int bpm_lds;
     bool operator<(const GraphKey& o) const {
-        return std::tie(device, prec, ws, cfg_mask, gemm_lds, bp_lds) <
-               std::tie(o.device, o.prec, o.ws, o.cfg_mask, o.gemm_lds, o.bp_lds);
+        return std::tie(device, prec, ws, cfg_mask, multi_mask, gemm_lds, bp_lds, bpm_lds) <
+               std::tie(o.device, o.prec, o.ws, o.cfg_mask, o.multi_mask, o.gemm_lds, o.bp_lds, o.bpm_lds);
     }
 };
 
@@ -609,18 +645,26 @@ void release_staging(Staging* st, bool recorded) {
     st->busy = false;
 }
 
-// The batch kernels: grouped GEMM over every job, then one persistent
-// backprojection launch per tile shape present, all reading the header at ws.
+// The batch kernels: grouped GEMM over every job, then persistent backprojection
+// launches (slice groups first, then single slices) per tile shape present, all
+// reading the header at ws.
 hipError_t enqueue_batch_kernels(const GraphKey& key, int cus, hipStream_t s) {
     const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(key.ws);
     const int g_occ = gemm_occupancy(key.prec, (size_t)key.gemm_lds);
     hipError_t e = launch_gemm_list(key.prec, &hdr->gemm, cus * g_occ, (size_t)key.gemm_lds, s);
     if (e != hipSuccess) return e;
     for (int c = 0; c < kNumTileConfigs; ++c) {
-        if (!(key.cfg_mask & (1u << c))) continue;
-        const int occ = bp_occupancy(c, (size_t)key.bp_lds);
-        e = launch_bp_list(c, &hdr->bp[c], cus * occ, (size_t)key.bp_lds, s);
-        if (e != hipSuccess) return e;
+        if (key.multi_mask & (1u << c)) {
+            const int m = tile_shape(c).multi;
+            const int occ = bp_occupancy(c, m, (size_t)key.bpm_lds);
+            e = launch_bp_list(c, m, &hdr->bpm[c], cus * occ, (size_t)key.bpm_lds, s);
+            if (e != hipSuccess) return e;
+        }
+        if (key.cfg_mask & (1u << c)) {
+            const int occ = bp_occupancy(c, 1, (size_t)key.bp_lds);
+            e = launch_bp_list(c, 1, &hdr->bp[c], cus * occ, (size_t)key.bp_lds, s);
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
@@ -700,51 +744,81 @@ int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes,
     BpJob* bj = reinterpret_cast<BpJob*>(img.data() + L.bp_jobs);
     int32_t* bidx = reinterpret_cast<int32_t*>(img.data() + L.bp_index);
     int32_t* bpre = reinterpret_cast<int32_t*>(img.data() + L.bp_prefix);
+    int32_t* bgsz = reinterpret_cast<int32_t*>(img.data() + L.bp_gsize);
 
-    int max_dh = 0, max_bp_lds = 0;
-    uint32_t mask = 0;
+    int max_dh = 0, max_bp_lds = 0, max_bpm_lds = 0;
+    uint32_t mask = 0, mmask = 0;
     int64_t gemm_tiles = 0;
     gp[0] = 0;
+    std::vector<float*> qptr((size_t)n);
     for (int32_t i = 0; i < n; ++i) {
         const Plan& p = *plans[(size_t)i];
         float* q = reinterpret_cast<float*>(wsc + L.q_off[(size_t)i]);
+        qptr[(size_t)i] = q;
         gj[i] = gemm_job(p, prec, jobs[i].sino, q, p.K);
         gemm_tiles += (int64_t)((p.K + kGemmBM - 1) / kGemmBM) * gj[i].tiles_n;
         if (gemm_tiles > INT32_MAX) return FBP_EUNSUPPORTED;
         gp[i + 1] = (int32_t)gemm_tiles;
-        bj[i] = bp_job(p, q, jobs[i].image);
         max_dh = std::max(max_dh, p.Dh);
-        max_bp_lds = std::max(max_bp_lds, bp_lds_bytes(p.cfg, p.WL, p.KB));
-        mask |= 1u << p.cfg;
     }
-    // Per tile shape: jobs in descending cost order (angles x per-tile work), ties by index.
-    int idx_off = 0, pre_off = 0;
-    for (int c = 0; c < kNumTileConfigs; ++c) {
-        std::vector<int32_t> sel;
-        for (int32_t i = 0; i < n; ++i)
-            if (plans[(size_t)i]->cfg == c) sel.push_back(i);
-        std::stable_sort(sel.begin(), sel.end(), [&](int32_t a, int32_t b) {
-            const Plan& pa = *plans[(size_t)a];
-            const Plan& pb = *plans[(size_t)b];
-            return (int64_t)pa.K * (pa.WL + 8) > (int64_t)pb.K * (pb.WL + 8);
-        });
+    // Per tile shape: jobs whose plan has a stack kernel go in groups of p.multi
+    // (consecutive in the job table), the rest singly; each list in descending cost
+    // order (angles x per-tile work), ties by first job index.
+    int pos = 0, idx_off = 0, pre_off = 0, cnt_off = 1;
+    auto add_list = [&](BpListArgs& a, const std::vector<std::vector<int32_t>>& items, bool multi) -> int {
         int64_t tiles = 0;
         bpre[pre_off] = 0;
-        for (size_t j = 0; j < sel.size(); ++j) {
-            const Plan& p = *plans[(size_t)sel[j]];
-            bidx[idx_off + (int)j] = sel[j];
+        for (size_t g = 0; g < items.size(); ++g) {
+            const Plan& p = *plans[(size_t)items[g][0]];
+            bidx[idx_off + (int)g] = pos;
+            bgsz[idx_off + (int)g] = (int32_t)items[g].size();
+            for (int32_t i : items[g]) bj[pos++] = bp_job(p, qptr[(size_t)i], jobs[i].image, multi);
             tiles += (int64_t)p.tiles_x * p.tiles_y;
             if (tiles > INT32_MAX) return FBP_EUNSUPPORTED;
-            bpre[pre_off + (int)j + 1] = (int32_t)tiles;
+            bpre[pre_off + (int)g + 1] = (int32_t)tiles;
         }
-        BpListArgs& a = hdr->bp[c];
         a.jobs = reinterpret_cast<const BpJob*>(wsc + L.bp_jobs);
         a.job_index = reinterpret_cast<const int32_t*>(wsc + L.bp_index) + idx_off;
         a.tile_prefix = reinterpret_cast<const int32_t*>(wsc + L.bp_prefix) + pre_off;
-        a.counts = reinterpret_cast<const int32_t*>(wsc + offsetof(BatchHeader, counts)) + 1 + c;
-        hdr->counts[1 + c] = (int32_t)sel.size();
-        idx_off += (int)sel.size();
-        pre_off += (int)sel.size() + 1;
+        a.group_size = reinterpret_cast<const int32_t*>(wsc + L.bp_gsize) + idx_off;
+        a.counts = reinterpret_cast<const int32_t*>(wsc + offsetof(BatchHeader, counts)) + cnt_off;
+        hdr->counts[cnt_off] = (int32_t)items.size();
+        idx_off += (int)items.size();
+        pre_off += (int)items.size() + 1;
+        ++cnt_off;
+        return FBP_OK;
+    };
+    auto cost = [&](const std::vector<int32_t>& it) {
+        const Plan& p = *plans[(size_t)it[0]];
+        return (int64_t)p.K * (p.WL + 8) * (int64_t)it.size();
+    };
+    auto by_cost = [&](const std::vector<int32_t>& a, const std::vector<int32_t>& b) {
+        const int64_t ca = cost(a), cb = cost(b);
+        return ca != cb ? ca > cb : a[0] < b[0];
+    };
+    for (int c = 0; c < kNumTileConfigs; ++c) {
+        std::vector<std::vector<int32_t>> groups, singles;
+        std::map<const Plan*, std::vector<int32_t>> by_plan;   // job order kept per plan
+        for (int32_t i = 0; i < n; ++i)
+            if (plans[(size_t)i]->cfg == c) by_plan[plans[(size_t)i]].push_back(i);
+        for (auto& kv : by_plan) {
+            const Plan& p = *kv.first;
+            const std::vector<int32_t>& v = kv.second;
+            const size_t m = (size_t)p.multi;
+            const size_t grouped = (m > 1) ? v.size() - v.size() % m : 0;
+            for (size_t g = 0; g < grouped; g += m)
+                groups.emplace_back(v.begin() + (ptrdiff_t)g, v.begin() + (ptrdiff_t)(g + m));
+            for (size_t g = grouped; g < v.size(); ++g) singles.push_back({v[g]});
+            if (grouped > 0) max_bpm_lds = std::max(max_bpm_lds, bp_lds_bytes(c, p.multi, p.WL, p.KBm));
+            if (grouped < v.size()) max_bp_lds = std::max(max_bp_lds, bp_lds_bytes(c, 1, p.WL, p.KB));
+        }
+        std::stable_sort(groups.begin(), groups.end(), by_cost);
+        std::stable_sort(singles.begin(), singles.end(), by_cost);
+        if (!groups.empty()) mmask |= 1u << c;
+        if (!singles.empty()) mask |= 1u << c;
+        rc = add_list(hdr->bpm[c], groups, true);
+        if (rc == FBP_OK) rc = add_list(hdr->bp[c], singles, false);
+        if (rc != FBP_OK) return rc;
     }
     hdr->gemm.jobs = reinterpret_cast<const GemmJob*>(wsc + L.gemm_jobs);
     hdr->gemm.tile_prefix = reinterpret_cast<const int32_t*>(wsc + L.gemm_prefix);
@@ -766,8 +840,10 @@ int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes,
     key.prec = prec;
     key.ws = reinterpret_cast<uintptr_t>(ws);
     key.cfg_mask = mask;
+    key.multi_mask = mmask;
     key.gemm_lds = (int)round_up((size_t)gemm_lds_bytes(prec, max_dh), 8192);
     key.bp_lds = (int)round_up((size_t)max_bp_lds, 4096);
+    key.bpm_lds = (int)round_up((size_t)max_bpm_lds, 4096);
     return launch_batch(key, cu_count(device), s);
 }
 
@@ -815,11 +891,10 @@ int autotune(const fbp_geom* g, hipStream_t s, int32_t* out_cfg) {
             ShapeParams sp;
             if (!shape_params(c, cs, p.angles, p.N, &sp)) continue;
             apply_shape(&p, c, sp);
-            const BpJob job = bp_job(p, q, im);
             float ms_min = 1e30f;
             for (int rep = 0; rep < 7 && rc == FBP_OK; ++rep) {
                 if (hipEventRecord(e0, s) != hipSuccess) { rc = FBP_EHIP; break; }
-                rc = run_backproject(p, 1, q, im, s, -1, &job);
+                rc = run_backproject(p, 1, q, im, s);
                 if (rc != FBP_OK) break;
                 if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
                     rc = FBP_EHIP;
@@ -1004,8 +1079,7 @@ int fbp_backproject_with_config(const fbp_geom* geom, int32_t n_slices, const fl
     ShapeParams sp;
     if (!shape_params(config, p->cs, p->angles, p->N, &sp)) return FBP_EUNSUPPORTED;
     apply_shape(&q, config, sp);
-    const BpJob job = bp_job(q, d_filtered, d_image);
-    return run_backproject(q, n_slices, d_filtered, d_image, (hipStream_t)hip_stream, config, &job);
+    return run_backproject(q, n_slices, d_filtered, d_image, (hipStream_t)hip_stream);
 }
 
 }  // extern "C"

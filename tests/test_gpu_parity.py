@@ -51,6 +51,8 @@ GEOMS = [
     (90, 101, 70, 1.0, "uniform", 2),     # quarter-turn symmetric, ragged quadrant tiles
     (40, 75, 50, 0.7, "uniform", 1),      # quarter-turn symmetric, dt < 1
     (2, 3, 2, 1.0, "uniform", 1),         # smallest quarter-turn case
+    (50, 101, 70, 1.0, "random", 9),      # stacks: two 4-slice groups and one single slice
+    (24, 230, 48, 0.35, "uniform", 5),    # stacks with windows over 63 bins (two staging segments)
 ]
 
 
