@@ -158,6 +158,12 @@ const char* fbp_tile_config_name(int32_t id);
 /* Static text for a status code (never NULL). */
 const char* fbp_status_string(int status);
 
+/* The HIP call behind the calling thread's most recent FBP_EHIP or FBP_ENOMEM,
+ * with HIP's error name, e.g. "hipMemcpy (filter taps): hipErrorInvalidValue (1)";
+ * "" if there was none.  Thread-local; valid until the thread's next library call
+ * that fails.  Never NULL. */
+const char* fbp_last_error(void);
+
 /* Library version string. */
 const char* fbp_version(void);
 

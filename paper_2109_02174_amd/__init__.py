@@ -9,7 +9,7 @@ from ._binding import (FBP_EHIP, FBP_EINVAL, FBP_ENOMEM, FBP_EUNSUPPORTED, FBP_E
                        FbpError, Geometry, alloc_workspace, fbp_autotune, fbp_backproject,
                        fbp_backproject_with_config, fbp_batch_workspace_bytes, fbp_filter,
                        fbp_num_tile_configs, fbp_plan_config, fbp_reconstruct,
-                       fbp_reconstruct_batch, fbp_status_string, fbp_tile_config_name, fbp_version,
+                       fbp_reconstruct_batch, fbp_status_string, fbp_tile_config_name, fbp_version, fbp_last_error,
                        fbp_workspace_bytes, load)
 
 __all__ = [
@@ -17,5 +17,5 @@ __all__ = [
     "FbpError", "Geometry", "alloc_workspace", "fbp_autotune", "fbp_backproject",
     "fbp_backproject_with_config", "fbp_batch_workspace_bytes", "fbp_filter",
     "fbp_num_tile_configs", "fbp_plan_config", "fbp_reconstruct", "fbp_reconstruct_batch",
-    "fbp_status_string", "fbp_tile_config_name", "fbp_version", "fbp_workspace_bytes", "load",
+    "fbp_status_string", "fbp_tile_config_name", "fbp_version", "fbp_last_error", "fbp_workspace_bytes", "load",
 ]

@@ -29,7 +29,12 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 
 class FbpError(RuntimeError):
     def __init__(self, status: int, where: str):
-        super().__init__(f"{where}: {fbp_status_string(status)} ({status})")
+        msg = f"{where}: {fbp_status_string(status)} ({status})"
+        if status in (FBP_EHIP, FBP_ENOMEM):
+            detail = fbp_last_error()
+            if detail:
+                msg += f" [{detail}]"
+        super().__init__(msg)
         self.status = status
 
 
@@ -71,6 +76,7 @@ def load():
         "fbp_tile_config_name": (ctypes.c_char_p, [i32]),
         "fbp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "fbp_version": (ctypes.c_char_p, []),
+        "fbp_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -135,6 +141,11 @@ def _raise(rc, where):
 
 def fbp_status_string(status: int) -> str:
     return load().fbp_status_string(int(status)).decode()
+
+
+def fbp_last_error() -> str:
+    """The HIP call behind this thread's last FBP_EHIP / FBP_ENOMEM ("" if none)."""
+    return load().fbp_last_error().decode()
 
 
 def fbp_version() -> str:

@@ -103,9 +103,10 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const SliceSet<M>& ss,
     using Sh = Shape<TW, P, S>;
     constexpr int NT = Sh::NT;
     constexpr int TH = Sh::TH;
+    constexpr int E = stage_elems(S);
     constexpr int ST = bin_stride<M>();
     constexpr int LM = log2_slices<M>();
-    constexpr int UB = (16 / (P * M) < 1) ? 1 : (16 / (P * M) > 4 ? 4 : 16 / (P * M));
+    constexpr int UB = (8 / (P * M) < 1) ? 1 : (8 / (P * M) > 4 ? 4 : 8 / (P * M));
     float4* prm = reinterpret_cast<float4*>(smem);                      // [2][kMaxKB]
     float4* win = reinterpret_cast<float4*>(smem + kPrmBytes);          // [KB][WL][ST]
 
@@ -156,11 +157,11 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const SliceSet<M>& ss,
                                                 __int_as_float(i0));
         }
     };
-    float pf[kStageE], pr[kStageE];
+    float pf[E], pr[E];
     auto load = [&](int kb, int buf) {
         const int nslot = min(KB, K - kb) << (LM + seg_shift);
 #pragma unroll
-        for (int e = 0; e < kStageE; ++e) {
+        for (int e = 0; e < E; ++e) {
             const int slot = wave + e * W;                       // wave-uniform
             if (slot < nslot) {
                 const int a = slot >> (LM + seg_shift);
@@ -182,7 +183,7 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const SliceSet<M>& ss,
     auto store = [&](int kb) {
         const int nslot = min(KB, K - kb) << (LM + seg_shift);
 #pragma unroll
-        for (int e = 0; e < kStageE; ++e) {
+        for (int e = 0; e < E; ++e) {
             const int slot = wave + e * W;
             if (slot < nslot) {
                 const int a = slot >> (LM + seg_shift);
@@ -216,7 +217,7 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const SliceSet<M>& ss,
         const float4* __restrict__ pa = prm + buf * kMaxKB;
         int a = (grp - k0 % S + S) % S;
         // UB angles per step: every window read of the step is issued before the
-        // first is consumed, so each wave keeps P M UB LDS reads in flight
+        // first is consumed, so each wave keeps P M UB (up to 8) LDS reads in flight
         for (; a + (UB - 1) * S < nb; a += UB * S) {
             float4 p[UB];
 #pragma unroll
@@ -597,10 +598,11 @@ __device__ __forceinline__ void tile_dispatch(const BpJob& job, const SliceSet<M
     }
 }
 
-// Resident waves per SIMD asked of the compiler: one workgroup per CU, so the
-// batched window reads (up to 16 float4 per lane) stay in registers.
+// Resident waves per SIMD asked of the compiler: four (128 VGPRs), so the batched
+// window reads (up to 16 float4 per lane) stay in registers while a CU still
+// holds 16 waves.
 template <int P, int S, bool ROT, int M>
-constexpr int min_waves() { return S; }
+constexpr int min_waves() { return 4; }
 
 // Slices s0 .. s0 + M - 1 of a strided stack (n_total slices in all).
 template <int M>
@@ -676,14 +678,14 @@ __global__ __launch_bounds__(kGroupThreads * S, (min_waves<P, S, ROT, M>())) voi
 }
 
 constexpr TileShape kShapes[kNumTileConfigs] = {
-    {32, 2, 16, 4, "32x16 tile, 2 px/lane, 4 angle groups; 4-slice stacks", 0, 4},
-    {16, 2, 32, 4, "16x32 tile, 2 px/lane, 4 angle groups; 4-slice stacks", 0, 4},
-    {32, 4, 32, 2, "32x32 tile, 4 px/lane, 2 angle groups"},
-    {32, 1, 8, 4, "32x8 tile, 1 px/lane, 4 angle groups; 4-slice stacks", 0, 4},
-    {32, 4, 32, 1, "32x32 tile, 4 px/lane, 1 angle group"},
-    {16, 2, 32, 2, "16x32 tile, 2 px/lane, 2 angle groups"},
-    {32, 2, 16, 1, "32x16 tile, 2 px/lane, 1 angle group"},
-    {16, 1, 16, 4, "16x16 tile, 1 px/lane, 4 angle groups; 4-slice stacks", 0, 4},
+    {32, 2, 16, 4, "32x16 tile, 2 px/lane, 4 angle groups"},
+    {16, 2, 32, 4, "16x32 tile, 2 px/lane, 4 angle groups"},
+    {32, 4, 32, 2, "32x32 tile, 4 px/lane, 2 angle groups; 2-slice stacks", 0, 2},
+    {32, 1, 8, 4, "32x8 tile, 1 px/lane, 4 angle groups"},
+    {32, 4, 32, 1, "32x32 tile, 4 px/lane, 1 angle group; 2-slice stacks", 0, 2},
+    {16, 2, 32, 2, "16x32 tile, 2 px/lane, 2 angle groups; 2-slice stacks", 0, 2},
+    {32, 2, 16, 1, "32x16 tile, 2 px/lane, 1 angle group; 4-slice stacks", 0, 4},
+    {16, 1, 16, 4, "16x16 tile, 1 px/lane, 4 angle groups"},
     {16, 4, 64, 4, "16x64 tile, 4 px/lane, 4 angle groups"},
     {16, 2, 32, 4, "16x32 quadrant tile x 4 rotations, 2 px/lane, 4 angle groups", 1},
     {16, 1, 16, 4, "16x16 quadrant tile x 4 rotations, 1 px/lane, 4 angle groups", 1},
@@ -722,17 +724,17 @@ constexpr int red_bytes() {
 // Every compiled kernel: (tile id, TW, P, S, quarter-turn, slices per workgroup).
 #define FBP_FOR_EACH_KERNEL(X)   \
     X(0, 32, 2, 4, false, 1)     \
-    X(0, 32, 2, 4, false, 4)     \
     X(1, 16, 2, 4, false, 1)     \
-    X(1, 16, 2, 4, false, 4)     \
     X(2, 32, 4, 2, false, 1)     \
+    X(2, 32, 4, 2, false, 2)     \
     X(3, 32, 1, 4, false, 1)     \
-    X(3, 32, 1, 4, false, 4)     \
     X(4, 32, 4, 1, false, 1)     \
+    X(4, 32, 4, 1, false, 2)     \
     X(5, 16, 2, 2, false, 1)     \
+    X(5, 16, 2, 2, false, 2)     \
     X(6, 32, 2, 1, false, 1)     \
+    X(6, 32, 2, 1, false, 4)     \
     X(7, 16, 1, 4, false, 1)     \
-    X(7, 16, 1, 4, false, 4)     \
     X(8, 16, 4, 4, false, 1)     \
     X(9, 16, 2, 4, true, 1)      \
     X(10, 16, 1, 4, true, 1)

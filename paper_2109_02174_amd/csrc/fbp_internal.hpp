@@ -76,6 +76,9 @@ constexpr int kBpThreads = 256;   // threads of the GEMM workgroups
 constexpr int kNumTileConfigs = 11;
 constexpr int kMaxKB = 64;
 constexpr int kStageE = 4;        // staged (angle, bin) elements per thread per block
+// Staged elements per thread per block for a shape with s angle groups: the
+// one-group shapes have a quarter of the waves, so each stages more.
+constexpr int stage_elems(int s) { return s == 1 ? 8 : kStageE; }
 // Dynamic LDS budget of one backprojection workgroup (bytes).
 constexpr int kBpLdsBudget = 48 * 1024;
 // Budget of a workgroup that backprojects several slices of one geometry.

@@ -125,7 +125,7 @@ struct Registry {
     std::mutex mu;
     std::map<GeomKey, std::unique_ptr<Plan>> plans;
     std::map<GeomKey, int> tuned;       // tile id chosen by fbp_autotune or the tune cache
-    bool tune_cache_loaded = false;
+    std::string tune_cache_loaded;      // path of the tune cache last read ("" = none)
 };
 
 Registry& registry() {
@@ -195,7 +195,7 @@ bool shape_params(int cfg, const std::vector<double>& cs, const std::vector<doub
     int shift = 0;
     while (63 * (1 << shift) < sp->WL) ++shift;
     sp->seg_shift = shift;
-    const int kb_stage = (kStageE * waves) >> shift;
+    const int kb_stage = (stage_elems(s.s) * waves) >> shift;
     const int kb_lds = (kBpLdsBudget - kBpPrmBytes) / (16 * sp->WL);
     sp->KB = std::min(kMaxKB, std::min(kb_stage, kb_lds));
     if (sp->KB < 1) return false;
@@ -205,7 +205,7 @@ bool shape_params(int cfg, const std::vector<double>& cs, const std::vector<doub
     sp->KBm = 0;
     if (s.multi > 1) {
         const int m = s.multi, lm = (m == 2) ? 1 : 2;
-        const int kbm_stage = (kStageE * waves) >> (shift + lm);
+        const int kbm_stage = (stage_elems(s.s) * waves) >> (shift + lm);
         const int kbm_lds = (kBpMultiLdsBudget - kBpPrmBytes) / (16 * sp->WL * (m | 1));
         const int kbm = std::min(kMaxKB, std::min(kbm_stage, kbm_lds));
         if (kbm >= 1 && bp_lds_bytes(cfg, m, sp->WL, kbm) <= kBpMultiLdsBudget) {
@@ -250,10 +250,12 @@ std::string arch_name(int device) {
     return colon == std::string::npos ? a : a.substr(0, colon);
 }
 
+// Entries of the tune cache named by FBP_TUNE_CACHE, read when a plan is created
+// and the variable names a file other than the one read last.
 void load_tune_cache_locked(Registry& R, int device) {
-    if (R.tune_cache_loaded) return;
-    R.tune_cache_loaded = true;
     const std::string path = tune_cache_path();
+    if (path == R.tune_cache_loaded) return;
+    R.tune_cache_loaded = path;
     if (path.empty()) return;
     std::ifstream in(path);
     if (!in) return;
@@ -282,10 +284,24 @@ int env_forced_config() {
     return (c >= 0 && c < kNumTileConfigs) ? c : -1;
 }
 
+// The HIP call behind this thread's last FBP_EHIP or FBP_ENOMEM.
+thread_local char t_last_error[256] = "";
+
+int hip_fail(hipError_t e, const char* what, int status = FBP_EHIP) {
+    std::snprintf(t_last_error, sizeof t_last_error, "%s: %s (%d)", what, hipGetErrorName(e), (int)e);
+    return status;
+}
+
+#define FBP_TRY_HIP(call)                                                   \
+    do {                                                                    \
+        const hipError_t fbp_e_ = (call);                                   \
+        if (fbp_e_ != hipSuccess) return hip_fail(fbp_e_, #call);           \
+    } while (0)
+
 // Look up or create the plan of a validated geometry on the current device.
 int get_plan(const fbp_geom* g, Plan** out) {
     int device = 0;
-    if (hipGetDevice(&device) != hipSuccess) return FBP_EHIP;
+    FBP_TRY_HIP(hipGetDevice(&device));
     const GeomKey key = make_key(device, g);
     Registry& R = registry();
     std::lock_guard<std::mutex> lock(R.mu);
@@ -330,18 +346,20 @@ int get_plan(const fbp_geom* g, Plan** out) {
     apply_shape(p.get(), cfg, sp);
     std::vector<float> cs32(p->cs.size());
     for (size_t i = 0; i < cs32.size(); ++i) cs32[i] = (float)p->cs[i];
-    if (hipMalloc(&p->d_cs, sizeof(double) * p->cs.size()) != hipSuccess) return FBP_ENOMEM;
-    if (hipMalloc(&p->d_cs32, sizeof(float) * cs32.size()) != hipSuccess) {
+    hipError_t e = hipMalloc(&p->d_cs, sizeof(double) * p->cs.size());
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (angle table)", FBP_ENOMEM);
+    e = hipMalloc(&p->d_cs32, sizeof(float) * cs32.size());
+    if (e != hipSuccess) {
         (void)hipFree(p->d_cs);
-        return FBP_ENOMEM;
+        return hip_fail(e, "hipMalloc (angle table)", FBP_ENOMEM);
     }
-    if (hipMemcpy(p->d_cs, p->cs.data(), sizeof(double) * p->cs.size(), hipMemcpyHostToDevice) !=
-            hipSuccess ||
-        hipMemcpy(p->d_cs32, cs32.data(), sizeof(float) * cs32.size(), hipMemcpyHostToDevice) !=
-            hipSuccess) {
+    e = hipMemcpy(p->d_cs, p->cs.data(), sizeof(double) * p->cs.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_cs32, cs32.data(), sizeof(float) * cs32.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
         (void)hipFree(p->d_cs);
         (void)hipFree(p->d_cs32);
-        return FBP_EHIP;
+        return hip_fail(e, "hipMemcpy (angle table)");
     }
     *out = p.get();
     R.plans[key] = std::move(p);
@@ -423,11 +441,13 @@ int ensure_taps(Plan* p, int prec) {
         }
         bytes = h16.size() * 2;
     }
-    if (hipMalloc(&dev, bytes) != hipSuccess) return FBP_ENOMEM;
+    hipError_t e = hipMalloc(&dev, bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (filter taps)", FBP_ENOMEM);
     const void* src = (prec == kFP32) ? (const void*)f32.data() : (const void*)h16.data();
-    if (hipMemcpy(dev, src, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    e = hipMemcpy(dev, src, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
         (void)hipFree(dev);
-        return FBP_EHIP;
+        return hip_fail(e, "hipMemcpy (filter taps)");
     }
     p->out_scale[prec] = out_scale;
     p->diag[prec] = diag;
@@ -472,12 +492,12 @@ BpJob bp_job(const Plan& p, const float* filt, float* img, bool multi = false) {
     return j;
 }
 
-int hip_status(hipError_t e) { return e == hipSuccess ? FBP_OK : FBP_EHIP; }
+int hip_status(hipError_t e, const char* what) { return e == hipSuccess ? FBP_OK : hip_fail(e, what); }
 
 int run_filter(const Plan& p, int prec, int32_t n, const float* sino, float* filt, hipStream_t s) {
     if (n == 0) return FBP_OK;
     const GemmJob j = gemm_job(p, prec, sino, filt, n * p.K);
-    return hip_status(launch_gemm_grid(prec, j, s));
+    return hip_status(launch_gemm_grid(prec, j, s), "filter kernel launch");
 }
 
 // A stack of n slices: groups of p.multi slices per workgroup, the rest (or all,
@@ -491,14 +511,15 @@ int run_backproject(const Plan& p, int32_t n, const float* filt, float* img, hip
     if (grouped > 0) {
         if ((int64_t)(grouped / p.multi) * tiles > INT32_MAX) return FBP_EUNSUPPORTED;
         const BpJob j = bp_job(p, filt, img, true);
-        const int rc = hip_status(launch_bp_grid(p.cfg, p.multi, j, grouped, qs, is, tiles, s));
+        const int rc = hip_status(launch_bp_grid(p.cfg, p.multi, j, grouped, qs, is, tiles, s),
+                                  "backprojection kernel launch");
         if (rc != FBP_OK) return rc;
     }
     const int32_t rest = n - grouped;
     if (rest == 0) return FBP_OK;
     if ((int64_t)rest * tiles > INT32_MAX) return FBP_EUNSUPPORTED;
     const BpJob j = bp_job(p, filt + (size_t)grouped * qs, img + (size_t)grouped * is);
-    return hip_status(launch_bp_grid(p.cfg, 1, j, rest, qs, is, tiles, s));
+    return hip_status(launch_bp_grid(p.cfg, 1, j, rest, qs, is, tiles, s), "backprojection kernel launch");
 }
 
 // ------------------------------------------------------------------ batch path
@@ -670,7 +691,7 @@ hipError_t enqueue_batch_kernels(const GraphKey& key, int cus, hipStream_t s) {
 }
 
 int launch_batch(const GraphKey& key, int cus, hipStream_t s) {
-    if (graphs_disabled()) return hip_status(enqueue_batch_kernels(key, cus, s));
+    if (graphs_disabled()) return hip_status(enqueue_batch_kernels(key, cus, s), "batch kernel launch");
     BatchState& S = batch_state();
     hipGraphExec_t exec = nullptr;
     {
@@ -684,7 +705,7 @@ int launch_batch(const GraphKey& key, int cus, hipStream_t s) {
             std::lock_guard<std::mutex> lock(S.mu);
             auto it = S.capture_stream.find(key.device);
             if (it == S.capture_stream.end()) {
-                if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return FBP_EHIP;
+                FBP_TRY_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
                 S.capture_stream[key.device] = cs;
             } else {
                 cs = it->second;
@@ -696,20 +717,20 @@ int launch_batch(const GraphKey& key, int cus, hipStream_t s) {
             exec = it->second;
         } else {
             hipGraph_t graph = nullptr;
-            if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return FBP_EHIP;
+            FBP_TRY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
             const hipError_t le = enqueue_batch_kernels(key, cus, cs);
             const hipError_t ce = hipStreamEndCapture(cs, &graph);
             if (le != hipSuccess || ce != hipSuccess || !graph) {
                 if (graph) (void)hipGraphDestroy(graph);
-                return FBP_EHIP;
+                return hip_fail(le != hipSuccess ? le : ce, "batch graph capture");
             }
             const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
-            if (ie != hipSuccess) return FBP_EHIP;
+            if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
             S.graphs[key] = exec;
         }
     }
-    return hip_status(hipGraphLaunch(exec, s));
+    return hip_status(hipGraphLaunch(exec, s), "hipGraphLaunch");
 }
 
 int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes, int32_t prec,
@@ -831,10 +852,10 @@ int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes,
     hipError_t e = hipMemcpyAsync(ws, st->host, L.desc_end, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipEventRecord(st->done, s);
     release_staging(st, e == hipSuccess);
-    if (e != hipSuccess) return FBP_EHIP;
+    if (e != hipSuccess) return hip_fail(e, "batch descriptor upload");
 
     int device = 0;
-    if (hipGetDevice(&device) != hipSuccess) return FBP_EHIP;
+    FBP_TRY_HIP(hipGetDevice(&device));
     GraphKey key;
     key.device = device;
     key.prec = prec;
@@ -849,74 +870,89 @@ int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes,
 
 // ------------------------------------------------------------------ autotuning
 
+// Device buffers and events of one tuning run, released on every exit path.
+struct TuneScratch {
+    float* q = nullptr;
+    float* im = nullptr;
+    double* dcs = nullptr;
+    float* dcs32 = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipStream_t s = nullptr;
+    ~TuneScratch() {
+        (void)hipStreamSynchronize(s);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (q) (void)hipFree(q);
+        if (im) (void)hipFree(im);
+        if (dcs) (void)hipFree(dcs);
+        if (dcs32) (void)hipFree(dcs32);
+    }
+};
+
+// Time every tile shape that supports the geometry on one zero slice (7 runs,
+// minimum of the last 5) and keep the fastest; returns FBP_OK with *best >= 0.
+int time_tile_shapes(const fbp_geom* g, const std::vector<double>& cs, hipStream_t s, int* best) {
+    TuneScratch t;
+    t.s = s;
+    const size_t qb = sino_bytes(g, 1), ib = image_bytes(g, 1);
+    std::vector<float> cs32(cs.size());
+    for (size_t i = 0; i < cs.size(); ++i) cs32[i] = (float)cs[i];
+    hipError_t e = hipMalloc(&t.q, qb);
+    if (e == hipSuccess) e = hipMalloc(&t.im, ib);
+    if (e == hipSuccess) e = hipMalloc(&t.dcs, sizeof(double) * cs.size());
+    if (e == hipSuccess) e = hipMalloc(&t.dcs32, sizeof(float) * cs32.size());
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (autotune scratch)", FBP_ENOMEM);
+    FBP_TRY_HIP(hipMemcpy(t.dcs, cs.data(), sizeof(double) * cs.size(), hipMemcpyHostToDevice));
+    FBP_TRY_HIP(hipMemcpy(t.dcs32, cs32.data(), sizeof(float) * cs32.size(), hipMemcpyHostToDevice));
+    FBP_TRY_HIP(hipMemsetAsync(t.q, 0, qb, s));
+    FBP_TRY_HIP(hipEventCreate(&t.e0));
+    FBP_TRY_HIP(hipEventCreate(&t.e1));
+    Plan p;   // scratch plan for the timing runs
+    p.K = g->n_angles;
+    p.D = g->n_det;
+    p.N = g->image_size;
+    p.dt = g->det_spacing;
+    p.cs = cs;
+    p.angles.assign(g->angles, g->angles + g->n_angles);
+    p.d_cs = t.dcs;
+    p.d_cs32 = t.dcs32;
+    *best = -1;
+    float best_ms = 0.0f;
+    for (int c = 0; c < kNumTileConfigs; ++c) {
+        ShapeParams sp;
+        if (!shape_params(c, cs, p.angles, p.N, &sp)) continue;
+        apply_shape(&p, c, sp);
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 7; ++rep) {
+            FBP_TRY_HIP(hipEventRecord(t.e0, s));
+            const int rc = run_backproject(p, 1, t.q, t.im, s);
+            if (rc != FBP_OK) return rc;
+            FBP_TRY_HIP(hipEventRecord(t.e1, s));
+            FBP_TRY_HIP(hipEventSynchronize(t.e1));
+            float ms = 0.0f;
+            FBP_TRY_HIP(hipEventElapsedTime(&ms, t.e0, t.e1));
+            if (rep >= 2) ms_min = std::min(ms_min, ms);   // first two runs warm up
+        }
+        if (*best < 0 || ms_min < best_ms) {
+            *best = c;
+            best_ms = ms_min;
+        }
+    }
+    return FBP_OK;
+}
+
 int autotune(const fbp_geom* g, hipStream_t s, int32_t* out_cfg) {
     int rc = check_geom(g);
     if (rc != FBP_OK) return rc;
     int device = 0;
-    if (hipGetDevice(&device) != hipSuccess) return FBP_EHIP;
+    FBP_TRY_HIP(hipGetDevice(&device));
     std::vector<double> cs(2 * (size_t)g->n_angles);
     for (int k = 0; k < g->n_angles; ++k) {
         cs[2 * k] = std::cos(g->angles[k]) / g->det_spacing;
         cs[2 * k + 1] = std::sin(g->angles[k]) / g->det_spacing;
     }
-    const size_t qb = sino_bytes(g, 1), ib = image_bytes(g, 1);
-    std::vector<float> cs32(cs.size());
-    for (size_t i = 0; i < cs.size(); ++i) cs32[i] = (float)cs[i];
-    float *q = nullptr, *im = nullptr, *dcs32 = nullptr;
-    double* dcs = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
     int best = -1;
-    float best_ms = 0.0f;
-    rc = FBP_OK;
-    if (hipMalloc(&q, qb) != hipSuccess || hipMalloc(&im, ib) != hipSuccess ||
-        hipMalloc(&dcs, sizeof(double) * cs.size()) != hipSuccess ||
-        hipMalloc(&dcs32, sizeof(float) * cs32.size()) != hipSuccess) {
-        rc = FBP_ENOMEM;
-    } else if (hipMemcpy(dcs, cs.data(), sizeof(double) * cs.size(), hipMemcpyHostToDevice) != hipSuccess ||
-               hipMemcpy(dcs32, cs32.data(), sizeof(float) * cs32.size(), hipMemcpyHostToDevice) != hipSuccess ||
-               hipMemsetAsync(q, 0, qb, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
-               hipEventCreate(&e1) != hipSuccess) {
-        rc = FBP_EHIP;
-    } else {
-        Plan p;   // scratch plan for the timing runs
-        p.K = g->n_angles;
-        p.D = g->n_det;
-        p.N = g->image_size;
-        p.dt = g->det_spacing;
-        p.cs = cs;
-        p.angles.assign(g->angles, g->angles + g->n_angles);
-        p.d_cs = dcs;
-        p.d_cs32 = dcs32;
-        for (int c = 0; c < kNumTileConfigs && rc == FBP_OK; ++c) {
-            ShapeParams sp;
-            if (!shape_params(c, cs, p.angles, p.N, &sp)) continue;
-            apply_shape(&p, c, sp);
-            float ms_min = 1e30f;
-            for (int rep = 0; rep < 7 && rc == FBP_OK; ++rep) {
-                if (hipEventRecord(e0, s) != hipSuccess) { rc = FBP_EHIP; break; }
-                rc = run_backproject(p, 1, q, im, s);
-                if (rc != FBP_OK) break;
-                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                    rc = FBP_EHIP;
-                    break;
-                }
-                float ms = 0.0f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (rep >= 2) ms_min = std::min(ms_min, ms);   // first two runs warm up
-            }
-            if (rc == FBP_OK && (best < 0 || ms_min < best_ms)) {
-                best = c;
-                best_ms = ms_min;
-            }
-        }
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    (void)hipStreamSynchronize(s);
-    if (q) (void)hipFree(q);
-    if (im) (void)hipFree(im);
-    if (dcs) (void)hipFree(dcs);
-    if (dcs32) (void)hipFree(dcs32);
+    rc = time_tile_shapes(g, cs, s, &best);
     if (rc != FBP_OK) return rc;
     if (best < 0) return FBP_EUNSUPPORTED;
     {
@@ -959,6 +995,8 @@ const char* fbp_status_string(int status) {
 }
 
 const char* fbp_version(void) { return "fbp-mi355x 0.1 (gfx950)"; }
+
+const char* fbp_last_error(void) { return t_last_error; }
 
 int32_t fbp_num_tile_configs(void) { return kNumTileConfigs; }
 

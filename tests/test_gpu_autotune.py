@@ -2,15 +2,11 @@
 
 The tuner times every compiled tile shape on one geometry and records the
 fastest; plans created afterwards use it, plans that already exist keep theirs.
-With FBP_TUNE_CACHE set, the choice is appended to a file that a fresh process
-reads back.  Every tile shape gives the oracle's result (checked in the parity
-tests), so tuning only moves time, never the tolerance.
+With FBP_TUNE_CACHE set, the choice is appended to a file, and the entries of the
+file it names are applied when plans are created.  Every tile shape gives the
+oracle's result (checked in the parity tests), so tuning only moves time, never
+the tolerance.
 """
-import json
-import os
-import subprocess
-import sys
-
 import numpy as np
 import pytest
 import torch
@@ -18,8 +14,6 @@ import torch
 import paper_2109_02174_amd as fbp
 
 pytestmark = pytest.mark.gpu
-
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_autotune_picks_a_valid_shape_and_new_plans_use_it():
@@ -35,24 +29,20 @@ def test_autotune_picks_a_valid_shape_and_new_plans_use_it():
     assert np.array_equal(a, fbp.fbp_backproject(g, q).cpu().numpy())
 
 
-def test_tune_cache_round_trip(tmp_path):
+def test_tune_cache_round_trip(tmp_path, monkeypatch):
+    # tuning appends "arch K D N dt_bits angle_hash tile" to the cache file
     cache = tmp_path / "tune.txt"
-    code = (
-        "import sys, json; sys.path.insert(0, %r)\n"
-        "import paper_2109_02174_amd as fbp\n"
-        "g = fbp.Geometry(61, 87, 57, 1.0)\n"
-        "mode = sys.argv[1]\n"
-        "best = fbp.fbp_autotune(g) if mode == 'tune' else -1\n"
-        "print(json.dumps({'best': best, 'plan': fbp.fbp_plan_config(g)}))\n" % ROOT)
-    env = dict(os.environ, FBP_TUNE_CACHE=str(cache))
-    out1 = subprocess.run([sys.executable, "-c", code, "tune"], env=env, capture_output=True, text=True,
-                          timeout=120)
-    assert out1.returncode == 0, out1.stderr
-    r1 = json.loads(out1.stdout.strip().splitlines()[-1])
+    monkeypatch.setenv("FBP_TUNE_CACHE", str(cache))
+    g = fbp.Geometry(61, 87, 57, 1.0)           # no plan of it exists yet
+    best = fbp.fbp_autotune(g)
     lines = cache.read_text().strip().splitlines()
-    assert len(lines) == 1 and lines[0].split()[0].startswith("gfx")
-    out2 = subprocess.run([sys.executable, "-c", code, "read"], env=env, capture_output=True, text=True,
-                          timeout=120)
-    assert out2.returncode == 0, out2.stderr
-    r2 = json.loads(out2.stdout.strip().splitlines()[-1])
-    assert r2["plan"] == r1["best"]
+    assert len(lines) == 1
+    fields = lines[0].split()
+    assert fields[0].startswith("gfx") and fields[1:4] == ["61", "87", "57"] and int(fields[-1]) == best
+    # a cache file with another entry for the geometry is read when its plan is created
+    other = next(c for c in range(fbp.fbp_num_tile_configs())
+                 if c != best and "rotations" not in fbp.fbp_tile_config_name(c))
+    cache2 = tmp_path / "tune2.txt"
+    cache2.write_text(" ".join(fields[:-1] + [str(other)]) + "\n")
+    monkeypatch.setenv("FBP_TUNE_CACHE", str(cache2))
+    assert fbp.fbp_plan_config(g) == other
