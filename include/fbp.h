@@ -100,6 +100,14 @@ int fbp_filter(const fbp_geom* geom, int32_t n_slices, const float* d_sino, floa
  * d_filtered is [n_slices][K][D], d_image is [n_slices][N][N]; no overlap.
  * Every image pixel is written.  With d_filtered = the raw sinogram this is
  * the exact adjoint of the linear-interpolation (hat) projector.
+ * Stacks of 4 or more slices run with the plan's stack tile shape
+ * (fbp_plan_stack_config), shorter ones slice by slice with its single-slice
+ * shape (fbp_plan_config).  A single-slice shape with one angle group splits
+ * the angles over several workgroups per tile and adds the parts in a fixed
+ * order from a partial-sum buffer owned by the plan (calls that use it are
+ * ordered among themselves on the device).  Results are deterministic for a
+ * given geometry, stack length and tuning; the two shapes agree within the
+ * FP32 tolerance.
  */
 int fbp_backproject(const fbp_geom* geom, int32_t n_slices, const float* d_filtered,
                     float* d_image, void* hip_stream);
@@ -119,8 +127,11 @@ size_t fbp_workspace_bytes(const fbp_geom* geom, int32_t n_slices, int32_t preci
 /*
  * Mixed-size batch (one slice per job, geometries may all differ): grouped
  * filter GEMMs and a persistent, cost-ordered backprojection launch per tile
- * shape, replayed from a captured HIP graph.  Each job's image is bitwise equal
- * to reconstructing that slice alone with fbp_reconstruct.  The workspace
+ * shape, replayed from a captured HIP graph.  Jobs of a geometry that occurs 4
+ * or more times take its stack shape (so each such image is bitwise equal to
+ * fbp_reconstruct of the geometry's stack); the others take the single-slice
+ * shape without angle split (bitwise equal to fbp_reconstruct alone unless that
+ * shape splits, then equal within the FP32 tolerance).  The workspace
  * (fbp_batch_workspace_bytes) holds the filtered rows and the tile list; calls
  * that share a workspace must be ordered on one stream.
  */
@@ -133,20 +144,28 @@ size_t fbp_batch_workspace_bytes(const fbp_job* jobs, int32_t n_jobs, int32_t pr
 /*
  * Tile-shape autotuning for one geometry: times each compiled backprojection
  * tile shape on synthetic data on `hip_stream` (allocates and frees scratch
- * memory, synchronises the stream) and records the fastest for this geometry.
- * Later plans of the geometry use it; a plan that already exists keeps its
- * shape, so results never depend on when tuning ran relative to a call.
- * `out_config` (may be NULL) receives the chosen tile id.
+ * memory, synchronises the stream), once for one slice and once per slice of a
+ * 16-slice stack, and records the fastest of each for this geometry.  Later
+ * plans of the geometry use them; a plan that already exists keeps its shapes,
+ * so results never depend on when tuning ran relative to a call.  With the
+ * environment variable FBP_TUNE_CACHE naming a file, the choice is appended to
+ * it, and the file's entries apply to plans created afterwards.
+ * `out_config` (may be NULL) receives the chosen single-slice tile id.
  */
 int fbp_autotune(const fbp_geom* geom, void* hip_stream, int32_t* out_config);
 
-/* Tile id the plan of this geometry uses, or a negative fbp_status. */
+/* Tile id the plan of this geometry uses for single slices (stacks of up to 3),
+ * or a negative fbp_status. */
 int fbp_plan_config(const fbp_geom* geom);
 
+/* Tile id the plan of this geometry uses for stacks of 4 or more slices, or a
+ * negative fbp_status. */
+int fbp_plan_stack_config(const fbp_geom* geom);
+
 /*
- * fbp_backproject with an explicit tile id instead of the plan's (for tests and
- * tuning).  Different tile ids may differ in the last bits (per-tile FP32
- * coordinates); each is deterministic.
+ * fbp_backproject with an explicit tile id in place of both of the plan's (for
+ * tests and tuning).  Different tile ids may differ in the last bits (per-tile
+ * FP32 coordinates, angle groups); each is deterministic.
  */
 int fbp_backproject_with_config(const fbp_geom* geom, int32_t n_slices, const float* d_filtered,
                                 float* d_image, int32_t config, void* hip_stream);

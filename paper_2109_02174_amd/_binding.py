@@ -71,6 +71,7 @@ def load():
         "fbp_batch_workspace_bytes": (sz, [ctypes.POINTER(c_job), i32, i32]),
         "fbp_autotune": (ctypes.c_int, [G, vp, ctypes.POINTER(i32)]),
         "fbp_plan_config": (ctypes.c_int, [G]),
+        "fbp_plan_stack_config": (ctypes.c_int, [G]),
         "fbp_backproject_with_config": (ctypes.c_int, [G, i32, vp, vp, i32, vp]),
         "fbp_num_tile_configs": (i32, []),
         "fbp_tile_config_name": (ctypes.c_char_p, [i32]),
@@ -287,4 +288,12 @@ def fbp_plan_config(geom: Geometry) -> int:
     rc = int(load().fbp_plan_config(ctypes.byref(g)))
     if rc < 0:
         raise FbpError(rc, "fbp_plan_config")
+    return rc
+
+
+def fbp_plan_stack_config(geom: Geometry) -> int:
+    g = geom.as_c()
+    rc = int(load().fbp_plan_stack_config(ctypes.byref(g)))
+    if rc < 0:
+        raise FbpError(rc, "fbp_plan_stack_config")
     return rc

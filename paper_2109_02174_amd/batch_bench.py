@@ -3,12 +3,14 @@
 Image side from {256, 384, 512, 1024}, angles from {360, 720, 1440} (uniform on
 [0, pi)), detectors ceil(sqrt(2) side) + 2, each slice a seeded 20-ellipse
 phantom with an exact FP64 sinogram generated in HBM (rounded to FP32 for the
-library).  Tile shapes come from the autotuner, one per geometry; the batch runs
-as grouped filter GEMMs plus persistent backprojection launches replayed from a
-captured HIP graph.  Reported beside it: the same slices reconstructed one per
-launch (fbp_reconstruct with one slice, no graph), and a sample of slices checked
-bitwise against the one-per-launch images.  (Agreement with the FP64 reference
-for sampled slices of this workload is checked by the GPU test-suite.)
+library).  Tile shapes come from the autotuner (a single-slice and a stack shape
+per geometry; every geometry here has far more than 4 slices, so the batch uses
+the stack shapes); the batch runs as grouped filter GEMMs plus persistent
+backprojection launches replayed from a captured HIP graph.  Reported beside it:
+the same slices reconstructed one per launch (fbp_reconstruct with one slice, no
+graph), and for a sample of slices the largest difference between the two,
+relative to the image's range.  (Agreement with the FP64 reference for sampled
+slices of this workload is checked by the GPU test-suite.)
 
 python -m paper_2109_02174_amd.batch_bench [--slices 1000] [--reps 5]
 """
@@ -68,7 +70,10 @@ def main():
     jobs, gobj, _ = build_jobs(args.slices)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
-    tuned = {f"{k[0]}x{k[1]}x{k[2]}": fbp.fbp_autotune(g) for k, g in sorted(gobj.items())}
+    tuned = {}
+    for k, g in sorted(gobj.items()):
+        fbp.fbp_autotune(g)
+        tuned[f"{k[0]}x{k[1]}x{k[2]}"] = {"single": fbp.fbp_plan_config(g), "stack": fbp.fbp_plan_stack_config(g)}
     ws = fbp.alloc_workspace(fbp.fbp_batch_workspace_bytes(jobs))
     stream = torch.cuda.current_stream()
 
@@ -109,8 +114,11 @@ def main():
         out["one_slice_per_launch"] = {"ms": base_ms, "slices_per_s": args.slices / (base_ms * 1e-3),
                                        "updates_per_s": total_upd / (base_ms * 1e-3)}
         out["speedup_vs_one_slice_per_launch"] = base_ms / batch_ms
-        out["batch_equals_alone_bitwise"] = all(
-            np.array_equal(batched[i], imgs[i].cpu().numpy()) for i in sample)
+        # geometries with 4+ slices in the batch run with their stack shape, alone with the
+        # single-slice shape: equal within the FP32 tolerance, not bitwise
+        out["batch_vs_alone_max_rel"] = max(
+            float(np.max(np.abs(batched[i] - imgs[i].cpu().numpy())) / np.max(np.abs(batched[i])))
+            for i in sample)
 
     print(json.dumps(out), flush=True)
 

@@ -35,6 +35,8 @@
 //  * Each pixel is written once by one lane; no atomics.  The summation order
 //    depends only on the tile shape, which is fixed per geometry, so repeated and
 //    batched calls are bitwise identical.
+#include <algorithm>
+
 #include "fbp_internal.hpp"
 
 namespace fbp {
@@ -96,9 +98,12 @@ constexpr int bin_stride() { return (M == 1) ? 1 : (M | 1); }
 template <int M>
 constexpr int log2_slices() { return M == 1 ? 0 : (M == 2 ? 1 : 2); }
 
+// With job.split = R > 1 the workgroup backprojects only the angles part, part + R,
+// part + 2R, ... and stores their unscaled sum (ss.img then points at the part's
+// plane of the partial-sum buffer).
 template <int TW, int P, int S, int M>
 __device__ __forceinline__ void bp_tile(const BpJob& job, const SliceSet<M>& ss, int c0, int r0,
-                                        char* smem) {
+                                        char* smem, int part) {
     static_assert(M == 1 || M == 2 || M == 4, "slices per workgroup");
     using Sh = Shape<TW, P, S>;
     constexpr int NT = Sh::NT;
@@ -115,7 +120,9 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const SliceSet<M>& ss,
     const int tl = t & (kGroupThreads - 1);
     const int lx = tl % TW;
     const int ly0 = (tl / TW) * P;
-    const int N = job.N, K = job.K, D = job.D, WL = job.WL, KB = job.KB;
+    const int N = job.N, D = job.D, WL = job.WL, KB = job.KB;
+    const int split = job.split;
+    const int K = (job.K - part + split - 1) / split;   // angles of this workgroup
     const double x0 = (double)c0 - job.half_pix;
     const double y0 = (double)r0 - job.half_pix;
     const float flx = (float)lx;
@@ -148,8 +155,9 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const SliceSet<M>& ss,
     auto params = [&](int kb, int buf) {
         const int nb = min(KB, K - kb);
         if (t < nb) {
-            const double cd = job.cs[2 * (kb + t)];
-            const double sd = job.cs[2 * (kb + t) + 1];
+            const int k = part + (kb + t) * split;
+            const double cd = job.cs[2 * k];
+            const double sd = job.cs[2 * k + 1];
             const double uo = x0 * cd + y0 * sd + job.centre_det;
             const double umin = uo + fmin(0.0, (double)(TW - 1) * cd) + fmin(0.0, (double)(TH - 1) * sd);
             const int i0 = (int)floor(umin) - 1;
@@ -173,7 +181,8 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const SliceSet<M>& ss,
                     if (m == mm) qm = ss.q[mm];
                 const int nrec = (m < ss.n) ? D * 4 : 0;
                 const __amdgpu_buffer_rsrc_t row = __builtin_amdgcn_make_buffer_rsrc(
-                    const_cast<float*>(qm + (size_t)(kb + a) * (size_t)D), (short)0, nrec, kBufferWord3);
+                    const_cast<float*>(qm + (size_t)(part + (kb + a) * split) * (size_t)D), (short)0, nrec,
+                    kBufferWord3);
                 const int g4 = (__float_as_int(prm[buf * kMaxKB + a].w) + 63 * seg + lane) * 4;
                 pf[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(row, g4, 0, 0));
                 pr[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(row, d4 - g4, 0, 0));
@@ -297,7 +306,7 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const SliceSet<M>& ss,
 
     // Each pixel of the upper half (and the middle row's left half for odd N) is
     // "primary"; its lane writes it and its reflection.
-    const float scale = job.scale;
+    const float scale = (split > 1) ? 1.0f : job.scale;
     const int half_rows = (N + 1) >> 1;
     const int c = c0 + lx;
 #pragma unroll
@@ -589,12 +598,12 @@ __device__ __forceinline__ void bp_tile_rot4(const BpJob& job, const float* __re
 
 template <int TW, int P, int S, bool ROT, int M>
 __device__ __forceinline__ void tile_dispatch(const BpJob& job, const SliceSet<M>& ss, int c0, int r0,
-                                              char* smem) {
+                                              char* smem, int part = 0) {
     if constexpr (ROT) {
         static_assert(M == 1, "quarter-turn shapes backproject one slice per workgroup");
         bp_tile_rot4<TW, P, S>(job, ss.q[0], ss.img[0], c0, r0, smem);
     } else {
-        bp_tile<TW, P, S, M>(job, ss, c0, r0, smem);
+        bp_tile<TW, P, S, M>(job, ss, c0, r0, smem, part);
     }
 }
 
@@ -630,6 +639,19 @@ __global__ __launch_bounds__(kGroupThreads * S, (min_waves<P, S, ROT, M>())) voi
     const int tt = lb - sg * tiles_per_slice;
     const int ty = tt / job.tiles_x;
     const int tx = tt - ty * job.tiles_x;
+    if constexpr (!ROT && M == 1) {
+        if (job.split > 1) {
+            // block group sg = (slice s, angle part r); the part's plane takes the sums
+            const int s = sg / job.split;
+            const int r = sg - s * job.split;
+            SliceSet<1> ss;
+            ss.n = 1;
+            ss.q[0] = job.q + (size_t)s * q_stride;
+            ss.img[0] = job.part + ((size_t)s * job.split + r) * ((size_t)job.N * job.N);
+            tile_dispatch<TW, P, S, ROT, M>(job, ss, tx * TW, ty * TH, smem, r);
+            return;
+        }
+    }
     const SliceSet<M> ss = stack_slices<M>(job, q_stride, img_stride, sg * M, n_slices);
     tile_dispatch<TW, P, S, ROT, M>(job, ss, tx * TW, ty * TH, smem);
 }
@@ -694,7 +716,8 @@ constexpr TileShape kShapes[kNumTileConfigs] = {
 template <int TW, int P, int S, bool ROT, int M>
 hipError_t grid_launch(const BpJob& job, int n_slices, size_t q_stride, size_t img_stride,
                        int tiles_per_slice, size_t lds, hipStream_t stream) {
-    const unsigned groups = (unsigned)((n_slices + M - 1) / M);
+    if (job.split > 1 && (ROT || M > 1)) return hipErrorInvalidValue;
+    const unsigned groups = (unsigned)((n_slices + M - 1) / M) * (unsigned)(job.split > 1 ? job.split : 1);
     const unsigned grid = groups * (unsigned)tiles_per_slice;
     return launch_kernel(bp_grid_kernel<TW, P, S, ROT, M>, dim3(grid), dim3(kGroupThreads * S), lds, stream, job,
                          q_stride, img_stride, tiles_per_slice, n_slices);
@@ -785,6 +808,29 @@ hipError_t launch_bp_list(int cfg, int m, const BpListArgs* a, int grid, size_t 
 #undef X
         default: return hipErrorInvalidValue;
     }
+}
+
+// Fixed-order sum of the angle parts: one thread per pixel, the parts read in
+// order 0 .. R-1 (coalesced across the wave).
+__global__ __launch_bounds__(256) void combine_parts_kernel(const float* __restrict__ part, float* __restrict__ img,
+                                                           int R, size_t plane, size_t total, float scale) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+        const size_t s = i / plane;
+        const size_t p = i - s * plane;
+        const float* src = part + s * (size_t)R * plane + p;
+        float acc = src[0];
+        for (int r = 1; r < R; ++r) acc += src[(size_t)r * plane];
+        img[i] = acc * scale;
+    }
+}
+
+hipError_t launch_combine_parts(const float* part, float* img, int n_slices, int R, size_t plane,
+                                float scale, hipStream_t stream) {
+    const size_t total = (size_t)n_slices * plane;
+    if (total == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((total + 255) / 256, 8192);
+    return launch_kernel(combine_parts_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, part, img, R, plane,
+                         total, scale);
 }
 
 int bp_occupancy(int cfg, int m, size_t lds) {

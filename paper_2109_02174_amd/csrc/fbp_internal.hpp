@@ -56,6 +56,9 @@ struct BpJob {
     int32_t seg_shift;    // log2 of the 63-bin staging segments per angle (>= WL / 63)
     int32_t tiles_x;      // tile columns of the half image
     float scale;          // pi/K
+    float* part;          // angle-split partial sums [n][split][N][N] (split > 1 only)
+    int32_t split;        // angle parts: workgroup part r takes the angles r, r + split, ...
+    int32_t pad_;
 };
 static_assert(sizeof(BpJob) % 8 == 0, "BpJob layout");
 
@@ -75,6 +78,8 @@ constexpr int kGroupThreads = 256;
 constexpr int kBpThreads = 256;   // threads of the GEMM workgroups
 constexpr int kNumTileConfigs = 11;
 constexpr int kMaxKB = 64;
+// Most angle parts a single slice's backprojection is split into (one-group shapes).
+constexpr int kMaxSplit = 16;
 constexpr int kStageE = 4;        // staged (angle, bin) elements per thread per block
 // Staged elements per thread per block for a shape with s angle groups: the
 // one-group shapes have a quarter of the waves, so each stages more.
@@ -105,6 +110,11 @@ int bp_lds_bytes(int cfg, int m, int WL, int KB);
 // slices per workgroup (m = 1, or tile_shape(cfg).multi).
 hipError_t launch_bp_grid(int cfg, int m, const BpJob& job, int n_slices, size_t q_stride,
                           size_t img_stride, int tiles_per_slice, hipStream_t stream);
+
+// img[s][i] = scale * (part[s][0][i] + part[s][1][i] + ... + part[s][R-1][i]), summed
+// in that order, for the angle-split partial sums of n_slices slices of N*N pixels.
+hipError_t launch_combine_parts(const float* part, float* img, int n_slices, int R, size_t plane,
+                                float scale, hipStream_t stream);
 
 // Persistent backprojection over a mixed list: tile index -> job by binary search in
 // tile_prefix (n_jobs + 1 entries, device); jobs and prefix live in device memory,

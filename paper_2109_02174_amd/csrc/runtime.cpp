@@ -102,6 +102,26 @@ GeomKey make_key(int device, const fbp_geom* g) {
     return k;
 }
 
+// How one tile shape runs for a geometry: window length, staging segments, angle
+// block, tile grid, stack kernel and angle split.
+struct ShapeParams {
+    int cfg = -1;
+    int WL = 0, KB = 0, seg_shift = 0, tiles_x = 0, tiles_y = 0;
+    int multi = 1, KBm = 0;   // slices per workgroup of the stack kernel, its angle block
+    int split = 1;            // angle parts of a single slice's launch (one-group shapes)
+};
+
+// Angle-split partial sums of one slice (kMaxSplit planes of N*N floats), shared by
+// every call on a plan; a call waits for the previous user's combine on its own
+// stream before overwriting them.
+struct PartBuffer {
+    float* ptr = nullptr;
+    int planes = 0;
+    hipEvent_t free_ev = nullptr;
+    bool recorded = false;
+    std::mutex mu;
+};
+
 struct Plan {
     int device = 0;
     int K = 0, D = 0, N = 0;
@@ -114,17 +134,20 @@ struct Plan {
     void* d_taps[3] = {nullptr, nullptr, nullptr};
     float out_scale[3] = {1.0f, 1.0f, 1.0f};
     float diag[3] = {0.0f, 0.0f, 0.0f};
-    int cfg = 0;
-    int WL = 0, KB = 0, seg_shift = 0;
-    int multi = 1, KBm = 0;          // slices per workgroup of the stack kernel, its angle block
-    int tiles_x = 0, tiles_y = 0;
+    ShapeParams one;                 // single slices and short stacks
+    ShapeParams stack;               // stacks of kStackMinSlices or more slices
+    PartBuffer part;
     std::mutex mu;
 };
+
+// Stacks at least this long take the stack configuration; shorter ones go slice by
+// slice through the single-slice configuration (angle-split where it has one).
+constexpr int kStackMinSlices = 4;
 
 struct Registry {
     std::mutex mu;
     std::map<GeomKey, std::unique_ptr<Plan>> plans;
-    std::map<GeomKey, int> tuned;       // tile id chosen by fbp_autotune or the tune cache
+    std::map<GeomKey, std::pair<int, int>> tuned;   // (single, stack) tile ids from fbp_autotune or the cache
     std::string tune_cache_loaded;      // path of the tune cache last read ("" = none)
 };
 
@@ -146,11 +169,6 @@ double span_for(const TileShape& s, const std::vector<double>& cs) {
     return span;
 }
 
-// Window length, staging row width and angle block of a tile id for a geometry.
-struct ShapeParams {
-    int WL = 0, KB = 0, seg_shift = 0, tiles_x = 0, tiles_y = 0;
-    int multi = 1, KBm = 0;
-};
 
 // Angle list closed under +pi/2: theta_{k+K/2} = theta_k + pi/2 for every k < K/2.
 bool quarter_turn_symmetric(const std::vector<double>& angles) {
@@ -163,8 +181,12 @@ bool quarter_turn_symmetric(const std::vector<double>& angles) {
 }
 
 bool shape_params(int cfg, const std::vector<double>& cs, const std::vector<double>& angles, int N,
-                  ShapeParams* sp) {
+                  int cus, ShapeParams* sp) {
     const TileShape& s = tile_shape(cfg);
+    sp->cfg = cfg;
+    sp->split = 1;
+    sp->multi = 1;
+    sp->KBm = 0;
     const int waves = kGroupThreads * s.s / 64;
     if (s.rot) {
         // quadrant tile plus its three rotations: even N, angles in quarter-turn pairs
@@ -201,8 +223,6 @@ bool shape_params(int cfg, const std::vector<double>& cs, const std::vector<doub
     if (sp->KB < 1) return false;
     // stack kernel: M slices' windows side by side (bin stride M | 1 float4s), one
     // staging slot per (angle, slice, segment)
-    sp->multi = 1;
-    sp->KBm = 0;
     if (s.multi > 1) {
         const int m = s.multi, lm = (m == 2) ? 1 : 2;
         const int kbm_stage = (stage_elems(s.s) * waves) >> (shift + lm);
@@ -216,26 +236,25 @@ bool shape_params(int cfg, const std::vector<double>& cs, const std::vector<doub
     sp->tiles_x = (N + s.tw - 1) / s.tw;
     const int half_rows = (N + 1) / 2;
     sp->tiles_y = (half_rows + s.th - 1) / s.th;
+    // one-group shapes split a single slice's angles over workgroups until there are
+    // about four workgroups per CU
+    if (s.s == 1) {
+        const int tiles = sp->tiles_x * sp->tiles_y;
+        sp->split = std::max(1, std::min(kMaxSplit, (4 * cus + tiles - 1) / tiles));
+    }
     return true;
 }
 
-void apply_shape(Plan* p, int cfg, const ShapeParams& sp) {
-    p->cfg = cfg;
-    p->WL = sp.WL;
-    p->KB = sp.KB;
-    p->seg_shift = sp.seg_shift;
-    p->multi = sp.multi;
-    p->KBm = sp.KBm;
-    p->tiles_x = sp.tiles_x;
-    p->tiles_y = sp.tiles_y;
-}
-
+// Shape of a single slice: enough tile pairs (or angle groups) to give every CU work.
 int default_config(int N) {
-    // Enough tile pairs to give every CU work for a single slice.
     if (N >= 1024) return 0;
     if (N >= 384) return 1;
     return 3;
 }
+
+// Shape of stacks: many slices fill the GPU, so the largest tiles with the stack
+// kernel (fewest staged bins per pixel) win.
+int default_stack_config(int N) { return N >= 256 ? 2 : 5; }
 
 std::string tune_cache_path() {
     const char* p = std::getenv("FBP_TUNE_CACHE");
@@ -262,18 +281,18 @@ void load_tune_cache_locked(Registry& R, int device) {
     const std::string arch = arch_name(device);
     std::string line;
     while (std::getline(in, line)) {
-        // one entry per line: arch K D N dt_bits angle_hash cfg
+        // one entry per line: arch K D N dt_bits angle_hash single_tile stack_tile
         std::istringstream ss(line);
         std::string a;
         GeomKey k;
-        int cfg;
+        int one, stack;
         unsigned long long dtb, ah;
-        if (!(ss >> a >> k.K >> k.D >> k.N >> dtb >> ah >> cfg)) continue;
-        if (a != arch || cfg < 0 || cfg >= kNumTileConfigs) continue;
+        if (!(ss >> a >> k.K >> k.D >> k.N >> dtb >> ah >> one >> stack)) continue;
+        if (a != arch || one < 0 || one >= kNumTileConfigs || stack < 0 || stack >= kNumTileConfigs) continue;
         k.device = device;
         k.dt_bits = dtb;
         k.angle_hash = ah;
-        R.tuned[k] = cfg;
+        R.tuned[k] = {one, stack};
     }
 }
 
@@ -297,6 +316,28 @@ int hip_fail(hipError_t e, const char* what, int status = FBP_EHIP) {
         const hipError_t fbp_e_ = (call);                                   \
         if (fbp_e_ != hipSuccess) return hip_fail(fbp_e_, #call);           \
     } while (0)
+
+// Compute units of a device (cached).
+int cu_count(int device) {
+    static std::mutex mu;
+    static std::map<int, int> counts;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = counts.find(device);
+    if (it != counts.end()) return it->second;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n < 1)
+        n = 256;
+    counts[device] = n;
+    return n;
+}
+
+// The shape of tile id cfg for a plan's geometry, or of the first shape that fits.
+bool pick_shape(int cfg, const Plan& p, int cus, ShapeParams* sp) {
+    if (cfg >= 0 && cfg < kNumTileConfigs && shape_params(cfg, p.cs, p.angles, p.N, cus, sp)) return true;
+    for (int c = 0; c < kNumTileConfigs; ++c)
+        if (shape_params(c, p.cs, p.angles, p.N, cus, sp)) return true;
+    return false;
+}
 
 // Look up or create the plan of a validated geometry on the current device.
 int get_plan(const fbp_geom* g, Plan** out) {
@@ -327,23 +368,14 @@ int get_plan(const fbp_geom* g, Plan** out) {
     }
     p->Dh = (p->D + 1) / 2;
     p->Dhp = (int)round_up((size_t)p->Dh, 64);
-    int cfg = env_forced_config();
-    if (cfg < 0) {
-        auto t = R.tuned.find(key);
-        cfg = (t != R.tuned.end()) ? t->second : default_config(p->N);
-    }
-    ShapeParams sp;
-    if (!shape_params(cfg, p->cs, p->angles, p->N, &sp)) {
-        // fall back to any shape whose window fits, else refuse
-        bool ok = false;
-        for (int c = 0; c < kNumTileConfigs && !ok; ++c)
-            if (shape_params(c, p->cs, p->angles, p->N, &sp)) {
-                cfg = c;
-                ok = true;
-            }
-        if (!ok) return FBP_EUNSUPPORTED;
-    }
-    apply_shape(p.get(), cfg, sp);
+    int one = default_config(p->N), stack = default_stack_config(p->N);
+    auto t = R.tuned.find(key);
+    if (t != R.tuned.end()) std::tie(one, stack) = t->second;
+    const int forced = env_forced_config();
+    if (forced >= 0) one = stack = forced;
+    const int cus = cu_count(device);
+    // an unsupported choice falls back to any shape whose window fits, else the geometry is refused
+    if (!pick_shape(one, *p, cus, &p->one) || !pick_shape(stack, *p, cus, &p->stack)) return FBP_EUNSUPPORTED;
     std::vector<float> cs32(p->cs.size());
     for (size_t i = 0; i < cs32.size(); ++i) cs32[i] = (float)p->cs[i];
     hipError_t e = hipMalloc(&p->d_cs, sizeof(double) * p->cs.size());
@@ -360,6 +392,20 @@ int get_plan(const fbp_geom* g, Plan** out) {
         (void)hipFree(p->d_cs);
         (void)hipFree(p->d_cs32);
         return hip_fail(e, "hipMemcpy (angle table)");
+    }
+    // partial sums of angle-split single slices (any shape's split fits); none for
+    // images over 2048^2, which then run unsplit
+    const size_t plane = (size_t)p->N * p->N;
+    if (plane <= (size_t)2048 * 2048) {
+        e = hipMalloc(&p->part.ptr, sizeof(float) * plane * kMaxSplit);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->part.free_ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipFree(p->d_cs);
+            (void)hipFree(p->d_cs32);
+            if (p->part.ptr) (void)hipFree(p->part.ptr);
+            return hip_fail(e, "hipMalloc (angle-split partial sums)", FBP_ENOMEM);
+        }
+        p->part.planes = kMaxSplit;
     }
     *out = p.get();
     R.plans[key] = std::move(p);
@@ -473,7 +519,7 @@ GemmJob gemm_job(const Plan& p, int prec, const float* sino, float* filt, int ro
 }
 
 // Descriptor of one slice (or, with multi, of the first slice of a group).
-BpJob bp_job(const Plan& p, const float* filt, float* img, bool multi = false) {
+BpJob bp_job(const Plan& p, const ShapeParams& sh, const float* filt, float* img, bool multi = false) {
     BpJob j{};
     j.q = filt;
     j.img = img;
@@ -484,11 +530,13 @@ BpJob bp_job(const Plan& p, const float* filt, float* img, bool multi = false) {
     j.N = p.N;
     j.K = p.K;
     j.D = p.D;
-    j.WL = p.WL;
-    j.KB = multi ? p.KBm : p.KB;
-    j.seg_shift = p.seg_shift;
-    j.tiles_x = p.tiles_x;
+    j.WL = sh.WL;
+    j.KB = multi ? sh.KBm : sh.KB;
+    j.seg_shift = sh.seg_shift;
+    j.tiles_x = sh.tiles_x;
     j.scale = (float)(kPi / (double)p.K);
+    j.part = nullptr;
+    j.split = 1;
     return j;
 }
 
@@ -500,26 +548,60 @@ int run_filter(const Plan& p, int prec, int32_t n, const float* sino, float* fil
     return hip_status(launch_gemm_grid(prec, j, s), "filter kernel launch");
 }
 
-// A stack of n slices: groups of p.multi slices per workgroup, the rest (or all,
-// without a stack kernel) one slice per workgroup.  Both give bitwise the same
-// slices.
-int run_backproject(const Plan& p, int32_t n, const float* filt, float* img, hipStream_t s) {
-    if (n == 0) return FBP_OK;
-    const int tiles = p.tiles_x * p.tiles_y;
+// n slices of a stack with shape sh: groups of sh.multi slices per workgroup, the
+// rest one slice per workgroup; both give bitwise the same slices.
+int run_stack(const Plan& p, const ShapeParams& sh, int32_t n, const float* filt, float* img, hipStream_t s) {
+    const int tiles = sh.tiles_x * sh.tiles_y;
     const size_t qs = (size_t)p.K * p.D, is = (size_t)p.N * p.N;
-    const int32_t grouped = (p.multi > 1) ? n - n % p.multi : 0;
+    const int32_t grouped = (sh.multi > 1) ? n - n % sh.multi : 0;
     if (grouped > 0) {
-        if ((int64_t)(grouped / p.multi) * tiles > INT32_MAX) return FBP_EUNSUPPORTED;
-        const BpJob j = bp_job(p, filt, img, true);
-        const int rc = hip_status(launch_bp_grid(p.cfg, p.multi, j, grouped, qs, is, tiles, s),
+        if ((int64_t)(grouped / sh.multi) * tiles > INT32_MAX) return FBP_EUNSUPPORTED;
+        const BpJob j = bp_job(p, sh, filt, img, true);
+        const int rc = hip_status(launch_bp_grid(sh.cfg, sh.multi, j, grouped, qs, is, tiles, s),
                                   "backprojection kernel launch");
         if (rc != FBP_OK) return rc;
     }
     const int32_t rest = n - grouped;
     if (rest == 0) return FBP_OK;
     if ((int64_t)rest * tiles > INT32_MAX) return FBP_EUNSUPPORTED;
-    const BpJob j = bp_job(p, filt + (size_t)grouped * qs, img + (size_t)grouped * is);
-    return hip_status(launch_bp_grid(p.cfg, 1, j, rest, qs, is, tiles, s), "backprojection kernel launch");
+    const BpJob j = bp_job(p, sh, filt + (size_t)grouped * qs, img + (size_t)grouped * is);
+    return hip_status(launch_bp_grid(sh.cfg, 1, j, rest, qs, is, tiles, s), "backprojection kernel launch");
+}
+
+// One slice with shape sh.  An angle-split shape backprojects its parts into the
+// partial-sum buffer (one workgroup per tile and part) and adds them in part order;
+// the buffer is used by one call at a time, in stream order.
+int run_single(const Plan& p, const ShapeParams& sh, PartBuffer* pb, const float* filt, float* img, hipStream_t s) {
+    if (sh.split <= 1 || !pb || !pb->ptr || pb->planes < sh.split) return run_stack(p, sh, 1, filt, img, s);
+    const int tiles = sh.tiles_x * sh.tiles_y;
+    if ((int64_t)tiles * sh.split > INT32_MAX) return FBP_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(pb->mu);
+    if (pb->recorded) FBP_TRY_HIP(hipStreamWaitEvent(s, pb->free_ev, 0));
+    BpJob j = bp_job(p, sh, filt, img);
+    j.part = pb->ptr;
+    j.split = sh.split;
+    const size_t qs = (size_t)p.K * p.D, is = (size_t)p.N * p.N;
+    int rc = hip_status(launch_bp_grid(sh.cfg, 1, j, 1, qs, is, tiles, s), "backprojection kernel launch");
+    if (rc == FBP_OK)
+        rc = hip_status(launch_combine_parts(pb->ptr, img, 1, sh.split, is, j.scale, s), "partial-sum kernel launch");
+    if (rc != FBP_OK) return rc;
+    FBP_TRY_HIP(hipEventRecord(pb->free_ev, s));
+    pb->recorded = true;
+    return FBP_OK;
+}
+
+// n slices: long stacks with the stack shape, short ones slice by slice with the
+// single-slice shape.
+int run_backproject(Plan& p, const ShapeParams& one, const ShapeParams& stack, int32_t n, const float* filt,
+                    float* img, hipStream_t s) {
+    if (n == 0) return FBP_OK;
+    if (n >= kStackMinSlices) return run_stack(p, stack, n, filt, img, s);
+    const size_t qs = (size_t)p.K * p.D, is = (size_t)p.N * p.N;
+    for (int32_t i = 0; i < n; ++i) {
+        const int rc = run_single(p, one, &p.part, filt + (size_t)i * qs, img + (size_t)i * is, s);
+        if (rc != FBP_OK) return rc;
+    }
+    return FBP_OK;
 }
 
 // ------------------------------------------------------------------ batch path
@@ -613,7 +695,6 @@ struct BatchState {
     std::vector<std::unique_ptr<Staging>> staging;
     std::map<GraphKey, hipGraphExec_t> graphs;
     std::map<int, hipStream_t> capture_stream;   // per device, default priority
-    std::map<int, int> cu_count;
 };
 
 BatchState& batch_state() {
@@ -624,18 +705,6 @@ BatchState& batch_state() {
 bool graphs_disabled() {
     const char* e = std::getenv("FBP_DISABLE_GRAPHS");
     return e && *e && *e != '0';
-}
-
-int cu_count(int device) {
-    BatchState& S = batch_state();
-    std::lock_guard<std::mutex> lock(S.mu);
-    auto it = S.cu_count.find(device);
-    if (it != S.cu_count.end()) return it->second;
-    int n = 0;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n < 1)
-        n = 256;
-    S.cu_count[device] = n;
-    return n;
 }
 
 Staging* acquire_staging(size_t need) {
@@ -782,19 +851,26 @@ int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes,
         gp[i + 1] = (int32_t)gemm_tiles;
         max_dh = std::max(max_dh, p.Dh);
     }
-    // Per tile shape: jobs whose plan has a stack kernel go in groups of p.multi
-    // (consecutive in the job table), the rest singly; each list in descending cost
-    // order (angles x per-tile work), ties by first job index.
+    // Jobs of a plan with kStackMinSlices or more jobs in the batch take its stack
+    // shape: groups of sh.multi slices (consecutive in the job table) and the rest
+    // singly; jobs of other plans go singly with the single-slice shape (unsplit: the
+    // batch fills the GPU).  Each list is in descending cost order (angles x per-tile
+    // work), ties by first job index.
+    struct Item {
+        std::vector<int32_t> jobs;
+        const ShapeParams* sh;
+    };
     int pos = 0, idx_off = 0, pre_off = 0, cnt_off = 1;
-    auto add_list = [&](BpListArgs& a, const std::vector<std::vector<int32_t>>& items, bool multi) -> int {
+    auto add_list = [&](BpListArgs& a, const std::vector<Item>& items, bool multi) -> int {
         int64_t tiles = 0;
         bpre[pre_off] = 0;
         for (size_t g = 0; g < items.size(); ++g) {
-            const Plan& p = *plans[(size_t)items[g][0]];
+            const Plan& p = *plans[(size_t)items[g].jobs[0]];
+            const ShapeParams& sh = *items[g].sh;
             bidx[idx_off + (int)g] = pos;
-            bgsz[idx_off + (int)g] = (int32_t)items[g].size();
-            for (int32_t i : items[g]) bj[pos++] = bp_job(p, qptr[(size_t)i], jobs[i].image, multi);
-            tiles += (int64_t)p.tiles_x * p.tiles_y;
+            bgsz[idx_off + (int)g] = (int32_t)items[g].jobs.size();
+            for (int32_t i : items[g].jobs) bj[pos++] = bp_job(p, sh, qptr[(size_t)i], jobs[i].image, multi);
+            tiles += (int64_t)sh.tiles_x * sh.tiles_y;
             if (tiles > INT32_MAX) return FBP_EUNSUPPORTED;
             bpre[pre_off + (int)g + 1] = (int32_t)tiles;
         }
@@ -809,36 +885,45 @@ int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes,
         ++cnt_off;
         return FBP_OK;
     };
-    auto cost = [&](const std::vector<int32_t>& it) {
-        const Plan& p = *plans[(size_t)it[0]];
-        return (int64_t)p.K * (p.WL + 8) * (int64_t)it.size();
+    auto cost = [&](const Item& it) {
+        const Plan& p = *plans[(size_t)it.jobs[0]];
+        return (int64_t)p.K * (it.sh->WL + 8) * (int64_t)it.jobs.size();
     };
-    auto by_cost = [&](const std::vector<int32_t>& a, const std::vector<int32_t>& b) {
+    auto by_cost = [&](const Item& a, const Item& b) {
         const int64_t ca = cost(a), cb = cost(b);
-        return ca != cb ? ca > cb : a[0] < b[0];
+        return ca != cb ? ca > cb : a.jobs[0] < b.jobs[0];
     };
-    for (int c = 0; c < kNumTileConfigs; ++c) {
-        std::vector<std::vector<int32_t>> groups, singles;
+    std::vector<std::vector<Item>> groups(kNumTileConfigs), singles(kNumTileConfigs);
+    {
         std::map<const Plan*, std::vector<int32_t>> by_plan;   // job order kept per plan
-        for (int32_t i = 0; i < n; ++i)
-            if (plans[(size_t)i]->cfg == c) by_plan[plans[(size_t)i]].push_back(i);
-        for (auto& kv : by_plan) {
-            const Plan& p = *kv.first;
-            const std::vector<int32_t>& v = kv.second;
-            const size_t m = (size_t)p.multi;
+        std::vector<const Plan*> order;                       // plans in order of first job
+        for (int32_t i = 0; i < n; ++i) {
+            auto& v = by_plan[plans[(size_t)i]];
+            if (v.empty()) order.push_back(plans[(size_t)i]);
+            v.push_back(i);
+        }
+        for (const Plan* pp : order) {
+            const Plan& p = *pp;
+            const std::vector<int32_t>& v = by_plan[pp];
+            const bool stacked = (int)v.size() >= kStackMinSlices;
+            const ShapeParams& sh = stacked ? p.stack : p.one;
+            const size_t m = stacked ? (size_t)sh.multi : 1;
             const size_t grouped = (m > 1) ? v.size() - v.size() % m : 0;
             for (size_t g = 0; g < grouped; g += m)
-                groups.emplace_back(v.begin() + (ptrdiff_t)g, v.begin() + (ptrdiff_t)(g + m));
-            for (size_t g = grouped; g < v.size(); ++g) singles.push_back({v[g]});
-            if (grouped > 0) max_bpm_lds = std::max(max_bpm_lds, bp_lds_bytes(c, p.multi, p.WL, p.KBm));
-            if (grouped < v.size()) max_bp_lds = std::max(max_bp_lds, bp_lds_bytes(c, 1, p.WL, p.KB));
+                groups[(size_t)sh.cfg].push_back({std::vector<int32_t>(v.begin() + (ptrdiff_t)g,
+                                                                       v.begin() + (ptrdiff_t)(g + m)), &sh});
+            for (size_t g = grouped; g < v.size(); ++g) singles[(size_t)sh.cfg].push_back({{v[g]}, &sh});
+            if (grouped > 0) max_bpm_lds = std::max(max_bpm_lds, bp_lds_bytes(sh.cfg, sh.multi, sh.WL, sh.KBm));
+            if (grouped < v.size()) max_bp_lds = std::max(max_bp_lds, bp_lds_bytes(sh.cfg, 1, sh.WL, sh.KB));
         }
-        std::stable_sort(groups.begin(), groups.end(), by_cost);
-        std::stable_sort(singles.begin(), singles.end(), by_cost);
-        if (!groups.empty()) mmask |= 1u << c;
-        if (!singles.empty()) mask |= 1u << c;
-        rc = add_list(hdr->bpm[c], groups, true);
-        if (rc == FBP_OK) rc = add_list(hdr->bp[c], singles, false);
+    }
+    for (int c = 0; c < kNumTileConfigs; ++c) {
+        std::stable_sort(groups[(size_t)c].begin(), groups[(size_t)c].end(), by_cost);
+        std::stable_sort(singles[(size_t)c].begin(), singles[(size_t)c].end(), by_cost);
+        if (!groups[(size_t)c].empty()) mmask |= 1u << c;
+        if (!singles[(size_t)c].empty()) mask |= 1u << c;
+        rc = add_list(hdr->bpm[c], groups[(size_t)c], true);
+        if (rc == FBP_OK) rc = add_list(hdr->bp[c], singles[(size_t)c], false);
         if (rc != FBP_OK) return rc;
     }
     hdr->gemm.jobs = reinterpret_cast<const GemmJob*>(wsc + L.gemm_jobs);
@@ -876,12 +961,15 @@ struct TuneScratch {
     float* im = nullptr;
     double* dcs = nullptr;
     float* dcs32 = nullptr;
+    PartBuffer part;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipStream_t s = nullptr;
     ~TuneScratch() {
         (void)hipStreamSynchronize(s);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
+        if (part.free_ev) (void)hipEventDestroy(part.free_ev);
+        if (part.ptr) (void)hipFree(part.ptr);
         if (q) (void)hipFree(q);
         if (im) (void)hipFree(im);
         if (dcs) (void)hipFree(dcs);
@@ -889,19 +977,29 @@ struct TuneScratch {
     }
 };
 
-// Time every tile shape that supports the geometry on one zero slice (7 runs,
-// minimum of the last 5) and keep the fastest; returns FBP_OK with *best >= 0.
-int time_tile_shapes(const fbp_geom* g, const std::vector<double>& cs, hipStream_t s, int* best) {
+constexpr int kTuneStackSlices = 16;
+
+// Time every tile shape that supports the geometry, on zero slices (7 runs, minimum
+// of the last 5): one slice through the single-slice path, and a stack of
+// kTuneStackSlices through the stack path.  Keeps the fastest of each.
+int time_tile_shapes(const fbp_geom* g, const std::vector<double>& cs, hipStream_t s, int* best_one,
+                     int* best_stack) {
     TuneScratch t;
     t.s = s;
-    const size_t qb = sino_bytes(g, 1), ib = image_bytes(g, 1);
+    const size_t qb = sino_bytes(g, kTuneStackSlices), ib = image_bytes(g, kTuneStackSlices);
+    const size_t plane = (size_t)g->image_size * (size_t)g->image_size;
     std::vector<float> cs32(cs.size());
     for (size_t i = 0; i < cs.size(); ++i) cs32[i] = (float)cs[i];
     hipError_t e = hipMalloc(&t.q, qb);
     if (e == hipSuccess) e = hipMalloc(&t.im, ib);
     if (e == hipSuccess) e = hipMalloc(&t.dcs, sizeof(double) * cs.size());
     if (e == hipSuccess) e = hipMalloc(&t.dcs32, sizeof(float) * cs32.size());
+    if (e == hipSuccess && plane <= (size_t)2048 * 2048) {
+        e = hipMalloc(&t.part.ptr, sizeof(float) * plane * kMaxSplit);
+        t.part.planes = kMaxSplit;
+    }
     if (e != hipSuccess) return hip_fail(e, "hipMalloc (autotune scratch)", FBP_ENOMEM);
+    FBP_TRY_HIP(hipEventCreateWithFlags(&t.part.free_ev, hipEventDisableTiming));
     FBP_TRY_HIP(hipMemcpy(t.dcs, cs.data(), sizeof(double) * cs.size(), hipMemcpyHostToDevice));
     FBP_TRY_HIP(hipMemcpy(t.dcs32, cs32.data(), sizeof(float) * cs32.size(), hipMemcpyHostToDevice));
     FBP_TRY_HIP(hipMemsetAsync(t.q, 0, qb, s));
@@ -916,16 +1014,14 @@ int time_tile_shapes(const fbp_geom* g, const std::vector<double>& cs, hipStream
     p.angles.assign(g->angles, g->angles + g->n_angles);
     p.d_cs = t.dcs;
     p.d_cs32 = t.dcs32;
-    *best = -1;
-    float best_ms = 0.0f;
-    for (int c = 0; c < kNumTileConfigs; ++c) {
-        ShapeParams sp;
-        if (!shape_params(c, cs, p.angles, p.N, &sp)) continue;
-        apply_shape(&p, c, sp);
+    int device = 0;
+    FBP_TRY_HIP(hipGetDevice(&device));
+    const int cus = cu_count(device);
+    auto time_ms = [&](auto&& run, float* out) -> int {
         float ms_min = 1e30f;
         for (int rep = 0; rep < 7; ++rep) {
             FBP_TRY_HIP(hipEventRecord(t.e0, s));
-            const int rc = run_backproject(p, 1, t.q, t.im, s);
+            const int rc = run();
             if (rc != FBP_OK) return rc;
             FBP_TRY_HIP(hipEventRecord(t.e1, s));
             FBP_TRY_HIP(hipEventSynchronize(t.e1));
@@ -933,9 +1029,26 @@ int time_tile_shapes(const fbp_geom* g, const std::vector<double>& cs, hipStream
             FBP_TRY_HIP(hipEventElapsedTime(&ms, t.e0, t.e1));
             if (rep >= 2) ms_min = std::min(ms_min, ms);   // first two runs warm up
         }
-        if (*best < 0 || ms_min < best_ms) {
-            *best = c;
-            best_ms = ms_min;
+        *out = ms_min;
+        return FBP_OK;
+    };
+    *best_one = *best_stack = -1;
+    float one_ms = 0.0f, stack_ms = 0.0f;
+    for (int c = 0; c < kNumTileConfigs; ++c) {
+        ShapeParams sp;
+        if (!shape_params(c, cs, p.angles, p.N, cus, &sp)) continue;
+        float ms = 0.0f;
+        int rc = time_ms([&] { return run_single(p, sp, &t.part, t.q, t.im, s); }, &ms);
+        if (rc != FBP_OK) return rc;
+        if (*best_one < 0 || ms < one_ms) {
+            *best_one = c;
+            one_ms = ms;
+        }
+        rc = time_ms([&] { return run_stack(p, sp, kTuneStackSlices, t.q, t.im, s); }, &ms);
+        if (rc != FBP_OK) return rc;
+        if (*best_stack < 0 || ms < stack_ms) {
+            *best_stack = c;
+            stack_ms = ms;
         }
     }
     return FBP_OK;
@@ -951,25 +1064,25 @@ int autotune(const fbp_geom* g, hipStream_t s, int32_t* out_cfg) {
         cs[2 * k] = std::cos(g->angles[k]) / g->det_spacing;
         cs[2 * k + 1] = std::sin(g->angles[k]) / g->det_spacing;
     }
-    int best = -1;
-    rc = time_tile_shapes(g, cs, s, &best);
+    int one = -1, stack = -1;
+    rc = time_tile_shapes(g, cs, s, &one, &stack);
     if (rc != FBP_OK) return rc;
-    if (best < 0) return FBP_EUNSUPPORTED;
+    if (one < 0 || stack < 0) return FBP_EUNSUPPORTED;
     {
         Registry& R = registry();
         std::lock_guard<std::mutex> lock(R.mu);
         const GeomKey key = make_key(device, g);
-        R.tuned[key] = best;
+        R.tuned[key] = {one, stack};
         const std::string path = tune_cache_path();
         if (!path.empty()) {
             std::ofstream out(path, std::ios::app);
             if (out)
                 out << arch_name(device) << ' ' << key.K << ' ' << key.D << ' ' << key.N << ' '
                     << (unsigned long long)key.dt_bits << ' ' << (unsigned long long)key.angle_hash << ' '
-                    << best << '\n';
+                    << one << ' ' << stack << '\n';
         }
     }
-    if (out_cfg) *out_cfg = best;
+    if (out_cfg) *out_cfg = one;
     return FBP_OK;
 }
 
@@ -1048,7 +1161,7 @@ int fbp_backproject(const fbp_geom* geom, int32_t n_slices, const float* d_filte
     Plan* p = nullptr;
     rc = get_plan(geom, &p);
     if (rc != FBP_OK) return rc;
-    return run_backproject(*p, n_slices, d_filtered, d_image, (hipStream_t)hip_stream);
+    return run_backproject(*p, p->one, p->stack, n_slices, d_filtered, d_image, (hipStream_t)hip_stream);
 }
 
 int fbp_reconstruct(const fbp_geom* geom, int32_t n_slices, const float* d_sino, float* d_image,
@@ -1072,7 +1185,7 @@ int fbp_reconstruct(const fbp_geom* geom, int32_t n_slices, const float* d_sino,
     float* filt = static_cast<float*>(d_workspace);
     const hipStream_t s = (hipStream_t)hip_stream;
     rc = run_filter(*p, precision, n_slices, d_sino, filt, s);
-    if (rc == FBP_OK) rc = run_backproject(*p, n_slices, filt, d_image, s);
+    if (rc == FBP_OK) rc = run_backproject(*p, p->one, p->stack, n_slices, filt, d_image, s);
     return rc;
 }
 
@@ -1091,7 +1204,15 @@ int fbp_plan_config(const fbp_geom* geom) {
     if (rc != FBP_OK) return rc;
     Plan* p = nullptr;
     const int prc = get_plan(geom, &p);
-    return prc == FBP_OK ? p->cfg : prc;
+    return prc == FBP_OK ? p->one.cfg : prc;
+}
+
+int fbp_plan_stack_config(const fbp_geom* geom) {
+    const int rc = check_geom(geom);
+    if (rc != FBP_OK) return rc;
+    Plan* p = nullptr;
+    const int prc = get_plan(geom, &p);
+    return prc == FBP_OK ? p->stack.cfg : prc;
 }
 
 int fbp_backproject_with_config(const fbp_geom* geom, int32_t n_slices, const float* d_filtered,
@@ -1107,17 +1228,9 @@ int fbp_backproject_with_config(const fbp_geom* geom, int32_t n_slices, const fl
     Plan* p = nullptr;
     rc = get_plan(geom, &p);
     if (rc != FBP_OK) return rc;
-    Plan q;   // same geometry, other tile shape
-    q.K = p->K;
-    q.D = p->D;
-    q.N = p->N;
-    q.dt = p->dt;
-    q.d_cs = p->d_cs;
-    q.d_cs32 = p->d_cs32;
-    ShapeParams sp;
-    if (!shape_params(config, p->cs, p->angles, p->N, &sp)) return FBP_EUNSUPPORTED;
-    apply_shape(&q, config, sp);
-    return run_backproject(q, n_slices, d_filtered, d_image, (hipStream_t)hip_stream);
+    ShapeParams sp;   // the plan's geometry with the given shape in both roles
+    if (!shape_params(config, p->cs, p->angles, p->N, cu_count(p->device), &sp)) return FBP_EUNSUPPORTED;
+    return run_backproject(*p, sp, sp, n_slices, d_filtered, d_image, (hipStream_t)hip_stream);
 }
 
 }  // extern "C"

@@ -12,8 +12,11 @@ waiter per stream resolves each request's future when its batch completes,
 returns its bytes to the budget, and records latency from arrival to
 completion.
 
-Every image is bitwise the image the same slice gets alone: tile shapes and
-summation order depend only on the geometry (see include/fbp.h).
+Every image equals the image the same request gets alone within the FP32
+tolerance, and bitwise when both ran with the same tile shape: a geometry with
+4 or more slices in a batch takes its stack shape, otherwise its single-slice
+shape (see include/fbp.h); tile shapes and summation order depend only on the
+geometry and that choice.
 
 The executor is an interface, so the scheduling logic runs on the CPU in tests
 with a fake executor; GpuExecutor drives libfbp.

@@ -1,7 +1,8 @@
 """GPU: tile autotuning and the tune cache.
 
-The tuner times every compiled tile shape on one geometry and records the
-fastest; plans created afterwards use it, plans that already exist keep theirs.
+The tuner times every compiled tile shape on one geometry, for one slice and
+for stacks, and records the fastest of each; plans created afterwards use them,
+plans that already exist keep theirs.
 With FBP_TUNE_CACHE set, the choice is appended to a file, and the entries of the
 file it names are applied when plans are created.  Every tile shape gives the
 oracle's result (checked in the parity tests), so tuning only moves time, never
@@ -30,7 +31,7 @@ def test_autotune_picks_a_valid_shape_and_new_plans_use_it():
 
 
 def test_tune_cache_round_trip(tmp_path, monkeypatch):
-    # tuning appends "arch K D N dt_bits angle_hash tile" to the cache file
+    # tuning appends "arch K D N dt_bits angle_hash single_tile stack_tile" to the cache file
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("FBP_TUNE_CACHE", str(cache))
     g = fbp.Geometry(61, 87, 57, 1.0)           # no plan of it exists yet
@@ -38,11 +39,13 @@ def test_tune_cache_round_trip(tmp_path, monkeypatch):
     lines = cache.read_text().strip().splitlines()
     assert len(lines) == 1
     fields = lines[0].split()
-    assert fields[0].startswith("gfx") and fields[1:4] == ["61", "87", "57"] and int(fields[-1]) == best
-    # a cache file with another entry for the geometry is read when its plan is created
-    other = next(c for c in range(fbp.fbp_num_tile_configs())
-                 if c != best and "rotations" not in fbp.fbp_tile_config_name(c))
+    assert fields[0].startswith("gfx") and fields[1:4] == ["61", "87", "57"] and int(fields[-2]) == best
+    # a cache file with other entries for the geometry is read when its plan is created
+    plain = [c for c in range(fbp.fbp_num_tile_configs()) if "rotations" not in fbp.fbp_tile_config_name(c)]
+    one = next(c for c in plain if c != best)
+    stack = next(c for c in plain if c != int(fields[-1]))
     cache2 = tmp_path / "tune2.txt"
-    cache2.write_text(" ".join(fields[:-1] + [str(other)]) + "\n")
+    cache2.write_text(" ".join(fields[:-2] + [str(one), str(stack)]) + "\n")
     monkeypatch.setenv("FBP_TUNE_CACHE", str(cache2))
-    assert fbp.fbp_plan_config(g) == other
+    assert fbp.fbp_plan_config(g) == one
+    assert fbp.fbp_plan_stack_config(g) == stack
