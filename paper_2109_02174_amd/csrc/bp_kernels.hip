@@ -341,7 +341,9 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const SliceSet<M>& ss,
 //     R^3 p : theta rev at V,   theta+pi/2 rev at U
 // (R(x, y) = (-y, x); "rev" is the reversed filtered row, as for the point
 // reflection).  Each window bin holds both angles' forward and reversed (A, dL)
-// pairs in 32 bytes: 8 updates per 2 coordinates, 2 truncations, 4 ds_read_b128.
+// pairs in two float4 planes (theta, theta + pi/2), so lanes at consecutive bins
+// read 16-byte-strided addresses without bank conflicts: 8 updates per 2
+// coordinates, 2 truncations, 4 ds_read_b128.
 // The eight updates of one angle pair (theta, theta + pi/2) for a pixel and its
 // three rotations, from the coordinates U, V and the window bins read at them;
 // the theta term first, then theta + pi/2, for every pixel.
@@ -358,16 +360,18 @@ __device__ __forceinline__ void rot_accumulate(float u, float v, const float4& q
     acc3 += fmaf(u, qu1.w, qu1.z);
 }
 
+// With job.split = R > 1 the workgroup takes only the angle pairs part, part + R,
+// ... and stores their unscaled sums (img then points at the part's plane).
 template <int TW, int P, int S>
 __device__ __forceinline__ void bp_tile_rot4(const BpJob& job, const float* __restrict__ q,
-                                             float* __restrict__ img, int c0, int r0, char* smem) {
+                                             float* __restrict__ img, int c0, int r0, char* smem, int part) {
     using Sh = Shape<TW, P, S, true>;
     constexpr int NT = Sh::NT;
     constexpr int TH = Sh::TH;
     constexpr int UB = (4 / P < 1) ? 1 : 4 / P;
     float4* prm = reinterpret_cast<float4*>(smem);                        // [2][kMaxKB]
     int2* pri = reinterpret_cast<int2*>(smem + 2 * kMaxKB * 16);          // [2][kMaxKB]
-    float4* win = reinterpret_cast<float4*>(smem + kRotPrmBytes);         // [KB][2][WL][2]
+    float4* win = reinterpret_cast<float4*>(smem + kRotPrmBytes);         // [KB][2][2][WL]
 
     const int t = threadIdx.x;
     const int grp = __builtin_amdgcn_readfirstlane(t >> 8);
@@ -375,7 +379,9 @@ __device__ __forceinline__ void bp_tile_rot4(const BpJob& job, const float* __re
     const int lx = tl % TW;
     const int ly0 = (tl / TW) * P;
     const int N = job.N, D = job.D, WL = job.WL, KB = job.KB;
-    const int K2 = job.K >> 1;                 // angle pairs (k, k + K/2)
+    const int KH = job.K >> 1;                 // angle pairs (k, k + K/2)
+    const int split = job.split;
+    const int K2 = (KH - part + split - 1) / split;   // pairs of this workgroup
     const double x0 = (double)c0 - job.half_pix;
     const double y0 = (double)r0 - job.half_pix;
     const float flx = (float)lx;
@@ -401,8 +407,9 @@ __device__ __forceinline__ void bp_tile_rot4(const BpJob& job, const float* __re
     auto params = [&](int kb, int buf) {
         const int nb = min(KB, K2 - kb);
         if (t < nb) {
-            const double cd = job.cs[2 * (kb + t)];
-            const double sd = job.cs[2 * (kb + t) + 1];
+            const int k = part + (kb + t) * split;
+            const double cd = job.cs[2 * k];
+            const double sd = job.cs[2 * k + 1];
             const double uo = x0 * cd + y0 * sd + job.centre_det;
             const double umin = uo + fmin(0.0, (double)(TW - 1) * cd) + fmin(0.0, (double)(TH - 1) * sd);
             const double vo = x0 * sd - y0 * cd + job.centre_det;
@@ -426,10 +433,11 @@ __device__ __forceinline__ void bp_tile_rot4(const BpJob& job, const float* __re
                 const int a = slot >> (seg_shift + 1);
                 const int w = (slot >> seg_shift) & 1;
                 const int seg = slot & ((1 << seg_shift) - 1);
+                const int k = part + (kb + a) * split;
                 const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
-                    const_cast<float*>(q + (size_t)(kb + a) * (size_t)D), (short)0, D * 4, kBufferWord3);
+                    const_cast<float*>(q + (size_t)k * (size_t)D), (short)0, D * 4, kBufferWord3);
                 const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
-                    const_cast<float*>(q + (size_t)(kb + a + K2) * (size_t)D), (short)0, D * 4, kBufferWord3);
+                    const_cast<float*>(q + (size_t)(k + KH) * (size_t)D), (short)0, D * 4, kBufferWord3);
                 const int2 io = pri[buf * kMaxKB + a];
                 const int g4 = ((w ? io.y : io.x) + 63 * seg + lane) * 4;
                 pf[e][0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, g4, 0, 0));
@@ -457,9 +465,9 @@ __device__ __forceinline__ void bp_tile_rot4(const BpJob& job, const float* __re
                     float d[4];
 #pragma unroll
                     for (int c = 0; c < 4; ++c) d[c] = nx[c] - pf[e][c];
-                    float4* dst = win + (((a * 2 + w) * WL + j) << 1);
+                    float4* dst = win + (a * 2 + w) * 2 * WL + j;
                     dst[0] = make_float4(fmaf(-jj, d[0], pf[e][0]), d[0], fmaf(-jj, d[1], pf[e][1]), d[1]);
-                    dst[1] = make_float4(fmaf(-jj, d[2], pf[e][2]), d[2], fmaf(-jj, d[3], pf[e][3]), d[3]);
+                    dst[WL] = make_float4(fmaf(-jj, d[2], pf[e][2]), d[2], fmaf(-jj, d[3], pf[e][3]), d[3]);
                 }
             }
         }
@@ -492,18 +500,18 @@ __device__ __forceinline__ void bp_tile_rot4(const BpJob& job, const float* __re
             for (int b = 0; b < UB; ++b) {
                 const float u0 = fmaf(flx, p[b].z, fmaf(fly, p[b].w, p[b].x));
                 const float v0 = fmaf(flx, p[b].w, fmaf(nfly, p[b].z, p[b].y));
-                const float4* __restrict__ wu = win + (((a + b) * 2) * WL << 1);
-                const float4* __restrict__ wv = win + (((a + b) * 2 + 1) * WL << 1);
+                const float4* __restrict__ wu = win + (a + b) * 4 * WL;
+                const float4* __restrict__ wv = wu + 2 * WL;
 #pragma unroll
                 for (int i = 0; i < P; ++i) {
                     u[b][i] = (i == 0) ? u0 : fmaf((float)i, p[b].w, u0);
                     v[b][i] = (i == 0) ? v0 : fmaf(-(float)i, p[b].z, v0);
                     const int ju = (int)u[b][i];   // both > 0: truncation is floor
                     const int jv = (int)v[b][i];
-                    qu0[b][i] = wu[2 * ju];
-                    qu1[b][i] = wu[2 * ju + 1];
-                    qv0[b][i] = wv[2 * jv];
-                    qv1[b][i] = wv[2 * jv + 1];
+                    qu0[b][i] = wu[ju];
+                    qu1[b][i] = wu[WL + ju];
+                    qv0[b][i] = wv[jv];
+                    qv1[b][i] = wv[WL + jv];
                 }
             }
 #pragma unroll
@@ -517,15 +525,15 @@ __device__ __forceinline__ void bp_tile_rot4(const BpJob& job, const float* __re
             const float4 p = pa[a];
             const float u0 = fmaf(flx, p.z, fmaf(fly, p.w, p.x));
             const float v0 = fmaf(flx, p.w, fmaf(nfly, p.z, p.y));
-            const float4* __restrict__ wu = win + ((a * 2) * WL << 1);
-            const float4* __restrict__ wv = win + ((a * 2 + 1) * WL << 1);
+            const float4* __restrict__ wu = win + a * 4 * WL;
+            const float4* __restrict__ wv = wu + 2 * WL;
 #pragma unroll
             for (int i = 0; i < P; ++i) {
                 const float uu = (i == 0) ? u0 : fmaf((float)i, p.w, u0);
                 const float vv = (i == 0) ? v0 : fmaf(-(float)i, p.z, v0);
                 const int ju = (int)uu;
                 const int jv = (int)vv;
-                rot_accumulate(uu, vv, wu[2 * ju], wu[2 * ju + 1], wv[2 * jv], wv[2 * jv + 1], acc0[i], acc1[i],
+                rot_accumulate(uu, vv, wu[ju], wu[WL + ju], wv[jv], wv[WL + jv], acc0[i], acc1[i],
                                acc2[i], acc3[i]);
             }
         }
@@ -563,7 +571,7 @@ __device__ __forceinline__ void bp_tile_rot4(const BpJob& job, const float* __re
 
     // p and R^2 p store directly; R p and R^3 p go through LDS so the transposed
     // tiles are written row-contiguously.
-    const float scale = job.scale;
+    const float scale = (split > 1) ? 1.0f : job.scale;
     const int half = N >> 1;
     const int c = c0 + lx;
     float* x1 = red;                                // [TH][TW + 1]
@@ -601,7 +609,7 @@ __device__ __forceinline__ void tile_dispatch(const BpJob& job, const SliceSet<M
                                               char* smem, int part = 0) {
     if constexpr (ROT) {
         static_assert(M == 1, "quarter-turn shapes backproject one slice per workgroup");
-        bp_tile_rot4<TW, P, S>(job, ss.q[0], ss.img[0], c0, r0, smem);
+        bp_tile_rot4<TW, P, S>(job, ss.q[0], ss.img[0], c0, r0, smem, part);
     } else {
         bp_tile<TW, P, S, M>(job, ss, c0, r0, smem, part);
     }
@@ -639,7 +647,7 @@ __global__ __launch_bounds__(kGroupThreads * S, (min_waves<P, S, ROT, M>())) voi
     const int tt = lb - sg * tiles_per_slice;
     const int ty = tt / job.tiles_x;
     const int tx = tt - ty * job.tiles_x;
-    if constexpr (!ROT && M == 1) {
+    if constexpr (M == 1) {
         if (job.split > 1) {
             // block group sg = (slice s, angle part r); the part's plane takes the sums
             const int s = sg / job.split;
@@ -711,12 +719,14 @@ constexpr TileShape kShapes[kNumTileConfigs] = {
     {16, 4, 64, 4, "16x64 tile, 4 px/lane, 4 angle groups"},
     {16, 2, 32, 4, "16x32 quadrant tile x 4 rotations, 2 px/lane, 4 angle groups", 1},
     {16, 1, 16, 4, "16x16 quadrant tile x 4 rotations, 1 px/lane, 4 angle groups", 1},
+    {32, 4, 32, 1, "32x32 quadrant tile x 4 rotations, 4 px/lane, 1 angle group", 1},
+    {16, 2, 32, 1, "16x32 quadrant tile x 4 rotations, 2 px/lane, 1 angle group", 1},
 };
 
 template <int TW, int P, int S, bool ROT, int M>
 hipError_t grid_launch(const BpJob& job, int n_slices, size_t q_stride, size_t img_stride,
                        int tiles_per_slice, size_t lds, hipStream_t stream) {
-    if (job.split > 1 && (ROT || M > 1)) return hipErrorInvalidValue;
+    if (job.split > 1 && M > 1) return hipErrorInvalidValue;
     const unsigned groups = (unsigned)((n_slices + M - 1) / M) * (unsigned)(job.split > 1 ? job.split : 1);
     const unsigned grid = groups * (unsigned)tiles_per_slice;
     return launch_kernel(bp_grid_kernel<TW, P, S, ROT, M>, dim3(grid), dim3(kGroupThreads * S), lds, stream, job,
@@ -760,7 +770,9 @@ constexpr int red_bytes() {
     X(7, 16, 1, 4, false, 1)     \
     X(8, 16, 4, 4, false, 1)     \
     X(9, 16, 2, 4, true, 1)      \
-    X(10, 16, 1, 4, true, 1)
+    X(10, 16, 1, 4, true, 1)     \
+    X(11, 32, 4, 1, true, 1)     \
+    X(12, 16, 2, 1, true, 1)
 
 constexpr int kernel_key(int cfg, int m) { return cfg * 8 + m; }
 
@@ -810,10 +822,35 @@ hipError_t launch_bp_list(int cfg, int m, const BpListArgs* a, int grid, size_t 
     }
 }
 
-// Fixed-order sum of the angle parts: one thread per pixel, the parts read in
-// order 0 .. R-1 (coalesced across the wave).
-__global__ __launch_bounds__(256) void combine_parts_kernel(const float* __restrict__ part, float* __restrict__ img,
-                                                           int R, size_t plane, size_t total, float scale) {
+// Fixed-order sum of the angle parts, four pixels per thread (float4 loads, the
+// parts read in order 0 .. R-1, coalesced across the wave); plane % 4 == 0.
+__global__ __launch_bounds__(256) void combine_parts_kernel(const float4* __restrict__ part, float4* __restrict__ img,
+                                                           int R, size_t plane4, size_t total4, float scale) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total4; i += (size_t)gridDim.x * 256) {
+        const size_t s = i / plane4;
+        const size_t p = i - s * plane4;
+        const float4* src = part + s * (size_t)R * plane4 + p;
+        float4 v[kMaxSplit];   // every part's load in flight before the first add
+#pragma unroll
+        for (int r = 0; r < kMaxSplit; ++r)
+            if (r < R) v[r] = src[(size_t)r * plane4];
+        float4 acc = v[0];
+#pragma unroll
+        for (int r = 1; r < kMaxSplit; ++r) {
+            if (r < R) {
+                acc.x += v[r].x;
+                acc.y += v[r].y;
+                acc.z += v[r].z;
+                acc.w += v[r].w;
+            }
+        }
+        img[i] = make_float4(acc.x * scale, acc.y * scale, acc.z * scale, acc.w * scale);
+    }
+}
+
+// The same for planes of any size, one pixel per thread.
+__global__ __launch_bounds__(256) void combine_parts_kernel_1(const float* __restrict__ part, float* __restrict__ img,
+                                                             int R, size_t plane, size_t total, float scale) {
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
         const size_t s = i / plane;
         const size_t p = i - s * plane;
@@ -828,8 +865,17 @@ hipError_t launch_combine_parts(const float* part, float* img, int n_slices, int
                                 float scale, hipStream_t stream) {
     const size_t total = (size_t)n_slices * plane;
     if (total == 0) return hipSuccess;
+    const bool vec = (plane % 4 == 0) && (reinterpret_cast<uintptr_t>(part) % 16 == 0) &&
+                     (reinterpret_cast<uintptr_t>(img) % 16 == 0);
+    if (vec) {
+        const size_t total4 = total / 4;
+        const size_t blocks = std::min<size_t>((total4 + 255) / 256, 8192);
+        return launch_kernel(combine_parts_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
+                             reinterpret_cast<const float4*>(part), reinterpret_cast<float4*>(img), R, plane / 4,
+                             total4, scale);
+    }
     const size_t blocks = std::min<size_t>((total + 255) / 256, 8192);
-    return launch_kernel(combine_parts_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, part, img, R, plane,
+    return launch_kernel(combine_parts_kernel_1, dim3((unsigned)blocks), dim3(256), 0, stream, part, img, R, plane,
                          total, scale);
 }
 

@@ -76,7 +76,7 @@ struct TileShape {
 
 constexpr int kGroupThreads = 256;
 constexpr int kBpThreads = 256;   // threads of the GEMM workgroups
-constexpr int kNumTileConfigs = 11;
+constexpr int kNumTileConfigs = 13;
 constexpr int kMaxKB = 64;
 // Most angle parts a single slice's backprojection is split into (one-group shapes).
 constexpr int kMaxSplit = 16;

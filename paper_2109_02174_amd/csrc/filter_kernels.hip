@@ -15,8 +15,9 @@
 // memory: each workgroup copies the slice of the 1D odd-tap table its outputs
 // need into LDS and feeds the B operand from there.
 //
-// Workgroup: 256 lanes = 4 waves; tile = 32 rows x 64 output bins.  Wave w owns
-// rows 16 (w/2) .. +16 and the output bins of parity w%2 (two 16x16 MFMA blocks).
+// Workgroup: 256 lanes = 4 waves; tile = 32 rows x kGemmBN output bins.  Wave w
+// owns rows 16 (w/2) .. +16 and the output bins of parity w%2 (kGemmBN/32 16x16
+// MFMA blocks).
 // A ring of register buffers keeps several chunks of sinogram rows in flight
 // while the current one is multiplied.
 //   FP32:       v_mfma_f32_16x16x4_f32, 32 inputs per parity per chunk.
@@ -38,6 +39,7 @@ typedef unsigned short v8u16 __attribute__((ext_vector_type(8)));
 constexpr int kTM = kGemmBM;        // rows per tile (32)
 constexpr int kTN = kGemmBN;        // output bins per tile (64 = 32 per parity)
 constexpr int kHalfN = kTN / 2;
+constexpr int kNB = kHalfN / 16;     // 16x16 MFMA blocks per wave
 
 __device__ __forceinline__ unsigned short to_bf16_rne(float x) {
     unsigned int u = __float_as_uint(x);
@@ -55,6 +57,23 @@ __device__ __forceinline__ float round_operand(float x) {
     if constexpr (PREC == kBF16) return __uint_as_float((unsigned int)to_bf16_rne(x) << 16);
     else if constexpr (PREC == kFP16) return (float)(_Float16)x;
     else return x;
+}
+
+// Buffer resource over rows m0 .. m0 + rows - 1 of P (row length D): loads at byte
+// offsets past the end return 0, so the padded rows and columns of a tile read
+// as zeros without branches (which would make the compiler wait for every load
+// in flight before each chunk instead of only the one it consumes).
+constexpr int kBufWord3 = 0x00020000;   // 32-bit data format, raw (stride 0) buffer
+constexpr int kOutOfRange = 0x7FFFFFF0;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rows(const float* P, int m0, int rows, int D) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(P + (size_t)m0 * D), (short)0, rows * D * 4,
+                                             kBufWord3);
+}
+
+__device__ __forceinline__ float load_elem(__amdgpu_buffer_rsrc_t rows, int row, int col, int D) {
+    const int off = (col < D) ? (row * D + col) * 4 : kOutOfRange;
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rows, off, 0, 0));
 }
 
 // Epilogue: lane l of a 16x16 block holds rows 4 (l/16) + i, column l % 16.
@@ -99,13 +118,12 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
     // ring of kPD chunks of 64 input columns in registers: chunk c + kPD - 1 is
     // loaded while chunk c is multiplied, hiding several chunks of load latency
     float pf[kPD][8];
+    const __amdgpu_buffer_rsrc_t prow = tile_rows(P, m0, min(kTM, R - m0), D);
     auto load = [&](float (&r)[8], int c0) {   // columns c0 .. c0+63 of rows m0 .. m0+31
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int e = t + i * kBpThreads;
-            const int row = e >> 6, col = c0 + (e & 63);
-            const int m = m0 + row;
-            r[i] = (m < R && col < D) ? P[(size_t)m * D + col] : 0.0f;
+            r[i] = load_elem(prow, e >> 6, c0 + (e & 63), D);
         }
     };
     auto store = [&](const float (&r)[8]) {
@@ -117,36 +135,39 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
         }
     };
 
-    v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    v4f acc[kNB];
+#pragma unroll
+    for (int j = 0; j < kNB; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
     const float* __restrict__ Arow = As + ((1 - sg) * kTM + wm * 16 + (l & 15)) * kAS32 + (l >> 4);
     const int bbase = (l & 15) - (l >> 4) + sg - jlo + nh0;   // + 16 ntile - m'
     const int nch = (D + 2 * kK32 - 1) / (2 * kK32);
+    // every chunk load is issued unconditionally (chunks past the end read zeros),
+    // so the wait before a chunk's store covers only that chunk
 #pragma unroll
-    for (int c = 0; c < kPD - 1; ++c)
-        if (c < nch) load(pf[c], c * 2 * kK32);
+    for (int c = 0; c < kPD - 1; ++c) load(pf[c], c * 2 * kK32);
     for (int cb = 0; cb < nch; cb += kPD) {
 #pragma unroll
         for (int u = 0; u < kPD; ++u) {
             const int c = cb + u;
+            load(pf[(u + kPD - 1) % kPD], (c + kPD - 1) * 2 * kK32);
+            __syncthreads();
+            store(pf[u]);
+            __syncthreads();
             if (c < nch) {
-                if (c + kPD - 1 < nch) load(pf[(u + kPD - 1) % kPD], (c + kPD - 1) * 2 * kK32);
-                __syncthreads();
-                store(pf[u]);
-                __syncthreads();
                 const int mh0 = c * kK32;
 #pragma unroll
                 for (int kk = 0; kk < kK32; kk += 4) {
                     const float a = Arow[kk];
-                    const float b0 = Bt[bbase - (mh0 + kk)];
-                    const float b1 = Bt[bbase + 16 - (mh0 + kk)];
-                    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc1, 0, 0, 0);
+#pragma unroll
+                    for (int j = 0; j < kNB; ++j)
+                        acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, Bt[bbase + 16 * j - (mh0 + kk)], acc[j],
+                                                                      0, 0, 0);
                 }
             }
         }
     }
-    store_block<kFP32>(acc0, job, m0 + wm * 16, nh0, sg);
-    store_block<kFP32>(acc1, job, m0 + wm * 16, nh0 + 16, sg);
+#pragma unroll
+    for (int j = 0; j < kNB; ++j) store_block<kFP32>(acc[j], job, m0 + wm * 16, nh0 + 16 * j, sg);
 }
 
 // ---------------------------------------------------------------- 16-bit operands
@@ -183,13 +204,12 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
     }
 
     float pf[kPD16][16];
+    const __amdgpu_buffer_rsrc_t prow = tile_rows(P, m0, min(kTM, R - m0), D);
     auto load = [&](float (&r)[16], int c0) {   // columns c0 .. c0+127 of rows m0 .. m0+31
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int e = t + i * kBpThreads;
-            const int row = e >> 7, col = c0 + (e & 127);
-            const int m = m0 + row;
-            r[i] = (m < R && col < D) ? P[(size_t)m * D + col] : 0.0f;
+            r[i] = load_elem(prow, e >> 7, c0 + (e & 127), D);
         }
     };
     auto store = [&](const float (&r)[16]) {
@@ -202,48 +222,48 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
         }
     };
 
-    v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    v4f acc[kNB];
+#pragma unroll
+    for (int j = 0; j < kNB; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
     const unsigned short* Arow = As + ((1 - sg) * kTM + wm * 16 + (l & 15)) * kAS16 + 8 * (l >> 4);
     const int kq = 8 * (l >> 4);
     const int nch = (D + 2 * kK16 - 1) / (2 * kK16);
 #pragma unroll
-    for (int c = 0; c < kPD16 - 1; ++c)
-        if (c < nch) load(pf[c], c * 2 * kK16);
+    for (int c = 0; c < kPD16 - 1; ++c) load(pf[c], c * 2 * kK16);
     for (int cb = 0; cb < nch; cb += kPD16) {
 #pragma unroll
         for (int u = 0; u < kPD16; ++u) {
             const int c = cb + u;
+            load(pf[(u + kPD16 - 1) % kPD16], (c + kPD16 - 1) * 2 * kK16);
+            __syncthreads();
+            store(pf[u]);
+            __syncthreads();
             if (c < nch) {
-                if (c + kPD16 - 1 < nch) load(pf[(u + kPD16 - 1) % kPD16], (c + kPD16 - 1) * 2 * kK16);
-                __syncthreads();
-                store(pf[u]);
-                __syncthreads();
                 const int mh0 = c * kK16;
 #pragma unroll
                 for (int ks = 0; ks < kK16; ks += 32) {
                     const v8u16 av = *reinterpret_cast<const v8u16*>(Arow + ks);
                     const int ya = (mh0 + ks + kq) - (nh0 + (l & 15)) - sg - ylo;
-                    const int yb = ya - 16;
-                    const int ca = ya & 7, cb2 = yb & 7;
-                    const v8u16 b0 = *reinterpret_cast<const v8u16*>(Tc + ca * cstride + (ya - ca));
-                    const v8u16 b1 = *reinterpret_cast<const v8u16*>(Tc + cb2 * cstride + (yb - cb2));
-                    if constexpr (PREC == kBF16) {
-                        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av),
-                                                                       __builtin_bit_cast(v8bf, b0), acc0, 0, 0, 0);
-                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av),
-                                                                       __builtin_bit_cast(v8bf, b1), acc1, 0, 0, 0);
-                    } else {
-                        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, av),
-                                                                      __builtin_bit_cast(v8h, b0), acc0, 0, 0, 0);
-                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, av),
-                                                                      __builtin_bit_cast(v8h, b1), acc1, 0, 0, 0);
+#pragma unroll
+                    for (int j = 0; j < kNB; ++j) {
+                        const int y = ya - 16 * j;
+                        const int cy = y & 7;
+                        const v8u16 bv = *reinterpret_cast<const v8u16*>(Tc + cy * cstride + (y - cy));
+                        if constexpr (PREC == kBF16)
+                            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av),
+                                                                             __builtin_bit_cast(v8bf, bv), acc[j],
+                                                                             0, 0, 0);
+                        else
+                            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, av),
+                                                                            __builtin_bit_cast(v8h, bv), acc[j],
+                                                                            0, 0, 0);
                     }
                 }
             }
         }
     }
-    store_block<PREC>(acc0, job, m0 + wm * 16, nh0, sg);
-    store_block<PREC>(acc1, job, m0 + wm * 16, nh0 + 16, sg);
+#pragma unroll
+    for (int j = 0; j < kNB; ++j) store_block<PREC>(acc[j], job, m0 + wm * 16, nh0 + 16 * j, sg);
 }
 
 template <int PREC>

@@ -208,6 +208,10 @@ bool shape_params(int cfg, const std::vector<double>& cs, const std::vector<doub
         const int half = N / 2;
         sp->tiles_x = (half + s.tw - 1) / s.tw;
         sp->tiles_y = (half + s.th - 1) / s.th;
+        if (s.s == 1) {
+            const int tiles = sp->tiles_x * sp->tiles_y;
+            sp->split = std::max(1, std::min(kMaxSplit, (4 * cus + tiles - 1) / tiles));
+        }
         return true;
     }
     const double span = span_for(s, cs);
@@ -245,15 +249,19 @@ bool shape_params(int cfg, const std::vector<double>& cs, const std::vector<doub
     return true;
 }
 
-// Shape of a single slice: enough tile pairs (or angle groups) to give every CU work.
-int default_config(int N) {
-    if (N >= 1024) return 0;
-    if (N >= 384) return 1;
-    return 3;
+// Shape of a single slice without tuning (measured on MI355X): the one-group
+// shapes split their angles over workgroups; the quarter-turn ones need even N
+// and angles closed under +pi/2.
+int default_config(int N, bool quarter_turn) {
+    if (quarter_turn && (N & 1) == 0) {
+        if (N >= 1024) return 11;
+        if (N >= 384) return 12;
+    }
+    if (N >= 1024) return 2;
+    if (N >= 192) return 4;
+    return 7;
 }
 
-// Shape of stacks: many slices fill the GPU, so the largest tiles with the stack
-// kernel (fewest staged bins per pixel) win.
 int default_stack_config(int N) { return N >= 256 ? 2 : 5; }
 
 std::string tune_cache_path() {
@@ -368,7 +376,7 @@ int get_plan(const fbp_geom* g, Plan** out) {
     }
     p->Dh = (p->D + 1) / 2;
     p->Dhp = (int)round_up((size_t)p->Dh, 64);
-    int one = default_config(p->N), stack = default_stack_config(p->N);
+    int one = default_config(p->N, quarter_turn_symmetric(p->angles)), stack = default_stack_config(p->N);
     auto t = R.tuned.find(key);
     if (t != R.tuned.end()) std::tie(one, stack) = t->second;
     const int forced = env_forced_config();
