@@ -7,6 +7,7 @@ against the FP64 oracle, a roofline entry for the dominant kernel
 (backprojection) and the oracle's own throughput on the host cores.
 
 python bench.py [--gpus 1] [--steps 200] [--warmup 20] [--precision fp32] [--no-cpu-baseline]
+               [--no-autotune] [--copy-mb MiB]
 """
 from __future__ import annotations
 
@@ -38,6 +39,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip tile autotuning (default shapes, or FBP_FORCE_CONFIG): for profiler runs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed region, one device copy of this many MiB (counter calibration)")
@@ -131,7 +134,7 @@ def main():
     sl = configs.c2_slice()
     geom = fbp.Geometry(sl.K, sl.D, sl.N, sl.dt, sl.angles)
     stream = torch.cuda.current_stream()
-    tuned = fbp.fbp_autotune(geom)
+    tuned = None if args.no_autotune else fbp.fbp_autotune(geom)
     cfg = fbp.fbp_plan_config(geom)
     sino = torch.tensor(sl.sino[None].astype(np.float32), device="cuda")
     img = torch.empty((1, sl.N, sl.N), dtype=torch.float32, device="cuda")

@@ -19,7 +19,8 @@
 // owns rows 16 (w/2) .. +16 and the output bins of parity w%2 (kGemmBN/32 16x16
 // MFMA blocks).
 // A ring of register buffers keeps several chunks of sinogram rows in flight
-// while the current one is multiplied.
+// while the current one is multiplied; the LDS panel they are staged into is
+// double-buffered, so each chunk needs one barrier.
 //   FP32:       v_mfma_f32_16x16x4_f32, 32 inputs per parity per chunk.
 //   BF16/FP16:  v_mfma_f32_16x16x32_{bf16,f16}, 64 per parity per chunk; the rows
 //               are rounded to 16 bits (RNE) as they are staged, and the tap slice
@@ -97,10 +98,11 @@ __device__ __forceinline__ void store_block(const v4f& acc, const GemmJob& job, 
 constexpr int kK32 = 32;                  // inputs per parity per chunk
 constexpr int kPD = 4;                    // chunks in flight (register ring)
 constexpr int kAS32 = kK32 + 1;           // LDS row stride (floats)
+constexpr int kABuf32 = 2 * kTM * kAS32;  // floats per panel buffer
 
 __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt, char* smem) {
-    float* As = reinterpret_cast<float*>(smem);          // [2 parity][32 rows][kAS32]
-    float* Bt = As + 2 * kTM * kAS32;                    // odd taps j = jlo + x
+    float* As = reinterpret_cast<float*>(smem);          // [2 buffers][2 parity][32 rows][kAS32]
+    float* Bt = As + 2 * kABuf32;                        // odd taps j = jlo + x
     const int t = threadIdx.x;
     const int w = t >> 6, l = t & 63;
     const int wm = w >> 1, sg = w & 1;                   // row half, output parity
@@ -126,18 +128,18 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
             r[i] = load_elem(prow, e >> 6, c0 + (e & 63), D);
         }
     };
-    auto store = [&](const float (&r)[8]) {
+    auto store = [&](const float (&r)[8], float* Ab) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int e = t + i * kBpThreads;
             const int row = e >> 6, col = e & 63;
-            As[((col & 1) * kTM + row) * kAS32 + (col >> 1)] = r[i];
+            Ab[((col & 1) * kTM + row) * kAS32 + (col >> 1)] = r[i];
         }
     };
 
-    v4f acc[kNB];
+    v4f acc[2][kNB];
 #pragma unroll
-    for (int j = 0; j < kNB; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < kNB; ++j) acc[0][j] = acc[1][j] = v4f{0.f, 0.f, 0.f, 0.f};
     const float* __restrict__ Arow = As + ((1 - sg) * kTM + wm * 16 + (l & 15)) * kAS32 + (l >> 4);
     const int bbase = (l & 15) - (l >> 4) + sg - jlo + nh0;   // + 16 ntile - m'
     const int nch = (D + 2 * kK32 - 1) / (2 * kK32);
@@ -150,24 +152,36 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
         for (int u = 0; u < kPD; ++u) {
             const int c = cb + u;
             load(pf[(u + kPD - 1) % kPD], (c + kPD - 1) * 2 * kK32);
-            __syncthreads();
-            store(pf[u]);
+            // double-buffered panel: every wave finished chunk c - 2 (same buffer)
+            // before it passed the barrier of chunk c - 1, so one barrier suffices
+            const int ab = (c & 1) * kABuf32;
+            store(pf[u], As + ab);
             __syncthreads();
             if (c < nch) {
                 const int mh0 = c * kK32;
+                // every fragment of the chunk is read before the first MFMA, so the
+                // LDS latency is paid once per chunk rather than once per k-step
+                constexpr int KS = kK32 / 4;
+                float a[KS], b[KS][kNB];
 #pragma unroll
-                for (int kk = 0; kk < kK32; kk += 4) {
-                    const float a = Arow[kk];
+                for (int k = 0; k < KS; ++k) {
+                    a[k] = Arow[ab + 4 * k];
+#pragma unroll
+                    for (int j = 0; j < kNB; ++j) b[k][j] = Bt[bbase + 16 * j - (mh0 + 4 * k)];
+                }
+                __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the MFMAs
+                // k-steps alternate between two accumulator sets: 2 kNB independent
+                // MFMA chains per wave
+#pragma unroll
+                for (int k = 0; k < KS; ++k)
 #pragma unroll
                     for (int j = 0; j < kNB; ++j)
-                        acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, Bt[bbase + 16 * j - (mh0 + kk)], acc[j],
-                                                                      0, 0, 0);
-                }
+                        acc[k & 1][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], b[k][j], acc[k & 1][j], 0, 0, 0);
             }
         }
     }
 #pragma unroll
-    for (int j = 0; j < kNB; ++j) store_block<kFP32>(acc[j], job, m0 + wm * 16, nh0 + 16 * j, sg);
+    for (int j = 0; j < kNB; ++j) store_block<kFP32>(acc[0][j] + acc[1][j], job, m0 + wm * 16, nh0 + 16 * j, sg);
 }
 
 // ---------------------------------------------------------------- 16-bit operands
@@ -175,13 +189,14 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
 constexpr int kK16 = 64;                  // inputs per parity per chunk
 constexpr int kPD16 = 3;                  // chunks in flight (register ring)
 constexpr int kAS16 = kK16 + 8;           // LDS row stride (16-bit), 16-byte aligned rows
+constexpr int kABuf16 = 2 * kTM * kAS16;  // 16-bit elements per panel buffer
 
 __device__ __forceinline__ int copy_stride16(int mpad) { return (mpad + kHalfN + 8 + 7 + 7) & ~7; }
 
 template <int PREC>
 __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt, char* smem) {
-    unsigned short* As = reinterpret_cast<unsigned short*>(smem);   // [2][32][kAS16]
-    unsigned short* Tc = As + 2 * kTM * kAS16;                      // 8 shifted tap copies
+    unsigned short* As = reinterpret_cast<unsigned short*>(smem);   // [2 buffers][2][32][kAS16]
+    unsigned short* Tc = As + 2 * kABuf16;                          // 8 shifted tap copies
     const int t = threadIdx.x;
     const int w = t >> 6, l = t & 63;
     const int wm = w >> 1, sg = w & 1;
@@ -212,19 +227,19 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
             r[i] = load_elem(prow, e >> 7, c0 + (e & 127), D);
         }
     };
-    auto store = [&](const float (&r)[16]) {
+    auto store = [&](const float (&r)[16], unsigned short* Ab) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int e = t + i * kBpThreads;
             const int row = e >> 7, col = e & 127;
-            As[((col & 1) * kTM + row) * kAS16 + (col >> 1)] =
+            Ab[((col & 1) * kTM + row) * kAS16 + (col >> 1)] =
                 (PREC == kBF16) ? to_bf16_rne(r[i]) : to_f16_rne(r[i]);
         }
     };
 
-    v4f acc[kNB];
+    v4f acc[2][kNB];
 #pragma unroll
-    for (int j = 0; j < kNB; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < kNB; ++j) acc[0][j] = acc[1][j] = v4f{0.f, 0.f, 0.f, 0.f};
     const unsigned short* Arow = As + ((1 - sg) * kTM + wm * 16 + (l & 15)) * kAS16 + 8 * (l >> 4);
     const int kq = 8 * (l >> 4);
     const int nch = (D + 2 * kK16 - 1) / (2 * kK16);
@@ -235,35 +250,44 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
         for (int u = 0; u < kPD16; ++u) {
             const int c = cb + u;
             load(pf[(u + kPD16 - 1) % kPD16], (c + kPD16 - 1) * 2 * kK16);
-            __syncthreads();
-            store(pf[u]);
+            const int ab = (c & 1) * kABuf16;   // double-buffered panel, one barrier
+            store(pf[u], As + ab);
             __syncthreads();
             if (c < nch) {
                 const int mh0 = c * kK16;
+                // all fragments of the chunk first, then the MFMAs (two accumulator sets)
+                constexpr int KS = kK16 / 32;
+                v8u16 av[KS], bv[KS][kNB];
 #pragma unroll
-                for (int ks = 0; ks < kK16; ks += 32) {
-                    const v8u16 av = *reinterpret_cast<const v8u16*>(Arow + ks);
-                    const int ya = (mh0 + ks + kq) - (nh0 + (l & 15)) - sg - ylo;
+                for (int k = 0; k < KS; ++k) {
+                    av[k] = *reinterpret_cast<const v8u16*>(Arow + ab + 32 * k);
+                    const int ya = (mh0 + 32 * k + kq) - (nh0 + (l & 15)) - sg - ylo;
 #pragma unroll
                     for (int j = 0; j < kNB; ++j) {
                         const int y = ya - 16 * j;
                         const int cy = y & 7;
-                        const v8u16 bv = *reinterpret_cast<const v8u16*>(Tc + cy * cstride + (y - cy));
-                        if constexpr (PREC == kBF16)
-                            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av),
-                                                                             __builtin_bit_cast(v8bf, bv), acc[j],
-                                                                             0, 0, 0);
-                        else
-                            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, av),
-                                                                            __builtin_bit_cast(v8h, bv), acc[j],
-                                                                            0, 0, 0);
+                        bv[k][j] = *reinterpret_cast<const v8u16*>(Tc + cy * cstride + (y - cy));
                     }
                 }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int k = 0; k < KS; ++k)
+#pragma unroll
+                    for (int j = 0; j < kNB; ++j) {
+                        if constexpr (PREC == kBF16)
+                            acc[k & 1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(v8bf, av[k]), __builtin_bit_cast(v8bf, bv[k][j]), acc[k & 1][j], 0,
+                                0, 0);
+                        else
+                            acc[k & 1][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                __builtin_bit_cast(v8h, av[k]), __builtin_bit_cast(v8h, bv[k][j]), acc[k & 1][j], 0,
+                                0, 0);
+                    }
             }
         }
     }
 #pragma unroll
-    for (int j = 0; j < kNB; ++j) store_block<PREC>(acc[j], job, m0 + wm * 16, nh0 + 16 * j, sg);
+    for (int j = 0; j < kNB; ++j) store_block<PREC>(acc[0][j] + acc[1][j], job, m0 + wm * 16, nh0 + 16 * j, sg);
 }
 
 template <int PREC>
@@ -320,10 +344,10 @@ int occ(int lds) {
 int gemm_lds_bytes(int prec, int Dh) {
     if (prec == kFP32) {
         const int mpad = (Dh + kK32 - 1) / kK32 * kK32;
-        return (2 * kTM * kAS32 + mpad + kHalfN) * 4;
+        return (2 * kABuf32 + mpad + kHalfN) * 4;
     }
     const int mpad = (Dh + kK16 - 1) / kK16 * kK16;
-    return (2 * kTM * kAS16 + 8 * ((mpad + kHalfN + 8 + 7 + 7) & ~7)) * 2;
+    return (2 * kABuf16 + 8 * ((mpad + kHalfN + 8 + 7 + 7) & ~7)) * 2;
 }
 
 hipError_t launch_gemm_grid(int prec, const GemmJob& job, hipStream_t stream) {
