@@ -35,7 +35,7 @@ BP_SOURCE = os.path.join(ROOT, "paper_2109_02174_amd", "csrc", "bp_kernels.hip")
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -91,9 +91,17 @@ def time_launches(fn, stream, n: int) -> float:
 
 
 def cpu_baseline(sl, seconds: float):
-    """The FP64 oracle timed on the host cores over repeated whole reconstructions."""
+    """The FP64 oracle timed on the host cores over repeated whole reconstructions,
+    with all threads (the reported value) and with one thread (3 runs)."""
     import oracle
     threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    one = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.fbp(sl.sino, sl.N, sl.dt, sl.angles)
+        one.append(time.perf_counter() - t0)
+    oracle.set_num_threads(threads)
     times = []
     out = None
     t_end = time.perf_counter() + seconds
@@ -112,6 +120,7 @@ def cpu_baseline(sl, seconds: float):
                    f"512x512/720-angle/725-bin slice, median {med * 1e3:.1f} ms each, "
                    f"{threads} OpenMP threads"),
         "slices_per_s": 1.0 / med,
+        "value_1_thread": sl.N * sl.N * sl.K / sorted(one)[1],
     }, out
 
 

@@ -48,8 +48,13 @@ def load_library(path: str):
                                        ctypes.c_int32, ctypes.c_double, dp, dp]
     lib.oracle_fbp.argtypes = lib.oracle_backproject.argtypes
     lib.oracle_forward_splat.argtypes = lib.oracle_backproject.argtypes
+    lib.oracle_filter_kind.argtypes = [dp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, dp]
+    lib.oracle_angle_weights.argtypes = [dp, ctypes.c_int32, dp]
+    lib.oracle_backproject_weighted.argtypes = [dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.c_int32, ctypes.c_double, dp, dp, dp]
     for fn in (lib.oracle_filter, lib.oracle_backproject, lib.oracle_fbp,
-               lib.oracle_forward_splat):
+               lib.oracle_forward_splat, lib.oracle_filter_kind, lib.oracle_angle_weights,
+               lib.oracle_backproject_weighted):
         fn.restype = ctypes.c_int
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
@@ -95,14 +100,40 @@ def ramlak_filter(P, dt: float) -> np.ndarray:
     return Q
 
 
+FILTERS = {"ramlak": 0, "shepp-logan": 1, "hann": 2}
+
+
+def filter_rows(P, dt: float, kind: str = "ramlak") -> np.ndarray:
+    """Rows filtered with the Ram-Lak, Shepp-Logan or Hann kernel (last axis = bins)."""
+    P = _f64(P)
+    D = P.shape[-1]
+    rows = int(np.prod(P.shape[:-1])) if P.ndim > 1 else 1
+    Q = np.empty_like(P)
+    rc = _load().oracle_filter_kind(_ptr(P), rows, D, float(dt), FILTERS[kind], _ptr(Q))
+    if rc != 0:
+        raise ValueError("oracle_filter_kind rejected its arguments")
+    return Q
+
+
+def angle_weights(angles) -> np.ndarray:
+    """Quadrature weight of every angle (half the gaps to its neighbours on the half-turn)."""
+    ang = _f64(angles).reshape(-1)
+    w = np.empty_like(ang)
+    rc = _load().oracle_angle_weights(_ptr(ang), ang.shape[0], _ptr(w))
+    if rc != 0:
+        raise ValueError("oracle_angle_weights rejected its arguments")
+    return w
+
+
 def _geom(arr: np.ndarray, angles):
     ang = _f64(angles).reshape(-1)
     K = ang.shape[0]
     return ang, K
 
 
-def backproject(Q, N: int, dt: float, angles) -> np.ndarray:
-    """Backprojection of filtered rows Q[B][K][D] (or [K][D]) onto N x N images."""
+def backproject(Q, N: int, dt: float, angles, weights=None) -> np.ndarray:
+    """Backprojection of filtered rows Q[B][K][D] (or [K][D]) onto N x N images, with
+    weight pi/K per angle, or the given per-angle weights."""
     Q = _f64(Q)
     squeeze = Q.ndim == 2
     if squeeze:
@@ -112,7 +143,14 @@ def backproject(Q, N: int, dt: float, angles) -> np.ndarray:
     if Ka != K:
         raise ValueError("angle count does not match the sinogram")
     img = np.empty((B, N, N), dtype=np.float64)
-    rc = _load().oracle_backproject(_ptr(Q), B, K, D, int(N), float(dt), _ptr(ang), _ptr(img))
+    if weights is not None:
+        w = _f64(weights).reshape(-1)
+        if w.shape[0] != K:
+            raise ValueError("weight count does not match the angles")
+        rc = _load().oracle_backproject_weighted(_ptr(Q), B, K, D, int(N), float(dt), _ptr(ang), _ptr(w),
+                                                 _ptr(img))
+    else:
+        rc = _load().oracle_backproject(_ptr(Q), B, K, D, int(N), float(dt), _ptr(ang), _ptr(img))
     if rc != 0:
         raise ValueError("oracle_backproject rejected its arguments")
     return img[0] if squeeze else img
@@ -133,6 +171,12 @@ def fbp(P, N: int, dt: float, angles) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle_fbp rejected its arguments")
     return img[0] if squeeze else img
+
+
+def fbp_variant(P, N: int, dt: float, angles, kind: str = "ramlak", weighted: bool = False) -> np.ndarray:
+    """Filter with the given kernel, then backproject with pi/K or the angle weights."""
+    Q = filter_rows(P, dt, kind)
+    return backproject(Q, N, dt, angles, angle_weights(angles) if weighted else None)
 
 
 def forward_splat(img, K: int, D: int, dt: float, angles) -> np.ndarray:

@@ -52,6 +52,24 @@ static double ramlak(int64_t d, double dt) {
     return -1.0 / (kPi * kPi * dd * dd * dt * dt);
 }
 
+/*
+ * Apodised kernels (the filter variants of the same convolution):
+ *   kind 0  Ram-Lak (above);
+ *   kind 1  Shepp-Logan, h(d) = -2 / (pi^2 dt^2 (4 d^2 - 1))  (Kak & Slaney, ch. 3),
+ *           whose response is the ramp times |sin(w/2)| / (w/2);
+ *   kind 2  Hann, the Ram-Lak kernel smoothed by the taps (1/4, 1/2, 1/4):
+ *           h(d) = h_RL(d)/2 + (h_RL(d-1) + h_RL(d+1))/4, whose response is the
+ *           ramp times cos^2(w/2) (a raised-cosine window falling to 0 at Nyquist).
+ */
+static double filter_tap(int kind, int64_t d, double dt) {
+    if (kind == 1) {
+        const double dd = (double)d;
+        return -2.0 / (kPi * kPi * dt * dt * (4.0 * dd * dd - 1.0));
+    }
+    if (kind == 2) return 0.5 * ramlak(d, dt) + 0.25 * (ramlak(d - 1, dt) + ramlak(d + 1, dt));
+    return ramlak(d, dt);
+}
+
 int oracle_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();
@@ -87,6 +105,67 @@ int oracle_filter(const double* P, int64_t n_rows, int32_t D, double dt, double*
             q[n] = dt * acc;
         }
     }
+    return 0;
+}
+
+/* oracle_filter with the kernel of the given kind (0 Ram-Lak, 1 Shepp-Logan, 2 Hann). */
+int oracle_filter_kind(const double* P, int64_t n_rows, int32_t D, double dt, int32_t kind, double* Q) {
+    if (!P || !Q || n_rows < 0 || D < 1 || !(dt > 0.0) || !isfinite(dt) || kind < 0 || kind > 2) return -1;
+    int64_t row;
+#pragma omp parallel for schedule(static)
+    for (row = 0; row < n_rows; ++row) {
+        const double* p = P + row * (int64_t)D;
+        double* q = Q + row * (int64_t)D;
+        for (int32_t n = 0; n < D; ++n) {
+            double acc = 0.0;
+            for (int32_t m = 0; m < D; ++m) acc += filter_tap(kind, (int64_t)n - m, dt) * p[m];
+            q[n] = dt * acc;
+        }
+    }
+    return 0;
+}
+
+/*
+ * Angular quadrature weights for an arbitrary angle list (the weight of each
+ * term of Eq. 2 when the angles are not evenly spaced).  Parallel rays at
+ * theta and theta + pi are the same lines, so every angle is reduced to
+ * [0, pi); in that sorted order each angle gets half of the gap to its
+ * predecessor plus half of the gap to its successor, the gaps wrapping around
+ * the half-turn.  Evenly spaced angles get pi/K each; the weights always sum
+ * to pi.  Angles equal modulo pi share their gaps.
+ */
+int oracle_angle_weights(const double* angles, int32_t K, double* w) {
+    if (!angles || !w || K < 1) return -1;
+    double* a = (double*)malloc(sizeof(double) * (size_t)K);
+    int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)K);
+    if (!a || !order) {
+        free(a);
+        free(order);
+        return -1;
+    }
+    for (int32_t k = 0; k < K; ++k) {
+        double t = fmod(angles[k], kPi);
+        if (t < 0.0) t += kPi;
+        a[k] = t;
+        order[k] = k;
+    }
+    /* insertion sort by reduced angle, ties by index (plain and obviously correct) */
+    for (int32_t i = 1; i < K; ++i) {
+        const int32_t cur = order[i];
+        int32_t j = i - 1;
+        while (j >= 0 && (a[order[j]] > a[cur] || (a[order[j]] == a[cur] && order[j] > cur))) {
+            order[j + 1] = order[j];
+            --j;
+        }
+        order[j + 1] = cur;
+    }
+    for (int32_t i = 0; i < K; ++i) {
+        const double prev = (i == 0) ? a[order[K - 1]] - kPi : a[order[i - 1]];
+        const double next = (i == K - 1) ? a[order[0]] + kPi : a[order[i + 1]];
+        w[order[i]] = 0.5 * (next - prev);
+    }
+    free(a);
+    free(order);
     return 0;
 }
 
@@ -140,6 +219,43 @@ int oracle_backproject(const double* Q, int32_t n_slices, int32_t K, int32_t D, 
         }
     }
     free(cs);
+    return 0;
+}
+
+/*
+ * oracle_backproject with a weight per angle in place of pi/K:
+ *     img[r][c] = sum_k weights[k] * [ (1-alpha) Q~[k][i] + alpha Q~[k][i+1] ].
+ */
+int oracle_backproject_weighted(const double* Q, int32_t n_slices, int32_t K, int32_t D, int32_t N,
+                                double dt, const double* angles, const double* weights, double* img) {
+    if (!Q || !img || !angles || !weights || n_slices < 0 || K < 1 || D < 1 || N < 1 || !(dt > 0.0) ||
+        !isfinite(dt))
+        return -1;
+    const double centre_det = 0.5 * (double)(D - 1);
+    const double centre_pix = 0.5 * (double)(N - 1);
+    int64_t sr;
+    const int64_t n_rows = (int64_t)n_slices * N;
+#pragma omp parallel for schedule(static)
+    for (sr = 0; sr < n_rows; ++sr) {
+        const int64_t s = sr / N;
+        const int32_t r = (int32_t)(sr % N);
+        const double y = (double)r - centre_pix;
+        const double* qs = Q + s * (int64_t)K * D;
+        double* out = img + s * (int64_t)N * N + (int64_t)r * N;
+        for (int32_t c = 0; c < N; ++c) {
+            const double x = (double)c - centre_pix;
+            double acc = 0.0;
+            for (int32_t k = 0; k < K; ++k) {
+                const double u = (x * cos(angles[k]) + y * sin(angles[k])) / dt + centre_det;
+                const double fi = floor(u);
+                const double alpha = u - fi;
+                const int64_t i = (int64_t)fi;
+                const double* q = qs + (int64_t)k * D;
+                acc += weights[k] * ((1.0 - alpha) * qtilde(q, D, i) + alpha * qtilde(q, D, i + 1));
+            }
+            out[c] = acc;
+        }
+    }
     return 0;
 }
 

@@ -45,6 +45,14 @@ MUTANTS = [
     ("nearest neighbour", "const double alpha = u - fi;", "const double alpha = (u - fi) < 0.5 ? 0.0 : 1.0;"),
     ("last angle dropped", "for (int32_t k = 0; k < K; ++k) {\n                const double u",
      "for (int32_t k = 0; k < K - 1; ++k) {\n                const double u"),
+    ("Shepp-Logan 4d^2+1", "(4.0 * dd * dd - 1.0)", "(4.0 * dd * dd + 1.0)"),
+    ("Shepp-Logan sign", "return -2.0 / (kPi * kPi", "return 2.0 / (kPi * kPi"),
+    ("Hann centre weight", "0.5 * ramlak(d, dt) + 0.25", "0.25 * ramlak(d, dt) + 0.25"),
+    ("Hann one-sided", "(ramlak(d - 1, dt) + ramlak(d + 1, dt))", "(ramlak(d - 1, dt) + ramlak(d - 1, dt))"),
+    ("weights without the half", "w[order[i]] = 0.5 * (next - prev);", "w[order[i]] = (next - prev);"),
+    ("weights without wrap-around", "a[order[K - 1]] - kPi", "a[order[0]]"),
+    ("weights not reduced to the half-turn", "double t = fmod(angles[k], kPi);", "double t = angles[k];"),
+    ("weighted backprojection ignores weights", "acc += weights[k] * (", "acc += (kPi / (double)K) * ("),
 ]
 
 

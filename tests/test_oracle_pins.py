@@ -313,3 +313,106 @@ def test_psnr_worked_values():
     assert abs(metrics.psnr(a, b, 255.0) - 20 * math.log10(255.0)) < 1e-12
     assert abs(metrics.psnr(a, b, 255.0) - 48.13080360867910) < 1e-9
     assert metrics.ssim(np.ones((16, 16)), np.ones((16, 16)), 1.0) == pytest.approx(1.0)
+
+
+# ---------------------------------------------------------------- filter variants and angle weights
+
+def _variant_response(kind, D, dt):
+    P = np.zeros(D)
+    P[D // 2] = 1.0
+    return oracle.filter_rows(P, dt, kind)
+
+
+@pytest.mark.parametrize("dt", [1.0, 0.6])
+def test_shepp_logan_response_is_ramp_times_sinc(dt):
+    """Shepp-Logan: the DTFT of dt h(d) is |sin(w/2)| / (pi dt), the ramp |w|/(2 pi dt)
+    times sin(w/2)/(w/2) (Kak & Slaney, ch. 3).  The series tail beyond |d| <= M is
+    (4/(pi^2 dt)) sum_{d>M} 1/(4d^2-1) = 2/(pi^2 dt (2M+1)) (telescoping)."""
+    D = 2001
+    M = D // 2
+    q = _variant_response("shepp-logan", D, dt)
+    d = np.arange(D) - M
+    bound = 2.0 / (math.pi ** 2 * dt * (2 * M + 1))
+    w = np.linspace(-math.pi, math.pi, 129)
+    H = (q[None, :] * np.cos(w[:, None] * d[None, :])).sum(axis=1)
+    assert np.max(np.abs(H - np.abs(np.sin(w / 2)) / (math.pi * dt))) <= bound * (1 + 1e-9) + 1e-13
+    assert abs(q.sum()) <= bound * (1 + 1e-9)                      # no DC gain
+
+
+@pytest.mark.parametrize("dt", [1.0, 2.0])
+def test_hann_response_is_ramp_times_cos_squared(dt):
+    """Hann: the ramp times cos^2(w/2), zero at DC and at Nyquist; tail bounded by the
+    Ram-Lak tail from |d| > M - 1."""
+    D = 2001
+    M = D // 2
+    q = _variant_response("hann", D, dt)
+    d = np.arange(D) - M
+    bound = 2.0 * 2.0 / (math.pi ** 2 * dt) * polygamma(1, (M - 1) / 2 + 0.5) / 4.0
+    w = np.linspace(-math.pi, math.pi, 129)
+    H = (q[None, :] * np.cos(w[:, None] * d[None, :])).sum(axis=1)
+    assert np.max(np.abs(H - np.abs(w) / (2 * math.pi * dt) * np.cos(w / 2) ** 2)) <= bound + 1e-13
+    assert abs(H[0]) <= bound and abs(H[-1]) <= bound
+
+
+def test_hann_is_ramlak_of_the_smoothed_row():
+    """Hann filtering equals Ram-Lak filtering of the row smoothed by (1/4, 1/2, 1/4),
+    the smoothing reaching one bin past each detector end (zeros beyond)."""
+    rng = ph.rng_for(910, 0)
+    P = rng.normal(size=(3, 57))
+    S = np.zeros((3, 59))
+    S[:, 1:-1] += 0.5 * P
+    S[:, :-2] += 0.25 * P
+    S[:, 2:] += 0.25 * P
+    ref = oracle.ramlak_filter(S, 0.8)[:, 1:-1]
+    assert np.max(np.abs(oracle.filter_rows(P, 0.8, "hann") - ref)) < 1e-13
+
+
+def test_angle_weights_worked_examples():
+    """Half the gap to each neighbour on the half-turn, gaps wrapping around."""
+    K = 12
+    w = oracle.angle_weights(np.arange(K) * math.pi / K)
+    assert np.max(np.abs(w - math.pi / K)) < 1e-15
+    # 0, pi/4, pi/2: neighbours of 0 are pi/2 - pi and pi/4
+    w3 = oracle.angle_weights([math.pi / 2, 0.0, math.pi / 4])
+    assert np.allclose(w3, [3 * math.pi / 8, 3 * math.pi / 8, math.pi / 4], rtol=0, atol=1e-15)
+    # a full turn of 2K angles covers each line twice: pi/(2K) each
+    w2 = oracle.angle_weights(np.arange(2 * K) * math.pi / K)
+    assert np.max(np.abs(w2 - math.pi / (2 * K))) < 1e-14
+    # any list: the weights are positive where the angles differ and sum to pi
+    a = ph.rng_for(911, 0).uniform(-4.0, 9.0, 37)
+    wa = oracle.angle_weights(a)
+    assert abs(wa.sum() - math.pi) < 1e-12 and np.all(wa > 0)
+
+
+def test_weighted_backprojection_is_linear_in_the_weights():
+    """Uniform weights pi/K give the plain backprojection; a single nonzero weight gives
+    that angle's linear interpolation alone; the map is linear in the weights."""
+    rng = ph.rng_for(912, 0)
+    K, D, N, dt = 9, 31, 17, 1.1
+    ang = np.sort(rng.uniform(0.0, math.pi, K))
+    Q = rng.normal(size=(K, D))
+    plain = oracle.backproject(Q, N, dt, ang)
+    assert np.max(np.abs(oracle.backproject(Q, N, dt, ang, np.full(K, math.pi / K)) - plain)) < 1e-13
+    e = np.zeros(K)
+    e[4] = 2.5
+    one = oracle.backproject(Q, N, dt, ang, e)
+    assert np.max(np.abs(one - 2.5 / math.pi * oracle.backproject(Q[4:5], N, dt, ang[4:5]))) < 1e-12
+    w1, w2 = rng.uniform(0, 1, K), rng.uniform(0, 1, K)
+    lhs = oracle.backproject(Q, N, dt, ang, w1 + w2)
+    rhs = oracle.backproject(Q, N, dt, ang, w1) + oracle.backproject(Q, N, dt, ang, w2)
+    assert np.max(np.abs(lhs - rhs)) < 1e-12
+
+
+def test_angle_weights_fix_a_clustered_acquisition():
+    """An elongated ellipse seen from clustered angles (40 in [0, 0.5), 20 in [0.5, pi)):
+    the angle-weighted reconstruction keeps the centre at the density, the
+    unweighted sum over-counts the cluster.  (A disk would not tell them apart:
+    all its projections are equal.)"""
+    N, D, rho = 81, 121, 1.5
+    ang = np.concatenate([np.linspace(0.0, 0.5, 40, endpoint=False), np.linspace(0.5, math.pi, 20, endpoint=False)])
+    sino = ph.ellipse_sinogram([ph.Ellipse(0.0, 0.0, 0.7, 0.2, 0.25, rho)], N, D, 1.0, ang)
+    c = (N - 1) // 2
+    weighted = oracle.fbp_variant(sino, N, 1.0, ang, "ramlak", weighted=True)
+    plain = oracle.fbp_variant(sino, N, 1.0, ang, "ramlak", weighted=False)
+    assert abs(weighted[c, c] / rho - 1.0) < 0.02
+    assert abs(plain[c, c] / rho - 1.0) > 0.2
