@@ -66,13 +66,30 @@ typedef enum {
     FBP_PREC_FP16 = 2       /* rounded to binary16 (RNE); taps pre-scaled by 2^s to stay normal */
 } fbp_precision;
 
-/* One parallel-beam geometry. */
+/* Filter kernel of the convolution Q = P * H (all with full support |d| <= D-1). */
+typedef enum {
+    FBP_FILTER_RAMLAK = 0,       /* h(0) = 1/(4 dt^2), h(even) = 0, h(odd d) = -1/(pi^2 d^2 dt^2) */
+    FBP_FILTER_SHEPP_LOGAN = 1,  /* h(d) = -2/(pi^2 dt^2 (4 d^2 - 1)): ramp x sin(w/2)/(w/2) */
+    FBP_FILTER_HANN = 2          /* Ram-Lak smoothed by (1/4, 1/2, 1/4): ramp x cos^2(w/2) */
+} fbp_filter_kind;
+
+/* Weight of each angle's term in Eq. 2. */
+typedef enum {
+    FBP_WEIGHT_UNIFORM = 0,      /* pi/K for every angle (angles evenly spread over a half-turn) */
+    FBP_WEIGHT_ANGLE_GAPS = 1    /* each angle, reduced to [0, pi), gets half the gaps to its two
+                                    neighbours (wrapping around); sums to pi; = pi/K when even */
+} fbp_weighting;
+
+/* One parallel-beam geometry (with the filter kernel and angular weights it is
+ * reconstructed with; zero-initialised fields give Ram-Lak and pi/K). */
 typedef struct {
     int32_t n_angles;        /* K >= 1 */
     int32_t n_det;           /* D >= 1 */
     int32_t image_size;      /* N >= 1: the image is N x N */
     double det_spacing;      /* dt > 0 and finite, in pixel units */
     const double* angles;    /* host array of K finite radians; copied into the plan, never kept */
+    int32_t filter;          /* fbp_filter_kind */
+    int32_t weighting;       /* fbp_weighting */
 } fbp_geom;
 
 /* One slice of a mixed batch. */
@@ -84,9 +101,12 @@ typedef struct {
 
 /*
  * Ramp filter (the convolution Q = P * H, section "Computed tomography"):
- *   d_filtered[b][k][n] = dt * sum_{m<D} h(n - m) * d_sino[b][k][m].
+ *   d_filtered[b][k][n] = dt * sum_{m<D} h(n - m) * d_sino[b][k][m],
+ * h the kernel geom->filter selects.
  * Runs as a GEMM on the matrix cores: rows of the sinogram times the Toeplitz
- * matrix of the kernel, operands in `precision`, FP32 accumulation.
+ * matrix of the kernel, operands in `precision`, FP32 accumulation.  The
+ * Ram-Lak kernel vanishes at even offsets, so it takes half the MACs of the
+ * others.
  * d_sino and d_filtered are [n_slices][K][D] and must not overlap.
  * n_slices == 0 is a valid no-op.
  */
@@ -94,8 +114,9 @@ int fbp_filter(const fbp_geom* geom, int32_t n_slices, const float* d_sino, floa
                int32_t precision, void* hip_stream);
 
 /*
- * Backprojection (Eq. 2 with weight pi/K and linear interpolation):
- *   d_image[b][r][c] = (pi/K) * sum_k Q~_k(u_k(x_c, y_r)),
+ * Backprojection (Eq. 2 with weight pi/K, or the angle-gap weights w_k of
+ * geom->weighting, and linear interpolation):
+ *   d_image[b][r][c] = sum_k w_k Q~_k(u_k(x_c, y_r)),
  *   u_k(x, y) = (x cos(theta_k) + y sin(theta_k)) / dt + (D-1)/2.
  * d_filtered is [n_slices][K][D], d_image is [n_slices][N][N]; no overlap.
  * Every image pixel is written.  With d_filtered = the raw sinogram this is

@@ -25,6 +25,8 @@ FBP_EUNSUPPORTED = -4
 FBP_EWORKSPACE = -5
 
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
+FILTERS = {"ramlak": 0, "shepp-logan": 1, "hann": 2}
+WEIGHTINGS = {"uniform": 0, "angle-gaps": 1}
 
 
 class FbpError(RuntimeError):
@@ -41,7 +43,8 @@ class FbpError(RuntimeError):
 class c_geom(ctypes.Structure):
     _fields_ = [("n_angles", ctypes.c_int32), ("n_det", ctypes.c_int32),
                 ("image_size", ctypes.c_int32), ("det_spacing", ctypes.c_double),
-                ("angles", ctypes.POINTER(ctypes.c_double))]
+                ("angles", ctypes.POINTER(ctypes.c_double)),
+                ("filter", ctypes.c_int32), ("weighting", ctypes.c_int32)]
 
 
 class c_job(ctypes.Structure):
@@ -89,12 +92,16 @@ def load():
 
 @dataclass
 class Geometry:
-    """Parallel-beam geometry: K angles (radians), D bins of width dt, N x N image."""
+    """Parallel-beam geometry: K angles (radians), D bins of width dt, N x N image, the
+    filter kernel ("ramlak", "shepp-logan", "hann") and the angular weights
+    ("uniform" pi/K, or "angle-gaps" for uneven angle lists)."""
     n_angles: int
     n_det: int
     image_size: int
     det_spacing: float = 1.0
     angles: np.ndarray = field(default=None)
+    filter: str = "ramlak"
+    weighting: str = "uniform"
 
     def __post_init__(self):
         if self.angles is None:
@@ -104,12 +111,14 @@ class Geometry:
     def as_c(self) -> c_geom:
         """The C struct (cached; the angle array is kept alive with it)."""
         key = (int(self.n_angles), int(self.n_det), int(self.image_size), float(self.det_spacing),
-               self.angles.ctypes.data)
+               self.angles.ctypes.data, self.filter, self.weighting)
         cached = getattr(self, "_c_cache", None)
         if cached is not None and cached[0] == key:
             return cached[1]
         g = c_geom(key[0], key[1], key[2], key[3],
-                   self.angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                   self.angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                   FILTERS.get(self.filter, -1) if isinstance(self.filter, str) else int(self.filter),
+                   WEIGHTINGS.get(self.weighting, -1) if isinstance(self.weighting, str) else int(self.weighting))
         g._keep = self.angles
         self._c_cache = (key, g)
         return g

@@ -165,6 +165,8 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const SliceSet<M>& ss,
                                                 __int_as_float(i0));
         }
     };
+    // angle weights (non-uniform angle lists): staged values are scaled by w_k/(pi/K)
+    const float* __restrict__ wscale = job.wscale;
     float pf[E], pr[E];
     auto load = [&](int kb, int buf) {
         const int nslot = min(KB, K - kb) << (LM + seg_shift);
@@ -180,9 +182,9 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const SliceSet<M>& ss,
                 for (int mm = 1; mm < M; ++mm)
                     if (m == mm) qm = ss.q[mm];
                 const int nrec = (m < ss.n) ? D * 4 : 0;
+                const int k = part + (kb + a) * split;
                 const __amdgpu_buffer_rsrc_t row = __builtin_amdgcn_make_buffer_rsrc(
-                    const_cast<float*>(qm + (size_t)(part + (kb + a) * split) * (size_t)D), (short)0, nrec,
-                    kBufferWord3);
+                    const_cast<float*>(qm + (size_t)k * (size_t)D), (short)0, nrec, kBufferWord3);
                 const int g4 = (__float_as_int(prm[buf * kMaxKB + a].w) + 63 * seg + lane) * 4;
                 pf[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(row, g4, 0, 0));
                 pr[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(row, d4 - g4, 0, 0));
@@ -198,6 +200,11 @@ __device__ __forceinline__ void bp_tile(const BpJob& job, const SliceSet<M>& ss,
                 const int a = slot >> (LM + seg_shift);
                 const int m = (slot >> seg_shift) & (M - 1);
                 const int j = 63 * (slot & ((1 << seg_shift) - 1)) + lane;
+                if (wscale) {   // uniform: the factor is a scalar load
+                    const float c = wscale[part + (kb + a) * split];
+                    pf[e] *= c;
+                    pr[e] *= c;
+                }
                 const float f1 = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(nxt, __builtin_bit_cast(int, pf[e])));
                 const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(nxt, __builtin_bit_cast(int, pr[e])));
                 if (lane < 63 && j < WL) {
@@ -423,6 +430,7 @@ __device__ __forceinline__ void bp_tile_rot4(const BpJob& job, const float* __re
     };
     // staging slot = (pair a, window w in {U, V}, 63-bin segment): 4 single-dword
     // buffer loads per lane (forward and reversed row of both angles)
+    const float* __restrict__ wscale = job.wscale;   // angle weights / (pi/K), or null
     float pf[kStageE][4];
     auto load = [&](int kb, int buf) {
         const int nslot = min(KB, K2 - kb) << (seg_shift + 1);
@@ -456,6 +464,14 @@ __device__ __forceinline__ void bp_tile_rot4(const BpJob& job, const float* __re
                 const int a = slot >> (seg_shift + 1);
                 const int w = (slot >> seg_shift) & 1;
                 const int j = 63 * (slot & ((1 << seg_shift) - 1)) + lane;
+                if (wscale) {   // uniform: the factors are scalar loads
+                    const int k = part + (kb + a) * split;
+                    const float ca = wscale[k], cb = wscale[k + KH];
+                    pf[e][0] *= ca;
+                    pf[e][1] *= ca;
+                    pf[e][2] *= cb;
+                    pf[e][3] *= cb;
+                }
                 float nx[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c)

@@ -57,6 +57,7 @@ struct BpJob {
     int32_t tiles_x;      // tile columns of the half image
     float scale;          // pi/K
     float* part;          // angle-split partial sums [n][split][N][N] (split > 1 only)
+    const float* wscale;  // [K] angle weight / (pi/K), or null for pi/K throughout
     int32_t split;        // angle parts: workgroup part r takes the angles r, r + split, ...
     int32_t pad_;
 };
@@ -151,7 +152,9 @@ struct GemmJob {
     float diag;           // tap(0), rounded like the taps (and pre-scaled for FP16)
     float out_scale;      // undoes the FP16 tap pre-scale (1 otherwise)
     int32_t tiles_n;      // ceil(D / 64)
-    int32_t pad;
+    int32_t full;         // 1: the kernel has even taps too (te(j) = tap(2j) in taps_even,
+                          //    same indexing); diag is then 0 and the centre tap is te(0)
+    const void* taps_even;
 };
 static_assert(sizeof(GemmJob) % 8 == 0, "GemmJob layout");
 
@@ -166,9 +169,9 @@ struct GemmListArgs {
     const int32_t* counts;      // device: counts[0] = n_jobs
 };
 // `args` is a DEVICE pointer (the batch header in the workspace).
-hipError_t launch_gemm_list(int prec, const GemmListArgs* args, int grid, size_t lds_bytes,
+hipError_t launch_gemm_list(int prec, bool full, const GemmListArgs* args, int grid, size_t lds_bytes,
                             hipStream_t stream);
 int gemm_lds_bytes(int prec, int Dh);
-int gemm_occupancy(int prec, size_t lds_bytes);
+int gemm_occupancy(int prec, bool full, size_t lds_bytes);
 
 }  // namespace fbp

@@ -87,8 +87,9 @@ __device__ __forceinline__ void store_block(const v4f& acc, const GemmJob& job, 
     for (int i = 0; i < 4; ++i) {
         const int m = row0 + 4 * (l >> 4) + i;
         if (m < job.R) {
-            const float pc = round_operand<PREC>(job.p[(size_t)m * job.D + n]);
-            job.q[(size_t)m * job.D + n] = fmaf(job.diag, pc, acc[i]) * job.out_scale;
+            float v = acc[i];
+            if (!job.full) v = fmaf(job.diag, round_operand<PREC>(job.p[(size_t)m * job.D + n]), v);
+            job.q[(size_t)m * job.D + n] = v * job.out_scale;
         }
     }
 }
@@ -100,9 +101,13 @@ constexpr int kPD = 4;                    // chunks in flight (register ring)
 constexpr int kAS32 = kK32 + 1;           // LDS row stride (floats)
 constexpr int kABuf32 = 2 * kTM * kAS32;  // floats per panel buffer
 
+// FULL: the kernel also has even taps; even outputs then take even inputs through
+// te and odd outputs odd inputs (the same-parity half of the panel), doubling the
+// MFMAs of the parity-split product.
+template <bool FULL>
 __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt, char* smem) {
     float* As = reinterpret_cast<float*>(smem);          // [2 buffers][2 parity][32 rows][kAS32]
-    float* Bt = As + 2 * kABuf32;                        // odd taps j = jlo + x
+    float* Bt = As + 2 * kABuf32;                        // odd taps j = jlo + x, then even taps
     const int t = threadIdx.x;
     const int w = t >> 6, l = t & 63;
     const int wm = w >> 1, sg = w & 1;                   // row half, output parity
@@ -114,8 +119,14 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
     const int jlo = nh0 - mpad + 1;
     const int n_taps = mpad + kHalfN;                    // j in [jlo, nh0 + 32]
 
+    float* Be = Bt + n_taps;                             // te(jlo + x) (FULL)
+
     __syncthreads();   // LDS reuse across tiles of a persistent workgroup
     for (int x = t; x < n_taps; x += kBpThreads) Bt[x] = taps[jlo + x + Dhp];
+    if constexpr (FULL) {
+        const float* __restrict__ te = static_cast<const float*>(job.taps_even);
+        for (int x = t; x < n_taps; x += kBpThreads) Be[x] = te[jlo + x + Dhp];
+    }
 
     // ring of kPD chunks of 64 input columns in registers: chunk c + kPD - 1 is
     // loaded while chunk c is multiplied, hiding several chunks of load latency
@@ -141,6 +152,7 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
 #pragma unroll
     for (int j = 0; j < kNB; ++j) acc[0][j] = acc[1][j] = v4f{0.f, 0.f, 0.f, 0.f};
     const float* __restrict__ Arow = As + ((1 - sg) * kTM + wm * 16 + (l & 15)) * kAS32 + (l >> 4);
+    const float* __restrict__ ArowS = As + (sg * kTM + wm * 16 + (l & 15)) * kAS32 + (l >> 4);   // same parity
     const int bbase = (l & 15) - (l >> 4) + sg - jlo + nh0;   // + 16 ntile - m'
     const int nch = (D + 2 * kK32 - 1) / (2 * kK32);
     // every chunk load is issued unconditionally (chunks past the end read zeros),
@@ -177,6 +189,21 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
 #pragma unroll
                     for (int j = 0; j < kNB; ++j)
                         acc[k & 1][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], b[k][j], acc[k & 1][j], 0, 0, 0);
+                if constexpr (FULL) {
+#pragma unroll
+                    for (int k = 0; k < KS; ++k) {
+                        a[k] = ArowS[ab + 4 * k];
+#pragma unroll
+                        for (int j = 0; j < kNB; ++j) b[k][j] = Be[bbase - sg + 16 * j - (mh0 + 4 * k)];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int k = 0; k < KS; ++k)
+#pragma unroll
+                        for (int j = 0; j < kNB; ++j)
+                            acc[k & 1][j] =
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], b[k][j], acc[k & 1][j], 0, 0, 0);
+                }
             }
         }
     }
@@ -193,7 +220,7 @@ constexpr int kABuf16 = 2 * kTM * kAS16;  // 16-bit elements per panel buffer
 
 __device__ __forceinline__ int copy_stride16(int mpad) { return (mpad + kHalfN + 8 + 7 + 7) & ~7; }
 
-template <int PREC>
+template <int PREC, bool FULL>
 __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt, char* smem) {
     unsigned short* As = reinterpret_cast<unsigned short*>(smem);   // [2 buffers][2][32][kAS16]
     unsigned short* Tc = As + 2 * kABuf16;                          // 8 shifted tap copies
@@ -211,11 +238,18 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
     const int ylo = -(nh0 + kHalfN);
     const int cstride = copy_stride16(mpad);
 
+    unsigned short* Te = Tc + 8 * cstride;                          // the same for te (FULL)
+
     __syncthreads();
     for (int x = t; x < 8 * cstride; x += kBpThreads) {
         const int c = x / cstride, y = x - c * cstride;
         const int idx = -(ylo + y + c) + Dhp;             // table index of to(-(y'))
         Tc[x] = (idx >= 0 && idx <= 2 * Dhp) ? taps[idx] : (unsigned short)0;
+        if constexpr (FULL) {
+            // te(n' - m') is read at y + s: copy c element y holds te(-(ylo + y + c))
+            const unsigned short* __restrict__ te = static_cast<const unsigned short*>(job.taps_even);
+            Te[x] = (idx >= 0 && idx <= 2 * Dhp) ? te[idx] : (unsigned short)0;
+        }
     }
 
     float pf[kPD16][16];
@@ -241,6 +275,7 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
 #pragma unroll
     for (int j = 0; j < kNB; ++j) acc[0][j] = acc[1][j] = v4f{0.f, 0.f, 0.f, 0.f};
     const unsigned short* Arow = As + ((1 - sg) * kTM + wm * 16 + (l & 15)) * kAS16 + 8 * (l >> 4);
+    const unsigned short* ArowS = As + (sg * kTM + wm * 16 + (l & 15)) * kAS16 + 8 * (l >> 4);   // same parity
     const int kq = 8 * (l >> 4);
     const int nch = (D + 2 * kK16 - 1) / (2 * kK16);
 #pragma unroll
@@ -270,19 +305,36 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
                     }
                 }
                 __builtin_amdgcn_sched_barrier(0);
+                auto mfma = [&](const v8u16& x, const v8u16& y, v4f& c) {
+                    if constexpr (PREC == kBF16)
+                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, x),
+                                                                    __builtin_bit_cast(v8bf, y), c, 0, 0, 0);
+                    else
+                        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, x),
+                                                                   __builtin_bit_cast(v8h, y), c, 0, 0, 0);
+                };
 #pragma unroll
                 for (int k = 0; k < KS; ++k)
 #pragma unroll
-                    for (int j = 0; j < kNB; ++j) {
-                        if constexpr (PREC == kBF16)
-                            acc[k & 1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                __builtin_bit_cast(v8bf, av[k]), __builtin_bit_cast(v8bf, bv[k][j]), acc[k & 1][j], 0,
-                                0, 0);
-                        else
-                            acc[k & 1][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                                __builtin_bit_cast(v8h, av[k]), __builtin_bit_cast(v8h, bv[k][j]), acc[k & 1][j], 0,
-                                0, 0);
+                    for (int j = 0; j < kNB; ++j) mfma(av[k], bv[k][j], acc[k & 1][j]);
+                if constexpr (FULL) {
+#pragma unroll
+                    for (int k = 0; k < KS; ++k) {
+                        av[k] = *reinterpret_cast<const v8u16*>(ArowS + ab + 32 * k);
+                        const int ya = (mh0 + 32 * k + kq) - (nh0 + (l & 15)) - ylo;   // + s - s
+#pragma unroll
+                        for (int j = 0; j < kNB; ++j) {
+                            const int y = ya - 16 * j;
+                            const int cy = y & 7;
+                            bv[k][j] = *reinterpret_cast<const v8u16*>(Te + cy * cstride + (y - cy));
+                        }
                     }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int k = 0; k < KS; ++k)
+#pragma unroll
+                        for (int j = 0; j < kNB; ++j) mfma(av[k], bv[k][j], acc[k & 1][j]);
+                }
             }
         }
     }
@@ -290,25 +342,27 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
     for (int j = 0; j < kNB; ++j) store_block<PREC>(acc[0][j] + acc[1][j], job, m0 + wm * 16, nh0 + 16 * j, sg);
 }
 
-template <int PREC>
+// One instantiation per (operand precision, kernel with or without even taps), so
+// the Ram-Lak path keeps its register budget.
+template <int PREC, bool FULL>
 __device__ __forceinline__ void gemm_tile(const GemmJob& job, int mt, int nt, char* smem) {
     if constexpr (PREC == kFP32)
-        gemm_tile_f32(job, mt, nt, smem);
+        gemm_tile_f32<FULL>(job, mt, nt, smem);
     else
-        gemm_tile_16<PREC>(job, mt, nt, smem);
+        gemm_tile_16<PREC, FULL>(job, mt, nt, smem);
 }
 
-template <int PREC>
+template <int PREC, bool FULL>
 __global__ __launch_bounds__(kBpThreads) void gemm_grid_kernel(GemmJob job) {
     extern __shared__ float4 smem4[];
     const int tiles_m = (job.R + kTM - 1) / kTM;
     // blockIdx.x: output tile index, row tiles fastest so neighbours share tap slices
     const int b = blockIdx.x;
     const int nt = b / tiles_m, mt = b - nt * tiles_m;
-    gemm_tile<PREC>(job, mt, nt, reinterpret_cast<char*>(smem4));
+    gemm_tile<PREC, FULL>(job, mt, nt, reinterpret_cast<char*>(smem4));
 }
 
-template <int PREC>
+template <int PREC, bool FULL>
 __global__ __launch_bounds__(kBpThreads) void gemm_list_kernel(const GemmListArgs* __restrict__ args) {
     extern __shared__ float4 smem4[];
     const GemmListArgs a = load_const(args);
@@ -326,57 +380,70 @@ __global__ __launch_bounds__(kBpThreads) void gemm_list_kernel(const GemmListArg
         const int tt = it - prefix[lo];
         const int tiles_m = (job.R + kTM - 1) / kTM;
         const int nt = tt / tiles_m, mt = tt - nt * tiles_m;
-        gemm_tile<PREC>(job, mt, nt, reinterpret_cast<char*>(smem4));
+        gemm_tile<PREC, FULL>(job, mt, nt, reinterpret_cast<char*>(smem4));
     }
 }
 
-template <int PREC>
+template <int PREC, bool FULL>
 int occ(int lds) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_list_kernel<PREC>, kBpThreads, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_list_kernel<PREC, FULL>, kBpThreads, lds) !=
         hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
+
+// Every compiled filter kernel: (precision, kernel with even taps).
+#define FBP_FOR_EACH_GEMM(X) \
+    X(kFP32, false)          \
+    X(kFP32, true)           \
+    X(kBF16, false)          \
+    X(kBF16, true)           \
+    X(kFP16, false)          \
+    X(kFP16, true)
+
+constexpr int gemm_key(int prec, bool full) { return prec * 2 + (full ? 1 : 0); }
 
 }  // namespace
 
 int gemm_lds_bytes(int prec, int Dh) {
     if (prec == kFP32) {
         const int mpad = (Dh + kK32 - 1) / kK32 * kK32;
-        return (2 * kABuf32 + mpad + kHalfN) * 4;
+        return (2 * kABuf32 + 2 * (mpad + kHalfN)) * 4;   // panel, odd and even taps
     }
     const int mpad = (Dh + kK16 - 1) / kK16 * kK16;
-    return (2 * kABuf16 + 8 * ((mpad + kHalfN + 8 + 7 + 7) & ~7)) * 2;
+    return (2 * kABuf16 + 2 * 8 * ((mpad + kHalfN + 8 + 7 + 7) & ~7)) * 2;
 }
 
 hipError_t launch_gemm_grid(int prec, const GemmJob& job, hipStream_t stream) {
     const int tiles_m = (job.R + kTM - 1) / kTM;
     const unsigned grid = (unsigned)(tiles_m * job.tiles_n);
     const size_t lds = (size_t)gemm_lds_bytes(prec, job.Dh);
-    switch (prec) {
-        case kFP32: return launch_kernel(gemm_grid_kernel<kFP32>, dim3(grid), dim3(kBpThreads), lds, stream, job);
-        case kBF16: return launch_kernel(gemm_grid_kernel<kBF16>, dim3(grid), dim3(kBpThreads), lds, stream, job);
-        case kFP16: return launch_kernel(gemm_grid_kernel<kFP16>, dim3(grid), dim3(kBpThreads), lds, stream, job);
+    switch (gemm_key(prec, job.full != 0)) {
+#define X(p, f) \
+        case gemm_key(p, f): return launch_kernel(gemm_grid_kernel<p, f>, dim3(grid), dim3(kBpThreads), lds, stream, job);
+        FBP_FOR_EACH_GEMM(X)
+#undef X
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_gemm_list(int prec, const GemmListArgs* a, int grid, size_t lds, hipStream_t stream) {
-    switch (prec) {
-        case kFP32: return launch_kernel(gemm_list_kernel<kFP32>, dim3(grid), dim3(kBpThreads), lds, stream, a);
-        case kBF16: return launch_kernel(gemm_list_kernel<kBF16>, dim3(grid), dim3(kBpThreads), lds, stream, a);
-        case kFP16: return launch_kernel(gemm_list_kernel<kFP16>, dim3(grid), dim3(kBpThreads), lds, stream, a);
+hipError_t launch_gemm_list(int prec, bool full, const GemmListArgs* a, int grid, size_t lds, hipStream_t stream) {
+    switch (gemm_key(prec, full)) {
+#define X(p, f) \
+        case gemm_key(p, f): return launch_kernel(gemm_list_kernel<p, f>, dim3(grid), dim3(kBpThreads), lds, stream, a);
+        FBP_FOR_EACH_GEMM(X)
+#undef X
         default: return hipErrorInvalidValue;
     }
 }
 
-int gemm_occupancy(int prec, size_t lds_bytes) {
+int gemm_occupancy(int prec, bool full, size_t lds_bytes) {
     const int lds = (int)lds_bytes;
-    switch (prec) {
-        case kFP32: return occ<kFP32>(lds);
-        case kBF16: return occ<kBF16>(lds);
-        case kFP16: return occ<kFP16>(lds);
+    switch (gemm_key(prec, full)) {
+#define X(p, f) case gemm_key(p, f): return occ<p, f>(lds);
+        FBP_FOR_EACH_GEMM(X)
+#undef X
         default: return 1;
     }
 }

@@ -44,6 +44,8 @@ int check_geom(const fbp_geom* g) {
     if (!g->angles) return FBP_EINVAL;
     for (int32_t k = 0; k < g->n_angles; ++k)
         if (!std::isfinite(g->angles[k])) return FBP_EINVAL;
+    if (g->filter < FBP_FILTER_RAMLAK || g->filter > FBP_FILTER_HANN) return FBP_EINVAL;
+    if (g->weighting < FBP_WEIGHT_UNIFORM || g->weighting > FBP_WEIGHT_ANGLE_GAPS) return FBP_EINVAL;
     if (g->n_det > kMaxDet || g->image_size > kMaxImage || g->n_angles > kMaxAngles)
         return FBP_EUNSUPPORTED;
     return FBP_OK;
@@ -72,9 +74,10 @@ struct GeomKey {
     int device, K, D, N;
     uint64_t dt_bits;
     uint64_t angle_hash;
+    int filter = 0, weighting = 0;
     bool operator<(const GeomKey& o) const {
-        return std::tie(device, K, D, N, dt_bits, angle_hash) <
-               std::tie(o.device, o.K, o.D, o.N, o.dt_bits, o.angle_hash);
+        return std::tie(device, K, D, N, dt_bits, angle_hash, filter, weighting) <
+               std::tie(o.device, o.K, o.D, o.N, o.dt_bits, o.angle_hash, o.filter, o.weighting);
     }
 };
 
@@ -99,6 +102,8 @@ GeomKey make_key(int device, const fbp_geom* g) {
     k.N = g->image_size;
     std::memcpy(&k.dt_bits, &g->det_spacing, 8);
     k.angle_hash = hash_angles(g->angles, g->n_angles);
+    k.filter = g->filter;
+    k.weighting = g->weighting;
     return k;
 }
 
@@ -134,6 +139,8 @@ struct Plan {
     void* d_taps[3] = {nullptr, nullptr, nullptr};
     float out_scale[3] = {1.0f, 1.0f, 1.0f};
     float diag[3] = {0.0f, 0.0f, 0.0f};
+    int filter = 0, weighting = 0;   // fbp_filter_kind, fbp_weighting
+    float* d_wscale = nullptr;       // [K] angle weights / (pi/K) (angle-gap weighting only)
     ShapeParams one;                 // single slices and short stacks
     ShapeParams stack;               // stacks of kStackMinSlices or more slices
     PartBuffer part;
@@ -159,7 +166,29 @@ Registry& registry() {
 bool angles_equal(const Plan& p, const fbp_geom* g) {
     return (int)p.angles.size() == g->n_angles &&
            std::memcmp(p.angles.data(), g->angles, sizeof(double) * (size_t)g->n_angles) == 0 &&
-           p.dt == g->det_spacing;
+           p.dt == g->det_spacing && p.filter == g->filter && p.weighting == g->weighting;
+}
+
+// Angular quadrature of Eq. 2 for an arbitrary angle list: the lines at theta and
+// theta + pi coincide, so each angle is taken modulo pi; in that order an angle's
+// weight is half the distance between its two neighbours (the first and last
+// wrap around the half-turn).  Returned as factors of pi/K (1 for even spacing).
+std::vector<double> angle_gap_factors(const std::vector<double>& angles) {
+    const size_t K = angles.size();
+    std::vector<std::pair<double, size_t>> a(K);
+    for (size_t k = 0; k < K; ++k) {
+        double t = std::fmod(angles[k], kPi);
+        if (t < 0.0) t += kPi;
+        a[k] = {t, k};
+    }
+    std::sort(a.begin(), a.end());
+    std::vector<double> f(K);
+    for (size_t i = 0; i < K; ++i) {
+        const double lo = (i == 0) ? a[K - 1].first - kPi : a[i - 1].first;
+        const double hi = (i + 1 == K) ? a[0].first + kPi : a[i + 1].first;
+        f[a[i].second] = 0.5 * (hi - lo) * (double)K / kPi;
+    }
+    return f;
 }
 
 double span_for(const TileShape& s, const std::vector<double>& cs) {
@@ -289,13 +318,13 @@ void load_tune_cache_locked(Registry& R, int device) {
     const std::string arch = arch_name(device);
     std::string line;
     while (std::getline(in, line)) {
-        // one entry per line: arch K D N dt_bits angle_hash single_tile stack_tile
+        // one entry per line: arch K D N dt_bits angle_hash single_tile stack_tile filter weighting
         std::istringstream ss(line);
         std::string a;
         GeomKey k;
         int one, stack;
         unsigned long long dtb, ah;
-        if (!(ss >> a >> k.K >> k.D >> k.N >> dtb >> ah >> one >> stack)) continue;
+        if (!(ss >> a >> k.K >> k.D >> k.N >> dtb >> ah >> one >> stack >> k.filter >> k.weighting)) continue;
         if (a != arch || one < 0 || one >= kNumTileConfigs || stack < 0 || stack >= kNumTileConfigs) continue;
         k.device = device;
         k.dt_bits = dtb;
@@ -368,6 +397,8 @@ int get_plan(const fbp_geom* g, Plan** out) {
     p->D = g->n_det;
     p->N = g->image_size;
     p->dt = g->det_spacing;
+    p->filter = g->filter;
+    p->weighting = g->weighting;
     p->angles.assign(g->angles, g->angles + g->n_angles);
     p->cs.resize(2 * (size_t)p->K);
     for (int k = 0; k < p->K; ++k) {
@@ -400,6 +431,19 @@ int get_plan(const fbp_geom* g, Plan** out) {
         (void)hipFree(p->d_cs);
         (void)hipFree(p->d_cs32);
         return hip_fail(e, "hipMemcpy (angle table)");
+    }
+    if (p->weighting == FBP_WEIGHT_ANGLE_GAPS) {
+        const std::vector<double> f = angle_gap_factors(p->angles);
+        std::vector<float> f32(f.begin(), f.end());
+        e = hipMalloc(&p->d_wscale, sizeof(float) * f32.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_wscale, f32.data(), sizeof(float) * f32.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(p->d_cs);
+            (void)hipFree(p->d_cs32);
+            if (p->d_wscale) (void)hipFree(p->d_wscale);
+            return hip_fail(e, "angle weights", FBP_ENOMEM);
+        }
     }
     // partial sums of angle-split single slices (any shape's split fits); none for
     // images over 2048^2, which then run unsplit
@@ -437,6 +481,8 @@ uint16_t f16_bits_rne(float x) {
 }
 
 // tap(d) = dt h(d): the Ram-Lak kernel times the bin width.
+// tap(d) = dt h(d) for the plan's kernel: Ram-Lak, Shepp-Logan (Kak & Slaney,
+// ch. 3) or Ram-Lak smoothed by (1/4, 1/2, 1/4) (Hann, response ramp x cos^2(w/2)).
 double ramlak_tap(int d, double dt) {
     if (d == 0) return 1.0 / (4.0 * dt);
     if (d % 2 == 0) return 0.0;
@@ -444,18 +490,34 @@ double ramlak_tap(int d, double dt) {
     return -1.0 / (kPi * kPi * dd * dd * dt);
 }
 
-// Odd-tap table to(j) = tap(2j - 1) for j in [-Dhp, Dhp] (zero where |2j - 1| > D - 1),
-// stored at index j + Dhp in the operand precision, plus the centre tap.
+double filter_tap(int kind, int d, double dt) {
+    if (kind == FBP_FILTER_SHEPP_LOGAN) {
+        const double dd = (double)d;
+        return -2.0 / (kPi * kPi * dt * (4.0 * dd * dd - 1.0));
+    }
+    if (kind == FBP_FILTER_HANN)
+        return 0.5 * ramlak_tap(d, dt) + 0.25 * (ramlak_tap(d - 1, dt) + ramlak_tap(d + 1, dt));
+    return ramlak_tap(d, dt);
+}
+
+// Tap tables in the operand precision, each indexed j + Dhp for j in [-Dhp, Dhp]
+// (zero where the offset exceeds D - 1): the odd taps to(j) = tap(2j - 1) and, for
+// kernels that do not vanish at even offsets, the even taps te(j) = tap(2j) after
+// them.  Ram-Lak keeps only its centre tap, applied in FP32 in the GEMM epilogue.
 int ensure_taps(Plan* p, int prec) {
     std::lock_guard<std::mutex> lock(p->mu);
     if (p->d_taps[prec]) return FBP_OK;
     const int Dhp = p->Dhp, D = p->D;
-    std::vector<double> taps(2 * (size_t)Dhp + 1, 0.0);
+    const bool full = p->filter != FBP_FILTER_RAMLAK;
+    const size_t len = 2 * (size_t)Dhp + 1;
+    std::vector<double> taps(full ? 2 * len : len, 0.0);
     for (int j = -Dhp; j <= Dhp; ++j) {
         const int d = 2 * j - 1;
-        if (d >= -(D - 1) && d <= D - 1) taps[(size_t)(j + Dhp)] = ramlak_tap(d, p->dt);
+        if (d >= -(D - 1) && d <= D - 1) taps[(size_t)(j + Dhp)] = filter_tap(p->filter, d, p->dt);
+        if (full && 2 * j >= -(D - 1) && 2 * j <= D - 1)
+            taps[len + (size_t)(j + Dhp)] = filter_tap(p->filter, 2 * j, p->dt);
     }
-    const double centre = ramlak_tap(0, p->dt);
+    const double centre = full ? 0.0 : filter_tap(p->filter, 0, p->dt);
     void* dev = nullptr;
     size_t bytes = 0;
     std::vector<float> f32;
@@ -470,16 +532,19 @@ int ensure_taps(Plan* p, int prec) {
         if (prec == kFP16) {
             // Pre-scale by 2^s so the smallest nonzero tap is a normal binary16 number
             // (>= 2^-14) while the largest stays below 2^15.
-            double tmax = std::fabs(centre), tmin = std::fabs(centre);
+            double tmax = 0.0, tmin = 0.0;
+            if (centre != 0.0) tmax = tmin = std::fabs(centre);
             for (double v : taps)
                 if (v != 0.0) {
                     tmax = std::max(tmax, std::fabs(v));
-                    tmin = std::min(tmin, std::fabs(v));
+                    tmin = (tmin == 0.0) ? std::fabs(v) : std::min(tmin, std::fabs(v));
                 }
-            int s = (int)std::ceil(-14.0 - std::log2(tmin));
-            s = std::min(s, (int)std::floor(15.0 - std::log2(tmax)));
-            scale = std::ldexp(1.0, s);
-            out_scale = (float)std::ldexp(1.0, -s);
+            if (tmax > 0.0) {
+                int s = (int)std::ceil(-14.0 - std::log2(tmin));
+                s = std::min(s, (int)std::floor(15.0 - std::log2(tmax)));
+                scale = std::ldexp(1.0, s);
+                out_scale = (float)std::ldexp(1.0, -s);
+            }
         }
         h16.resize(taps.size());
         for (size_t i = 0; i < taps.size(); ++i) {
@@ -522,6 +587,10 @@ GemmJob gemm_job(const Plan& p, int prec, const float* sino, float* filt, int ro
     j.Dhp = p.Dhp;
     j.diag = p.diag[prec];
     j.out_scale = p.out_scale[prec];
+    j.full = (p.filter != FBP_FILTER_RAMLAK) ? 1 : 0;
+    j.taps_even = j.full ? static_cast<const char*>(p.d_taps[prec]) +
+                               (2 * (size_t)p.Dhp + 1) * (prec == kFP32 ? 4 : 2)
+                         : nullptr;
     j.tiles_n = (p.D + kGemmBN - 1) / kGemmBN;
     return j;
 }
@@ -545,6 +614,7 @@ BpJob bp_job(const Plan& p, const ShapeParams& sh, const float* filt, float* img
     j.scale = (float)(kPi / (double)p.K);
     j.part = nullptr;
     j.split = 1;
+    j.wscale = p.d_wscale;
     return j;
 }
 
@@ -616,13 +686,14 @@ int run_backproject(Plan& p, const ShapeParams& one, const ShapeParams& stack, i
 
 // Header at the start of a batch workspace.  The list kernels read their
 // arguments from here, so one captured graph per workspace serves every batch.
+// gemm[0] lists the Ram-Lak jobs, gemm[1] the jobs whose kernel has even taps;
 // bp[c] lists single slices of tile shape c, bpm[c] groups of slices that share
 // a geometry (stack kernel of shape c).
 struct BatchHeader {
-    GemmListArgs gemm;
+    GemmListArgs gemm[2];
     BpListArgs bp[kNumTileConfigs];
     BpListArgs bpm[kNumTileConfigs];
-    int32_t counts[1 + 2 * kNumTileConfigs];
+    int32_t counts[2 + 2 * kNumTileConfigs];
 };
 
 struct BatchLayout {
@@ -639,7 +710,7 @@ BatchLayout batch_layout(const fbp_job* jobs, int32_t n) {
     L.gemm_jobs = o;
     o = round_up(o + sizeof(GemmJob) * (size_t)n, 256);
     L.gemm_prefix = o;
-    o = round_up(o + sizeof(int32_t) * (size_t)(n + 1), 256);
+    o = round_up(o + sizeof(int32_t) * (size_t)(n + 2), 256);
     L.bp_jobs = o;
     o = round_up(o + sizeof(BpJob) * (size_t)n, 256);
     L.bp_index = o;
@@ -689,12 +760,14 @@ struct GraphKey {
     uintptr_t ws;
     uint32_t cfg_mask;     // tile shapes with single-slice entries
     uint32_t multi_mask;   // tile shapes with slice groups
+    int gemm_kinds;        // bit 0: Ram-Lak filter jobs, bit 1: jobs with even taps
     int gemm_lds;
     int bp_lds;
     int bpm_lds;
     bool operator<(const GraphKey& o) const {
-        return std::tie(device, prec, ws, cfg_mask, multi_mask, gemm_lds, bp_lds, bpm_lds) <
-               std::tie(o.device, o.prec, o.ws, o.cfg_mask, o.multi_mask, o.gemm_lds, o.bp_lds, o.bpm_lds);
+        return std::tie(device, prec, ws, cfg_mask, multi_mask, gemm_kinds, gemm_lds, bp_lds, bpm_lds) <
+               std::tie(o.device, o.prec, o.ws, o.cfg_mask, o.multi_mask, o.gemm_kinds, o.gemm_lds, o.bp_lds,
+                        o.bpm_lds);
     }
 };
 
@@ -748,9 +821,13 @@ void release_staging(Staging* st, bool recorded) {
 // reading the header at ws.
 hipError_t enqueue_batch_kernels(const GraphKey& key, int cus, hipStream_t s) {
     const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(key.ws);
-    const int g_occ = gemm_occupancy(key.prec, (size_t)key.gemm_lds);
-    hipError_t e = launch_gemm_list(key.prec, &hdr->gemm, cus * g_occ, (size_t)key.gemm_lds, s);
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    for (int kind = 0; kind < 2; ++kind) {
+        if (!(key.gemm_kinds & (1 << kind))) continue;
+        const int g_occ = gemm_occupancy(key.prec, kind == 1, (size_t)key.gemm_lds);
+        e = launch_gemm_list(key.prec, kind == 1, &hdr->gemm[kind], cus * g_occ, (size_t)key.gemm_lds, s);
+        if (e != hipSuccess) return e;
+    }
     for (int c = 0; c < kNumTileConfigs; ++c) {
         if (key.multi_mask & (1u << c)) {
             const int m = tile_shape(c).multi;
@@ -846,18 +923,37 @@ int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes,
 
     int max_dh = 0, max_bp_lds = 0, max_bpm_lds = 0;
     uint32_t mask = 0, mmask = 0;
-    int64_t gemm_tiles = 0;
-    gp[0] = 0;
     std::vector<float*> qptr((size_t)n);
     for (int32_t i = 0; i < n; ++i) {
-        const Plan& p = *plans[(size_t)i];
-        float* q = reinterpret_cast<float*>(wsc + L.q_off[(size_t)i]);
-        qptr[(size_t)i] = q;
-        gj[i] = gemm_job(p, prec, jobs[i].sino, q, p.K);
-        gemm_tiles += (int64_t)((p.K + kGemmBM - 1) / kGemmBM) * gj[i].tiles_n;
-        if (gemm_tiles > INT32_MAX) return FBP_EUNSUPPORTED;
-        gp[i + 1] = (int32_t)gemm_tiles;
-        max_dh = std::max(max_dh, p.Dh);
+        qptr[(size_t)i] = reinterpret_cast<float*>(wsc + L.q_off[(size_t)i]);
+        max_dh = std::max(max_dh, plans[(size_t)i]->Dh);
+    }
+    // filter jobs: the Ram-Lak ones first, then those with even taps, each list with
+    // its own tile prefix
+    int gemm_kinds = 0;
+    int32_t n_gemm[2] = {0, 0};
+    {
+        int pos_g = 0, pre_g = 0;
+        for (int kind = 0; kind < 2; ++kind) {
+            int64_t tiles = 0;
+            gp[pre_g] = 0;
+            for (int32_t i = 0; i < n; ++i) {
+                const Plan& p = *plans[(size_t)i];
+                if ((p.filter != FBP_FILTER_RAMLAK) != (kind == 1)) continue;
+                gj[pos_g] = gemm_job(p, prec, jobs[i].sino, qptr[(size_t)i], p.K);
+                tiles += (int64_t)((p.K + kGemmBM - 1) / kGemmBM) * gj[pos_g].tiles_n;
+                if (tiles > INT32_MAX) return FBP_EUNSUPPORTED;
+                ++pos_g;
+                gp[pre_g + ++n_gemm[kind]] = (int32_t)tiles;
+            }
+            GemmListArgs& a = hdr->gemm[kind];
+            a.jobs = reinterpret_cast<const GemmJob*>(wsc + L.gemm_jobs) + (pos_g - n_gemm[kind]);
+            a.tile_prefix = reinterpret_cast<const int32_t*>(wsc + L.gemm_prefix) + pre_g;
+            a.counts = reinterpret_cast<const int32_t*>(wsc + offsetof(BatchHeader, counts)) + kind;
+            hdr->counts[kind] = n_gemm[kind];
+            if (n_gemm[kind] > 0) gemm_kinds |= 1 << kind;
+            pre_g += n_gemm[kind] + 1;
+        }
     }
     // Jobs of a plan with kStackMinSlices or more jobs in the batch take its stack
     // shape: groups of sh.multi slices (consecutive in the job table) and the rest
@@ -868,7 +964,7 @@ int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes,
         std::vector<int32_t> jobs;
         const ShapeParams* sh;
     };
-    int pos = 0, idx_off = 0, pre_off = 0, cnt_off = 1;
+    int pos = 0, idx_off = 0, pre_off = 0, cnt_off = 2;
     auto add_list = [&](BpListArgs& a, const std::vector<Item>& items, bool multi) -> int {
         int64_t tiles = 0;
         bpre[pre_off] = 0;
@@ -934,10 +1030,6 @@ int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes,
         if (rc == FBP_OK) rc = add_list(hdr->bp[c], singles[(size_t)c], false);
         if (rc != FBP_OK) return rc;
     }
-    hdr->gemm.jobs = reinterpret_cast<const GemmJob*>(wsc + L.gemm_jobs);
-    hdr->gemm.tile_prefix = reinterpret_cast<const int32_t*>(wsc + L.gemm_prefix);
-    hdr->gemm.counts = reinterpret_cast<const int32_t*>(wsc + offsetof(BatchHeader, counts));
-    hdr->counts[0] = n;
 
     Staging* st = acquire_staging(L.desc_end);
     if (!st) return FBP_ENOMEM;
@@ -955,6 +1047,7 @@ int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes,
     key.ws = reinterpret_cast<uintptr_t>(ws);
     key.cfg_mask = mask;
     key.multi_mask = mmask;
+    key.gemm_kinds = gemm_kinds;
     key.gemm_lds = (int)round_up((size_t)gemm_lds_bytes(prec, max_dh), 8192);
     key.bp_lds = (int)round_up((size_t)max_bp_lds, 4096);
     key.bpm_lds = (int)round_up((size_t)max_bpm_lds, 4096);
@@ -1087,7 +1180,7 @@ int autotune(const fbp_geom* g, hipStream_t s, int32_t* out_cfg) {
             if (out)
                 out << arch_name(device) << ' ' << key.K << ' ' << key.D << ' ' << key.N << ' '
                     << (unsigned long long)key.dt_bits << ' ' << (unsigned long long)key.angle_hash << ' '
-                    << one << ' ' << stack << '\n';
+                    << one << ' ' << stack << ' ' << key.filter << ' ' << key.weighting << '\n';
         }
     }
     if (out_cfg) *out_cfg = one;

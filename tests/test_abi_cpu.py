@@ -75,6 +75,21 @@ def test_invalid_geometry_rejected(lib, K, D, N, dt):
     assert lib.fbp_workspace_bytes(ctypes.byref(g), 1, 0) == 0
 
 
+@pytest.mark.parametrize("filt,weighting", [(-1, 0), (3, 0), (0, -1), (0, 2)])
+def test_unknown_filter_or_weighting_rejected(lib, filt, weighting):
+    ang = (ctypes.c_double * 4)(0.0, 0.5, 1.0, 1.5)
+    g = B.c_geom(4, 7, 5, 1.0, ang, filt, weighting)
+    assert lib.fbp_filter(ctypes.byref(g), 1, FAKE, FAKE2, 0, None) == B.FBP_EINVAL
+    assert lib.fbp_backproject(ctypes.byref(g), 1, FAKE, FAKE2, None) == B.FBP_EINVAL
+    assert lib.fbp_workspace_bytes(ctypes.byref(g), 1, 0) == 0
+
+
+def test_geometry_struct_matches_the_header():
+    # the binding's structs follow include/fbp.h field for field
+    assert ctypes.sizeof(B.c_geom) == 40 and B.c_geom.filter.offset == 32 and B.c_geom.weighting.offset == 36
+    assert ctypes.sizeof(B.c_job) == 56
+
+
 def test_null_and_nonfinite_angles_rejected(lib):
     g = B.c_geom(4, 7, 5, 1.0, None)
     assert lib.fbp_backproject(ctypes.byref(g), 1, FAKE, FAKE2, None) == B.FBP_EINVAL

@@ -31,7 +31,7 @@ def test_autotune_picks_a_valid_shape_and_new_plans_use_it():
 
 
 def test_tune_cache_round_trip(tmp_path, monkeypatch):
-    # tuning appends "arch K D N dt_bits angle_hash single_tile stack_tile" to the cache file
+    # tuning appends "arch K D N dt_bits angle_hash single_tile stack_tile filter weighting"
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("FBP_TUNE_CACHE", str(cache))
     g = fbp.Geometry(61, 87, 57, 1.0)           # no plan of it exists yet
@@ -39,13 +39,14 @@ def test_tune_cache_round_trip(tmp_path, monkeypatch):
     lines = cache.read_text().strip().splitlines()
     assert len(lines) == 1
     fields = lines[0].split()
-    assert fields[0].startswith("gfx") and fields[1:4] == ["61", "87", "57"] and int(fields[-2]) == best
+    assert fields[0].startswith("gfx") and fields[1:4] == ["61", "87", "57"] and int(fields[6]) == best
+    assert fields[8:] == ["0", "0"]
     # a cache file with other entries for the geometry is read when its plan is created
     plain = [c for c in range(fbp.fbp_num_tile_configs()) if "rotations" not in fbp.fbp_tile_config_name(c)]
     one = next(c for c in plain if c != best)
-    stack = next(c for c in plain if c != int(fields[-1]))
+    stack = next(c for c in plain if c != int(fields[7]))
     cache2 = tmp_path / "tune2.txt"
-    cache2.write_text(" ".join(fields[:-2] + [str(one), str(stack)]) + "\n")
+    cache2.write_text(" ".join(fields[:6] + [str(one), str(stack)] + fields[8:]) + "\n")
     monkeypatch.setenv("FBP_TUNE_CACHE", str(cache2))
     assert fbp.fbp_plan_config(g) == one
     assert fbp.fbp_plan_stack_config(g) == stack
