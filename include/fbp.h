@@ -142,6 +142,18 @@ int fbp_reconstruct(const fbp_geom* geom, int32_t n_slices, const float* d_sino,
                     void* d_workspace, size_t workspace_bytes, int32_t precision,
                     void* hip_stream);
 
+/*
+ * Forward projector, the exact adjoint of fbp_backproject (for iterative methods
+ * and adjoint checks):
+ *   d_sino[b][k][j] = w_k * sum_{r,c} d_image[b][r][c] * max(0, 1 - |u_k(x_c, y_r) - j|),
+ * u_k as in fbp_backproject, w_k = pi/K or the angle-gap weights of
+ * geom->weighting.  d_image is [n_slices][N][N], d_sino [n_slices][K][D]; no
+ * overlap.  Gather-only (one lane per detector bin), no atomics, deterministic;
+ * <fbp_project(x), y> = <x, fbp_backproject(y)> up to FP32 rounding.
+ */
+int fbp_project(const fbp_geom* geom, int32_t n_slices, const float* d_image, float* d_sino,
+                void* hip_stream);
+
 /* Workspace bytes fbp_reconstruct needs (0 on invalid arguments). */
 size_t fbp_workspace_bytes(const fbp_geom* geom, int32_t n_slices, int32_t precision);
 

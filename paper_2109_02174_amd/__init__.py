@@ -8,7 +8,7 @@ continuous-batching serving loop.
 from ._binding import (FBP_EHIP, FBP_EINVAL, FBP_ENOMEM, FBP_EUNSUPPORTED, FBP_EWORKSPACE, FBP_OK,
                        FbpError, Geometry, alloc_workspace, fbp_autotune, fbp_backproject,
                        fbp_backproject_with_config, fbp_batch_workspace_bytes, fbp_filter,
-                       fbp_num_tile_configs, fbp_plan_config, fbp_plan_stack_config, fbp_reconstruct,
+                       fbp_num_tile_configs, fbp_plan_config, fbp_plan_stack_config, fbp_project, fbp_reconstruct,
                        fbp_reconstruct_batch, fbp_status_string, fbp_tile_config_name, fbp_version, fbp_last_error,
                        fbp_workspace_bytes, load)
 
@@ -16,6 +16,6 @@ __all__ = [
     "FBP_OK", "FBP_EINVAL", "FBP_ENOMEM", "FBP_EHIP", "FBP_EUNSUPPORTED", "FBP_EWORKSPACE",
     "FbpError", "Geometry", "alloc_workspace", "fbp_autotune", "fbp_backproject",
     "fbp_backproject_with_config", "fbp_batch_workspace_bytes", "fbp_filter",
-    "fbp_num_tile_configs", "fbp_plan_config", "fbp_plan_stack_config", "fbp_reconstruct", "fbp_reconstruct_batch",
+    "fbp_num_tile_configs", "fbp_plan_config", "fbp_plan_stack_config", "fbp_project", "fbp_reconstruct", "fbp_reconstruct_batch",
     "fbp_status_string", "fbp_tile_config_name", "fbp_version", "fbp_last_error", "fbp_workspace_bytes", "load",
 ]

@@ -68,6 +68,7 @@ def load():
     sig = {
         "fbp_filter": (ctypes.c_int, [G, i32, vp, vp, i32, vp]),
         "fbp_backproject": (ctypes.c_int, [G, i32, vp, vp, vp]),
+        "fbp_project": (ctypes.c_int, [G, i32, vp, vp, vp]),
         "fbp_reconstruct": (ctypes.c_int, [G, i32, vp, vp, vp, sz, i32, vp]),
         "fbp_workspace_bytes": (sz, [G, i32, i32]),
         "fbp_reconstruct_batch": (ctypes.c_int, [ctypes.POINTER(c_job), i32, vp, sz, i32, vp]),
@@ -208,6 +209,21 @@ def fbp_backproject(geom: Geometry, filtered, out=None, stream=None):
     rc = load().fbp_backproject(ctypes.byref(g), n, filtered.data_ptr(), out.data_ptr(),
                                 _stream_ptr(stream))
     _raise(rc, "fbp_backproject")
+    return out
+
+
+def fbp_project(geom: Geometry, image, out=None, stream=None):
+    """Forward projection (adjoint of fbp_backproject): image [B][N][N] -> rows [B][K][D]."""
+    import torch
+    n = image.shape[0]
+    sshape, ishape = _shapes(geom, n)
+    _check_tensor(image, ishape, "image")
+    if out is None:
+        out = torch.empty(sshape, dtype=torch.float32, device=image.device)
+    _check_tensor(out, sshape, "out")
+    g = geom.as_c()
+    rc = load().fbp_project(ctypes.byref(g), n, image.data_ptr(), out.data_ptr(), _stream_ptr(stream))
+    _raise(rc, "fbp_project")
     return out
 
 

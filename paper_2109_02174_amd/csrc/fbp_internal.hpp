@@ -135,6 +135,21 @@ hipError_t launch_bp_list(int cfg, int m, const BpListArgs* args, int grid, size
                           hipStream_t stream);
 int bp_occupancy(int cfg, int m, size_t lds_bytes);   // resident workgroups per CU
 
+// ------------------------------------------------------------------ forward projector
+
+// Everything the projector (adjoint of the backprojector) needs for one geometry.
+struct ProjJob {
+    const float* img;     // [n][N][N]
+    float* sino;          // [n][K][D]
+    const double* cs;     // [K][2]: cos/dt, sin/dt (FP64)
+    const float* wscale;  // [K] angle weight / (pi/K), or null
+    double half_pix;      // (N-1)/2
+    double centre_det;    // (D-1)/2
+    int32_t N, K, D;
+    float scale;          // pi/K
+};
+hipError_t launch_project(const ProjJob& job, int n_slices, hipStream_t stream);
+
 // ------------------------------------------------------------------ ramp filter GEMM
 
 enum Prec : int32_t { kFP32 = 0, kBF16 = 1, kFP16 = 2 };

@@ -1290,6 +1290,32 @@ int fbp_reconstruct(const fbp_geom* geom, int32_t n_slices, const float* d_sino,
     return rc;
 }
 
+int fbp_project(const fbp_geom* geom, int32_t n_slices, const float* d_image, float* d_sino, void* hip_stream) {
+    int rc = check_geom(geom);
+    if (rc == FBP_OK) rc = check_slices(geom, n_slices);
+    if (rc != FBP_OK) return rc;
+    if (n_slices == 0) return FBP_OK;
+    if (!d_image || !d_sino || !aligned4(d_image) || !aligned4(d_sino)) return FBP_EINVAL;
+    if (overlaps(d_image, image_bytes(geom, n_slices), d_sino, sino_bytes(geom, n_slices))) return FBP_EINVAL;
+    Plan* p = nullptr;
+    rc = get_plan(geom, &p);
+    if (rc != FBP_OK) return rc;
+    ProjJob j{};
+    j.img = d_image;
+    j.sino = d_sino;
+    j.cs = p->d_cs;
+    j.wscale = p->d_wscale;
+    j.half_pix = 0.5 * (double)(p->N - 1);
+    j.centre_det = 0.5 * (double)(p->D - 1);
+    j.N = p->N;
+    j.K = p->K;
+    j.D = p->D;
+    j.scale = (float)(kPi / (double)p->K);
+    const hipError_t e = launch_project(j, n_slices, (hipStream_t)hip_stream);
+    if (e == hipErrorInvalidValue) return FBP_EUNSUPPORTED;
+    return hip_status(e, "projector kernel launch");
+}
+
 int fbp_reconstruct_batch(const fbp_job* jobs, int32_t n_jobs, void* d_workspace,
                           size_t workspace_bytes, int32_t precision, void* hip_stream) {
     return reconstruct_batch(jobs, n_jobs, d_workspace, workspace_bytes, precision,

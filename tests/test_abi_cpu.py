@@ -71,6 +71,7 @@ def test_invalid_geometry_rejected(lib, K, D, N, dt):
     g = B.c_geom(K, D, N, dt, (ctypes.c_double * max(K, 1))())
     assert lib.fbp_filter(ctypes.byref(g), 1, FAKE, FAKE2, 0, None) == B.FBP_EINVAL
     assert lib.fbp_backproject(ctypes.byref(g), 1, FAKE, FAKE2, None) == B.FBP_EINVAL
+    assert lib.fbp_project(ctypes.byref(g), 1, FAKE, FAKE2, None) == B.FBP_EINVAL
     assert lib.fbp_reconstruct(ctypes.byref(g), 1, FAKE, FAKE2, FAKE3, 1 << 20, 0, None) == B.FBP_EINVAL
     assert lib.fbp_workspace_bytes(ctypes.byref(g), 1, 0) == 0
 
@@ -102,6 +103,7 @@ def test_null_and_nonfinite_angles_rejected(lib):
 def test_oversized_geometry_is_unsupported(lib):
     _, g = _geom(D=100000)
     assert lib.fbp_backproject(ctypes.byref(g), 1, FAKE, FAKE2, None) == B.FBP_EUNSUPPORTED
+    assert lib.fbp_project(ctypes.byref(g), 1, FAKE, FAKE2, None) == B.FBP_EUNSUPPORTED
 
 
 def test_pointer_checks(lib):
@@ -115,9 +117,14 @@ def test_pointer_checks(lib):
     assert lib.fbp_filter(gp, -1, FAKE, FAKE2, 0, None) == B.FBP_EINVAL
     assert lib.fbp_backproject(gp, 1, FAKE, FAKE + 4, None) == B.FBP_EINVAL      # overlap
     assert lib.fbp_backproject(gp, 1, FAKE, FAKE2 + 1, None) == B.FBP_EINVAL
+    assert lib.fbp_project(gp, 1, FAKE, FAKE + 4, None) == B.FBP_EINVAL          # overlap
+    assert lib.fbp_project(gp, 1, FAKE + 1, FAKE2, None) == B.FBP_EINVAL          # misaligned
+    assert lib.fbp_project(gp, 1, None, FAKE2, None) == B.FBP_EINVAL
+    assert lib.fbp_project(gp, -1, FAKE, FAKE2, None) == B.FBP_EINVAL
     # empty calls are valid no-ops that touch nothing
     assert lib.fbp_filter(gp, 0, None, None, 0, None) == B.FBP_OK
     assert lib.fbp_backproject(gp, 0, None, None, None) == B.FBP_OK
+    assert lib.fbp_project(gp, 0, None, None, None) == B.FBP_OK
     assert lib.fbp_reconstruct(gp, 0, None, None, None, 0, 0, None) == B.FBP_OK
 
 

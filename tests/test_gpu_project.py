@@ -1,0 +1,135 @@
+"""GPU: the forward projector (adjoint of the backprojector).
+
+fbp_project maps an image to projection rows with the hat-function weights of
+the backprojector's linear interpolation (Eq. 2 with linear interpolation, read
+as a linear map), so it is checked against the FP64 oracle's own adjoint
+(oracle.forward_splat, pinned there by brute force against oracle.backproject)
+element by element, and against the GPU backprojector through the identity
+<P x, y> = <x, P^T y>.
+
+Tolerance: each term w * x carries a hat weight rounded a few times in FP32
+(|error| <= 4 * 2^-24), and each lane adds at most N * (2 sqrt(2) dt + 1) terms
+in a fixed order; the bound below allows 16 FP32 ulps of max|x| per term.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2109_02174_amd as fbp
+from paper_2109_02174_amd import phantom as ph
+
+pytestmark = pytest.mark.gpu
+
+
+def _tol(x, N, dt, K):
+    terms = N * (2.0 * math.sqrt(2.0) * dt + 1.0)
+    return (math.pi / K) * terms * 16 * 2.0 ** -24 * float(np.max(np.abs(x))) + 1e-30
+
+
+def _angles(K, kind, seed):
+    if kind == "uniform":
+        return ph.uniform_angles(K)
+    # random angles over the whole turn: both walk directions, every sign of cos and sin
+    return ph.rng_for(1500, seed).uniform(0.0, 2.0 * math.pi, K)
+
+
+@pytest.mark.parametrize("K,D,N,dt,B,kind", [
+    (180, 183, 128, 1.0, 1, "uniform"),
+    (61, 95, 45, 1.0, 2, "random"),          # odd image side
+    (40, 230, 48, 0.35, 1, "random"),        # fine detector: several bins per pixel
+    (33, 40, 64, 1.7, 1, "random"),          # coarse detector, rays past the row ends
+    (1, 17, 9, 1.0, 3, "random"),            # one angle
+    (7, 1, 5, 1.0, 1, "random"),             # one bin
+    (5, 9, 1, 1.0, 1, "random"),             # one pixel
+    (4, 300, 20, 1.0, 1, "uniform"),         # more than one block of bins
+])
+def test_projector_matches_oracle(K, D, N, dt, B, kind):
+    ang = _angles(K, kind, K * D + N)
+    g = fbp.Geometry(K, D, N, dt, ang)
+    x = ph.rng_for(1501, K + N).normal(size=(B, N, N)).astype(np.float32)
+    got = fbp.fbp_project(g, torch.tensor(x, device="cuda")).cpu().numpy()
+    ref = oracle.forward_splat(x.astype(np.float64), K, D, dt, ang)
+    assert got.shape == ref.shape
+    assert np.max(np.abs(got - ref)) <= _tol(x, N, dt, K)
+
+
+def test_axis_aligned_angles():
+    """cos or sin exactly zero (and |cos| = |sin|): the walk direction flips there."""
+    ang = np.array([0.0, math.pi / 4, math.pi / 2, 3 * math.pi / 4, math.pi, 1.5 * math.pi])
+    K, D, N = len(ang), 91, 64
+    g = fbp.Geometry(K, D, N, 1.0, ang)
+    x = ph.rng_for(1502, 0).normal(size=(1, N, N)).astype(np.float32)
+    got = fbp.fbp_project(g, torch.tensor(x, device="cuda")).cpu().numpy()
+    ref = oracle.forward_splat(x.astype(np.float64), K, D, 1.0, ang)
+    assert np.max(np.abs(got - ref)) <= _tol(x, N, 1.0, K)
+
+
+def test_weighted_projection_is_the_adjoint_of_weighted_backprojection():
+    K, D, N = 50, 73, 48
+    ang = np.sort(ph.rng_for(1503, 0).uniform(0.0, math.pi, K))
+    x = ph.rng_for(1504, 0).normal(size=(2, N, N)).astype(np.float32)
+    w = oracle.angle_weights(ang)
+    ref = oracle.forward_splat(x.astype(np.float64), K, D, 1.0, ang) * (w * K / math.pi)[None, :, None]
+    g = fbp.Geometry(K, D, N, 1.0, ang, weighting="angle-gaps")
+    got = fbp.fbp_project(g, torch.tensor(x, device="cuda")).cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= _tol(x, N, 1.0, K) * np.max(w) * K / math.pi
+
+
+@pytest.mark.parametrize("K,D,N,B", [(720, 725, 512, 1), (360, 363, 256, 3)])
+def test_adjoint_identity_with_the_backprojector(K, D, N, B):
+    """<P x, y> = <x, P^T y> with both maps on the GPU, at the benchmark's shape."""
+    g = fbp.Geometry(K, D, N, 1.0)
+    rng = ph.rng_for(1505, N)
+    x = torch.tensor(rng.normal(size=(B, N, N)).astype(np.float32), device="cuda")
+    y = torch.tensor(rng.normal(size=(B, K, D)).astype(np.float32), device="cuda")
+    px = fbp.fbp_project(g, x).double()
+    bty = fbp.fbp_backproject(g, y).double()
+    for b in range(B):
+        lhs = float(torch.sum(px[b] * y[b].double()))
+        rhs = float(torch.sum(x[b].double() * bty[b]))
+        # both sides are sums of the same K*N^2*2 products, rounded differently in FP32
+        scale = float(torch.sum(torch.abs(px[b]) * torch.abs(y[b].double())))
+        assert abs(lhs - rhs) <= 1e-5 * scale, (b, lhs, rhs)
+
+
+def test_full_size_sampled_angles_match_oracle():
+    """512x512 image, 720 angles, 725 bins: a sample of angles, each computed by the
+    oracle as a one-angle projection (its weight pi/1 rescaled to pi/720)."""
+    K, D, N = 720, 725, 512
+    g = fbp.Geometry(K, D, N, 1.0)
+    sl = ph.ellipse_slice(1506, 0, N, K, D, 1.0, n_ellipses=20)
+    x = sl.phantom.astype(np.float32)[None]
+    got = fbp.fbp_project(g, torch.tensor(x, device="cuda")).cpu().numpy()[0]
+    ang = ph.uniform_angles(K)
+    for k in (0, 1, 179, 180, 181, 359, 360, 500, 719):
+        ref = oracle.forward_splat(x[0].astype(np.float64), 1, D, 1.0, ang[k:k + 1])[0] / K
+        assert np.max(np.abs(got[k] - ref)) <= _tol(x, N, 1.0, K), k
+
+
+def test_projection_of_analytic_phantom_is_close_to_its_radon_transform():
+    """Discretisation check, not parity: the projector applied to a sampled ellipse
+    phantom approaches the phantom's analytic line integrals (times pi/K)."""
+    K, D, N = 180, 183, 128
+    sl = ph.ellipse_slice(1507, 0, N, K, D, 1.0, n_ellipses=10)
+    g = fbp.Geometry(K, D, N, 1.0)
+    got = fbp.fbp_project(g, torch.tensor(sl.phantom.astype(np.float32)[None], device="cuda")).cpu().numpy()[0]
+    exact = sl.sino * math.pi / K
+    rel = np.sqrt(np.mean((got - exact) ** 2)) / np.sqrt(np.mean(exact ** 2))
+    assert rel < 0.05, rel
+
+
+def test_stream_ordering_and_empty_call():
+    g = fbp.Geometry(30, 41, 24, 1.0)
+    x = torch.tensor(ph.rng_for(1508, 0).normal(size=(2, 24, 24)).astype(np.float32), device="cuda")
+    ref = fbp.fbp_project(g, x).cpu().numpy()
+    st = torch.cuda.Stream()
+    out = torch.full((2, 30, 41), float("nan"), device="cuda")
+    with torch.cuda.stream(st):
+        fbp.fbp_project(g, x, out=out, stream=st)
+    st.synchronize()
+    assert np.array_equal(out.cpu().numpy(), ref)
+    empty = fbp.fbp_project(g, torch.empty((0, 24, 24), device="cuda"))
+    assert empty.shape == (0, 30, 41)
