@@ -139,7 +139,7 @@ int bp_occupancy(int cfg, int m, size_t lds_bytes);   // resident workgroups per
 
 // Everything the projector (adjoint of the backprojector) needs for one geometry.
 struct ProjJob {
-    const float* img;     // [n][N][N]
+    const float* pimg;    // padded copies, [n][2][N+1][pitch]: rows, then columns (see launch_pad)
     float* sino;          // [n][K][D]
     const double* cs;     // [K][2]: cos/dt, sin/dt (FP64)
     const float* wscale;  // [K] angle weight / (pi/K), or null
@@ -147,8 +147,22 @@ struct ProjJob {
     double centre_det;    // (D-1)/2
     int32_t N, K, D;
     float scale;          // pi/K
+    int32_t T;            // pixels read per line
+    int32_t fast3;        // 1: three taps, 1 <= r <= 1.5 on every angle
+    int32_t pad, pitch;   // zeros before each line; floats per padded line
 };
+// Tap count, kernel choice and padded-copy layout of a geometry's projector (cs as
+// in ProjJob); T == 0 when unsupported.
+struct ProjLayout {
+    int T = 0;
+    bool fast3 = false;
+    int pad = 0, pitch = 0;
+    size_t slice_floats = 0;   // floats of the two padded planes of one slice
+};
+ProjLayout project_layout(const double* cs, int K, int N);
 hipError_t launch_project(const ProjJob& job, int n_slices, hipStream_t stream);
+// Padded row and column copies of n N x N slices into out (n * slice_floats floats).
+hipError_t launch_pad(const float* img, float* out, int N, int pad, int pitch, int n_slices, hipStream_t stream);
 
 // ------------------------------------------------------------------ ramp filter GEMM
 

@@ -127,6 +127,18 @@ struct PartBuffer {
     std::mutex mu;
 };
 
+// Padded row and column copies of the slices being forward-projected: made on the
+// first fbp_project of a plan, for up to `slices` slices at a time (at most 256 MiB
+// unless one slice needs more), shared by calls in stream order like PartBuffer.
+struct ProjScratch {
+    ProjLayout layout;
+    float* ptr = nullptr;
+    int slices = 0;
+    hipEvent_t free_ev = nullptr;
+    bool recorded = false;
+    std::mutex mu;
+};
+
 struct Plan {
     int device = 0;
     int K = 0, D = 0, N = 0;
@@ -144,6 +156,7 @@ struct Plan {
     ShapeParams one;                 // single slices and short stacks
     ShapeParams stack;               // stacks of kStackMinSlices or more slices
     PartBuffer part;
+    ProjScratch proj;
     std::mutex mu;
 };
 
@@ -1300,9 +1313,26 @@ int fbp_project(const fbp_geom* geom, int32_t n_slices, const float* d_image, fl
     Plan* p = nullptr;
     rc = get_plan(geom, &p);
     if (rc != FBP_OK) return rc;
+    ProjScratch& ps = p->proj;
+    std::lock_guard<std::mutex> lock(ps.mu);
+    if (!ps.ptr) {
+        ps.layout = project_layout(p->cs.data(), p->K, p->N);
+        if (ps.layout.T == 0) return FBP_EUNSUPPORTED;
+        const size_t slice_bytes = sizeof(float) * ps.layout.slice_floats;
+        const int slices = (int)std::max<size_t>(1, std::min<size_t>(16, ((size_t)256 << 20) / slice_bytes));
+        hipError_t e = hipMalloc(&ps.ptr, slice_bytes * (size_t)slices);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ps.free_ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (ps.ptr) (void)hipFree(ps.ptr);
+            ps.ptr = nullptr;
+            return hip_fail(e, "hipMalloc (projector copies)", FBP_ENOMEM);
+        }
+        ps.slices = slices;
+    }
+    const hipStream_t s = (hipStream_t)hip_stream;
+    const ProjLayout& L = ps.layout;
     ProjJob j{};
-    j.img = d_image;
-    j.sino = d_sino;
+    j.pimg = ps.ptr;
     j.cs = p->d_cs;
     j.wscale = p->d_wscale;
     j.half_pix = 0.5 * (double)(p->N - 1);
@@ -1311,9 +1341,23 @@ int fbp_project(const fbp_geom* geom, int32_t n_slices, const float* d_image, fl
     j.K = p->K;
     j.D = p->D;
     j.scale = (float)(kPi / (double)p->K);
-    const hipError_t e = launch_project(j, n_slices, (hipStream_t)hip_stream);
-    if (e == hipErrorInvalidValue) return FBP_EUNSUPPORTED;
-    return hip_status(e, "projector kernel launch");
+    j.T = L.T;
+    j.fast3 = L.fast3 ? 1 : 0;
+    j.pad = L.pad;
+    j.pitch = L.pitch;
+    const size_t is = (size_t)p->N * p->N, qs = (size_t)p->K * p->D;
+    if (ps.recorded) FBP_TRY_HIP(hipStreamWaitEvent(s, ps.free_ev, 0));
+    for (int32_t i0 = 0; i0 < n_slices; i0 += ps.slices) {
+        const int n = std::min<int32_t>(ps.slices, n_slices - i0);
+        j.sino = d_sino + (size_t)i0 * qs;
+        hipError_t e = launch_pad(d_image + (size_t)i0 * is, ps.ptr, p->N, L.pad, L.pitch, n, s);
+        if (e == hipSuccess) e = launch_project(j, n, s);
+        if (e != hipSuccess)
+            return e == hipErrorInvalidValue ? FBP_EUNSUPPORTED : hip_status(e, "projector kernel launch");
+    }
+    FBP_TRY_HIP(hipEventRecord(ps.free_ev, s));
+    ps.recorded = true;
+    return FBP_OK;
 }
 
 int fbp_reconstruct_batch(const fbp_job* jobs, int32_t n_jobs, void* d_workspace,

@@ -40,7 +40,10 @@ def _angles(K, kind, seed):
     (180, 183, 128, 1.0, 1, "uniform"),
     (61, 95, 45, 1.0, 2, "random"),          # odd image side
     (40, 230, 48, 0.35, 1, "random"),        # fine detector: several bins per pixel
-    (33, 40, 64, 1.7, 1, "random"),          # coarse detector, rays past the row ends
+    (33, 40, 64, 1.7, 1, "random"),          # coarse detector: five pixels per line (run-time count)
+    (29, 120, 50, 0.6, 1, "random"),         # two pixels per line
+    (31, 70, 57, 1.2, 2, "random"),          # four pixels per line
+    (45, 430, 300, 1.0, 1, "random"),        # walks longer than one re-anchoring run
     (1, 17, 9, 1.0, 3, "random"),            # one angle
     (7, 1, 5, 1.0, 1, "random"),             # one bin
     (5, 9, 1, 1.0, 1, "random"),             # one pixel
