@@ -52,9 +52,17 @@ def load_library(path: str):
     lib.oracle_angle_weights.argtypes = [dp, ctypes.c_int32, dp]
     lib.oracle_backproject_weighted.argtypes = [dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                 ctypes.c_int32, ctypes.c_double, dp, dp, dp]
+    lib.oracle_fan_filter.argtypes = [dp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_int32, dp]
+    lib.oracle_fan_backproject.argtypes = [dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_double, ctypes.c_double, dp, dp, dp]
+    lib.oracle_fan_fbp.argtypes = [dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_double, ctypes.c_double, dp, dp]
+    lib.oracle_fan_splat.argtypes = lib.oracle_fan_fbp.argtypes
     for fn in (lib.oracle_filter, lib.oracle_backproject, lib.oracle_fbp,
                lib.oracle_forward_splat, lib.oracle_filter_kind, lib.oracle_angle_weights,
-               lib.oracle_backproject_weighted):
+               lib.oracle_backproject_weighted, lib.oracle_fan_filter, lib.oracle_fan_backproject,
+               lib.oracle_fan_fbp, lib.oracle_fan_splat):
         fn.restype = ctypes.c_int
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
@@ -196,4 +204,86 @@ def forward_splat(img, K: int, D: int, dt: float, angles) -> np.ndarray:
                                       _ptr(sino))
     if rc != 0:
         raise ValueError("oracle_forward_splat rejected its arguments")
+    return sino[0] if squeeze else sino
+
+
+# ---------------------------------------------------------------- fan beam
+# Flat detector through the rotation centre, source at distance R (see the
+# fan-beam block of fbp_oracle.c for the conventions).
+
+def _views(arr, betas):
+    ang = _f64(betas).reshape(-1)
+    return ang, ang.shape[0]
+
+
+def fan_filter(P, ds: float, R: float, kind: str = "ramlak") -> np.ndarray:
+    """Pre-weighted, half-kernel filtered views of P[..., D]."""
+    P = _f64(P)
+    shape = P.shape
+    D = shape[-1]
+    rows = int(np.prod(shape[:-1])) if len(shape) > 1 else 1
+    Q = np.empty_like(P)
+    rc = _load().oracle_fan_filter(_ptr(P), rows, D, float(ds), float(R), FILTERS[kind], _ptr(Q))
+    if rc != 0:
+        raise ValueError("oracle_fan_filter rejected its arguments")
+    return Q
+
+
+def fan_backproject(Q, N: int, ds: float, R: float, betas, weights=None) -> np.ndarray:
+    """Distance-weighted backprojection of filtered views Q[B][K][D] (or [K][D])."""
+    Q = _f64(Q)
+    squeeze = Q.ndim == 2
+    if squeeze:
+        Q = Q[None]
+    B, K, D = Q.shape
+    ang, Ka = _views(Q, betas)
+    if Ka != K:
+        raise ValueError("view count does not match the sinogram")
+    img = np.empty((B, N, N), dtype=np.float64)
+    wp = None
+    if weights is not None:
+        w = _f64(weights).reshape(-1)
+        if w.shape[0] != K:
+            raise ValueError("weight count does not match the views")
+        wp = _ptr(w)
+    rc = _load().oracle_fan_backproject(_ptr(Q), B, K, D, int(N), float(ds), float(R), _ptr(ang), wp,
+                                        _ptr(img))
+    if rc != 0:
+        raise ValueError("oracle_fan_backproject rejected its arguments")
+    return img[0] if squeeze else img
+
+
+def fan_fbp(P, N: int, ds: float, R: float, betas) -> np.ndarray:
+    """Fan-beam reconstruction (Ram-Lak, weights 2 pi / K) of P[B][K][D] (or [K][D])."""
+    P = _f64(P)
+    squeeze = P.ndim == 2
+    if squeeze:
+        P = P[None]
+    B, K, D = P.shape
+    ang, Ka = _views(P, betas)
+    if Ka != K:
+        raise ValueError("view count does not match the sinogram")
+    img = np.empty((B, N, N), dtype=np.float64)
+    rc = _load().oracle_fan_fbp(_ptr(P), B, K, D, int(N), float(ds), float(R), _ptr(ang), _ptr(img))
+    if rc != 0:
+        raise ValueError("oracle_fan_fbp rejected its arguments")
+    return img[0] if squeeze else img
+
+
+def fan_splat(img, K: int, D: int, ds: float, R: float, betas) -> np.ndarray:
+    """Exact adjoint of :func:`fan_backproject` with weights 2 pi / K (tiny grids)."""
+    img = _f64(img)
+    squeeze = img.ndim == 2
+    if squeeze:
+        img = img[None]
+    B, N, N2 = img.shape
+    if N != N2:
+        raise ValueError("image must be square")
+    ang, Ka = _views(img, betas)
+    if Ka != K:
+        raise ValueError("view count mismatch")
+    sino = np.empty((B, K, D), dtype=np.float64)
+    rc = _load().oracle_fan_splat(_ptr(img), B, int(K), int(D), N, float(ds), float(R), _ptr(ang), _ptr(sino))
+    if rc != 0:
+        raise ValueError("oracle_fan_splat rejected its arguments")
     return sino[0] if squeeze else sino

@@ -63,8 +63,9 @@ def detector_coords(D: int, dt: float) -> np.ndarray:
     return (np.arange(D, dtype=np.float64) - 0.5 * (D - 1)) * dt
 
 
-def ellipse_sinogram(ellipses, N: int, D: int, dt: float, angles) -> np.ndarray:
-    """Exact parallel-beam projections [K][D] (pixel units) of a sum of ellipses.
+def ellipse_line_integrals(ellipses, N: int, theta, t) -> np.ndarray:
+    """Exact line integrals (pixel units) of a sum of ellipses along the lines
+    x cos(theta) + y sin(theta) = t (theta, t: arrays of one shape).
 
     For an ellipse with semi-axes A, B (pixels), rotation phi, centre (x0, y0)
     and density rho, the line integral at (theta, t) is
@@ -72,10 +73,10 @@ def ellipse_sinogram(ellipses, N: int, D: int, dt: float, angles) -> np.ndarray:
     with s^2 = A^2 cos^2(theta-phi) + B^2 sin^2(theta-phi) and
     tau = t - x0 cos(theta) - y0 sin(theta)  (Kak & Slaney 1988, ch. 3).
     """
-    ang = np.asarray(angles, dtype=np.float64).reshape(-1, 1)
-    t = detector_coords(D, dt).reshape(1, -1)
+    ang = np.asarray(theta, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
     half = 0.5 * N
-    sino = np.zeros((ang.shape[0], D), dtype=np.float64)
+    out = np.zeros(np.broadcast(ang, t).shape, dtype=np.float64)
     ct, st = np.cos(ang), np.sin(ang)
     for e in ellipses:
         A, B = e.a * half, e.b * half
@@ -84,10 +85,33 @@ def ellipse_sinogram(ellipses, N: int, D: int, dt: float, angles) -> np.ndarray:
         tau = t - x0 * ct - y0 * st
         rad = s2 - tau * tau
         inside = rad > 0.0
-        contrib = np.where(inside, 2.0 * e.rho * A * B * np.sqrt(np.where(inside, rad, 0.0)) / s2,
-                           0.0)
-        sino += contrib
-    return sino
+        out += np.where(inside, 2.0 * e.rho * A * B * np.sqrt(np.where(inside, rad, 0.0)) / s2, 0.0)
+    return out
+
+
+def ellipse_sinogram(ellipses, N: int, D: int, dt: float, angles) -> np.ndarray:
+    """Exact parallel-beam projections [K][D] (pixel units) of a sum of ellipses."""
+    ang = np.asarray(angles, dtype=np.float64).reshape(-1, 1)
+    t = detector_coords(D, dt).reshape(1, -1)
+    return ellipse_line_integrals(ellipses, N, ang, t)
+
+
+def fan_rays(R: float, D: int, ds: float, betas):
+    """(theta, t) [K][D] of the fan-beam rays: source at R (cos b, sin b), flat
+    detector through the centre along (-sin b, cos b), bin j at s_j.  The ray
+    through the source and s e has normal angle b + pi/2 - atan(s/R) and
+    distance R s / sqrt(R^2 + s^2) from the centre."""
+    b = np.asarray(betas, dtype=np.float64).reshape(-1, 1)
+    s = detector_coords(D, ds).reshape(1, -1)
+    theta = b + 0.5 * math.pi - np.arctan(s / R)
+    t = R * s / np.sqrt(R * R + s * s)
+    return np.broadcast_to(theta, (b.shape[0], D)), np.broadcast_to(t, (b.shape[0], D))
+
+
+def ellipse_fan_sinogram(ellipses, N: int, D: int, ds: float, R: float, betas) -> np.ndarray:
+    """Exact fan-beam projections [K][D] (pixel units) of a sum of ellipses."""
+    theta, t = fan_rays(R, D, ds, betas)
+    return ellipse_line_integrals(ellipses, N, theta, t)
 
 
 def ellipse_sinogram_device(ellipses, N: int, D: int, dt: float, angles, device="cuda"):
@@ -194,3 +218,24 @@ def ellipse_slice(config_id: int, slice_id: int, N: int, K: int, D: int, dt: flo
     elif noise is not None:
         raise ValueError(f"unknown noise model {noise!r}")
     return SliceInput(sino, rasterise(ells, N), tuple(ells), N, K, D, dt, ang)
+
+
+
+def disk_fan_sinogram(radius: float, rho: float, D: int, ds: float, R: float, betas, x0: float = 0.0,
+                      y0: float = 0.0) -> np.ndarray:
+    """Fan-beam projections of a uniform disk: 2 rho sqrt(radius^2 - tau^2) along each ray."""
+    theta, t = fan_rays(R, D, ds, betas)
+    tau = t - x0 * np.cos(theta) - y0 * np.sin(theta)
+    rad = radius * radius - tau * tau
+    return np.where(rad > 0.0, 2.0 * rho * np.sqrt(np.maximum(rad, 0.0)), 0.0)
+
+
+def fan_slice(config_id: int, slice_id: int, N: int, K: int, D: int, ds: float, R: float,
+              n_ellipses: int = 20, betas=None) -> SliceInput:
+    """One seeded ellipse-phantom fan-beam slice (views evenly spread over a full turn
+    unless given); `angles` of the result holds the source angles."""
+    rng = rng_for(config_id, slice_id)
+    ells = draw_ellipses(rng, n_ellipses)
+    b = np.arange(K, dtype=np.float64) * (2.0 * math.pi / K) if betas is None else np.asarray(betas, np.float64)
+    sino = ellipse_fan_sinogram(ells, N, D, ds, R, b)
+    return SliceInput(sino, rasterise(ells, N), tuple(ells), N, K, D, ds, b)

@@ -53,6 +53,16 @@ MUTANTS = [
     ("weights without wrap-around", "a[order[K - 1]] - kPi", "a[order[0]]"),
     ("weights not reduced to the half-turn", "double t = fmod(angles[k], kPi);", "double t = angles[k];"),
     ("weighted backprojection ignores weights", "acc += weights[k] * (", "acc += (kPi / (double)K) * ("),
+    ("fan filter without the half", "acc += 0.5 * filter_tap(kind, (int64_t)n - m, ds)",
+     "acc += filter_tap(kind, (int64_t)n - m, ds)"),
+    ("fan pre-weight squared", "pw[m] = R / sqrt(R * R + s * s);", "pw[m] = R * R / (R * R + s * s);"),
+    ("fan pre-weight missing", "pw[m] = R / sqrt(R * R + s * s);", "pw[m] = 1.0;"),
+    ("fan magnification to the first power", "acc += wk * (R / L) * (R / L) * (", "acc += wk * (R / L) * ("),
+    ("fan detector axis reversed", "const double sx = R * (-x * sb + y * cb) / L;",
+     "const double sx = R * (x * sb - y * cb) / L;"),
+    ("fan depth sign", "const double L = R - (x * cb + y * sb);", "const double L = R + (x * cb + y * sb);"),
+    ("fan weight pi/K", "weights[k] : 2.0 * kPi / (double)K;", "weights[k] : kPi / (double)K;"),
+    ("fan coordinate not divided by ds", "const double u = sx / ds + centre_det;", "const double u = sx + centre_det;"),
 ]
 
 
