@@ -80,8 +80,19 @@ typedef enum {
                                     neighbours (wrapping around); sums to pi; = pi/K when even */
 } fbp_weighting;
 
-/* One parallel-beam geometry (with the filter kernel and angular weights it is
- * reconstructed with; zero-initialised fields give Ram-Lak and pi/K). */
+/* One geometry (with the filter kernel and angular weights it is reconstructed
+ * with; zero-initialised fields give parallel beam, Ram-Lak and pi/K).
+ *
+ * source_distance == 0: parallel beam, the ray x cos(theta_k) + y sin(theta_k) = t
+ *   (section "Computed tomography"), angles theta_k, bins at t_j = (j - (D-1)/2) dt.
+ * source_distance == R > 0: fan beam with a flat detector (Kak & Slaney 1988,
+ *   ch. 3): view k has its source at R (cos b_k, sin b_k), angles holds the b_k
+ *   (views spread over a full turn), and bin j sits at s_j = (j - (D-1)/2) dt on
+ *   the detector line through the centre along (-sin b_k, cos b_k).  R must
+ *   exceed N / sqrt(2) (the source stays outside the image); weighting must be
+ *   FBP_WEIGHT_UNIFORM.  Fan geometries run through fbp_filter, fbp_backproject
+ *   and fbp_reconstruct only (the other entry points return FBP_EUNSUPPORTED).
+ */
 typedef struct {
     int32_t n_angles;        /* K >= 1 */
     int32_t n_det;           /* D >= 1 */
@@ -90,6 +101,7 @@ typedef struct {
     const double* angles;    /* host array of K finite radians; copied into the plan, never kept */
     int32_t filter;          /* fbp_filter_kind */
     int32_t weighting;       /* fbp_weighting */
+    double source_distance;  /* 0: parallel beam; R > N/sqrt(2): fan beam, flat detector */
 } fbp_geom;
 
 /* One slice of a mixed batch. */
@@ -109,6 +121,9 @@ typedef struct {
  * others.
  * d_sino and d_filtered are [n_slices][K][D] and must not overlap.
  * n_slices == 0 is a valid no-op.
+ * Fan beam: each view is first multiplied by R / sqrt(R^2 + s_m^2) (through a
+ * scratch buffer owned by the plan, calls ordered on the device) and the kernel
+ * is halved:  d_filtered[b][k][n] = dt * sum_m (h(n-m)/2) * d_sino[b][k][m] R / sqrt(R^2 + s_m^2).
  */
 int fbp_filter(const fbp_geom* geom, int32_t n_slices, const float* d_sino, float* d_filtered,
                int32_t precision, void* hip_stream);
@@ -129,6 +144,10 @@ int fbp_filter(const fbp_geom* geom, int32_t n_slices, const float* d_sino, floa
  * ordered among themselves on the device).  Results are deterministic for a
  * given geometry, stack length and tuning; the two shapes agree within the
  * FP32 tolerance.
+ * Fan beam: d_image[b](X) = (2 pi / K) sum_k (R/L_k)^2 Q~_k(s_k(X) / dt + (D-1)/2),
+ * L_k = R - (x cos b_k + y sin b_k) the depth of X along the central ray and
+ * s_k(X) = R (-x sin b_k + y cos b_k) / L_k where the ray through X meets the
+ * detector; 16 x 16 pixel tiles, one pixel per lane, deterministic.
  */
 int fbp_backproject(const fbp_geom* geom, int32_t n_slices, const float* d_filtered,
                     float* d_image, void* hip_stream);

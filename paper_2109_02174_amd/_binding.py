@@ -44,7 +44,8 @@ class c_geom(ctypes.Structure):
     _fields_ = [("n_angles", ctypes.c_int32), ("n_det", ctypes.c_int32),
                 ("image_size", ctypes.c_int32), ("det_spacing", ctypes.c_double),
                 ("angles", ctypes.POINTER(ctypes.c_double)),
-                ("filter", ctypes.c_int32), ("weighting", ctypes.c_int32)]
+                ("filter", ctypes.c_int32), ("weighting", ctypes.c_int32),
+                ("source_distance", ctypes.c_double)]
 
 
 class c_job(ctypes.Structure):
@@ -93,9 +94,11 @@ def load():
 
 @dataclass
 class Geometry:
-    """Parallel-beam geometry: K angles (radians), D bins of width dt, N x N image, the
-    filter kernel ("ramlak", "shepp-logan", "hann") and the angular weights
-    ("uniform" pi/K, or "angle-gaps" for uneven angle lists)."""
+    """Geometry: K angles (radians), D bins of width dt, N x N image, the filter kernel
+    ("ramlak", "shepp-logan", "hann"), the angular weights ("uniform" pi/K, or
+    "angle-gaps" for uneven angle lists) and the source distance (0: parallel beam;
+    R > N/sqrt(2): fan beam with a flat detector, the angles being the source
+    angles, by default spread over a full turn)."""
     n_angles: int
     n_det: int
     image_size: int
@@ -103,23 +106,26 @@ class Geometry:
     angles: np.ndarray = field(default=None)
     filter: str = "ramlak"
     weighting: str = "uniform"
+    source_distance: float = 0.0
 
     def __post_init__(self):
         if self.angles is None:
-            self.angles = np.arange(self.n_angles, dtype=np.float64) * (np.pi / self.n_angles)
+            turn = 2.0 * np.pi if self.source_distance > 0 else np.pi
+            self.angles = np.arange(self.n_angles, dtype=np.float64) * (turn / self.n_angles)
         self.angles = np.ascontiguousarray(self.angles, dtype=np.float64)
 
     def as_c(self) -> c_geom:
         """The C struct (cached; the angle array is kept alive with it)."""
         key = (int(self.n_angles), int(self.n_det), int(self.image_size), float(self.det_spacing),
-               self.angles.ctypes.data, self.filter, self.weighting)
+               self.angles.ctypes.data, self.filter, self.weighting, float(self.source_distance))
         cached = getattr(self, "_c_cache", None)
         if cached is not None and cached[0] == key:
             return cached[1]
         g = c_geom(key[0], key[1], key[2], key[3],
                    self.angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                    FILTERS.get(self.filter, -1) if isinstance(self.filter, str) else int(self.filter),
-                   WEIGHTINGS.get(self.weighting, -1) if isinstance(self.weighting, str) else int(self.weighting))
+                   WEIGHTINGS.get(self.weighting, -1) if isinstance(self.weighting, str) else int(self.weighting),
+                   key[7])
         g._keep = self.angles
         self._c_cache = (key, g)
         return g

@@ -164,6 +164,30 @@ hipError_t launch_project(const ProjJob& job, int n_slices, hipStream_t stream);
 // Padded row and column copies of n N x N slices into out (n * slice_floats floats).
 hipError_t launch_pad(const float* img, float* out, int N, int pad, int pitch, int n_slices, hipStream_t stream);
 
+// ------------------------------------------------------------------ fan beam
+
+// Distance-weighted fan-beam backprojection of one geometry (flat detector
+// through the rotation centre, source at distance R).
+struct FanJob {
+    const float* q;       // [n][K][D] filtered views
+    float* img;           // [n][N][N]
+    const double* cs;     // [K][2]: cos b, sin b (FP64)
+    double R, ds;         // source distance, bin width
+    double half_pix;      // (N-1)/2
+    double centre_det;    // (D-1)/2
+    int32_t N, K, D;
+    int32_t WL;           // window pairs staged per view (bound over tiles and views)
+    int32_t KB;           // views per staged block
+    int32_t tiles_x;      // ceil(N / kFanTile)
+    float scale;          // 2 pi / K
+};
+constexpr int kFanTile = 16;
+constexpr size_t kFanLdsBudget = 48 * 1024;
+size_t fan_lds_bytes(int KB, int WL);
+hipError_t launch_fan_bp(const FanJob& job, int n_slices, hipStream_t stream);
+// out[r][m] = in[r][m] * w[m] over rows x D floats.
+hipError_t launch_preweight(const float* in, float* out, const float* w, int64_t rows, int D, hipStream_t stream);
+
 // ------------------------------------------------------------------ ramp filter GEMM
 
 enum Prec : int32_t { kFP32 = 0, kBF16 = 1, kFP16 = 2 };

@@ -46,10 +46,16 @@ int check_geom(const fbp_geom* g) {
         if (!std::isfinite(g->angles[k])) return FBP_EINVAL;
     if (g->filter < FBP_FILTER_RAMLAK || g->filter > FBP_FILTER_HANN) return FBP_EINVAL;
     if (g->weighting < FBP_WEIGHT_UNIFORM || g->weighting > FBP_WEIGHT_ANGLE_GAPS) return FBP_EINVAL;
+    const double R = g->source_distance;
+    if (!std::isfinite(R) || R < 0.0) return FBP_EINVAL;
+    if (R > 0.0 && !(R > 0.70710678118654752 * (double)g->image_size)) return FBP_EINVAL;   // source in the image
     if (g->n_det > kMaxDet || g->image_size > kMaxImage || g->n_angles > kMaxAngles)
         return FBP_EUNSUPPORTED;
+    if (R > 0.0 && g->weighting != FBP_WEIGHT_UNIFORM) return FBP_EUNSUPPORTED;
     return FBP_OK;
 }
+
+bool is_fan(const fbp_geom* g) { return g->source_distance > 0.0; }
 
 int check_prec(int32_t p) { return (p == kFP32 || p == kBF16 || p == kFP16) ? FBP_OK : FBP_EINVAL; }
 
@@ -75,9 +81,10 @@ struct GeomKey {
     uint64_t dt_bits;
     uint64_t angle_hash;
     int filter = 0, weighting = 0;
+    uint64_t r_bits = 0;   // source distance (0: parallel beam)
     bool operator<(const GeomKey& o) const {
-        return std::tie(device, K, D, N, dt_bits, angle_hash, filter, weighting) <
-               std::tie(o.device, o.K, o.D, o.N, o.dt_bits, o.angle_hash, o.filter, o.weighting);
+        return std::tie(device, K, D, N, dt_bits, angle_hash, filter, weighting, r_bits) <
+               std::tie(o.device, o.K, o.D, o.N, o.dt_bits, o.angle_hash, o.filter, o.weighting, o.r_bits);
     }
 };
 
@@ -104,6 +111,7 @@ GeomKey make_key(int device, const fbp_geom* g) {
     k.angle_hash = hash_angles(g->angles, g->n_angles);
     k.filter = g->filter;
     k.weighting = g->weighting;
+    std::memcpy(&k.r_bits, &g->source_distance, 8);
     return k;
 }
 
@@ -139,6 +147,16 @@ struct ProjScratch {
     std::mutex mu;
 };
 
+// Stream-ordered scratch rows owned by a plan (fan-beam pre-weighted views): up
+// to `rows` rows of D floats at a time, shared by calls like PartBuffer.
+struct RowScratch {
+    float* ptr = nullptr;
+    int64_t rows = 0;
+    hipEvent_t free_ev = nullptr;
+    bool recorded = false;
+    std::mutex mu;
+};
+
 struct Plan {
     int device = 0;
     int K = 0, D = 0, N = 0;
@@ -157,6 +175,13 @@ struct Plan {
     ShapeParams stack;               // stacks of kStackMinSlices or more slices
     PartBuffer part;
     ProjScratch proj;
+    // fan beam (R > 0): source distance, FP64 (cos b, sin b), pre-weights per bin,
+    // backprojection window bound and view block, pre-weighted view scratch
+    double R = 0.0;
+    double* d_fcs = nullptr;
+    float* d_fanw = nullptr;
+    int fan_WL = 0, fan_KB = 0;
+    RowScratch fanrows;
     std::mutex mu;
 };
 
@@ -179,7 +204,8 @@ Registry& registry() {
 bool angles_equal(const Plan& p, const fbp_geom* g) {
     return (int)p.angles.size() == g->n_angles &&
            std::memcmp(p.angles.data(), g->angles, sizeof(double) * (size_t)g->n_angles) == 0 &&
-           p.dt == g->det_spacing && p.filter == g->filter && p.weighting == g->weighting;
+           p.dt == g->det_spacing && p.filter == g->filter && p.weighting == g->weighting &&
+           p.R == g->source_distance;
 }
 
 // Angular quadrature of Eq. 2 for an arbitrary angle list: the lines at theta and
@@ -389,6 +415,58 @@ bool pick_shape(int cfg, const Plan& p, int cus, ShapeParams* sp) {
     return false;
 }
 
+// Largest |grad s| (detector coordinate per unit of image length) over the disk
+// of radius r around the centre seen from distance R:  R |X - S| / L^2, with
+// |X - S|^2 = L^2 + v^2 and v^2 <= r^2 - (R - L)^2 for depth L in [R - r, R + r],
+// sampled densely (the function is smooth) and padded by 1%.
+double fan_max_gradient(double R, double r) {
+    double g = 0.0;
+    const int n = 4096;
+    for (int i = 0; i <= n; ++i) {
+        const double L = (R - r) + 2.0 * r * (double)i / n;
+        const double v2 = std::max(0.0, r * r - (R - L) * (R - L));
+        g = std::max(g, R * std::sqrt(L * L + v2) / (L * L));
+    }
+    return 1.01 * g;
+}
+
+// Fan-beam tables of a plan: FP64 (cos b, sin b), FP32 pre-weights R/sqrt(R^2+s^2),
+// and the backprojection window bound: a 16 x 16 tile spans at most
+// (kFanTile-1) sqrt(2) pixels, so its shadow spans at most that times the largest
+// gradient of s, divided by dt, bins; four more cover the floor of both ends and
+// the pair read past the last one.
+int make_fan_plan(Plan* p) {
+    const double r = 0.70710678118654752 * (double)(p->N - 1);
+    const double span = (double)(kFanTile - 1) * 1.4142135623730951 * fan_max_gradient(p->R, r) / p->dt;
+    if (!(span < 4096.0)) return FBP_EUNSUPPORTED;
+    p->fan_WL = (int)std::ceil(span) + 4;
+    p->fan_KB = (int)std::min<size_t>(64, (kFanLdsBudget - 64 * 36) / (8 * (size_t)p->fan_WL));
+    if (p->fan_KB < 1) return FBP_EUNSUPPORTED;
+    std::vector<double> fcs(2 * (size_t)p->K);
+    for (int k = 0; k < p->K; ++k) {
+        fcs[2 * k] = std::cos(p->angles[k]);
+        fcs[2 * k + 1] = std::sin(p->angles[k]);
+    }
+    std::vector<float> w(p->D);
+    for (int m = 0; m < p->D; ++m) {
+        const double sm = ((double)m - 0.5 * (double)(p->D - 1)) * p->dt;
+        w[m] = (float)(p->R / std::sqrt(p->R * p->R + sm * sm));
+    }
+    hipError_t e = hipMalloc(&p->d_fcs, sizeof(double) * fcs.size());
+    if (e == hipSuccess) e = hipMalloc(&p->d_fanw, sizeof(float) * w.size());
+    if (e == hipSuccess) e = hipMemcpy(p->d_fcs, fcs.data(), sizeof(double) * fcs.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_fanw, w.data(), sizeof(float) * w.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fanrows.free_ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        if (p->d_fcs) (void)hipFree(p->d_fcs);
+        if (p->d_fanw) (void)hipFree(p->d_fanw);
+        p->d_fcs = nullptr;
+        p->d_fanw = nullptr;
+        return hip_fail(e, "fan-beam tables", FBP_ENOMEM);
+    }
+    return FBP_OK;
+}
+
 // Look up or create the plan of a validated geometry on the current device.
 int get_plan(const fbp_geom* g, Plan** out) {
     int device = 0;
@@ -420,6 +498,14 @@ int get_plan(const fbp_geom* g, Plan** out) {
     }
     p->Dh = (p->D + 1) / 2;
     p->Dhp = (int)round_up((size_t)p->Dh, 64);
+    p->R = g->source_distance;
+    if (p->R > 0.0) {
+        const int rc = make_fan_plan(p.get());
+        if (rc != FBP_OK) return rc;
+        *out = p.get();
+        R.plans[key] = std::move(p);
+        return FBP_OK;
+    }
     int one = default_config(p->N, quarter_turn_symmetric(p->angles)), stack = default_stack_config(p->N);
     auto t = R.tuned.find(key);
     if (t != R.tuned.end()) std::tie(one, stack) = t->second;
@@ -599,7 +685,7 @@ GemmJob gemm_job(const Plan& p, int prec, const float* sino, float* filt, int ro
     j.Dh = p.Dh;
     j.Dhp = p.Dhp;
     j.diag = p.diag[prec];
-    j.out_scale = p.out_scale[prec];
+    j.out_scale = p.out_scale[prec] * (p.R > 0.0 ? 0.5f : 1.0f);   // fan beam: half the kernel
     j.full = (p.filter != FBP_FILTER_RAMLAK) ? 1 : 0;
     j.taps_even = j.full ? static_cast<const char*>(p.d_taps[prec]) +
                                (2 * (size_t)p.Dhp + 1) * (prec == kFP32 ? 4 : 2)
@@ -633,10 +719,60 @@ BpJob bp_job(const Plan& p, const ShapeParams& sh, const float* filt, float* img
 
 int hip_status(hipError_t e, const char* what) { return e == hipSuccess ? FBP_OK : hip_fail(e, what); }
 
-int run_filter(const Plan& p, int prec, int32_t n, const float* sino, float* filt, hipStream_t s) {
+// Fan beam: the views are pre-weighted into the plan's scratch rows (at most
+// 64 MiB of them at a time, at least one slice) and filtered from there.
+int run_fan_filter(Plan& p, int prec, int32_t n, const float* sino, float* filt, hipStream_t s) {
+    RowScratch& rs = p.fanrows;
+    std::lock_guard<std::mutex> lock(rs.mu);
+    if (!rs.ptr) {
+        const int64_t per_slice = (int64_t)p.K * p.D;
+        const int64_t slices = std::max<int64_t>(1, ((int64_t)64 << 20) / (4 * per_slice));
+        const hipError_t e = hipMalloc(&rs.ptr, sizeof(float) * (size_t)(slices * per_slice));
+        if (e != hipSuccess) {
+            rs.ptr = nullptr;
+            return hip_fail(e, "hipMalloc (fan-beam scratch)", FBP_ENOMEM);
+        }
+        rs.rows = slices * p.K;
+    }
+    if (rs.recorded) FBP_TRY_HIP(hipStreamWaitEvent(s, rs.free_ev, 0));
+    const int64_t chunk = rs.rows / p.K;
+    for (int64_t i0 = 0; i0 < n; i0 += chunk) {
+        const int64_t m = std::min<int64_t>(chunk, n - i0);
+        const size_t off = (size_t)i0 * p.K * p.D;
+        hipError_t e = launch_preweight(sino + off, rs.ptr, p.d_fanw, m * p.K, p.D, s);
+        if (e == hipSuccess) e = launch_gemm_grid(prec, gemm_job(p, prec, rs.ptr, filt + off, (int)(m * p.K)), s);
+        if (e != hipSuccess) return hip_status(e, "fan-beam filter launch");
+    }
+    FBP_TRY_HIP(hipEventRecord(rs.free_ev, s));
+    rs.recorded = true;
+    return FBP_OK;
+}
+
+int run_filter(Plan& p, int prec, int32_t n, const float* sino, float* filt, hipStream_t s) {
     if (n == 0) return FBP_OK;
+    if (p.R > 0.0) return run_fan_filter(p, prec, n, sino, filt, s);
     const GemmJob j = gemm_job(p, prec, sino, filt, n * p.K);
     return hip_status(launch_gemm_grid(prec, j, s), "filter kernel launch");
+}
+
+int run_fan_backproject(const Plan& p, int32_t n, const float* filt, float* img, hipStream_t s) {
+    FanJob j{};
+    j.q = filt;
+    j.img = img;
+    j.cs = p.d_fcs;
+    j.R = p.R;
+    j.ds = p.dt;
+    j.half_pix = 0.5 * (double)(p.N - 1);
+    j.centre_det = 0.5 * (double)(p.D - 1);
+    j.N = p.N;
+    j.K = p.K;
+    j.D = p.D;
+    j.WL = p.fan_WL;
+    j.KB = p.fan_KB;
+    j.tiles_x = (p.N + kFanTile - 1) / kFanTile;
+    j.scale = (float)(2.0 * kPi / (double)p.K);
+    const hipError_t e = launch_fan_bp(j, n, s);
+    return e == hipErrorInvalidValue ? FBP_EUNSUPPORTED : hip_status(e, "fan-beam backprojection launch");
 }
 
 // n slices of a stack with shape sh: groups of sh.multi slices per workgroup, the
@@ -686,6 +822,7 @@ int run_single(const Plan& p, const ShapeParams& sh, PartBuffer* pb, const float
 int run_backproject(Plan& p, const ShapeParams& one, const ShapeParams& stack, int32_t n, const float* filt,
                     float* img, hipStream_t s) {
     if (n == 0) return FBP_OK;
+    if (p.R > 0.0) return run_fan_backproject(p, n, filt, img, s);
     if (n >= kStackMinSlices) return run_stack(p, stack, n, filt, img, s);
     const size_t qs = (size_t)p.K * p.D, is = (size_t)p.N * p.N;
     for (int32_t i = 0; i < n; ++i) {
@@ -748,6 +885,7 @@ int check_jobs(const fbp_job* jobs, int32_t n) {
     for (int32_t i = 0; i < n; ++i) {
         const int rc = check_geom(&jobs[i].geom);
         if (rc != FBP_OK) return rc;
+        if (is_fan(&jobs[i].geom)) return FBP_EUNSUPPORTED;   // batches are parallel beam
         if (!jobs[i].sino || !jobs[i].image) return FBP_EINVAL;
         if (!aligned4(jobs[i].sino) || !aligned4(jobs[i].image)) return FBP_EINVAL;
         if (overlaps(jobs[i].sino, sino_bytes(&jobs[i].geom, 1), jobs[i].image,
@@ -1171,6 +1309,7 @@ int time_tile_shapes(const fbp_geom* g, const std::vector<double>& cs, hipStream
 int autotune(const fbp_geom* g, hipStream_t s, int32_t* out_cfg) {
     int rc = check_geom(g);
     if (rc != FBP_OK) return rc;
+    if (is_fan(g)) return FBP_EUNSUPPORTED;                  // one fan-beam kernel: nothing to tune
     int device = 0;
     FBP_TRY_HIP(hipGetDevice(&device));
     std::vector<double> cs(2 * (size_t)g->n_angles);
@@ -1242,7 +1381,7 @@ size_t fbp_workspace_bytes(const fbp_geom* geom, int32_t n_slices, int32_t preci
 size_t fbp_batch_workspace_bytes(const fbp_job* jobs, int32_t n_jobs, int32_t precision) {
     if (check_prec(precision) != FBP_OK || n_jobs < 0 || (n_jobs > 0 && !jobs)) return 0;
     for (int32_t i = 0; i < n_jobs; ++i)
-        if (check_geom(&jobs[i].geom) != FBP_OK) return 0;
+        if (check_geom(&jobs[i].geom) != FBP_OK || is_fan(&jobs[i].geom)) return 0;
     return batch_layout(jobs, n_jobs).total;
 }
 
@@ -1307,6 +1446,7 @@ int fbp_project(const fbp_geom* geom, int32_t n_slices, const float* d_image, fl
     int rc = check_geom(geom);
     if (rc == FBP_OK) rc = check_slices(geom, n_slices);
     if (rc != FBP_OK) return rc;
+    if (is_fan(geom)) return FBP_EUNSUPPORTED;
     if (n_slices == 0) return FBP_OK;
     if (!d_image || !d_sino || !aligned4(d_image) || !aligned4(d_sino)) return FBP_EINVAL;
     if (overlaps(d_image, image_bytes(geom, n_slices), d_sino, sino_bytes(geom, n_slices))) return FBP_EINVAL;
@@ -1373,6 +1513,7 @@ int fbp_autotune(const fbp_geom* geom, void* hip_stream, int32_t* out_config) {
 int fbp_plan_config(const fbp_geom* geom) {
     const int rc = check_geom(geom);
     if (rc != FBP_OK) return rc;
+    if (is_fan(geom)) return FBP_EUNSUPPORTED;
     Plan* p = nullptr;
     const int prc = get_plan(geom, &p);
     return prc == FBP_OK ? p->one.cfg : prc;
@@ -1381,6 +1522,7 @@ int fbp_plan_config(const fbp_geom* geom) {
 int fbp_plan_stack_config(const fbp_geom* geom) {
     const int rc = check_geom(geom);
     if (rc != FBP_OK) return rc;
+    if (is_fan(geom)) return FBP_EUNSUPPORTED;
     Plan* p = nullptr;
     const int prc = get_plan(geom, &p);
     return prc == FBP_OK ? p->stack.cfg : prc;
@@ -1391,6 +1533,7 @@ int fbp_backproject_with_config(const fbp_geom* geom, int32_t n_slices, const fl
     int rc = check_geom(geom);
     if (rc == FBP_OK) rc = check_slices(geom, n_slices);
     if (rc != FBP_OK) return rc;
+    if (is_fan(geom)) return FBP_EUNSUPPORTED;
     if (config < 0 || config >= kNumTileConfigs) return FBP_EINVAL;
     if (n_slices == 0) return FBP_OK;
     if (!d_filtered || !d_image || !aligned4(d_filtered) || !aligned4(d_image)) return FBP_EINVAL;

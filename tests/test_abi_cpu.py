@@ -6,6 +6,7 @@ argument validation returns the documented status codes before any HIP call
 sources: no atomics, no CUDA headers.
 """
 import ctypes
+import math
 import os
 import re
 
@@ -87,8 +88,9 @@ def test_unknown_filter_or_weighting_rejected(lib, filt, weighting):
 
 def test_geometry_struct_matches_the_header():
     # the binding's structs follow include/fbp.h field for field
-    assert ctypes.sizeof(B.c_geom) == 40 and B.c_geom.filter.offset == 32 and B.c_geom.weighting.offset == 36
-    assert ctypes.sizeof(B.c_job) == 56
+    assert ctypes.sizeof(B.c_geom) == 48 and B.c_geom.filter.offset == 32 and B.c_geom.weighting.offset == 36
+    assert B.c_geom.source_distance.offset == 40
+    assert ctypes.sizeof(B.c_job) == 64
 
 
 def test_null_and_nonfinite_angles_rejected(lib):
@@ -189,3 +191,31 @@ def test_product_never_touches_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle\b|liboracle|fbp_oracle", text, re.M), \
                     f"{f} loads the oracle"
+
+
+@pytest.mark.parametrize("R", [-1.0, float("nan"), float("inf"), 3.0, 5 / math.sqrt(2.0)])
+def test_bad_source_distance_rejected(lib, R):
+    # the source must stay outside the 5 x 5 image: R > 5 / sqrt(2)
+    ang = (ctypes.c_double * 4)(0.0, 0.5, 1.0, 1.5)
+    g = B.c_geom(4, 7, 5, 1.0, ang, 0, 0, R)
+    assert lib.fbp_filter(ctypes.byref(g), 1, FAKE, FAKE2, 0, None) == B.FBP_EINVAL
+    assert lib.fbp_backproject(ctypes.byref(g), 1, FAKE, FAKE2, None) == B.FBP_EINVAL
+
+
+def test_fan_beam_entry_points_that_do_not_take_it(lib):
+    ang = (ctypes.c_double * 4)(0.0, 1.5, 3.0, 4.5)
+    g = B.c_geom(4, 9, 5, 1.0, ang, 0, 0, 10.0)
+    gp = ctypes.byref(g)
+    assert lib.fbp_project(gp, 1, FAKE, FAKE2, None) == B.FBP_EUNSUPPORTED
+    assert lib.fbp_plan_config(gp) == B.FBP_EUNSUPPORTED
+    assert lib.fbp_plan_stack_config(gp) == B.FBP_EUNSUPPORTED
+    assert lib.fbp_backproject_with_config(gp, 1, FAKE, FAKE2, 0, None) == B.FBP_EUNSUPPORTED
+    assert lib.fbp_autotune(gp, None, None) == B.FBP_EUNSUPPORTED
+    job = B.c_job(g, FAKE, FAKE2)
+    assert lib.fbp_batch_workspace_bytes(ctypes.byref(job), 1, 0) == 0
+    assert lib.fbp_reconstruct_batch(ctypes.byref(job), 1, FAKE3, 1 << 20, 0, None) == B.FBP_EUNSUPPORTED
+    # angle-gap weights are parallel-beam only
+    g2 = B.c_geom(4, 9, 5, 1.0, ang, 0, 1, 10.0)
+    assert lib.fbp_backproject(ctypes.byref(g2), 1, FAKE, FAKE2, None) == B.FBP_EUNSUPPORTED
+    # validation still runs first: overlapping buffers are invalid
+    assert lib.fbp_backproject(gp, 1, FAKE, FAKE + 4, None) == B.FBP_EINVAL
