@@ -28,6 +28,8 @@ namespace fbp {
 namespace {
 
 constexpr int kFanThreads = kFanTile * kFanTile;
+constexpr int kRawF32 = 0x00020000;     // buffer resource word 3: 32-bit data, raw (stride 0)
+constexpr int kPastEnd = 0x7FFFFFF0;    // byte offset beyond any view block: reads as 0
 
 __global__ __launch_bounds__(256) void preweight_kernel(const float* __restrict__ in, float* __restrict__ out,
                                                         const float* __restrict__ w, int64_t n, int D) {
@@ -36,88 +38,146 @@ __global__ __launch_bounds__(256) void preweight_kernel(const float* __restrict_
         out[e] = in[e] * w[e % D];
 }
 
+// M slices per workgroup (a stack of one geometry): the map of a pixel and view
+// (rho, u, window index) is made once and applied to the M slices' windows, so a
+// slice's arithmetic and summation order are those of M = 1 (bitwise equal).
+template <int M>
 __global__ __launch_bounds__(kFanThreads) void fan_bp_kernel(FanJob job) {
     extern __shared__ __align__(16) char smem[];
     const int KB = job.KB, WL = job.WL, N = job.N, K = job.K, D = job.D;
     float* coef = reinterpret_cast<float*>(smem);                      // [KB][8]
     int* org = reinterpret_cast<int*>(coef + 8 * KB);                  // [KB] window origins
-    float2* win = reinterpret_cast<float2*>(org + ((KB + 3) & ~3));    // [KB][WL] (A_i, dQ_i)
+    float2* win = reinterpret_cast<float2*>(org + ((KB + 3) & ~3));    // [KB][WL][M] (A_i, dQ_i)
     const int tiles = job.tiles_x * job.tiles_x;
-    const int s = blockIdx.x / tiles;
-    const int tile = blockIdx.x - s * tiles;
+    const int g = blockIdx.x / tiles;                                  // group of M slices
+    const int tile = blockIdx.x - g * tiles;
     const int c0 = (tile % job.tiles_x) * kFanTile, r0 = (tile / job.tiles_x) * kFanTile;
     const int dx = threadIdx.x & (kFanTile - 1), dy = threadIdx.x / kFanTile;
     const bool inside = c0 + dx < N && r0 + dy < N;
     const int cw = min(kFanTile, N - c0), rh = min(kFanTile, N - r0);   // pixels of the tile in the image
     const float fdx = (float)dx, fdy = (float)dy;
-    const float* __restrict__ qs = job.q + (size_t)s * K * D;
-    float acc = 0.0f;
+    const size_t qstride = (size_t)K * D;
+    const float* __restrict__ qs = job.q + (size_t)g * M * qstride;
+    const float inv_wl = 1.0f / (float)WL;
+    float acc[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) acc[m] = 0.0f;
     for (int k0 = 0; k0 < K; k0 += KB) {
         const int nk = min(KB, K - k0);
         __syncthreads();                                               // previous block's reads done
         if ((int)threadIdx.x < nk) {
-            // FP64: window origin and map coefficients of this tile for view k0 + t
+            // FP64: window origin and map coefficients of this tile for view k0 + t.
+            // The window starts half_span bins below the bin of the tile's centre
+            // (the centre of its pixels inside the image): no pixel of the tile is
+            // farther than that from it.
             const int k = k0 + threadIdx.x;
             const double c = job.cs[2 * k], sn = job.cs[2 * k + 1];
             const double R = job.R, ds = job.ds, cd = job.centre_det;
             const double xt = (double)c0 - job.half_pix, yt = (double)r0 - job.half_pix;
             const double Lt = R - (c * xt + sn * yt);                  // depth of the tile origin
             const double Nt = R * (-sn * xt + c * yt);                 // R (X . e) at the tile origin
-            double umin = INFINITY;
-            for (int q = 0; q < 4; ++q) {                              // extremes sit at the corners
-                const double ex = (q & 1) ? (double)(cw - 1) : 0.0, ey = (q & 2) ? (double)(rh - 1) : 0.0;
-                const double u = (Nt + R * (-sn * ex + c * ey)) / ((Lt - c * ex - sn * ey) * ds) + cd;
-                umin = fmin(umin, u);
-            }
-            const double i0 = floor(umin);
+            const double ex = 0.5 * (double)(cw - 1), ey = 0.5 * (double)(rh - 1);
+            const double uc = (Nt + R * (-sn * ex + c * ey)) / ((Lt - c * ex - sn * ey) * ds) + cd;
+            const double i0 = floor(uc - job.half_span);
             const double G = (i0 - cd) * ds;
             const double a0 = Nt - G * Lt, a1 = -R * sn + G * c, a2 = R * c + G * sn;
-            const double inv = 1.0 / (ds * R);
+            const double inv = job.inv_dsR, ir = job.inv_R;
             float* cf = coef + 8 * threadIdx.x;
             cf[0] = (float)(a0 * inv);
             cf[1] = (float)(a1 * inv);
             cf[2] = (float)(a2 * inv);
             cf[3] = 0.0f;
-            cf[4] = (float)(Lt / R);
-            cf[5] = (float)(-c / R);
-            cf[6] = (float)(-sn / R);
+            cf[4] = (float)(Lt * ir);
+            cf[5] = (float)(-c * ir);
+            cf[6] = (float)(-sn * ir);
             cf[7] = 0.0f;
             org[threadIdx.x] = (int)i0;
         }
         __syncthreads();
-        // windows: value at local u in [i, i+1) is A_i + u dQ_i, zero beyond the detector
-        for (int e = threadIdx.x; e < nk * WL; e += kFanThreads) {
-            const int kk = e / WL, i = e - kk * WL;
-            const int bin = org[kk] + i;
-            const float* __restrict__ q = qs + (size_t)(k0 + kk) * D;
-            const float a = (bin >= 0 && bin < D) ? q[bin] : 0.0f;
-            const float b = (bin + 1 >= 0 && bin + 1 < D) ? q[bin + 1] : 0.0f;
-            const float dq = b - a;
-            win[e] = make_float2(fmaf(-(float)i, dq, a), dq);
+        // windows: value at local u in [i, i+1) is A_i + u dQ_i, zero beyond the detector;
+        // e -> (view, bin) by a float reciprocal (exact: e < KB WL <= 6144, margin 0.5/WL);
+        // branch-free buffer loads: offsets of bins off the detector are past the end
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const __amdgpu_buffer_rsrc_t rows = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float*>(qs + m * qstride + (size_t)k0 * D), (short)0, nk * D * 4, kRawF32);
+#pragma unroll 2
+            for (int e = threadIdx.x; e < nk * WL; e += kFanThreads) {
+                const int kk = (int)(((float)e + 0.5f) * inv_wl), i = e - kk * WL;
+                const int bin = org[kk] + i;
+                const int o = (kk * D + bin) * 4;
+                const int oa = (unsigned)bin < (unsigned)D ? o : kPastEnd;
+                const int ob = (unsigned)(bin + 1) < (unsigned)D ? o + 4 : kPastEnd;
+                const float a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rows, oa, 0, 0));
+                const float b = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rows, ob, 0, 0));
+                const float dq = b - a;
+                win[e * M + m] = make_float2(fmaf(-(float)i, dq, a), dq);
+            }
         }
         __syncthreads();
         if (inside) {
-            for (int kk = 0; kk < nk; ++kk) {
+            const float umax = (float)(WL - 1);
+            // one view: the pixel's map, then the M slices' pairs at its window index
+            auto map = [&](int kk, float& u, float& w) {
                 const float4 nf = *reinterpret_cast<const float4*>(coef + 8 * kk);
                 const float4 df = *reinterpret_cast<const float4*>(coef + 8 * kk + 4);
                 const float den = fmaf(df.z, fdy, fmaf(df.y, fdx, df.x));
                 const float num = fmaf(nf.z, fdy, fmaf(nf.y, fdx, nf.x));
                 const float rho = __builtin_amdgcn_rcpf(den);          // R / L
-                const float u = num * rho;
-                const int i = min(max((int)u, 0), WL - 1);
-                const float2 p = win[kk * WL + i];
-                acc = fmaf(rho * rho, fmaf(u, p.y, p.x), acc);
+                u = num * rho;
+                w = rho * rho;
+                const int i = (int)__builtin_amdgcn_fmed3f(u, 0.0f, umax);   // in the window whatever u holds
+                return win + (size_t)(kk * WL + i) * M;                // the M slices' pairs, together
+            };
+            auto fetch = [&](const float2* pw, float2 (&p)[M]) {
+                if constexpr (M == 1) {
+                    p[0] = pw[0];
+                } else {
+#pragma unroll
+                    for (int h = 0; h < M / 2; ++h) {                  // 16-byte reads, two slices each
+                        const float4 v = reinterpret_cast<const float4*>(pw)[h];
+                        p[2 * h] = make_float2(v.x, v.y);
+                        p[2 * h + 1] = make_float2(v.z, v.w);
+                    }
+                }
+            };
+            int kk = 0;
+            // four views per round: all maps, then all reads, then the sums in view order
+            for (; kk + 4 <= nk; kk += 4) {
+                float u[4], w[4];
+                const float2* pw[4];
+                float2 p[4][M];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pw[q] = map(kk + q, u[q], w[q]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) fetch(pw[q], p[q]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                    for (int m = 0; m < M; ++m) acc[m] = fmaf(w[q], fmaf(u[q], p[q][m].y, p[q][m].x), acc[m]);
+                }
+            }
+            for (; kk < nk; ++kk) {
+                float u, w;
+                float2 p[M];
+                fetch(map(kk, u, w), p);
+#pragma unroll
+                for (int m = 0; m < M; ++m) acc[m] = fmaf(w, fmaf(u, p[m].y, p[m].x), acc[m]);
             }
         }
     }
-    if (inside) job.img[(size_t)s * N * N + (size_t)(r0 + dy) * N + (c0 + dx)] = acc * job.scale;
+    if (inside) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            job.img[((size_t)g * M + m) * N * N + (size_t)(r0 + dy) * N + (c0 + dx)] = acc[m] * job.scale;
+    }
 }
 
 }  // namespace
 
-size_t fan_lds_bytes(int KB, int WL) {
+size_t fan_lds_bytes(int KB, int WL, int M) {
     return sizeof(float) * 8 * (size_t)KB + sizeof(int) * (size_t)((KB + 3) & ~3) +
-           sizeof(float) * 2 * (size_t)KB * (size_t)WL;
+           sizeof(float) * 2 * (size_t)M * (size_t)KB * (size_t)WL;
 }
 
 hipError_t launch_preweight(const float* in, float* out, const float* w, int64_t rows, int D, hipStream_t stream) {
@@ -127,14 +187,33 @@ hipError_t launch_preweight(const float* in, float* out, const float* w, int64_t
     return launch_kernel(preweight_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, in, out, w, n, D);
 }
 
-hipError_t launch_fan_bp(const FanJob& job, int n_slices, hipStream_t stream) {
+// n_slices of one geometry: groups of M through the M-slice kernel (KB views per
+// block for it), the rest one slice per workgroup.
+hipError_t launch_fan_bp(const FanJob& job, int n_slices, int M, int KBm, hipStream_t stream) {
     if (n_slices <= 0) return hipSuccess;
-    if (job.KB < 1 || job.WL < 2) return hipErrorInvalidValue;
-    const int64_t blocks = (int64_t)job.tiles_x * job.tiles_x * n_slices;
-    if (blocks > INT32_MAX) return hipErrorInvalidValue;
-    const size_t lds = fan_lds_bytes(job.KB, job.WL);
-    if (lds > kFanLdsBudget) return hipErrorInvalidValue;
-    return launch_kernel(fan_bp_kernel, dim3((unsigned)blocks), dim3(kFanThreads), lds, stream, job);
+    if (job.KB < 1 || job.WL < 2 || (M != 1 && M != 2 && M != 4) || (M > 1 && KBm < 1)) return hipErrorInvalidValue;
+    const int64_t tiles = (int64_t)job.tiles_x * job.tiles_x;
+    const int grouped = (M > 1) ? n_slices - n_slices % M : 0;
+    if (grouped > 0) {
+        FanJob j = job;
+        j.KB = KBm;
+        const size_t lds = fan_lds_bytes(KBm, job.WL, M);
+        const int64_t blocks = tiles * (grouped / M);
+        if (blocks > INT32_MAX || lds > kFanLdsBudget) return hipErrorInvalidValue;
+        const hipError_t e = (M == 2)
+            ? launch_kernel(fan_bp_kernel<2>, dim3((unsigned)blocks), dim3(kFanThreads), lds, stream, j)
+            : launch_kernel(fan_bp_kernel<4>, dim3((unsigned)blocks), dim3(kFanThreads), lds, stream, j);
+        if (e != hipSuccess) return e;
+    }
+    const int rest = n_slices - grouped;
+    if (rest == 0) return hipSuccess;
+    FanJob j = job;
+    j.q = job.q + (size_t)grouped * job.K * job.D;
+    j.img = job.img + (size_t)grouped * job.N * job.N;
+    const size_t lds = fan_lds_bytes(job.KB, job.WL, 1);
+    const int64_t blocks = tiles * rest;
+    if (blocks > INT32_MAX || lds > kFanLdsBudget) return hipErrorInvalidValue;
+    return launch_kernel(fan_bp_kernel<1>, dim3((unsigned)blocks), dim3(kFanThreads), lds, stream, j);
 }
 
 }  // namespace fbp

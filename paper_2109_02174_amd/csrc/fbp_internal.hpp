@@ -173,6 +173,8 @@ struct FanJob {
     float* img;           // [n][N][N]
     const double* cs;     // [K][2]: cos b, sin b (FP64)
     double R, ds;         // source distance, bin width
+    double inv_R, inv_dsR;   // 1/R, 1/(ds R)
+    double half_span;     // bound on |u - u(tile centre)| over a tile's pixels, in bins
     double half_pix;      // (N-1)/2
     double centre_det;    // (D-1)/2
     int32_t N, K, D;
@@ -183,8 +185,10 @@ struct FanJob {
 };
 constexpr int kFanTile = 16;
 constexpr size_t kFanLdsBudget = 48 * 1024;
-size_t fan_lds_bytes(int KB, int WL);
-hipError_t launch_fan_bp(const FanJob& job, int n_slices, hipStream_t stream);
+size_t fan_lds_bytes(int KB, int WL, int M);
+// n_slices through the M-slice kernel (M = 2 or 4, KBm views per block) in groups,
+// the remainder (and everything when M = 1) one slice per workgroup.
+hipError_t launch_fan_bp(const FanJob& job, int n_slices, int M, int KBm, hipStream_t stream);
 // out[r][m] = in[r][m] * w[m] over rows x D floats.
 hipError_t launch_preweight(const float* in, float* out, const float* w, int64_t rows, int D, hipStream_t stream);
 

@@ -180,7 +180,8 @@ struct Plan {
     double R = 0.0;
     double* d_fcs = nullptr;
     float* d_fanw = nullptr;
-    int fan_WL = 0, fan_KB = 0;
+    int fan_WL = 0, fan_KB = 0, fan_KB4 = 0;   // window pairs; views per block (one slice, four)
+    double fan_half_span = 0.0;
     RowScratch fanrows;
     std::mutex mu;
 };
@@ -431,17 +432,20 @@ double fan_max_gradient(double R, double r) {
 }
 
 // Fan-beam tables of a plan: FP64 (cos b, sin b), FP32 pre-weights R/sqrt(R^2+s^2),
-// and the backprojection window bound: a 16 x 16 tile spans at most
-// (kFanTile-1) sqrt(2) pixels, so its shadow spans at most that times the largest
-// gradient of s, divided by dt, bins; four more cover the floor of both ends and
-// the pair read past the last one.
+// and the backprojection window bound: no pixel of a 16 x 16 tile is farther than
+// (kFanTile-1)/sqrt(2) from the tile's centre, so its bin is within half_span =
+// that times the largest gradient of s, over dt, of the centre's; a window from
+// floor(u_centre - half_span) then needs ceil(2 half_span) + 2 pairs, plus two
+// for rounding.  Views per block: up to 64 for one slice, 16 for four (four
+// slices' windows; small blocks keep the LDS per workgroup low).
 int make_fan_plan(Plan* p) {
     const double r = 0.70710678118654752 * (double)(p->N - 1);
-    const double span = (double)(kFanTile - 1) * 1.4142135623730951 * fan_max_gradient(p->R, r) / p->dt;
-    if (!(span < 4096.0)) return FBP_EUNSUPPORTED;
-    p->fan_WL = (int)std::ceil(span) + 4;
+    p->fan_half_span = (double)(kFanTile - 1) * 0.70710678118654752 * fan_max_gradient(p->R, r) / p->dt;
+    if (!(p->fan_half_span < 2048.0)) return FBP_EUNSUPPORTED;
+    p->fan_WL = (int)std::ceil(2.0 * p->fan_half_span) + 4;
     p->fan_KB = (int)std::min<size_t>(64, (kFanLdsBudget - 64 * 36) / (8 * (size_t)p->fan_WL));
     if (p->fan_KB < 1) return FBP_EUNSUPPORTED;
+    p->fan_KB4 = (int)std::min<size_t>(16, (kFanLdsBudget - 64 * 36) / (4 * 8 * (size_t)p->fan_WL));
     std::vector<double> fcs(2 * (size_t)p->K);
     for (int k = 0; k < p->K; ++k) {
         fcs[2 * k] = std::cos(p->angles[k]);
@@ -762,6 +766,9 @@ int run_fan_backproject(const Plan& p, int32_t n, const float* filt, float* img,
     j.cs = p.d_fcs;
     j.R = p.R;
     j.ds = p.dt;
+    j.inv_R = 1.0 / p.R;
+    j.inv_dsR = 1.0 / (p.dt * p.R);
+    j.half_span = p.fan_half_span;
     j.half_pix = 0.5 * (double)(p.N - 1);
     j.centre_det = 0.5 * (double)(p.D - 1);
     j.N = p.N;
@@ -771,7 +778,9 @@ int run_fan_backproject(const Plan& p, int32_t n, const float* filt, float* img,
     j.KB = p.fan_KB;
     j.tiles_x = (p.N + kFanTile - 1) / kFanTile;
     j.scale = (float)(2.0 * kPi / (double)p.K);
-    const hipError_t e = launch_fan_bp(j, n, s);
+    // stacks of 4 or more share each pixel's map over 4 slices per workgroup
+    const int M = (n >= kStackMinSlices && p.fan_KB4 >= 1) ? 4 : 1;
+    const hipError_t e = launch_fan_bp(j, n, M, p.fan_KB4, s);
     return e == hipErrorInvalidValue ? FBP_EUNSUPPORTED : hip_status(e, "fan-beam backprojection launch");
 }
 

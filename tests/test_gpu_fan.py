@@ -51,6 +51,7 @@ def test_fan_filter_matches_oracle(kind, K, D, dt, R, B):
 @pytest.mark.parametrize("K,D,N,dt,Rf,B,kind", [
     (90, 129, 70, 1.0, 1.6, 1, "turn"),
     (61, 95, 45, 1.0, 2.0, 3, "random"),        # odd side, ragged tiles, three slices
+    (37, 140, 70, 0.8, 1.4, 6, "random"),       # stack: a group of four slices per workgroup and two single
     (40, 260, 48, 0.6, 1.3, 1, "random"),       # fine detector, strong magnification
     (50, 161, 40, 1.0, 1.02, 1, "random"),      # source just outside the image corners
     (1, 77, 33, 1.0, 1.5, 2, "random"),         # one view
