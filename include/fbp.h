@@ -63,7 +63,11 @@ typedef enum {
 typedef enum {
     FBP_PREC_FP32 = 0,
     FBP_PREC_BF16 = 1,      /* sinogram rows and kernel taps rounded to bfloat16 (RNE) */
-    FBP_PREC_FP16 = 2       /* rounded to binary16 (RNE); taps pre-scaled by 2^s to stay normal */
+    FBP_PREC_FP16 = 2,      /* rounded to binary16 (RNE); taps pre-scaled by 2^s to stay normal */
+    FBP_PREC_FP32_FFT = 3   /* FP32 without the GEMM: each pair of rows, zero-padded to a power of two
+                               L >= 2D-1, is filtered by FFT, multiplication by the taps' DFT and
+                               inverse FFT (equal to the linear convolution); D <= 4096; not for
+                               fbp_reconstruct_batch (FBP_EUNSUPPORTED) */
 } fbp_precision;
 
 /* Filter kernel of the convolution Q = P * H (all with full support |d| <= D-1). */

@@ -24,7 +24,7 @@ FBP_EHIP = -3
 FBP_EUNSUPPORTED = -4
 FBP_EWORKSPACE = -5
 
-PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2, "fft": 3}
 FILTERS = {"ramlak": 0, "shepp-logan": 1, "hann": 2}
 WEIGHTINGS = {"uniform": 0, "angle-gaps": 1}
 

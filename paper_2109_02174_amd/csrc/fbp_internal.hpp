@@ -195,6 +195,23 @@ hipError_t launch_preweight(const float* in, float* out, const float* w, int64_t
 // ------------------------------------------------------------------ ramp filter GEMM
 
 enum Prec : int32_t { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
+constexpr int32_t kFFT32 = 3;     // FP32 through the FFT path (no GEMM)
+
+// ------------------------------------------------------------------ FFT filter path
+
+// Ramp filter of R rows by FFT: pairs of rows packed as one complex row, zero
+// padded to L = 2^log2L >= 2D - 1, multiplied by the real DFT of the taps.
+struct FftJob {
+    const float* p;       // [R][D]
+    float* q;             // [R][D]
+    const float2* tw;     // [L]: e^{-2 pi i m / L}
+    const float* H;       // [L]: DFT of the taps t(d), |d| <= D-1, times (output scale) / L
+    int32_t R, D;
+    int32_t log2L;
+};
+constexpr int kFftMaxLog2 = 13;   // L <= 8192 (LDS of 64 KiB): D <= 4096
+int fft_length_log2(int D);
+hipError_t launch_fft_filter(const FftJob& job, hipStream_t stream);
 
 // One ramp-filter GEMM problem: Q[R][D] = P[R][D] x T, T[m][n] = tap(n - m), computed
 // as two parity-split half GEMMs over the odd taps to(j) = tap(2j - 1) plus the

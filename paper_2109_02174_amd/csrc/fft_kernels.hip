@@ -1,0 +1,201 @@
+// FFT filter path for gfx950: the ramp filter of every projection row as a
+// circular convolution of the zero-padded row, computed with one complex FFT per
+// pair of rows in LDS.
+//
+// The filter (the convolution Q = P * H, arXiv 2109.02174, section "Computed
+// tomography") is linear with taps t(d) = dt h(d) for |d| <= D-1.  With the row
+// zero-padded to L >= 2D - 1 points, the circular convolution with the taps
+// wrapped modulo L equals the linear one on the D output bins (no output sees a
+// wrapped tap).  The taps are even in d, so their L-point DFT H is real and even;
+// two real rows a, b packed as z = a + i b therefore give
+//     IFFT(FFT(z) H) = (a * t) + i (b * t)
+// and the two filtered rows are the real and imaginary parts.  One workgroup per
+// row pair: load (zero padding), forward FFT, multiply by H (which also carries
+// 1/L and the output scale), inverse FFT, store the first D points.
+//
+// The FFT is a Stockham autosort FFT in LDS (natural order in and out, one
+// buffer: every pass reads all of its inputs into registers before a barrier
+// and writes all of its outputs after it): one radix-2 pass when log2 L is odd,
+// then radix-4 passes.  Twiddles come from a table e^{-2 pi i m / L} made in
+// FP64 on the host; up to L = 4096 its first quarter is copied to LDS and the
+// rest follows from W^(m + jL/4) = (-i)^j W^m.
+#include "fbp_internal.hpp"
+
+namespace fbp {
+
+namespace {
+
+// threads per workgroup: one radix-4 butterfly per thread and pass (64 to 1024)
+constexpr int fft_threads(int log2L) {
+    return log2L <= 8 ? 64 : (log2L >= 12 ? 1024 : (1 << (log2L - 2)));
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
+template <int LOG2L>
+__global__ __launch_bounds__(fft_threads(LOG2L)) void fft_filter_kernel(FftJob job) {
+    constexpr int kFftThreads = fft_threads(LOG2L);
+    constexpr int L = 1 << LOG2L;
+    constexpr int Q4 = L / 4;                                   // radix-4 butterflies per pass
+    constexpr int NB4 = Q4 >= kFftThreads ? Q4 / kFftThreads : 1;
+    constexpr int H2 = L / 2;                                   // radix-2 butterflies
+    constexpr int NB2 = H2 >= kFftThreads ? H2 / kFftThreads : 1;
+    // twiddles from an LDS copy of the first quarter of the table (L <= 4096):
+    // W^(m + jL/4) = (-i)^j W^m
+    constexpr bool kLdsTw = LOG2L >= 2 && LOG2L <= 12;
+    constexpr int QT = kLdsTw ? L / 4 : 1;
+    __shared__ float2 buf[L];
+    __shared__ float2 qtw[QT];
+    const int t = threadIdx.x;
+    const int D = job.D;
+    const int ra = 2 * blockIdx.x, rb = ra + 1;
+    const bool has_b = rb < job.R;
+    const float* __restrict__ pa = job.p + (size_t)ra * D;
+    const float* __restrict__ pb = job.p + (size_t)(has_b ? rb : ra) * D;
+    const float2* __restrict__ tw = job.tw;
+
+    for (int n = t; n < L; n += kFftThreads) {
+        const float a = n < D ? pa[n] : 0.0f;
+        const float b = (has_b && n < D) ? pb[n] : 0.0f;
+        buf[n] = make_float2(a, b);
+    }
+    if constexpr (kLdsTw) {
+        for (int m = t; m < QT; m += kFftThreads) qtw[m] = tw[m];
+    }
+    __syncthreads();
+    auto twiddle = [&](int m) -> float2 {                       // W^m, m < 3L/4
+        if constexpr (kLdsTw) {
+            const float2 w = qtw[m & (QT - 1)];
+            switch (m >> (LOG2L - 2)) {
+                case 0: return w;
+                case 1: return make_float2(w.y, -w.x);
+                default: return make_float2(-w.x, -w.y);
+            }
+        } else {
+            return tw[m];
+        }
+    };
+
+    auto fft = [&](bool inverse) {
+        int Ns = 1;
+        if constexpr ((LOG2L & 1) != 0) {                       // radix 2 (k = 0: no twiddle)
+            float2 v[NB2][2];
+#pragma unroll
+            for (int q = 0; q < NB2; ++q) {
+                const int j = t + q * kFftThreads;
+                if (j < H2) {
+                    v[q][0] = buf[j];
+                    v[q][1] = buf[j + H2];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < NB2; ++q) {
+                const int j = t + q * kFftThreads;
+                if (j < H2) {
+                    buf[2 * j] = make_float2(v[q][0].x + v[q][1].x, v[q][0].y + v[q][1].y);
+                    buf[2 * j + 1] = make_float2(v[q][0].x - v[q][1].x, v[q][0].y - v[q][1].y);
+                }
+            }
+            __syncthreads();
+            Ns = 2;
+        }
+        for (; Ns < L; Ns *= 4) {                               // radix 4
+            float2 v[NB4][4];
+#pragma unroll
+            for (int q = 0; q < NB4; ++q) {
+                const int j = t + q * kFftThreads;
+                if (j < Q4) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[q][r] = buf[j + r * Q4];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < NB4; ++q) {
+                const int j = t + q * kFftThreads;
+                if (j < Q4) {
+                    const int k = j & (Ns - 1);
+                    const int step = k * (L / (4 * Ns));        // twiddle W^(r k L / (4 Ns)), index < 3L/4
+                    if (step != 0) {
+#pragma unroll
+                        for (int r = 1; r < 4; ++r) {
+                            float2 w = twiddle(r * step);
+                            if (inverse) w.y = -w.y;
+                            v[q][r] = cmul(v[q][r], w);
+                        }
+                    }
+                    const float2 a0 = make_float2(v[q][0].x + v[q][2].x, v[q][0].y + v[q][2].y);
+                    const float2 a1 = make_float2(v[q][0].x - v[q][2].x, v[q][0].y - v[q][2].y);
+                    const float2 a2 = make_float2(v[q][1].x + v[q][3].x, v[q][1].y + v[q][3].y);
+                    const float2 d3 = make_float2(v[q][1].x - v[q][3].x, v[q][1].y - v[q][3].y);
+                    // -i d3 (forward) or +i d3 (inverse)
+                    const float2 a3 = inverse ? make_float2(-d3.y, d3.x) : make_float2(d3.y, -d3.x);
+                    const int o = (j - k) * 4 + k;
+                    buf[o] = make_float2(a0.x + a2.x, a0.y + a2.y);
+                    buf[o + Ns] = make_float2(a1.x + a3.x, a1.y + a3.y);
+                    buf[o + 2 * Ns] = make_float2(a0.x - a2.x, a0.y - a2.y);
+                    buf[o + 3 * Ns] = make_float2(a1.x - a3.x, a1.y - a3.y);
+                }
+            }
+            __syncthreads();
+        }
+    };
+
+    fft(false);
+    for (int n = t; n < L; n += kFftThreads) {
+        const float h = job.H[n];
+        const float2 z = buf[n];
+        buf[n] = make_float2(z.x * h, z.y * h);
+    }
+    __syncthreads();
+    fft(true);
+
+    float* __restrict__ qa = job.q + (size_t)ra * D;
+    float* __restrict__ qb = job.q + (size_t)rb * D;
+    for (int n = t; n < D; n += kFftThreads) {
+        const float2 z = buf[n];
+        qa[n] = z.x;
+        if (has_b) qb[n] = z.y;
+    }
+}
+
+template <int LOG2L>
+hipError_t launch_fft_l(const FftJob& job, unsigned blocks, hipStream_t stream) {
+    return launch_kernel(fft_filter_kernel<LOG2L>, dim3(blocks), dim3(fft_threads(LOG2L)), 0, stream, job);
+}
+
+}  // namespace
+
+int fft_length_log2(int D) {
+    int lg = 0;
+    while ((1 << lg) < 2 * D - 1) ++lg;
+    return lg;
+}
+
+hipError_t launch_fft_filter(const FftJob& job, hipStream_t stream) {
+    if (job.R <= 0) return hipSuccess;
+    if (job.log2L < 0 || job.log2L > kFftMaxLog2 || (1 << job.log2L) < 2 * job.D - 1) return hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)((job.R + 1) / 2);
+    switch (job.log2L) {
+        case 0: return launch_fft_l<0>(job, blocks, stream);
+        case 1: return launch_fft_l<1>(job, blocks, stream);
+        case 2: return launch_fft_l<2>(job, blocks, stream);
+        case 3: return launch_fft_l<3>(job, blocks, stream);
+        case 4: return launch_fft_l<4>(job, blocks, stream);
+        case 5: return launch_fft_l<5>(job, blocks, stream);
+        case 6: return launch_fft_l<6>(job, blocks, stream);
+        case 7: return launch_fft_l<7>(job, blocks, stream);
+        case 8: return launch_fft_l<8>(job, blocks, stream);
+        case 9: return launch_fft_l<9>(job, blocks, stream);
+        case 10: return launch_fft_l<10>(job, blocks, stream);
+        case 11: return launch_fft_l<11>(job, blocks, stream);
+        case 12: return launch_fft_l<12>(job, blocks, stream);
+        case 13: return launch_fft_l<13>(job, blocks, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace fbp

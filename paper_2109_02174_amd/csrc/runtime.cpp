@@ -57,7 +57,7 @@ int check_geom(const fbp_geom* g) {
 
 bool is_fan(const fbp_geom* g) { return g->source_distance > 0.0; }
 
-int check_prec(int32_t p) { return (p == kFP32 || p == kBF16 || p == kFP16) ? FBP_OK : FBP_EINVAL; }
+int check_prec(int32_t p) { return (p == kFP32 || p == kBF16 || p == kFP16 || p == kFFT32) ? FBP_OK : FBP_EINVAL; }
 
 size_t sino_bytes(const fbp_geom* g, int64_t n) {
     return (size_t)n * (size_t)g->n_angles * (size_t)g->n_det * sizeof(float);
@@ -182,6 +182,10 @@ struct Plan {
     float* d_fanw = nullptr;
     int fan_WL = 0, fan_KB = 0, fan_KB4 = 0;   // window pairs; views per block (one slice, four)
     double fan_half_span = 0.0;
+    // FFT filter path: twiddles and the taps' DFT for L = 2^fft_log2 (made on first use)
+    float2* d_fft_tw = nullptr;
+    float* d_fft_H = nullptr;
+    int fft_log2 = -1;
     RowScratch fanrows;
     std::mutex mu;
 };
@@ -607,7 +611,48 @@ double filter_tap(int kind, int d, double dt) {
 // (zero where the offset exceeds D - 1): the odd taps to(j) = tap(2j - 1) and, for
 // kernels that do not vanish at even offsets, the even taps te(j) = tap(2j) after
 // them.  Ram-Lak keeps only its centre tap, applied in FP32 in the GEMM epilogue.
+// FFT path tables: L = 2^ceil(log2(2D-1)); tw[m] = e^{-2 pi i m/L}; H[f] = the DFT of
+// the (even) taps, t(0) + 2 sum_{d=1}^{D-1} t(d) cos(2 pi f d / L), in FP64, times
+// the output scale (1/2 for fan beam) and 1/L (the inverse transform's factor).
+int ensure_fft(Plan* p) {
+    std::lock_guard<std::mutex> lock(p->mu);
+    if (p->d_fft_H) return FBP_OK;
+    const int lg = fft_length_log2(p->D);
+    if (lg > kFftMaxLog2) return FBP_EUNSUPPORTED;
+    const int L = 1 << lg;
+    std::vector<double> ctab(L);
+    std::vector<float2> tw(L);
+    for (int m = 0; m < L; ++m) {
+        const double a = 2.0 * kPi * (double)m / (double)L;
+        ctab[m] = std::cos(a);
+        tw[m] = make_float2((float)std::cos(a), (float)-std::sin(a));
+    }
+    std::vector<double> t(p->D);
+    for (int d = 0; d < p->D; ++d) t[d] = filter_tap(p->filter, d, p->dt);
+    const double scale = (p->R > 0.0 ? 0.5 : 1.0) / (double)L;
+    std::vector<float> H(L);
+    for (int f = 0; f < L; ++f) {
+        double acc = t[0];
+        for (int d = 1; d < p->D; ++d) acc += 2.0 * t[d] * ctab[(size_t)((int64_t)f * d % L)];
+        H[f] = (float)(acc * scale);
+    }
+    hipError_t e = hipMalloc(&p->d_fft_tw, sizeof(float2) * L);
+    if (e == hipSuccess) e = hipMalloc(&p->d_fft_H, sizeof(float) * L);
+    if (e == hipSuccess) e = hipMemcpy(p->d_fft_tw, tw.data(), sizeof(float2) * L, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_fft_H, H.data(), sizeof(float) * L, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (p->d_fft_tw) (void)hipFree(p->d_fft_tw);
+        if (p->d_fft_H) (void)hipFree(p->d_fft_H);
+        p->d_fft_tw = nullptr;
+        p->d_fft_H = nullptr;
+        return hip_fail(e, "FFT filter tables", FBP_ENOMEM);
+    }
+    p->fft_log2 = lg;
+    return FBP_OK;
+}
+
 int ensure_taps(Plan* p, int prec) {
+    if (prec == kFFT32) return ensure_fft(p);
     std::lock_guard<std::mutex> lock(p->mu);
     if (p->d_taps[prec]) return FBP_OK;
     const int Dhp = p->Dhp, D = p->D;
@@ -723,6 +768,22 @@ BpJob bp_job(const Plan& p, const ShapeParams& sh, const float* filt, float* img
 
 int hip_status(hipError_t e, const char* what) { return e == hipSuccess ? FBP_OK : hip_fail(e, what); }
 
+// rows x D: the GEMM in the operand precision, or the FFT path.
+hipError_t launch_filter_rows(const Plan& p, int prec, const float* in, float* out, int rows, hipStream_t s) {
+    if (prec == kFFT32) {
+        FftJob j{};
+        j.p = in;
+        j.q = out;
+        j.tw = p.d_fft_tw;
+        j.H = p.d_fft_H;
+        j.R = rows;
+        j.D = p.D;
+        j.log2L = p.fft_log2;
+        return launch_fft_filter(j, s);
+    }
+    return launch_gemm_grid(prec, gemm_job(p, prec, in, out, rows), s);
+}
+
 // Fan beam: the views are pre-weighted into the plan's scratch rows (at most
 // 64 MiB of them at a time, at least one slice) and filtered from there.
 int run_fan_filter(Plan& p, int prec, int32_t n, const float* sino, float* filt, hipStream_t s) {
@@ -744,7 +805,7 @@ int run_fan_filter(Plan& p, int prec, int32_t n, const float* sino, float* filt,
         const int64_t m = std::min<int64_t>(chunk, n - i0);
         const size_t off = (size_t)i0 * p.K * p.D;
         hipError_t e = launch_preweight(sino + off, rs.ptr, p.d_fanw, m * p.K, p.D, s);
-        if (e == hipSuccess) e = launch_gemm_grid(prec, gemm_job(p, prec, rs.ptr, filt + off, (int)(m * p.K)), s);
+        if (e == hipSuccess) e = launch_filter_rows(p, prec, rs.ptr, filt + off, (int)(m * p.K), s);
         if (e != hipSuccess) return hip_status(e, "fan-beam filter launch");
     }
     FBP_TRY_HIP(hipEventRecord(rs.free_ev, s));
@@ -755,8 +816,7 @@ int run_fan_filter(Plan& p, int prec, int32_t n, const float* sino, float* filt,
 int run_filter(Plan& p, int prec, int32_t n, const float* sino, float* filt, hipStream_t s) {
     if (n == 0) return FBP_OK;
     if (p.R > 0.0) return run_fan_filter(p, prec, n, sino, filt, s);
-    const GemmJob j = gemm_job(p, prec, sino, filt, n * p.K);
-    return hip_status(launch_gemm_grid(prec, j, s), "filter kernel launch");
+    return hip_status(launch_filter_rows(p, prec, sino, filt, n * p.K, s), "filter kernel launch");
 }
 
 int run_fan_backproject(const Plan& p, int32_t n, const float* filt, float* img, hipStream_t s) {
@@ -1052,6 +1112,7 @@ int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes,
     int rc = check_jobs(jobs, n);
     if (rc == FBP_OK) rc = check_prec(prec);
     if (rc != FBP_OK) return rc;
+    if (prec == kFFT32) return FBP_EUNSUPPORTED;     // batches filter through grouped GEMMs
     if (n == 0) return FBP_OK;
     const BatchLayout L = batch_layout(jobs, n);
     if (!ws || ws_bytes < L.total) return FBP_EWORKSPACE;
@@ -1388,7 +1449,7 @@ size_t fbp_workspace_bytes(const fbp_geom* geom, int32_t n_slices, int32_t preci
 }
 
 size_t fbp_batch_workspace_bytes(const fbp_job* jobs, int32_t n_jobs, int32_t precision) {
-    if (check_prec(precision) != FBP_OK || n_jobs < 0 || (n_jobs > 0 && !jobs)) return 0;
+    if (check_prec(precision) != FBP_OK || precision == kFFT32 || n_jobs < 0 || (n_jobs > 0 && !jobs)) return 0;
     for (int32_t i = 0; i < n_jobs; ++i)
         if (check_geom(&jobs[i].geom) != FBP_OK || is_fan(&jobs[i].geom)) return 0;
     return batch_layout(jobs, n_jobs).total;
