@@ -59,6 +59,13 @@ def load_library(path: str):
     lib.oracle_fan_fbp.argtypes = [dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_double, ctypes.c_double, dp, dp]
     lib.oracle_fan_splat.argtypes = lib.oracle_fan_fbp.argtypes
+    i32, f64 = ctypes.c_int32, ctypes.c_double
+    lib.oracle_cone_filter.argtypes = [dp, i32, i32, i32, f64, f64, f64, i32, dp]
+    lib.oracle_cone_backproject.argtypes = [dp, i32, i32, i32, i32, i32, f64, f64, f64, dp, dp]
+    lib.oracle_cone_fdk.argtypes = lib.oracle_cone_backproject.argtypes
+    lib.oracle_cone_splat.argtypes = lib.oracle_cone_backproject.argtypes
+    for fn in (lib.oracle_cone_filter, lib.oracle_cone_backproject, lib.oracle_cone_fdk, lib.oracle_cone_splat):
+        fn.restype = ctypes.c_int
     for fn in (lib.oracle_filter, lib.oracle_backproject, lib.oracle_fbp,
                lib.oracle_forward_splat, lib.oracle_filter_kind, lib.oracle_angle_weights,
                lib.oracle_backproject_weighted, lib.oracle_fan_filter, lib.oracle_fan_backproject,
@@ -287,3 +294,64 @@ def fan_splat(img, K: int, D: int, ds: float, R: float, betas) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle_fan_splat rejected its arguments")
     return sino[0] if squeeze else sino
+
+
+# ---------------------------------------------------------------- cone beam (FDK)
+# Circular source orbit at distance R, flat detector through the axis: columns
+# (u, width du) along (-sin b, cos b, 0), rows (v, width dv) along z; projections
+# [K][Dv][Du], volumes [Nz][N][N] (see the cone-beam block of fbp_oracle.c).
+
+def cone_filter(P, du: float, dv: float, R: float, kind: str = "ramlak") -> np.ndarray:
+    """Pre-weighted, half-kernel row-filtered views P[K][Dv][Du]."""
+    P = _f64(P)
+    K, Dv, Du = P.shape
+    Q = np.empty_like(P)
+    rc = _load().oracle_cone_filter(_ptr(P), K, Dv, Du, float(du), float(dv), float(R), FILTERS[kind], _ptr(Q))
+    if rc != 0:
+        raise ValueError("oracle_cone_filter rejected its arguments")
+    return Q
+
+
+def cone_backproject(Q, N: int, Nz: int, du: float, dv: float, R: float, betas) -> np.ndarray:
+    """Distance-weighted bilinear backprojection of filtered views Q[K][Dv][Du]."""
+    Q = _f64(Q)
+    K, Dv, Du = Q.shape
+    ang = _f64(betas).reshape(-1)
+    if ang.shape[0] != K:
+        raise ValueError("view count does not match the projections")
+    vol = np.empty((Nz, N, N), dtype=np.float64)
+    rc = _load().oracle_cone_backproject(_ptr(Q), K, Dv, Du, int(N), int(Nz), float(du), float(dv), float(R),
+                                         _ptr(ang), _ptr(vol))
+    if rc != 0:
+        raise ValueError("oracle_cone_backproject rejected its arguments")
+    return vol
+
+
+def cone_fdk(P, N: int, Nz: int, du: float, dv: float, R: float, betas) -> np.ndarray:
+    """FDK reconstruction (Ram-Lak) of P[K][Dv][Du]."""
+    P = _f64(P)
+    K, Dv, Du = P.shape
+    ang = _f64(betas).reshape(-1)
+    if ang.shape[0] != K:
+        raise ValueError("view count does not match the projections")
+    vol = np.empty((Nz, N, N), dtype=np.float64)
+    rc = _load().oracle_cone_fdk(_ptr(P), K, Dv, Du, int(N), int(Nz), float(du), float(dv), float(R), _ptr(ang),
+                                 _ptr(vol))
+    if rc != 0:
+        raise ValueError("oracle_cone_fdk rejected its arguments")
+    return vol
+
+
+def cone_splat(vol, K: int, Dv: int, Du: int, du: float, dv: float, R: float, betas) -> np.ndarray:
+    """Exact adjoint of :func:`cone_backproject` (tiny grids)."""
+    vol = _f64(vol)
+    Nz, N, N2 = vol.shape
+    if N != N2:
+        raise ValueError("volume slices must be square")
+    ang = _f64(betas).reshape(-1)
+    proj = np.empty((K, Dv, Du), dtype=np.float64)
+    rc = _load().oracle_cone_splat(_ptr(vol), int(K), int(Dv), int(Du), N, Nz, float(du), float(dv), float(R),
+                                   _ptr(ang), _ptr(proj))
+    if rc != 0:
+        raise ValueError("oracle_cone_splat rejected its arguments")
+    return proj

@@ -463,3 +463,148 @@ int oracle_fan_splat(const double* img, int32_t n_slices, int32_t K, int32_t D, 
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------ cone beam (FDK)
+ *
+ * Circular cone-beam geometry with a flat detector (Feldkamp, Davis & Kress
+ * 1984; Kak & Slaney 1988, ch. 3), the 3D extension of the fan beam above:
+ *   - the source of view k sits at S = (R cos b_k, R sin b_k, 0);
+ *   - the detector is the virtual plane through the rotation axis perpendicular
+ *     to the central ray, with axes e = (-sin b_k, cos b_k, 0) (columns) and
+ *     (0, 0, 1) (rows); column i sits at s_i = (i - (Du-1)/2) du, row j at
+ *     z_j = (j - (Dv-1)/2) dv;
+ *   - voxel (p, r, c) of an Nz x N x N volume sits at x = c - (N-1)/2,
+ *     y = r - (N-1)/2, z = p - (Nz-1)/2 (unit voxels);
+ *   - a point X at depth L = R - (x cos b + y sin b) is seen at
+ *     s = R (x, y) . e / L and z' = R z / L.
+ * The reconstruction (FDK):
+ *   1. pre-weight   P'[k][j][i] = P[k][j][i] R / sqrt(R^2 + s_i^2 + z_j^2);
+ *   2. filter every detector row along the columns with half the kernel (as the
+ *      fan beam, bin width du);
+ *   3. backproject  vol(X) = (2 pi / K) sum_k (R/L)^2 Q~_k(s/du + (Du-1)/2, z'/dv + (Dv-1)/2)
+ *      with bilinear interpolation, zero beyond the detector.
+ * Projections are [K][Dv][Du]; the source must stay outside the volume's
+ * cylinder: R > N / sqrt(2).
+ */
+
+/* Steps 1-2 on n_views views [n_views][Dv][Du]. */
+int oracle_cone_filter(const double* P, int32_t n_views, int32_t Dv, int32_t Du, double du, double dv, double R,
+                       int32_t kind, double* Q) {
+    if (!P || !Q || n_views < 0 || Dv < 1 || Du < 1 || !(du > 0.0) || !isfinite(du) || !(dv > 0.0) ||
+        !isfinite(dv) || !(R > 0.0) || !isfinite(R) || kind < 0 || kind > 2)
+        return -1;
+    int64_t row;
+    const int64_t n_rows = (int64_t)n_views * Dv;
+#pragma omp parallel for schedule(static)
+    for (row = 0; row < n_rows; ++row) {
+        const int32_t j = (int32_t)(row % Dv);
+        const double zj = ((double)j - 0.5 * (double)(Dv - 1)) * dv;
+        const double* p = P + row * (int64_t)Du;
+        double* q = Q + row * (int64_t)Du;
+        for (int32_t n = 0; n < Du; ++n) {
+            double acc = 0.0;
+            for (int32_t m = 0; m < Du; ++m) {
+                const double sm = ((double)m - 0.5 * (double)(Du - 1)) * du;
+                const double w = R / sqrt(R * R + sm * sm + zj * zj);
+                acc += 0.5 * filter_tap(kind, (int64_t)n - m, du) * (w * p[m]);
+            }
+            q[n] = du * acc;
+        }
+    }
+    return 0;
+}
+
+/* Detector value at (column i, row j), zero off the detector. */
+static double qcone(const double* q, int32_t Dv, int32_t Du, int64_t i, int64_t j) {
+    return (i >= 0 && i < Du && j >= 0 && j < Dv) ? q[j * (int64_t)Du + i] : 0.0;
+}
+
+/* Step 3: Q is [K][Dv][Du] filtered views, vol is [Nz][N][N]. */
+int oracle_cone_backproject(const double* Q, int32_t K, int32_t Dv, int32_t Du, int32_t N, int32_t Nz, double du,
+                            double dv, double R, const double* betas, double* vol) {
+    if (!Q || !vol || !betas || K < 1 || Dv < 1 || Du < 1 || N < 1 || Nz < 1 || !(du > 0.0) || !isfinite(du) ||
+        !(dv > 0.0) || !isfinite(dv) || !fan_args_ok(N, R))
+        return -1;
+    const double cu = 0.5 * (double)(Du - 1), cv = 0.5 * (double)(Dv - 1);
+    const double centre_pix = 0.5 * (double)(N - 1), centre_z = 0.5 * (double)(Nz - 1);
+    const double weight = 2.0 * kPi / (double)K;
+    int64_t pr;
+    const int64_t n_rows = (int64_t)Nz * N;
+#pragma omp parallel for schedule(static)
+    for (pr = 0; pr < n_rows; ++pr) {
+        const int32_t p = (int32_t)(pr / N);
+        const int32_t r = (int32_t)(pr % N);
+        const double z = (double)p - centre_z, y = (double)r - centre_pix;
+        double* out = vol + pr * (int64_t)N;
+        for (int32_t c = 0; c < N; ++c) {
+            const double x = (double)c - centre_pix;
+            double acc = 0.0;
+            for (int32_t k = 0; k < K; ++k) {
+                const double cb = cos(betas[k]), sb = sin(betas[k]);
+                const double L = R - (x * cb + y * sb);
+                const double u = R * (-x * sb + y * cb) / L / du + cu;
+                const double v = R * z / L / dv + cv;
+                const double fi = floor(u), fj = floor(v);
+                const double a = u - fi, bb = v - fj;
+                const int64_t i = (int64_t)fi, j = (int64_t)fj;
+                const double* q = Q + (int64_t)k * Dv * Du;
+                const double val = (1.0 - a) * (1.0 - bb) * qcone(q, Dv, Du, i, j) +
+                                   a * (1.0 - bb) * qcone(q, Dv, Du, i + 1, j) +
+                                   (1.0 - a) * bb * qcone(q, Dv, Du, i, j + 1) +
+                                   a * bb * qcone(q, Dv, Du, i + 1, j + 1);
+                acc += (R / L) * (R / L) * val;
+            }
+            out[c] = weight * acc;
+        }
+    }
+    return 0;
+}
+
+/* Steps 1-3 (Ram-Lak). */
+int oracle_cone_fdk(const double* P, int32_t K, int32_t Dv, int32_t Du, int32_t N, int32_t Nz, double du, double dv,
+                    double R, const double* betas, double* vol) {
+    if (!P || !vol || !betas || K < 1 || Dv < 1 || Du < 1) return -1;
+    const size_t count = (size_t)K * (size_t)Dv * (size_t)Du;
+    double* Q = (double*)malloc(sizeof(double) * count);
+    if (!Q) return -1;
+    int rc = oracle_cone_filter(P, K, Dv, Du, du, dv, R, 0, Q);
+    if (rc == 0) rc = oracle_cone_backproject(Q, K, Dv, Du, N, Nz, du, dv, R, betas, vol);
+    free(Q);
+    return rc;
+}
+
+/* Adjoint of oracle_cone_backproject, from its own definition (tiny grids):
+ *   proj[k][j][i] = (2 pi / K) sum_X vol(X) (R/L)^2 max(0, 1 - |u - i|) max(0, 1 - |v - j|). */
+int oracle_cone_splat(const double* vol, int32_t K, int32_t Dv, int32_t Du, int32_t N, int32_t Nz, double du,
+                      double dv, double R, const double* betas, double* proj) {
+    if (!vol || !proj || !betas || K < 1 || Dv < 1 || Du < 1 || N < 1 || Nz < 1 || !(du > 0.0) || !(dv > 0.0) ||
+        !fan_args_ok(N, R))
+        return -1;
+    const double cu = 0.5 * (double)(Du - 1), cv = 0.5 * (double)(Dv - 1);
+    const double centre_pix = 0.5 * (double)(N - 1), centre_z = 0.5 * (double)(Nz - 1);
+    const double weight = 2.0 * kPi / (double)K;
+    int64_t kj;
+    const int64_t n_rows = (int64_t)K * Dv;
+#pragma omp parallel for schedule(static)
+    for (kj = 0; kj < n_rows; ++kj) {
+        const int32_t k = (int32_t)(kj / Dv), j = (int32_t)(kj % Dv);
+        const double cb = cos(betas[k]), sb = sin(betas[k]);
+        for (int32_t i = 0; i < Du; ++i) {
+            double acc = 0.0;
+            for (int32_t p = 0; p < Nz; ++p)
+                for (int32_t r = 0; r < N; ++r)
+                    for (int32_t c = 0; c < N; ++c) {
+                        const double x = (double)c - centre_pix, y = (double)r - centre_pix;
+                        const double z = (double)p - centre_z;
+                        const double L = R - (x * cb + y * sb);
+                        const double u = R * (-x * sb + y * cb) / L / du + cu;
+                        const double v = R * z / L / dv + cv;
+                        const double wu = 1.0 - fabs(u - (double)i), wv = 1.0 - fabs(v - (double)j);
+                        if (wu > 0.0 && wv > 0.0)
+                            acc += (R / L) * (R / L) * wu * wv * vol[((int64_t)p * N + r) * N + c];
+                    }
+            proj[kj * (int64_t)Du + i] = weight * acc;
+        }
+    }
+    return 0;
+}

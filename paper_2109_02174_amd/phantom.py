@@ -239,3 +239,97 @@ def fan_slice(config_id: int, slice_id: int, N: int, K: int, D: int, ds: float, 
     b = np.arange(K, dtype=np.float64) * (2.0 * math.pi / K) if betas is None else np.asarray(betas, np.float64)
     sino = ellipse_fan_sinogram(ells, N, D, ds, R, b)
     return SliceInput(sino, rasterise(ells, N), tuple(ells), N, K, D, ds, b)
+
+
+# ---------------------------------------------------------------- cone beam (3D)
+# Circular orbit: source at (R cos b, R sin b, 0); flat detector through the axis,
+# columns along (-sin b, cos b, 0) at s_i = (i - (Du-1)/2) du, rows along z at
+# z_j = (j - (Dv-1)/2) dv; volume voxel (p, r, c) at (c - (N-1)/2, r - (N-1)/2,
+# p - (Nz-1)/2) in voxel units.
+
+@dataclass(frozen=True)
+class Ellipsoid:
+    cx: float
+    cy: float
+    cz: float
+    a: float
+    b: float
+    c: float
+    phi: float      # rotation about z
+    rho: float
+
+
+def draw_ellipsoids(rng: np.random.Generator, n: int) -> list:
+    """n ellipsoids in normalised units (the volume spans [-1, 1]^3)."""
+    out = []
+    for _ in range(n):
+        cx, cy, cz = rng.uniform(-0.5, 0.5, 3)
+        a, b, c = rng.uniform(0.08, 0.4, 3)
+        out.append(Ellipsoid(float(cx), float(cy), float(cz), float(a), float(b), float(c),
+                             float(rng.uniform(0.0, math.pi)), float(rng.uniform(-0.5, 1.0))))
+    return out
+
+
+def cone_rays(R: float, Dv: int, Du: int, du: float, dv: float, betas):
+    """Source points [K][3] and unit ray directions [K][Dv][Du][3]."""
+    b = np.asarray(betas, dtype=np.float64).reshape(-1)
+    S = np.stack([R * np.cos(b), R * np.sin(b), np.zeros_like(b)], axis=-1)
+    e = np.stack([-np.sin(b), np.cos(b), np.zeros_like(b)], axis=-1)
+    s = detector_coords(Du, du)
+    z = detector_coords(Dv, dv)
+    P = (e[:, None, None, :] * s[None, None, :, None] +
+         np.array([0.0, 0.0, 1.0])[None, None, None, :] * z[None, :, None, None])
+    d = P - S[:, None, None, :]
+    d /= np.linalg.norm(d, axis=-1, keepdims=True)
+    return S, d
+
+
+def ellipsoid_cone_projections(ellipsoids, N: int, Nz: int, Dv: int, Du: int, du: float, dv: float, R: float,
+                               betas) -> np.ndarray:
+    """Exact cone-beam line integrals [K][Dv][Du] (voxel units) of a sum of ellipsoids:
+    each ray is mapped into the ellipsoid's unit-sphere frame, where the chord length
+    follows from a quadratic."""
+    S, d = cone_rays(R, Dv, Du, du, dv, betas)
+    half = 0.5 * N
+    out = np.zeros(d.shape[:3], dtype=np.float64)
+    for el in ellipsoids:
+        C = np.array([el.cx * half, el.cy * half, el.cz * half])
+        cph, sph = math.cos(el.phi), math.sin(el.phi)
+        rot_t = np.array([[cph, sph, 0.0], [-sph, cph, 0.0], [0.0, 0.0, 1.0]])   # world -> body
+        scale = np.array([1.0 / (el.a * half), 1.0 / (el.b * half), 1.0 / (el.c * half)])
+        Y0 = (rot_t @ (S - C).T).T * scale                      # [K][3]
+        Dy = np.einsum("ij,kvuj->kvui", rot_t, d) * scale       # [K][Dv][Du][3]
+        aa = np.sum(Dy * Dy, axis=-1)
+        bb = np.sum(Dy * Y0[:, None, None, :], axis=-1)
+        cc = np.sum(Y0 * Y0, axis=-1)[:, None, None] - 1.0
+        disc = bb * bb - aa * cc
+        out += np.where(disc > 0.0, el.rho * 2.0 * np.sqrt(np.maximum(disc, 0.0)) / aa, 0.0)
+    return out
+
+
+def ball_cone_projections(radius: float, rho: float, Dv: int, Du: int, du: float, dv: float, R: float, betas,
+                          centre=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Cone-beam projections of a uniform ball: 2 rho sqrt(radius^2 - dist^2) along each ray."""
+    S, d = cone_rays(R, Dv, Du, du, dv, betas)
+    C = np.asarray(centre, dtype=np.float64)
+    w = C[None, :] - S                                           # source -> centre
+    t = np.sum(d * w[:, None, None, :], axis=-1)
+    dist2 = np.sum(w * w, axis=-1)[:, None, None] - t * t
+    rad = radius * radius - dist2
+    return np.where(rad > 0.0, 2.0 * rho * np.sqrt(np.maximum(rad, 0.0)), 0.0)
+
+
+def rasterise_volume(ellipsoids, N: int, Nz: int) -> np.ndarray:
+    """Voxel-centre samples [Nz][N][N] of the ellipsoid phantom."""
+    half = 0.5 * N
+    x = (np.arange(N, dtype=np.float64) - 0.5 * (N - 1)).reshape(1, 1, -1)
+    y = (np.arange(N, dtype=np.float64) - 0.5 * (N - 1)).reshape(1, -1, 1)
+    z = (np.arange(Nz, dtype=np.float64) - 0.5 * (Nz - 1)).reshape(-1, 1, 1)
+    vol = np.zeros((Nz, N, N), dtype=np.float64)
+    for el in ellipsoids:
+        dx, dy, dz = x - el.cx * half, y - el.cy * half, z - el.cz * half
+        u = dx * math.cos(el.phi) + dy * math.sin(el.phi)
+        v = -dx * math.sin(el.phi) + dy * math.cos(el.phi)
+        vol += np.where((u / (el.a * half)) ** 2 + (v / (el.b * half)) ** 2 + (dz / (el.c * half)) ** 2 <= 1.0,
+                        el.rho, 0.0)
+    return vol

@@ -63,6 +63,16 @@ MUTANTS = [
     ("fan depth sign", "const double L = R - (x * cb + y * sb);", "const double L = R + (x * cb + y * sb);"),
     ("fan weight pi/K", "weights[k] : 2.0 * kPi / (double)K;", "weights[k] : kPi / (double)K;"),
     ("fan coordinate not divided by ds", "const double u = sx / ds + centre_det;", "const double u = sx + centre_det;"),
+    ("cone pre-weight without the row", "sqrt(R * R + sm * sm + zj * zj)", "sqrt(R * R + sm * sm)"),
+    ("cone filter without the half", "acc += 0.5 * filter_tap(kind, (int64_t)n - m, du)",
+     "acc += filter_tap(kind, (int64_t)n - m, du)"),
+    ("cone row not magnified", "const double v = R * z / L / dv + cv;", "const double v = z / dv + cv;"),
+    ("cone row sign", "const double v = R * z / L / dv + cv;", "const double v = -R * z / L / dv + cv;"),
+    ("cone bilinear corner", "a * bb * qcone(q, Dv, Du, i + 1, j + 1)", "a * bb * qcone(q, Dv, Du, i + 1, j)"),
+    ("cone detector transposed", "q[j * (int64_t)Du + i]", "q[i * (int64_t)Dv + j]"),
+    ("cone weight pi/K", "centre_z = 0.5 * (double)(Nz - 1);\n    const double weight = 2.0 * kPi / (double)K;",
+     "centre_z = 0.5 * (double)(Nz - 1);\n    const double weight = kPi / (double)K;"),
+    ("cone magnification to the first power", "acc += (R / L) * (R / L) * val;", "acc += (R / L) * val;"),
 ]
 
 

@@ -515,3 +515,95 @@ def test_fan_ellipse_phantom_is_recovered():
     e_fan = np.sqrt(np.mean((img - sl.phantom) ** 2))
     e_par = np.sqrt(np.mean((par - sl.phantom) ** 2))
     assert e_fan < 1.3 * e_par + 1e-3 * sl.value_range
+
+
+# ---------------------------------------------------------------- cone beam (FDK)
+# Source at (R cos b, R sin b, 0); flat detector through the axis, columns along
+# (-sin b, cos b, 0), rows along z (Feldkamp, Davis & Kress 1984).
+
+def test_cone_central_slice_is_the_fan_beam():
+    """On the orbit plane (z = 0, odd Nz and Dv) the pre-weight, the row filter and
+    the backprojection reduce to the fan beam of the central detector row."""
+    K, Dv, Du, N, Nz, du, dv, R = 20, 7, 41, 16, 5, 0.8, 1.1, 30.0
+    rng = ph.rng_for(3100, 0)
+    P = rng.normal(size=(K, Dv, Du))
+    b = rng.uniform(0.0, 2.0 * math.pi, K)
+    vol = oracle.cone_fdk(P, N, Nz, du, dv, R, b)
+    fan = oracle.fan_fbp(P[:, Dv // 2, :], N, du, R, b)
+    assert np.allclose(vol[Nz // 2], fan, rtol=1e-12, atol=1e-12)
+
+
+def test_cone_filter_weights_each_ray_by_its_cosine():
+    """Filter step: each detector value times the cosine of its ray's angle to the
+    central ray (numpy dot products of the two directions), then half the parallel
+    filter along every row."""
+    K, Dv, Du, du, dv, R = 3, 5, 29, 0.9, 1.3, 22.0
+    P = ph.rng_for(3101, 0).normal(size=(K, Dv, Du))
+    s = ph.detector_coords(Du, du)
+    z = ph.detector_coords(Dv, dv)
+    S = np.array([R, 0.0, 0.0])                         # view b = 0: detector axes (0,1,0), (0,0,1)
+    cosang = np.empty((Dv, Du))
+    for j in range(Dv):
+        for i in range(Du):
+            ray = np.array([0.0, s[i], z[j]]) - S
+            cosang[j, i] = np.dot(ray, -S) / (np.linalg.norm(ray) * np.linalg.norm(S))
+    ref = 0.5 * oracle.filter_rows((P * cosang[None]).reshape(K * Dv, Du), du).reshape(K, Dv, Du)
+    assert np.allclose(oracle.cone_filter(P, du, dv, R), ref, rtol=1e-12, atol=1e-12)
+
+
+def test_cone_backprojection_geometry():
+    """Views linear in the column and row indices (exact under bilinear interpolation
+    inside the detector) backproject to sum_k (2 pi/K) (R/L)^2 (u + 3 v), with the
+    detector coordinates and the depth from intersecting the ray source -> voxel with
+    the detector plane (numpy.linalg.solve)."""
+    K, Dv, Du, N, Nz, du, dv, R = 5, 61, 71, 6, 5, 0.5, 0.4, 14.0
+    b = ph.rng_for(3102, 0).uniform(0.0, 2.0 * math.pi, K)
+    jj, ii = np.meshgrid(np.arange(Dv, dtype=np.float64), np.arange(Du, dtype=np.float64), indexing="ij")
+    Q = np.tile((ii + 3.0 * jj)[None], (K, 1, 1))
+    got = oracle.cone_backproject(Q, N, Nz, du, dv, R, b)
+    cxy = np.arange(N) - 0.5 * (N - 1)
+    cz = np.arange(Nz) - 0.5 * (Nz - 1)
+    ref = np.zeros((Nz, N, N))
+    for p in range(Nz):
+        for r in range(N):
+            for c in range(N):
+                X = np.array([cxy[c], cxy[r], cz[p]])
+                for bk in b:
+                    S = np.array([R * math.cos(bk), R * math.sin(bk), 0.0])
+                    e = np.array([-math.sin(bk), math.cos(bk), 0.0])
+                    ez = np.array([0.0, 0.0, 1.0])
+                    lam, mu, nu = np.linalg.solve(np.column_stack([X - S, -e, -ez]), -S)
+                    L = np.dot(X - S, -S) / R
+                    u = mu / du + 0.5 * (Du - 1)
+                    v = nu / dv + 0.5 * (Dv - 1)
+                    assert 0.0 <= u <= Du - 1 and 0.0 <= v <= Dv - 1
+                    ref[p, r, c] += (2.0 * math.pi / K) * (R / L) ** 2 * (u + 3.0 * v)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-9)
+
+
+def test_cone_splat_is_adjoint_of_backprojection():
+    K, Dv, Du, N, Nz, du, dv, R = 4, 7, 9, 4, 3, 0.9, 1.1, 6.0
+    rng = ph.rng_for(3103, 0)
+    b = rng.uniform(0.0, 2.0 * math.pi, K)
+    x = rng.normal(size=(Nz, N, N))
+    y = rng.normal(size=(K, Dv, Du))
+    lhs = float(np.sum(oracle.cone_splat(x, K, Dv, Du, du, dv, R, b) * y))
+    rhs = float(np.sum(x * oracle.cone_backproject(y, N, Nz, du, dv, R, b)))
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1.0)
+
+
+def test_cone_ball_reconstructs_its_density():
+    """A centred ball of density 1.5 from exact cone-beam projections: FDK recovers
+    the density inside, on and off the orbit plane (small cone angle: the FDK
+    approximation error stays below the tolerance)."""
+    N, Nz, K, Dv, Du, du, dv = 40, 25, 240, 41, 81, 0.75, 0.75
+    R = 2.0 * N / math.sqrt(2.0)
+    b = np.arange(K) * (2.0 * math.pi / K)
+    P = ph.ball_cone_projections(12.0, 1.5, Dv, Du, du, dv, R, b)
+    vol = oracle.cone_fdk(P, N, Nz, du, dv, R, b)
+    cxy = np.arange(N) - 0.5 * (N - 1)
+    cz = np.arange(Nz) - 0.5 * (Nz - 1)
+    rr = np.sqrt(cz[:, None, None] ** 2 + cxy[None, :, None] ** 2 + cxy[None, None, :] ** 2)
+    inside = rr < 9.0
+    assert abs(np.mean(vol[inside]) - 1.5) < 0.015 and np.max(np.abs(vol[inside] - 1.5)) < 0.08
+    assert np.max(np.abs(vol[rr > 16.0])) < 0.2
