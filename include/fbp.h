@@ -242,6 +242,55 @@ const char* fbp_last_error(void);
 /* Library version string. */
 const char* fbp_version(void);
 
+/* ------------------------------------------------------------------ cone beam (FDK)
+ *
+ * Circular cone-beam geometry with a flat detector (the 3D extension of the fan
+ * beam; Feldkamp, Davis & Kress 1984; Kak & Slaney 1988, ch. 3): view k has its
+ * source at (R cos b_k, R sin b_k, 0); the detector is the plane through the
+ * rotation axis perpendicular to the central ray, column i at
+ * s_i = (i - (Du-1)/2) du along (-sin b_k, cos b_k, 0), row j at
+ * z_j = (j - (Dv-1)/2) dv along z.  Voxel (p, r, c) of the Nz x N x N volume
+ * sits at (c - (N-1)/2, r - (N-1)/2, p - (Nz-1)/2) in voxel units.
+ * Projections are [K][Dv][Du] (device, FP32), volumes [Nz][N][N].
+ */
+typedef struct {
+    int32_t n_views;          /* K >= 1: source angles, spread over a full turn */
+    int32_t n_det_u;          /* Du >= 1 detector columns */
+    int32_t n_det_v;          /* Dv >= 1 detector rows */
+    int32_t volume_size;      /* N >= 1 */
+    int32_t volume_depth;     /* Nz >= 1 */
+    int32_t filter;           /* fbp_filter_kind */
+    double det_spacing_u;     /* du > 0, finite */
+    double det_spacing_v;     /* dv > 0, finite */
+    double source_distance;   /* R > N / sqrt(2), finite */
+    const double* angles;     /* host array of K finite radians; copied into the plan */
+} fbp_cone_geom;
+
+/*
+ * FDK steps 1-2: d_filtered[k][j][n] = du * sum_m (h(n-m)/2) * d_proj[k][j][m] R / sqrt(R^2 + s_m^2 + z_j^2)
+ * (pre-weight through a scratch buffer owned by the plan, calls ordered on the
+ * device; then the FP32 filter GEMM over the K*Dv detector rows).  No overlap.
+ */
+int fbp_cone_filter(const fbp_cone_geom* geom, const float* d_proj, float* d_filtered, void* hip_stream);
+
+/*
+ * FDK step 3: d_volume(X) = (2 pi / K) sum_k (R/L_k)^2 Q~_k(u, v) with bilinear
+ * interpolation (zero off the detector), L_k = R - (x cos b_k + y sin b_k),
+ * u = R (-x sin b_k + y cos b_k) / (L_k du) + (Du-1)/2, v = R z / (L_k dv) + (Dv-1)/2.
+ * Workgroups own 16 x 16 columns x 32 slices, stage detector windows in LDS,
+ * sum the views in a fixed order (deterministic, no atomics).  No overlap.
+ */
+int fbp_cone_backproject(const fbp_cone_geom* geom, const float* d_filtered, float* d_volume,
+                         void* hip_stream);
+
+/* fbp_cone_backproject(fbp_cone_filter(d_proj)) with the filtered views in the
+ * caller's workspace (fbp_cone_workspace_bytes, 256-byte aligned, no overlap). */
+int fbp_cone_reconstruct(const fbp_cone_geom* geom, const float* d_proj, float* d_volume, void* d_workspace,
+                         size_t workspace_bytes, void* hip_stream);
+
+/* Workspace bytes fbp_cone_reconstruct needs (0 on invalid arguments). */
+size_t fbp_cone_workspace_bytes(const fbp_cone_geom* geom);
+
 #ifdef __cplusplus
 }
 #endif

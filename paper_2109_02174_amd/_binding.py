@@ -48,6 +48,13 @@ class c_geom(ctypes.Structure):
                 ("source_distance", ctypes.c_double)]
 
 
+class c_cone_geom(ctypes.Structure):
+    _fields_ = [("n_views", ctypes.c_int32), ("n_det_u", ctypes.c_int32), ("n_det_v", ctypes.c_int32),
+                ("volume_size", ctypes.c_int32), ("volume_depth", ctypes.c_int32), ("filter", ctypes.c_int32),
+                ("det_spacing_u", ctypes.c_double), ("det_spacing_v", ctypes.c_double),
+                ("source_distance", ctypes.c_double), ("angles", ctypes.POINTER(ctypes.c_double))]
+
+
 class c_job(ctypes.Structure):
     _fields_ = [("geom", c_geom), ("sino", ctypes.c_void_p), ("image", ctypes.c_void_p)]
 
@@ -70,6 +77,10 @@ def load():
         "fbp_filter": (ctypes.c_int, [G, i32, vp, vp, i32, vp]),
         "fbp_backproject": (ctypes.c_int, [G, i32, vp, vp, vp]),
         "fbp_project": (ctypes.c_int, [G, i32, vp, vp, vp]),
+        "fbp_cone_filter": (ctypes.c_int, [ctypes.POINTER(c_cone_geom), vp, vp, vp]),
+        "fbp_cone_backproject": (ctypes.c_int, [ctypes.POINTER(c_cone_geom), vp, vp, vp]),
+        "fbp_cone_reconstruct": (ctypes.c_int, [ctypes.POINTER(c_cone_geom), vp, vp, vp, sz, vp]),
+        "fbp_cone_workspace_bytes": (sz, [ctypes.POINTER(c_cone_geom)]),
         "fbp_reconstruct": (ctypes.c_int, [G, i32, vp, vp, vp, sz, i32, vp]),
         "fbp_workspace_bytes": (sz, [G, i32, i32]),
         "fbp_reconstruct_batch": (ctypes.c_int, [ctypes.POINTER(c_job), i32, vp, sz, i32, vp]),
@@ -328,3 +339,89 @@ def fbp_plan_stack_config(geom: Geometry) -> int:
     if rc < 0:
         raise FbpError(rc, "fbp_plan_stack_config")
     return rc
+
+
+# ---------------------------------------------------------------- cone beam (FDK)
+
+@dataclass
+class ConeGeometry:
+    """Circular cone-beam geometry: K source angles (default: a full turn), a flat
+    detector of Dv rows x Du columns (spacings dv, du) through the rotation axis,
+    source distance R > N/sqrt(2), an Nz x N x N volume, and the filter kernel."""
+    n_views: int
+    n_det_u: int
+    n_det_v: int
+    volume_size: int
+    volume_depth: int
+    source_distance: float
+    det_spacing_u: float = 1.0
+    det_spacing_v: float = 1.0
+    angles: np.ndarray = field(default=None)
+    filter: str = "ramlak"
+
+    def __post_init__(self):
+        if self.angles is None:
+            self.angles = np.arange(self.n_views, dtype=np.float64) * (2.0 * np.pi / self.n_views)
+        self.angles = np.ascontiguousarray(self.angles, dtype=np.float64)
+
+    def as_c(self) -> c_cone_geom:
+        g = c_cone_geom(int(self.n_views), int(self.n_det_u), int(self.n_det_v), int(self.volume_size),
+                        int(self.volume_depth),
+                        FILTERS.get(self.filter, -1) if isinstance(self.filter, str) else int(self.filter),
+                        float(self.det_spacing_u), float(self.det_spacing_v), float(self.source_distance),
+                        self.angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        g._keep = self.angles
+        return g
+
+    def proj_shape(self):
+        return (self.n_views, self.n_det_v, self.n_det_u)
+
+    def volume_shape(self):
+        return (self.volume_depth, self.volume_size, self.volume_size)
+
+
+def fbp_cone_filter(geom: ConeGeometry, proj, out=None, stream=None):
+    """FDK pre-weighting and row filter: projections [K][Dv][Du] -> filtered views."""
+    import torch
+    _check_tensor(proj, geom.proj_shape(), "proj")
+    if out is None:
+        out = torch.empty(geom.proj_shape(), dtype=torch.float32, device=proj.device)
+    _check_tensor(out, geom.proj_shape(), "out")
+    g = geom.as_c()
+    _raise(load().fbp_cone_filter(ctypes.byref(g), proj.data_ptr(), out.data_ptr(), _stream_ptr(stream)),
+           "fbp_cone_filter")
+    return out
+
+
+def fbp_cone_backproject(geom: ConeGeometry, filtered, out=None, stream=None):
+    """FDK distance-weighted bilinear backprojection: filtered views -> volume [Nz][N][N]."""
+    import torch
+    _check_tensor(filtered, geom.proj_shape(), "filtered")
+    if out is None:
+        out = torch.empty(geom.volume_shape(), dtype=torch.float32, device=filtered.device)
+    _check_tensor(out, geom.volume_shape(), "out")
+    g = geom.as_c()
+    _raise(load().fbp_cone_backproject(ctypes.byref(g), filtered.data_ptr(), out.data_ptr(), _stream_ptr(stream)),
+           "fbp_cone_backproject")
+    return out
+
+
+def fbp_cone_workspace_bytes(geom: ConeGeometry) -> int:
+    g = geom.as_c()
+    return int(load().fbp_cone_workspace_bytes(ctypes.byref(g)))
+
+
+def fbp_cone_reconstruct(geom: ConeGeometry, proj, out=None, workspace=None, stream=None):
+    """FDK reconstruction of projections [K][Dv][Du] into a volume [Nz][N][N]."""
+    import torch
+    _check_tensor(proj, geom.proj_shape(), "proj")
+    if out is None:
+        out = torch.empty(geom.volume_shape(), dtype=torch.float32, device=proj.device)
+    _check_tensor(out, geom.volume_shape(), "out")
+    if workspace is None:
+        workspace = alloc_workspace(fbp_cone_workspace_bytes(geom), proj.device)
+    g = geom.as_c()
+    rc = load().fbp_cone_reconstruct(ctypes.byref(g), proj.data_ptr(), out.data_ptr(), workspace.data_ptr(),
+                                     workspace.numel() * workspace.element_size(), _stream_ptr(stream))
+    _raise(rc, "fbp_cone_reconstruct")
+    return out

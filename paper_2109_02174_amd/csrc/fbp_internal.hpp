@@ -192,6 +192,34 @@ hipError_t launch_fan_bp(const FanJob& job, int n_slices, int M, int KBm, hipStr
 // out[r][m] = in[r][m] * w[m] over rows x D floats.
 hipError_t launch_preweight(const float* in, float* out, const float* w, int64_t rows, int D, hipStream_t stream);
 
+// ------------------------------------------------------------------ cone beam (FDK)
+
+// Cone-beam backprojection of one geometry: projections [K][Dv][Du], volume
+// [Nz][N][N], source orbit of radius R, flat detector through the axis.
+struct ConeJob {
+    const float* q;        // [K][Dv][Du] filtered views
+    float* vol;            // [Nz][N][N]
+    const double* cs;      // [K][2]: cos b, sin b (FP64)
+    double R, du, dv;
+    double inv_R, inv_duR; // 1/R, 1/(du R)
+    double half_span;      // bound on |u - u(tile centre)| over a tile's columns, in detector columns
+    double cu, cv;         // (Du-1)/2, (Dv-1)/2
+    double half_pix;       // (N-1)/2
+    double half_z;         // (Nz-1)/2
+    int32_t N, Nz, K, Du, Dv;
+    int32_t WL, WV;        // staged window: columns, rows (bounds over tiles, z blocks and views)
+    int32_t KB;            // views per staged block
+    int32_t tiles_x;       // ceil(N / kConeTile)
+    float scale;           // 2 pi / K
+};
+constexpr int kConeTile = 16;
+constexpr int kConeZB = 32;          // voxels in z per lane
+constexpr size_t kConeLdsBudget = 48 * 1024;
+size_t cone_lds_bytes(int KB, int WL, int WV, bool staged);
+// staged: detector windows through LDS (KB views of (WV+1) x (WL+1) values must
+// fit kConeLdsBudget); otherwise values are read from global memory.
+hipError_t launch_cone_bp(const ConeJob& job, bool staged, hipStream_t stream);
+
 // ------------------------------------------------------------------ ramp filter GEMM
 
 enum Prec : int32_t { kFP32 = 0, kBF16 = 1, kFP16 = 2 };

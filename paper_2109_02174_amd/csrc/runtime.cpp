@@ -1409,6 +1409,229 @@ int autotune(const fbp_geom* g, hipStream_t s, int32_t* out_cfg) {
     return FBP_OK;
 }
 
+// ------------------------------------------------------------------ cone beam (FDK)
+
+int check_cone_geom(const fbp_cone_geom* g) {
+    if (!g) return FBP_EINVAL;
+    if (g->n_views < 1 || g->n_det_u < 1 || g->n_det_v < 1 || g->volume_size < 1 || g->volume_depth < 1)
+        return FBP_EINVAL;
+    if (!std::isfinite(g->det_spacing_u) || !(g->det_spacing_u > 0.0)) return FBP_EINVAL;
+    if (!std::isfinite(g->det_spacing_v) || !(g->det_spacing_v > 0.0)) return FBP_EINVAL;
+    if (!g->angles) return FBP_EINVAL;
+    for (int32_t k = 0; k < g->n_views; ++k)
+        if (!std::isfinite(g->angles[k])) return FBP_EINVAL;
+    if (g->filter < FBP_FILTER_RAMLAK || g->filter > FBP_FILTER_HANN) return FBP_EINVAL;
+    const double R = g->source_distance;
+    if (!std::isfinite(R) || !(R > 0.70710678118654752 * (double)g->volume_size)) return FBP_EINVAL;
+    if (g->n_det_u > kMaxDet || g->n_det_v > kMaxDet || g->volume_size > kMaxImage ||
+        g->volume_depth > kMaxImage || g->n_views > kMaxAngles)
+        return FBP_EUNSUPPORTED;
+    if ((int64_t)g->n_views * g->n_det_v > INT32_MAX) return FBP_EUNSUPPORTED;
+    return FBP_OK;
+}
+
+size_t cone_proj_bytes(const fbp_cone_geom* g) {
+    return sizeof(float) * (size_t)g->n_views * (size_t)g->n_det_v * (size_t)g->n_det_u;
+}
+size_t cone_vol_bytes(const fbp_cone_geom* g) {
+    return sizeof(float) * (size_t)g->volume_depth * (size_t)g->volume_size * (size_t)g->volume_size;
+}
+
+struct ConeKey {
+    int device, K, Du, Dv, N, Nz, filter;
+    uint64_t du_bits, dv_bits, r_bits, angle_hash;
+    bool operator<(const ConeKey& o) const {
+        return std::tie(device, K, Du, Dv, N, Nz, filter, du_bits, dv_bits, r_bits, angle_hash) <
+               std::tie(o.device, o.K, o.Du, o.Dv, o.N, o.Nz, o.filter, o.du_bits, o.dv_bits, o.r_bits, o.angle_hash);
+    }
+};
+
+// Plan of one cone-beam geometry: the row filter's taps (a one-angle parallel-beam
+// plan over the Du columns), FP64 (cos b, sin b), FP32 pre-weights
+// R / sqrt(R^2 + s^2 + z^2) per detector cell, the staged window bounds and a
+// scratch buffer for the pre-weighted views.
+struct ConePlan {
+    int K = 0, Du = 0, Dv = 0, N = 0, Nz = 0, filter = 0;
+    double du = 1.0, dv = 1.0, R = 0.0;
+    std::vector<double> angles;
+    Plan* taps = nullptr;
+    double* d_cs = nullptr;
+    float* d_pw = nullptr;
+    int WL = 0, WV = 0, KB = 0;
+    bool staged = true;
+    double half_span = 0.0;
+    RowScratch rows;
+};
+
+struct ConeRegistry {
+    std::mutex mu;
+    std::map<ConeKey, std::unique_ptr<ConePlan>> plans;
+};
+
+ConeRegistry& cone_registry() {
+    static ConeRegistry* r = new ConeRegistry();   // never destroyed: plans live until process exit
+    return *r;
+}
+
+// Window bounds.  Columns: as the fan beam (a 16 x 16 column tile's shadow is at
+// most (kConeTile-1) sqrt(2) max|grad s| / du columns wide).  Rows: over a block of
+// kConeZB slices and a tile, v = z rho / dv + (Dv-1)/2 with rho = R/L in
+// [rho_lo, rho_hi]; the span is at most ((kConeZB-1) rho_max + max|z| drho) / dv,
+// rho_max = R/(R - r) and drho <= (tile diagonal) R/(R - r)^2 (|grad L| = 1,
+// |grad rho| = R/L^2); four more rows cover the floors and the bilinear neighbour.
+int make_cone_plan(ConePlan* c) {
+    const double r = 0.70710678118654752 * (double)(c->N - 1);
+    const double diag = (double)(kConeTile - 1) * 1.4142135623730951;
+    c->half_span = 0.5 * diag * fan_max_gradient(c->R, r) / c->du;
+    const double rho_max = c->R / (c->R - r);
+    const double drho = diag * c->R / ((c->R - r) * (c->R - r));
+    const double span_v = ((double)(kConeZB - 1) * rho_max + 0.5 * (double)(c->Nz - 1) * drho) / c->dv;
+    if (!(c->half_span < 1e6) || !(span_v < 1e6)) return FBP_EUNSUPPORTED;
+    c->WL = (int)std::ceil(2.0 * c->half_span) + 4;
+    c->WV = (int)std::ceil(span_v) + 4;
+    const size_t per_view = sizeof(float) * (size_t)(c->WL + 1) * (size_t)(c->WV + 1) + 40;
+    c->KB = (int)std::min<size_t>(16, kConeLdsBudget / per_view);
+    c->staged = c->KB >= 2;                      // windows through LDS, else direct reads
+    if (!c->staged) c->KB = 16;
+    std::vector<double> cs(2 * (size_t)c->K);
+    for (int k = 0; k < c->K; ++k) {
+        cs[2 * k] = std::cos(c->angles[k]);
+        cs[2 * k + 1] = std::sin(c->angles[k]);
+    }
+    std::vector<float> pw((size_t)c->Dv * c->Du);
+    for (int j = 0; j < c->Dv; ++j) {
+        const double zj = ((double)j - 0.5 * (double)(c->Dv - 1)) * c->dv;
+        for (int i = 0; i < c->Du; ++i) {
+            const double si = ((double)i - 0.5 * (double)(c->Du - 1)) * c->du;
+            pw[(size_t)j * c->Du + i] = (float)(c->R / std::sqrt(c->R * c->R + si * si + zj * zj));
+        }
+    }
+    hipError_t e = hipMalloc(&c->d_cs, sizeof(double) * cs.size());
+    if (e == hipSuccess) e = hipMalloc(&c->d_pw, sizeof(float) * pw.size());
+    if (e == hipSuccess) e = hipMemcpy(c->d_cs, cs.data(), sizeof(double) * cs.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_pw, pw.data(), sizeof(float) * pw.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->rows.free_ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        if (c->d_cs) (void)hipFree(c->d_cs);
+        if (c->d_pw) (void)hipFree(c->d_pw);
+        c->d_cs = nullptr;
+        c->d_pw = nullptr;
+        return hip_fail(e, "cone-beam tables", FBP_ENOMEM);
+    }
+    return FBP_OK;
+}
+
+int get_cone_plan(const fbp_cone_geom* g, ConePlan** out) {
+    // the taps come from a one-angle parallel-beam plan over the detector columns
+    const double zero = 0.0;
+    fbp_geom pg{};
+    pg.n_angles = 1;
+    pg.n_det = g->n_det_u;
+    pg.image_size = 1;
+    pg.det_spacing = g->det_spacing_u;
+    pg.angles = &zero;
+    pg.filter = g->filter;
+    Plan* taps = nullptr;
+    int rc = get_plan(&pg, &taps);
+    if (rc == FBP_OK) rc = ensure_taps(taps, kFP32);
+    if (rc != FBP_OK) return rc;
+    int device = 0;
+    FBP_TRY_HIP(hipGetDevice(&device));
+    ConeKey key{device, g->n_views, g->n_det_u, g->n_det_v, g->volume_size, g->volume_depth, g->filter, 0, 0, 0,
+                hash_angles(g->angles, g->n_views)};
+    std::memcpy(&key.du_bits, &g->det_spacing_u, 8);
+    std::memcpy(&key.dv_bits, &g->det_spacing_v, 8);
+    std::memcpy(&key.r_bits, &g->source_distance, 8);
+    ConeRegistry& CR = cone_registry();
+    std::lock_guard<std::mutex> lock(CR.mu);
+    auto it = CR.plans.find(key);
+    if (it != CR.plans.end()) {
+        if ((int)it->second->angles.size() != g->n_views ||
+            std::memcmp(it->second->angles.data(), g->angles, sizeof(double) * (size_t)g->n_views) != 0)
+            return FBP_EUNSUPPORTED;   // 64-bit hash collision: refuse, never mix
+        *out = it->second.get();
+        return FBP_OK;
+    }
+    auto c = std::make_unique<ConePlan>();
+    c->K = g->n_views;
+    c->Du = g->n_det_u;
+    c->Dv = g->n_det_v;
+    c->N = g->volume_size;
+    c->Nz = g->volume_depth;
+    c->filter = g->filter;
+    c->du = g->det_spacing_u;
+    c->dv = g->det_spacing_v;
+    c->R = g->source_distance;
+    c->angles.assign(g->angles, g->angles + g->n_views);
+    c->taps = taps;
+    rc = make_cone_plan(c.get());
+    if (rc != FBP_OK) return rc;
+    *out = c.get();
+    CR.plans[key] = std::move(c);
+    return FBP_OK;
+}
+
+// Pre-weight (through the plan's scratch, at most 64 MiB of views at a time) and
+// filter every detector row with half the kernel.
+int run_cone_filter(ConePlan& c, const float* proj, float* filt, hipStream_t s) {
+    RowScratch& rs = c.rows;
+    std::lock_guard<std::mutex> lock(rs.mu);
+    const int64_t per_view = (int64_t)c.Dv * c.Du;
+    if (!rs.ptr) {
+        const int64_t views = std::max<int64_t>(1, std::min<int64_t>(c.K, ((int64_t)64 << 20) / (4 * per_view)));
+        const hipError_t e = hipMalloc(&rs.ptr, sizeof(float) * (size_t)(views * per_view));
+        if (e != hipSuccess) {
+            rs.ptr = nullptr;
+            return hip_fail(e, "hipMalloc (cone-beam scratch)", FBP_ENOMEM);
+        }
+        rs.rows = views;
+    }
+    if (rs.recorded) FBP_TRY_HIP(hipStreamWaitEvent(s, rs.free_ev, 0));
+    for (int64_t k0 = 0; k0 < c.K; k0 += rs.rows) {
+        const int64_t m = std::min<int64_t>(rs.rows, c.K - k0);
+        const size_t off = (size_t)(k0 * per_view);
+        hipError_t e = launch_preweight(proj + off, rs.ptr, c.d_pw, m, (int)per_view, s);
+        if (e == hipSuccess) {
+            GemmJob j = gemm_job(*c.taps, kFP32, rs.ptr, filt + off, (int)(m * c.Dv));
+            j.out_scale *= 0.5f;                                       // half the kernel
+            e = launch_gemm_grid(kFP32, j, s);
+        }
+        if (e != hipSuccess) return hip_status(e, "cone-beam filter launch");
+    }
+    FBP_TRY_HIP(hipEventRecord(rs.free_ev, s));
+    rs.recorded = true;
+    return FBP_OK;
+}
+
+int run_cone_backproject(const ConePlan& c, const float* filt, float* vol, hipStream_t s) {
+    ConeJob j{};
+    j.q = filt;
+    j.vol = vol;
+    j.cs = c.d_cs;
+    j.R = c.R;
+    j.du = c.du;
+    j.dv = c.dv;
+    j.inv_R = 1.0 / c.R;
+    j.inv_duR = 1.0 / (c.du * c.R);
+    j.half_span = c.half_span;
+    j.cu = 0.5 * (double)(c.Du - 1);
+    j.cv = 0.5 * (double)(c.Dv - 1);
+    j.half_pix = 0.5 * (double)(c.N - 1);
+    j.half_z = 0.5 * (double)(c.Nz - 1);
+    j.N = c.N;
+    j.Nz = c.Nz;
+    j.K = c.K;
+    j.Du = c.Du;
+    j.Dv = c.Dv;
+    j.WL = c.WL;
+    j.WV = c.WV;
+    j.KB = c.KB;
+    j.tiles_x = (c.N + kConeTile - 1) / kConeTile;
+    j.scale = (float)(2.0 * kPi / (double)c.K);
+    const hipError_t e = launch_cone_bp(j, c.staged, s);
+    return e == hipErrorInvalidValue ? FBP_EUNSUPPORTED : hip_status(e, "cone-beam backprojection launch");
+}
+
 }  // namespace
 }  // namespace fbp
 
@@ -1615,6 +1838,54 @@ int fbp_backproject_with_config(const fbp_geom* geom, int32_t n_slices, const fl
     ShapeParams sp;   // the plan's geometry with the given shape in both roles
     if (!shape_params(config, p->cs, p->angles, p->N, cu_count(p->device), &sp)) return FBP_EUNSUPPORTED;
     return run_backproject(*p, sp, sp, n_slices, d_filtered, d_image, (hipStream_t)hip_stream);
+}
+
+size_t fbp_cone_workspace_bytes(const fbp_cone_geom* geom) {
+    if (check_cone_geom(geom) != FBP_OK) return 0;
+    return round_up(cone_proj_bytes(geom), 256);
+}
+
+int fbp_cone_filter(const fbp_cone_geom* geom, const float* d_proj, float* d_filtered, void* hip_stream) {
+    int rc = check_cone_geom(geom);
+    if (rc != FBP_OK) return rc;
+    if (!d_proj || !d_filtered || !aligned4(d_proj) || !aligned4(d_filtered)) return FBP_EINVAL;
+    const size_t pb = cone_proj_bytes(geom);
+    if (overlaps(d_proj, pb, d_filtered, pb)) return FBP_EINVAL;
+    ConePlan* c = nullptr;
+    rc = get_cone_plan(geom, &c);
+    if (rc != FBP_OK) return rc;
+    return run_cone_filter(*c, d_proj, d_filtered, (hipStream_t)hip_stream);
+}
+
+int fbp_cone_backproject(const fbp_cone_geom* geom, const float* d_filtered, float* d_volume, void* hip_stream) {
+    int rc = check_cone_geom(geom);
+    if (rc != FBP_OK) return rc;
+    if (!d_filtered || !d_volume || !aligned4(d_filtered) || !aligned4(d_volume)) return FBP_EINVAL;
+    if (overlaps(d_filtered, cone_proj_bytes(geom), d_volume, cone_vol_bytes(geom))) return FBP_EINVAL;
+    ConePlan* c = nullptr;
+    rc = get_cone_plan(geom, &c);
+    if (rc != FBP_OK) return rc;
+    return run_cone_backproject(*c, d_filtered, d_volume, (hipStream_t)hip_stream);
+}
+
+int fbp_cone_reconstruct(const fbp_cone_geom* geom, const float* d_proj, float* d_volume, void* d_workspace,
+                         size_t workspace_bytes, void* hip_stream) {
+    int rc = check_cone_geom(geom);
+    if (rc != FBP_OK) return rc;
+    if (!d_proj || !d_volume || !aligned4(d_proj) || !aligned4(d_volume)) return FBP_EINVAL;
+    const size_t pb = cone_proj_bytes(geom), vb = cone_vol_bytes(geom);
+    if (overlaps(d_proj, pb, d_volume, vb)) return FBP_EINVAL;
+    if (!d_workspace || workspace_bytes < pb) return FBP_EWORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(d_workspace) & 255u) != 0) return FBP_EINVAL;
+    if (overlaps(d_workspace, pb, d_proj, pb) || overlaps(d_workspace, pb, d_volume, vb)) return FBP_EINVAL;
+    ConePlan* c = nullptr;
+    rc = get_cone_plan(geom, &c);
+    if (rc != FBP_OK) return rc;
+    float* filt = static_cast<float*>(d_workspace);
+    const hipStream_t s = (hipStream_t)hip_stream;
+    rc = run_cone_filter(*c, d_proj, filt, s);
+    if (rc == FBP_OK) rc = run_cone_backproject(*c, filt, d_volume, s);
+    return rc;
 }
 
 }  // extern "C"

@@ -219,3 +219,38 @@ def test_fan_beam_entry_points_that_do_not_take_it(lib):
     assert lib.fbp_backproject(ctypes.byref(g2), 1, FAKE, FAKE2, None) == B.FBP_EUNSUPPORTED
     # validation still runs first: overlapping buffers are invalid
     assert lib.fbp_backproject(gp, 1, FAKE, FAKE + 4, None) == B.FBP_EINVAL
+
+
+def test_cone_geometry_struct_matches_the_header():
+    assert ctypes.sizeof(B.c_cone_geom) == 56
+    assert B.c_cone_geom.det_spacing_u.offset == 24 and B.c_cone_geom.angles.offset == 48
+
+
+@pytest.mark.parametrize("field,value", [("n_views", 0), ("n_det_u", 0), ("n_det_v", 0), ("volume_size", 0),
+                                         ("volume_depth", 0), ("filter", 5), ("det_spacing_u", 0.0),
+                                         ("det_spacing_v", float("nan")), ("source_distance", 3.0),
+                                         ("source_distance", float("inf"))])
+def test_cone_geometry_validation(lib, field, value):
+    ang = (ctypes.c_double * 4)(0.0, 1.5, 3.0, 4.5)
+    g = B.c_cone_geom(4, 9, 5, 6, 3, 0, 1.0, 1.0, 20.0, ang)
+    setattr(g, field, value)
+    gp = ctypes.byref(g)
+    assert lib.fbp_cone_filter(gp, FAKE, FAKE2, None) == B.FBP_EINVAL
+    assert lib.fbp_cone_backproject(gp, FAKE, FAKE2, None) == B.FBP_EINVAL
+    assert lib.fbp_cone_reconstruct(gp, FAKE, FAKE2, FAKE3, 1 << 20, None) == B.FBP_EINVAL
+    assert lib.fbp_cone_workspace_bytes(gp) == 0
+
+
+def test_cone_pointer_checks(lib):
+    ang = (ctypes.c_double * 4)(0.0, 1.5, 3.0, 4.5)
+    g = B.c_cone_geom(4, 9, 5, 6, 3, 0, 1.0, 1.0, 20.0, ang)
+    gp = ctypes.byref(g)
+    assert lib.fbp_cone_workspace_bytes(gp) == 4 * 5 * 9 * 4 + (256 - (4 * 5 * 9 * 4) % 256)
+    assert lib.fbp_cone_filter(gp, None, FAKE2, None) == B.FBP_EINVAL
+    assert lib.fbp_cone_filter(gp, FAKE, FAKE + 16, None) == B.FBP_EINVAL             # overlap
+    assert lib.fbp_cone_backproject(gp, FAKE, FAKE2 + 2, None) == B.FBP_EINVAL        # misaligned
+    assert lib.fbp_cone_reconstruct(gp, FAKE, FAKE2, None, 0, None) == B.FBP_EWORKSPACE
+    assert lib.fbp_cone_reconstruct(gp, FAKE, FAKE2, FAKE3, 16, None) == B.FBP_EWORKSPACE
+    assert lib.fbp_cone_reconstruct(gp, FAKE, FAKE2, FAKE3 + 4, 1 << 20, None) == B.FBP_EINVAL
+    g.angles = None
+    assert lib.fbp_cone_filter(gp, FAKE, FAKE2, None) == B.FBP_EINVAL
