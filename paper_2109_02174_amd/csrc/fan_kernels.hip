@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kFanThreads) void fan_bp_kernel(FanJob job) {
     int* org = reinterpret_cast<int*>(coef + 8 * KB);                  // [KB] window origins
     float2* win = reinterpret_cast<float2*>(org + ((KB + 3) & ~3));    // [KB][WL][M] (A_i, dQ_i)
     const int tiles = job.tiles_x * job.tiles_x;
-    const int g = blockIdx.x / tiles;                                  // group of M slices
+    const int g = blockIdx.x / tiles;                                  // group of M slices, or view part
     const int tile = blockIdx.x - g * tiles;
     const int c0 = (tile % job.tiles_x) * kFanTile, r0 = (tile / job.tiles_x) * kFanTile;
     const int dx = threadIdx.x & (kFanTile - 1), dy = threadIdx.x / kFanTile;
@@ -57,13 +57,17 @@ __global__ __launch_bounds__(kFanThreads) void fan_bp_kernel(FanJob job) {
     const int cw = min(kFanTile, N - c0), rh = min(kFanTile, N - r0);   // pixels of the tile in the image
     const float fdx = (float)dx, fdy = (float)dy;
     const size_t qstride = (size_t)K * D;
-    const float* __restrict__ qs = job.q + (size_t)g * M * qstride;
+    // split > 1 (one slice, M = 1): this workgroup sums the views of part g only
+    const int kpart = (K + job.split - 1) / job.split;
+    const int kbeg = job.split > 1 ? g * kpart : 0;
+    const int kend = job.split > 1 ? min(K, kbeg + kpart) : K;
+    const float* __restrict__ qs = job.q + (job.split > 1 ? (size_t)0 : (size_t)g * M * qstride);
     const float inv_wl = 1.0f / (float)WL;
     float acc[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) acc[m] = 0.0f;
-    for (int k0 = 0; k0 < K; k0 += KB) {
-        const int nk = min(KB, K - k0);
+    for (int k0 = kbeg; k0 < kend; k0 += KB) {
+        const int nk = min(KB, kend - k0);
         __syncthreads();                                               // previous block's reads done
         if ((int)threadIdx.x < nk) {
             // FP64: window origin and map coefficients of this tile for view k0 + t.
@@ -167,9 +171,13 @@ __global__ __launch_bounds__(kFanThreads) void fan_bp_kernel(FanJob job) {
         }
     }
     if (inside) {
+        if (job.split > 1) {                                           // partial sum of part g
+            job.part[(size_t)g * N * N + (size_t)(r0 + dy) * N + (c0 + dx)] = acc[0];
+        } else {
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            job.img[((size_t)g * M + m) * N * N + (size_t)(r0 + dy) * N + (c0 + dx)] = acc[m] * job.scale;
+            for (int m = 0; m < M; ++m)
+                job.img[((size_t)g * M + m) * N * N + (size_t)(r0 + dy) * N + (c0 + dx)] = acc[m] * job.scale;
+        }
     }
 }
 
@@ -207,6 +215,13 @@ hipError_t launch_fan_bp(const FanJob& job, int n_slices, int M, int KBm, hipStr
     }
     const int rest = n_slices - grouped;
     if (rest == 0) return hipSuccess;
+    if (job.split > 1) {                                               // one slice, views split over parts
+        if (n_slices != 1 || M != 1 || !job.part || job.split > job.K) return hipErrorInvalidValue;
+        const size_t lds = fan_lds_bytes(job.KB, job.WL, 1);
+        const int64_t blocks = tiles * job.split;
+        if (blocks > INT32_MAX || lds > kFanLdsBudget) return hipErrorInvalidValue;
+        return launch_kernel(fan_bp_kernel<1>, dim3((unsigned)blocks), dim3(kFanThreads), lds, stream, job);
+    }
     FanJob j = job;
     j.q = job.q + (size_t)grouped * job.K * job.D;
     j.img = job.img + (size_t)grouped * job.N * job.N;

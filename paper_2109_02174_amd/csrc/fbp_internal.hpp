@@ -182,6 +182,8 @@ struct FanJob {
     int32_t KB;           // views per staged block
     int32_t tiles_x;      // ceil(N / kFanTile)
     float scale;          // 2 pi / K
+    float* part;          // split > 1: [split][N][N] partial sums (one slice, M = 1)
+    int32_t split;        // view parts of a single slice (1: none)
 };
 constexpr int kFanTile = 16;
 constexpr size_t kFanLdsBudget = 48 * 1024;

@@ -181,6 +181,7 @@ struct Plan {
     double* d_fcs = nullptr;
     float* d_fanw = nullptr;
     int fan_WL = 0, fan_KB = 0, fan_KB4 = 0;   // window pairs; views per block (one slice, four)
+    int fan_split = 1;                          // view parts of a single slice
     double fan_half_span = 0.0;
     // FFT filter path: twiddles and the taps' DFT for L = 2^fft_log2 (made on first use)
     float2* d_fft_tw = nullptr;
@@ -450,6 +451,24 @@ int make_fan_plan(Plan* p) {
     p->fan_KB = (int)std::min<size_t>(64, (kFanLdsBudget - 64 * 36) / (8 * (size_t)p->fan_WL));
     if (p->fan_KB < 1) return FBP_EUNSUPPORTED;
     p->fan_KB4 = (int)std::min<size_t>(16, (kFanLdsBudget - 64 * 36) / (4 * 8 * (size_t)p->fan_WL));
+    // single slices: views split over enough parts for about 16 workgroups per CU,
+    // partial sums in planes owned by the plan (images up to 2048^2)
+    const int tiles = ((p->N + kFanTile - 1) / kFanTile) * ((p->N + kFanTile - 1) / kFanTile);
+    const int cus = cu_count(p->device);
+    p->fan_split = std::max(1, std::min({kMaxSplit, p->K, (16 * cus + tiles / 2) / tiles}));
+    const size_t plane = (size_t)p->N * p->N;
+    if (p->fan_split > 1 && plane <= (size_t)2048 * 2048) {
+        hipError_t e = hipMalloc(&p->part.ptr, sizeof(float) * plane * p->fan_split);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->part.free_ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (p->part.ptr) (void)hipFree(p->part.ptr);
+            p->part.ptr = nullptr;
+            return hip_fail(e, "hipMalloc (fan-beam partial sums)", FBP_ENOMEM);
+        }
+        p->part.planes = p->fan_split;
+    } else {
+        p->fan_split = 1;
+    }
     std::vector<double> fcs(2 * (size_t)p->K);
     for (int k = 0; k < p->K; ++k) {
         fcs[2 * k] = std::cos(p->angles[k]);
@@ -819,7 +838,7 @@ int run_filter(Plan& p, int prec, int32_t n, const float* sino, float* filt, hip
     return hip_status(launch_filter_rows(p, prec, sino, filt, n * p.K, s), "filter kernel launch");
 }
 
-int run_fan_backproject(const Plan& p, int32_t n, const float* filt, float* img, hipStream_t s) {
+int run_fan_backproject(Plan& p, int32_t n, const float* filt, float* img, hipStream_t s) {
     FanJob j{};
     j.q = filt;
     j.img = img;
@@ -838,8 +857,30 @@ int run_fan_backproject(const Plan& p, int32_t n, const float* filt, float* img,
     j.KB = p.fan_KB;
     j.tiles_x = (p.N + kFanTile - 1) / kFanTile;
     j.scale = (float)(2.0 * kPi / (double)p.K);
+    j.part = nullptr;
+    j.split = 1;
     // stacks of 4 or more share each pixel's map over 4 slices per workgroup
     const int M = (n >= kStackMinSlices && p.fan_KB4 >= 1) ? 4 : 1;
+    if (M == 1 && p.fan_split > 1 && p.part.ptr) {
+        // slice by slice, the views split over parts summed in a fixed order
+        PartBuffer& pb = p.part;
+        std::lock_guard<std::mutex> lock(pb.mu);
+        if (pb.recorded) FBP_TRY_HIP(hipStreamWaitEvent(s, pb.free_ev, 0));
+        const size_t qs = (size_t)p.K * p.D, is = (size_t)p.N * p.N;
+        for (int32_t i = 0; i < n; ++i) {
+            FanJob ji = j;
+            ji.q = filt + i * qs;
+            ji.part = pb.ptr;
+            ji.split = p.fan_split;
+            hipError_t e = launch_fan_bp(ji, 1, 1, p.fan_KB4, s);
+            if (e == hipSuccess) e = launch_combine_parts(pb.ptr, img + i * is, 1, p.fan_split, is, j.scale, s);
+            if (e != hipSuccess)
+                return e == hipErrorInvalidValue ? FBP_EUNSUPPORTED : hip_status(e, "fan-beam backprojection launch");
+        }
+        FBP_TRY_HIP(hipEventRecord(pb.free_ev, s));
+        pb.recorded = true;
+        return FBP_OK;
+    }
     const hipError_t e = launch_fan_bp(j, n, M, p.fan_KB4, s);
     return e == hipErrorInvalidValue ? FBP_EUNSUPPORTED : hip_status(e, "fan-beam backprojection launch");
 }
