@@ -13,14 +13,14 @@
 //
 // A workgroup owns a 16 x 16 column tile of the volume and a block of 32 slices
 // in z (one column per lane, 32 voxels each).  Per block of views it stages, for
-// each view, the detector window the tile's voxels can see (columns from the
-// in-plane map, rows from the z extent times the magnification range) as raw
-// values in LDS.  The in-plane map is that of the fan beam (per (tile, view) an
-// FP64 origin and six FP32 coefficients; per column rho = R/L, the column
-// coordinate u and the weight rho^2); along z the row coordinate is
+// each view, exactly the detector window the block's voxels can see (found in
+// FP64 from the tile's corners and the block's z extent) as raw values in LDS,
+// windows packed back to back.  The in-plane map is that of the fan beam (per
+// (tile, view) an FP64 origin and six FP32 coefficients; per column rho = R/L,
+// the column coordinate u and the weight rho^2); along z the row coordinate is
 // v = z rho / dv + const, one FMA per voxel, and the four detector values come
-// from two two-dword LDS reads.  Views are summed in a fixed order, each voxel is
-// written once, no atomics.
+// from two two-dword LDS reads at one address.  Views are summed in a fixed
+// order, each voxel is written once, no atomics.
 #include "fbp_internal.hpp"
 
 #include <algorithm>
@@ -30,18 +30,27 @@ namespace fbp {
 namespace {
 
 constexpr int kConeThreads = kConeTile * kConeTile;
+constexpr int kConeCoef = 12;                           // per-view floats in LDS
 
-// STAGED: the detector windows go through LDS (they fit: the host checked);
-// otherwise (strong magnification) the four values come from global memory with
-// detector bounds checks, in the same arithmetic order.
-template <bool STAGED>
+// STAGED: each view's detector window goes through LDS with a row pitch of P
+// floats (P = 0: the pitch is job.pitch; a fixed P lets the two rows of a bilinear
+// sample come from one LDS address with constant offsets).  Windows are packed
+// back to back by their actual row count, so a block takes as many of the next
+// KB views as fit job.cap floats (at least one: the host checks that the largest
+// possible window fits).  Otherwise the four values come from global memory with
+// detector bounds checks.  Both read the same per-view window and share the
+// arithmetic.
+template <bool STAGED, int P>
 __global__ __launch_bounds__(kConeThreads) void cone_bp_kernel(ConeJob job) {
     extern __shared__ __align__(16) char smem[];
-    const int KB = job.KB, WL = job.WL, WV = job.WV, N = job.N, K = job.K, Du = job.Du, Dv = job.Dv;
-    const int CW = WL + 1, RW = WV + 1;                 // staged columns and rows per view (+1: bilinear)
-    float* coef = reinterpret_cast<float*>(smem);      // [KB][8]: n0 n1 n2 cvj d0 d1 d2 -
-    int* org = reinterpret_cast<int*>(coef + 8 * KB);  // [KB][2]: column and row origins
-    float* win = reinterpret_cast<float*>(org + 2 * KB);   // [KB][RW][CW]
+    const int KB = job.KB, N = job.N, K = job.K, Du = job.Du, Dv = job.Dv;
+    const int pitch = P > 0 ? P : job.pitch;
+    const int RW = job.WV + 1;                         // rows of the largest window
+    // per view: n0 n1 n2 cvj | d0 d1 d2 umax | vmax - - - (floats), then
+    // column origin, row origin, columns, rows (ints)
+    float* coef = reinterpret_cast<float*>(smem);
+    int* org = reinterpret_cast<int*>(coef + kConeCoef * KB);
+    float* win = reinterpret_cast<float*>(org + 4 * KB);
     const int tiles = job.tiles_x * job.tiles_x;
     const int zb = blockIdx.x / tiles;
     const int tile = blockIdx.x - zb * tiles;
@@ -54,38 +63,45 @@ __global__ __launch_bounds__(kConeThreads) void cone_bp_kernel(ConeJob job) {
     const float fdx = (float)dx, fdy = (float)dy;
     const double zlo = (double)z0 - job.half_z, zhi = zlo + (double)(zn - 1);
     const float zlo_dv = (float)(zlo / job.dv), inv_dv = (float)(1.0 / job.dv);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float acc[kConeZB];
 #pragma unroll
     for (int q = 0; q < kConeZB; ++q) acc[q] = 0.0f;
-    const int per_view = RW * CW;
-    const float inv_cw = 1.0f / (float)CW, inv_pv = 1.0f / (float)per_view;
-    for (int k0 = 0; k0 < K; k0 += KB) {
-        const int nk = min(KB, K - k0);
+    for (int k0 = 0; k0 < K;) {
+        const int nmax = min(KB, K - k0);
         __syncthreads();                                // previous block's reads done
-        if ((int)threadIdx.x < nk) {
-            // FP64, per view: column window and in-plane map (as the fan beam), row
-            // window from the z extent times the range of R/L over the tile
+        if ((int)threadIdx.x < nmax) {
+            // FP64, per view: the in-plane map (as the fan beam) and the window of
+            // detector cells the tile's voxels can reach.  u = N/L and rho = R/L are
+            // linear-fractional in (x, y), so over the tile their extremes sit at
+            // the corners; v = z rho / dv + cv is then extreme at a corner of
+            // (z, rho).  One cell of margin on each side covers FP32 rounding, and
+            // the clamps below keep every read inside the window regardless.
             const int k = k0 + threadIdx.x;
             const double c = job.cs[2 * k], sn = job.cs[2 * k + 1];
             const double R = job.R, du = job.du;
             const double xt = (double)c0 - job.half_pix, yt = (double)r0 - job.half_pix;
             const double Lt = R - (c * xt + sn * yt);
             const double Nt = R * (-sn * xt + c * yt);
-            const double ex = 0.5 * (double)(cw - 1), ey = 0.5 * (double)(rh - 1);
-            const double uc = (Nt + R * (-sn * ex + c * ey)) / ((Lt - c * ex - sn * ey) * du) + job.cu;
-            const double i0 = floor(uc - job.half_span);
-            const double G = (i0 - job.cu) * du;
-            const double a0 = Nt - G * Lt, a1 = -R * sn + G * c, a2 = R * c + G * sn;
-            double Lmin = INFINITY, Lmax = -INFINITY;
-            for (int q = 0; q < 4; ++q) {               // L is linear: extremes at the corners
-                const double L = Lt - c * ((q & 1) ? (double)(cw - 1) : 0.0) - sn * ((q & 2) ? (double)(rh - 1) : 0.0);
+            double Lmin = INFINITY, Lmax = -INFINITY, umin = INFINITY, umax = -INFINITY;
+            for (int q = 0; q < 4; ++q) {
+                const double ex = (q & 1) ? (double)(cw - 1) : 0.0, ey = (q & 2) ? (double)(rh - 1) : 0.0;
+                const double L = Lt - c * ex - sn * ey;
+                const double u = (Nt + R * (-sn * ex + c * ey)) / (L * du);
                 Lmin = fmin(Lmin, L);
                 Lmax = fmax(Lmax, L);
+                umin = fmin(umin, u);
+                umax = fmax(umax, u);
             }
             const double rlo = R / Lmax, rhi = R / Lmin;
-            const double vmin = fmin(fmin(zlo * rlo, zlo * rhi), fmin(zhi * rlo, zhi * rhi)) / job.dv + job.cv;
-            const double j0 = floor(vmin);
-            float* cf = coef + 8 * threadIdx.x;
+            const double vmin = fmin(fmin(zlo * rlo, zlo * rhi), fmin(zhi * rlo, zhi * rhi)) / job.dv;
+            const double vmax = fmax(fmax(zlo * rlo, zlo * rhi), fmax(zhi * rlo, zhi * rhi)) / job.dv;
+            const double i0 = floor(umin + job.cu) - 1.0, j0 = floor(vmin + job.cv) - 1.0;
+            const int nc = (int)fmin((double)pitch, floor(umax + job.cu) + 3.0 - i0);
+            const int nr = (int)fmin((double)RW, floor(vmax + job.cv) + 4.0 - j0);   // one more row: see the clamp
+            const double G = (i0 - job.cu) * du;
+            const double a0 = Nt - G * Lt, a1 = -R * sn + G * c, a2 = R * c + G * sn;
+            float* cf = coef + kConeCoef * threadIdx.x;
             cf[0] = (float)(a0 * job.inv_duR);
             cf[1] = (float)(a1 * job.inv_duR);
             cf[2] = (float)(a2 * job.inv_duR);
@@ -93,74 +109,121 @@ __global__ __launch_bounds__(kConeThreads) void cone_bp_kernel(ConeJob job) {
             cf[4] = (float)(Lt * job.inv_R);
             cf[5] = (float)(-c * job.inv_R);
             cf[6] = (float)(-sn * job.inv_R);
-            cf[7] = 0.0f;
-            org[2 * threadIdx.x] = (int)i0;
-            org[2 * threadIdx.x + 1] = (int)j0;
+            cf[7] = (float)(nc - 2);
+            cf[8] = (float)(nr - 2);
+            int* og = org + 4 * threadIdx.x;
+            og[0] = (int)i0;
+            og[1] = (int)j0;
+            og[2] = nc;
+            og[3] = nr;
         }
         __syncthreads();
-        // stage the windows (zero off the detector); e -> (view, row, column) by
-        // float reciprocals (exact: e < KB RW CW <= 2^20 and the margins 0.5/CW, 0.5/per_view)
-        for (int e = threadIdx.x; STAGED && e < nk * per_view; e += kConeThreads) {
-            const int kk = (int)(((float)e + 0.5f) * inv_pv);
-            const int rem = e - kk * per_view;
-            const int rr = (int)(((float)rem + 0.5f) * inv_cw);
-            const int cc = rem - rr * CW;
-            const int col = org[2 * kk] + cc, row = org[2 * kk + 1] + rr;
-            float val = 0.0f;
-            if ((unsigned)col < (unsigned)Du && (unsigned)row < (unsigned)Dv)
-                val = job.q[((size_t)(k0 + kk) * Dv + row) * Du + col];
-            win[e] = val;
+        int nk = nmax;
+        if constexpr (STAGED) {
+            // stage the windows (zero off the detector) while they fit: a wave
+            // covers 2^lg columns of 64 / 2^lg rows per load, four loads in flight
+            // per lane
+            int off = 0;
+            nk = 0;
+            for (int kk = 0; kk < nmax; ++kk) {
+                const int i0 = org[4 * kk], j0 = org[4 * kk + 1], nc = org[4 * kk + 2], nr = org[4 * kk + 3];
+                if (off + nr * pitch > job.cap) break;
+                const int lg = nc <= 16 ? 4 : (nc <= 32 ? 5 : 6);
+                const int rows = 64 >> lg;              // rows per wave and load
+                const int cc0 = lane & ((1 << lg) - 1);
+                const int rsub = wave * rows + (lane >> lg);
+                const int step = 4 * rows;              // rows per round of the four waves
+                const float* __restrict__ src = job.q + (size_t)(k0 + kk) * Dv * Du;
+                float* dst = win + off;
+                for (int cc = cc0; cc - cc0 < nc; cc += 1 << lg) {
+                    const int col = i0 + cc;
+                    const bool col_ok = cc < nc;
+                    const bool col_in = col_ok && (unsigned)col < (unsigned)Du;
+                    for (int rb = rsub; rb < nr; rb += 4 * step) {
+                        float val[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int rr = rb + u * step;
+                            const int row = j0 + rr;
+                            val[u] = (col_in && rr < nr && (unsigned)row < (unsigned)Dv) ? src[row * Du + col] : 0.0f;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int rr = rb + u * step;
+                            if (col_ok && rr < nr) dst[rr * pitch + cc] = val[u];
+                        }
+                    }
+                }
+                off += nr * pitch;
+                nk = kk + 1;
+            }
+            __syncthreads();
         }
-        __syncthreads();
         if (inside) {
-            const float umax = (float)(WL - 1), vmax = (float)(WV - 1);
+            int off = 0;
             for (int kk = 0; kk < nk; ++kk) {
-                const float4 nf = *reinterpret_cast<const float4*>(coef + 8 * kk);
-                const float4 df = *reinterpret_cast<const float4*>(coef + 8 * kk + 4);
+                const float4 nf = *reinterpret_cast<const float4*>(coef + kConeCoef * kk);
+                const float4 df = *reinterpret_cast<const float4*>(coef + kConeCoef * kk + 4);
+                const float vmax = coef[kConeCoef * kk + 8];
                 const float den = fmaf(df.z, fdy, fmaf(df.y, fdx, df.x));
                 const float num = fmaf(nf.z, fdy, fmaf(nf.y, fdx, nf.x));
                 const float rho = __builtin_amdgcn_rcpf(den);          // R / L
-                const float u = __builtin_amdgcn_fmed3f(num * rho, 0.0f, umax);
+                const float u = __builtin_amdgcn_fmed3f(num * rho, 0.0f, df.w);
                 const float w = rho * rho;
                 const int iu = (int)u;
                 const float fu = u - (float)iu;
+                const float wb = w * fu, wa = w - wb;                  // column weights
                 const float a = rho * inv_dv;                          // rows per slice
                 const float v0 = fmaf(zlo_dv, rho, nf.w);              // window row of the block's first slice
                 if constexpr (STAGED) {
-                    const float* __restrict__ base = win + kk * per_view + iu;
-#pragma unroll
-                    for (int q = 0; q < kConeZB; ++q) {
-                        const float v = __builtin_amdgcn_fmed3f(fmaf((float)q, a, v0), 0.0f, vmax);
+                    // byte offset of the sample's window column in LDS, kept in one
+                    // register so each sample's address is one 24-bit multiply-add
+                    unsigned boff = (unsigned)((const char*)(win + off + iu) - smem);
+                    off += org[4 * kk + 3] * pitch;
+                    asm volatile("" : "+v"(boff));
+                    auto sample = [&](int q, float v) {
                         const int iv = (int)v;
-                        const float fv = v - (float)iv;
-                        const float* __restrict__ p = base + iv * CW;
-                        const float r0v = fmaf(fu, p[1] - p[0], p[0]);
-                        const float r1v = fmaf(fu, p[CW + 1] - p[CW], p[CW]);
-                        acc[q] = fmaf(w, fmaf(fv, r1v - r0v, r0v), acc[q]);
+                        const float fv = __builtin_amdgcn_fractf(v);   // v >= 0: v - floor(v)
+                        const float* __restrict__ p =
+                            reinterpret_cast<const float*>(smem + __umul24((unsigned)iv, (unsigned)(4 * pitch)) + boff);
+                        const float c0v = fmaf(fv, p[pitch] - p[0], p[0]);
+                        const float c1v = fmaf(fv, p[pitch + 1] - p[1], p[1]);
+                        acc[q] = fmaf(wb, c1v, fmaf(wa, c0v, acc[q]));
+                    };
+                    // v is monotone in q (a > 0, and FP32 rounding keeps the order), so
+                    // when the first and last slices' rows lie in the window every
+                    // slice's does and the clamp can be left out
+                    if (v0 >= 0.0f && fmaf((float)(kConeZB - 1), a, v0) <= vmax) {
+#pragma unroll
+                        for (int q = 0; q < kConeZB; ++q) sample(q, fmaf((float)q, a, v0));
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < kConeZB; ++q)
+                            sample(q, __builtin_amdgcn_fmed3f(fmaf((float)q, a, v0), 0.0f, vmax));
                     }
                 } else {
                     const float* __restrict__ qv = job.q + (size_t)(k0 + kk) * Dv * Du;
-                    const int col = org[2 * kk] + iu;
-                    const int row0 = org[2 * kk + 1];
+                    const int col = org[4 * kk] + iu;
+                    const int row0 = org[4 * kk + 1];
                     auto at = [&](int cc, int rr) {
-                        return ((unsigned)cc < (unsigned)Du && (unsigned)rr < (unsigned)Dv) ? qv[(size_t)rr * Du + cc]
-                                                                                        : 0.0f;
+                        return ((unsigned)cc < (unsigned)Du && (unsigned)rr < (unsigned)Dv) ? qv[rr * Du + cc] : 0.0f;
                     };
 #pragma unroll 4
                     for (int q = 0; q < kConeZB; ++q) {
                         const float v = __builtin_amdgcn_fmed3f(fmaf((float)q, a, v0), 0.0f, vmax);
                         const int iv = (int)v;
-                        const float fv = v - (float)iv;
+                        const float fv = __builtin_amdgcn_fractf(v);
                         const int row = row0 + iv;
                         const float p00 = at(col, row), p01 = at(col + 1, row);
                         const float p10 = at(col, row + 1), p11 = at(col + 1, row + 1);
-                        const float r0v = fmaf(fu, p01 - p00, p00);
-                        const float r1v = fmaf(fu, p11 - p10, p10);
-                        acc[q] = fmaf(w, fmaf(fv, r1v - r0v, r0v), acc[q]);
+                        const float c0v = fmaf(fv, p10 - p00, p00);
+                        const float c1v = fmaf(fv, p11 - p01, p01);
+                        acc[q] = fmaf(wb, c1v, fmaf(wa, c0v, acc[q]));
                     }
                 }
             }
         }
+        k0 += nk;
     }
     if (inside) {
 #pragma unroll
@@ -170,22 +233,45 @@ __global__ __launch_bounds__(kConeThreads) void cone_bp_kernel(ConeJob job) {
     }
 }
 
+// fixed row pitches (floats) of the staged windows; the second row of a bilinear
+// sample sits at an LDS offset of P + 1 <= 255 dwords
+constexpr int kConePitches[] = {16, 24, 32, 40, 48, 64, 80, 96, 128, 160, 192, 248};
+
+template <int I>
+hipError_t launch_pitch(int pitch, const ConeJob& job, dim3 grid, size_t lds, hipStream_t stream) {
+    if constexpr (I < (int)(sizeof(kConePitches) / sizeof(int))) {
+        if (pitch == kConePitches[I])
+            return launch_kernel(cone_bp_kernel<true, kConePitches[I]>, grid, dim3(kConeThreads), lds, stream, job);
+        return launch_pitch<I + 1>(pitch, job, grid, lds, stream);
+    } else {
+        return launch_kernel(cone_bp_kernel<true, 0>, grid, dim3(kConeThreads), lds, stream, job);
+    }
+}
+
 }  // namespace
 
-size_t cone_lds_bytes(int KB, int WL, int WV, bool staged) {
-    return sizeof(float) * 8 * (size_t)KB + sizeof(int) * 2 * (size_t)KB +
-           (staged ? sizeof(float) * (size_t)KB * (size_t)(WV + 1) * (size_t)(WL + 1) : 0);
+int cone_pitch(int WL) {
+    for (int p : kConePitches)
+        if (p >= WL + 1) return p;
+    return WL + 1;
+}
+
+size_t cone_lds_bytes(int KB, int cap, bool staged) {
+    return sizeof(float) * kConeCoef * (size_t)KB + sizeof(int) * 4 * (size_t)KB +
+           (staged ? sizeof(float) * (size_t)cap : 0);
 }
 
 hipError_t launch_cone_bp(const ConeJob& job, bool staged, hipStream_t stream) {
-    if (job.KB < 1 || job.KB > kConeThreads || job.WL < 2 || job.WV < 2) return hipErrorInvalidValue;
-    const size_t lds = cone_lds_bytes(job.KB, job.WL, job.WV, staged);
-    if (lds > kConeLdsBudget || (staged && (size_t)job.KB * (job.WV + 1) * (job.WL + 1) > ((size_t)1 << 20)))
+    if (job.KB < 1 || job.KB > kConeThreads || job.WL < 2 || job.WV < 2 || job.pitch < job.WL + 1)
         return hipErrorInvalidValue;
+    if (staged && (int64_t)(job.WV + 1) * job.pitch > job.cap) return hipErrorInvalidValue;   // one window must fit
+    const size_t lds = cone_lds_bytes(job.KB, job.cap, staged);
+    if (lds > kConeLdsBudget) return hipErrorInvalidValue;
     const int64_t blocks = (int64_t)job.tiles_x * job.tiles_x * ((job.Nz + kConeZB - 1) / kConeZB);
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
-    return staged ? launch_kernel(cone_bp_kernel<true>, dim3((unsigned)blocks), dim3(kConeThreads), lds, stream, job)
-                  : launch_kernel(cone_bp_kernel<false>, dim3((unsigned)blocks), dim3(kConeThreads), lds, stream, job);
+    const dim3 grid((unsigned)blocks);
+    return staged ? launch_pitch<0>(job.pitch, job, grid, lds, stream)
+                  : launch_kernel(cone_bp_kernel<false, 0>, grid, dim3(kConeThreads), lds, stream, job);
 }
 
 }  // namespace fbp

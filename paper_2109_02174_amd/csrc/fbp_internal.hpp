@@ -209,17 +209,21 @@ struct ConeJob {
     double half_pix;       // (N-1)/2
     double half_z;         // (Nz-1)/2
     int32_t N, Nz, K, Du, Dv;
-    int32_t WL, WV;        // staged window: columns, rows (bounds over tiles, z blocks and views)
-    int32_t KB;            // views per staged block
+    int32_t WL, WV;        // window bounds over tiles, z blocks and views: columns, rows
+    int32_t pitch;         // row pitch of a staged window in floats (>= WL + 1)
+    int32_t KB;            // views whose windows a block computes (it stages those that fit)
+    int32_t cap;           // LDS floats for the staged windows of a block (>= (WV + 1) pitch)
     int32_t tiles_x;       // ceil(N / kConeTile)
     float scale;           // 2 pi / K
 };
 constexpr int kConeTile = 16;
 constexpr int kConeZB = 32;          // voxels in z per lane
-constexpr size_t kConeLdsBudget = 48 * 1024;
-size_t cone_lds_bytes(int KB, int WL, int WV, bool staged);
-// staged: detector windows through LDS (KB views of (WV+1) x (WL+1) values must
-// fit kConeLdsBudget); otherwise values are read from global memory.
+constexpr size_t kConeLdsBudget = 40 * 1024;   // four workgroups per CU
+// row pitch of the staged windows for a column bound WL (one of a fixed set, else WL + 1)
+int cone_pitch(int WL);
+size_t cone_lds_bytes(int KB, int cap, bool staged);
+// staged: detector windows through LDS (cap floats, which must hold the largest
+// window of WV + 1 rows of pitch floats); otherwise values are read from global memory.
 hipError_t launch_cone_bp(const ConeJob& job, bool staged, hipStream_t stream);
 
 // ------------------------------------------------------------------ ramp filter GEMM

@@ -1498,7 +1498,7 @@ struct ConePlan {
     Plan* taps = nullptr;
     double* d_cs = nullptr;
     float* d_pw = nullptr;
-    int WL = 0, WV = 0, KB = 0;
+    int WL = 0, WV = 0, KB = 0, pitch = 0, cap = 0;
     bool staged = true;
     double half_span = 0.0;
     RowScratch rows;
@@ -1519,7 +1519,10 @@ ConeRegistry& cone_registry() {
 // kConeZB slices and a tile, v = z rho / dv + (Dv-1)/2 with rho = R/L in
 // [rho_lo, rho_hi]; the span is at most ((kConeZB-1) rho_max + max|z| drho) / dv,
 // rho_max = R/(R - r) and drho <= (tile diagonal) R/(R - r)^2 (|grad L| = 1,
-// |grad rho| = R/L^2); four more rows cover the floors and the bilinear neighbour.
+// |grad rho| = R/L^2).  The kernel's per-view windows (floors, a cell of margin on
+// each side, the bilinear neighbour and one spare row) then stay within WL + 1
+// columns and WV + 1 rows.  A workgroup's LDS holds cap floats of windows packed
+// by their row counts; the windows go through LDS when the largest one fits.
 int make_cone_plan(ConePlan* c) {
     const double r = 0.70710678118654752 * (double)(c->N - 1);
     const double diag = (double)(kConeTile - 1) * 1.4142135623730951;
@@ -1529,11 +1532,11 @@ int make_cone_plan(ConePlan* c) {
     const double span_v = ((double)(kConeZB - 1) * rho_max + 0.5 * (double)(c->Nz - 1) * drho) / c->dv;
     if (!(c->half_span < 1e6) || !(span_v < 1e6)) return FBP_EUNSUPPORTED;
     c->WL = (int)std::ceil(2.0 * c->half_span) + 4;
-    c->WV = (int)std::ceil(span_v) + 4;
-    const size_t per_view = sizeof(float) * (size_t)(c->WL + 1) * (size_t)(c->WV + 1) + 40;
-    c->KB = (int)std::min<size_t>(16, kConeLdsBudget / per_view);
-    c->staged = c->KB >= 2;                      // windows through LDS, else direct reads
-    if (!c->staged) c->KB = 16;
+    c->WV = (int)std::ceil(span_v) + 5;
+    c->pitch = cone_pitch(c->WL);
+    c->KB = 16;
+    c->cap = (int)((kConeLdsBudget - cone_lds_bytes(c->KB, 0, false)) / sizeof(float));
+    c->staged = (int64_t)(c->WV + 1) * c->pitch <= c->cap;   // windows through LDS, else direct reads
     std::vector<double> cs(2 * (size_t)c->K);
     for (int k = 0; k < c->K; ++k) {
         cs[2 * k] = std::cos(c->angles[k]);
@@ -1666,7 +1669,9 @@ int run_cone_backproject(const ConePlan& c, const float* filt, float* vol, hipSt
     j.Dv = c.Dv;
     j.WL = c.WL;
     j.WV = c.WV;
+    j.pitch = c.pitch;
     j.KB = c.KB;
+    j.cap = c.cap;
     j.tiles_x = (c.N + kConeTile - 1) / kConeTile;
     j.scale = (float)(2.0 * kPi / (double)c.K);
     const hipError_t e = launch_cone_bp(j, c.staged, s);
