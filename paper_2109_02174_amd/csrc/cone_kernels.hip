@@ -24,6 +24,7 @@
 #include "fbp_internal.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace fbp {
 
@@ -31,6 +32,55 @@ namespace {
 
 constexpr int kConeThreads = kConeTile * kConeTile;
 constexpr int kConeCoef = 12;                           // per-view floats in LDS
+
+// Copies units of G consecutive detector columns (G = 4: one 16-byte load and
+// LDS store; the window origins, Du, the pitch and the view base are then
+// multiples of four floats, so a unit lies wholly on or off the detector) of the
+// windows of views kq .. kq+3 into LDS, one unit per lane and view in flight.
+template <int G>
+__device__ __forceinline__ void cone_stage(const ConeJob& job, const int* org, float* win, int kq, int nk, int k0,
+                                           int pitch) {
+    using V = typename std::conditional<G == 4, float4, float>::type;
+    int i0[4], j0[4], ng[4], nr[4], units[4], off[4];
+    float inv_ng[4];
+    int most = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int kk = min(kq + u, nk - 1);
+        const int4 o = *reinterpret_cast<const int4*>(org + 8 * kk);
+        i0[u] = o.x;
+        j0[u] = o.y;
+        ng[u] = o.z / G;
+        nr[u] = o.w;
+        off[u] = org[8 * kk + 4];
+        units[u] = kq + u < nk ? ng[u] * nr[u] : 0;
+        inv_ng[u] = 1.0f / (float)ng[u];
+        most = max(most, units[u]);
+    }
+    for (int e = threadIdx.x; e < most; e += kConeThreads) {
+        V val[4];
+        int at[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            // unit e is (row e / ng, group e % ng); the quotient from a float
+            // reciprocal is exact: e < 2^16, and (e + 1/2) / ng is at least
+            // 1 / (2 ng) away from an integer
+            const int rr = (int)(((float)e + 0.5f) * inv_ng[u]);
+            const int cc = G * (e - __mul24(rr, ng[u]));
+            const int row = j0[u] + rr, col = i0[u] + cc;
+            at[u] = e < units[u] ? off[u] + __mul24(rr, pitch) + cc : -1;
+            const float* __restrict__ src = job.q + (size_t)(k0 + kq + u) * job.Dv * job.Du;
+            const unsigned gb = (unsigned)(__mul24(row, job.Du) + col) * 4u;   // < 2^28
+            if (e < units[u] && (unsigned)row < (unsigned)job.Dv && (unsigned)col < (unsigned)job.Du)
+                val[u] = *reinterpret_cast<const V*>(reinterpret_cast<const char*>(src) + gb);
+            else
+                val[u] = V{};
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (at[u] >= 0) *reinterpret_cast<V*>(win + at[u]) = val[u];
+    }
+}
 
 // STAGED: each view's detector window goes through LDS with a row pitch of P
 // floats (P = 0: the pitch is job.pitch; a fixed P lets the two rows of a bilinear
@@ -46,11 +96,14 @@ __global__ __launch_bounds__(kConeThreads) void cone_bp_kernel(ConeJob job) {
     const int KB = job.KB, N = job.N, K = job.K, Du = job.Du, Dv = job.Dv;
     const int pitch = P > 0 ? P : job.pitch;
     const int RW = job.WV + 1;                         // rows of the largest window
-    // per view: n0 n1 n2 cvj | d0 d1 d2 umax | vmax - - - (floats), then
-    // column origin, row origin, columns, rows (ints)
+    const int A = job.vec4 ? 4 : 1;                    // column alignment of the windows
+    // per view: n0 n1 n2 cvj | d0 d1 d2 umax | vmax - - - (floats); column
+    // origin, row origin, columns, rows, LDS offset, - - - (ints); then the
+    // number of views in the block
     float* coef = reinterpret_cast<float*>(smem);
     int* org = reinterpret_cast<int*>(coef + kConeCoef * KB);
-    float* win = reinterpret_cast<float*>(org + 4 * KB);
+    int* nk_lds = org + 8 * KB;
+    float* win = reinterpret_cast<float*>(nk_lds + 4);
     const int tiles = job.tiles_x * job.tiles_x;
     const int zb = blockIdx.x / tiles;
     const int tile = blockIdx.x - zb * tiles;
@@ -63,104 +116,94 @@ __global__ __launch_bounds__(kConeThreads) void cone_bp_kernel(ConeJob job) {
     const float fdx = (float)dx, fdy = (float)dy;
     const double zlo = (double)z0 - job.half_z, zhi = zlo + (double)(zn - 1);
     const float zlo_dv = (float)(zlo / job.dv), inv_dv = (float)(1.0 / job.dv);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float acc[kConeZB];
 #pragma unroll
     for (int q = 0; q < kConeZB; ++q) acc[q] = 0.0f;
     for (int k0 = 0; k0 < K;) {
         const int nmax = min(KB, K - k0);
         __syncthreads();                                // previous block's reads done
-        if ((int)threadIdx.x < nmax) {
-            // FP64, per view: the in-plane map (as the fan beam) and the window of
-            // detector cells the tile's voxels can reach.  u = N/L and rho = R/L are
-            // linear-fractional in (x, y), so over the tile their extremes sit at
-            // the corners; v = z rho / dv + cv is then extreme at a corner of
-            // (z, rho).  One cell of margin on each side covers FP32 rounding, and
-            // the clamps below keep every read inside the window regardless.
-            const int k = k0 + threadIdx.x;
-            const double c = job.cs[2 * k], sn = job.cs[2 * k + 1];
-            const double R = job.R, du = job.du;
-            const double xt = (double)c0 - job.half_pix, yt = (double)r0 - job.half_pix;
-            const double Lt = R - (c * xt + sn * yt);
-            const double Nt = R * (-sn * xt + c * yt);
-            double Lmin = INFINITY, Lmax = -INFINITY, umin = INFINITY, umax = -INFINITY;
-            for (int q = 0; q < 4; ++q) {
-                const double ex = (q & 1) ? (double)(cw - 1) : 0.0, ey = (q & 2) ? (double)(rh - 1) : 0.0;
-                const double L = Lt - c * ex - sn * ey;
-                const double u = (Nt + R * (-sn * ex + c * ey)) / (L * du);
-                Lmin = fmin(Lmin, L);
-                Lmax = fmax(Lmax, L);
-                umin = fmin(umin, u);
-                umax = fmax(umax, u);
+        if (threadIdx.x < 64) {                         // wave 0: one view per lane (KB <= 64)
+            int size = 0;
+            if ((int)threadIdx.x < nmax) {
+                // FP64, per view: the in-plane map (as the fan beam) and the window
+                // of detector cells the tile's voxels can reach.  u = N/L and
+                // rho = R/L are linear-fractional in (x, y), so over the tile their
+                // extremes sit at the corners; v = z rho / dv + cv is then extreme
+                // at a corner of (z, rho).  One cell of margin on each side covers
+                // FP32 rounding, and the clamps below keep every read inside the
+                // window regardless.
+                const int k = k0 + threadIdx.x;
+                const double c = job.cs[2 * k], sn = job.cs[2 * k + 1];
+                const double R = job.R, du = job.du;
+                const double xt = (double)c0 - job.half_pix, yt = (double)r0 - job.half_pix;
+                const double Lt = R - (c * xt + sn * yt);
+                const double Nt = R * (-sn * xt + c * yt);
+                double Lmin = INFINITY, Lmax = -INFINITY, umin = INFINITY, umax = -INFINITY;
+                for (int q = 0; q < 4; ++q) {
+                    const double ex = (q & 1) ? (double)(cw - 1) : 0.0, ey = (q & 2) ? (double)(rh - 1) : 0.0;
+                    const double L = Lt - c * ex - sn * ey;
+                    const double u = (Nt + R * (-sn * ex + c * ey)) / (L * du);
+                    Lmin = fmin(Lmin, L);
+                    Lmax = fmax(Lmax, L);
+                    umin = fmin(umin, u);
+                    umax = fmax(umax, u);
+                }
+                const double rlo = R / Lmax, rhi = R / Lmin;
+                const double vmin = fmin(fmin(zlo * rlo, zlo * rhi), fmin(zhi * rlo, zhi * rhi)) / job.dv;
+                const double vmax = fmax(fmax(zlo * rlo, zlo * rhi), fmax(zhi * rlo, zhi * rhi)) / job.dv;
+                // column origin rounded down to the alignment, width up to it
+                const int i0 = (int)floor(umin + job.cu) - 1;
+                const int i0a = i0 - (((i0 % A) + A) % A);
+                const int j0 = (int)floor(vmin + job.cv) - 1;
+                const int ncw = (int)floor(umax + job.cu) + 3 - i0a;
+                const int nc = min(pitch, (ncw + A - 1) / A * A);
+                const int nr = min(RW, (int)floor(vmax + job.cv) + 4 - j0);   // one more row: see the clamp
+                const double G = ((double)i0a - job.cu) * du;
+                const double a0 = Nt - G * Lt, a1 = -R * sn + G * c, a2 = R * c + G * sn;
+                float* cf = coef + kConeCoef * threadIdx.x;
+                cf[0] = (float)(a0 * job.inv_duR);
+                cf[1] = (float)(a1 * job.inv_duR);
+                cf[2] = (float)(a2 * job.inv_duR);
+                cf[3] = (float)(job.cv - (double)j0);
+                cf[4] = (float)(Lt * job.inv_R);
+                cf[5] = (float)(-c * job.inv_R);
+                cf[6] = (float)(-sn * job.inv_R);
+                cf[7] = (float)(nc - 2);
+                cf[8] = (float)(nr - 2);
+                int* og = org + 8 * threadIdx.x;
+                og[0] = i0a;
+                og[1] = j0;
+                og[2] = nc;
+                og[3] = nr;
+                size = nr * pitch;
             }
-            const double rlo = R / Lmax, rhi = R / Lmin;
-            const double vmin = fmin(fmin(zlo * rlo, zlo * rhi), fmin(zhi * rlo, zhi * rhi)) / job.dv;
-            const double vmax = fmax(fmax(zlo * rlo, zlo * rhi), fmax(zhi * rlo, zhi * rhi)) / job.dv;
-            const double i0 = floor(umin + job.cu) - 1.0, j0 = floor(vmin + job.cv) - 1.0;
-            const int nc = (int)fmin((double)pitch, floor(umax + job.cu) + 3.0 - i0);
-            const int nr = (int)fmin((double)RW, floor(vmax + job.cv) + 4.0 - j0);   // one more row: see the clamp
-            const double G = (i0 - job.cu) * du;
-            const double a0 = Nt - G * Lt, a1 = -R * sn + G * c, a2 = R * c + G * sn;
-            float* cf = coef + kConeCoef * threadIdx.x;
-            cf[0] = (float)(a0 * job.inv_duR);
-            cf[1] = (float)(a1 * job.inv_duR);
-            cf[2] = (float)(a2 * job.inv_duR);
-            cf[3] = (float)(job.cv - j0);
-            cf[4] = (float)(Lt * job.inv_R);
-            cf[5] = (float)(-c * job.inv_R);
-            cf[6] = (float)(-sn * job.inv_R);
-            cf[7] = (float)(nc - 2);
-            cf[8] = (float)(nr - 2);
-            int* og = org + 4 * threadIdx.x;
-            og[0] = (int)i0;
-            og[1] = (int)j0;
-            og[2] = nc;
-            og[3] = nr;
+            if constexpr (STAGED) {
+                // pack the windows: LDS offsets from a prefix sum over the lanes; the
+                // block takes the views whose windows end within cap (a prefix of them)
+                int incl = size;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int y = __shfl_up(incl, d, 64);
+                    if ((int)threadIdx.x >= d) incl += y;
+                }
+                if ((int)threadIdx.x < nmax) org[8 * threadIdx.x + 4] = incl - size;
+                const unsigned long long fit = __ballot((int)threadIdx.x < nmax && incl <= job.cap);
+                if (threadIdx.x == 0) nk_lds[0] = __popcll(fit);
+            }
         }
         __syncthreads();
         int nk = nmax;
         if constexpr (STAGED) {
-            // stage the windows (zero off the detector) while they fit: a wave
-            // covers 2^lg columns of 64 / 2^lg rows per load, four loads in flight
-            // per lane
-            int off = 0;
-            nk = 0;
-            for (int kk = 0; kk < nmax; ++kk) {
-                const int i0 = org[4 * kk], j0 = org[4 * kk + 1], nc = org[4 * kk + 2], nr = org[4 * kk + 3];
-                if (off + nr * pitch > job.cap) break;
-                const int lg = nc <= 16 ? 4 : (nc <= 32 ? 5 : 6);
-                const int rows = 64 >> lg;              // rows per wave and load
-                const int cc0 = lane & ((1 << lg) - 1);
-                const int rsub = wave * rows + (lane >> lg);
-                const int step = 4 * rows;              // rows per round of the four waves
-                const float* __restrict__ src = job.q + (size_t)(k0 + kk) * Dv * Du;
-                float* dst = win + off;
-                for (int cc = cc0; cc - cc0 < nc; cc += 1 << lg) {
-                    const int col = i0 + cc;
-                    const bool col_ok = cc < nc;
-                    const bool col_in = col_ok && (unsigned)col < (unsigned)Du;
-                    for (int rb = rsub; rb < nr; rb += 4 * step) {
-                        float val[4];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int rr = rb + u * step;
-                            const int row = j0 + rr;
-                            val[u] = (col_in && rr < nr && (unsigned)row < (unsigned)Dv) ? src[row * Du + col] : 0.0f;
-                        }
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int rr = rb + u * step;
-                            if (col_ok && rr < nr) dst[rr * pitch + cc] = val[u];
-                        }
-                    }
-                }
-                off += nr * pitch;
-                nk = kk + 1;
+            nk = nk_lds[0];
+            for (int kq = 0; kq < nk; kq += 4) {
+                if (job.vec4)
+                    cone_stage<4>(job, org, win, kq, nk, k0, pitch);
+                else
+                    cone_stage<1>(job, org, win, kq, nk, k0, pitch);
             }
             __syncthreads();
         }
         if (inside) {
-            int off = 0;
             for (int kk = 0; kk < nk; ++kk) {
                 const float4 nf = *reinterpret_cast<const float4*>(coef + kConeCoef * kk);
                 const float4 df = *reinterpret_cast<const float4*>(coef + kConeCoef * kk + 4);
@@ -178,8 +221,7 @@ __global__ __launch_bounds__(kConeThreads) void cone_bp_kernel(ConeJob job) {
                 if constexpr (STAGED) {
                     // byte offset of the sample's window column in LDS, kept in one
                     // register so each sample's address is one 24-bit multiply-add
-                    unsigned boff = (unsigned)((const char*)(win + off + iu) - smem);
-                    off += org[4 * kk + 3] * pitch;
+                    unsigned boff = (unsigned)((const char*)(win + org[8 * kk + 4] + iu) - smem);
                     asm volatile("" : "+v"(boff));
                     auto sample = [&](int q, float v) {
                         const int iv = (int)v;
@@ -203,8 +245,8 @@ __global__ __launch_bounds__(kConeThreads) void cone_bp_kernel(ConeJob job) {
                     }
                 } else {
                     const float* __restrict__ qv = job.q + (size_t)(k0 + kk) * Dv * Du;
-                    const int col = org[4 * kk] + iu;
-                    const int row0 = org[4 * kk + 1];
+                    const int col = org[8 * kk] + iu;
+                    const int row0 = org[8 * kk + 1];
                     auto at = [&](int cc, int rr) {
                         return ((unsigned)cc < (unsigned)Du && (unsigned)rr < (unsigned)Dv) ? qv[rr * Du + cc] : 0.0f;
                     };
@@ -253,16 +295,19 @@ hipError_t launch_pitch(int pitch, const ConeJob& job, dim3 grid, size_t lds, hi
 int cone_pitch(int WL) {
     for (int p : kConePitches)
         if (p >= WL + 1) return p;
-    return WL + 1;
+    return (WL + 4) / 4 * 4;
 }
 
 size_t cone_lds_bytes(int KB, int cap, bool staged) {
-    return sizeof(float) * kConeCoef * (size_t)KB + sizeof(int) * 4 * (size_t)KB +
+    return sizeof(float) * kConeCoef * (size_t)KB + sizeof(int) * 8 * (size_t)KB + sizeof(int) * 4 +
            (staged ? sizeof(float) * (size_t)cap : 0);
 }
 
 hipError_t launch_cone_bp(const ConeJob& job, bool staged, hipStream_t stream) {
-    if (job.KB < 1 || job.KB > kConeThreads || job.WL < 2 || job.WV < 2 || job.pitch < job.WL + 1)
+    if (job.KB < 1 || job.KB > 64 || job.WL < 2 || job.WV < 2 || job.pitch < job.WL + 1)
+        return hipErrorInvalidValue;
+    if (job.vec4 && (job.Du % 4 != 0 || job.pitch % 4 != 0 || job.pitch < job.WL + 7 ||
+                     reinterpret_cast<uintptr_t>(job.q) % 16 != 0))
         return hipErrorInvalidValue;
     if (staged && (int64_t)(job.WV + 1) * job.pitch > job.cap) return hipErrorInvalidValue;   // one window must fit
     const size_t lds = cone_lds_bytes(job.KB, job.cap, staged);

@@ -213,13 +213,16 @@ struct ConeJob {
     int32_t pitch;         // row pitch of a staged window in floats (>= WL + 1)
     int32_t KB;            // views whose windows a block computes (it stages those that fit)
     int32_t cap;           // LDS floats for the staged windows of a block (>= (WV + 1) pitch)
+    int32_t vec4;          // stage groups of four columns (Du, pitch multiples of 4, q 16-byte aligned,
+                           // pitch >= WL + 7 for the wider aligned windows)
     int32_t tiles_x;       // ceil(N / kConeTile)
     float scale;           // 2 pi / K
 };
 constexpr int kConeTile = 16;
 constexpr int kConeZB = 32;          // voxels in z per lane
 constexpr size_t kConeLdsBudget = 40 * 1024;   // four workgroups per CU
-// row pitch of the staged windows for a column bound WL (one of a fixed set, else WL + 1)
+// row pitch of the staged windows for a column bound WL (one of a fixed set, else
+// WL + 1 rounded up to a multiple of four)
 int cone_pitch(int WL);
 size_t cone_lds_bytes(int KB, int cap, bool staged);
 // staged: detector windows through LDS (cap floats, which must hold the largest

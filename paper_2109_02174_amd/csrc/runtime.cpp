@@ -1533,7 +1533,7 @@ int make_cone_plan(ConePlan* c) {
     if (!(c->half_span < 1e6) || !(span_v < 1e6)) return FBP_EUNSUPPORTED;
     c->WL = (int)std::ceil(2.0 * c->half_span) + 4;
     c->WV = (int)std::ceil(span_v) + 5;
-    c->pitch = cone_pitch(c->WL);
+    c->pitch = cone_pitch(c->Du % 4 == 0 ? c->WL + 6 : c->WL);   // room for windows aligned to four columns
     c->KB = 16;
     c->cap = (int)((kConeLdsBudget - cone_lds_bytes(c->KB, 0, false)) / sizeof(float));
     c->staged = (int64_t)(c->WV + 1) * c->pitch <= c->cap;   // windows through LDS, else direct reads
@@ -1672,6 +1672,8 @@ int run_cone_backproject(const ConePlan& c, const float* filt, float* vol, hipSt
     j.pitch = c.pitch;
     j.KB = c.KB;
     j.cap = c.cap;
+    j.vec4 = c.staged && c.Du % 4 == 0 && c.pitch % 4 == 0 && c.pitch >= c.WL + 7 &&
+             reinterpret_cast<uintptr_t>(filt) % 16 == 0;
     j.tiles_x = (c.N + kConeTile - 1) / kConeTile;
     j.scale = (float)(2.0 * kPi / (double)c.K);
     const hipError_t e = launch_cone_bp(j, c.staged, s);
