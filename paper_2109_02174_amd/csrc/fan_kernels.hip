@@ -181,11 +181,210 @@ __global__ __launch_bounds__(kFanThreads) void fan_bp_kernel(FanJob job) {
     }
 }
 
+// Quarter-turn views (K = 4 K4, b_{k + i K4} = b_k + i pi/2): turning a pixel by
+// +pi/2 about the centre, (x, y) -> (-y, x), and its view by +pi/2 leaves the
+// depth L and the detector coordinate s unchanged.  A workgroup owns a 16 x 16
+// tile of the top-left quadrant and its three turned copies R_j (j = 1..3).  Per
+// base view k < K4 a lane makes its pixel's maps at the four views k + m K4
+// (m = 0..3) and applies map m to R_j X at view k + ((m + j) mod 4) K4 for every
+// j: sixteen updates per four maps.  The four windows of map m (one per j, all
+// at map m's origin) sit side by side per bin, so one read at the map's window
+// index fetches the pairs of the four turned pixels (times M slices).  Each
+// output pixel sums its views in a fixed order (base views ascending, then m).
+template <int M>
+__global__ __launch_bounds__(kFanThreads) void fan_rot_kernel(FanJob job) {
+    extern __shared__ __align__(16) char smem[];
+    const int KB = job.KB, WL = job.WL, N = job.N, K = job.K, D = job.D;
+    const int K4 = K / 4, H = N / 2;
+    float* coef = reinterpret_cast<float*>(smem);                      // [KB][4 maps][8]
+    int* org = reinterpret_cast<int*>(coef + 32 * KB);                 // [KB][4 maps] window origins
+    float2* win = reinterpret_cast<float2*>(org + 4 * KB);             // [KB][4 maps][WL][4 turns][M]
+    const int tiles = job.tiles_x * job.tiles_x;                       // quadrant tiles
+    const int g = blockIdx.x / tiles;                                  // group of M slices, or view part
+    const int tile = blockIdx.x - g * tiles;
+    const int c0 = (tile % job.tiles_x) * kFanTile, r0 = (tile / job.tiles_x) * kFanTile;
+    const int dx = threadIdx.x & (kFanTile - 1), dy = threadIdx.x / kFanTile;
+    const bool inside = c0 + dx < H && r0 + dy < H;
+    const int cw = min(kFanTile, H - c0), rh = min(kFanTile, H - r0);   // pixels of the tile in the quadrant
+    const float fdx = (float)dx, fdy = (float)dy;
+    const size_t qstride = (size_t)K * D;
+    // split > 1 (one slice, M = 1): this workgroup sums the base views of part g only
+    const int kpart = (K4 + job.split - 1) / job.split;
+    const int kbeg = job.split > 1 ? g * kpart : 0;
+    const int kend = job.split > 1 ? min(K4, kbeg + kpart) : K4;
+    const float* __restrict__ qs = job.q + (job.split > 1 ? (size_t)0 : (size_t)g * M * qstride);
+    const float inv_wl = 1.0f / (float)WL;
+    float acc[4][M];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int m = 0; m < M; ++m) acc[j][m] = 0.0f;
+    for (int k0 = kbeg; k0 < kend; k0 += KB) {
+        const int nk = min(KB, kend - k0);
+        __syncthreads();                                               // previous block's reads done
+        if ((int)threadIdx.x < 4 * nk) {
+            // FP64: window origin and map of this tile at view k0 + kk + m K4, as in
+            // the one-view kernel
+            const int k = k0 + ((int)threadIdx.x >> 2) + ((int)threadIdx.x & 3) * K4;
+            const double c = job.cs[2 * k], sn = job.cs[2 * k + 1];
+            const double R = job.R, ds = job.ds, cd = job.centre_det;
+            const double xt = (double)c0 - job.half_pix, yt = (double)r0 - job.half_pix;
+            const double Lt = R - (c * xt + sn * yt);
+            const double Nt = R * (-sn * xt + c * yt);
+            const double ex = 0.5 * (double)(cw - 1), ey = 0.5 * (double)(rh - 1);
+            const double uc = (Nt + R * (-sn * ex + c * ey)) / ((Lt - c * ex - sn * ey) * ds) + cd;
+            const double i0 = floor(uc - job.half_span);
+            const double G = (i0 - cd) * ds;
+            const double a0 = Nt - G * Lt, a1 = -R * sn + G * c, a2 = R * c + G * sn;
+            const double inv = job.inv_dsR, ir = job.inv_R;
+            float* cf = coef + 8 * threadIdx.x;
+            cf[0] = (float)(a0 * inv);
+            cf[1] = (float)(a1 * inv);
+            cf[2] = (float)(a2 * inv);
+            cf[3] = 0.0f;
+            cf[4] = (float)(Lt * ir);
+            cf[5] = (float)(-c * ir);
+            cf[6] = (float)(-sn * ir);
+            cf[7] = 0.0f;
+            org[threadIdx.x] = (int)i0;
+        }
+        __syncthreads();
+        // windows: element e = ((kk 4 + m) WL + i) 4 + j holds bin org + i of view
+        // k0 + kk + ((m + j) mod 4) K4; (kk 4 + m, i) from a float reciprocal (exact:
+        // e / 4 < 4 KB WL, which the LDS budget keeps below 2^11; margin 0.5/WL);
+        // branch-free buffer loads over the slice's K D values (offsets of bins off
+        // the detector are past the end)
+#pragma unroll
+        for (int mm = 0; mm < M; ++mm) {
+            const __amdgpu_buffer_rsrc_t rows = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float*>(qs + mm * qstride), (short)0, (int)(qstride * 4), kRawF32);
+#pragma unroll 2
+            for (int e = threadIdx.x; e < nk * 16 * WL; e += kFanThreads) {
+                const int j = e & 3, e4 = e >> 2;
+                const int km = (int)(((float)e4 + 0.5f) * inv_wl), i = e4 - km * WL;
+                const int view = k0 + (km >> 2) + (((km & 3) + j) & 3) * K4;
+                const int bin = org[km] + i;
+                const int o = (view * D + bin) * 4;
+                const int oa = (unsigned)bin < (unsigned)D ? o : kPastEnd;
+                const int ob = (unsigned)(bin + 1) < (unsigned)D ? o + 4 : kPastEnd;
+                const float a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rows, oa, 0, 0));
+                const float b = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rows, ob, 0, 0));
+                const float dq = b - a;
+                win[e * M + mm] = make_float2(fmaf(-(float)i, dq, a), dq);
+            }
+        }
+        __syncthreads();
+        if (inside) {
+            const float umax = (float)(WL - 1);
+            for (int kk = 0; kk < nk; ++kk) {
+                float u[4], w[4];
+                const float4* pw[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {                          // the four maps first
+                    const float4 nf = *reinterpret_cast<const float4*>(coef + 8 * (4 * kk + m));
+                    const float4 df = *reinterpret_cast<const float4*>(coef + 8 * (4 * kk + m) + 4);
+                    const float den = fmaf(df.z, fdy, fmaf(df.y, fdx, df.x));
+                    const float num = fmaf(nf.z, fdy, fmaf(nf.y, fdx, nf.x));
+                    const float rho = __builtin_amdgcn_rcpf(den);      // R / L
+                    u[m] = num * rho;
+                    w[m] = rho * rho;
+                    const int i = (int)__builtin_amdgcn_fmed3f(u[m], 0.0f, umax);   // in the window whatever u holds
+                    pw[m] = reinterpret_cast<const float4*>(win + (size_t)((4 * kk + m) * WL + i) * 4 * M);
+                }
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    float4 v[2 * M];                                   // (A, dQ) of the 4 turns x M slices
+#pragma unroll
+                    for (int h = 0; h < 2 * M; ++h) v[h] = pw[m][h];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+                        for (int mm = 0; mm < M; ++mm) {
+                            const int f = j * M + mm;                  // pair f: float4 f / 2, half f % 2
+                            const float A = (f & 1) ? v[f >> 1].z : v[f >> 1].x;
+                            const float dQ = (f & 1) ? v[f >> 1].w : v[f >> 1].y;
+                            acc[j][mm] = fmaf(w[m], fmaf(u[m], dQ, A), acc[j][mm]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (inside) {
+        const int c = c0 + dx, r = r0 + dy;
+        // R_j (c, r): j = 1 (-y, x), j = 2 (-x, -y), j = 3 (y, -x) about the centre
+        const int cj[4] = {c, N - 1 - r, N - 1 - c, r};
+        const int rj[4] = {r, c, N - 1 - r, N - 1 - c};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const size_t pix = (size_t)rj[j] * N + cj[j];
+            if (job.split > 1) {
+                job.part[(size_t)g * N * N + pix] = acc[j][0];
+            } else {
+#pragma unroll
+                for (int mm = 0; mm < M; ++mm) job.img[((size_t)g * M + mm) * N * N + pix] = acc[j][mm] * job.scale;
+            }
+        }
+    }
+}
+
 }  // namespace
 
 size_t fan_lds_bytes(int KB, int WL, int M) {
     return sizeof(float) * 8 * (size_t)KB + sizeof(int) * (size_t)((KB + 3) & ~3) +
            sizeof(float) * 2 * (size_t)M * (size_t)KB * (size_t)WL;
+}
+
+bool fan_rot_addressable(int K, int D, int WL) {
+    // every byte offset the staging forms, (view D + bin) 4 with bin < D + WL,
+    // stays below the past-the-end offset
+    return ((int64_t)K * D + WL + 1) * 4 < (int64_t)kPastEnd;
+}
+
+size_t fan_rot_lds_bytes(int KB, int WL, int M) {
+    return sizeof(float) * 32 * (size_t)KB + sizeof(int) * 4 * (size_t)KB +
+           sizeof(float) * 2 * 16 * (size_t)M * (size_t)KB * (size_t)WL;
+}
+
+// Quarter-turn form (even N, K = 4 K4 with the views in quarter turns, K D 4 bytes
+// addressable by a buffer resource): groups of M slices, the rest one slice per
+// workgroup; a single slice may split its base views over job.split parts.
+hipError_t launch_fan_rot(const FanJob& job, int n_slices, int M, int KBm, hipStream_t stream) {
+    if (n_slices <= 0) return hipSuccess;
+    if ((job.N & 1) || (job.K & 3) || job.K < 4 || job.KB < 1 || 4 * job.KB > kFanThreads || job.WL < 2 ||
+        (M != 1 && M != 2 && M != 4) || (M > 1 && (KBm < 1 || 4 * KBm > kFanThreads)) ||
+        !fan_rot_addressable(job.K, job.D, job.WL) || job.tiles_x != (job.N / 2 + kFanTile - 1) / kFanTile)
+        return hipErrorInvalidValue;
+    const int64_t tiles = (int64_t)job.tiles_x * job.tiles_x;
+    const int grouped = (M > 1) ? n_slices - n_slices % M : 0;
+    if (grouped > 0) {
+        FanJob j = job;
+        j.KB = KBm;
+        j.split = 1;
+        const size_t lds = fan_rot_lds_bytes(KBm, job.WL, M);
+        const int64_t blocks = tiles * (grouped / M);
+        if (blocks > INT32_MAX || lds > kFanLdsBudget) return hipErrorInvalidValue;
+        const hipError_t e = (M == 2)
+            ? launch_kernel(fan_rot_kernel<2>, dim3((unsigned)blocks), dim3(kFanThreads), lds, stream, j)
+            : launch_kernel(fan_rot_kernel<4>, dim3((unsigned)blocks), dim3(kFanThreads), lds, stream, j);
+        if (e != hipSuccess) return e;
+    }
+    const int rest = n_slices - grouped;
+    if (rest == 0) return hipSuccess;
+    const size_t lds = fan_rot_lds_bytes(job.KB, job.WL, 1);
+    if (lds > kFanLdsBudget) return hipErrorInvalidValue;
+    if (job.split > 1) {                                               // one slice, base views split over parts
+        if (n_slices != 1 || M != 1 || !job.part || job.split > job.K / 4) return hipErrorInvalidValue;
+        const int64_t blocks = tiles * job.split;
+        if (blocks > INT32_MAX) return hipErrorInvalidValue;
+        return launch_kernel(fan_rot_kernel<1>, dim3((unsigned)blocks), dim3(kFanThreads), lds, stream, job);
+    }
+    FanJob j = job;
+    j.q = job.q + (size_t)grouped * job.K * job.D;
+    j.img = job.img + (size_t)grouped * job.N * job.N;
+    const int64_t blocks = tiles * rest;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    return launch_kernel(fan_rot_kernel<1>, dim3((unsigned)blocks), dim3(kFanThreads), lds, stream, j);
 }
 
 hipError_t launch_preweight(const float* in, float* out, const float* w, int64_t rows, int D, hipStream_t stream) {

@@ -182,6 +182,8 @@ struct Plan {
     float* d_fanw = nullptr;
     int fan_WL = 0, fan_KB = 0, fan_KB4 = 0;   // window pairs; views per block (one slice, four)
     int fan_split = 1;                          // view parts of a single slice
+    bool fan_rot = false;                       // quarter-turn form (a quadrant tile and its turns)
+    int fan_rot_KB = 0, fan_rot_M = 1, fan_rot_KBm = 0;   // its base views per block; stack group
     double fan_half_span = 0.0;
     // FFT filter path: twiddles and the taps' DFT for L = 2^fft_log2 (made on first use)
     float2* d_fft_tw = nullptr;
@@ -251,6 +253,27 @@ bool quarter_turn_symmetric(const std::vector<double>& angles) {
     const size_t h = K / 2;
     for (size_t k = 0; k < h; ++k)
         if (std::fabs(angles[k + h] - angles[k] - 0.5 * kPi) > 1e-12) return false;
+    return true;
+}
+
+// Quarter-turn fan beam: LDS per workgroup for the staged windows (small blocks:
+// more workgroups per CU hide the staging and barrier latency; 20 KB measured best
+// of 12-48 KB at 512^2 / 720 views), workgroups per CU a single slice's base-view
+// split aims at, stack groups tried (largest first).
+constexpr size_t kFanRotLds = 20 * 1024;
+constexpr int kFanRotWgsPerCu = 8;
+constexpr int kFanRotStackM[] = {4, 2};
+
+// Fan-beam views in quarter turns: K = 4 K4 and b_{k + i K4} = b_k + i pi/2 (mod 2 pi)
+// for every k < K4 and i = 1..3.
+bool fan_quarter_turns(const std::vector<double>& angles) {
+    const size_t K = angles.size();
+    if (K < 4 || (K & 3)) return false;
+    const size_t q = K / 4;
+    for (size_t k = 0; k < q; ++k)
+        for (size_t i = 1; i < 4; ++i)
+            if (std::fabs(std::remainder(angles[k + i * q] - angles[k] - 0.5 * kPi * (double)i, 2.0 * kPi)) > 1e-12)
+                return false;
     return true;
 }
 
@@ -451,11 +474,28 @@ int make_fan_plan(Plan* p) {
     p->fan_KB = (int)std::min<size_t>(64, (kFanLdsBudget - 64 * 36) / (8 * (size_t)p->fan_WL));
     if (p->fan_KB < 1) return FBP_EUNSUPPORTED;
     p->fan_KB4 = (int)std::min<size_t>(16, (kFanLdsBudget - 64 * 36) / (4 * 8 * (size_t)p->fan_WL));
-    // single slices: views split over enough parts for about 16 workgroups per CU,
-    // partial sums in planes owned by the plan (images up to 2048^2)
-    const int tiles = ((p->N + kFanTile - 1) / kFanTile) * ((p->N + kFanTile - 1) / kFanTile);
+    // quarter-turn form when the views come in quarter turns (N even): base views
+    // per block for one slice, and the largest stack group whose block fits
+    p->fan_rot = (p->N % 2 == 0) && fan_quarter_turns(p->angles) && fan_rot_addressable(p->K, p->D, p->fan_WL);
+    if (p->fan_rot) {
+        p->fan_rot_KB = (int)std::min<size_t>(64, kFanRotLds / fan_rot_lds_bytes(1, p->fan_WL, 1));
+        p->fan_rot = p->fan_rot_KB >= 1;
+        for (int m : kFanRotStackM) {
+            const int kb = (int)std::min<size_t>(64, kFanRotLds / fan_rot_lds_bytes(1, p->fan_WL, m));
+            if (kb >= 2) {
+                p->fan_rot_M = m;
+                p->fan_rot_KBm = kb;
+                break;
+            }
+        }
+    }
+    // single slices: views (base views) split over enough parts for about 16
+    // workgroups per CU, partial sums in planes owned by the plan (images up to 2048^2)
+    const int tx = p->fan_rot ? (p->N / 2 + kFanTile - 1) / kFanTile : (p->N + kFanTile - 1) / kFanTile;
+    const int tiles = tx * tx;
     const int cus = cu_count(p->device);
-    p->fan_split = std::max(1, std::min({kMaxSplit, p->K, (16 * cus + tiles / 2) / tiles}));
+    const int per_cu = p->fan_rot ? kFanRotWgsPerCu : 16;
+    p->fan_split = std::max(1, std::min({kMaxSplit, p->fan_rot ? p->K / 4 : p->K, (per_cu * cus + tiles / 2) / tiles}));
     const size_t plane = (size_t)p->N * p->N;
     if (p->fan_split > 1 && plane <= (size_t)2048 * 2048) {
         hipError_t e = hipMalloc(&p->part.ptr, sizeof(float) * plane * p->fan_split);
@@ -855,12 +895,17 @@ int run_fan_backproject(Plan& p, int32_t n, const float* filt, float* img, hipSt
     j.D = p.D;
     j.WL = p.fan_WL;
     j.KB = p.fan_KB;
-    j.tiles_x = (p.N + kFanTile - 1) / kFanTile;
+    j.tiles_x = p.fan_rot ? (p.N / 2 + kFanTile - 1) / kFanTile : (p.N + kFanTile - 1) / kFanTile;
     j.scale = (float)(2.0 * kPi / (double)p.K);
     j.part = nullptr;
     j.split = 1;
-    // stacks of 4 or more share each pixel's map over 4 slices per workgroup
-    const int M = (n >= kStackMinSlices && p.fan_KB4 >= 1) ? 4 : 1;
+    if (p.fan_rot) j.KB = p.fan_rot_KB;
+    auto launch = [&](const FanJob& jj, int ns, int m) {
+        return p.fan_rot ? launch_fan_rot(jj, ns, m, p.fan_rot_KBm, s) : launch_fan_bp(jj, ns, m, p.fan_KB4, s);
+    };
+    // stacks of 4 or more share each pixel's map over several slices per workgroup
+    const int M = p.fan_rot ? ((n >= kStackMinSlices && p.fan_rot_KBm >= 1) ? p.fan_rot_M : 1)
+                            : ((n >= kStackMinSlices && p.fan_KB4 >= 1) ? 4 : 1);
     if (M == 1 && p.fan_split > 1 && p.part.ptr) {
         // slice by slice, the views split over parts summed in a fixed order
         PartBuffer& pb = p.part;
@@ -872,7 +917,7 @@ int run_fan_backproject(Plan& p, int32_t n, const float* filt, float* img, hipSt
             ji.q = filt + i * qs;
             ji.part = pb.ptr;
             ji.split = p.fan_split;
-            hipError_t e = launch_fan_bp(ji, 1, 1, p.fan_KB4, s);
+            hipError_t e = launch(ji, 1, 1);
             if (e == hipSuccess) e = launch_combine_parts(pb.ptr, img + i * is, 1, p.fan_split, is, j.scale, s);
             if (e != hipSuccess)
                 return e == hipErrorInvalidValue ? FBP_EUNSUPPORTED : hip_status(e, "fan-beam backprojection launch");
@@ -881,7 +926,7 @@ int run_fan_backproject(Plan& p, int32_t n, const float* filt, float* img, hipSt
         pb.recorded = true;
         return FBP_OK;
     }
-    const hipError_t e = launch_fan_bp(j, n, M, p.fan_KB4, s);
+    const hipError_t e = launch(j, n, M);
     return e == hipErrorInvalidValue ? FBP_EUNSUPPORTED : hip_status(e, "fan-beam backprojection launch");
 }
 

@@ -56,6 +56,9 @@ def test_fan_filter_matches_oracle(kind, K, D, dt, R, B):
     (50, 161, 40, 1.0, 1.02, 1, "random"),      # source just outside the image corners
     (1, 77, 33, 1.0, 1.5, 2, "random"),         # one view
     (24, 300, 16, 0.25, 4.0, 1, "turn"),        # one tile, many bins per pixel
+    (120, 129, 70, 1.0, 1.6, 1, "turn"),        # quarter turns: quadrant tiles and their turns, ragged quadrant
+    (84, 161, 46, 0.8, 1.3, 6, "turn"),         # quarter turns, stack: a group of slices per workgroup and two single
+    (8, 95, 34, 1.0, 2.0, 3, "turn"),           # quarter turns, two base views, three slices one by one
 ])
 def test_fan_backprojection_matches_oracle(K, D, N, dt, Rf, B, kind):
     R = Rf * N / math.sqrt(2.0)
@@ -156,3 +159,24 @@ def test_fan_geometry_is_refused_where_unsupported():
     with pytest.raises(fbp.FbpError) as e:
         fbp.fbp_project(g, x)
     assert e.value.status == fbp.FBP_EUNSUPPORTED
+
+
+def test_fan_quarter_turn_form_matches_general_form():
+    """Views in quarter turns take the quadrant-and-turns kernel; the same views
+    listed with a 1e-9 rad perturbation (no longer quarter turns) take the one-tile
+    kernel.  Both agree with the oracle, and with each other within the FP32
+    tolerance."""
+    N, K, D, dt = 64, 120, 129, 1.0
+    R = 1.5 * N / math.sqrt(2.0)
+    b = np.arange(K, dtype=np.float64) * (2.0 * math.pi / K)
+    bp = b.copy()
+    bp[K // 4] += 1e-9
+    Q = ph.rng_for(1608, 0).normal(size=(2, K, D)).astype(np.float32)
+    ref = oracle.fan_backproject(Q.astype(np.float64), N, dt, R, b)
+    tol = _bp_tol(Q, N, R)
+    out = {}
+    for name, ang in (("turns", b), ("general", bp)):
+        g = fbp.Geometry(K, D, N, dt, ang, source_distance=R)
+        out[name] = fbp.fbp_backproject(g, torch.tensor(Q, device="cuda")).cpu().numpy()
+        assert np.max(np.abs(out[name] - ref)) <= tol, name
+    assert np.max(np.abs(out["turns"] - out["general"])) <= tol
