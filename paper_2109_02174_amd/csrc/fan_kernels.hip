@@ -107,9 +107,9 @@ __global__ __launch_bounds__(kFanThreads) void fan_bp_kernel(FanJob job) {
                 const_cast<float*>(qs + m * qstride + (size_t)k0 * D), (short)0, nk * D * 4, kRawF32);
 #pragma unroll 2
             for (int e = threadIdx.x; e < nk * WL; e += kFanThreads) {
-                const int kk = (int)(((float)e + 0.5f) * inv_wl), i = e - kk * WL;
+                const int kk = (int)(((float)e + 0.5f) * inv_wl), i = e - __mul24(kk, WL);
                 const int bin = org[kk] + i;
-                const int o = (kk * D + bin) * 4;
+                const int o = (__mul24(kk, D) + bin) * 4;
                 const int oa = (unsigned)bin < (unsigned)D ? o : kPastEnd;
                 const int ob = (unsigned)(bin + 1) < (unsigned)D ? o + 4 : kPastEnd;
                 const float a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rows, oa, 0, 0));
@@ -249,28 +249,44 @@ __global__ __launch_bounds__(kFanThreads) void fan_rot_kernel(FanJob job) {
             org[threadIdx.x] = (int)i0;
         }
         __syncthreads();
-        // windows: element e = ((kk 4 + m) WL + i) 4 + j holds bin org + i of view
-        // k0 + kk + ((m + j) mod 4) K4; (kk 4 + m, i) from a float reciprocal (exact:
-        // e / 4 < 4 KB WL, which the LDS budget keeps below 2^11; margin 0.5/WL);
-        // branch-free buffer loads over the slice's K D values (offsets of bins off
-        // the detector are past the end)
+        // windows: (map km = kk 4 + m, bin index i) holds, for the four turns j, the
+        // pairs of bin org + i of view k0 + kk + ((m + j) mod 4) K4 (times M slices)
+        // side by side; (km, i) from a float reciprocal (exact: km WL + i < 4 KB WL,
+        // which the LDS budget keeps below 2^11; margin 0.5/WL).  Branch-free buffer
+        // loads over each slice's K D values (offsets of bins off the detector are
+        // past the end), 8 M in flight per lane.
+        {
+            __amdgpu_buffer_rsrc_t rows[M];
 #pragma unroll
-        for (int mm = 0; mm < M; ++mm) {
-            const __amdgpu_buffer_rsrc_t rows = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<float*>(qs + mm * qstride), (short)0, (int)(qstride * 4), kRawF32);
-#pragma unroll 2
-            for (int e = threadIdx.x; e < nk * 16 * WL; e += kFanThreads) {
-                const int j = e & 3, e4 = e >> 2;
-                const int km = (int)(((float)e4 + 0.5f) * inv_wl), i = e4 - km * WL;
-                const int view = k0 + (km >> 2) + (((km & 3) + j) & 3) * K4;
+            for (int mm = 0; mm < M; ++mm)
+                rows[mm] = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(qs + mm * qstride), (short)0,
+                                                             (int)(qstride * 4), kRawF32);
+            for (int e4 = threadIdx.x; e4 < 4 * nk * WL; e4 += kFanThreads) {
+                const int km = (int)(((float)e4 + 0.5f) * inv_wl);
+                const int i = e4 - __mul24(km, WL);
                 const int bin = org[km] + i;
-                const int o = (view * D + bin) * 4;
-                const int oa = (unsigned)bin < (unsigned)D ? o : kPastEnd;
-                const int ob = (unsigned)(bin + 1) < (unsigned)D ? o + 4 : kPastEnd;
-                const float a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rows, oa, 0, 0));
-                const float b = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rows, ob, 0, 0));
-                const float dq = b - a;
-                win[e * M + mm] = make_float2(fmaf(-(float)i, dq, a), dq);
+                const bool va = (unsigned)bin < (unsigned)D, vb = (unsigned)(bin + 1) < (unsigned)D;
+                const int m = km & 3, kb = k0 + (km >> 2);
+                const float fi = (float)i;
+                float2 pr[4][M];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int o = (__mul24(kb + __mul24((m + j) & 3, K4), D) + bin) * 4;   // below kPastEnd
+                    const int oa = va ? o : kPastEnd, ob = vb ? o + 4 : kPastEnd;
+#pragma unroll
+                    for (int mm = 0; mm < M; ++mm) {
+                        const float a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rows[mm], oa, 0, 0));
+                        const float b = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rows[mm], ob, 0, 0));
+                        const float dq = b - a;
+                        pr[j][mm] = make_float2(fmaf(-fi, dq, a), dq);
+                    }
+                }
+                float4* dst = reinterpret_cast<float4*>(win + (size_t)e4 * 4 * M);
+#pragma unroll
+                for (int h = 0; h < 2 * M; ++h) {
+                    const float2 x = pr[(2 * h) / M][(2 * h) % M], y = pr[(2 * h + 1) / M][(2 * h + 1) % M];
+                    dst[h] = make_float4(x.x, x.y, y.x, y.y);
+                }
             }
         }
         __syncthreads();
