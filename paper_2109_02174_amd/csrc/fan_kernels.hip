@@ -188,9 +188,10 @@ __global__ __launch_bounds__(kFanThreads) void fan_bp_kernel(FanJob job) {
 // base view k < K4 a lane makes its pixel's maps at the four views k + m K4
 // (m = 0..3) and applies map m to R_j X at view k + ((m + j) mod 4) K4 for every
 // j: sixteen updates per four maps.  The four windows of map m (one per j, all
-// at map m's origin) sit side by side per bin, so one read at the map's window
-// index fetches the pairs of the four turned pixels (times M slices).  Each
-// output pixel sums its views in a fixed order (base views ascending, then m).
+// at map m's origin) are interleaved two pairs per float4 plane, so 2M reads at
+// the map's window index fetch the pairs of the four turned pixels (times M
+// slices).  Each output pixel sums its views in a fixed order (base views
+// ascending, then m).
 template <int M>
 __global__ __launch_bounds__(kFanThreads) void fan_rot_kernel(FanJob job) {
     extern __shared__ __align__(16) char smem[];
@@ -198,7 +199,9 @@ __global__ __launch_bounds__(kFanThreads) void fan_rot_kernel(FanJob job) {
     const int K4 = K / 4, H = N / 2;
     float* coef = reinterpret_cast<float*>(smem);                      // [KB][4 maps][8]
     int* org = reinterpret_cast<int*>(coef + 32 * KB);                 // [KB][4 maps] window origins
-    float2* win = reinterpret_cast<float2*>(org + 4 * KB);             // [KB][4 maps][WL][4 turns][M]
+    // [KB][4 maps][2M planes][WL] float4: plane h holds pairs 2h, 2h+1 of the
+    // (turn j, slice) list j M + slice, so lanes at consecutive bins read 16-byte strides
+    float4* win = reinterpret_cast<float4*>(org + 4 * KB);
     const int tiles = job.tiles_x * job.tiles_x;                       // quadrant tiles
     const int g = blockIdx.x / tiles;                                  // group of M slices, or view part
     const int tile = blockIdx.x - g * tiles;
@@ -251,7 +254,7 @@ __global__ __launch_bounds__(kFanThreads) void fan_rot_kernel(FanJob job) {
         __syncthreads();
         // windows: (map km = kk 4 + m, bin index i) holds, for the four turns j, the
         // pairs of bin org + i of view k0 + kk + ((m + j) mod 4) K4 (times M slices)
-        // side by side; (km, i) from a float reciprocal (exact: km WL + i < 4 KB WL,
+        // in the 2M planes of map km; (km, i) from a float reciprocal (exact: km WL + i < 4 KB WL,
         // which the LDS budget keeps below 2^11; margin 0.5/WL).  Branch-free buffer
         // loads over each slice's K D values (offsets of bins off the detector are
         // past the end), 8 M in flight per lane.
@@ -281,11 +284,11 @@ __global__ __launch_bounds__(kFanThreads) void fan_rot_kernel(FanJob job) {
                         pr[j][mm] = make_float2(fmaf(-fi, dq, a), dq);
                     }
                 }
-                float4* dst = reinterpret_cast<float4*>(win + (size_t)e4 * 4 * M);
+                float4* dst = win + (size_t)km * 2 * M * WL + i;
 #pragma unroll
                 for (int h = 0; h < 2 * M; ++h) {
                     const float2 x = pr[(2 * h) / M][(2 * h) % M], y = pr[(2 * h + 1) / M][(2 * h + 1) % M];
-                    dst[h] = make_float4(x.x, x.y, y.x, y.y);
+                    dst[h * WL] = make_float4(x.x, x.y, y.x, y.y);
                 }
             }
         }
@@ -305,13 +308,13 @@ __global__ __launch_bounds__(kFanThreads) void fan_rot_kernel(FanJob job) {
                     u[m] = num * rho;
                     w[m] = rho * rho;
                     const int i = (int)__builtin_amdgcn_fmed3f(u[m], 0.0f, umax);   // in the window whatever u holds
-                    pw[m] = reinterpret_cast<const float4*>(win + (size_t)((4 * kk + m) * WL + i) * 4 * M);
+                    pw[m] = win + (size_t)(4 * kk + m) * 2 * M * WL + i;
                 }
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     float4 v[2 * M];                                   // (A, dQ) of the 4 turns x M slices
 #pragma unroll
-                    for (int h = 0; h < 2 * M; ++h) v[h] = pw[m][h];
+                    for (int h = 0; h < 2 * M; ++h) v[h] = pw[m][h * WL];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
 #pragma unroll
