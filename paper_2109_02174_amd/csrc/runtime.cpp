@@ -256,11 +256,13 @@ bool quarter_turn_symmetric(const std::vector<double>& angles) {
     return true;
 }
 
-// Quarter-turn fan beam: LDS per workgroup for the staged windows (small blocks:
-// more workgroups per CU hide the staging and barrier latency; 20 KB measured best
-// of 12-48 KB at 512^2 / 720 views), workgroups per CU a single slice's base-view
-// split aims at, stack groups tried (largest first).
+// Quarter-turn fan beam: LDS per workgroup for the staged windows of one slice
+// (small blocks: more workgroups per CU hide the staging and barrier latency; 20 KB
+// measured best of 16-48 KB at 512^2 / 720 views) and of a stack group (40 KB: two
+// base views of four slices), workgroups per CU a single slice's base-view split
+// aims at, stack groups tried (largest first).
 constexpr size_t kFanRotLds = 20 * 1024;
+constexpr size_t kFanRotLdsStack = 40 * 1024;
 constexpr int kFanRotWgsPerCu = 8;
 constexpr int kFanRotStackM[] = {4, 2};
 
@@ -481,7 +483,7 @@ int make_fan_plan(Plan* p) {
         p->fan_rot_KB = (int)std::min<size_t>(64, kFanRotLds / fan_rot_lds_bytes(1, p->fan_WL, 1));
         p->fan_rot = p->fan_rot_KB >= 1;
         for (int m : kFanRotStackM) {
-            const int kb = (int)std::min<size_t>(64, kFanRotLds / fan_rot_lds_bytes(1, p->fan_WL, m));
+            const int kb = (int)std::min<size_t>(64, kFanRotLdsStack / fan_rot_lds_bytes(1, p->fan_WL, m));
             if (kb >= 2) {
                 p->fan_rot_M = m;
                 p->fan_rot_KBm = kb;
