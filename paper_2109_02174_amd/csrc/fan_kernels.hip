@@ -47,7 +47,9 @@ __global__ __launch_bounds__(kFanThreads) void fan_bp_kernel(FanJob job) {
     const int KB = job.KB, WL = job.WL, N = job.N, K = job.K, D = job.D;
     float* coef = reinterpret_cast<float*>(smem);                      // [KB][8]
     int* org = reinterpret_cast<int*>(coef + 8 * KB);                  // [KB] window origins
-    float2* win = reinterpret_cast<float2*>(org + ((KB + 3) & ~3));    // [KB][WL][M] (A_i, dQ_i)
+    // (A_i, dQ_i) pairs: M = 1 [KB][WL]; M > 1 [KB][M/2 planes][WL] float4 holding
+    // slices 2h, 2h+1, so lanes at consecutive bins read 16-byte strides
+    float2* win = reinterpret_cast<float2*>(org + ((KB + 3) & ~3));
     const int tiles = job.tiles_x * job.tiles_x;
     const int g = blockIdx.x / tiles;                                  // group of M slices, or view part
     const int tile = blockIdx.x - g * tiles;
@@ -115,7 +117,8 @@ __global__ __launch_bounds__(kFanThreads) void fan_bp_kernel(FanJob job) {
                 const float a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rows, oa, 0, 0));
                 const float b = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rows, ob, 0, 0));
                 const float dq = b - a;
-                win[e * M + m] = make_float2(fmaf(-(float)i, dq, a), dq);
+                const int at = M == 1 ? e : ((kk * (M / 2) + m / 2) * WL + i) * 2 + (m & 1);
+                win[at] = make_float2(fmaf(-(float)i, dq, a), dq);
             }
         }
         __syncthreads();
@@ -131,7 +134,8 @@ __global__ __launch_bounds__(kFanThreads) void fan_bp_kernel(FanJob job) {
                 u = num * rho;
                 w = rho * rho;
                 const int i = (int)__builtin_amdgcn_fmed3f(u, 0.0f, umax);   // in the window whatever u holds
-                return win + (size_t)(kk * WL + i) * M;                // the M slices' pairs, together
+                return M == 1 ? win + (size_t)kk * WL + i                // pair, or first plane of the M slices
+                              : win + ((size_t)kk * (M / 2) * WL + i) * 2;
             };
             auto fetch = [&](const float2* pw, float2 (&p)[M]) {
                 if constexpr (M == 1) {
@@ -139,7 +143,7 @@ __global__ __launch_bounds__(kFanThreads) void fan_bp_kernel(FanJob job) {
                 } else {
 #pragma unroll
                     for (int h = 0; h < M / 2; ++h) {                  // 16-byte reads, two slices each
-                        const float4 v = reinterpret_cast<const float4*>(pw)[h];
+                        const float4 v = reinterpret_cast<const float4*>(pw)[h * WL];
                         p[2 * h] = make_float2(v.x, v.y);
                         p[2 * h + 1] = make_float2(v.z, v.w);
                     }
