@@ -115,3 +115,15 @@ def test_cone_unaligned_views_match_oracle():
     assert np.max(np.abs(got - ref)) <= tol
     aligned = fbp.fbp_cone_backproject(g, torch.tensor(Q, device="cuda")).cpu().numpy()
     assert np.max(np.abs(aligned - ref)) <= tol
+
+
+@pytest.mark.parametrize("K,Dv,Du,N,Nz", [(4, 1, 1, 1, 1), (3, 1, 5, 2, 1), (6, 4, 1, 3, 2), (2, 2, 8, 1, 33)])
+def test_cone_degenerate_sizes(K, Dv, Du, N, Nz):
+    """One voxel, one slice, one detector row or column: still the oracle's values."""
+    R = 3.0 + N
+    b = _views(K, "random", K + Dv + Du)
+    g = fbp.ConeGeometry(K, Du, Dv, N, Nz, R, 1.0, 1.0, b)
+    Q = ph.rng_for(1806, K + N).normal(size=(K, Dv, Du)).astype(np.float32)
+    got = fbp.fbp_cone_backproject(g, torch.tensor(Q, device="cuda")).cpu().numpy()
+    ref = oracle.cone_backproject(Q.astype(np.float64), N, Nz, 1.0, 1.0, R, b)
+    assert np.max(np.abs(got - ref)) <= _tol(Q, N, Nz, 1.0, R)

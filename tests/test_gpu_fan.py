@@ -180,3 +180,19 @@ def test_fan_quarter_turn_form_matches_general_form():
         out[name] = fbp.fbp_backproject(g, torch.tensor(Q, device="cuda")).cpu().numpy()
         assert np.max(np.abs(out[name] - ref)) <= tol, name
     assert np.max(np.abs(out["turns"] - out["general"])) <= tol
+
+
+def test_fan_degenerate_sizes():
+    """Zero slices are a no-op; the smallest images (one pixel; two pixels, the
+    smallest quarter-turn quadrant) and a one-bin detector agree with the oracle."""
+    g = fbp.Geometry(8, 5, 4, 1.0, source_distance=6.0)
+    for fn, shape in ((fbp.fbp_filter, (0, 8, 5)), (fbp.fbp_backproject, (0, 4, 4)), (fbp.fbp_reconstruct, (0, 4, 4))):
+        assert fn(g, torch.zeros((0, 8, 5), device="cuda")).shape == shape
+    for K, D, N, kind in ((4, 3, 1, "turn"), (8, 5, 2, "turn"), (12, 1, 2, "turn"), (5, 4, 2, "random")):
+        R = 3.0 + N
+        b = _views(K, kind, K + D + N)
+        g = fbp.Geometry(K, D, N, 1.0, b, source_distance=R)
+        Q = ph.rng_for(1609, K + D).normal(size=(2, K, D)).astype(np.float32)
+        got = fbp.fbp_backproject(g, torch.tensor(Q, device="cuda")).cpu().numpy()
+        ref = oracle.fan_backproject(Q.astype(np.float64), N, 1.0, R, b)
+        assert np.max(np.abs(got - ref)) <= _bp_tol(Q, N, R), (K, D, N)
