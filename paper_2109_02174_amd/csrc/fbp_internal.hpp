@@ -251,6 +251,7 @@ struct FftJob {
     const float* H;       // [L]: DFT of the taps t(d), |d| <= D-1, times (output scale) / L
     int32_t R, D;
     int32_t log2L;
+    const float* colw;    // [D] factor per column applied on load, or null
 };
 constexpr int kFftMaxLog2 = 13;   // L <= 8192 (LDS of 64 KiB): D <= 4096
 int fft_length_log2(int D);
@@ -272,6 +273,8 @@ struct GemmJob {
     int32_t full;         // 1: the kernel has even taps too (te(j) = tap(2j) in taps_even,
                           //    same indexing); diag is then 0 and the centre tap is te(0)
     const void* taps_even;
+    const float* colw;    // [D] factor per input column applied to P before the product
+                          // (fan-beam pre-weights), or null
 };
 static_assert(sizeof(GemmJob) % 8 == 0, "GemmJob layout");
 

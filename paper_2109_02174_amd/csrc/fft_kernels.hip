@@ -56,9 +56,10 @@ __global__ __launch_bounds__(fft_threads(LOG2L)) void fft_filter_kernel(FftJob j
     const float* __restrict__ pb = job.p + (size_t)(has_b ? rb : ra) * D;
     const float2* __restrict__ tw = job.tw;
 
-    for (int n = t; n < L; n += kFftThreads) {
-        const float a = n < D ? pa[n] : 0.0f;
-        const float b = (has_b && n < D) ? pb[n] : 0.0f;
+    for (int n = t; n < L; n += kFftThreads) {                  // column weights (if any) applied on load
+        const float w = (job.colw && n < D) ? job.colw[n] : 1.0f;
+        const float a = n < D ? pa[n] * w : 0.0f;
+        const float b = (has_b && n < D) ? pb[n] * w : 0.0f;
         buf[n] = make_float2(a, b);
     }
     if constexpr (kLdsTw) {

@@ -77,6 +77,18 @@ __device__ __forceinline__ float load_elem(__amdgpu_buffer_rsrc_t rows, int row,
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rows, off, 0, 0));
 }
 
+// Column weights (job.colw: one factor per input column, applied to P before the
+// product, e.g. the fan-beam cosine pre-weights); columns past D read 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t col_weights(const GemmJob& job) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(job.colw), (short)0, job.colw ? job.D * 4 : 0,
+                                             kBufWord3);
+}
+
+__device__ __forceinline__ float load_weight(const GemmJob& job, __amdgpu_buffer_rsrc_t wcol, int col) {
+    if (!job.colw) return 1.0f;
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(wcol, col * 4, 0, 0));
+}
+
 // Epilogue: lane l of a 16x16 block holds rows 4 (l/16) + i, column l % 16.
 template <int PREC>
 __device__ __forceinline__ void store_block(const v4f& acc, const GemmJob& job, int row0, int nh0, int sg) {
@@ -88,7 +100,10 @@ __device__ __forceinline__ void store_block(const v4f& acc, const GemmJob& job, 
         const int m = row0 + 4 * (l >> 4) + i;
         if (m < job.R) {
             float v = acc[i];
-            if (!job.full) v = fmaf(job.diag, round_operand<PREC>(job.p[(size_t)m * job.D + n]), v);
+            if (!job.full) {
+                const float pv = job.p[(size_t)m * job.D + n] * (job.colw ? job.colw[n] : 1.0f);
+                v = fmaf(job.diag, round_operand<PREC>(pv), v);
+            }
             job.q[(size_t)m * job.D + n] = v * job.out_scale;
         }
     }
@@ -130,21 +145,25 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
 
     // ring of kPD chunks of 64 input columns in registers: chunk c + kPD - 1 is
     // loaded while chunk c is multiplied, hiding several chunks of load latency
-    float pf[kPD][8];
+    // ring entry: a thread's 8 elements of a chunk (all in column c0 + t % 64) and
+    // that column's weight (1 without column weights: the product is then exact)
+    float pf[kPD][9];
     const __amdgpu_buffer_rsrc_t prow = tile_rows(P, m0, min(kTM, R - m0), D);
-    auto load = [&](float (&r)[8], int c0) {   // columns c0 .. c0+63 of rows m0 .. m0+31
+    const __amdgpu_buffer_rsrc_t wcol = col_weights(job);
+    auto load = [&](float (&r)[9], int c0) {   // columns c0 .. c0+63 of rows m0 .. m0+31
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int e = t + i * kBpThreads;
             r[i] = load_elem(prow, e >> 6, c0 + (e & 63), D);
         }
+        r[8] = load_weight(job, wcol, c0 + (t & 63));
     };
-    auto store = [&](const float (&r)[8], float* Ab) {
+    auto store = [&](const float (&r)[9], float* Ab) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int e = t + i * kBpThreads;
             const int row = e >> 6, col = e & 63;
-            Ab[((col & 1) * kTM + row) * kAS32 + (col >> 1)] = r[i];
+            Ab[((col & 1) * kTM + row) * kAS32 + (col >> 1)] = r[i] * r[8];
         }
     };
 
@@ -252,22 +271,26 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
         }
     }
 
-    float pf[kPD16][16];
+    // ring entry: a thread's 16 elements of a chunk (all in column c0 + t % 128) and
+    // that column's weight (1 without column weights)
+    float pf[kPD16][17];
     const __amdgpu_buffer_rsrc_t prow = tile_rows(P, m0, min(kTM, R - m0), D);
-    auto load = [&](float (&r)[16], int c0) {   // columns c0 .. c0+127 of rows m0 .. m0+31
+    const __amdgpu_buffer_rsrc_t wcol = col_weights(job);
+    auto load = [&](float (&r)[17], int c0) {   // columns c0 .. c0+127 of rows m0 .. m0+31
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int e = t + i * kBpThreads;
             r[i] = load_elem(prow, e >> 7, c0 + (e & 127), D);
         }
+        r[16] = load_weight(job, wcol, c0 + (t & 127));
     };
-    auto store = [&](const float (&r)[16], unsigned short* Ab) {
+    auto store = [&](const float (&r)[17], unsigned short* Ab) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int e = t + i * kBpThreads;
             const int row = e >> 7, col = e & 127;
-            Ab[((col & 1) * kTM + row) * kAS16 + (col >> 1)] =
-                (PREC == kBF16) ? to_bf16_rne(r[i]) : to_f16_rne(r[i]);
+            const float x = r[i] * r[16];
+            Ab[((col & 1) * kTM + row) * kAS16 + (col >> 1)] = (PREC == kBF16) ? to_bf16_rne(x) : to_f16_rne(x);
         }
     };
 

@@ -147,7 +147,7 @@ struct ProjScratch {
     std::mutex mu;
 };
 
-// Stream-ordered scratch rows owned by a plan (fan-beam pre-weighted views): up
+// Stream-ordered scratch rows owned by a plan (cone-beam pre-weighted views): up
 // to `rows` rows of D floats at a time, shared by calls like PartBuffer.
 struct RowScratch {
     float* ptr = nullptr;
@@ -176,7 +176,7 @@ struct Plan {
     PartBuffer part;
     ProjScratch proj;
     // fan beam (R > 0): source distance, FP64 (cos b, sin b), pre-weights per bin,
-    // backprojection window bound and view block, pre-weighted view scratch
+    // backprojection window bound and view block
     double R = 0.0;
     double* d_fcs = nullptr;
     float* d_fanw = nullptr;
@@ -189,7 +189,6 @@ struct Plan {
     float2* d_fft_tw = nullptr;
     float* d_fft_H = nullptr;
     int fft_log2 = -1;
-    RowScratch fanrows;
     std::mutex mu;
 };
 
@@ -525,7 +524,6 @@ int make_fan_plan(Plan* p) {
     if (e == hipSuccess) e = hipMalloc(&p->d_fanw, sizeof(float) * w.size());
     if (e == hipSuccess) e = hipMemcpy(p->d_fcs, fcs.data(), sizeof(double) * fcs.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_fanw, w.data(), sizeof(float) * w.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fanrows.free_ev, hipEventDisableTiming);
     if (e != hipSuccess) {
         if (p->d_fcs) (void)hipFree(p->d_fcs);
         if (p->d_fanw) (void)hipFree(p->d_fanw);
@@ -830,7 +828,8 @@ BpJob bp_job(const Plan& p, const ShapeParams& sh, const float* filt, float* img
 int hip_status(hipError_t e, const char* what) { return e == hipSuccess ? FBP_OK : hip_fail(e, what); }
 
 // rows x D: the GEMM in the operand precision, or the FFT path.
-hipError_t launch_filter_rows(const Plan& p, int prec, const float* in, float* out, int rows, hipStream_t s) {
+hipError_t launch_filter_rows(const Plan& p, int prec, const float* in, float* out, int rows, hipStream_t s,
+                              const float* colw = nullptr) {
     if (prec == kFFT32) {
         FftJob j{};
         j.p = in;
@@ -840,38 +839,19 @@ hipError_t launch_filter_rows(const Plan& p, int prec, const float* in, float* o
         j.R = rows;
         j.D = p.D;
         j.log2L = p.fft_log2;
+        j.colw = colw;
         return launch_fft_filter(j, s);
     }
-    return launch_gemm_grid(prec, gemm_job(p, prec, in, out, rows), s);
+    GemmJob j = gemm_job(p, prec, in, out, rows);
+    j.colw = colw;
+    return launch_gemm_grid(prec, j, s);
 }
 
-// Fan beam: the views are pre-weighted into the plan's scratch rows (at most
-// 64 MiB of them at a time, at least one slice) and filtered from there.
+// Fan beam: the cosine pre-weights R / sqrt(R^2 + s^2) are column weights of the
+// filter kernels, applied to each value as it is loaded (the same FP32 product a
+// separate pre-weighting pass would store).
 int run_fan_filter(Plan& p, int prec, int32_t n, const float* sino, float* filt, hipStream_t s) {
-    RowScratch& rs = p.fanrows;
-    std::lock_guard<std::mutex> lock(rs.mu);
-    if (!rs.ptr) {
-        const int64_t per_slice = (int64_t)p.K * p.D;
-        const int64_t slices = std::max<int64_t>(1, ((int64_t)64 << 20) / (4 * per_slice));
-        const hipError_t e = hipMalloc(&rs.ptr, sizeof(float) * (size_t)(slices * per_slice));
-        if (e != hipSuccess) {
-            rs.ptr = nullptr;
-            return hip_fail(e, "hipMalloc (fan-beam scratch)", FBP_ENOMEM);
-        }
-        rs.rows = slices * p.K;
-    }
-    if (rs.recorded) FBP_TRY_HIP(hipStreamWaitEvent(s, rs.free_ev, 0));
-    const int64_t chunk = rs.rows / p.K;
-    for (int64_t i0 = 0; i0 < n; i0 += chunk) {
-        const int64_t m = std::min<int64_t>(chunk, n - i0);
-        const size_t off = (size_t)i0 * p.K * p.D;
-        hipError_t e = launch_preweight(sino + off, rs.ptr, p.d_fanw, m * p.K, p.D, s);
-        if (e == hipSuccess) e = launch_filter_rows(p, prec, rs.ptr, filt + off, (int)(m * p.K), s);
-        if (e != hipSuccess) return hip_status(e, "fan-beam filter launch");
-    }
-    FBP_TRY_HIP(hipEventRecord(rs.free_ev, s));
-    rs.recorded = true;
-    return FBP_OK;
+    return hip_status(launch_filter_rows(p, prec, sino, filt, n * p.K, s, p.d_fanw), "fan-beam filter launch");
 }
 
 int run_filter(Plan& p, int prec, int32_t n, const float* sino, float* filt, hipStream_t s) {

@@ -135,7 +135,8 @@ def test_fan_single_slices_on_two_streams():
 
 
 def test_fan_scratch_is_ordered_across_streams():
-    # the pre-weighted views go through one scratch buffer per plan
+    # filter calls of one plan on two streams (the pre-weights are applied as the
+    # filter loads each value) give every slice its own result
     N, K, D = 48, 90, 101
     g = fbp.Geometry(K, D, N, 1.0, source_distance=1.5 * N / math.sqrt(2.0))
     P = torch.tensor(ph.rng_for(1606, 0).normal(size=(6, K, D)).astype(np.float32), device="cuda")
