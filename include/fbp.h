@@ -125,9 +125,8 @@ typedef struct {
  * others.
  * d_sino and d_filtered are [n_slices][K][D] and must not overlap.
  * n_slices == 0 is a valid no-op.
- * Fan beam: each view is first multiplied by R / sqrt(R^2 + s_m^2) (through a
- * scratch buffer owned by the plan, calls ordered on the device) and the kernel
- * is halved:  d_filtered[b][k][n] = dt * sum_m (h(n-m)/2) * d_sino[b][k][m] R / sqrt(R^2 + s_m^2).
+ * Fan beam: each view value is multiplied by R / sqrt(R^2 + s_m^2) as the filter
+ * loads it (no scratch) and the kernel is halved:  d_filtered[b][k][n] = dt * sum_m (h(n-m)/2) * d_sino[b][k][m] R / sqrt(R^2 + s_m^2).
  */
 int fbp_filter(const fbp_geom* geom, int32_t n_slices, const float* d_sino, float* d_filtered,
                int32_t precision, void* hip_stream);
