@@ -115,9 +115,10 @@ def test_fan_paths_agree_bitwise_and_repeat():
     assert np.array_equal(fbp.fbp_reconstruct(g, P).cpu().numpy(), whole)
 
 
-def test_fan_single_slices_on_two_streams():
+@pytest.mark.parametrize("K", [90, 96])   # one-tile kernel; quarter turns
+def test_fan_single_slices_on_two_streams(K):
     # the plan's partial-sum planes are shared: calls on two streams must not mix
-    N, K, D = 48, 90, 101
+    N, D = 48, 101
     g = fbp.Geometry(K, D, N, 1.0, source_distance=1.5 * N / math.sqrt(2.0))
     Q = torch.tensor(ph.rng_for(1607, 0).normal(size=(6, K, D)).astype(np.float32), device="cuda")
     ref = [fbp.fbp_backproject(g, Q[i:i + 1].contiguous()).cpu().numpy() for i in range(6)]
