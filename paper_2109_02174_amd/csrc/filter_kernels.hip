@@ -84,13 +84,12 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t col_weights(const GemmJob& job
                                              kBufWord3);
 }
 
-__device__ __forceinline__ float load_weight(const GemmJob& job, __amdgpu_buffer_rsrc_t wcol, int col) {
-    if (!job.colw) return 1.0f;
+__device__ __forceinline__ float load_weight(__amdgpu_buffer_rsrc_t wcol, int col) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(wcol, col * 4, 0, 0));
 }
 
 // Epilogue: lane l of a 16x16 block holds rows 4 (l/16) + i, column l % 16.
-template <int PREC>
+template <int PREC, bool CW>
 __device__ __forceinline__ void store_block(const v4f& acc, const GemmJob& job, int row0, int nh0, int sg) {
     const int l = threadIdx.x & 63;
     const int n = 2 * (nh0 + (l & 15)) + sg;
@@ -101,7 +100,8 @@ __device__ __forceinline__ void store_block(const v4f& acc, const GemmJob& job, 
         if (m < job.R) {
             float v = acc[i];
             if (!job.full) {
-                const float pv = job.p[(size_t)m * job.D + n] * (job.colw ? job.colw[n] : 1.0f);
+                float pv = job.p[(size_t)m * job.D + n];
+                if constexpr (CW) pv *= job.colw[n];
                 v = fmaf(job.diag, round_operand<PREC>(pv), v);
             }
             job.q[(size_t)m * job.D + n] = v * job.out_scale;
@@ -119,7 +119,7 @@ constexpr int kABuf32 = 2 * kTM * kAS32;  // floats per panel buffer
 // FULL: the kernel also has even taps; even outputs then take even inputs through
 // te and odd outputs odd inputs (the same-parity half of the panel), doubling the
 // MFMAs of the parity-split product.
-template <bool FULL>
+template <bool FULL, bool CW>
 __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt, char* smem) {
     float* As = reinterpret_cast<float*>(smem);          // [2 buffers][2 parity][32 rows][kAS32]
     float* Bt = As + 2 * kABuf32;                        // odd taps j = jlo + x, then even taps
@@ -145,25 +145,26 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
 
     // ring of kPD chunks of 64 input columns in registers: chunk c + kPD - 1 is
     // loaded while chunk c is multiplied, hiding several chunks of load latency
-    // ring entry: a thread's 8 elements of a chunk (all in column c0 + t % 64) and
-    // that column's weight (1 without column weights: the product is then exact)
-    float pf[kPD][9];
+    // ring entry: a thread's 8 elements of a chunk (all in column c0 + t % 64) and,
+    // with column weights (CW), that column's weight
+    constexpr int RE = CW ? 9 : 8;
+    float pf[kPD][RE];
     const __amdgpu_buffer_rsrc_t prow = tile_rows(P, m0, min(kTM, R - m0), D);
     const __amdgpu_buffer_rsrc_t wcol = col_weights(job);
-    auto load = [&](float (&r)[9], int c0) {   // columns c0 .. c0+63 of rows m0 .. m0+31
+    auto load = [&](float (&r)[RE], int c0) {   // columns c0 .. c0+63 of rows m0 .. m0+31
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int e = t + i * kBpThreads;
             r[i] = load_elem(prow, e >> 6, c0 + (e & 63), D);
         }
-        r[8] = load_weight(job, wcol, c0 + (t & 63));
+        if constexpr (CW) r[RE - 1] = load_weight(wcol, c0 + (t & 63));
     };
-    auto store = [&](const float (&r)[9], float* Ab) {
+    auto store = [&](const float (&r)[RE], float* Ab) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int e = t + i * kBpThreads;
             const int row = e >> 6, col = e & 63;
-            Ab[((col & 1) * kTM + row) * kAS32 + (col >> 1)] = r[i] * r[8];
+            Ab[((col & 1) * kTM + row) * kAS32 + (col >> 1)] = CW ? r[i] * r[RE - 1] : r[i];
         }
     };
 
@@ -227,7 +228,7 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
         }
     }
 #pragma unroll
-    for (int j = 0; j < kNB; ++j) store_block<kFP32>(acc[0][j] + acc[1][j], job, m0 + wm * 16, nh0 + 16 * j, sg);
+    for (int j = 0; j < kNB; ++j) store_block<kFP32, CW>(acc[0][j] + acc[1][j], job, m0 + wm * 16, nh0 + 16 * j, sg);
 }
 
 // ---------------------------------------------------------------- 16-bit operands
@@ -239,7 +240,7 @@ constexpr int kABuf16 = 2 * kTM * kAS16;  // 16-bit elements per panel buffer
 
 __device__ __forceinline__ int copy_stride16(int mpad) { return (mpad + kHalfN + 8 + 7 + 7) & ~7; }
 
-template <int PREC, bool FULL>
+template <int PREC, bool FULL, bool CW>
 __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt, char* smem) {
     unsigned short* As = reinterpret_cast<unsigned short*>(smem);   // [2 buffers][2][32][kAS16]
     unsigned short* Tc = As + 2 * kABuf16;                          // 8 shifted tap copies
@@ -271,25 +272,26 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
         }
     }
 
-    // ring entry: a thread's 16 elements of a chunk (all in column c0 + t % 128) and
-    // that column's weight (1 without column weights)
-    float pf[kPD16][17];
+    // ring entry: a thread's 16 elements of a chunk (all in column c0 + t % 128) and,
+    // with column weights (CW), that column's weight
+    constexpr int RE = CW ? 17 : 16;
+    float pf[kPD16][RE];
     const __amdgpu_buffer_rsrc_t prow = tile_rows(P, m0, min(kTM, R - m0), D);
     const __amdgpu_buffer_rsrc_t wcol = col_weights(job);
-    auto load = [&](float (&r)[17], int c0) {   // columns c0 .. c0+127 of rows m0 .. m0+31
+    auto load = [&](float (&r)[RE], int c0) {   // columns c0 .. c0+127 of rows m0 .. m0+31
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int e = t + i * kBpThreads;
             r[i] = load_elem(prow, e >> 7, c0 + (e & 127), D);
         }
-        r[16] = load_weight(job, wcol, c0 + (t & 127));
+        if constexpr (CW) r[RE - 1] = load_weight(wcol, c0 + (t & 127));
     };
-    auto store = [&](const float (&r)[17], unsigned short* Ab) {
+    auto store = [&](const float (&r)[RE], unsigned short* Ab) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int e = t + i * kBpThreads;
             const int row = e >> 7, col = e & 127;
-            const float x = r[i] * r[16];
+            const float x = CW ? r[i] * r[RE - 1] : r[i];
             Ab[((col & 1) * kTM + row) * kAS16 + (col >> 1)] = (PREC == kBF16) ? to_bf16_rne(x) : to_f16_rne(x);
         }
     };
@@ -362,27 +364,29 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
         }
     }
 #pragma unroll
-    for (int j = 0; j < kNB; ++j) store_block<PREC>(acc[0][j] + acc[1][j], job, m0 + wm * 16, nh0 + 16 * j, sg);
+    for (int j = 0; j < kNB; ++j) store_block<PREC, CW>(acc[0][j] + acc[1][j], job, m0 + wm * 16, nh0 + 16 * j, sg);
 }
 
 // One instantiation per (operand precision, kernel with or without even taps), so
 // the Ram-Lak path keeps its register budget.
-template <int PREC, bool FULL>
+template <int PREC, bool FULL, bool CW = false>
 __device__ __forceinline__ void gemm_tile(const GemmJob& job, int mt, int nt, char* smem) {
     if constexpr (PREC == kFP32)
-        gemm_tile_f32<FULL>(job, mt, nt, smem);
+        gemm_tile_f32<FULL, CW>(job, mt, nt, smem);
     else
-        gemm_tile_16<PREC, FULL>(job, mt, nt, smem);
+        gemm_tile_16<PREC, FULL, CW>(job, mt, nt, smem);
 }
 
-template <int PREC, bool FULL>
+// CW: the job has column weights (job.colw); a separate instantiation keeps the
+// unweighted filter's ring and stores as they were
+template <int PREC, bool FULL, bool CW>
 __global__ __launch_bounds__(kBpThreads) void gemm_grid_kernel(GemmJob job) {
     extern __shared__ float4 smem4[];
     const int tiles_m = (job.R + kTM - 1) / kTM;
     // blockIdx.x: output tile index, row tiles fastest so neighbours share tap slices
     const int b = blockIdx.x;
     const int nt = b / tiles_m, mt = b - nt * tiles_m;
-    gemm_tile<PREC, FULL>(job, mt, nt, reinterpret_cast<char*>(smem4));
+    gemm_tile<PREC, FULL, CW>(job, mt, nt, reinterpret_cast<char*>(smem4));
 }
 
 template <int PREC, bool FULL>
@@ -443,8 +447,10 @@ hipError_t launch_gemm_grid(int prec, const GemmJob& job, hipStream_t stream) {
     const unsigned grid = (unsigned)(tiles_m * job.tiles_n);
     const size_t lds = (size_t)gemm_lds_bytes(prec, job.Dh);
     switch (gemm_key(prec, job.full != 0)) {
-#define X(p, f) \
-        case gemm_key(p, f): return launch_kernel(gemm_grid_kernel<p, f>, dim3(grid), dim3(kBpThreads), lds, stream, job);
+#define X(p, f)                                                                                             \
+        case gemm_key(p, f):                                                                                    \
+            return job.colw ? launch_kernel(gemm_grid_kernel<p, f, true>, dim3(grid), dim3(kBpThreads), lds, stream, job) \
+                            : launch_kernel(gemm_grid_kernel<p, f, false>, dim3(grid), dim3(kBpThreads), lds, stream, job);
         FBP_FOR_EACH_GEMM(X)
 #undef X
         default: return hipErrorInvalidValue;
