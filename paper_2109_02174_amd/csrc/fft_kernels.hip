@@ -15,8 +15,11 @@
 //
 // The FFT is a Stockham autosort FFT in LDS (natural order in and out, one
 // buffer: every pass reads all of its inputs into registers before a barrier
-// and writes all of its outputs after it): one radix-2 pass when log2 L is odd,
-// then radix-4 passes.  Twiddles come from a table e^{-2 pi i m / L} made in
+// and writes all of its outputs after it): up to L = 2^11 one radix-2 pass when
+// log2 L is odd, then radix-4 passes; longer transforms use radix-8 passes (an
+// 8-point DFT as two 4-point DFTs of the sums and twiddled differences) after one
+// radix-2 or radix-4 pass, e.g. 5 passes instead of 7 at L = 2^13.  Twiddles come
+// from a table e^{-2 pi i m / L} made in
 // FP64 on the host; up to L = 4096 its first quarter is copied to LDS and the
 // rest follows from W^(m + jL/4) = (-i)^j W^m.
 #include "fbp_internal.hpp"
@@ -42,6 +45,8 @@ __global__ __launch_bounds__(fft_threads(LOG2L)) void fft_filter_kernel(FftJob j
     constexpr int NB4 = Q4 >= kFftThreads ? Q4 / kFftThreads : 1;
     constexpr int H2 = L / 2;                                   // radix-2 butterflies
     constexpr int NB2 = H2 >= kFftThreads ? H2 / kFftThreads : 1;
+    constexpr int Q8 = L / 8;                                   // radix-8 butterflies per pass
+    constexpr int NB8 = Q8 >= kFftThreads ? Q8 / kFftThreads : 1;
     // twiddles from an LDS copy of the first quarter of the table (L <= 4096):
     // W^(m + jL/4) = (-i)^j W^m
     constexpr bool kLdsTw = LOG2L >= 2 && LOG2L <= 12;
@@ -66,22 +71,42 @@ __global__ __launch_bounds__(fft_threads(LOG2L)) void fft_filter_kernel(FftJob j
         for (int m = t; m < QT; m += kFftThreads) qtw[m] = tw[m];
     }
     __syncthreads();
-    auto twiddle = [&](int m) -> float2 {                       // W^m, m < 3L/4
+    auto twiddle = [&](int m) -> float2 {                       // W^m, m < L
         if constexpr (kLdsTw) {
             const float2 w = qtw[m & (QT - 1)];
             switch (m >> (LOG2L - 2)) {
                 case 0: return w;
                 case 1: return make_float2(w.y, -w.x);
-                default: return make_float2(-w.x, -w.y);
+                case 2: return make_float2(-w.x, -w.y);
+                default: return make_float2(-w.y, w.x);
             }
         } else {
             return tw[m];
         }
     };
+    auto add = [](float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); };
+    auto sub = [](float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); };
+    // 4-point DFT (forward: e^{-2 pi i r s / 4}; inverse: its conjugate)
+    auto dft4 = [&](float2 x0, float2 x1, float2 x2, float2 x3, bool inverse, float2* y, int ys) {
+        const float2 t0 = add(x0, x2), t1 = sub(x0, x2), t2 = add(x1, x3), d = sub(x1, x3);
+        const float2 t3 = inverse ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);
+        y[0] = add(t0, t2);
+        y[ys] = add(t1, t3);
+        y[2 * ys] = sub(t0, t2);
+        y[3 * ys] = sub(t1, t3);
+    };
+
+    // pass schedule: up to L = 2^11 one radix-2 pass when log2 L is odd, then radix-4
+    // passes; from 2^12 on one radix-2 (log2 L = 1 mod 3) or radix-4 (= 2 mod 3)
+    // pass, then radix-8 passes (fewer barriers; below 2^12 half the threads of a
+    // radix-8 pass would idle and it measured slower)
+    constexpr bool R8 = LOG2L >= 12;
+    constexpr bool kFirst2 = R8 ? (LOG2L % 3 == 1) : ((LOG2L & 1) != 0);
+    constexpr int kN4 = R8 ? (LOG2L % 3 == 2 ? 1 : 0) : LOG2L / 2;
 
     auto fft = [&](bool inverse) {
         int Ns = 1;
-        if constexpr ((LOG2L & 1) != 0) {                       // radix 2 (k = 0: no twiddle)
+        if constexpr (kFirst2) {                                // one radix-2 pass (k = 0: no twiddle)
             float2 v[NB2][2];
 #pragma unroll
             for (int q = 0; q < NB2; ++q) {
@@ -103,7 +128,7 @@ __global__ __launch_bounds__(fft_threads(LOG2L)) void fft_filter_kernel(FftJob j
             __syncthreads();
             Ns = 2;
         }
-        for (; Ns < L; Ns *= 4) {                               // radix 4
+        for (int p4 = 0; p4 < kN4; ++p4, Ns *= 4) {             // radix 4
             float2 v[NB4][4];
 #pragma unroll
             for (int q = 0; q < NB4; ++q) {
@@ -128,17 +153,59 @@ __global__ __launch_bounds__(fft_threads(LOG2L)) void fft_filter_kernel(FftJob j
                             v[q][r] = cmul(v[q][r], w);
                         }
                     }
-                    const float2 a0 = make_float2(v[q][0].x + v[q][2].x, v[q][0].y + v[q][2].y);
-                    const float2 a1 = make_float2(v[q][0].x - v[q][2].x, v[q][0].y - v[q][2].y);
-                    const float2 a2 = make_float2(v[q][1].x + v[q][3].x, v[q][1].y + v[q][3].y);
-                    const float2 d3 = make_float2(v[q][1].x - v[q][3].x, v[q][1].y - v[q][3].y);
-                    // -i d3 (forward) or +i d3 (inverse)
-                    const float2 a3 = inverse ? make_float2(-d3.y, d3.x) : make_float2(d3.y, -d3.x);
+                    float2 y[4];
+                    dft4(v[q][0], v[q][1], v[q][2], v[q][3], inverse, y, 1);
                     const int o = (j - k) * 4 + k;
-                    buf[o] = make_float2(a0.x + a2.x, a0.y + a2.y);
-                    buf[o + Ns] = make_float2(a1.x + a3.x, a1.y + a3.y);
-                    buf[o + 2 * Ns] = make_float2(a0.x - a2.x, a0.y - a2.y);
-                    buf[o + 3 * Ns] = make_float2(a1.x - a3.x, a1.y - a3.y);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) buf[o + r * Ns] = y[r];
+                }
+            }
+            __syncthreads();
+        }
+        if constexpr (!R8) return;
+        for (; R8 && Ns < L; Ns *= 8) {                         // radix 8
+            float2 v[NB8][8];
+#pragma unroll
+            for (int q = 0; q < NB8; ++q) {
+                const int j = t + q * kFftThreads;
+                if (j < Q8) {
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) v[q][r] = buf[j + r * Q8];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < NB8; ++q) {
+                const int j = t + q * kFftThreads;
+                if (j < Q8) {
+                    const int k = j & (Ns - 1);
+                    const int step = k * (L / (8 * Ns));        // twiddle W^(r k L / (8 Ns)), index < 7L/8
+                    if (step != 0) {
+#pragma unroll
+                        for (int r = 1; r < 8; ++r) {
+                            float2 w = twiddle(r * step);
+                            if (inverse) w.y = -w.y;
+                            v[q][r] = cmul(v[q][r], w);
+                        }
+                    }
+                    // 8-point DFT: two 4-point DFTs of the sums and of the differences
+                    // times e^{-+2 pi i r / 8} (even and odd outputs)
+                    constexpr float c = 0.70710678118654752f;
+                    const float2 a0 = add(v[q][0], v[q][4]), a1 = add(v[q][1], v[q][5]);
+                    const float2 a2 = add(v[q][2], v[q][6]), a3 = add(v[q][3], v[q][7]);
+                    const float2 b0 = sub(v[q][0], v[q][4]), d1 = sub(v[q][1], v[q][5]);
+                    const float2 d2 = sub(v[q][2], v[q][6]), d3 = sub(v[q][3], v[q][7]);
+                    const float2 b1 = inverse ? make_float2(c * (d1.x - d1.y), c * (d1.x + d1.y))
+                                              : make_float2(c * (d1.x + d1.y), c * (d1.y - d1.x));
+                    const float2 b2 = inverse ? make_float2(-d2.y, d2.x) : make_float2(d2.y, -d2.x);
+                    const float2 b3 = inverse ? make_float2(-c * (d3.x + d3.y), c * (d3.x - d3.y))
+                                              : make_float2(c * (d3.y - d3.x), -c * (d3.x + d3.y));
+                    float2 y[8];
+                    dft4(a0, a1, a2, a3, inverse, y, 2);
+                    dft4(b0, b1, b2, b3, inverse, y + 1, 2);
+                    const int o = (j - k) * 8 + k;
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) buf[o + r * Ns] = y[r];
                 }
             }
             __syncthreads();
