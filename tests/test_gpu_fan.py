@@ -190,7 +190,8 @@ def test_fan_degenerate_sizes():
     g = fbp.Geometry(8, 5, 4, 1.0, source_distance=6.0)
     for fn, shape in ((fbp.fbp_filter, (0, 8, 5)), (fbp.fbp_backproject, (0, 4, 4)), (fbp.fbp_reconstruct, (0, 4, 4))):
         assert fn(g, torch.zeros((0, 8, 5), device="cuda")).shape == shape
-    for K, D, N, kind in ((4, 3, 1, "turn"), (8, 5, 2, "turn"), (12, 1, 2, "turn"), (5, 4, 2, "random")):
+    for K, D, N, kind in ((4, 3, 1, "turn"), (4, 5, 2, "turn"), (8, 5, 2, "turn"), (12, 1, 2, "turn"),
+                          (5, 4, 2, "random")):
         R = 3.0 + N
         b = _views(K, kind, K + D + N)
         g = fbp.Geometry(K, D, N, 1.0, b, source_distance=R)
