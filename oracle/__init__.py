@@ -55,7 +55,7 @@ def load_library(path: str):
     lib.oracle_fan_filter.argtypes = [dp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_int32, dp]
     lib.oracle_fan_backproject.argtypes = [dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                           ctypes.c_double, ctypes.c_double, dp, dp, dp]
+                                           ctypes.c_double, ctypes.c_double, dp, dp]
     lib.oracle_fan_fbp.argtypes = [dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_double, ctypes.c_double, dp, dp]
     lib.oracle_fan_splat.argtypes = lib.oracle_fan_fbp.argtypes
@@ -236,8 +236,9 @@ def fan_filter(P, ds: float, R: float, kind: str = "ramlak") -> np.ndarray:
     return Q
 
 
-def fan_backproject(Q, N: int, ds: float, R: float, betas, weights=None) -> np.ndarray:
-    """Distance-weighted backprojection of filtered views Q[B][K][D] (or [K][D])."""
+def fan_backproject(Q, N: int, ds: float, R: float, betas) -> np.ndarray:
+    """Distance-weighted backprojection of filtered views Q[B][K][D] (or [K][D]),
+    weight 2 pi / K per view."""
     Q = _f64(Q)
     squeeze = Q.ndim == 2
     if squeeze:
@@ -247,14 +248,7 @@ def fan_backproject(Q, N: int, ds: float, R: float, betas, weights=None) -> np.n
     if Ka != K:
         raise ValueError("view count does not match the sinogram")
     img = np.empty((B, N, N), dtype=np.float64)
-    wp = None
-    if weights is not None:
-        w = _f64(weights).reshape(-1)
-        if w.shape[0] != K:
-            raise ValueError("weight count does not match the views")
-        wp = _ptr(w)
-    rc = _load().oracle_fan_backproject(_ptr(Q), B, K, D, int(N), float(ds), float(R), _ptr(ang), wp,
-                                        _ptr(img))
+    rc = _load().oracle_fan_backproject(_ptr(Q), B, K, D, int(N), float(ds), float(R), _ptr(ang), _ptr(img))
     if rc != 0:
         raise ValueError("oracle_fan_backproject rejected its arguments")
     return img[0] if squeeze else img

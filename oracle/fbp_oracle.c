@@ -371,10 +371,10 @@ int oracle_fan_filter(const double* P, int64_t n_rows, int32_t D, double ds, dou
     return 0;
 }
 
-/* Step 3: Q is [n_slices][K][D] filtered views, betas the K source angles,
- * weights the per-view weights (null: 2 pi / K each). */
+/* Step 3: Q is [n_slices][K][D] filtered views, betas the K source angles
+ * (spread over a full turn, weight 2 pi / K each). */
 int oracle_fan_backproject(const double* Q, int32_t n_slices, int32_t K, int32_t D, int32_t N, double ds,
-                           double R, const double* betas, const double* weights, double* img) {
+                           double R, const double* betas, double* img) {
     if (!Q || !img || !betas || n_slices < 0 || K < 1 || D < 1 || N < 1 || !(ds > 0.0) || !isfinite(ds) ||
         !fan_args_ok(N, R))
         return -1;
@@ -401,7 +401,7 @@ int oracle_fan_backproject(const double* Q, int32_t n_slices, int32_t K, int32_t
                 const double alpha = u - fi;
                 const int64_t i = (int64_t)fi;
                 const double* q = qs + (int64_t)k * D;
-                const double wk = weights ? weights[k] : 2.0 * kPi / (double)K;
+                const double wk = 2.0 * kPi / (double)K;
                 acc += wk * (R / L) * (R / L) * ((1.0 - alpha) * qtilde(q, D, i) + alpha * qtilde(q, D, i + 1));
             }
             out[c] = acc;
@@ -418,7 +418,7 @@ int oracle_fan_fbp(const double* P, int32_t n_slices, int32_t K, int32_t D, int3
     double* Q = (double*)malloc(sizeof(double) * (count ? count : 1));
     if (!Q) return -1;
     int rc = oracle_fan_filter(P, (int64_t)n_slices * K, D, ds, R, 0, Q);
-    if (rc == 0) rc = oracle_fan_backproject(Q, n_slices, K, D, N, ds, R, betas, NULL, img);
+    if (rc == 0) rc = oracle_fan_backproject(Q, n_slices, K, D, N, ds, R, betas, img);
     free(Q);
     return rc;
 }

@@ -61,7 +61,7 @@ MUTANTS = [
     ("fan detector axis reversed", "const double sx = R * (-x * sb + y * cb) / L;",
      "const double sx = R * (x * sb - y * cb) / L;"),
     ("fan depth sign", "const double L = R - (x * cb + y * sb);", "const double L = R + (x * cb + y * sb);"),
-    ("fan weight pi/K", "weights[k] : 2.0 * kPi / (double)K;", "weights[k] : kPi / (double)K;"),
+    ("fan weight pi/K", "const double wk = 2.0 * kPi / (double)K;", "const double wk = kPi / (double)K;"),
     ("fan coordinate not divided by ds", "const double u = sx / ds + centre_det;", "const double u = sx + centre_det;"),
     ("cone pre-weight without the row", "sqrt(R * R + sm * sm + zj * zj)", "sqrt(R * R + sm * sm)"),
     ("cone filter without the half", "acc += 0.5 * filter_tap(kind, (int64_t)n - m, du)",

@@ -130,6 +130,32 @@ def test_uniform_disk_centre_converges_as_r_to_minus_3_halves():
         assert abs(q - 2 ** 1.5) < 0.1
 
 
+def _disk_centre_closed_form(R: int, rho: float) -> float:
+    """Centre pixel of the discrete FBP of a centred disk (odd N and D, unit bins).
+
+    Every angle sees the same projection P(t) = 2 rho sqrt(R^2 - t^2), and the
+    centre pixel's ray coordinate is an integer bin, so Eq. 2 with weight pi/K
+    gives pi * Q(0) with no interpolation.  With the Ram-Lak taps (h(0) = 1/4,
+    h(odd d) = -1/(pi^2 d^2), zero at even d != 0):
+        Q(0) = rho R / 2 - (4 rho / pi^2) sum_{odd m < R} sqrt(R^2 - m^2) / m^2.
+    """
+    m = np.arange(1, R, 2, dtype=np.float64)
+    return float(np.pi * (rho * R / 2.0 - (4.0 * rho / np.pi ** 2) * np.sum(np.sqrt(R * R - m * m) / (m * m))))
+
+
+@pytest.mark.parametrize("R,expected", [(32, 0.99911910), (64, 0.99969277), (128, 0.99989215)])
+def test_uniform_disk_centre_closed_form(R, expected):
+    """The disk's centre value equals the odd-m closed form, whose values for rho = 1
+    are 0.99911910 (R = 32), 0.99969277 (R = 64) and 0.99989215 (R = 128)."""
+    assert abs(_disk_centre_closed_form(R, 1.0) - expected) < 5e-9
+    for K in (4, 7, 90):
+        N, D = 2 * R + 33, 2 * R + 41
+        ang = ph.uniform_angles(K)
+        img = oracle.fbp(ph.disk_sinogram(R, 2.5, D, 1.0, ang), N, 1.0, ang)
+        c = (N - 1) // 2
+        assert abs(img[c, c] - _disk_centre_closed_form(R, 2.5)) < 1e-12 * R
+
+
 def test_uniform_disk_interior_is_flat():
     """Away from the rim the reconstruction of a disk stays within 1% of its density."""
     R, N, D, K = 40, 101, 145, 360
