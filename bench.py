@@ -7,7 +7,7 @@ against the FP64 oracle, a roofline entry for the dominant kernel
 (backprojection) and the oracle's own throughput on the host cores.
 
 python bench.py [--gpus 1] [--steps 200] [--warmup 20] [--precision fp32] [--no-cpu-baseline]
-               [--no-autotune] [--copy-mb MiB]
+               [--no-autotune] [--copy-mb MiB] [--latency-samples 1000]
 """
 from __future__ import annotations
 
@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip tile autotuning (default shapes, or FBP_FORCE_CONFIG): for profiler runs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--latency-samples", type=int, default=1000,
+                    help="requests timed one at a time after the timed region (p50/p99)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed region, one device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -166,18 +168,20 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
 
-    # latency: each step bracketed by events, after the timed region
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    for a, b in evs:
-        a.record(stream)
+    # latency, after the timed region: each request submitted alone on an idle GPU and
+    # timed from submission to completion on the host (at least 1000 samples)
+    n_lat = max(args.latency_samples, 1)
+    lat = []
+    for _ in range(n_lat):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         step()
-        b.record(stream)
-    torch.cuda.synchronize()
-    per_step = sorted(a.elapsed_time(b) for a, b in evs)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t1) * 1e3)
+    lat.sort()
     updates = sl.N * sl.N * sl.K
-    p50 = per_step[len(per_step) // 2]
-    p99 = per_step[min(len(per_step) - 1, int(math.ceil(0.99 * len(per_step))) - 1)]
+    p50 = lat[len(lat) // 2]
+    p99 = lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)]
 
     # dominant kernel alone (backprojection) and the filter GEMM alone, same stream
     fbp.fbp_filter(geom, sino, out=filt, precision=args.precision)
@@ -209,7 +213,8 @@ def main():
                    "filter_precision": args.precision, "tile_config": cfg,
                    "tile_config_name": fbp.fbp_tile_config_name(cfg), "autotuned": tuned},
         "slices_per_s": 1e3 / ms_per_step,
-        "latency_ms": {"p50": p50, "p99": p99, "min": per_step[0], "max": per_step[-1]},
+        "latency_ms": {"p50": p50, "p99": p99, "min": lat[0], "max": lat[-1], "samples": len(lat),
+                       "timing": "host submit to completion, one request at a time on an idle GPU"},
         "roofline": {"bound": "alu", "achieved": bp_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": bp_tflops / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": traffic,
