@@ -24,10 +24,13 @@
  *
  * Ownership: the caller owns every device buffer and keeps it alive until the
  * work queued on `hip_stream` has finished.  The library owns only per-geometry
- * plan state (FP64 cos/sin tables, the filter kernel table, the tile choice),
- * created on the first call for a geometry and kept until process exit.  Once a
- * geometry's plan exists, fbp_filter, fbp_backproject, fbp_reconstruct and
- * fbp_reconstruct_batch allocate no device memory.
+ * plan state (FP64 cos/sin tables, the tile choice, partial-sum planes for the
+ * shapes that split a slice's angles), created on the first call for a geometry
+ * and kept until process exit, plus tables made on first use: the filter taps
+ * of each operand precision (on the first filter call with that precision), the
+ * FFT tables (first FBP_PREC_FP32_FFT call), the forward projector's padded
+ * copies (first fbp_project call) and the cone-beam pre-weighting rows (first
+ * fbp_cone_filter call).  Once those exist, no call allocates device memory.
  *
  * Errors: arguments are validated on the host before any HIP call; a rejected
  * call has queued no work.  Launch failures are reported as FBP_EHIP.  Work is
@@ -35,10 +38,15 @@
  * execution surface at the caller's next synchronisation.  No function aborts,
  * throws or prints on the hot path.  All functions are thread-safe.
  *
- * Determinism: every output value is written once, by one GPU lane, with a
- * summation order fixed by the geometry alone (no atomics).  Repeated calls,
- * and a slice reconstructed alone or inside a batch, give bitwise-equal
- * results.
+ * Determinism: every output value is written once, by one GPU thread (no
+ * atomics), and every call is bitwise reproducible.  For parallel-beam
+ * geometries with even N whose angles come in quarter-turn pairs
+ * (theta_{k+K/2} = theta_k + pi/2, as every uniform list with even K) the tile
+ * shape and the summation order depend on the geometry alone: a slice
+ * reconstructed alone, in a stack or inside a batch gives bitwise-equal images,
+ * whatever the autotuner chose.  Other geometries may run single slices, stacks
+ * and batches with different tile shapes (and the autotuner picks shapes by
+ * timing); those paths agree within the FP32 tolerance.
  */
 #ifndef FBP_H
 #define FBP_H
@@ -139,13 +147,16 @@ int fbp_filter(const fbp_geom* geom, int32_t n_slices, const float* d_sino, floa
  * d_filtered is [n_slices][K][D], d_image is [n_slices][N][N]; no overlap.
  * Every image pixel is written.  With d_filtered = the raw sinogram this is
  * the exact adjoint of the linear-interpolation (hat) projector.
- * Stacks of 4 or more slices run with the plan's stack tile shape
+ * Quarter-turn geometries (see Determinism above) run one kernel for any
+ * number of slices: a 16-wave workgroup per 16 x 16 tile of the top-left
+ * quadrant and its three turns, wave w summing the w-th of 16 contiguous chunks
+ * of the angle pairs in ascending order, the chunk sums added in order.  Other
+ * geometries: stacks of 4 or more slices run with the plan's stack tile shape
  * (fbp_plan_stack_config), shorter ones slice by slice with its single-slice
- * shape (fbp_plan_config).  A single-slice shape with one angle group splits
+ * shape (fbp_plan_config); a single-slice shape with one angle group splits
  * the angles over several workgroups per tile and adds the parts in a fixed
  * order from a partial-sum buffer owned by the plan (calls that use it are
- * ordered among themselves on the device).  Results are deterministic for a
- * given geometry, stack length and tuning; the two shapes agree within the
+ * ordered among themselves on the device); the two shapes agree within the
  * FP32 tolerance.
  * Fan beam: d_image[b](X) = (2 pi / K) sum_k (R/L_k)^2 Q~_k(s_k(X) / dt + (D-1)/2),
  * L_k = R - (x cos b_k + y sin b_k) the depth of X along the central ray and
@@ -180,15 +191,19 @@ int fbp_project(const fbp_geom* geom, int32_t n_slices, const float* d_image, fl
 size_t fbp_workspace_bytes(const fbp_geom* geom, int32_t n_slices, int32_t precision);
 
 /*
- * Mixed-size batch (one slice per job, geometries may all differ): grouped
- * filter GEMMs and a persistent, cost-ordered backprojection launch per tile
- * shape, replayed from a captured HIP graph.  Jobs of a geometry that occurs 4
- * or more times take its stack shape (so each such image is bitwise equal to
- * fbp_reconstruct of the geometry's stack); the others take the single-slice
- * shape without angle split (bitwise equal to fbp_reconstruct alone unless that
- * shape splits, then equal within the FP32 tolerance).  The workspace
- * (fbp_batch_workspace_bytes) holds the filtered rows and the tile list; calls
- * that share a workspace must be ordered on one stream.
+ * Mixed-size batch: fbp_reconstruct of every job (the convolution Q = P * H and
+ * Eq. 2 of section "Computed tomography", each job with its own geometry, one
+ * slice per job).  Grouped filter GEMMs and a persistent, cost-ordered
+ * backprojection launch per tile shape, replayed from a captured HIP graph.
+ * Quarter-turn geometries all take the chunked quarter-turn kernel, so each such
+ * image is bitwise equal to fbp_reconstruct of the slice alone or in a stack.
+ * For other geometries, jobs of a geometry that occurs 4 or more times take its
+ * stack shape (bitwise equal to fbp_reconstruct of the geometry's stack) and
+ * the others its single-slice shape without angle split (bitwise equal to
+ * fbp_reconstruct alone unless that shape splits, then equal within the FP32
+ * tolerance).  The workspace (fbp_batch_workspace_bytes) holds the filtered
+ * rows and the tile list; calls that share a workspace must be ordered on one
+ * stream.
  */
 int fbp_reconstruct_batch(const fbp_job* jobs, int32_t n_jobs, void* d_workspace,
                           size_t workspace_bytes, int32_t precision, void* hip_stream);
@@ -200,7 +215,9 @@ size_t fbp_batch_workspace_bytes(const fbp_job* jobs, int32_t n_jobs, int32_t pr
  * Tile-shape autotuning for one geometry: times each compiled backprojection
  * tile shape on synthetic data on `hip_stream` (allocates and frees scratch
  * memory, synchronises the stream), once for one slice and once per slice of a
- * 16-slice stack, and records the fastest of each for this geometry.  Later
+ * 16-slice stack, and records the fastest of each for this geometry.  Where a
+ * chunked quarter-turn shape fits the geometry only its window pitches are
+ * timed; they compute the same bits, so tuning then never changes a result.  Later
  * plans of the geometry use them; a plan that already exists keeps its shapes,
  * so results never depend on when tuning ran relative to a call.  With the
  * environment variable FBP_TUNE_CACHE naming a file, the choice is appended to

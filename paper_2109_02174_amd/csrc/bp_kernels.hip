@@ -737,6 +737,8 @@ constexpr TileShape kShapes[kNumTileConfigs] = {
     {16, 1, 16, 4, "16x16 quadrant tile x 4 rotations, 1 px/lane, 4 angle groups", 1},
     {32, 4, 32, 1, "32x32 quadrant tile x 4 rotations, 4 px/lane, 1 angle group", 1},
     {16, 2, 32, 1, "16x32 quadrant tile x 4 rotations, 2 px/lane, 1 angle group", 1},
+    {16, 4, 16, kQtChunks, "16x16 quadrant tile x 4 rotations, 4 px/lane, 16 angle chunks (one per wave), 32-bin windows", 2},
+    {16, 4, 16, kQtChunks, "16x16 quadrant tile x 4 rotations, 4 px/lane, 16 angle chunks (one per wave), 64-bin windows", 2},
 };
 
 template <int TW, int P, int S, bool ROT, int M>
@@ -797,6 +799,7 @@ constexpr int kernel_key(int cfg, int m) { return cfg * 8 + m; }
 const TileShape& tile_shape(int cfg) { return kShapes[cfg]; }
 
 int bp_lds_bytes(int cfg, int m, int WL, int KB) {
+    if (cfg == kQtCfg32 || cfg == kQtCfg64) return m == 1 ? 0 : -1;   // static LDS
     int red = -1;
     switch (kernel_key(cfg, m)) {
 #define X(id, tw, p, s, rot, mm) case kernel_key(id, mm): red = red_bytes<tw, p, s, rot, mm>(); break;
@@ -816,6 +819,10 @@ int bp_lds_bytes(int cfg, int m, int WL, int KB) {
 
 hipError_t launch_bp_grid(int cfg, int m, const BpJob& job, int n_slices, size_t q_stride,
                           size_t img_stride, int tiles_per_slice, hipStream_t stream) {
+    if (cfg == kQtCfg32 || cfg == kQtCfg64) {
+        if (m != 1 || job.split > 1) return hipErrorInvalidValue;
+        return launch_bp_qt_grid(job, n_slices, q_stride, img_stride, tiles_per_slice, stream);
+    }
     const int lds = bp_lds_bytes(cfg, m, job.WL, job.KB);
     if (lds < 0) return hipErrorInvalidValue;
     switch (kernel_key(cfg, m)) {
@@ -830,6 +837,8 @@ hipError_t launch_bp_grid(int cfg, int m, const BpJob& job, int n_slices, size_t
 }
 
 hipError_t launch_bp_list(int cfg, int m, const BpListArgs* a, int grid, size_t lds, hipStream_t stream) {
+    if (cfg == kQtCfg32 || cfg == kQtCfg64)
+        return m == 1 ? launch_bp_qt_list(cfg == kQtCfg32 ? 32 : 64, a, grid, stream) : hipErrorInvalidValue;
     switch (kernel_key(cfg, m)) {
 #define X(id, tw, p, s, rot, mm) case kernel_key(id, mm): return list_launch<tw, p, s, rot, mm>(a, grid, lds, stream);
         FBP_FOR_EACH_KERNEL(X)
@@ -896,6 +905,7 @@ hipError_t launch_combine_parts(const float* part, float* img, int n_slices, int
 }
 
 int bp_occupancy(int cfg, int m, size_t lds) {
+    if (cfg == kQtCfg32 || cfg == kQtCfg64) return 1;   // 16 waves and most of the LDS per workgroup
     switch (kernel_key(cfg, m)) {
 #define X(id, tw, p, s, rot, mm) case kernel_key(id, mm): return occupancy<tw, p, s, rot, mm>(lds);
         FBP_FOR_EACH_KERNEL(X)

@@ -1,0 +1,366 @@
+// Quarter-turn backprojection with one contiguous angle chunk per wave.
+//
+// Computes Eq. 2 of arXiv 2109.02174 (section "Computed tomography") with the
+// pi/K weight (or per-angle weights) and linear interpolation, for angle lists
+// closed under +pi/2 (theta_{k+K/2} = theta_k + pi/2) and even N:
+//     img[r][c] = w * sum_k Q~_k(u_k),  u_k = (x_c cos th_k + y_r sin th_k)/dt + (D-1)/2.
+//
+// Design:
+//  * A workgroup of 16 waves owns a 16 x 16 tile T of the top-left image quadrant
+//    and its three 90-degree turns (1024 pixels).  Rotating a pixel by +90 degrees
+//    and its angle by +pi/2 leaves the ray coordinate unchanged, so for an angle
+//    pair (theta, theta + pi/2) the four turned copies of a pixel need two local
+//    coordinates, U (the tile) and V (its turn), for eight updates.
+//  * Every wave covers the whole tile (lane: one column, four rows) and takes one
+//    contiguous chunk of the K/2 angle pairs: wave w sums pairs
+//    [w K/32, (w+1) K/32) in ascending order, from zero.  The 16 chunk sums are
+//    added in wave order at the end through LDS.  The summation order therefore
+//    depends on K alone, and the same kernel serves single slices, stacks and
+//    batches, which so give bitwise-equal images.
+//  * Each wave stages its own windows in its own LDS region, so the main loop has
+//    no workgroup barrier: a wave synchronises only with itself (LDS operations
+//    of one wave complete in order).  Per pair it stages the window of bins the
+//    tile sees at theta and at theta + pi/2 (U) and the same for the turned tile
+//    (V); a window bin j holds (A_j, dL_j) for the forward and the reversed row,
+//    dL_j = L[j+1] - L[j] and A_j = L[j] - j dL_j, so the interpolated value at
+//    local coordinate u in [j, j+1) is A_j + u dL_j (one FMA, no fraction).
+//  * Windows have a fixed pitch of WP bins (a template parameter), so one address
+//    register per coordinate serves the four 16-byte reads of a pair (immediate
+//    offsets for the second plane, the turned window and the next pair).
+//  * Per (tile, pair) the window origin is FP64 (from the tile's corner bounds);
+//    lanes work in FP32 coordinates local to it.  The window starts one bin below
+//    the tile's smallest coordinate, so local coordinates are positive and
+//    truncation is floor.
+//  * The next block's filtered rows are loaded into registers while the current
+//    block is computed, with buffer loads whose range check supplies the zeros
+//    beyond the detector ends.
+//  * Each pixel is written once by one thread; no atomics.
+#include "fbp_internal.hpp"
+
+namespace fbp {
+
+namespace {
+
+constexpr int kWaves = kQtChunks;     // angle chunks = waves per workgroup
+constexpr int kThreads = 64 * kWaves;
+constexpr int kTile = kQtTile;        // quadrant tile side
+constexpr int kRows = 4;              // rows per lane: 64 lanes x 4 rows = 16 x 16
+constexpr int kBufferWord3 = 0x00020000;
+constexpr int kPartPitch = kTile + 1; // row pitch of the chunk sums in LDS
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// XCD-aware remap: hardware places block b on XCD b % 8; give each XCD a contiguous
+// range of logical tiles so the tiles sharing filtered rows share an L2.
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+    const int x = b & 7;
+    const int slot = b >> 3;
+    const int per = G >> 3;
+    const int extra = G & 7;
+    return x * per + min(x, extra) + slot;
+}
+
+// LDS bytes of one wave's region: pair constants of two blocks (float4 + int2 per
+// pair), then B pairs x 4 planes x WP bins of float4.
+template <int WP, int B>
+struct QtLds {
+    static constexpr int PRM = ((2 * B * 24) + 15) & ~15;
+    static constexpr int REGION = PRM + B * 4 * WP * 16;
+    static constexpr int WINDOWS = kWaves * REGION;
+    static constexpr int PARTS = kWaves * 4 * kTile * kPartPitch * 4;
+    static constexpr int BYTES = WINDOWS > PARTS ? WINDOWS : PARTS;
+};
+
+// The eight updates of one angle pair (theta, theta + pi/2) for a pixel p and its
+// turns R p, R^2 p, R^3 p (R(x, y) = (-y, x)), from the coordinates U = u_theta(p)
+// and V = u_theta(R p) and the window bins read there; "rev" is the reversed row
+// (the point reflection R^2 p reads it at the same local coordinate):
+//     p     : theta fwd at U,   theta+pi/2 rev at V
+//     R p   : theta fwd at V,   theta+pi/2 fwd at U
+//     R^2 p : theta rev at U,   theta+pi/2 fwd at V
+//     R^3 p : theta rev at V,   theta+pi/2 rev at U
+// The theta term is added first, then the theta + pi/2 term.
+__device__ __forceinline__ void pair_update(float u, float v, const float4& qu0, const float4& qu1,
+                                            const float4& qv0, const float4& qv1, float& a0, float& a1,
+                                            float& a2, float& a3) {
+    a0 += fmaf(u, qu0.y, qu0.x);
+    a0 += fmaf(v, qv1.w, qv1.z);
+    a2 += fmaf(u, qu0.w, qu0.z);
+    a2 += fmaf(v, qv1.y, qv1.x);
+    a1 += fmaf(v, qv0.y, qv0.x);
+    a1 += fmaf(u, qu1.y, qu1.x);
+    a3 += fmaf(v, qv0.w, qv0.z);
+    a3 += fmaf(u, qu1.w, qu1.z);
+}
+
+// One tile (top-left corner (c0, r0) of the quadrant) of one slice: rows q
+// ([K][D]) into img ([N][N]).  smem holds QtLds<WP, B>::BYTES.
+template <int WP, int B>
+__device__ __forceinline__ void qt_tile(const BpJob& job, const float* __restrict__ q, float* __restrict__ img,
+                                        int c0, int r0, char* smem) {
+    using L = QtLds<WP, B>;
+    constexpr int WPASS = 64 / WP;            // windows staged per pass of the wave
+    constexpr int NPASS = 2 * B / WPASS;      // passes per block (two windows per pair)
+    static_assert(WPASS >= 1 && NPASS * WPASS == 2 * B, "staging passes");
+
+    const int t = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int lane = t & 63;
+    char* region = smem + wave * L::REGION;
+    float4* prm = reinterpret_cast<float4*>(region);                // [2][B] {bU, bV, cos/dt, sin/dt}
+    int2* pri = reinterpret_cast<int2*>(region + 2 * B * 16);       // [2][B] {iU, iV}
+    float4* win = reinterpret_cast<float4*>(region + L::PRM);       // [B][4][WP]
+
+    const int N = job.N, D = job.D;
+    const int KH = job.K >> 1;
+    const int lo = (int)(((long long)wave * KH) / kWaves);
+    const int hi = (int)(((long long)(wave + 1) * KH) / kWaves);
+    const int n = hi - lo;
+    const double x0 = (double)c0 - job.half_pix;
+    const double y0 = (double)r0 - job.half_pix;
+    const int lx = lane & (kTile - 1);
+    const int ly0 = (lane >> 4) * kRows;
+    const float flx = (float)lx;
+    const float fly = (float)ly0;
+    const float nfly = -fly;
+    const int nxt = ((lane + 1) & 63) << 2;     // ds_bpermute source: lane + 1
+    const int d4 = (D - 1) * 4;
+    const int jl = lane & (WP - 1);             // window bin of this lane when staging
+    const int wl = (WPASS == 2) ? (lane >> 5) : 0;
+    const float* __restrict__ wscale = job.wscale;
+
+    float acc0[kRows], acc1[kRows], acc2[kRows], acc3[kRows];
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+        acc0[i] = 0.0f;
+        acc1[i] = 0.0f;
+        acc2[i] = 0.0f;
+        acc3[i] = 0.0f;
+    }
+
+    // window origins (FP64) of the pairs lo + kb .. lo + kb + B - 1, into buffer buf
+    auto params = [&](int kb, int buf) {
+        const int k = lo + kb + lane;
+        if (lane < B && k < hi) {
+            const double cd = job.cs[2 * k];
+            const double sd = job.cs[2 * k + 1];
+            const double uo = x0 * cd + y0 * sd + job.centre_det;
+            const double umin = uo + fmin(0.0, (double)(kTile - 1) * cd) + fmin(0.0, (double)(kTile - 1) * sd);
+            const double vo = x0 * sd - y0 * cd + job.centre_det;
+            const double vmin = vo + fmin(0.0, (double)(kTile - 1) * sd) + fmin(0.0, -(double)(kTile - 1) * cd);
+            const int iu = (int)floor(umin) - 1;
+            const int iv = (int)floor(vmin) - 1;
+            prm[buf * B + lane] = make_float4((float)(uo - (double)iu), (float)(vo - (double)iv), (float)cd, (float)sd);
+            pri[buf * B + lane] = make_int2(iu, iv);
+        }
+    };
+    // staging: pass ps covers windows ps*WPASS .. ps*WPASS + WPASS - 1 (window s =
+    // 2 b + w: pair b, w = 0 the tile's window U, w = 1 the turned tile's V); each
+    // lane loads one bin of the forward and reversed rows at theta and theta + pi/2
+    float pf[NPASS][4];
+    auto load = [&](int kb, int buf) {
+        const int nb = min(B, n - kb);
+#pragma unroll
+        for (int ps = 0; ps < NPASS; ++ps) {
+            const int s0 = ps * WPASS;            // first window of the pass (uniform)
+            const int b = s0 >> 1;                // pair (uniform: a pass never spans two pairs)
+            if (b < nb) {
+                const int w = (WPASS == 2) ? wl : (s0 & 1);
+                const int k = lo + kb + b;
+                const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<float*>(q + (size_t)k * (size_t)D), (short)0, D * 4, kBufferWord3);
+                const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<float*>(q + (size_t)(k + KH) * (size_t)D), (short)0, D * 4, kBufferWord3);
+                const int2 io = pri[buf * B + b];
+                const int g4 = ((w ? io.y : io.x) + jl) * 4;
+                pf[ps][0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, g4, 0, 0));
+                pf[ps][1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, d4 - g4, 0, 0));
+                pf[ps][2] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, g4, 0, 0));
+                pf[ps][3] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, d4 - g4, 0, 0));
+            }
+        }
+    };
+    auto store = [&](int kb) {
+        const int nb = min(B, n - kb);
+#pragma unroll
+        for (int ps = 0; ps < NPASS; ++ps) {
+            const int s0 = ps * WPASS;
+            const int b = s0 >> 1;
+            if (b < nb) {
+                const int w = (WPASS == 2) ? wl : (s0 & 1);
+                if (wscale) {   // angle weights / (pi/K): scalar loads
+                    const int k = lo + kb + b;
+                    const float ca = wscale[k], cb = wscale[k + KH];
+                    pf[ps][0] *= ca;
+                    pf[ps][1] *= ca;
+                    pf[ps][2] *= cb;
+                    pf[ps][3] *= cb;
+                }
+                float nx[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    nx[c] = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(nxt, __builtin_bit_cast(int, pf[ps][c])));
+                if (jl < WP - 1) {   // bin jl + 1 comes from the next lane of the same window
+                    const float jj = (float)jl;
+                    float d[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) d[c] = nx[c] - pf[ps][c];
+                    float4* dst = win + (b * 4 + w * 2) * WP + jl;
+                    dst[0] = make_float4(fmaf(-jj, d[0], pf[ps][0]), d[0], fmaf(-jj, d[1], pf[ps][1]), d[1]);
+                    dst[WP] = make_float4(fmaf(-jj, d[2], pf[ps][2]), d[2], fmaf(-jj, d[3], pf[ps][3]), d[3]);
+                }
+            }
+        }
+    };
+    auto compute = [&](int kb, int buf) {
+        const int nb = min(B, n - kb);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            if (b < nb) {
+                const float4 p = prm[buf * B + b];    // bU, bV, cos, sin
+                const float u0 = fmaf(flx, p.z, fmaf(fly, p.w, p.x));
+                const float v0 = fmaf(flx, p.w, fmaf(nfly, p.z, p.y));
+                const float4* __restrict__ wu = win + b * 4 * WP;
+                const float4* __restrict__ wv = wu + 2 * WP;
+                float u[kRows], v[kRows];
+                float4 qu0[kRows], qu1[kRows], qv0[kRows], qv1[kRows];
+#pragma unroll
+                for (int i = 0; i < kRows; ++i) {
+                    u[i] = (i == 0) ? u0 : fmaf((float)i, p.w, u0);
+                    v[i] = (i == 0) ? v0 : fmaf(-(float)i, p.z, v0);
+                    const int ju = (int)u[i];   // both > 0: truncation is floor
+                    const int jv = (int)v[i];
+                    qu0[i] = wu[ju];
+                    qu1[i] = wu[WP + ju];
+                    qv0[i] = wv[jv];
+                    qv1[i] = wv[WP + jv];
+                }
+#pragma unroll
+                for (int i = 0; i < kRows; ++i)
+                    pair_update(u[i], v[i], qu0[i], qu1[i], qv0[i], qv1[i], acc0[i], acc1[i], acc2[i], acc3[i]);
+            }
+        }
+    };
+
+    if (n > 0) {
+        params(0, 0);
+        wave_sync();
+        load(0, 0);
+        int buf = 0;
+        for (int kb = 0; kb < n; kb += B, buf ^= 1) {
+            store(kb);
+            if (kb + B < n) params(kb + B, buf ^ 1);
+            wave_sync();
+            if (kb + B < n) load(kb + B, buf ^ 1);
+            compute(kb, buf);
+            wave_sync();
+        }
+    }
+
+    // chunk sums through LDS, added in wave order; each output written once
+    __syncthreads();   // every wave is done with its windows
+    float* part = reinterpret_cast<float*>(smem);   // [wave][turn][row][kPartPitch]
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+        float* pp = part + ((wave * 4) * kTile + ly0 + i) * kPartPitch + lx;
+        pp[0 * kTile * kPartPitch] = acc0[i];
+        pp[1 * kTile * kPartPitch] = acc1[i];
+        pp[2 * kTile * kPartPitch] = acc2[i];
+        pp[3 * kTile * kPartPitch] = acc3[i];
+    }
+    __syncthreads();
+    const int turn = t >> 8;       // 0: p, 1: R p, 2: R^2 p, 3: R^3 p
+    const int e = t & 255;
+    // p and R^2 p run along tile rows, R p and R^3 p along tile columns, so that
+    // consecutive threads write consecutive image addresses
+    const int ty = (turn & 1) ? (e & (kTile - 1)) : (e >> 4);
+    const int tx = (turn & 1) ? (e >> 4) : (e & (kTile - 1));
+    const float* src = part + (turn * kTile + ty) * kPartPitch + tx;
+    float sum = 0.0f;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) sum += src[w * 4 * kTile * kPartPitch];
+    const int r = r0 + ty, c = c0 + tx, half = N >> 1;
+    if (r < half && c < half) {
+        size_t o;
+        if (turn == 0) o = (size_t)r * N + c;
+        else if (turn == 1) o = (size_t)c * N + (N - 1 - r);
+        else if (turn == 2) o = (size_t)(N - 1 - r) * N + (N - 1 - c);
+        else o = (size_t)(N - 1 - c) * N + r;
+        img[o] = sum * job.scale;
+    }
+}
+
+template <int WP, int B>
+__global__ __launch_bounds__(kThreads) void bp_qt_grid_kernel(BpJob job, size_t q_stride, size_t img_stride,
+                                                              int tiles_per_slice) {
+    __shared__ __attribute__((aligned(16))) char smem[QtLds<WP, B>::BYTES];
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int s = lb / tiles_per_slice;
+    const int tt = lb - s * tiles_per_slice;
+    const int ty = tt / job.tiles_x;
+    const int tx = tt - ty * job.tiles_x;
+    qt_tile<WP, B>(job, job.q + (size_t)s * q_stride, job.img + (size_t)s * img_stride, tx * kTile, ty * kTile,
+                   smem);
+}
+
+// Persistent form over a mixed list (same arguments as the other list kernels):
+// tile index -> job by binary search in the tile prefix; one job per slice.
+template <int WP, int B>
+__global__ __launch_bounds__(kThreads) void bp_qt_list_kernel(const BpListArgs* __restrict__ args) {
+    __shared__ __attribute__((aligned(16))) char smem[QtLds<WP, B>::BYTES];
+    const BpListArgs a = load_const(args);
+    const auto* __restrict__ prefix = as_const(a.tile_prefix);
+    const int n_sel = *as_const(a.counts);
+    if (n_sel <= 0) return;
+    const int total = prefix[n_sel];
+    const int G = gridDim.x;
+    for (int it = xcd_remap(blockIdx.x, G); it < total; it += G) {
+        int lo = 0, hi = n_sel - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= it) lo = mid; else hi = mid - 1;
+        }
+        const BpJob job = load_const(a.jobs + as_const(a.job_index)[lo]);
+        const int tt = it - prefix[lo];
+        const int ty = tt / job.tiles_x;
+        const int tx = tt - ty * job.tiles_x;
+        __syncthreads();   // the previous tile's chunk sums are read before windows overwrite them
+        qt_tile<WP, B>(job, job.q, job.img, tx * kTile, ty * kTile, smem);
+    }
+}
+
+}  // namespace
+
+int qt_pitch_for(int WL) {
+    if (WL <= 31) return 32;
+    if (WL <= 63) return 64;
+    return 0;
+}
+
+int qt_block_pairs(int WP) { return WP == 32 ? 4 : 2; }
+
+hipError_t launch_bp_qt_grid(const BpJob& job, int n_slices, size_t q_stride, size_t img_stride,
+                             int tiles_per_slice, hipStream_t stream) {
+    const long long grid = (long long)n_slices * tiles_per_slice;
+    if (grid <= 0) return hipSuccess;
+    if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (job.WL == 32)
+        return launch_kernel(bp_qt_grid_kernel<32, 4>, dim3((unsigned)grid), dim3(kThreads), 0, stream, job, q_stride,
+                             img_stride, tiles_per_slice);
+    if (job.WL == 64)
+        return launch_kernel(bp_qt_grid_kernel<64, 2>, dim3((unsigned)grid), dim3(kThreads), 0, stream, job, q_stride,
+                             img_stride, tiles_per_slice);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_bp_qt_list(int WP, const BpListArgs* a, int grid, hipStream_t stream) {
+    if (WP == 32) return launch_kernel(bp_qt_list_kernel<32, 4>, dim3(grid), dim3(kThreads), 0, stream, a);
+    if (WP == 64) return launch_kernel(bp_qt_list_kernel<64, 2>, dim3(grid), dim3(kThreads), 0, stream, a);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace fbp

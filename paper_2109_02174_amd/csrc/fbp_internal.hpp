@@ -71,13 +71,21 @@ static_assert(sizeof(BpJob) % 8 == 0, "BpJob layout");
 struct TileShape {
     int32_t tw, p, th, s;
     const char* name;
-    int32_t rot = 0;      // 1: quadrant tile and its three 90-degree rotations (angle pairs)
+    int32_t rot = 0;      // 1: quadrant tile and its three 90-degree rotations (angle pairs);
+                          // 2: the same with one contiguous angle chunk per wave (bp_qt_kernels)
     int32_t multi = 1;    // slices per workgroup of the stack variant (1: none)
 };
 
 constexpr int kGroupThreads = 256;
 constexpr int kBpThreads = 256;   // threads of the GEMM workgroups
-constexpr int kNumTileConfigs = 13;
+constexpr int kNumTileConfigs = 15;
+// Chunked quarter-turn shapes (rot == 2): tile ids, angle chunks (= waves per
+// workgroup) and quadrant tile side.  The two ids differ only in the LDS pitch of
+// the staged windows (32 or 64 bins), not in their arithmetic.
+constexpr int kQtCfg32 = 13;
+constexpr int kQtCfg64 = 14;
+constexpr int kQtChunks = 16;
+constexpr int kQtTile = 16;
 constexpr int kMaxKB = 64;
 // Most angle parts a single slice's backprojection is split into (one-group shapes).
 constexpr int kMaxSplit = 16;
@@ -134,6 +142,14 @@ struct BpListArgs {
 hipError_t launch_bp_list(int cfg, int m, const BpListArgs* args, int grid, size_t lds_bytes,
                           hipStream_t stream);
 int bp_occupancy(int cfg, int m, size_t lds_bytes);   // resident workgroups per CU
+
+// Chunked quarter-turn backprojector (bp_qt_kernels.hip): job.WL is the window
+// pitch (32 or 64 bins); its LDS is static, one 1024-thread workgroup per tile.
+int qt_pitch_for(int WL);          // pitch that holds a window of WL bins, 0 if none
+int qt_block_pairs(int WP);        // angle pairs staged per block
+hipError_t launch_bp_qt_grid(const BpJob& job, int n_slices, size_t q_stride, size_t img_stride,
+                             int tiles_per_slice, hipStream_t stream);
+hipError_t launch_bp_qt_list(int WP, const BpListArgs* args, int grid, hipStream_t stream);
 
 // ------------------------------------------------------------------ forward projector
 

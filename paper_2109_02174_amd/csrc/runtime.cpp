@@ -286,6 +286,26 @@ bool shape_params(int cfg, const std::vector<double>& cs, const std::vector<doub
     sp->multi = 1;
     sp->KBm = 0;
     const int waves = kGroupThreads * s.s / 64;
+    if (s.rot == 2) {
+        // chunked quarter-turn shape: even N, angles in quarter-turn pairs, and a
+        // window that fits this id's pitch (one bin short of it: the staging pairs
+        // each bin with the next lane's)
+        if ((N & 1) || !quarter_turn_symmetric(angles)) return false;
+        double span = 0.0;
+        for (size_t k = 0; 2 * k + 1 < cs.size(); ++k)
+            span = std::max(span, (kQtTile - 1) * (std::fabs(cs[2 * k]) + std::fabs(cs[2 * k + 1])));
+        if (!(span < 1e6)) return false;
+        const int wl = window_length(span);
+        const int pitch = (cfg == kQtCfg32) ? 32 : 64;
+        if (wl > pitch - 1) return false;
+        sp->WL = pitch;
+        sp->KB = qt_block_pairs(pitch);
+        sp->seg_shift = 0;
+        const int half = N / 2;
+        sp->tiles_x = (half + kQtTile - 1) / kQtTile;
+        sp->tiles_y = sp->tiles_x;
+        return true;
+    }
     if (s.rot) {
         // quadrant tile plus its three rotations: even N, angles in quarter-turn pairs
         if ((N & 1) || !quarter_turn_symmetric(angles)) return false;
@@ -351,16 +371,17 @@ bool shape_params(int cfg, const std::vector<double>& cs, const std::vector<doub
 // shapes split their angles over workgroups; the quarter-turn ones need even N
 // and angles closed under +pi/2.
 int default_config(int N, bool quarter_turn) {
-    if (quarter_turn && (N & 1) == 0) {
-        if (N >= 1024) return 11;
-        if (N >= 384) return 12;
-    }
+    if (quarter_turn && (N & 1) == 0) return kQtCfg32;
     if (N >= 1024) return 2;
     if (N >= 192) return 4;
     return 7;
 }
+int default_stack_config(int N, bool quarter_turn) {
+    if (quarter_turn && (N & 1) == 0) return kQtCfg32;
+    return N >= 256 ? 2 : 5;
+}
 
-int default_stack_config(int N) { return N >= 256 ? 2 : 5; }
+bool qt_family(int cfg) { return cfg == kQtCfg32 || cfg == kQtCfg64; }
 
 std::string tune_cache_path() {
     const char* p = std::getenv("FBP_TUNE_CACHE");
@@ -438,8 +459,14 @@ int cu_count(int device) {
 }
 
 // The shape of tile id cfg for a plan's geometry, or of the first shape that fits.
+// A chunked quarter-turn id whose window does not fit its pitch takes the other
+// pitch (same arithmetic); a geometry neither fits takes the plain shapes.
 bool pick_shape(int cfg, const Plan& p, int cus, ShapeParams* sp) {
     if (cfg >= 0 && cfg < kNumTileConfigs && shape_params(cfg, p.cs, p.angles, p.N, cus, sp)) return true;
+    if (qt_family(cfg)) {
+        if (shape_params(cfg == kQtCfg32 ? kQtCfg64 : kQtCfg32, p.cs, p.angles, p.N, cus, sp)) return true;
+        if (shape_params(default_config(p.N, false), p.cs, p.angles, p.N, cus, sp)) return true;
+    }
     for (int c = 0; c < kNumTileConfigs; ++c)
         if (shape_params(c, p.cs, p.angles, p.N, cus, sp)) return true;
     return false;
@@ -573,7 +600,8 @@ int get_plan(const fbp_geom* g, Plan** out) {
         R.plans[key] = std::move(p);
         return FBP_OK;
     }
-    int one = default_config(p->N, quarter_turn_symmetric(p->angles)), stack = default_stack_config(p->N);
+    const bool qt = quarter_turn_symmetric(p->angles);
+    int one = default_config(p->N, qt), stack = default_stack_config(p->N, qt);
     auto t = R.tuned.find(key);
     if (t != R.tuned.end()) std::tie(one, stack) = t->second;
     const int forced = env_forced_config();
@@ -827,6 +855,13 @@ BpJob bp_job(const Plan& p, const ShapeParams& sh, const float* filt, float* img
 
 int hip_status(hipError_t e, const char* what) { return e == hipSuccess ? FBP_OK : hip_fail(e, what); }
 
+// A call that queued work on a plan-owned buffer and then failed still records the
+// buffer's event, so later users of the buffer wait for the work already queued.
+int fail_after_queued(int rc, hipEvent_t free_ev, bool* recorded, hipStream_t s) {
+    if (hipEventRecord(free_ev, s) == hipSuccess) *recorded = true;
+    return rc;
+}
+
 // rows x D: the GEMM in the operand precision, or the FFT path.
 hipError_t launch_filter_rows(const Plan& p, int prec, const float* in, float* out, int rows, hipStream_t s,
                               const float* colw = nullptr) {
@@ -901,8 +936,11 @@ int run_fan_backproject(Plan& p, int32_t n, const float* filt, float* img, hipSt
             ji.split = p.fan_split;
             hipError_t e = launch(ji, 1, 1);
             if (e == hipSuccess) e = launch_combine_parts(pb.ptr, img + i * is, 1, p.fan_split, is, j.scale, s);
-            if (e != hipSuccess)
-                return e == hipErrorInvalidValue ? FBP_EUNSUPPORTED : hip_status(e, "fan-beam backprojection launch");
+            if (e != hipSuccess) {
+                const int rc = e == hipErrorInvalidValue ? FBP_EUNSUPPORTED
+                                                         : hip_status(e, "fan-beam backprojection launch");
+                return i > 0 ? fail_after_queued(rc, pb.free_ev, &pb.recorded, s) : rc;
+            }
         }
         FBP_TRY_HIP(hipEventRecord(pb.free_ev, s));
         pb.recorded = true;
@@ -946,9 +984,9 @@ int run_single(const Plan& p, const ShapeParams& sh, PartBuffer* pb, const float
     j.split = sh.split;
     const size_t qs = (size_t)p.K * p.D, is = (size_t)p.N * p.N;
     int rc = hip_status(launch_bp_grid(sh.cfg, 1, j, 1, qs, is, tiles, s), "backprojection kernel launch");
-    if (rc == FBP_OK)
-        rc = hip_status(launch_combine_parts(pb->ptr, img, 1, sh.split, is, j.scale, s), "partial-sum kernel launch");
     if (rc != FBP_OK) return rc;
+    rc = hip_status(launch_combine_parts(pb->ptr, img, 1, sh.split, is, j.scale, s), "partial-sum kernel launch");
+    if (rc != FBP_OK) return fail_after_queued(rc, pb->free_ev, &pb->recorded, s);
     FBP_TRY_HIP(hipEventRecord(pb->free_ev, s));
     pb->recorded = true;
     return FBP_OK;
@@ -1424,8 +1462,16 @@ int time_tile_shapes(const fbp_geom* g, const std::vector<double>& cs, hipStream
     };
     *best_one = *best_stack = -1;
     float one_ms = 0.0f, stack_ms = 0.0f;
+    // where a chunked quarter-turn shape fits, only its window pitches are timed:
+    // they give the same bits, so the choice moves time but never the result
+    bool qt_fits = false;
+    for (int c : {kQtCfg32, kQtCfg64}) {
+        ShapeParams sp;
+        qt_fits = qt_fits || shape_params(c, cs, p.angles, p.N, cus, &sp);
+    }
     for (int c = 0; c < kNumTileConfigs; ++c) {
         ShapeParams sp;
+        if (qt_fits != qt_family(c)) continue;
         if (!shape_params(c, cs, p.angles, p.N, cus, &sp)) continue;
         float ms = 0.0f;
         int rc = time_ms([&] { return run_single(p, sp, &t.part, t.q, t.im, s); }, &ms);
@@ -1658,16 +1704,21 @@ int run_cone_filter(ConePlan& c, const float* proj, float* filt, hipStream_t s) 
         rs.rows = views;
     }
     if (rs.recorded) FBP_TRY_HIP(hipStreamWaitEvent(s, rs.free_ev, 0));
+    bool queued = false;
     for (int64_t k0 = 0; k0 < c.K; k0 += rs.rows) {
         const int64_t m = std::min<int64_t>(rs.rows, c.K - k0);
         const size_t off = (size_t)(k0 * per_view);
         hipError_t e = launch_preweight(proj + off, rs.ptr, c.d_pw, m, (int)per_view, s);
         if (e == hipSuccess) {
+            queued = true;
             GemmJob j = gemm_job(*c.taps, kFP32, rs.ptr, filt + off, (int)(m * c.Dv));
             j.out_scale *= 0.5f;                                       // half the kernel
             e = launch_gemm_grid(kFP32, j, s);
         }
-        if (e != hipSuccess) return hip_status(e, "cone-beam filter launch");
+        if (e != hipSuccess) {
+            const int rc = hip_status(e, "cone-beam filter launch");
+            return queued ? fail_after_queued(rc, rs.free_ev, &rs.recorded, s) : rc;
+        }
     }
     FBP_TRY_HIP(hipEventRecord(rs.free_ev, s));
     rs.recorded = true;

@@ -178,6 +178,8 @@ def test_kernels_use_no_atomics_and_no_cuda():
     for path in _kernel_sources():
         text = open(path).read()
         code = re.sub(r"//.*", "", re.sub(r"/\*.*?\*/", "", text, flags=re.S))
+        # memory-order constants of a fence are not atomic operations
+        code = re.sub(r"__builtin_amdgcn_fence\(__ATOMIC_(RELEASE|ACQUIRE), \"wavefront\"\)", "", code)
         assert not re.search(r"atomic", code, re.I), f"atomic operation in {path}"
         assert "cuda" not in code.lower(), f"CUDA reference in {path}"
         assert "__HIP_PLATFORM" not in code

@@ -1,0 +1,117 @@
+"""CPU replay of the chunked quarter-turn backprojector's window coordinates.
+
+The kernel stages, per (tile, angle pair), a window of WP bins that starts one bin
+below the smallest ray coordinate of the tile, and reads bins j and (through the
+staged differences) j + 1 at j = trunc(u) of each pixel's FP32 local coordinate.
+This test restates in NumPy the host's window bound and pitch choice and the
+kernel's FP64 window origins and FP32 coordinate arithmetic (fused multiply-adds
+rounded once), and asserts that every bin a pixel reads was staged: 0 <= j and
+j <= WP - 2 (the last bin of a window has no staged difference).  It covers the
+GPU test geometries and the benchmark workloads (512^2 / 720 angles / 725 bins,
+and the mixed-batch sides 256 ... 1024).  No GPU is involved.
+"""
+import math
+
+import numpy as np
+import pytest
+
+TILE, CHUNKS, ROWS = 16, 16, 4
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float64).astype(np.float32)
+
+
+def fma32(a, b, c):
+    """fmaf: the exact a*b + c rounded once to FP32 (the product of two FP32 values is
+    exact in FP64, and the sum's rounding to FP64 cannot move it across an FP32
+    rounding boundary by more than the checks' margin)."""
+    d = lambda x: np.asarray(x, dtype=np.float64)
+    return f32(d(a) * d(b) + d(c))
+
+
+def pitch_for(K, N, dt, angles):
+    c = np.cos(angles) / dt
+    s = np.sin(angles) / dt
+    span = np.max((TILE - 1) * (np.abs(c) + np.abs(s)))
+    wl = int(span) + 5
+    if wl <= 31:
+        return 32
+    if wl <= 63:
+        return 64
+    return 0
+
+
+def replay(K, D, N, dt, angles, WP=None):
+    """Pitch, and the smallest and largest bin read over every tile, pair and pixel."""
+    WP = pitch_for(K, N, dt, angles) if WP is None else WP
+    assert WP in (32, 64)
+    KH = K // 2
+    cd = np.cos(angles[:KH]) / dt
+    sd = np.sin(angles[:KH]) / dt
+    half = N // 2
+    tiles = (half + TILE - 1) // TILE
+    hp, cdet = 0.5 * (N - 1), 0.5 * (D - 1)
+    t0 = np.arange(tiles) * TILE
+    c0, r0 = [a.ravel() for a in np.meshgrid(t0, t0, indexing="xy")]
+    x0 = (c0 - hp)[:, None]
+    y0 = (r0 - hp)[:, None]
+    uo = x0 * cd + y0 * sd + cdet
+    umin = uo + np.minimum(0.0, (TILE - 1) * cd) + np.minimum(0.0, (TILE - 1) * sd)
+    vo = x0 * sd - y0 * cd + cdet
+    vmin = vo + np.minimum(0.0, (TILE - 1) * sd) + np.minimum(0.0, -(TILE - 1) * cd)
+    iu = np.floor(umin).astype(np.int64) - 1
+    iv = np.floor(vmin).astype(np.int64) - 1
+    bU, bV = f32(uo - iu), f32(vo - iv)
+    c32, s32 = f32(cd)[None, :], f32(sd)[None, :]
+    lo, hi = np.inf, -np.inf
+    for lx in range(TILE):
+        for ly0 in range(0, TILE, ROWS):
+            u0 = fma32(np.float32(lx), c32, fma32(np.float32(ly0), s32, bU))
+            v0 = fma32(np.float32(lx), s32, fma32(np.float32(-ly0), c32, bV))
+            for i in range(ROWS):
+                u = u0 if i == 0 else fma32(np.float32(i), s32, u0)
+                v = v0 if i == 0 else fma32(np.float32(-i), c32, v0)
+                assert np.all(u > 0.0) and np.all(v > 0.0), "truncation would not be floor"
+                ju = np.trunc(u)
+                jv = np.trunc(v)
+                lo = min(lo, ju.min(), jv.min())
+                hi = max(hi, ju.max(), jv.max())
+    return WP, int(lo), int(hi)
+
+
+def _uniform(K):
+    return np.arange(K) * (math.pi / K)
+
+
+@pytest.mark.parametrize("K,D,N,dt", [
+    (2, 3, 2, 1.0), (90, 101, 70, 1.0), (180, 183, 128, 1.0), (40, 75, 50, 0.7), (4, 9, 100, 1.0),
+    (720, 725, 512, 1.0), (360, 365, 256, 1.0), (1440, 546, 384, 1.0), (720, 1451, 1024, 1.0),
+    (30, 101, 64, 0.36),
+])
+def test_qt_reads_stay_in_the_staged_window(K, D, N, dt):
+    WP, lo, hi = replay(K, D, N, dt, _uniform(K))
+    assert lo >= 1          # the window starts one bin below the tile's smallest coordinate
+    assert hi <= WP - 2
+    # the host's bound leaves two bins of margin above the largest bin read
+    assert hi <= WP - 4
+
+
+def test_qt_lds_fits_one_workgroup():
+    """Static LDS of the two pitches (16 waves x (pair constants + B pairs x 4 planes x
+    WP bins x 16 bytes), or the chunk sums) stays within gfx950's 160 KB."""
+    for wp, b in ((32, 4), (64, 2)):
+        prm = (2 * b * 24 + 15) & ~15
+        windows = CHUNKS * (prm + b * 4 * wp * 16)
+        parts = CHUNKS * 4 * TILE * (TILE + 1) * 4
+        assert max(windows, parts) <= 160 * 1024
+
+
+def test_replay_catches_a_pitch_too_small_for_the_window():
+    """The replay has teeth: at dt = 0.7 the window needs the 64-bin pitch; with the
+    32-bin one some pixel would read past the staged bins."""
+    K, D, N, dt = 40, 75, 50, 0.7
+    WP, lo, hi = replay(K, D, N, dt, _uniform(K))
+    assert WP == 64 and lo >= 1 and hi <= WP - 4
+    _, _, hi32 = replay(K, D, N, dt, _uniform(K), WP=32)
+    assert hi32 > 32 - 2
