@@ -92,6 +92,15 @@ def time_launches(fn, stream, n: int) -> float:
     return e0.elapsed_time(e1) / n
 
 
+def bp_kernel_name(shape_name: str) -> str:
+    """The backprojection kernel(s) one launch of a tile shape runs."""
+    if "angle chunks" in shape_name:
+        return "bp_qt_grid_kernel"
+    if "1 angle group" in shape_name:
+        return "bp_grid_kernel + combine_parts_kernel (angle-split single slice)"
+    return "bp_grid_kernel"
+
+
 def cpu_baseline(sl, seconds: float):
     """The FP64 oracle timed on the host cores over repeated whole reconstructions,
     with all threads (the reported value) and with one thread (3 runs)."""
@@ -218,8 +227,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": bp_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": bp_tflops / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": traffic,
-                     "kernel": "bp_grid_kernel" + (" + combine_parts_kernel (angle-split single slice)"
-                                                   if "1 angle group" in fbp.fbp_tile_config_name(cfg) else ""),
+                     "kernel": bp_kernel_name(fbp.fbp_tile_config_name(cfg)),
                      "kernel_ms": bp_ms, "flops_per_update": BP_FLOPS_PER_UPDATE,
                      "updates_per_launch": updates},
         "filter_gemm": {"kernel_ms": flt_ms, "dense_tflops": gemm_flops / (flt_ms * 1e-3) / 1e12,

@@ -905,7 +905,7 @@ hipError_t launch_combine_parts(const float* part, float* img, int n_slices, int
 }
 
 int bp_occupancy(int cfg, int m, size_t lds) {
-    if (cfg == kQtCfg32 || cfg == kQtCfg64) return 1;   // 16 waves and most of the LDS per workgroup
+    if (cfg == kQtCfg32 || cfg == kQtCfg64) return 1;   // one 16-wave workgroup per CU
     switch (kernel_key(cfg, m)) {
 #define X(id, tw, p, s, rot, mm) case kernel_key(id, mm): return occupancy<tw, p, s, rot, mm>(lds);
         FBP_FOR_EACH_KERNEL(X)

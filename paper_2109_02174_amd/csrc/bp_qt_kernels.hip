@@ -43,10 +43,14 @@ namespace {
 
 constexpr int kWaves = kQtChunks;     // angle chunks = waves per workgroup
 constexpr int kThreads = 64 * kWaves;
-constexpr int kTile = kQtTile;        // quadrant tile side
-constexpr int kRows = 4;              // rows per lane: 64 lanes x 4 rows = 16 x 16
+constexpr int kTile = kQtTile;        // quadrant tile width
+constexpr int kTileH = kQtTileH;      // quadrant tile height
+constexpr int kRows = kQtRows;        // rows per lane: 64 lanes x kRows rows = kTile x kTileH
 constexpr int kBufferWord3 = 0x00020000;
 constexpr int kPartPitch = kTile + 1; // row pitch of the chunk sums in LDS
+// Resident waves per SIMD asked of the compiler: four (one 16-wave workgroup per CU;
+// two rows per lane with twice the waves measured 30% slower).
+constexpr int kWavesPerSimd = 4;
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -64,14 +68,17 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
     return x * per + min(x, extra) + slot;
 }
 
-// LDS bytes of one wave's region: pair constants of two blocks (float4 + int2 per
-// pair), then B pairs x 4 planes x WP bins of float4.
+// Angle pairs whose window origins a wave makes at once (one per lane).
+constexpr int kRound = 64;
+
+// LDS bytes of one wave's region: the constants of a round of pairs (float4 +
+// int2 per pair), then B pairs x 4 planes x WP bins of float4.
 template <int WP, int B>
 struct QtLds {
-    static constexpr int PRM = ((2 * B * 24) + 15) & ~15;
+    static constexpr int PRM = kRound * 24;
     static constexpr int REGION = PRM + B * 4 * WP * 16;
     static constexpr int WINDOWS = kWaves * REGION;
-    static constexpr int PARTS = kWaves * 4 * kTile * kPartPitch * 4;
+    static constexpr int PARTS = kWaves * 4 * kTileH * kPartPitch * 4;
     static constexpr int BYTES = WINDOWS > PARTS ? WINDOWS : PARTS;
 };
 
@@ -98,8 +105,10 @@ __device__ __forceinline__ void pair_update(float u, float v, const float4& qu0,
 }
 
 // One tile (top-left corner (c0, r0) of the quadrant) of one slice: rows q
-// ([K][D]) into img ([N][N]).  smem holds QtLds<WP, B>::BYTES.
-template <int WP, int B>
+// ([K][D]) into img ([N][N]).  smem holds QtLds<WP, B>::BYTES.  WS: the job has
+// per-angle weights (a separate instantiation keeps the uniform path free of
+// their scalar loads, which would otherwise order the staging's LDS operations).
+template <int WP, int B, bool WS>
 __device__ __forceinline__ void qt_tile(const BpJob& job, const float* __restrict__ q, float* __restrict__ img,
                                         int c0, int r0, char* smem) {
     using L = QtLds<WP, B>;
@@ -111,8 +120,8 @@ __device__ __forceinline__ void qt_tile(const BpJob& job, const float* __restric
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int lane = t & 63;
     char* region = smem + wave * L::REGION;
-    float4* prm = reinterpret_cast<float4*>(region);                // [2][B] {bU, bV, cos/dt, sin/dt}
-    int2* pri = reinterpret_cast<int2*>(region + 2 * B * 16);       // [2][B] {iU, iV}
+    float4* prm = reinterpret_cast<float4*>(region);                // [kRound] {bU, bV, cos/dt, sin/dt}
+    int2* pri = reinterpret_cast<int2*>(region + kRound * 16);      // [kRound] {iU, iV}
     float4* win = reinterpret_cast<float4*>(region + L::PRM);       // [B][4][WP]
 
     const int N = job.N, D = job.D;
@@ -127,7 +136,6 @@ __device__ __forceinline__ void qt_tile(const BpJob& job, const float* __restric
     const float flx = (float)lx;
     const float fly = (float)ly0;
     const float nfly = -fly;
-    const int nxt = ((lane + 1) & 63) << 2;     // ds_bpermute source: lane + 1
     const int d4 = (D - 1) * 4;
     const int jl = lane & (WP - 1);             // window bin of this lane when staging
     const int wl = (WPASS == 2) ? (lane >> 5) : 0;
@@ -142,86 +150,112 @@ __device__ __forceinline__ void qt_tile(const BpJob& job, const float* __restric
         acc3[i] = 0.0f;
     }
 
-    // window origins (FP64) of the pairs lo + kb .. lo + kb + B - 1, into buffer buf
-    auto params = [&](int kb, int buf) {
-        const int k = lo + kb + lane;
-        if (lane < B && k < hi) {
+    // window origins (FP64) of the pairs lo + rs .. lo + rs + 63 of a round, one per lane
+    auto params = [&](int rs) {
+        const int k = lo + rs + lane;
+        if (k < hi) {
             const double cd = job.cs[2 * k];
             const double sd = job.cs[2 * k + 1];
             const double uo = x0 * cd + y0 * sd + job.centre_det;
-            const double umin = uo + fmin(0.0, (double)(kTile - 1) * cd) + fmin(0.0, (double)(kTile - 1) * sd);
+            const double umin = uo + fmin(0.0, (double)(kTile - 1) * cd) + fmin(0.0, (double)(kTileH - 1) * sd);
             const double vo = x0 * sd - y0 * cd + job.centre_det;
-            const double vmin = vo + fmin(0.0, (double)(kTile - 1) * sd) + fmin(0.0, -(double)(kTile - 1) * cd);
+            const double vmin = vo + fmin(0.0, (double)(kTile - 1) * sd) + fmin(0.0, -(double)(kTileH - 1) * cd);
             const int iu = (int)floor(umin) - 1;
             const int iv = (int)floor(vmin) - 1;
-            prm[buf * B + lane] = make_float4((float)(uo - (double)iu), (float)(vo - (double)iv), (float)cd, (float)sd);
-            pri[buf * B + lane] = make_int2(iu, iv);
+            prm[lane] = make_float4((float)(uo - (double)iu), (float)(vo - (double)iv), (float)cd, (float)sd);
+            pri[lane] = make_int2(iu, iv);
         }
     };
     // staging: pass ps covers windows ps*WPASS .. ps*WPASS + WPASS - 1 (window s =
     // 2 b + w: pair b, w = 0 the tile's window U, w = 1 the turned tile's V); each
-    // lane loads one bin of the forward and reversed rows at theta and theta + pi/2
-    float pf[NPASS][4];
-    auto load = [&](int kb, int buf) {
-        const int nb = min(B, n - kb);
+    // lane loads one bin and the next of the forward and reversed rows at theta and
+    // theta + pi/2 (the next bin from memory rather than from the next lane: the
+    // kernel is bound by LDS instructions, and this takes four per pair off them)
+    float pf[NPASS][4], pn[NPASS][4];
+    // The neighbour's byte offset is formed from an opaque 4, so the compiler does not
+    // fuse a bin's load and its neighbour's into one two-dword load: that load's range
+    // check would return zero for both when only the neighbour is off the detector.
+    int four;
+    asm volatile("v_mov_b32 %0, 4" : "=v"(four));
+    // kb: first pair of the block within the round (lo + rnd + kb overall)
+    int rnd = 0;
+    auto load = [&](int kb, int nr) {
+        const int nb = min(B, nr - kb);
 #pragma unroll
         for (int ps = 0; ps < NPASS; ++ps) {
             const int s0 = ps * WPASS;            // first window of the pass (uniform)
             const int b = s0 >> 1;                // pair (uniform: a pass never spans two pairs)
             if (b < nb) {
                 const int w = (WPASS == 2) ? wl : (s0 & 1);
-                const int k = lo + kb + b;
+                const int k = lo + rnd + kb + b;
                 const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
                     const_cast<float*>(q + (size_t)k * (size_t)D), (short)0, D * 4, kBufferWord3);
                 const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
                     const_cast<float*>(q + (size_t)(k + KH) * (size_t)D), (short)0, D * 4, kBufferWord3);
-                const int2 io = pri[buf * B + b];
+                const int2 io = pri[kb + b];
                 const int g4 = ((w ? io.y : io.x) + jl) * 4;
                 pf[ps][0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, g4, 0, 0));
                 pf[ps][1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, d4 - g4, 0, 0));
                 pf[ps][2] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, g4, 0, 0));
                 pf[ps][3] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, d4 - g4, 0, 0));
+                const int gn = g4 + four, dn = d4 - g4 - four;
+                pn[ps][0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, gn, 0, 0));
+                pn[ps][1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, dn, 0, 0));
+                pn[ps][2] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, gn, 0, 0));
+                pn[ps][3] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, dn, 0, 0));
             }
         }
     };
-    auto store = [&](int kb) {
-        const int nb = min(B, n - kb);
+    auto store = [&](int kb, int nr) {
+        const int nb = min(B, nr - kb);
+        float nx[NPASS][4];
+#pragma unroll
+        for (int ps = 0; ps < NPASS; ++ps) {
+            const int b = (ps * WPASS) >> 1;
+            if (b < nb) {
+                if constexpr (WS) {   // angle weights / (pi/K): scalar loads
+                    const int k = lo + rnd + kb + b;
+                    const float ca = wscale[k], cb = wscale[k + KH];
+                    pf[ps][0] *= ca;
+                    pf[ps][1] *= ca;
+                    pf[ps][2] *= cb;
+                    pf[ps][3] *= cb;
+                    pn[ps][0] *= ca;
+                    pn[ps][1] *= ca;
+                    pn[ps][2] *= cb;
+                    pn[ps][3] *= cb;
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) nx[ps][c] = pn[ps][c];
+            }
+        }
+        const float jj = (float)jl;
 #pragma unroll
         for (int ps = 0; ps < NPASS; ++ps) {
             const int s0 = ps * WPASS;
             const int b = s0 >> 1;
             if (b < nb) {
                 const int w = (WPASS == 2) ? wl : (s0 & 1);
-                if (wscale) {   // angle weights / (pi/K): scalar loads
-                    const int k = lo + kb + b;
-                    const float ca = wscale[k], cb = wscale[k + KH];
-                    pf[ps][0] *= ca;
-                    pf[ps][1] *= ca;
-                    pf[ps][2] *= cb;
-                    pf[ps][3] *= cb;
-                }
-                float nx[4];
+                float d[4];
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    nx[c] = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(nxt, __builtin_bit_cast(int, pf[ps][c])));
-                if (jl < WP - 1) {   // bin jl + 1 comes from the next lane of the same window
-                    const float jj = (float)jl;
-                    float d[4];
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) d[c] = nx[c] - pf[ps][c];
-                    float4* dst = win + (b * 4 + w * 2) * WP + jl;
-                    dst[0] = make_float4(fmaf(-jj, d[0], pf[ps][0]), d[0], fmaf(-jj, d[1], pf[ps][1]), d[1]);
-                    dst[WP] = make_float4(fmaf(-jj, d[2], pf[ps][2]), d[2], fmaf(-jj, d[3], pf[ps][3]), d[3]);
-                }
+                for (int c = 0; c < 4; ++c) d[c] = nx[ps][c] - pf[ps][c];
+                float4* dst = win + (b * 4 + w * 2) * WP + jl;
+                dst[0] = make_float4(fmaf(-jj, d[0], pf[ps][0]), d[0], fmaf(-jj, d[1], pf[ps][1]), d[1]);
+                dst[WP] = make_float4(fmaf(-jj, d[2], pf[ps][2]), d[2], fmaf(-jj, d[3], pf[ps][3]), d[3]);
             }
         }
     };
-    auto compute = [&](int kb, int buf) {
-        const int nb = min(B, n - kb);
+    auto compute = [&](int kb, int nr) {
+        const int nb = min(B, nr - kb);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             if (b < nb) {
-                const float4 p = prm[buf * B + b];    // bU, bV, cos, sin
+                // raised priority while the pair's window reads are issued, so that
+                // waves queue their reads early and do their updates in the shadow
+                // of other waves' reads
+                __builtin_amdgcn_sched_barrier(0);
+                __builtin_amdgcn_s_setprio(3);
+                const float4 p = prm[kb + b];    // bU, bV, cos, sin
                 const float u0 = fmaf(flx, p.z, fmaf(fly, p.w, p.x));
                 const float v0 = fmaf(flx, p.w, fmaf(nfly, p.z, p.y));
                 const float4* __restrict__ wu = win + b * 4 * WP;
@@ -239,6 +273,8 @@ __device__ __forceinline__ void qt_tile(const BpJob& job, const float* __restric
                     qv0[i] = wv[jv];
                     qv1[i] = wv[WP + jv];
                 }
+                __builtin_amdgcn_sched_barrier(0);
+                __builtin_amdgcn_s_setprio(0);
 #pragma unroll
                 for (int i = 0; i < kRows; ++i)
                     pair_update(u[i], v[i], qu0[i], qu1[i], qv0[i], qv1[i], acc0[i], acc1[i], acc2[i], acc3[i]);
@@ -246,17 +282,18 @@ __device__ __forceinline__ void qt_tile(const BpJob& job, const float* __restric
         }
     };
 
-    if (n > 0) {
-        params(0, 0);
+    // rounds of up to kRound pairs (one for K <= 2048): the window origins of the
+    // round, then blocks of B pairs, the next block's rows loaded during the current
+    for (rnd = 0; rnd < n; rnd += kRound) {
+        const int nr = min(kRound, n - rnd);
+        params(rnd);
         wave_sync();
-        load(0, 0);
-        int buf = 0;
-        for (int kb = 0; kb < n; kb += B, buf ^= 1) {
-            store(kb);
-            if (kb + B < n) params(kb + B, buf ^ 1);
+        load(0, nr);
+        for (int kb = 0; kb < nr; kb += B) {
+            store(kb, nr);
             wave_sync();
-            if (kb + B < n) load(kb + B, buf ^ 1);
-            compute(kb, buf);
+            if (kb + B < nr) load(kb + B, nr);
+            compute(kb, nr);
             wave_sync();
         }
     }
@@ -266,25 +303,25 @@ __device__ __forceinline__ void qt_tile(const BpJob& job, const float* __restric
     float* part = reinterpret_cast<float*>(smem);   // [wave][turn][row][kPartPitch]
 #pragma unroll
     for (int i = 0; i < kRows; ++i) {
-        float* pp = part + ((wave * 4) * kTile + ly0 + i) * kPartPitch + lx;
-        pp[0 * kTile * kPartPitch] = acc0[i];
-        pp[1 * kTile * kPartPitch] = acc1[i];
-        pp[2 * kTile * kPartPitch] = acc2[i];
-        pp[3 * kTile * kPartPitch] = acc3[i];
+        float* pp = part + ((wave * 4) * kTileH + ly0 + i) * kPartPitch + lx;
+        pp[0 * kTileH * kPartPitch] = acc0[i];
+        pp[1 * kTileH * kPartPitch] = acc1[i];
+        pp[2 * kTileH * kPartPitch] = acc2[i];
+        pp[3 * kTileH * kPartPitch] = acc3[i];
     }
     __syncthreads();
     const int turn = t >> 8;       // 0: p, 1: R p, 2: R^2 p, 3: R^3 p
-    const int e = t & 255;
+    const int e = t & 255;         // tile element (threads past kTile * kTileH idle)
     // p and R^2 p run along tile rows, R p and R^3 p along tile columns, so that
     // consecutive threads write consecutive image addresses
-    const int ty = (turn & 1) ? (e & (kTile - 1)) : (e >> 4);
-    const int tx = (turn & 1) ? (e >> 4) : (e & (kTile - 1));
-    const float* src = part + (turn * kTile + ty) * kPartPitch + tx;
+    const int ty = (turn & 1) ? (e % kTileH) : (e / kTile);
+    const int tx = (turn & 1) ? (e / kTileH) : (e % kTile);
+    const float* src = part + (turn * kTileH + ty) * kPartPitch + tx;
     float sum = 0.0f;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) sum += src[w * 4 * kTile * kPartPitch];
+    for (int w = 0; w < kWaves; ++w) sum += src[w * 4 * kTileH * kPartPitch];
     const int r = r0 + ty, c = c0 + tx, half = N >> 1;
-    if (r < half && c < half) {
+    if (e < kTile * kTileH && r < half && c < half) {
         size_t o;
         if (turn == 0) o = (size_t)r * N + c;
         else if (turn == 1) o = (size_t)c * N + (N - 1 - r);
@@ -294,8 +331,8 @@ __device__ __forceinline__ void qt_tile(const BpJob& job, const float* __restric
     }
 }
 
-template <int WP, int B>
-__global__ __launch_bounds__(kThreads) void bp_qt_grid_kernel(BpJob job, size_t q_stride, size_t img_stride,
+template <int WP, int B, bool WS>
+__global__ __launch_bounds__(kThreads, kWavesPerSimd) void bp_qt_grid_kernel(BpJob job, size_t q_stride, size_t img_stride,
                                                               int tiles_per_slice) {
     __shared__ __attribute__((aligned(16))) char smem[QtLds<WP, B>::BYTES];
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -303,14 +340,14 @@ __global__ __launch_bounds__(kThreads) void bp_qt_grid_kernel(BpJob job, size_t 
     const int tt = lb - s * tiles_per_slice;
     const int ty = tt / job.tiles_x;
     const int tx = tt - ty * job.tiles_x;
-    qt_tile<WP, B>(job, job.q + (size_t)s * q_stride, job.img + (size_t)s * img_stride, tx * kTile, ty * kTile,
+    qt_tile<WP, B, WS>(job, job.q + (size_t)s * q_stride, job.img + (size_t)s * img_stride, tx * kTile, ty * kTileH,
                    smem);
 }
 
 // Persistent form over a mixed list (same arguments as the other list kernels):
 // tile index -> job by binary search in the tile prefix; one job per slice.
 template <int WP, int B>
-__global__ __launch_bounds__(kThreads) void bp_qt_list_kernel(const BpListArgs* __restrict__ args) {
+__global__ __launch_bounds__(kThreads, kWavesPerSimd) void bp_qt_list_kernel(const BpListArgs* __restrict__ args) {
     __shared__ __attribute__((aligned(16))) char smem[QtLds<WP, B>::BYTES];
     const BpListArgs a = load_const(args);
     const auto* __restrict__ prefix = as_const(a.tile_prefix);
@@ -329,7 +366,10 @@ __global__ __launch_bounds__(kThreads) void bp_qt_list_kernel(const BpListArgs* 
         const int ty = tt / job.tiles_x;
         const int tx = tt - ty * job.tiles_x;
         __syncthreads();   // the previous tile's chunk sums are read before windows overwrite them
-        qt_tile<WP, B>(job, job.q, job.img, tx * kTile, ty * kTile, smem);
+        if (job.wscale)
+            qt_tile<WP, B, true>(job, job.q, job.img, tx * kTile, ty * kTileH, smem);
+        else
+            qt_tile<WP, B, false>(job, job.q, job.img, tx * kTile, ty * kTileH, smem);
     }
 }
 
@@ -341,25 +381,33 @@ int qt_pitch_for(int WL) {
     return 0;
 }
 
-int qt_block_pairs(int WP) { return WP == 32 ? 4 : 2; }
+int qt_block_pairs(int WP) { return WP == 32 ? 2 : 1; }
 
 hipError_t launch_bp_qt_grid(const BpJob& job, int n_slices, size_t q_stride, size_t img_stride,
                              int tiles_per_slice, hipStream_t stream) {
     const long long grid = (long long)n_slices * tiles_per_slice;
     if (grid <= 0) return hipSuccess;
     if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
+    constexpr int B32 = 2, B64 = 1;
+    const dim3 g((unsigned)grid), b(kThreads);
+    const bool ws = job.wscale != nullptr;
     if (job.WL == 32)
-        return launch_kernel(bp_qt_grid_kernel<32, 4>, dim3((unsigned)grid), dim3(kThreads), 0, stream, job, q_stride,
-                             img_stride, tiles_per_slice);
+        return ws ? launch_kernel(bp_qt_grid_kernel<32, B32, true>, g, b, 0, stream, job, q_stride, img_stride,
+                                  tiles_per_slice)
+                  : launch_kernel(bp_qt_grid_kernel<32, B32, false>, g, b, 0, stream, job, q_stride, img_stride,
+                                  tiles_per_slice);
     if (job.WL == 64)
-        return launch_kernel(bp_qt_grid_kernel<64, 2>, dim3((unsigned)grid), dim3(kThreads), 0, stream, job, q_stride,
-                             img_stride, tiles_per_slice);
+        return ws ? launch_kernel(bp_qt_grid_kernel<64, B64, true>, g, b, 0, stream, job, q_stride, img_stride,
+                                  tiles_per_slice)
+                  : launch_kernel(bp_qt_grid_kernel<64, B64, false>, g, b, 0, stream, job, q_stride, img_stride,
+                                  tiles_per_slice);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_bp_qt_list(int WP, const BpListArgs* a, int grid, hipStream_t stream) {
-    if (WP == 32) return launch_kernel(bp_qt_list_kernel<32, 4>, dim3(grid), dim3(kThreads), 0, stream, a);
-    if (WP == 64) return launch_kernel(bp_qt_list_kernel<64, 2>, dim3(grid), dim3(kThreads), 0, stream, a);
+    constexpr int B32 = 2, B64 = 1;
+    if (WP == 32) return launch_kernel(bp_qt_list_kernel<32, B32>, dim3(grid), dim3(kThreads), 0, stream, a);
+    if (WP == 64) return launch_kernel(bp_qt_list_kernel<64, B64>, dim3(grid), dim3(kThreads), 0, stream, a);
     return hipErrorInvalidValue;
 }
 

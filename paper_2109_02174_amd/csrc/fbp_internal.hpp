@@ -85,7 +85,9 @@ constexpr int kNumTileConfigs = 15;
 constexpr int kQtCfg32 = 13;
 constexpr int kQtCfg64 = 14;
 constexpr int kQtChunks = 16;
-constexpr int kQtTile = 16;
+constexpr int kQtTile = 16;                 // tile width (columns); one column per lane of a 16-lane row
+constexpr int kQtRows = 4;                  // rows per lane
+constexpr int kQtTileH = 4 * kQtRows;       // tile height: four 16-lane rows of a wave
 constexpr int kMaxKB = 64;
 // Most angle parts a single slice's backprojection is split into (one-group shapes).
 constexpr int kMaxSplit = 16;

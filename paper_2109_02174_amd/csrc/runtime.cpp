@@ -291,9 +291,11 @@ bool shape_params(int cfg, const std::vector<double>& cs, const std::vector<doub
         // window that fits this id's pitch (one bin short of it: the staging pairs
         // each bin with the next lane's)
         if ((N & 1) || !quarter_turn_symmetric(angles)) return false;
-        double span = 0.0;
-        for (size_t k = 0; 2 * k + 1 < cs.size(); ++k)
-            span = std::max(span, (kQtTile - 1) * (std::fabs(cs[2 * k]) + std::fabs(cs[2 * k + 1])));
+        double span = 0.0;   // the tile and its turn: (W-1)|c| + (H-1)|s| and (W-1)|s| + (H-1)|c|
+        for (size_t k = 0; 2 * k + 1 < cs.size(); ++k) {
+            const double c = std::fabs(cs[2 * k]), sn = std::fabs(cs[2 * k + 1]);
+            span = std::max(span, std::max((kQtTile - 1) * c + (kQtTileH - 1) * sn, (kQtTile - 1) * sn + (kQtTileH - 1) * c));
+        }
         if (!(span < 1e6)) return false;
         const int wl = window_length(span);
         const int pitch = (cfg == kQtCfg32) ? 32 : 64;
@@ -303,7 +305,7 @@ bool shape_params(int cfg, const std::vector<double>& cs, const std::vector<doub
         sp->seg_shift = 0;
         const int half = N / 2;
         sp->tiles_x = (half + kQtTile - 1) / kQtTile;
-        sp->tiles_y = sp->tiles_x;
+        sp->tiles_y = (half + kQtTileH - 1) / kQtTileH;
         return true;
     }
     if (s.rot) {
@@ -786,12 +788,22 @@ int ensure_taps(Plan* p, int prec) {
             const float v = (float)(taps[i] * scale);
             h16[i] = (prec == kBF16) ? bf16_bits_rne(v) : f16_bits_rne(v);
         }
-        const float c = (float)(centre * scale);
-        if (prec == kBF16) {
-            const uint32_t u = (uint32_t)bf16_bits_rne(c) << 16;
-            std::memcpy(&diag, &u, 4);
-        } else {
-            diag = (float)(_Float16)c;
+        if (!full) {
+            // The centre tap is applied in the FP32 epilogue, so it stays FP32 and takes
+            // the value that makes the rounded kernel sum to the exact one: with rows of
+            // large smooth projections, the rounded odd taps' sum error would otherwise
+            // leak the rows' mean into the filtered rows.
+            double exact = centre, rounded = 0.0;
+            for (int d = 1; d <= D - 1; d += 2) exact += 2.0 * filter_tap(p->filter, d, p->dt);
+            for (size_t i = 0; i < taps.size(); ++i) {
+                if (taps[i] == 0.0) continue;
+                const uint32_t u = (prec == kBF16) ? (uint32_t)h16[i] << 16 : 0u;
+                float r;
+                if (prec == kBF16) std::memcpy(&r, &u, 4);
+                else r = (float)(_Float16)(float)(taps[i] * scale);
+                rounded += (double)r;
+            }
+            diag = (float)(exact * scale - rounded);
         }
         bytes = h16.size() * 2;
     }

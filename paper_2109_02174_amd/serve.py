@@ -12,11 +12,16 @@ waiter per stream resolves each request's future when its batch completes,
 returns its bytes to the budget, and records latency from arrival to
 completion.
 
-Every image equals the image the same request gets alone within the FP32
-tolerance, and bitwise when both ran with the same tile shape: a geometry with
-4 or more slices in a batch takes its stack shape, otherwise its single-slice
-shape (see include/fbp.h); tile shapes and summation order depend only on the
-geometry and that choice.
+A batch is closed once its estimated cost (pixel-angle updates, N^2 K per
+slice) or slice count would pass a bound, so a request that arrives behind a
+long queue waits for bounded batches rather than for one batch holding
+everything admitted before it; up to n_streams bounded batches run at once.
+
+Every image equals the image the same request gets alone: bitwise for
+quarter-turn geometries (even N, angles closed under +pi/2), whose tile shape
+and summation order depend on the geometry alone, and within the FP32 tolerance
+otherwise, where a geometry with 4 or more slices in a batch takes its stack
+shape and a shorter run its single-slice shape (see include/fbp.h).
 
 The executor is an interface, so the scheduling logic runs on the CPU in tests
 with a fake executor; GpuExecutor drives libfbp.
@@ -42,6 +47,7 @@ class Request:
     sino: object            # device tensor [B][K][D]
     n_slices: int
     nbytes: int = 0         # device footprint while admitted
+    cost: int = 0           # pixel-angle updates
     arrival: float = 0.0
     rid: int = -1
     future: Future = field(default_factory=Future)
@@ -51,6 +57,16 @@ class Request:
 def footprint_bytes(K: int, D: int, N: int, n_slices: int) -> int:
     """Device bytes a request holds while admitted: sinogram + filtered rows + image."""
     return n_slices * (2 * K * D + N * N) * 4
+
+
+def request_cost(K: int, N: int, n_slices: int) -> int:
+    """Work of a request in pixel-angle updates (the backprojection's N^2 K per slice)."""
+    return n_slices * N * N * K
+
+
+# Default bound on a batch's cost: about two milliseconds of backprojection at the
+# single-GPU rate (~5e12 updates/s); one request larger than this runs alone.
+DEFAULT_BATCH_COST = 10 ** 10
 
 
 class Executor:
@@ -116,10 +132,11 @@ class Server:
     """Continuous batching over `executor.n_streams` streams under an HBM budget."""
 
     def __init__(self, executor: Executor, hbm_budget_bytes: int, max_batch_slices: int = 4096,
-                 clock=time.perf_counter):
+                 max_batch_cost: int = DEFAULT_BATCH_COST, clock=time.perf_counter):
         self.ex = executor
         self.budget = int(hbm_budget_bytes)
         self.max_batch_slices = max_batch_slices
+        self.max_batch_cost = max_batch_cost
         self.clock = clock
         self._lock = threading.Condition()
         self._pending = collections.deque()      # arrived, not admitted (FIFO)
@@ -146,7 +163,8 @@ class Server:
     def submit(self, geom, sino, n_slices: int = None) -> Future:
         n = int(sino.shape[0]) if n_slices is None else int(n_slices)
         req = Request(geom=geom, sino=sino, n_slices=n,
-                      nbytes=footprint_bytes(geom.n_angles, geom.n_det, geom.image_size, n))
+                      nbytes=footprint_bytes(geom.n_angles, geom.n_det, geom.image_size, n),
+                      cost=request_cost(geom.n_angles, geom.image_size, n))
         req.arrival = self.clock()
         req.rid = next(self._ids)
         if req.nbytes > self.budget:
@@ -216,11 +234,13 @@ class Server:
                 if self._stop:
                     return
                 s = self._free_streams.pop(0)
-                batch, n = [], 0
-                while self._admitted and (not batch or n + self._admitted[0].n_slices <= self.max_batch_slices):
+                batch, n, cost = [], 0, 0
+                while self._admitted and (not batch or (n + self._admitted[0].n_slices <= self.max_batch_slices and
+                                                        cost + self._admitted[0].cost <= self.max_batch_cost)):
                     r = self._admitted.popleft()
                     batch.append(r)
                     n += r.n_slices
+                    cost += r.cost
             try:
                 handle = self.ex.launch(s, batch)
             except Exception as e:   # launch failure: fail the batch, free its memory and stream

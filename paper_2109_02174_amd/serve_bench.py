@@ -5,7 +5,8 @@ mixed batch (side {256,384,512,1024}, angles {360,720,1440}, detectors
 ceil(sqrt(2) side)+2), FP32.  Sinograms are placed in HBM before the run (a pool
 of 64 seeded phantom slices per geometry that requests read from; host-to-device
 transfer is outside the measurement).  The server admits requests under a 200 GB
-HBM budget and batches continuously over two streams.
+HBM budget and batches continuously over four streams, each batch bounded in
+cost (pixel-angle updates).
 
 First the saturation throughput is measured (all requests offered at once),
 then a sweep of offered loads from 25% to 120% of it.  At every point the same
@@ -13,6 +14,7 @@ arrival sequence is also served by the plain baseline: FIFO, one slice per
 fbp_reconstruct call, one stream, synchronous.  Latency is arrival to completion.
 
 python -m paper_2109_02174_amd.serve_bench [--requests 2000] [--points 0.25,0.5,0.75,1.0,1.2]
+                                           [--streams 4] [--batch-cost 1e10]
 """
 from __future__ import annotations
 
@@ -61,10 +63,11 @@ def build_pools(device="cuda", per_geom: int = 64):
     return pools, geoms
 
 
-def run_server(reqs, arrivals, pools, geoms, n_streams=2, collect=None):
+def run_server(reqs, arrivals, pools, geoms, n_streams=4, batch_cost=None, collect=None):
     """Serve the requests at the given arrival offsets (seconds); return stats."""
-    from .serve import GpuExecutor, Server
-    srv = Server(GpuExecutor(n_streams=n_streams), BUDGET_BYTES)
+    from .serve import DEFAULT_BATCH_COST, GpuExecutor, Server
+    srv = Server(GpuExecutor(n_streams=n_streams), BUDGET_BYTES,
+                 max_batch_cost=DEFAULT_BATCH_COST if batch_cost is None else int(batch_cost))
     kept = {}
     t0 = time.perf_counter()
     for i, ((side, K, n), at) in enumerate(zip(reqs, arrivals)):
@@ -121,7 +124,12 @@ def main():
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--points", default="0.25,0.5,0.75,1.0,1.2")
     ap.add_argument("--no-baseline", action="store_true")
+    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--batch-cost", type=float, default=None,
+                    help="bound on a batch's pixel-angle updates (default: serve.DEFAULT_BATCH_COST)")
     args = ap.parse_args()
+    if not 1 <= args.streams <= 4:
+        ap.error("--streams must be 1 to 4")
     import torch
 
     from . import _binding as fbp
@@ -129,17 +137,19 @@ def main():
     tuned = {f"{k[0]}x{k[1]}": fbp.fbp_autotune(g) for k, g in sorted(geoms.items())}
     reqs, gaps = make_requests(args.requests)
     torch.cuda.synchronize()
-    run_server(reqs[:50], np.zeros(50), pools, geoms)                     # warm-up: plans, graphs
-    sat = run_server(reqs, np.zeros(len(reqs)), pools, geoms)             # offered load: everything at t=0
+    kw = {"n_streams": args.streams, "batch_cost": args.batch_cost}
+    run_server(reqs[:50], np.zeros(50), pools, geoms, **kw)               # warm-up: plans, graphs
+    sat = run_server(reqs, np.zeros(len(reqs)), pools, geoms, **kw)       # offered load: everything at t=0
     out = {"workload": "Poisson arrivals, requests of U{1..64} slices of one mixed geometry, FP32, "
-                       "sinograms resident in HBM, budget 200 GB, 2 streams",
+                       f"sinograms resident in HBM, budget 200 GB, {args.streams} streams, batch cost bound "
+                       f"{args.batch_cost or 'default'}",
            "requests_per_point": len(reqs), "saturation": sat, "tile_config_per_geometry": tuned,
            "points": []}
     sat_qps = sat["requests_per_s"]
     for f in [float(x) for x in args.points.split(",")]:
         qps = f * sat_qps
         arrivals = np.cumsum(gaps) / qps
-        pt = {"load": f, "qps": qps, "served": run_server(reqs, arrivals, pools, geoms)}
+        pt = {"load": f, "qps": qps, "served": run_server(reqs, arrivals, pools, geoms, **kw)}
         if not args.no_baseline:
             pt["one_slice_per_launch"] = run_baseline(reqs, arrivals, pools, geoms)
         out["points"].append(pt)

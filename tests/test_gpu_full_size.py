@@ -1,10 +1,12 @@
 """GPU parity at the full workload sizes, on sampled slices the oracle recomputes.
 
 * 256-slice stack of 512^2 / 720 angles / 725 bins (the precision sweep), one
-  fbp_reconstruct call per precision: sampled slices vs the FP64 oracle (FP32
-  gated at the stated tolerance, BF16/FP16 stated with loose floors).
+  fbp_reconstruct call per precision: eight slices spread over the stack vs the
+  FP64 oracle (FP32 gated at the stated tolerance; BF16 and FP16 at floors a few
+  dB under their measured errors, which are printed).
 * The 1000-slice mixed batch (one fbp_reconstruct_batch call, as the batch
-  benchmark runs it): the smallest, median and largest slices vs the oracle.
+  benchmark runs it): one slice of every distinct geometry (side x angle count)
+  vs the oracle.
 Sinograms are generated in HBM in FP64 by the input generator; the oracle gets
 the same FP64 values copied to the host.
 """
@@ -21,6 +23,11 @@ from paper_2109_02174_amd.batch_bench import build_jobs
 pytestmark = pytest.mark.gpu
 
 
+SAMPLE = (0, 37, 74, 97, 150, 201, 230, 255)
+MIN_PSNR = {"bf16": 45.0, "fp16": 60.0}
+_refs = {}
+
+
 def _stack(n=256):
     g = configs.C3["geom"]
     geo = fbp.Geometry(g.K, g.D, g.N, g.dt, ph.uniform_angles(g.K))
@@ -28,7 +35,7 @@ def _stack(n=256):
     for i in range(n):
         ells = ph.draw_ellipses(ph.rng_for(3, i), 20)
         s64 = ph.ellipse_sinogram_device(ells, g.N, g.D, g.dt, geo.angles)
-        if i in (0, 97, 255):
+        if i in SAMPLE:
             host[i] = (s64.cpu().numpy(), ph.rasterise(ells, g.N))
         sl.append(s64.to(torch.float32))
     return geo, torch.stack(sl).contiguous(), host
@@ -39,29 +46,30 @@ def stack():
     return _stack()
 
 
-@pytest.mark.parametrize("prec,gate", [("fp32", True), ("bf16", False), ("fp16", False)])
-def test_precision_sweep_stack_sampled_slices(stack, prec, gate):
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_precision_sweep_stack_sampled_slices(stack, prec):
     geo, sino, host = stack
     out = fbp.fbp_reconstruct(geo, sino, precision=prec)
     torch.cuda.synchronize()
     for i, (s64, raster) in host.items():
-        ref = oracle.fbp(s64, geo.image_size, geo.det_spacing, geo.angles)
+        if i not in _refs:
+            _refs[i] = oracle.fbp(s64, geo.image_size, geo.det_spacing, geo.angles)
         R = float(raster.max() - raster.min())
-        m = metrics.compare(out[i].cpu().numpy(), ref, R)
+        m = metrics.compare(out[i].cpu().numpy(), _refs[i], R)
         print(prec, i, m)
-        if gate:
+        if prec == "fp32":
             assert m["max_abs_rel"] <= 2e-4 and m["rmse_rel"] <= 2e-5 and m["psnr_db"] >= 94
-        elif prec == "fp16":
-            assert m["psnr_db"] >= 55
         else:
-            assert m["psnr_db"] >= 20
+            assert m["psnr_db"] >= MIN_PSNR[prec]
 
 
-def test_mixed_batch_full_size_sampled_slices():
+def test_mixed_batch_full_size_one_slice_per_geometry():
     geoms = configs.c4_geometries(1000)
-    upd = np.array([g.N * g.N * g.K for g in geoms])
-    order = np.argsort(upd, kind="stable")
-    sample = {int(order[0]), int(order[len(order) // 2]), int(order[-1])}
+    first = {}
+    for i, g in enumerate(geoms):
+        first.setdefault((g.N, g.K), i)
+    sample = set(first.values())
+    assert len(sample) == 12
     jobs, _, host = build_jobs(1000, keep_host=sample)
     fbp.fbp_reconstruct_batch(jobs)
     torch.cuda.synchronize()

@@ -1,27 +1,47 @@
-"""GPU: the continuous-batching server on libfbp.  Every served image equals the
-image of reconstructing that request alone, whatever else shared its batch:
-bitwise where both ran with the same tile shape, and within the FP32 tolerance
-where the batch gave the request's geometry its stack shape (4 or more slices of
-it in the batch) and the request alone did not, or the other way round."""
+"""GPU: the continuous-batching server on libfbp.
+
+Every served image is checked against the FP64 oracle (the filtered
+backprojection of Eq. 2, section "Computed tomography") at the FP32 gate, and
+against the image of reconstructing that request alone, whatever else shared
+its batch: bitwise for quarter-turn geometries (even N, uniform angles with even
+K), whose tile shape and summation order depend on the geometry alone, and
+within the FP32 tolerance for the others, where the batch may give a geometry
+its stack shape and the request alone its single-slice shape.
+"""
 import numpy as np
 import pytest
 import torch
 
+import oracle
 import paper_2109_02174_amd as fbp
+from paper_2109_02174_amd import configs, metrics
 from paper_2109_02174_amd import phantom as ph
 from paper_2109_02174_amd.serve import GpuExecutor, Server
+from paper_2109_02174_amd.serve_bench import make_requests
 
 pytestmark = pytest.mark.gpu
 
 GEOMS = [(64, 90, 93), (100, 120, 145), (128, 180, 183), (33, 37, 49)]
 
 
-def test_served_images_equal_alone_under_poisson_arrivals():
+def _quarter_turn(g):
+    return g.image_size % 2 == 0 and g.n_angles % 2 == 0
+
+
+def _gate(got, ref, value_range):
+    m = metrics.compare(got, ref, value_range)
+    assert m["max_abs_rel"] <= 2e-4 and m["rmse_rel"] <= 2e-5 and m["psnr_db"] >= 94, m
+    return m
+
+
+def test_served_images_match_oracle_and_alone_under_poisson_arrivals():
     geoms = {k: fbp.Geometry(k[1], k[2], k[0]) for k in GEOMS}
     rng = ph.rng_for(1200, 0)
-    pools = {k: torch.tensor(np.stack([ph.ellipse_slice(1200, 10 * i + b, k[0], k[1], k[2], n_ellipses=5).sino
-                                       for b in range(6)]).astype(np.float32), device="cuda")
-             for i, k in enumerate(GEOMS)}
+    slices = {k: [ph.ellipse_slice(1200, 10 * i + b, k[0], k[1], k[2], n_ellipses=5) for b in range(6)]
+              for i, k in enumerate(GEOMS)}
+    pools = {k: torch.tensor(np.stack([s.sino for s in v]).astype(np.float32), device="cuda")
+             for k, v in slices.items()}
+    refs = {k: [oracle.fbp(s.sino, k[0], 1.0, geoms[k].angles) for s in v] for k, v in slices.items()}
     srv = Server(GpuExecutor(n_streams=2), hbm_budget_bytes=64 << 20)
     sent = []
     for i in range(40):
@@ -36,6 +56,55 @@ def test_served_images_equal_alone_under_poisson_arrivals():
     assert st["completed"] == 40 and st["failed"] == 0
     assert st["batches"] < 40                      # arrivals were batched together
     for k, n, f in sent:
-        alone = fbp.fbp_reconstruct(geoms[k], pools[k][:n]).cpu().numpy()
         got = f.result().cpu().numpy()
-        assert np.max(np.abs(got - alone)) <= 2e-4 * np.max(np.abs(alone))
+        for b in range(n):
+            _gate(got[b].astype(np.float64), refs[k][b], slices[k][b].value_range)
+        alone = fbp.fbp_reconstruct(geoms[k], pools[k][:n]).cpu().numpy()
+        if _quarter_turn(geoms[k]):
+            assert np.array_equal(got, alone)
+        else:
+            assert np.max(np.abs(got - alone)) <= 2e-4 * np.max(np.abs(alone))
+
+
+def test_serving_mix_full_size_matches_oracle():
+    """About 20 requests drawn from the serving workload's mix (sides 256 ... 1024,
+    360 ... 1440 angles, detectors ceil(sqrt 2 side) + 2, 1 ... 64 slices of one
+    geometry each), arriving while earlier batches run: every slice bitwise equal to
+    its request reconstructed alone, and the first slice of every request against
+    the FP64 oracle at the FP32 gate."""
+    reqs, _ = make_requests(20)
+    assert {r[0] for r in reqs} >= {256, 512, 1024} and max(r[2] for r in reqs) > 32
+    geoms, pools, host = {}, [], []
+    for i, (side, K, n) in enumerate(reqs):
+        key = (side, K)
+        if key not in geoms:
+            geoms[key] = fbp.Geometry(K, configs.c4_detectors(side), side, 1.0, ph.uniform_angles(K))
+        g = geoms[key]
+        sl = []
+        for b in range(n):
+            ells = ph.draw_ellipses(ph.rng_for(1210, 100 * i + b), 20)
+            s64 = ph.ellipse_sinogram_device(ells, side, g.n_det, 1.0, g.angles)
+            if b == 0:
+                host.append((s64.cpu().numpy(), ph.rasterise(ells, side)))
+            sl.append(s64.to(torch.float32))
+        pools.append(torch.stack(sl).contiguous())
+    srv = Server(GpuExecutor(n_streams=2), hbm_budget_bytes=200 * 10 ** 9)
+    rng = ph.rng_for(1210, 999)
+    futs = []
+    for i, (side, K, n) in enumerate(reqs):
+        futs.append(srv.submit(geoms[(side, K)], pools[i]))
+        if rng.uniform() < 0.4:
+            torch.cuda.synchronize()
+    assert srv.drain(timeout=300)
+    st = srv.stats()
+    srv.shutdown()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    for i, (side, K, n) in enumerate(reqs):
+        g = geoms[(side, K)]
+        got = futs[i].result()
+        alone = fbp.fbp_reconstruct(g, pools[i])
+        assert torch.equal(got, alone), f"request {i} ({side}, {K}, {n}) differs from alone"
+        s64, raster = host[i]
+        ref = oracle.fbp(s64, side, 1.0, g.angles)
+        m = _gate(got[0].cpu().numpy().astype(np.float64), ref, float(raster.max() - raster.min()))
+        print(i, side, K, n, m)

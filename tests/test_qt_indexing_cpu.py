@@ -98,10 +98,10 @@ def test_qt_reads_stay_in_the_staged_window(K, D, N, dt):
 
 
 def test_qt_lds_fits_one_workgroup():
-    """Static LDS of the two pitches (16 waves x (pair constants + B pairs x 4 planes x
-    WP bins x 16 bytes), or the chunk sums) stays within gfx950's 160 KB."""
-    for wp, b in ((32, 4), (64, 2)):
-        prm = (2 * b * 24 + 15) & ~15
+    """Static LDS of the two pitches (16 waves x (constants of 64 pairs + B pairs x 4
+    planes x WP bins x 16 bytes), or the chunk sums) stays within gfx950's 160 KB."""
+    for wp, b in ((32, 2), (64, 1)):
+        prm = 64 * 24
         windows = CHUNKS * (prm + b * 4 * wp * 16)
         parts = CHUNKS * 4 * TILE * (TILE + 1) * 4
         assert max(windows, parts) <= 160 * 1024

@@ -2,8 +2,9 @@
 
 Covers admission under the HBM budget, rejection of oversized requests, FIFO
 admission, continuous batching (arrivals during a running batch join the next
-one), overlap of batches on several streams, failure isolation, and delivery of
-correct images (an executor that reconstructs with the FP64 oracle).
+one), the bound on a batch's cost, overlap of batches on several streams,
+failure isolation, and delivery of correct images (an executor that
+reconstructs with the FP64 oracle).
 """
 import threading
 import time
@@ -14,7 +15,7 @@ import pytest
 import oracle
 from paper_2109_02174_amd import phantom as ph
 from paper_2109_02174_amd._binding import Geometry
-from paper_2109_02174_amd.serve import Executor, RequestTooLarge, Server, footprint_bytes
+from paper_2109_02174_amd.serve import Executor, RequestTooLarge, Server, footprint_bytes, request_cost
 
 
 class FakeSino:
@@ -122,6 +123,26 @@ def test_arrivals_during_a_batch_join_the_next_batch():
     assert len(ex.batches[0][1]) == 1
     assert len(ex.batches[1][1]) == 6
     assert all(f.exception() is None for f in rest + [first])
+    srv.shutdown()
+
+
+def test_batch_cost_is_bounded_and_order_kept():
+    """A queue of admitted requests is cut into batches of at most max_batch_cost
+    updates (in arrival order); a request costlier than the bound runs alone."""
+    g = _geom()
+    unit = request_cost(g.n_angles, g.image_size, 1)
+    ex = SleepExecutor(n_streams=1, run_s=0.2)
+    srv = Server(ex, hbm_budget_bytes=1 << 30, max_batch_cost=5 * unit)
+    first = srv.submit(g, FakeSino(1))
+    time.sleep(0.05)                              # the rest queue behind the first batch
+    sizes = [2, 2, 2, 9, 1, 3, 1, 1]
+    futs = [srv.submit(g, FakeSino(n)) for n in sizes]
+    assert srv.drain(timeout=20)
+    assert all(f.exception() is None for f in futs + [first])
+    got = [[r - 1 for r in rids] for _, rids in ex.batches[1:]]   # request ids of the queued ones
+    assert got == [[0, 1], [2], [3], [4, 5, 6], [7]]
+    for b in got:
+        assert sum(sizes[i] for i in b) * unit <= 5 * unit or len(b) == 1
     srv.shutdown()
 
 
