@@ -293,6 +293,8 @@ struct GemmJob {
     const void* taps_even;
     const float* colw;    // [D] factor per input column applied to P before the product
                           // (fan-beam pre-weights), or null
+    int32_t wide;         // FP32 only: 1 = tiles of 96 output bins (tiles_n = ceil(D / 96)), 0 = 64
+    int32_t pad_;
 };
 static_assert(sizeof(GemmJob) % 8 == 0, "GemmJob layout");
 
@@ -309,7 +311,9 @@ struct GemmListArgs {
 // `args` is a DEVICE pointer (the batch header in the workspace).
 hipError_t launch_gemm_list(int prec, bool full, const GemmListArgs* args, int grid, size_t lds_bytes,
                             hipStream_t stream);
-int gemm_lds_bytes(int prec, int Dh);
+// LDS of a filter workgroup; full: the kernel has even taps too (their copies
+// double the tap area); wide: FP32 96-bin tiles.
+int gemm_lds_bytes(int prec, int Dh, bool full, bool wide = false);
 int gemm_occupancy(int prec, bool full, size_t lds_bytes);
 
 }  // namespace fbp

@@ -113,34 +113,65 @@ __device__ __forceinline__ void store_block(const v4f& acc, const GemmJob& job, 
 
 constexpr int kK32 = 32;                  // inputs per parity per chunk
 constexpr int kPD = 4;                    // chunks in flight (register ring)
-constexpr int kAS32 = kK32 + 1;           // LDS row stride (floats)
-constexpr int kABuf32 = 2 * kTM * kAS32;  // floats per panel buffer
+constexpr int kAS32 = kK32 + 4;           // LDS row stride (floats): 16-byte rows, no bank conflicts
+constexpr int kPar32 = kTM * kAS32 + 32;  // parity plane stride (floats; 32 banks apart, so the two
+                                          // parities' stores of one column pair never share a bank)
+constexpr int kABuf32 = 2 * kPar32;       // floats per panel buffer
+
+// Tap copies of the FP32 path: y runs over [jlo, jhi], jhi = nh0 + HN (HN output
+// bins per parity); copy s (s = 0..3) holds to(jhi - (x + s)) at x, so the eight
+// taps a lane needs for the eight k-steps of a chunk (descending y) are eight
+// consecutive floats of one copy starting at a multiple of four: two aligned
+// 16-byte reads.  The copies sit 16 banks apart (stride = 16 mod 64 floats), so the
+// 16 lanes of a row, which read four offsets in each of the four copies, cover the
+// 64 banks once.
+__host__ __device__ constexpr int copy_stride32(int mpad, int hn) {
+    const int s = (mpad + hn + 8 + 3) & ~3;
+    return s + ((16 - s % 64) + 64) % 64;
+}
 
 // FULL: the kernel also has even taps; even outputs then take even inputs through
 // te and odd outputs odd inputs (the same-parity half of the panel), doubling the
 // MFMAs of the parity-split product.
-template <bool FULL, bool CW>
+//
+// The inputs of a chunk are assigned to the MFMA k-steps as m' = mh0 + 8 q + kk
+// (q = lane / 16, kk = k-step 0..7), so a lane's A values and B values over the
+// chunk's eight k-steps are eight consecutive floats in LDS: two 16-byte reads for A
+// and two per 16-wide block for B, instead of one 4-byte read per k-step.
+template <bool FULL, bool CW, int NB>
 __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt, char* smem) {
-    float* As = reinterpret_cast<float*>(smem);          // [2 buffers][2 parity][32 rows][kAS32]
-    float* Bt = As + 2 * kABuf32;                        // odd taps j = jlo + x, then even taps
+    constexpr int HN = 16 * NB;                          // output bins per parity of the tile
+    float* As = reinterpret_cast<float*>(smem);          // [2 buffers][2 parity planes][32 rows][kAS32]
+    float* Tc = As + 2 * kABuf32;                        // 4 copies of the odd taps, then of the even taps
     const int t = threadIdx.x;
     const int w = t >> 6, l = t & 63;
     const int wm = w >> 1, sg = w & 1;                   // row half, output parity
-    const int m0 = mt * kTM, nh0 = nt * kHalfN;
+    const int m0 = mt * kTM, nh0 = nt * HN;
     const int R = job.R, D = job.D, Dh = job.Dh, Dhp = job.Dhp;
     const float* __restrict__ taps = static_cast<const float*>(job.taps);
     const float* __restrict__ P = job.p;
     const int mpad = (Dh + kK32 - 1) / kK32 * kK32;       // inputs per parity, padded
-    const int jlo = nh0 - mpad + 1;
-    const int n_taps = mpad + kHalfN;                    // j in [jlo, nh0 + 32]
-
-    float* Be = Bt + n_taps;                             // te(jlo + x) (FULL)
+    const int jhi = nh0 + HN;
+    const int cstride = copy_stride32(mpad, HN);
+    float* Te = Tc + 4 * cstride;                        // even-tap copies (FULL)
 
     __syncthreads();   // LDS reuse across tiles of a persistent workgroup
-    for (int x = t; x < n_taps; x += kBpThreads) Bt[x] = taps[jlo + x + Dhp];
-    if constexpr (FULL) {
-        const float* __restrict__ te = static_cast<const float*>(job.taps_even);
-        for (int x = t; x < n_taps; x += kBpThreads) Be[x] = te[jlo + x + Dhp];
+    // one load per tap, stored into the four copies (element x - c of copy c)
+#pragma unroll 2
+    for (int x = t; x < cstride + 3; x += kBpThreads) {
+        const int idx = jhi - x + Dhp;                   // table index of to(jhi - x)
+        const bool in = idx >= 0 && idx <= 2 * Dhp;
+        const float v = in ? taps[idx] : 0.0f;
+        float ve = 0.0f;
+        if constexpr (FULL) ve = in ? static_cast<const float*>(job.taps_even)[idx] : 0.0f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int y = x - c;
+            if (y >= 0 && y < cstride) {
+                Tc[c * cstride + y] = v;
+                if constexpr (FULL) Te[c * cstride + y] = ve;
+            }
+        }
     }
 
     // ring of kPD chunks of 64 input columns in registers: chunk c + kPD - 1 is
@@ -164,16 +195,25 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
         for (int i = 0; i < 8; ++i) {
             const int e = t + i * kBpThreads;
             const int row = e >> 6, col = e & 63;
-            Ab[((col & 1) * kTM + row) * kAS32 + (col >> 1)] = CW ? r[i] * r[RE - 1] : r[i];
+            Ab[(col & 1) * kPar32 + row * kAS32 + (col >> 1)] = CW ? r[i] * r[RE - 1] : r[i];
         }
     };
 
-    v4f acc[2][kNB];
+    v4f acc[2][NB];
 #pragma unroll
-    for (int j = 0; j < kNB; ++j) acc[0][j] = acc[1][j] = v4f{0.f, 0.f, 0.f, 0.f};
-    const float* __restrict__ Arow = As + ((1 - sg) * kTM + wm * 16 + (l & 15)) * kAS32 + (l >> 4);
-    const float* __restrict__ ArowS = As + (sg * kTM + wm * 16 + (l & 15)) * kAS32 + (l >> 4);   // same parity
-    const int bbase = (l & 15) - (l >> 4) + sg - jlo + nh0;   // + 16 ntile - m'
+    for (int j = 0; j < NB; ++j) acc[0][j] = acc[1][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int q = l >> 4;
+    const int arow = (wm * 16 + (l & 15)) * kAS32 + 8 * q;
+    const float* __restrict__ Arow = As + (1 - sg) * kPar32 + arow;
+    const float* __restrict__ ArowS = As + sg * kPar32 + arow;   // same parity (FULL)
+    // B: x0 = jhi - (n' - m' + s) at kk = 0, n' = nh0 + 16 j + l % 16, m' = mh0 + 8 q;
+    // its residue mod 4 (the copy) is the same for every chunk and block
+    const int xl = jhi - nh0 - (l & 15) - sg + 8 * q;
+    const int cs = xl & 3;
+    const float* __restrict__ Bl = Tc + cs * cstride + (xl - cs);
+    const int xle = xl + sg;                               // even taps: y = n' - m'
+    const int cse = xle & 3;
+    const float* __restrict__ Ble = Te + cse * cstride + (xle - cse);
     const int nch = (D + 2 * kK32 - 1) / (2 * kK32);
     // every chunk load is issued unconditionally (chunks past the end read zeros),
     // so the wait before a chunk's store covers only that chunk
@@ -191,44 +231,46 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
             __syncthreads();
             if (c < nch) {
                 const int mh0 = c * kK32;
-                // every fragment of the chunk is read before the first MFMA, so the
-                // LDS latency is paid once per chunk rather than once per k-step
                 constexpr int KS = kK32 / 4;
-                float a[KS], b[KS][kNB];
+                auto fragments = [&](const float* arow_p, const float* brow_p, float (&a)[KS], float (&b)[NB][KS]) {
+                    const float4 a0 = *reinterpret_cast<const float4*>(arow_p + ab);
+                    const float4 a1 = *reinterpret_cast<const float4*>(arow_p + ab + 4);
+                    a[0] = a0.x; a[1] = a0.y; a[2] = a0.z; a[3] = a0.w;
+                    a[4] = a1.x; a[5] = a1.y; a[6] = a1.z; a[7] = a1.w;
 #pragma unroll
-                for (int k = 0; k < KS; ++k) {
-                    a[k] = Arow[ab + 4 * k];
-#pragma unroll
-                    for (int j = 0; j < kNB; ++j) b[k][j] = Bt[bbase + 16 * j - (mh0 + 4 * k)];
-                }
+                    for (int j = 0; j < NB; ++j) {
+                        const float* bp = brow_p + mh0 - 16 * j;
+                        const float4 b0 = *reinterpret_cast<const float4*>(bp);
+                        const float4 b1 = *reinterpret_cast<const float4*>(bp + 4);
+                        b[j][0] = b0.x; b[j][1] = b0.y; b[j][2] = b0.z; b[j][3] = b0.w;
+                        b[j][4] = b1.x; b[j][5] = b1.y; b[j][6] = b1.z; b[j][7] = b1.w;
+                    }
+                };
+                float a[KS], b[NB][KS];
+                fragments(Arow, Bl, a, b);
                 __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the MFMAs
                 // k-steps alternate between two accumulator sets: 2 kNB independent
                 // MFMA chains per wave
 #pragma unroll
                 for (int k = 0; k < KS; ++k)
 #pragma unroll
-                    for (int j = 0; j < kNB; ++j)
-                        acc[k & 1][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], b[k][j], acc[k & 1][j], 0, 0, 0);
+                    for (int j = 0; j < NB; ++j)
+                        acc[k & 1][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], b[j][k], acc[k & 1][j], 0, 0, 0);
                 if constexpr (FULL) {
-#pragma unroll
-                    for (int k = 0; k < KS; ++k) {
-                        a[k] = ArowS[ab + 4 * k];
-#pragma unroll
-                        for (int j = 0; j < kNB; ++j) b[k][j] = Be[bbase - sg + 16 * j - (mh0 + 4 * k)];
-                    }
+                    fragments(ArowS, Ble, a, b);
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int k = 0; k < KS; ++k)
 #pragma unroll
-                        for (int j = 0; j < kNB; ++j)
+                        for (int j = 0; j < NB; ++j)
                             acc[k & 1][j] =
-                                __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], b[k][j], acc[k & 1][j], 0, 0, 0);
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], b[j][k], acc[k & 1][j], 0, 0, 0);
                 }
             }
         }
     }
 #pragma unroll
-    for (int j = 0; j < kNB; ++j) store_block<kFP32, CW>(acc[0][j] + acc[1][j], job, m0 + wm * 16, nh0 + 16 * j, sg);
+    for (int j = 0; j < NB; ++j) store_block<kFP32, CW>(acc[0][j] + acc[1][j], job, m0 + wm * 16, nh0 + 16 * j, sg);
 }
 
 // ---------------------------------------------------------------- 16-bit operands
@@ -261,14 +303,22 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
     unsigned short* Te = Tc + 8 * cstride;                          // the same for te (FULL)
 
     __syncthreads();
-    for (int x = t; x < 8 * cstride; x += kBpThreads) {
-        const int c = x / cstride, y = x - c * cstride;
-        const int idx = -(ylo + y + c) + Dhp;             // table index of to(-(y'))
-        Tc[x] = (idx >= 0 && idx <= 2 * Dhp) ? taps[idx] : (unsigned short)0;
-        if constexpr (FULL) {
-            // te(n' - m') is read at y + s: copy c element y holds te(-(ylo + y + c))
-            const unsigned short* __restrict__ te = static_cast<const unsigned short*>(job.taps_even);
-            Te[x] = (idx >= 0 && idx <= 2 * Dhp) ? te[idx] : (unsigned short)0;
+    // copy c element y holds to(-(ylo + y + c)) (and te the same for FULL: te(n' - m')
+    // is read at y + s); one load per tap, stored into the eight copies
+#pragma unroll 2
+    for (int x = t; x < cstride + 7; x += kBpThreads) {
+        const int idx = -(ylo + x) + Dhp;                // table index of to(-(ylo + x))
+        const bool in = idx >= 0 && idx <= 2 * Dhp;
+        const unsigned short v = in ? taps[idx] : (unsigned short)0;
+        unsigned short ve = 0;
+        if constexpr (FULL) ve = in ? static_cast<const unsigned short*>(job.taps_even)[idx] : (unsigned short)0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int y = x - c;
+            if (y >= 0 && y < cstride) {
+                Tc[c * cstride + y] = v;
+                if constexpr (FULL) Te[c * cstride + y] = ve;
+            }
         }
     }
 
@@ -369,24 +419,25 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
 
 // One instantiation per (operand precision, kernel with or without even taps), so
 // the Ram-Lak path keeps its register budget.
-template <int PREC, bool FULL, bool CW = false>
+template <int PREC, bool FULL, bool CW = false, int NB = kNB>
 __device__ __forceinline__ void gemm_tile(const GemmJob& job, int mt, int nt, char* smem) {
     if constexpr (PREC == kFP32)
-        gemm_tile_f32<FULL, CW>(job, mt, nt, smem);
+        gemm_tile_f32<FULL, CW, NB>(job, mt, nt, smem);
     else
         gemm_tile_16<PREC, FULL, CW>(job, mt, nt, smem);
 }
 
 // CW: the job has column weights (job.colw); a separate instantiation keeps the
 // unweighted filter's ring and stores as they were
-template <int PREC, bool FULL, bool CW>
+// NB: 16-wide MFMA blocks per wave and parity (2: 64-bin tiles, 3: 96-bin tiles, FP32)
+template <int PREC, bool FULL, bool CW, int NB>
 __global__ __launch_bounds__(kBpThreads) void gemm_grid_kernel(GemmJob job) {
     extern __shared__ float4 smem4[];
     const int tiles_m = (job.R + kTM - 1) / kTM;
     // blockIdx.x: output tile index, row tiles fastest so neighbours share tap slices
     const int b = blockIdx.x;
     const int nt = b / tiles_m, mt = b - nt * tiles_m;
-    gemm_tile<PREC, FULL, CW>(job, mt, nt, reinterpret_cast<char*>(smem4));
+    gemm_tile<PREC, FULL, CW, NB>(job, mt, nt, reinterpret_cast<char*>(smem4));
 }
 
 template <int PREC, bool FULL>
@@ -433,24 +484,36 @@ constexpr int gemm_key(int prec, bool full) { return prec * 2 + (full ? 1 : 0); 
 
 }  // namespace
 
-int gemm_lds_bytes(int prec, int Dh) {
+int gemm_lds_bytes(int prec, int Dh, bool full, bool wide) {
+    const int tables = full ? 2 : 1;   // odd taps, and even taps for kernels that have them
     if (prec == kFP32) {
         const int mpad = (Dh + kK32 - 1) / kK32 * kK32;
-        return (2 * kABuf32 + 2 * (mpad + kHalfN)) * 4;   // panel, odd and even taps
+        // panel, four copies of each tap table
+        return (2 * kABuf32 + tables * 4 * copy_stride32(mpad, wide ? 48 : kHalfN)) * 4;
     }
     const int mpad = (Dh + kK16 - 1) / kK16 * kK16;
-    return (2 * kABuf16 + 2 * 8 * ((mpad + kHalfN + 8 + 7 + 7) & ~7)) * 2;
+    return (2 * kABuf16 + tables * 8 * ((mpad + kHalfN + 8 + 7 + 7) & ~7)) * 2;
 }
 
 hipError_t launch_gemm_grid(int prec, const GemmJob& job, hipStream_t stream) {
     const int tiles_m = (job.R + kTM - 1) / kTM;
     const unsigned grid = (unsigned)(tiles_m * job.tiles_n);
-    const size_t lds = (size_t)gemm_lds_bytes(prec, job.Dh);
+    const bool wide = job.wide != 0;
+    if (wide && (prec != kFP32 || job.tiles_n != (job.D + 95) / 96)) return hipErrorInvalidValue;
+    const size_t lds = (size_t)gemm_lds_bytes(prec, job.Dh, job.full != 0, wide);
+    const dim3 g(grid), b(kBpThreads);
+    if (wide) {
+        if (job.full)
+            return job.colw ? launch_kernel(gemm_grid_kernel<kFP32, true, true, 3>, g, b, lds, stream, job)
+                            : launch_kernel(gemm_grid_kernel<kFP32, true, false, 3>, g, b, lds, stream, job);
+        return job.colw ? launch_kernel(gemm_grid_kernel<kFP32, false, true, 3>, g, b, lds, stream, job)
+                        : launch_kernel(gemm_grid_kernel<kFP32, false, false, 3>, g, b, lds, stream, job);
+    }
     switch (gemm_key(prec, job.full != 0)) {
 #define X(p, f)                                                                                             \
         case gemm_key(p, f):                                                                                    \
-            return job.colw ? launch_kernel(gemm_grid_kernel<p, f, true>, dim3(grid), dim3(kBpThreads), lds, stream, job) \
-                            : launch_kernel(gemm_grid_kernel<p, f, false>, dim3(grid), dim3(kBpThreads), lds, stream, job);
+            return job.colw ? launch_kernel(gemm_grid_kernel<p, f, true, kNB>, g, b, lds, stream, job) \
+                            : launch_kernel(gemm_grid_kernel<p, f, false, kNB>, g, b, lds, stream, job);
         FBP_FOR_EACH_GEMM(X)
 #undef X
         default: return hipErrorInvalidValue;

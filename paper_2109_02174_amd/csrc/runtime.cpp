@@ -891,6 +891,16 @@ hipError_t launch_filter_rows(const Plan& p, int prec, const float* in, float* o
     }
     GemmJob j = gemm_job(p, prec, in, out, rows);
     j.colw = colw;
+    if (prec == kFP32) {
+        // 96-bin tiles where they leave fewer tiles on the most loaded CU (in units of
+        // a 32-bin half tile); same arithmetic per output bin, so the same bits
+        const int64_t tm = (rows + kGemmBM - 1) / kGemmBM, cus = cu_count(p.device);
+        const int64_t t64 = tm * ((p.D + 63) / 64), t96 = tm * ((p.D + 95) / 96);
+        if ((t96 + cus - 1) / cus * 3 < (t64 + cus - 1) / cus * 2) {
+            j.wide = 1;
+            j.tiles_n = (p.D + 95) / 96;
+        }
+    }
     return launch_gemm_grid(prec, j, s);
 }
 
@@ -1387,7 +1397,7 @@ int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes,
     key.cfg_mask = mask;
     key.multi_mask = mmask;
     key.gemm_kinds = gemm_kinds;
-    key.gemm_lds = (int)round_up((size_t)gemm_lds_bytes(prec, max_dh), 8192);
+    key.gemm_lds = (int)round_up((size_t)gemm_lds_bytes(prec, max_dh, (gemm_kinds & 2) != 0), 8192);
     key.bp_lds = (int)round_up((size_t)max_bp_lds, 4096);
     key.bpm_lds = (int)round_up((size_t)max_bpm_lds, 4096);
     return launch_batch(key, cu_count(device), s);
