@@ -47,16 +47,6 @@ __device__ __forceinline__ float ld_zero(const float* __restrict__ row, int g, i
     return (g >= 0 && g < D) ? row[g] : 0.0f;
 }
 
-// XCD-aware remap: hardware places block b on XCD b % 8; give each XCD a contiguous
-// range of logical tiles so the tiles sharing filtered rows share an L2.
-__device__ __forceinline__ int xcd_logical(int b, int G) {
-    const int x = b & 7;
-    const int slot = b >> 3;
-    const int per = G >> 3;
-    const int extra = G & 7;
-    return x * per + min(x, extra) + slot;
-}
-
 // Word 3 of a raw (stride 0) buffer resource: 32-bit data format, no swizzle; reads
 // at byte offsets >= num_records return 0.
 constexpr int kBufferWord3 = 0x00020000;

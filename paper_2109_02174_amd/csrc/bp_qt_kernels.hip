@@ -58,16 +58,6 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// XCD-aware remap: hardware places block b on XCD b % 8; give each XCD a contiguous
-// range of logical tiles so the tiles sharing filtered rows share an L2.
-__device__ __forceinline__ int xcd_remap(int b, int G) {
-    const int x = b & 7;
-    const int slot = b >> 3;
-    const int per = G >> 3;
-    const int extra = G & 7;
-    return x * per + min(x, extra) + slot;
-}
-
 // Angle pairs whose window origins a wave makes at once (one per lane).
 constexpr int kRound = 64;
 
@@ -335,7 +325,7 @@ template <int WP, int B, bool WS>
 __global__ __launch_bounds__(kThreads, kWavesPerSimd) void bp_qt_grid_kernel(BpJob job, size_t q_stride, size_t img_stride,
                                                               int tiles_per_slice) {
     __shared__ __attribute__((aligned(16))) char smem[QtLds<WP, B>::BYTES];
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int s = lb / tiles_per_slice;
     const int tt = lb - s * tiles_per_slice;
     const int ty = tt / job.tiles_x;
@@ -355,7 +345,7 @@ __global__ __launch_bounds__(kThreads, kWavesPerSimd) void bp_qt_list_kernel(con
     if (n_sel <= 0) return;
     const int total = prefix[n_sel];
     const int G = gridDim.x;
-    for (int it = xcd_remap(blockIdx.x, G); it < total; it += G) {
+    for (int it = xcd_logical(blockIdx.x, G); it < total; it += G) {
         int lo = 0, hi = n_sel - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;

@@ -27,6 +27,17 @@ __device__ __forceinline__ T load_const(const T* p) {
     return v;
 }
 
+// XCD-aware block order: the hardware places block b on XCD b % 8, and each XCD has
+// its own L2.  xcd_logical gives each XCD a contiguous range of logical work items
+// (a bijection of [0, G)), so items that read the same rows share an L2.
+__device__ __forceinline__ int xcd_logical(int b, int G) {
+    const int x = b & 7;
+    const int slot = b >> 3;
+    const int per = G >> 3;
+    const int extra = G & 7;
+    return x * per + min(x, extra) + slot;
+}
+
 // Launch with the error returned by the launch itself (not a thread's sticky
 // last-error state, which an unrelated earlier call may have set).
 template <typename T>

@@ -433,10 +433,10 @@ __device__ __forceinline__ void gemm_tile(const GemmJob& job, int mt, int nt, ch
 template <int PREC, bool FULL, bool CW, int NB>
 __global__ __launch_bounds__(kBpThreads) void gemm_grid_kernel(GemmJob job) {
     extern __shared__ float4 smem4[];
-    const int tiles_m = (job.R + kTM - 1) / kTM;
-    // blockIdx.x: output tile index, row tiles fastest so neighbours share tap slices
-    const int b = blockIdx.x;
-    const int nt = b / tiles_m, mt = b - nt * tiles_m;
+    // logical tile: column tiles fastest, so the tiles of one row block (which all read
+    // that block's rows) run on one XCD and share its L2
+    const int b = xcd_logical(blockIdx.x, gridDim.x);
+    const int mt = b / job.tiles_n, nt = b - mt * job.tiles_n;
     gemm_tile<PREC, FULL, CW, NB>(job, mt, nt, reinterpret_cast<char*>(smem4));
 }
 
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(kBpThreads) void gemm_list_kernel(const GemmListArg
     const int n_jobs = *as_const(a.counts);
     if (n_jobs <= 0) return;
     const int total = prefix[n_jobs];
-    for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    for (int it = xcd_logical(blockIdx.x, gridDim.x); it < total; it += gridDim.x) {
         int lo = 0, hi = n_jobs - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -456,8 +456,7 @@ __global__ __launch_bounds__(kBpThreads) void gemm_list_kernel(const GemmListArg
         }
         const GemmJob job = load_const(a.jobs + lo);
         const int tt = it - prefix[lo];
-        const int tiles_m = (job.R + kTM - 1) / kTM;
-        const int nt = tt / tiles_m, mt = tt - nt * tiles_m;
+        const int mt = tt / job.tiles_n, nt = tt - mt * job.tiles_n;
         gemm_tile<PREC, FULL>(job, mt, nt, reinterpret_cast<char*>(smem4));
     }
 }
