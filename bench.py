@@ -7,7 +7,10 @@ against the FP64 oracle, a roofline entry for the dominant kernel
 (backprojection) and the oracle's own throughput on the host cores.
 
 python bench.py [--gpus 1] [--steps 200] [--warmup 20] [--precision fp32] [--no-cpu-baseline]
-               [--no-autotune] [--copy-mb MiB] [--latency-samples 1000]
+               [--no-autotune] [--copy-mb MiB] [--latency-samples 1000] [--workload c2|c1]
+
+--workload c1 runs the same measurement on the small 128^2 / 180-angle / 183-bin
+slice (a reported side result; the default and the headline line is c2).
 """
 from __future__ import annotations
 
@@ -29,7 +32,8 @@ FP32_MATRIX_PEAK_TFLOPS = 157.3      # MI355X published FP32 matrix peak
 HBM_PEAK_GBS = 8000.0
 BP_FLOPS_PER_UPDATE = 7              # coordinate FMA (2) + fraction (1) + lerp (3) + accumulate (1)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bp_c2_hbm_traffic.txt")
-BP_SOURCE = os.path.join(ROOT, "paper_2109_02174_amd", "csrc", "bp_kernels.hip")
+BP_SOURCES = {"bp_qt_grid_kernel": os.path.join(ROOT, "paper_2109_02174_amd", "csrc", "bp_qt_kernels.hip"),
+              "bp_grid_kernel": os.path.join(ROOT, "paper_2109_02174_amd", "csrc", "bp_kernels.hip")}
 
 
 def parse():
@@ -44,6 +48,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--latency-samples", type=int, default=1000,
                     help="requests timed one at a time after the timed region (p50/p99)")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1"],
+                    help="c2: 512^2 / 720 angles / 725 bins (default); c1: 128^2 / 180 / 183")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed region, one device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -53,9 +59,10 @@ def source_hash(path: str) -> str:
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
-def recorded_traffic(updates_per_launch: int):
+def recorded_traffic(kernel: str):
     """HBM bytes per backprojection launch from the committed rocprofv3 counter summary,
-    or None when the summary is absent or was taken on a different kernel source."""
+    or None when the summary is absent, covers another kernel, or was taken on a
+    different source of that kernel."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     fields = {}
@@ -63,7 +70,9 @@ def recorded_traffic(updates_per_launch: int):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             fields[k.strip()] = v.strip()
-    if fields.get("bp_kernels_sha256_16") != source_hash(BP_SOURCE):
+    if fields.get("kernel") != kernel or kernel not in BP_SOURCES:
+        return None
+    if fields.get("bp_source_sha256_16") != source_hash(BP_SOURCES[kernel]):
         return None
     try:
         return int(float(fields["hbm_bytes_per_launch"]))
@@ -128,7 +137,7 @@ def cpu_baseline(sl, seconds: float):
     return {
         "value": upd / med, "unit": UNIT, "cores": threads, "kind": "oracle",
         "sample": (f"{len(times)} whole FP64 reconstructions (filter + backprojection) of the "
-                   f"512x512/720-angle/725-bin slice, median {med * 1e3:.1f} ms each, "
+                   f"{sl.N}x{sl.N}/{sl.K}-angle/{sl.D}-bin slice, median {med * 1e3:.1f} ms each, "
                    f"{threads} OpenMP threads"),
         "slices_per_s": 1.0 / med,
         "value_1_thread": sl.N * sl.N * sl.K / sorted(one)[1],
@@ -151,7 +160,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    sl = configs.c2_slice()
+    sl = configs.c2_slice() if args.workload == "c2" else configs.c1_slice()
     geom = fbp.Geometry(sl.K, sl.D, sl.N, sl.dt, sl.angles)
     stream = torch.cuda.current_stream()
     tuned = None if args.no_autotune else fbp.fbp_autotune(geom)
@@ -199,7 +208,8 @@ def main():
     flt_ms = time_launches(lambda: fbp.fbp_filter(geom, sino, out=filt, precision=args.precision),
                            stream, n_k)
     bp_tflops = BP_FLOPS_PER_UPDATE * updates / (bp_ms * 1e-3) / 1e12
-    traffic = recorded_traffic(updates)
+    bp_kernel = bp_kernel_name(fbp.fbp_tile_config_name(cfg))
+    traffic = recorded_traffic(bp_kernel) if args.workload == "c2" else None   # summary is for c2
     gemm_flops = 2.0 * sl.K * sl.D * sl.D
 
     if args.copy_mb > 0:
@@ -217,7 +227,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else f"{args.precision} filter operands, f32",
         "data": "synthetic (seeded 20-ellipse phantom, analytic sinogram, Poisson I0=1e5)",
-        "config": {"workload": "single slice 512x512, 720 angles in [0,pi), 725 bins",
+        "config": {"workload": f"single slice {sl.N}x{sl.N}, {sl.K} angles in [0,pi), {sl.D} bins",
                    "image": sl.N, "angles": sl.K, "detectors": sl.D, "det_spacing": sl.dt,
                    "filter_precision": args.precision, "tile_config": cfg,
                    "tile_config_name": fbp.fbp_tile_config_name(cfg), "autotuned": tuned},
@@ -227,7 +237,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": bp_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": bp_tflops / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": traffic,
-                     "kernel": bp_kernel_name(fbp.fbp_tile_config_name(cfg)),
+                     "kernel": bp_kernel,
                      "kernel_ms": bp_ms, "flops_per_update": BP_FLOPS_PER_UPDATE,
                      "updates_per_launch": updates},
         "filter_gemm": {"kernel_ms": flt_ms, "dense_tflops": gemm_flops / (flt_ms * 1e-3) / 1e12,

@@ -305,7 +305,7 @@ struct GemmJob {
     const float* colw;    // [D] factor per input column applied to P before the product
                           // (fan-beam pre-weights), or null
     int32_t wide;         // FP32 only: 1 = tiles of 96 output bins (tiles_n = ceil(D / 96)), 0 = 64
-    int32_t pad_;
+    int32_t groups;       // FP32 grid launches: 1 or 2 groups of four waves per tile (same bits)
 };
 static_assert(sizeof(GemmJob) % 8 == 0, "GemmJob layout");
 

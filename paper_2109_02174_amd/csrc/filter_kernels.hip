@@ -88,9 +88,28 @@ __device__ __forceinline__ float load_weight(__amdgpu_buffer_rsrc_t wcol, int co
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(wcol, col * 4, 0, 0));
 }
 
-// Epilogue: lane l of a 16x16 block holds rows 4 (l/16) + i, column l % 16.
-template <int PREC, bool CW>
-__device__ __forceinline__ void store_block(const v4f& acc, const GemmJob& job, int row0, int nh0, int sg) {
+// Centre-tap inputs of a 16x16 output block, loaded at the start of the tile so
+// their latency hides behind the product: lane l gets P[row0 + 4 (l/16) + i][n]
+// (times the column weight with CW), n = 2 (nh0 + l % 16) + sg; prow covers rows
+// m0 .. (out-of-range rows and columns read 0).
+template <bool CW>
+__device__ __forceinline__ void load_centre(float (&pre)[4], __amdgpu_buffer_rsrc_t prow,
+                                            __amdgpu_buffer_rsrc_t wcol, int D, int row0m, int nh0, int sg) {
+    const int l = threadIdx.x & 63;
+    const int n = 2 * (nh0 + (l & 15)) + sg;
+    const float w = CW ? load_weight(wcol, n) : 1.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        pre[i] = load_elem(prow, row0m + 4 * (l >> 4) + i, n, D);
+        if constexpr (CW) pre[i] *= w;
+    }
+}
+
+// Epilogue: lane l of a 16x16 block holds rows 4 (l/16) + i, column l % 16; pre:
+// its centre-tap inputs (load_centre), used by kernels without even taps.
+template <int PREC>
+__device__ __forceinline__ void store_block(const v4f& acc, const float (&pre)[4], const GemmJob& job, int row0,
+                                            int nh0, int sg) {
     const int l = threadIdx.x & 63;
     const int n = 2 * (nh0 + (l & 15)) + sg;
     if (n >= job.D) return;
@@ -99,11 +118,7 @@ __device__ __forceinline__ void store_block(const v4f& acc, const GemmJob& job, 
         const int m = row0 + 4 * (l >> 4) + i;
         if (m < job.R) {
             float v = acc[i];
-            if (!job.full) {
-                float pv = job.p[(size_t)m * job.D + n];
-                if constexpr (CW) pv *= job.colw[n];
-                v = fmaf(job.diag, round_operand<PREC>(pv), v);
-            }
+            if (!job.full) v = fmaf(job.diag, round_operand<PREC>(pre[i]), v);
             job.q[(size_t)m * job.D + n] = v * job.out_scale;
         }
     }
@@ -136,14 +151,28 @@ __host__ __device__ constexpr int copy_stride32(int mpad, int hn) {
 //
 // The inputs of a chunk are assigned to the MFMA k-steps as m' = mh0 + 8 q + kk
 // (q = lane / 16, kk = k-step 0..7), so a lane's A values and B values over the
-// chunk's eight k-steps are eight consecutive floats in LDS: two 16-byte reads for A
-// and two per 16-wide block for B, instead of one 4-byte read per k-step.
-template <bool FULL, bool CW, int NB>
+// chunk's eight k-steps are eight consecutive floats in LDS (16-byte reads instead
+// of one 4-byte read per k-step).  k-steps 0..3 of every chunk go into accumulator
+// set 0 and k-steps 4..7 into set 1; the output is set 0 + set 1.
+//
+// G: groups of four waves.  G = 1: one group does both sets.  G = 2 (small grids,
+// where one group per CU leaves one wave per SIMD): group g does set g of every
+// chunk on the shared panel, and group 1 hands its sums to group 0 through LDS.
+// Every accumulator sees the same MFMAs in the same order either way, so the two
+// forms give the same bits and the host may pick either per launch.
+template <bool FULL, bool CW, int NB, int G>
 __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt, char* smem) {
+    static_assert(G == 1 || G == 2, "groups");
     constexpr int HN = 16 * NB;                          // output bins per parity of the tile
+    constexpr int NT = 256 * G;                          // threads
+    constexpr int KS = kK32 / 4;                         // k-steps per chunk
+    constexpr int NS = 2 / G;                            // accumulator sets per group
+    constexpr int KG = KS / 2;                           // k-steps per set
     float* As = reinterpret_cast<float*>(smem);          // [2 buffers][2 parity planes][32 rows][kAS32]
     float* Tc = As + 2 * kABuf32;                        // 4 copies of the odd taps, then of the even taps
-    const int t = threadIdx.x;
+    const int tid = threadIdx.x;
+    const int grp = G == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 8);
+    const int t = tid & 255;                             // thread within its group
     const int w = t >> 6, l = t & 63;
     const int wm = w >> 1, sg = w & 1;                   // row half, output parity
     const int m0 = mt * kTM, nh0 = nt * HN;
@@ -155,10 +184,47 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
     const int cstride = copy_stride32(mpad, HN);
     float* Te = Tc + 4 * cstride;                        // even-tap copies (FULL)
 
+    // ring of kPD chunks of 64 input columns in registers: chunk c + kPD - 1 is
+    // loaded while chunk c is multiplied, hiding several chunks of load latency
+    // ring entry: a thread's EL elements of a chunk (all in column c0 + tid % 64) and,
+    // with column weights (CW), that column's weight
+    constexpr int EL = 2048 / NT;
+    constexpr int RE = CW ? EL + 1 : EL;
+    float pf[kPD][RE];
+    const __amdgpu_buffer_rsrc_t prow = tile_rows(P, m0, min(kTM, R - m0), D);
+    const __amdgpu_buffer_rsrc_t wcol = col_weights(job);
+    auto load = [&](float (&r)[RE], int c0) {   // columns c0 .. c0+63 of rows m0 .. m0+31
+#pragma unroll
+        for (int i = 0; i < EL; ++i) {
+            const int e = tid + i * NT;
+            r[i] = load_elem(prow, e >> 6, c0 + (e & 63), D);
+        }
+        if constexpr (CW) r[RE - 1] = load_weight(wcol, c0 + (tid & 63));
+    };
+    auto store = [&](const float (&r)[RE], float* Ab) {
+#pragma unroll
+        for (int i = 0; i < EL; ++i) {
+            const int e = tid + i * NT;
+            const int row = e >> 6, col = e & 63;
+            Ab[(col & 1) * kPar32 + row * kAS32 + (col >> 1)] = CW ? r[i] * r[RE - 1] : r[i];
+        }
+    };
+
+    // the first chunks, the centre-tap inputs and the taps are all requested before
+    // the first wait, so their memory latencies overlap
+#pragma unroll
+    for (int c = 0; c < kPD - 1; ++c) load(pf[c], c * 2 * kK32);
+    float pre[NB][4];
+    if constexpr (!FULL) {
+        if (grp == 0) {
+#pragma unroll
+            for (int j = 0; j < NB; ++j) load_centre<CW>(pre[j], prow, wcol, D, wm * 16, nh0 + 16 * j, sg);
+        }
+    }
     __syncthreads();   // LDS reuse across tiles of a persistent workgroup
     // one load per tap, stored into the four copies (element x - c of copy c)
 #pragma unroll 2
-    for (int x = t; x < cstride + 3; x += kBpThreads) {
+    for (int x = tid; x < cstride + 3; x += NT) {
         const int idx = jhi - x + Dhp;                   // table index of to(jhi - x)
         const bool in = idx >= 0 && idx <= 2 * Dhp;
         const float v = in ? taps[idx] : 0.0f;
@@ -174,51 +240,27 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
         }
     }
 
-    // ring of kPD chunks of 64 input columns in registers: chunk c + kPD - 1 is
-    // loaded while chunk c is multiplied, hiding several chunks of load latency
-    // ring entry: a thread's 8 elements of a chunk (all in column c0 + t % 64) and,
-    // with column weights (CW), that column's weight
-    constexpr int RE = CW ? 9 : 8;
-    float pf[kPD][RE];
-    const __amdgpu_buffer_rsrc_t prow = tile_rows(P, m0, min(kTM, R - m0), D);
-    const __amdgpu_buffer_rsrc_t wcol = col_weights(job);
-    auto load = [&](float (&r)[RE], int c0) {   // columns c0 .. c0+63 of rows m0 .. m0+31
+    v4f acc[NS][NB];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int e = t + i * kBpThreads;
-            r[i] = load_elem(prow, e >> 6, c0 + (e & 63), D);
-        }
-        if constexpr (CW) r[RE - 1] = load_weight(wcol, c0 + (t & 63));
-    };
-    auto store = [&](const float (&r)[RE], float* Ab) {
+    for (int h = 0; h < NS; ++h)
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int e = t + i * kBpThreads;
-            const int row = e >> 6, col = e & 63;
-            Ab[(col & 1) * kPar32 + row * kAS32 + (col >> 1)] = CW ? r[i] * r[RE - 1] : r[i];
-        }
-    };
-
-    v4f acc[2][NB];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) acc[0][j] = acc[1][j] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < NB; ++j) acc[h][j] = v4f{0.f, 0.f, 0.f, 0.f};
     const int q = l >> 4;
-    const int arow = (wm * 16 + (l & 15)) * kAS32 + 8 * q;
+    const int k0 = G == 1 ? 0 : KG * grp;                // first k-step of this group
+    const int arow = (wm * 16 + (l & 15)) * kAS32 + 8 * q + k0;
     const float* __restrict__ Arow = As + (1 - sg) * kPar32 + arow;
     const float* __restrict__ ArowS = As + sg * kPar32 + arow;   // same parity (FULL)
     // B: x0 = jhi - (n' - m' + s) at kk = 0, n' = nh0 + 16 j + l % 16, m' = mh0 + 8 q;
     // its residue mod 4 (the copy) is the same for every chunk and block
     const int xl = jhi - nh0 - (l & 15) - sg + 8 * q;
     const int cs = xl & 3;
-    const float* __restrict__ Bl = Tc + cs * cstride + (xl - cs);
+    const float* __restrict__ Bl = Tc + cs * cstride + (xl - cs) + k0;
     const int xle = xl + sg;                               // even taps: y = n' - m'
     const int cse = xle & 3;
-    const float* __restrict__ Ble = Te + cse * cstride + (xle - cse);
+    const float* __restrict__ Ble = Te + cse * cstride + (xle - cse) + k0;
     const int nch = (D + 2 * kK32 - 1) / (2 * kK32);
     // every chunk load is issued unconditionally (chunks past the end read zeros),
     // so the wait before a chunk's store covers only that chunk
-#pragma unroll
-    for (int c = 0; c < kPD - 1; ++c) load(pf[c], c * 2 * kK32);
     for (int cb = 0; cb < nch; cb += kPD) {
 #pragma unroll
         for (int u = 0; u < kPD; ++u) {
@@ -231,46 +273,54 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
             __syncthreads();
             if (c < nch) {
                 const int mh0 = c * kK32;
-                constexpr int KS = kK32 / 4;
-                auto fragments = [&](const float* arow_p, const float* brow_p, float (&a)[KS], float (&b)[NB][KS]) {
-                    const float4 a0 = *reinterpret_cast<const float4*>(arow_p + ab);
-                    const float4 a1 = *reinterpret_cast<const float4*>(arow_p + ab + 4);
-                    a[0] = a0.x; a[1] = a0.y; a[2] = a0.z; a[3] = a0.w;
-                    a[4] = a1.x; a[5] = a1.y; a[6] = a1.z; a[7] = a1.w;
+                // this group's k-steps of the chunk: A and B fragments (four floats each
+                // per set), then the MFMAs, the sets interleaved
+                auto product = [&](const float* arow_p, const float* brow_p) {
+                    float a[NS][KG], b[NS][NB][KG];
 #pragma unroll
-                    for (int j = 0; j < NB; ++j) {
-                        const float* bp = brow_p + mh0 - 16 * j;
-                        const float4 b0 = *reinterpret_cast<const float4*>(bp);
-                        const float4 b1 = *reinterpret_cast<const float4*>(bp + 4);
-                        b[j][0] = b0.x; b[j][1] = b0.y; b[j][2] = b0.z; b[j][3] = b0.w;
-                        b[j][4] = b1.x; b[j][5] = b1.y; b[j][6] = b1.z; b[j][7] = b1.w;
+                    for (int h = 0; h < NS; ++h) {
+                        const float4 av = *reinterpret_cast<const float4*>(arow_p + ab + KG * h);
+                        a[h][0] = av.x; a[h][1] = av.y; a[h][2] = av.z; a[h][3] = av.w;
+#pragma unroll
+                        for (int j = 0; j < NB; ++j) {
+                            const float4 bv = *reinterpret_cast<const float4*>(brow_p + mh0 - 16 * j + KG * h);
+                            b[h][j][0] = bv.x; b[h][j][1] = bv.y; b[h][j][2] = bv.z; b[h][j][3] = bv.w;
+                        }
                     }
+                    __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the MFMAs
+#pragma unroll
+                    for (int k = 0; k < KG; ++k)
+#pragma unroll
+                        for (int h = 0; h < NS; ++h)
+#pragma unroll
+                            for (int j = 0; j < NB; ++j)
+                                acc[h][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[h][k], b[h][j][k], acc[h][j], 0, 0, 0);
                 };
-                float a[KS], b[NB][KS];
-                fragments(Arow, Bl, a, b);
-                __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the MFMAs
-                // k-steps alternate between two accumulator sets: 2 kNB independent
-                // MFMA chains per wave
-#pragma unroll
-                for (int k = 0; k < KS; ++k)
-#pragma unroll
-                    for (int j = 0; j < NB; ++j)
-                        acc[k & 1][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], b[j][k], acc[k & 1][j], 0, 0, 0);
-                if constexpr (FULL) {
-                    fragments(ArowS, Ble, a, b);
-                    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                    for (int k = 0; k < KS; ++k)
-#pragma unroll
-                        for (int j = 0; j < NB; ++j)
-                            acc[k & 1][j] =
-                                __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], b[j][k], acc[k & 1][j], 0, 0, 0);
-                }
+                static_assert(KG == 4, "four k-steps per set");
+                product(Arow, Bl);
+                if constexpr (FULL) product(ArowS, Ble);
             }
         }
     }
+    if constexpr (G == 1) {
 #pragma unroll
-    for (int j = 0; j < NB; ++j) store_block<kFP32, CW>(acc[0][j] + acc[1][j], job, m0 + wm * 16, nh0 + 16 * j, sg);
+        for (int j = 0; j < NB; ++j)
+            store_block<kFP32>(acc[0][j] + acc[1][j], pre[j], job, m0 + wm * 16, nh0 + 16 * j, sg);
+    } else {
+        // set 1 (group 1) through LDS to group 0, which adds set 0 + set 1
+        __syncthreads();   // every panel read
+        v4f* xch = reinterpret_cast<v4f*>(smem);   // [NB][256]
+        if (grp == 1) {
+#pragma unroll
+            for (int j = 0; j < NB; ++j) xch[j * 256 + t] = acc[0][j];
+        }
+        __syncthreads();
+        if (grp == 0) {
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                store_block<kFP32>(acc[0][j] + xch[j * 256 + t], pre[j], job, m0 + wm * 16, nh0 + 16 * j, sg);
+        }
+    }
 }
 
 // ---------------------------------------------------------------- 16-bit operands
@@ -302,26 +352,6 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
 
     unsigned short* Te = Tc + 8 * cstride;                          // the same for te (FULL)
 
-    __syncthreads();
-    // copy c element y holds to(-(ylo + y + c)) (and te the same for FULL: te(n' - m')
-    // is read at y + s); one load per tap, stored into the eight copies
-#pragma unroll 2
-    for (int x = t; x < cstride + 7; x += kBpThreads) {
-        const int idx = -(ylo + x) + Dhp;                // table index of to(-(ylo + x))
-        const bool in = idx >= 0 && idx <= 2 * Dhp;
-        const unsigned short v = in ? taps[idx] : (unsigned short)0;
-        unsigned short ve = 0;
-        if constexpr (FULL) ve = in ? static_cast<const unsigned short*>(job.taps_even)[idx] : (unsigned short)0;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int y = x - c;
-            if (y >= 0 && y < cstride) {
-                Tc[c * cstride + y] = v;
-                if constexpr (FULL) Te[c * cstride + y] = ve;
-            }
-        }
-    }
-
     // ring entry: a thread's 16 elements of a chunk (all in column c0 + t % 128) and,
     // with column weights (CW), that column's weight
     constexpr int RE = CW ? 17 : 16;
@@ -346,6 +376,35 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
         }
     };
 
+    // the first chunks, the centre-tap inputs and the taps are all requested before
+    // the first wait, so their memory latencies overlap
+#pragma unroll
+    for (int c = 0; c < kPD16 - 1; ++c) load(pf[c], c * 2 * kK16);
+    float pre[kNB][4];
+    if constexpr (!FULL) {
+#pragma unroll
+        for (int j = 0; j < kNB; ++j) load_centre<CW>(pre[j], prow, wcol, D, wm * 16, nh0 + 16 * j, sg);
+    }
+    __syncthreads();
+    // copy c element y holds to(-(ylo + y + c)) (and te the same for FULL: te(n' - m')
+    // is read at y + s); one load per tap, stored into the eight copies
+#pragma unroll 2
+    for (int x = t; x < cstride + 7; x += kBpThreads) {
+        const int idx = -(ylo + x) + Dhp;                // table index of to(-(ylo + x))
+        const bool in = idx >= 0 && idx <= 2 * Dhp;
+        const unsigned short v = in ? taps[idx] : (unsigned short)0;
+        unsigned short ve = 0;
+        if constexpr (FULL) ve = in ? static_cast<const unsigned short*>(job.taps_even)[idx] : (unsigned short)0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int y = x - c;
+            if (y >= 0 && y < cstride) {
+                Tc[c * cstride + y] = v;
+                if constexpr (FULL) Te[c * cstride + y] = ve;
+            }
+        }
+    }
+
     v4f acc[2][kNB];
 #pragma unroll
     for (int j = 0; j < kNB; ++j) acc[0][j] = acc[1][j] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -353,8 +412,6 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
     const unsigned short* ArowS = As + (sg * kTM + wm * 16 + (l & 15)) * kAS16 + 8 * (l >> 4);   // same parity
     const int kq = 8 * (l >> 4);
     const int nch = (D + 2 * kK16 - 1) / (2 * kK16);
-#pragma unroll
-    for (int c = 0; c < kPD16 - 1; ++c) load(pf[c], c * 2 * kK16);
     for (int cb = 0; cb < nch; cb += kPD16) {
 #pragma unroll
         for (int u = 0; u < kPD16; ++u) {
@@ -414,15 +471,15 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
         }
     }
 #pragma unroll
-    for (int j = 0; j < kNB; ++j) store_block<PREC, CW>(acc[0][j] + acc[1][j], job, m0 + wm * 16, nh0 + 16 * j, sg);
+    for (int j = 0; j < kNB; ++j) store_block<PREC>(acc[0][j] + acc[1][j], pre[j], job, m0 + wm * 16, nh0 + 16 * j, sg);
 }
 
 // One instantiation per (operand precision, kernel with or without even taps), so
 // the Ram-Lak path keeps its register budget.
-template <int PREC, bool FULL, bool CW = false, int NB = kNB>
+template <int PREC, bool FULL, bool CW = false, int NB = kNB, int G = 1>
 __device__ __forceinline__ void gemm_tile(const GemmJob& job, int mt, int nt, char* smem) {
     if constexpr (PREC == kFP32)
-        gemm_tile_f32<FULL, CW, NB>(job, mt, nt, smem);
+        gemm_tile_f32<FULL, CW, NB, G>(job, mt, nt, smem);
     else
         gemm_tile_16<PREC, FULL, CW>(job, mt, nt, smem);
 }
@@ -430,14 +487,15 @@ __device__ __forceinline__ void gemm_tile(const GemmJob& job, int mt, int nt, ch
 // CW: the job has column weights (job.colw); a separate instantiation keeps the
 // unweighted filter's ring and stores as they were
 // NB: 16-wide MFMA blocks per wave and parity (2: 64-bin tiles, 3: 96-bin tiles, FP32)
-template <int PREC, bool FULL, bool CW, int NB>
-__global__ __launch_bounds__(kBpThreads) void gemm_grid_kernel(GemmJob job) {
+// G: groups of four waves (FP32: 1 or 2)
+template <int PREC, bool FULL, bool CW, int NB, int G>
+__global__ __launch_bounds__(kBpThreads * G) void gemm_grid_kernel(GemmJob job) {
     extern __shared__ float4 smem4[];
     // logical tile: column tiles fastest, so the tiles of one row block (which all read
     // that block's rows) run on one XCD and share its L2
     const int b = xcd_logical(blockIdx.x, gridDim.x);
     const int mt = b / job.tiles_n, nt = b - mt * job.tiles_n;
-    gemm_tile<PREC, FULL, CW, NB>(job, mt, nt, reinterpret_cast<char*>(smem4));
+    gemm_tile<PREC, FULL, CW, NB, G>(job, mt, nt, reinterpret_cast<char*>(smem4));
 }
 
 template <int PREC, bool FULL>
@@ -471,13 +529,15 @@ int occ(int lds) {
 }
 
 // Every compiled filter kernel: (precision, kernel with even taps).
+#define FBP_FOR_EACH_GEMM16(X) \
+    X(kBF16, false)            \
+    X(kBF16, true)             \
+    X(kFP16, false)            \
+    X(kFP16, true)
 #define FBP_FOR_EACH_GEMM(X) \
     X(kFP32, false)          \
     X(kFP32, true)           \
-    X(kBF16, false)          \
-    X(kBF16, true)           \
-    X(kFP16, false)          \
-    X(kFP16, true)
+    FBP_FOR_EACH_GEMM16(X)
 
 constexpr int gemm_key(int prec, bool full) { return prec * 2 + (full ? 1 : 0); }
 
@@ -494,26 +554,36 @@ int gemm_lds_bytes(int prec, int Dh, bool full, bool wide) {
     return (2 * kABuf16 + tables * 8 * ((mpad + kHalfN + 8 + 7 + 7) & ~7)) * 2;
 }
 
+// FP32 grid launch with the tile width (NB) and group count (G) as template arguments.
+template <int NB, int G>
+hipError_t launch_f32(const GemmJob& job, dim3 g, size_t lds, hipStream_t stream) {
+    const dim3 b(kBpThreads * G);
+    if (job.full)
+        return job.colw ? launch_kernel(gemm_grid_kernel<kFP32, true, true, NB, G>, g, b, lds, stream, job)
+                        : launch_kernel(gemm_grid_kernel<kFP32, true, false, NB, G>, g, b, lds, stream, job);
+    return job.colw ? launch_kernel(gemm_grid_kernel<kFP32, false, true, NB, G>, g, b, lds, stream, job)
+                    : launch_kernel(gemm_grid_kernel<kFP32, false, false, NB, G>, g, b, lds, stream, job);
+}
+
 hipError_t launch_gemm_grid(int prec, const GemmJob& job, hipStream_t stream) {
     const int tiles_m = (job.R + kTM - 1) / kTM;
     const unsigned grid = (unsigned)(tiles_m * job.tiles_n);
     const bool wide = job.wide != 0;
     if (wide && (prec != kFP32 || job.tiles_n != (job.D + 95) / 96)) return hipErrorInvalidValue;
+    if (job.groups != 1 && (prec != kFP32 || job.groups != 2)) return hipErrorInvalidValue;
     const size_t lds = (size_t)gemm_lds_bytes(prec, job.Dh, job.full != 0, wide);
-    const dim3 g(grid), b(kBpThreads);
-    if (wide) {
-        if (job.full)
-            return job.colw ? launch_kernel(gemm_grid_kernel<kFP32, true, true, 3>, g, b, lds, stream, job)
-                            : launch_kernel(gemm_grid_kernel<kFP32, true, false, 3>, g, b, lds, stream, job);
-        return job.colw ? launch_kernel(gemm_grid_kernel<kFP32, false, true, 3>, g, b, lds, stream, job)
-                        : launch_kernel(gemm_grid_kernel<kFP32, false, false, 3>, g, b, lds, stream, job);
+    const dim3 g(grid);
+    if (prec == kFP32) {
+        if (wide) return job.groups == 2 ? launch_f32<3, 2>(job, g, lds, stream) : launch_f32<3, 1>(job, g, lds, stream);
+        return job.groups == 2 ? launch_f32<kNB, 2>(job, g, lds, stream) : launch_f32<kNB, 1>(job, g, lds, stream);
     }
+    const dim3 b(kBpThreads);
     switch (gemm_key(prec, job.full != 0)) {
-#define X(p, f)                                                                                             \
-        case gemm_key(p, f):                                                                                    \
-            return job.colw ? launch_kernel(gemm_grid_kernel<p, f, true, kNB>, g, b, lds, stream, job) \
-                            : launch_kernel(gemm_grid_kernel<p, f, false, kNB>, g, b, lds, stream, job);
-        FBP_FOR_EACH_GEMM(X)
+#define X(p, f)                                                                                              \
+        case gemm_key(p, f):                                                                                     \
+            return job.colw ? launch_kernel(gemm_grid_kernel<p, f, true, kNB, 1>, g, b, lds, stream, job) \
+                            : launch_kernel(gemm_grid_kernel<p, f, false, kNB, 1>, g, b, lds, stream, job);
+        FBP_FOR_EACH_GEMM16(X)
 #undef X
         default: return hipErrorInvalidValue;
     }

@@ -839,6 +839,7 @@ GemmJob gemm_job(const Plan& p, int prec, const float* sino, float* filt, int ro
                                (2 * (size_t)p.Dhp + 1) * (prec == kFP32 ? 4 : 2)
                          : nullptr;
     j.tiles_n = (p.D + kGemmBN - 1) / kGemmBN;
+    j.groups = 1;
     return j;
 }
 
@@ -900,6 +901,9 @@ hipError_t launch_filter_rows(const Plan& p, int prec, const float* in, float* o
             j.wide = 1;
             j.tiles_n = (p.D + 95) / 96;
         }
+        // two groups of four waves per tile when the grid leaves about one wave per
+        // SIMD (same bits as one group)
+        if (tm * j.tiles_n <= cus) j.groups = 2;
     }
     return launch_gemm_grid(prec, j, s);
 }

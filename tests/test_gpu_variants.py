@@ -122,3 +122,18 @@ def test_batch_mixes_filters_and_weights():
         assert m["max_abs_rel"] <= 2e-4 and m["rmse_rel"] <= 2e-5, (g.filter, g.weighting, m)
         alone = fbp.fbp_reconstruct(g, sino[None].contiguous()).cpu().numpy()[0]
         assert np.max(np.abs(got - alone)) <= 2e-5 * sl.value_range
+
+
+@pytest.mark.parametrize("kind", ["ramlak", "hann"])
+@pytest.mark.parametrize("K,D", [(720, 725), (180, 183), (90, 1451), (33, 64)])
+def test_filter_one_slice_equals_its_place_in_a_stack(kind, K, D):
+    """A single slice's filter grid is small, so each tile runs as two groups of
+    four waves splitting the k-steps; in a 24-slice stack the tiles run as one
+    group (and at other tile widths): the arithmetic order is the same, so the
+    filtered rows are bitwise equal."""
+    g = fbp.Geometry(K, D, 64, 1.0, filter=kind)
+    P = torch.tensor(ph.rng_for(1402, K + D).normal(size=(24, K, D)).astype(np.float32), device="cuda")
+    stack = fbp.fbp_filter(g, P).cpu().numpy()
+    for s in (0, 11, 23):
+        one = fbp.fbp_filter(g, P[s:s + 1].contiguous()).cpu().numpy()[0]
+        assert np.array_equal(one, stack[s]), (kind, K, D, s)
