@@ -52,6 +52,8 @@ GEOMS = [
     (40, 75, 50, 0.7, "uniform", 1),      # quarter-turn symmetric, dt < 1
     (64, 41, 48, 1.0, "uniform", 1),      # quarter-turn, windows past both detector ends (zero extension)
     (2, 3, 2, 1.0, "uniform", 1),         # smallest quarter-turn case
+    (4, 7, 2, 1.0, "uniform", 1),         # quarter-turn, one pixel per quadrant, two angle pairs
+    (8, 33, 34, 1.0, "uniform", 2),       # quarter-turn, quadrant of 17 (one full and one 1-wide tile)
     (50, 101, 70, 1.0, "random", 9),      # stacks: two 4-slice groups and one single slice
     (24, 230, 48, 0.35, "uniform", 5),    # stacks with windows over 63 bins (two staging segments)
 ]
