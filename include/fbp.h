@@ -102,8 +102,9 @@ typedef enum {
  *   (views spread over a full turn), and bin j sits at s_j = (j - (D-1)/2) dt on
  *   the detector line through the centre along (-sin b_k, cos b_k).  R must
  *   exceed N / sqrt(2) (the source stays outside the image); weighting must be
- *   FBP_WEIGHT_UNIFORM.  Fan geometries run through fbp_filter, fbp_backproject
- *   and fbp_reconstruct only (the other entry points return FBP_EUNSUPPORTED).
+ *   FBP_WEIGHT_UNIFORM.  Fan geometries run through fbp_filter, fbp_backproject,
+ *   fbp_reconstruct and fbp_reconstruct_batch; fbp_autotune has nothing to tune
+ *   for them (FBP_OK, tile id -1); the other entry points return FBP_EUNSUPPORTED.
  */
 typedef struct {
     int32_t n_angles;        /* K >= 1 */
@@ -201,9 +202,11 @@ size_t fbp_workspace_bytes(const fbp_geom* geom, int32_t n_slices, int32_t preci
  * stack shape (bitwise equal to fbp_reconstruct of the geometry's stack) and
  * the others its single-slice shape without angle split (bitwise equal to
  * fbp_reconstruct alone unless that shape splits, then equal within the FP32
- * tolerance).  The workspace (fbp_batch_workspace_bytes) holds the filtered
- * rows and the tile list; calls that share a workspace must be ordered on one
- * stream.
+ * tolerance).  Fan-beam jobs (Kak & Slaney 1988, ch. 3) run after the
+ * parallel-beam ones, one by one through the fan-beam kernels, each bitwise
+ * equal to fbp_reconstruct of the slice alone.  The workspace
+ * (fbp_batch_workspace_bytes) holds the filtered rows and the tile list; calls
+ * that share a workspace must be ordered on one stream.
  */
 int fbp_reconstruct_batch(const fbp_job* jobs, int32_t n_jobs, void* d_workspace,
                           size_t workspace_bytes, int32_t precision, void* hip_stream);

@@ -1086,7 +1086,6 @@ int check_jobs(const fbp_job* jobs, int32_t n) {
     for (int32_t i = 0; i < n; ++i) {
         const int rc = check_geom(&jobs[i].geom);
         if (rc != FBP_OK) return rc;
-        if (is_fan(&jobs[i].geom)) return FBP_EUNSUPPORTED;   // batches are parallel beam
         if (!jobs[i].sino || !jobs[i].image) return FBP_EINVAL;
         if (!aligned4(jobs[i].sino) || !aligned4(jobs[i].image)) return FBP_EINVAL;
         if (overlaps(jobs[i].sino, sino_bytes(&jobs[i].geom, 1), jobs[i].image,
@@ -1239,25 +1238,11 @@ int launch_batch(const GraphKey& key, int cus, hipStream_t s) {
     return hip_status(hipGraphLaunch(exec, s), "hipGraphLaunch");
 }
 
-int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes, int32_t prec,
-                      hipStream_t s) {
-    int rc = check_jobs(jobs, n);
-    if (rc == FBP_OK) rc = check_prec(prec);
-    if (rc != FBP_OK) return rc;
-    if (prec == kFFT32) return FBP_EUNSUPPORTED;     // batches filter through grouped GEMMs
-    if (n == 0) return FBP_OK;
-    const BatchLayout L = batch_layout(jobs, n);
-    if (!ws || ws_bytes < L.total) return FBP_EWORKSPACE;
-    if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return FBP_EINVAL;
-    for (int32_t i = 0; i < n; ++i) {
-        if (overlaps(ws, L.total, jobs[i].sino, sino_bytes(&jobs[i].geom, 1)) ||
-            overlaps(ws, L.total, jobs[i].image, image_bytes(&jobs[i].geom, 1)))
-            return FBP_EINVAL;
-        for (int32_t j = 0; j < i; ++j)   // images must not overlap each other
-            if (overlaps(jobs[i].image, image_bytes(&jobs[i].geom, 1), jobs[j].image,
-                         image_bytes(&jobs[j].geom, 1)))
-                return FBP_EINVAL;
-    }
+// The parallel-beam jobs of a batch (arguments checked by reconstruct_batch), with
+// layout L of these jobs in ws.
+int reconstruct_batch_parallel(const fbp_job* jobs, int32_t n, const BatchLayout& L, void* ws, int32_t prec,
+                               hipStream_t s) {
+    int rc = FBP_OK;
     std::vector<Plan*> plans((size_t)n);
     for (int32_t i = 0; i < n; ++i) {
         rc = get_plan(&jobs[i].geom, &plans[(size_t)i]);
@@ -1407,6 +1392,58 @@ int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes,
     return launch_batch(key, cu_count(device), s);
 }
 
+int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes, int32_t prec,
+                      hipStream_t s) {
+    int rc = check_jobs(jobs, n);
+    if (rc == FBP_OK) rc = check_prec(prec);
+    if (rc != FBP_OK) return rc;
+    if (prec == kFFT32) return FBP_EUNSUPPORTED;     // batches filter through grouped GEMMs
+    if (n == 0) return FBP_OK;
+    const BatchLayout L = batch_layout(jobs, n);
+    if (!ws || ws_bytes < L.total) return FBP_EWORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return FBP_EINVAL;
+    for (int32_t i = 0; i < n; ++i) {
+        if (overlaps(ws, L.total, jobs[i].sino, sino_bytes(&jobs[i].geom, 1)) ||
+            overlaps(ws, L.total, jobs[i].image, image_bytes(&jobs[i].geom, 1)))
+            return FBP_EINVAL;
+        for (int32_t j = 0; j < i; ++j)   // images must not overlap each other
+            if (overlaps(jobs[i].image, image_bytes(&jobs[i].geom, 1), jobs[j].image,
+                         image_bytes(&jobs[j].geom, 1)))
+                return FBP_EINVAL;
+    }
+    std::vector<fbp_job> par;
+    std::vector<int32_t> fan;
+    for (int32_t i = 0; i < n; ++i) {
+        if (is_fan(&jobs[i].geom)) fan.push_back(i);
+        else par.push_back(jobs[i]);
+    }
+    if (fan.empty()) return reconstruct_batch_parallel(jobs, n, L, ws, prec, s);
+    // Fan-beam jobs: after the parallel-beam ones (laid out as a batch of their own
+    // at the start of ws, which is no larger than L's descriptors and rows), one by
+    // one through the fan-beam filter and backprojection, each with its rows in the
+    // space after them; every image is bitwise fbp_reconstruct of the slice alone.
+    size_t o = 0;
+    if (!par.empty()) {
+        const BatchLayout Lp = batch_layout(par.data(), (int32_t)par.size());
+        rc = reconstruct_batch_parallel(par.data(), (int32_t)par.size(), Lp, ws, prec, s);
+        if (rc != FBP_OK) return rc;
+        o = Lp.total;
+    }
+    char* wsc = static_cast<char*>(ws);
+    for (int32_t i : fan) {
+        Plan* p = nullptr;
+        rc = get_plan(&jobs[i].geom, &p);
+        if (rc == FBP_OK) rc = ensure_taps(p, prec);
+        if (rc != FBP_OK) return rc;
+        float* filt = reinterpret_cast<float*>(wsc + o);
+        o = round_up(o + sino_bytes(&jobs[i].geom, 1), 256);
+        rc = run_fan_filter(*p, prec, 1, jobs[i].sino, filt, s);
+        if (rc == FBP_OK) rc = run_fan_backproject(*p, 1, filt, jobs[i].image, s);
+        if (rc != FBP_OK) return rc;
+    }
+    return FBP_OK;
+}
+
 // ------------------------------------------------------------------ autotuning
 
 // Device buffers and events of one tuning run, released on every exit path.
@@ -1519,7 +1556,10 @@ int time_tile_shapes(const fbp_geom* g, const std::vector<double>& cs, hipStream
 int autotune(const fbp_geom* g, hipStream_t s, int32_t* out_cfg) {
     int rc = check_geom(g);
     if (rc != FBP_OK) return rc;
-    if (is_fan(g)) return FBP_EUNSUPPORTED;                  // one fan-beam kernel: nothing to tune
+    if (is_fan(g)) {   // one fan-beam kernel: nothing to tune
+        if (out_cfg) *out_cfg = -1;
+        return FBP_OK;
+    }
     int device = 0;
     FBP_TRY_HIP(hipGetDevice(&device));
     std::vector<double> cs(2 * (size_t)g->n_angles);
@@ -1826,7 +1866,7 @@ size_t fbp_workspace_bytes(const fbp_geom* geom, int32_t n_slices, int32_t preci
 size_t fbp_batch_workspace_bytes(const fbp_job* jobs, int32_t n_jobs, int32_t precision) {
     if (check_prec(precision) != FBP_OK || precision == kFFT32 || n_jobs < 0 || (n_jobs > 0 && !jobs)) return 0;
     for (int32_t i = 0; i < n_jobs; ++i)
-        if (check_geom(&jobs[i].geom) != FBP_OK || is_fan(&jobs[i].geom)) return 0;
+        if (check_geom(&jobs[i].geom) != FBP_OK) return 0;
     return batch_layout(jobs, n_jobs).total;
 }
 

@@ -204,7 +204,7 @@ def test_bad_source_distance_rejected(lib, R):
     assert lib.fbp_backproject(ctypes.byref(g), 1, FAKE, FAKE2, None) == B.FBP_EINVAL
 
 
-def test_fan_beam_entry_points_that_do_not_take_it(lib):
+def test_fan_beam_entry_points(lib):
     ang = (ctypes.c_double * 4)(0.0, 1.5, 3.0, 4.5)
     g = B.c_geom(4, 9, 5, 1.0, ang, 0, 0, 10.0)
     gp = ctypes.byref(g)
@@ -212,10 +212,14 @@ def test_fan_beam_entry_points_that_do_not_take_it(lib):
     assert lib.fbp_plan_config(gp) == B.FBP_EUNSUPPORTED
     assert lib.fbp_plan_stack_config(gp) == B.FBP_EUNSUPPORTED
     assert lib.fbp_backproject_with_config(gp, 1, FAKE, FAKE2, 0, None) == B.FBP_EUNSUPPORTED
-    assert lib.fbp_autotune(gp, None, None) == B.FBP_EUNSUPPORTED
+    # one fan-beam kernel: nothing to tune, no tile id
+    out = ctypes.c_int32(7)
+    assert lib.fbp_autotune(gp, None, ctypes.byref(out)) == B.FBP_OK and out.value == -1
+    # batches take fan-beam jobs: the workspace is sized for them and checked first
     job = B.c_job(g, FAKE, FAKE2)
-    assert lib.fbp_batch_workspace_bytes(ctypes.byref(job), 1, 0) == 0
-    assert lib.fbp_reconstruct_batch(ctypes.byref(job), 1, FAKE3, 1 << 20, 0, None) == B.FBP_EUNSUPPORTED
+    need = lib.fbp_batch_workspace_bytes(ctypes.byref(job), 1, 0)
+    assert need >= 4 * 9 * 4
+    assert lib.fbp_reconstruct_batch(ctypes.byref(job), 1, FAKE3, need - 1, 0, None) == B.FBP_EWORKSPACE
     # angle-gap weights are parallel-beam only
     g2 = B.c_geom(4, 9, 5, 1.0, ang, 0, 1, 10.0)
     assert lib.fbp_backproject(ctypes.byref(g2), 1, FAKE, FAKE2, None) == B.FBP_EUNSUPPORTED

@@ -163,6 +163,35 @@ def test_fan_geometry_is_refused_where_unsupported():
     assert e.value.status == fbp.FBP_EUNSUPPORTED
 
 
+def test_fan_jobs_in_a_mixed_batch():
+    """Fan-beam jobs (one-tile and quarter-turn forms, Shepp-Logan filter on one)
+    between parallel-beam jobs of one batch: every image bitwise equal to
+    fbp_reconstruct of the slice alone, the fan images against the oracle's
+    fan-beam reconstruction."""
+    N, D = 48, 101
+    R = 1.5 * N / math.sqrt(2.0)
+    fan_a = fbp.Geometry(90, D, N, 1.0, source_distance=R)
+    fan_b = fbp.Geometry(96, D, N, 1.0, filter="shepp-logan", source_distance=R)
+    par = fbp.Geometry(60, 75, 50, 1.0)
+    geoms = [par, fan_a, par, fan_b, fan_a]
+    rng = ph.rng_for(1609, 0)
+    jobs = []
+    for g in geoms:
+        P = torch.tensor(rng.normal(size=(1, g.n_angles, g.n_det)).astype(np.float32), device="cuda")
+        jobs.append((g, P, torch.full((1, g.image_size, g.image_size), float("nan"), device="cuda")))
+    fbp.fbp_reconstruct_batch([(g, P[0], im[0]) for g, P, im in jobs])
+    torch.cuda.synchronize()
+    for g, P, im in jobs:
+        alone = fbp.fbp_reconstruct(g, P)
+        assert torch.equal(im, alone)
+        if g.source_distance > 0:
+            kind = "shepp-logan" if g is fan_b else "ramlak"
+            ref = oracle.fan_backproject(oracle.fan_filter(P.cpu().numpy().astype(np.float64), 1.0, R, kind),
+                                         N, 1.0, R, g.angles)
+            err = np.max(np.abs(im.cpu().numpy().astype(np.float64) - ref))
+            assert err <= 2e-4 * np.max(np.abs(ref)), err
+
+
 def test_fan_quarter_turn_form_matches_general_form():
     """Views in quarter turns take the quadrant-and-turns kernel; the same views
     listed with a 1e-9 rad perturbation (no longer quarter turns) take the one-tile
