@@ -228,3 +228,16 @@ def test_fan_degenerate_sizes():
         got = fbp.fbp_backproject(g, torch.tensor(Q, device="cuda")).cpu().numpy()
         ref = oracle.fan_backproject(Q.astype(np.float64), N, 1.0, R, b)
         assert np.max(np.abs(got - ref)) <= _bp_tol(Q, N, R), (K, D, N)
+
+
+@pytest.mark.parametrize("K,D", [(720, 801), (90, 101)])
+def test_fan_filter_one_slice_equals_its_place_in_a_stack(K, D):
+    """The pre-weighted filter of a single view set runs as two four-wave groups per
+    tile (each one accumulator set); in a stack it runs as one group (both sets):
+    the same products in the same order, so the bits agree."""
+    g = fbp.Geometry(K, D, 256, 1.0, source_distance=1.5 * 256 / math.sqrt(2.0))
+    P = torch.tensor(ph.rng_for(1610, K).normal(size=(24, K, D)).astype(np.float32), device="cuda")
+    stack = fbp.fbp_filter(g, P).cpu().numpy()
+    for s in (0, 23):
+        one = fbp.fbp_filter(g, P[s:s + 1].contiguous()).cpu().numpy()[0]
+        assert np.array_equal(one, stack[s]), (K, D, s)
