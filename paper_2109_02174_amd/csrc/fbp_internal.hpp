@@ -304,7 +304,8 @@ struct GemmJob {
     const void* taps_even;
     const float* colw;    // [D] factor per input column applied to P before the product
                           // (fan-beam pre-weights), or null
-    int32_t wide;         // FP32 only: 1 = tiles of 96 output bins (tiles_n = ceil(D / 96)), 0 = 64
+    int32_t nb;           // FP32 grid launches: tiles of 32 nb output bins (nb = 1, 2, 3; tiles_n =
+                          // ceil(D / (32 nb))); 0 = the default 64-bin tiles
     int32_t groups;       // FP32 grid launches: 1 or 2 groups of four waves per tile (same bits)
 };
 static_assert(sizeof(GemmJob) % 8 == 0, "GemmJob layout");
@@ -323,8 +324,8 @@ struct GemmListArgs {
 hipError_t launch_gemm_list(int prec, bool full, const GemmListArgs* args, int grid, size_t lds_bytes,
                             hipStream_t stream);
 // LDS of a filter workgroup; full: the kernel has even taps too (their copies
-// double the tap area); wide: FP32 96-bin tiles.
-int gemm_lds_bytes(int prec, int Dh, bool full, bool wide = false);
+// double the tap area); nb: FP32 tiles of 32 nb output bins (0: the default 64).
+int gemm_lds_bytes(int prec, int Dh, bool full, int nb = 0);
 int gemm_occupancy(int prec, bool full, size_t lds_bytes);
 
 }  // namespace fbp

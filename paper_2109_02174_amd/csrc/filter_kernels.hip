@@ -486,7 +486,7 @@ __device__ __forceinline__ void gemm_tile(const GemmJob& job, int mt, int nt, ch
 
 // CW: the job has column weights (job.colw); a separate instantiation keeps the
 // unweighted filter's ring and stores as they were
-// NB: 16-wide MFMA blocks per wave and parity (2: 64-bin tiles, 3: 96-bin tiles, FP32)
+// NB: 16-wide MFMA blocks per wave and parity (2: 64-bin tiles; FP32 also 1: 32-bin, 3: 96-bin)
 // G: groups of four waves (FP32: 1 or 2)
 template <int PREC, bool FULL, bool CW, int NB, int G>
 __global__ __launch_bounds__(kBpThreads * G) void gemm_grid_kernel(GemmJob job) {
@@ -543,12 +543,12 @@ constexpr int gemm_key(int prec, bool full) { return prec * 2 + (full ? 1 : 0); 
 
 }  // namespace
 
-int gemm_lds_bytes(int prec, int Dh, bool full, bool wide) {
+int gemm_lds_bytes(int prec, int Dh, bool full, int nb) {
     const int tables = full ? 2 : 1;   // odd taps, and even taps for kernels that have them
     if (prec == kFP32) {
         const int mpad = (Dh + kK32 - 1) / kK32 * kK32;
         // panel, four copies of each tap table
-        return (2 * kABuf32 + tables * 4 * copy_stride32(mpad, wide ? 48 : kHalfN)) * 4;
+        return (2 * kABuf32 + tables * 4 * copy_stride32(mpad, nb > 0 ? 16 * nb : kHalfN)) * 4;
     }
     const int mpad = (Dh + kK16 - 1) / kK16 * kK16;
     return (2 * kABuf16 + tables * 8 * ((mpad + kHalfN + 8 + 7 + 7) & ~7)) * 2;
@@ -568,14 +568,17 @@ hipError_t launch_f32(const GemmJob& job, dim3 g, size_t lds, hipStream_t stream
 hipError_t launch_gemm_grid(int prec, const GemmJob& job, hipStream_t stream) {
     const int tiles_m = (job.R + kTM - 1) / kTM;
     const unsigned grid = (unsigned)(tiles_m * job.tiles_n);
-    const bool wide = job.wide != 0;
-    if (wide && (prec != kFP32 || job.tiles_n != (job.D + 95) / 96)) return hipErrorInvalidValue;
+    const int nb = job.nb > 0 ? job.nb : kNB;
+    if (nb != kNB && (prec != kFP32 || nb > 3 || job.tiles_n != (job.D + 32 * nb - 1) / (32 * nb)))
+        return hipErrorInvalidValue;
     if (job.groups != 1 && (prec != kFP32 || job.groups != 2)) return hipErrorInvalidValue;
-    const size_t lds = (size_t)gemm_lds_bytes(prec, job.Dh, job.full != 0, wide);
+    const size_t lds = (size_t)gemm_lds_bytes(prec, job.Dh, job.full != 0, job.nb);
     const dim3 g(grid);
     if (prec == kFP32) {
-        if (wide) return job.groups == 2 ? launch_f32<3, 2>(job, g, lds, stream) : launch_f32<3, 1>(job, g, lds, stream);
-        return job.groups == 2 ? launch_f32<kNB, 2>(job, g, lds, stream) : launch_f32<kNB, 1>(job, g, lds, stream);
+        const bool g2 = job.groups == 2;
+        if (nb == 1) return g2 ? launch_f32<1, 2>(job, g, lds, stream) : launch_f32<1, 1>(job, g, lds, stream);
+        if (nb == 3) return g2 ? launch_f32<3, 2>(job, g, lds, stream) : launch_f32<3, 1>(job, g, lds, stream);
+        return g2 ? launch_f32<kNB, 2>(job, g, lds, stream) : launch_f32<kNB, 1>(job, g, lds, stream);
     }
     const dim3 b(kBpThreads);
     switch (gemm_key(prec, job.full != 0)) {

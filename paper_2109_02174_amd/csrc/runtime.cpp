@@ -893,12 +893,17 @@ hipError_t launch_filter_rows(const Plan& p, int prec, const float* in, float* o
     GemmJob j = gemm_job(p, prec, in, out, rows);
     j.colw = colw;
     if (prec == kFP32) {
-        // 96-bin tiles where they leave fewer tiles on the most loaded CU (in units of
-        // a 32-bin half tile); same arithmetic per output bin, so the same bits
+        // Tile width (the same arithmetic per output bin at every width, so the same
+        // bits): 32-bin tiles when even those leave each CU at most one tile (very
+        // small grids); else 96-bin tiles where they leave fewer tiles on the most
+        // loaded CU than 64-bin ones (in units of 32 bins)
         const int64_t tm = (rows + kGemmBM - 1) / kGemmBM, cus = cu_count(p.device);
-        const int64_t t64 = tm * ((p.D + 63) / 64), t96 = tm * ((p.D + 95) / 96);
-        if ((t96 + cus - 1) / cus * 3 < (t64 + cus - 1) / cus * 2) {
-            j.wide = 1;
+        const int64_t t32 = tm * ((p.D + 31) / 32), t64 = tm * ((p.D + 63) / 64), t96 = tm * ((p.D + 95) / 96);
+        if (t32 <= cus) {
+            j.nb = 1;
+            j.tiles_n = (p.D + 31) / 32;
+        } else if ((t96 + cus - 1) / cus * 3 < (t64 + cus - 1) / cus * 2) {
+            j.nb = 3;
             j.tiles_n = (p.D + 95) / 96;
         }
         // two groups of four waves per tile when the grid leaves about one wave per

@@ -59,6 +59,8 @@ def test_precision_sweep_stack_sampled_slices(stack, prec):
         print(prec, i, m)
         if prec == "fp32":
             assert m["max_abs_rel"] <= 2e-4 and m["rmse_rel"] <= 2e-5 and m["psnr_db"] >= 94
+            # regression gate: about three times the largest measured (5.0e-6 / 1.1e-6)
+            assert m["max_abs_rel"] <= 1.5e-5 and m["rmse_rel"] <= 3.3e-6, m
         else:
             assert m["psnr_db"] >= MIN_PSNR[prec]
 
@@ -80,3 +82,5 @@ def test_mixed_batch_full_size_one_slice_per_geometry():
         m = metrics.compare(jobs[i][2].cpu().numpy(), ref, float(raster.max() - raster.min()))
         print(i, g.image_size, g.n_angles, m)
         assert m["max_abs_rel"] <= 2e-4 and m["rmse_rel"] <= 2e-5 and m["psnr_db"] >= 94
+        # regression gate: about three times the largest measured (1.5e-5 / 1.8e-6)
+        assert m["max_abs_rel"] <= 5e-5 and m["rmse_rel"] <= 6e-6, m

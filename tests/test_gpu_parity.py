@@ -125,6 +125,10 @@ def test_reconstruction_matches_oracle(cfg):
     assert m["max_abs_rel"] <= 2e-4
     assert m["rmse_rel"] <= 2e-5
     assert m["psnr_db"] >= 94.0
+    # regression gate: about three times the error these kernels give on this input
+    # (C1 9.4e-7 / 2.2e-7, C2 2.2e-6 / 3.4e-7 measured)
+    tight = {"C1": (3e-6, 7e-7), "C2": (7e-6, 1e-6)}[cfg]
+    assert m["max_abs_rel"] <= tight[0] and m["rmse_rel"] <= tight[1], m
 
 
 def test_gaussian_centre_on_gpu():
