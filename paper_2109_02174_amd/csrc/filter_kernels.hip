@@ -15,9 +15,11 @@
 // memory: each workgroup copies the slice of the 1D odd-tap table its outputs
 // need into LDS and feeds the B operand from there.
 //
-// Workgroup: 256 lanes = 4 waves; tile = 32 rows x kGemmBN output bins.  Wave w
-// owns rows 16 (w/2) .. +16 and the output bins of parity w%2 (kGemmBN/32 16x16
-// MFMA blocks).
+// Workgroup: a group of 256 lanes = 4 waves per tile of 32 rows x kGemmBN output
+// bins (FP32 tiles also 32 or 96 bins wide; FP32 grids with no more tiles than
+// CUs run two groups per tile, each taking half of every chunk's k-steps).  Wave
+// w of a group owns rows 16 (w/2) .. +16 and the output bins of parity w%2 (one
+// 16x16 MFMA block per 16 bins of that parity).
 // A ring of register buffers keeps several chunks of sinogram rows in flight
 // while the current one is multiplied; the LDS panel they are staged into is
 // double-buffered, so each chunk needs one barrier.
