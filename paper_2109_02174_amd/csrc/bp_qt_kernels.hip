@@ -35,6 +35,8 @@
 //    block is computed, with buffer loads whose range check supplies the zeros
 //    beyond the detector ends.
 //  * Each pixel is written once by one thread; no atomics.
+#include <algorithm>
+
 #include "fbp_internal.hpp"
 
 namespace fbp {
@@ -61,16 +63,22 @@ __device__ __forceinline__ void wave_sync() {
 // Angle pairs whose window origins a wave makes at once (one per lane).
 constexpr int kRound = 64;
 
-// LDS bytes of one wave's region: the constants of a round of pairs (float4 +
-// int2 per pair), then B pairs x 4 planes x WP bins of float4.
-template <int WP, int B>
+// LDS of a workgroup: per wave, the constants of a round of pairs (float4 + int2
+// per pair) and B pairs x 4 planes x WP bins of float4; after the 16 wave regions,
+// the chunk sums [wave][turn][row][kPartPitch], in a region of their own so that a
+// workgroup that runs several tiles loads its next tile's first windows while the
+// current tile's chunk sums are added.
+// SEP = false (a workgroup per tile): the chunk sums reuse the window regions.
+template <int WP, int B, bool SEP>
 struct QtLds {
     static constexpr int PRM = kRound * 24;
     static constexpr int REGION = PRM + B * 4 * WP * 16;
     static constexpr int WINDOWS = kWaves * REGION;
     static constexpr int PARTS = kWaves * 4 * kTileH * kPartPitch * 4;
-    static constexpr int BYTES = WINDOWS > PARTS ? WINDOWS : PARTS;
+    static constexpr int PARTS_AT = SEP ? WINDOWS : 0;
+    static constexpr int BYTES = SEP ? WINDOWS + PARTS : (WINDOWS > PARTS ? WINDOWS : PARTS);
 };
+static_assert(QtLds<32, 2, true>::BYTES <= 160 * 1024 && QtLds<64, 1, true>::BYTES <= 160 * 1024, "LDS");
 
 // The eight updates of one angle pair (theta, theta + pi/2) for a pixel p and its
 // turns R p, R^2 p, R^3 p (R(x, y) = (-y, x)), from the coordinates U = u_theta(p)
@@ -94,14 +102,42 @@ __device__ __forceinline__ void pair_update(float u, float v, const float4& qu0,
     a3 += fmaf(u, qu1.w, qu1.z);
 }
 
-// One tile (top-left corner (c0, r0) of the quadrant) of one slice: rows q
-// ([K][D]) into img ([N][N]).  smem holds QtLds<WP, B>::BYTES.  WS: the job has
-// per-angle weights (a separate instantiation keeps the uniform path free of
-// their scalar loads, which would otherwise order the staging's LDS operations).
-template <int WP, int B, bool WS>
-__device__ __forceinline__ void qt_tile(const BpJob& job, const float* __restrict__ q, float* __restrict__ img,
-                                        int c0, int r0, char* smem) {
-    using L = QtLds<WP, B>;
+// One tile of one slice: the slice's rows ([K][D]) and image ([N][N]), the fields
+// of its job the kernel reads (by value: a pointer to a kernel argument would put
+// the argument in private memory), and the top-left corner (c0, r0) of the
+// quadrant tile.
+struct QtTile {
+    const float* q;
+    float* img;
+    const double* cs;
+    const float* wscale;
+    double half_pix, centre_det;
+    float scale;
+    int N, K, D, c0, r0;
+};
+
+__device__ __forceinline__ void set_job(QtTile& tl, const BpJob& job) {
+    tl.cs = job.cs;
+    tl.wscale = job.wscale;
+    tl.half_pix = job.half_pix;
+    tl.centre_det = job.centre_det;
+    tl.scale = job.scale;
+    tl.N = job.N;
+    tl.K = job.K;
+    tl.D = job.D;
+}
+
+// Backprojects the tiles next() hands out, one after another (one for a single
+// slice's grid), each exactly as a workgroup of its own would: the summation order
+// depends on the tile's geometry alone.  While a tile's chunk sums are added, the
+// window origins and first rows of the next tile are already loading.  smem holds
+// QtLds<WP, B, SEP>::BYTES; without SEP next() must hand out one tile only.  WSM: 0
+// no job has per-angle weights, 1 every job has them, 2 either (a separate
+// instantiation keeps the uniform path free of the weights' scalar loads, which
+// would otherwise order the staging's LDS operations).
+template <int WP, int B, int WSM, bool SEP, class Next>
+__device__ __forceinline__ void qt_run(Next next, char* smem) {
+    using L = QtLds<WP, B, SEP>;
     constexpr int WPASS = 64 / WP;            // windows staged per pass of the wave
     constexpr int NPASS = 2 * B / WPASS;      // passes per block (two windows per pair)
     static_assert(WPASS >= 1 && NPASS * WPASS == 2 * B, "staging passes");
@@ -113,42 +149,55 @@ __device__ __forceinline__ void qt_tile(const BpJob& job, const float* __restric
     float4* prm = reinterpret_cast<float4*>(region);                // [kRound] {bU, bV, cos/dt, sin/dt}
     int2* pri = reinterpret_cast<int2*>(region + kRound * 16);      // [kRound] {iU, iV}
     float4* win = reinterpret_cast<float4*>(region + L::PRM);       // [B][4][WP]
+    float* part = reinterpret_cast<float*>(smem + L::PARTS_AT);     // [wave][turn][row][kPartPitch]
 
-    const int N = job.N, D = job.D;
-    const int KH = job.K >> 1;
-    const int lo = (int)(((long long)wave * KH) / kWaves);
-    const int hi = (int)(((long long)(wave + 1) * KH) / kWaves);
-    const int n = hi - lo;
-    const double x0 = (double)c0 - job.half_pix;
-    const double y0 = (double)r0 - job.half_pix;
     const int lx = lane & (kTile - 1);
     const int ly0 = (lane >> 4) * kRows;
     const float flx = (float)lx;
     const float fly = (float)ly0;
     const float nfly = -fly;
-    const int d4 = (D - 1) * 4;
     const int jl = lane & (WP - 1);             // window bin of this lane when staging
     const int wl = (WPASS == 2) ? (lane >> 5) : 0;
-    const float* __restrict__ wscale = job.wscale;
+
+    // the tile's values every phase uses; wave w sums the pairs [lo, hi)
+    struct Vals {
+        QtTile tl;
+        int KH, lo, hi, n, d4;
+        double x0, y0;
+    };
+    auto vals = [&](const QtTile& tl) {
+        Vals v;
+        v.tl = tl;
+        v.KH = tl.K >> 1;
+        v.lo = (int)(((long long)wave * v.KH) / kWaves);
+        v.hi = (int)(((long long)(wave + 1) * v.KH) / kWaves);
+        v.n = v.hi - v.lo;
+        v.d4 = (tl.D - 1) * 4;
+        v.x0 = (double)tl.c0 - tl.half_pix;
+        v.y0 = (double)tl.r0 - tl.half_pix;
+        return v;
+    };
 
     float acc0[kRows], acc1[kRows], acc2[kRows], acc3[kRows];
+    auto zero = [&]() {
 #pragma unroll
-    for (int i = 0; i < kRows; ++i) {
-        acc0[i] = 0.0f;
-        acc1[i] = 0.0f;
-        acc2[i] = 0.0f;
-        acc3[i] = 0.0f;
-    }
+        for (int i = 0; i < kRows; ++i) {
+            acc0[i] = 0.0f;
+            acc1[i] = 0.0f;
+            acc2[i] = 0.0f;
+            acc3[i] = 0.0f;
+        }
+    };
 
     // window origins (FP64) of the pairs lo + rs .. lo + rs + 63 of a round, one per lane
-    auto params = [&](int rs) {
-        const int k = lo + rs + lane;
-        if (k < hi) {
-            const double cd = job.cs[2 * k];
-            const double sd = job.cs[2 * k + 1];
-            const double uo = x0 * cd + y0 * sd + job.centre_det;
+    auto params = [&](const Vals& v, int rs) {
+        const int k = v.lo + rs + lane;
+        if (k < v.hi) {
+            const double cd = v.tl.cs[2 * k];
+            const double sd = v.tl.cs[2 * k + 1];
+            const double uo = v.x0 * cd + v.y0 * sd + v.tl.centre_det;
             const double umin = uo + fmin(0.0, (double)(kTile - 1) * cd) + fmin(0.0, (double)(kTileH - 1) * sd);
-            const double vo = x0 * sd - y0 * cd + job.centre_det;
+            const double vo = v.x0 * sd - v.y0 * cd + v.tl.centre_det;
             const double vmin = vo + fmin(0.0, (double)(kTile - 1) * sd) + fmin(0.0, -(double)(kTileH - 1) * cd);
             const int iu = (int)floor(umin) - 1;
             const int iv = (int)floor(vmin) - 1;
@@ -169,26 +218,27 @@ __device__ __forceinline__ void qt_tile(const BpJob& job, const float* __restric
     asm volatile("v_mov_b32 %0, 4" : "=v"(four));
     // kb: first pair of the block within the round (lo + rnd + kb overall)
     int rnd = 0;
-    auto load = [&](int kb, int nr) {
+    auto load = [&](const Vals& v, int kb, int nr) {
         const int nb = min(B, nr - kb);
+        const int D = v.tl.D;
 #pragma unroll
         for (int ps = 0; ps < NPASS; ++ps) {
             const int s0 = ps * WPASS;            // first window of the pass (uniform)
             const int b = s0 >> 1;                // pair (uniform: a pass never spans two pairs)
             if (b < nb) {
                 const int w = (WPASS == 2) ? wl : (s0 & 1);
-                const int k = lo + rnd + kb + b;
+                const int k = v.lo + rnd + kb + b;
                 const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
-                    const_cast<float*>(q + (size_t)k * (size_t)D), (short)0, D * 4, kBufferWord3);
+                    const_cast<float*>(v.tl.q + (size_t)k * (size_t)D), (short)0, D * 4, kBufferWord3);
                 const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
-                    const_cast<float*>(q + (size_t)(k + KH) * (size_t)D), (short)0, D * 4, kBufferWord3);
+                    const_cast<float*>(v.tl.q + (size_t)(k + v.KH) * (size_t)D), (short)0, D * 4, kBufferWord3);
                 const int2 io = pri[kb + b];
                 const int g4 = ((w ? io.y : io.x) + jl) * 4;
                 pf[ps][0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, g4, 0, 0));
-                pf[ps][1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, d4 - g4, 0, 0));
+                pf[ps][1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, v.d4 - g4, 0, 0));
                 pf[ps][2] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, g4, 0, 0));
-                pf[ps][3] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, d4 - g4, 0, 0));
-                const int gn = g4 + four, dn = d4 - g4 - four;
+                pf[ps][3] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, v.d4 - g4, 0, 0));
+                const int gn = g4 + four, dn = v.d4 - g4 - four;
                 pn[ps][0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, gn, 0, 0));
                 pn[ps][1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, dn, 0, 0));
                 pn[ps][2] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, gn, 0, 0));
@@ -196,16 +246,19 @@ __device__ __forceinline__ void qt_tile(const BpJob& job, const float* __restric
             }
         }
     };
-    auto store = [&](int kb, int nr) {
+    auto store = [&](const Vals& v, int kb, int nr) {
         const int nb = min(B, nr - kb);
         float nx[NPASS][4];
 #pragma unroll
         for (int ps = 0; ps < NPASS; ++ps) {
             const int b = (ps * WPASS) >> 1;
             if (b < nb) {
-                if constexpr (WS) {   // angle weights / (pi/K): scalar loads
-                    const int k = lo + rnd + kb + b;
-                    const float ca = wscale[k], cb = wscale[k + KH];
+                bool ws = WSM == 1;
+                if constexpr (WSM == 2) ws = v.tl.wscale != nullptr;
+                if (WSM != 0 && ws) {   // angle weights / (pi/K): scalar loads
+                    const float* __restrict__ wscale = v.tl.wscale;
+                    const int k = v.lo + rnd + kb + b;
+                    const float ca = wscale[k], cb = wscale[k + v.KH];
                     pf[ps][0] *= ca;
                     pf[ps][1] *= ca;
                     pf[ps][2] *= cb;
@@ -271,96 +324,160 @@ __device__ __forceinline__ void qt_tile(const BpJob& job, const float* __restric
             }
         }
     };
-
-    // rounds of up to kRound pairs (one for K <= 2048): the window origins of the
-    // round, then blocks of B pairs, the next block's rows loaded during the current
-    for (rnd = 0; rnd < n; rnd += kRound) {
-        const int nr = min(kRound, n - rnd);
-        params(rnd);
-        wave_sync();
-        load(0, nr);
-        for (int kb = 0; kb < nr; kb += B) {
-            store(kb, nr);
+    // the first round's window origins and the first block's rows of a tile
+    auto begin = [&](const Vals& v) {
+        rnd = 0;
+        if (v.n > 0) {
+            params(v, 0);
             wave_sync();
-            if (kb + B < nr) load(kb + B, nr);
-            compute(kb, nr);
-            wave_sync();
+            load(v, 0, min(kRound, v.n));
         }
-    }
+    };
 
-    // chunk sums through LDS, added in wave order; each output written once
-    __syncthreads();   // every wave is done with its windows
-    float* part = reinterpret_cast<float*>(smem);   // [wave][turn][row][kPartPitch]
+    QtTile tile;
+    if (!next(tile)) return;
+    Vals cur = vals(tile);
+    zero();
+    begin(cur);
+    for (;;) {
+        // rounds of up to kRound pairs (one for K <= 2048): the window origins of the
+        // round, then blocks of B pairs, the next block's rows loaded during the
+        // current (the first round's origins and rows were started by begin)
+        for (rnd = 0; rnd < cur.n; rnd += kRound) {
+            const int nr = min(kRound, cur.n - rnd);
+            if (rnd > 0) {
+                params(cur, rnd);
+                wave_sync();
+                load(cur, 0, nr);
+            }
+            for (int kb = 0; kb < nr; kb += B) {
+                store(cur, kb, nr);
+                wave_sync();
+                if (kb + B < nr) load(cur, kb + B, nr);
+                compute(kb, nr);
+                wave_sync();
+            }
+        }
+
+        // chunk sums through LDS, added in wave order; each output written once
+        // every thread is done adding the previous tile's chunk sums (and, when the sums
+        // reuse the window regions, every wave is done with its windows)
+        __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kRows; ++i) {
-        float* pp = part + ((wave * 4) * kTileH + ly0 + i) * kPartPitch + lx;
-        pp[0 * kTileH * kPartPitch] = acc0[i];
-        pp[1 * kTileH * kPartPitch] = acc1[i];
-        pp[2 * kTileH * kPartPitch] = acc2[i];
-        pp[3 * kTileH * kPartPitch] = acc3[i];
-    }
-    __syncthreads();
-    const int turn = t >> 8;       // 0: p, 1: R p, 2: R^2 p, 3: R^3 p
-    const int e = t & 255;         // tile element (threads past kTile * kTileH idle)
-    // p and R^2 p run along tile rows, R p and R^3 p along tile columns, so that
-    // consecutive threads write consecutive image addresses
-    const int ty = (turn & 1) ? (e % kTileH) : (e / kTile);
-    const int tx = (turn & 1) ? (e / kTileH) : (e % kTile);
-    const float* src = part + (turn * kTileH + ty) * kPartPitch + tx;
-    float sum = 0.0f;
+        for (int i = 0; i < kRows; ++i) {
+            float* pp = part + ((wave * 4) * kTileH + ly0 + i) * kPartPitch + lx;
+            pp[0 * kTileH * kPartPitch] = acc0[i];
+            pp[1 * kTileH * kPartPitch] = acc1[i];
+            pp[2 * kTileH * kPartPitch] = acc2[i];
+            pp[3 * kTileH * kPartPitch] = acc3[i];
+        }
+        const bool more = SEP && next(tile);
+        Vals nxt;
+        if (more) {   // the next tile's first windows load while these sums are added
+            nxt = vals(tile);
+            zero();
+            begin(nxt);
+        }
+        __syncthreads();
+        const int N = cur.tl.N;
+        const int turn = t >> 8;       // 0: p, 1: R p, 2: R^2 p, 3: R^3 p
+        const int e = t & 255;         // tile element (threads past kTile * kTileH idle)
+        // p and R^2 p run along tile rows, R p and R^3 p along tile columns, so that
+        // consecutive threads write consecutive image addresses
+        const int ty = (turn & 1) ? (e % kTileH) : (e / kTile);
+        const int tx = (turn & 1) ? (e / kTileH) : (e % kTile);
+        const float* src = part + (turn * kTileH + ty) * kPartPitch + tx;
+        float sum = 0.0f;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) sum += src[w * 4 * kTileH * kPartPitch];
-    const int r = r0 + ty, c = c0 + tx, half = N >> 1;
-    if (e < kTile * kTileH && r < half && c < half) {
-        size_t o;
-        if (turn == 0) o = (size_t)r * N + c;
-        else if (turn == 1) o = (size_t)c * N + (N - 1 - r);
-        else if (turn == 2) o = (size_t)(N - 1 - r) * N + (N - 1 - c);
-        else o = (size_t)(N - 1 - c) * N + r;
-        img[o] = sum * job.scale;
+        for (int w = 0; w < kWaves; ++w) sum += src[w * 4 * kTileH * kPartPitch];
+        const int r = cur.tl.r0 + ty, c = cur.tl.c0 + tx, half = N >> 1;
+        if (e < kTile * kTileH && r < half && c < half) {
+            size_t o;
+            if (turn == 0) o = (size_t)r * N + c;
+            else if (turn == 1) o = (size_t)c * N + (N - 1 - r);
+            else if (turn == 2) o = (size_t)(N - 1 - r) * N + (N - 1 - c);
+            else o = (size_t)(N - 1 - c) * N + r;
+            cur.tl.img[o] = sum * cur.tl.scale;
+        }
+        if (!more) break;
+        cur = nxt;
     }
 }
 
-template <int WP, int B, bool WS>
+// Grid form over n slices of one geometry (tiles_per_slice each).  PERSIST = false:
+// a workgroup per tile, blocks mapped to tiles XCD-aware.  PERSIST: a smaller grid
+// of persistent workgroups, each XCD taking a contiguous range of tiles (whole
+// slices of a stack, which share an L2) split among its workgroups.
+template <int WP, int B, bool WS, bool PERSIST>
 __global__ __launch_bounds__(kThreads, kWavesPerSimd) void bp_qt_grid_kernel(BpJob job, size_t q_stride, size_t img_stride,
-                                                              int tiles_per_slice) {
-    __shared__ __attribute__((aligned(16))) char smem[QtLds<WP, B>::BYTES];
-    const int lb = xcd_logical(blockIdx.x, gridDim.x);
-    const int s = lb / tiles_per_slice;
-    const int tt = lb - s * tiles_per_slice;
-    const int ty = tt / job.tiles_x;
-    const int tx = tt - ty * job.tiles_x;
-    qt_tile<WP, B, WS>(job, job.q + (size_t)s * q_stride, job.img + (size_t)s * img_stride, tx * kTile, ty * kTileH,
-                   smem);
+                                                              int tiles_per_slice, int total) {
+    __shared__ __attribute__((aligned(16))) char smem[QtLds<WP, B, PERSIST>::BYTES];
+    const int G = gridDim.x, b = blockIdx.x;
+    int it, end, step;
+    if (!PERSIST || G >= total) {
+        it = xcd_logical(b, G);
+        end = it + 1;
+        step = 1;
+    } else if ((G & 7) == 0) {
+        const int x = b & 7, per = G >> 3;
+        it = (int)(((long long)x * total) >> 3) + (b >> 3);
+        end = (int)(((long long)(x + 1) * total) >> 3);
+        step = per;
+    } else {
+        it = b;
+        end = total;
+        step = G;
+    }
+    auto next = [&](QtTile& tl) {
+        if (it >= end) return false;
+        const int s = it / tiles_per_slice;
+        const int tt = it - s * tiles_per_slice;
+        const int ty = tt / job.tiles_x;
+        const int tx = tt - ty * job.tiles_x;
+        set_job(tl, job);
+        tl.q = job.q + (size_t)s * q_stride;
+        tl.img = job.img + (size_t)s * img_stride;
+        tl.c0 = tx * kTile;
+        tl.r0 = ty * kTileH;
+        it += step;
+        return true;
+    };
+    qt_run<WP, B, WS ? 1 : 0, PERSIST>(next, smem);
 }
 
 // Persistent form over a mixed list (same arguments as the other list kernels):
 // tile index -> job by binary search in the tile prefix; one job per slice.
 template <int WP, int B>
 __global__ __launch_bounds__(kThreads, kWavesPerSimd) void bp_qt_list_kernel(const BpListArgs* __restrict__ args) {
-    __shared__ __attribute__((aligned(16))) char smem[QtLds<WP, B>::BYTES];
+    __shared__ __attribute__((aligned(16))) char smem[QtLds<WP, B, true>::BYTES];
     const BpListArgs a = load_const(args);
     const auto* __restrict__ prefix = as_const(a.tile_prefix);
     const int n_sel = *as_const(a.counts);
     if (n_sel <= 0) return;
     const int total = prefix[n_sel];
     const int G = gridDim.x;
-    for (int it = xcd_logical(blockIdx.x, G); it < total; it += G) {
+    int it = xcd_logical(blockIdx.x, G);
+    BpJob job;
+    auto next = [&](QtTile& tl) {
+        if (it >= total) return false;
         int lo = 0, hi = n_sel - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (prefix[mid] <= it) lo = mid; else hi = mid - 1;
         }
-        const BpJob job = load_const(a.jobs + as_const(a.job_index)[lo]);
+        job = load_const(a.jobs + as_const(a.job_index)[lo]);
         const int tt = it - prefix[lo];
         const int ty = tt / job.tiles_x;
         const int tx = tt - ty * job.tiles_x;
-        __syncthreads();   // the previous tile's chunk sums are read before windows overwrite them
-        if (job.wscale)
-            qt_tile<WP, B, true>(job, job.q, job.img, tx * kTile, ty * kTileH, smem);
-        else
-            qt_tile<WP, B, false>(job, job.q, job.img, tx * kTile, ty * kTileH, smem);
-    }
+        set_job(tl, job);
+        tl.q = job.q;
+        tl.img = job.img;
+        tl.c0 = tx * kTile;
+        tl.r0 = ty * kTileH;
+        it += G;
+        return true;
+    };
+    qt_run<WP, B, 2, true>(next, smem);
 }
 
 }  // namespace
@@ -375,22 +492,29 @@ int qt_block_pairs(int WP) { return WP == 32 ? 2 : 1; }
 
 hipError_t launch_bp_qt_grid(const BpJob& job, int n_slices, size_t q_stride, size_t img_stride,
                              int tiles_per_slice, hipStream_t stream) {
-    const long long grid = (long long)n_slices * tiles_per_slice;
-    if (grid <= 0) return hipSuccess;
-    if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
+    const long long total = (long long)n_slices * tiles_per_slice;
+    if (total <= 0) return hipSuccess;
+    if (total > 0x7fffffffLL) return hipErrorInvalidValue;
+    // one 16-wave workgroup per CU at a time: a workgroup per tile up to one per CU,
+    // persistent workgroups (several tiles each) beyond
+    const int cus = current_device_cus();
+    const int grid = (int)std::min<long long>(total, cus);
+    const int tot = (int)total;
     constexpr int B32 = 2, B64 = 1;
     const dim3 g((unsigned)grid), b(kThreads);
-    const bool ws = job.wscale != nullptr;
-    if (job.WL == 32)
-        return ws ? launch_kernel(bp_qt_grid_kernel<32, B32, true>, g, b, 0, stream, job, q_stride, img_stride,
-                                  tiles_per_slice)
-                  : launch_kernel(bp_qt_grid_kernel<32, B32, false>, g, b, 0, stream, job, q_stride, img_stride,
-                                  tiles_per_slice);
-    if (job.WL == 64)
-        return ws ? launch_kernel(bp_qt_grid_kernel<64, B64, true>, g, b, 0, stream, job, q_stride, img_stride,
-                                  tiles_per_slice)
-                  : launch_kernel(bp_qt_grid_kernel<64, B64, false>, g, b, 0, stream, job, q_stride, img_stride,
-                                  tiles_per_slice);
+    const bool ws = job.wscale != nullptr, persist = grid < tot;
+#define FBP_QT_GRID(WP, BB)                                                                                       \
+    (persist ? (ws ? launch_kernel(bp_qt_grid_kernel<WP, BB, true, true>, g, b, 0, stream, job, q_stride,           \
+                                   img_stride, tiles_per_slice, tot)                                                \
+                   : launch_kernel(bp_qt_grid_kernel<WP, BB, false, true>, g, b, 0, stream, job, q_stride,          \
+                                   img_stride, tiles_per_slice, tot))                                               \
+             : (ws ? launch_kernel(bp_qt_grid_kernel<WP, BB, true, false>, g, b, 0, stream, job, q_stride,          \
+                                   img_stride, tiles_per_slice, tot)                                                \
+                   : launch_kernel(bp_qt_grid_kernel<WP, BB, false, false>, g, b, 0, stream, job, q_stride,         \
+                                   img_stride, tiles_per_slice, tot)))
+    if (job.WL == 32) return FBP_QT_GRID(32, B32);
+    if (job.WL == 64) return FBP_QT_GRID(64, B64);
+#undef FBP_QT_GRID
     return hipErrorInvalidValue;
 }
 

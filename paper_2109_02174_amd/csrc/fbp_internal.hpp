@@ -164,6 +164,9 @@ hipError_t launch_bp_qt_grid(const BpJob& job, int n_slices, size_t q_stride, si
                              int tiles_per_slice, hipStream_t stream);
 hipError_t launch_bp_qt_list(int WP, const BpListArgs* args, int grid, hipStream_t stream);
 
+// Compute units of the current device (cached; runtime.cpp).
+int current_device_cus();
+
 // ------------------------------------------------------------------ forward projector
 
 // Everything the projector (adjoint of the backprojector) needs for one geometry.

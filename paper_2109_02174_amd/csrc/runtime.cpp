@@ -1830,6 +1830,13 @@ int run_cone_backproject(const ConePlan& c, const float* filt, float* vol, hipSt
 }
 
 }  // namespace
+
+int current_device_cus() {
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return 256;
+    return cu_count(device);
+}
+
 }  // namespace fbp
 
 // ====================================================================== C ABI
