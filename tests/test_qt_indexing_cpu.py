@@ -3,12 +3,15 @@
 The kernel stages, per (tile, angle pair), a window of WP bins that starts one bin
 below the smallest ray coordinate of the tile, and reads bins j and (through the
 staged differences) j + 1 at j = trunc(u) of each pixel's FP32 local coordinate.
-This test restates in NumPy the host's window bound and pitch choice and the
+This file restates in NumPy the host's window bound and pitch choice and the
 kernel's FP64 window origins and FP32 coordinate arithmetic (fused multiply-adds
 rounded once), and asserts that every bin a pixel reads was staged: 0 <= j and
 j <= WP - 2 (the last bin of a window has no staged difference).  It covers the
 GPU test geometries and the benchmark workloads (512^2 / 720 angles / 725 bins,
-and the mixed-batch sides 256 ... 1024).  No GPU is involved.
+and the mixed-batch sides 256 ... 1024).  It also replays how the grid and list
+kernels hand tiles to workgroups (one per tile, or persistent workgroups taking
+per-XCD ranges) and checks that every tile is backprojected exactly once.  No GPU
+is involved.
 """
 import math
 
@@ -116,3 +119,67 @@ def test_replay_catches_a_pitch_too_small_for_the_window():
     assert WP == 64 and lo >= 1 and hi <= WP - 4
     _, _, hi32 = replay(K, D, N, dt, _uniform(K), WP=32)
     assert hi32 > 32 - 2
+
+
+def xcd_logical(b, G):
+    """The kernels' block -> logical item map: XCD b % 8 takes a contiguous range."""
+    x, slot = b & 7, b >> 3
+    per, extra = G >> 3, G & 7
+    return x * per + min(x, extra) + slot
+
+
+def grid_tiles(G, total, persist):
+    """Tiles each workgroup of the quarter-turn grid kernel visits, in order (a
+    restatement of its start / end / step choice)."""
+    out = []
+    for b in range(G):
+        if not persist or G >= total:
+            it = xcd_logical(b, G)
+            end, step = it + 1, 1
+        elif G % 8 == 0:
+            x, per = b & 7, G >> 3
+            it = (x * total >> 3) + (b >> 3)
+            end, step = (x + 1) * total >> 3, per
+        else:
+            it, end, step = b, total, G
+        seq = []
+        while it < end:
+            seq.append(it)
+            it += step
+        out.append(seq)
+    return out
+
+
+def test_xcd_logical_is_a_bijection():
+    for G in range(1, 600):
+        assert sorted(xcd_logical(b, G) for b in range(G)) == list(range(G))
+
+
+@pytest.mark.parametrize("cus", [256, 255, 248, 80, 8, 7, 1])
+@pytest.mark.parametrize("total", [1, 7, 64, 255, 256, 257, 1000, 256 * 16, 65536 + 3])
+def test_grid_kernel_visits_every_tile_once(cus, total):
+    """The host launches min(total, CUs) workgroups, persistent when that is fewer
+    than the tiles; every tile is then backprojected by exactly one workgroup, and
+    with a grid that is a multiple of 8 each XCD's tiles are one contiguous range."""
+    G = min(total, cus)
+    persist = G < total
+    seqs = grid_tiles(G, total, persist)
+    flat = sorted(t for s in seqs for t in s)
+    assert flat == list(range(total))
+    if persist and G % 8 == 0:
+        for x in range(8):
+            mine = sorted(t for b in range(x, G, 8) for t in seqs[b])
+            assert mine == list(range(x * total >> 3, (x + 1) * total >> 3))
+
+
+def test_list_kernel_visits_every_tile_once():
+    """The list kernels start at xcd_logical(block) and stride by the grid size."""
+    for G in (1, 7, 8, 255, 256):
+        for total in (0, 1, 5, 256, 1001):
+            seen = []
+            for b in range(G):
+                it = xcd_logical(b, G)
+                while it < total:
+                    seen.append(it)
+                    it += G
+            assert sorted(seen) == list(range(total))
