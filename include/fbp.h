@@ -31,6 +31,8 @@
  * FFT tables (first FBP_PREC_FP32_FFT call), the forward projector's padded
  * copies (first fbp_project call) and the cone-beam pre-weighting rows (first
  * fbp_cone_filter call).  Once those exist, no call allocates device memory.
+ * The library's one static device array, the FBP_NOALLOC_WORKSPACE_BYTES
+ * workspace of fbp_reconstruct_noalloc, exists on every GPU that loads it.
  *
  * Errors: arguments are validated on the host before any HIP call; a rejected
  * call has queued no work.  Launch failures are reported as FBP_EHIP.  Work is
@@ -64,7 +66,9 @@ typedef enum {
     FBP_ENOMEM = -2,        /* plan creation could not allocate device or host memory */
     FBP_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
     FBP_EUNSUPPORTED = -4,  /* valid but outside the supported range (e.g. geometry too large) */
-    FBP_EWORKSPACE = -5     /* workspace missing or smaller than the *_workspace_bytes query */
+    FBP_EWORKSPACE = -5,    /* workspace missing or smaller than the *_workspace_bytes query */
+    FBP_ENOTREADY = -6      /* fbp_reconstruct_noalloc: no plan or filter taps exist yet for the
+                               geometry and precision on this device (nothing was queued) */
 } fbp_status;
 
 /* Operand precision of the ramp-filter GEMM; accumulation is always FP32. */
@@ -175,6 +179,29 @@ int fbp_backproject(const fbp_geom* geom, int32_t n_slices, const float* d_filte
 int fbp_reconstruct(const fbp_geom* geom, int32_t n_slices, const float* d_sino, float* d_image,
                     void* d_workspace, size_t workspace_bytes, int32_t precision,
                     void* hip_stream);
+
+/* Size of the library's own workspace of fbp_reconstruct_noalloc (one per GPU). */
+#define FBP_NOALLOC_WORKSPACE_BYTES ((size_t)64 << 20)
+
+/*
+ * fbp_reconstruct for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the filtered rows go to a workspace inside the library, a static device
+ * array of FBP_NOALLOC_WORKSPACE_BYTES that each GPU the library runs on holds
+ * until the process ends, instead of a caller's buffer.  Same kernels, so
+ * bitwise equal to fbp_reconstruct with the same arguments.
+ * Calls no hipMalloc, hipFree or other allocating routine: the geometry's plan
+ * and the filter taps of `precision` must already exist on the current device
+ * (made by an earlier fbp_reconstruct or fbp_filter call with this geometry and
+ * precision), else FBP_ENOTREADY.  More than FBP_NOALLOC_WORKSPACE_BYTES of
+ * filtered rows (n_slices * K * D * 4 bytes) gives FBP_EWORKSPACE.  Both are
+ * returned before anything is queued.
+ * Every call on one GPU uses that GPU's one array and leaves its contents
+ * there: calls whose work can overlap on the device (unordered streams, other
+ * threads) race on it and give wrong images.  Order them on one stream.
+ */
+int fbp_reconstruct_noalloc(const fbp_geom* geom, int32_t n_slices, const float* d_sino, float* d_image,
+                            int32_t precision, void* hip_stream);
 
 /*
  * Forward projector, the exact adjoint of fbp_backproject (for iterative methods

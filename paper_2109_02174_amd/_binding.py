@@ -23,6 +23,8 @@ FBP_ENOMEM = -2
 FBP_EHIP = -3
 FBP_EUNSUPPORTED = -4
 FBP_EWORKSPACE = -5
+FBP_ENOTREADY = -6
+NOALLOC_WORKSPACE_BYTES = 64 << 20   # FBP_NOALLOC_WORKSPACE_BYTES
 
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2, "fft": 3}
 FILTERS = {"ramlak": 0, "shepp-logan": 1, "hann": 2}
@@ -82,6 +84,7 @@ def load():
         "fbp_cone_reconstruct": (ctypes.c_int, [ctypes.POINTER(c_cone_geom), vp, vp, vp, sz, vp]),
         "fbp_cone_workspace_bytes": (sz, [ctypes.POINTER(c_cone_geom)]),
         "fbp_reconstruct": (ctypes.c_int, [G, i32, vp, vp, vp, sz, i32, vp]),
+        "fbp_reconstruct_noalloc": (ctypes.c_int, [G, i32, vp, vp, i32, vp]),
         "fbp_workspace_bytes": (sz, [G, i32, i32]),
         "fbp_reconstruct_batch": (ctypes.c_int, [ctypes.POINTER(c_job), i32, vp, sz, i32, vp]),
         "fbp_batch_workspace_bytes": (sz, [ctypes.POINTER(c_job), i32, i32]),
@@ -281,6 +284,21 @@ def fbp_reconstruct(geom: Geometry, sino, out=None, workspace=None, precision="f
                                 workspace.data_ptr(), workspace.numel() * workspace.element_size(),
                                 _prec(precision), _stream_ptr(stream))
     _raise(rc, "fbp_reconstruct")
+    return out
+
+
+def fbp_reconstruct_noalloc(geom: Geometry, sino, out, precision="fp32", stream=None):
+    """fbp_reconstruct with the filtered rows in the library's static workspace:
+    allocates nothing (`out` is required), and needs the geometry's plan and the
+    precision's taps made by an earlier fbp_reconstruct or fbp_filter."""
+    n = sino.shape[0]
+    sshape, ishape = _shapes(geom, n)
+    _check_tensor(sino, sshape, "sino")
+    _check_tensor(out, ishape, "out")
+    g = geom.as_c()
+    rc = load().fbp_reconstruct_noalloc(ctypes.byref(g), n, sino.data_ptr(), out.data_ptr(),
+                                        _prec(precision), _stream_ptr(stream))
+    _raise(rc, "fbp_reconstruct_noalloc")
     return out
 
 

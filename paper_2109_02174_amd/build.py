@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfbp.so")
-SOURCES = ["bp_kernels.hip", "bp_qt_kernels.hip", "filter_kernels.hip", "project_kernels.hip", "fan_kernels.hip", "fft_kernels.hip", "cone_kernels.hip", "runtime.cpp"]
+SOURCES = ["bp_kernels.hip", "bp_qt_kernels.hip", "filter_kernels.hip", "project_kernels.hip", "fan_kernels.hip", "fft_kernels.hip", "cone_kernels.hip", "noalloc.hip", "runtime.cpp"]
 HEADERS = ["fbp_internal.hpp", os.path.join("..", "..", "include", "fbp.h")]
 ARCH = "gfx950"
 

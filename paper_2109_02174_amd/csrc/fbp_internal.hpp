@@ -331,4 +331,8 @@ hipError_t launch_gemm_list(int prec, bool full, const GemmListArgs* args, int g
 int gemm_lds_bytes(int prec, int Dh, bool full, int nb = 0);
 int gemm_occupancy(int prec, bool full, size_t lds_bytes);
 
+// Device address and size of fbp_reconstruct_noalloc's static workspace on the
+// current device (looked up once per device).
+hipError_t noalloc_workspace(void** ptr, size_t* bytes);
+
 }  // namespace fbp

@@ -660,6 +660,21 @@ int get_plan(const fbp_geom* g, Plan** out) {
     return FBP_OK;
 }
 
+// The existing plan of a validated geometry on the current device, never creating
+// one: FBP_ENOTREADY when there is none.
+int find_plan(const fbp_geom* g, Plan** out) {
+    int device = 0;
+    FBP_TRY_HIP(hipGetDevice(&device));
+    const GeomKey key = make_key(device, g);
+    Registry& R = registry();
+    std::lock_guard<std::mutex> lock(R.mu);
+    auto it = R.plans.find(key);
+    if (it == R.plans.end()) return FBP_ENOTREADY;
+    if (!angles_equal(*it->second, g)) return FBP_EUNSUPPORTED;
+    *out = it->second.get();
+    return FBP_OK;
+}
+
 // ------------------------------------------------------------------ filter taps
 
 uint16_t bf16_bits_rne(float x) {
@@ -864,6 +879,12 @@ BpJob bp_job(const Plan& p, const ShapeParams& sh, const float* filt, float* img
     j.split = 1;
     j.wscale = p.d_wscale;
     return j;
+}
+
+// Whether the filter tables of `prec` exist (ensure_taps made them).
+bool taps_ready(Plan* p, int prec) {
+    std::lock_guard<std::mutex> lock(p->mu);
+    return prec == kFFT32 ? p->d_fft_H != nullptr : p->d_taps[prec] != nullptr;
 }
 
 int hip_status(hipError_t e, const char* what) { return e == hipSuccess ? FBP_OK : hip_fail(e, what); }
@@ -1853,6 +1874,7 @@ const char* fbp_status_string(int status) {
         case FBP_EHIP: return "HIP runtime error";
         case FBP_EUNSUPPORTED: return "unsupported geometry or size";
         case FBP_EWORKSPACE: return "workspace missing or too small";
+        case FBP_ENOTREADY: return "no plan or filter taps for this geometry and precision yet";
         default: return "unknown status";
     }
 }
@@ -1933,6 +1955,33 @@ int fbp_reconstruct(const fbp_geom* geom, int32_t n_slices, const float* d_sino,
     if (rc == FBP_OK) rc = ensure_taps(p, precision);
     if (rc != FBP_OK) return rc;
     float* filt = static_cast<float*>(d_workspace);
+    const hipStream_t s = (hipStream_t)hip_stream;
+    rc = run_filter(*p, precision, n_slices, d_sino, filt, s);
+    if (rc == FBP_OK) rc = run_backproject(*p, p->one, p->stack, n_slices, filt, d_image, s);
+    return rc;
+}
+
+int fbp_reconstruct_noalloc(const fbp_geom* geom, int32_t n_slices, const float* d_sino, float* d_image,
+                            int32_t precision, void* hip_stream) {
+    int rc = check_geom(geom);
+    if (rc == FBP_OK) rc = check_prec(precision);
+    if (rc == FBP_OK) rc = check_slices(geom, n_slices);
+    if (rc != FBP_OK) return rc;
+    if (n_slices == 0) return FBP_OK;
+    if (!d_sino || !d_image || !aligned4(d_sino) || !aligned4(d_image)) return FBP_EINVAL;
+    const size_t sb = sino_bytes(geom, n_slices), ib = image_bytes(geom, n_slices);
+    if (overlaps(d_sino, sb, d_image, ib)) return FBP_EINVAL;
+    if (sb > FBP_NOALLOC_WORKSPACE_BYTES) return FBP_EWORKSPACE;
+    Plan* p = nullptr;
+    rc = find_plan(geom, &p);
+    if (rc != FBP_OK) return rc;
+    if (!taps_ready(p, precision)) return FBP_ENOTREADY;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    const hipError_t e = noalloc_workspace(&ws, &ws_bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress (static workspace)");
+    if (ws_bytes < sb) return FBP_EWORKSPACE;
+    float* filt = static_cast<float*>(ws);
     const hipStream_t s = (hipStream_t)hip_stream;
     rc = run_filter(*p, precision, n_slices, d_sino, filt, s);
     if (rc == FBP_OK) rc = run_backproject(*p, p->one, p->stack, n_slices, filt, d_image, s);

@@ -44,7 +44,7 @@ def test_header_symbols_exported(lib):
 
 def test_status_strings(lib):
     assert fbp.fbp_status_string(0) == "ok"
-    for code in (-1, -2, -3, -4, -5):
+    for code in (-1, -2, -3, -4, -5, -6):
         s = fbp.fbp_status_string(code)
         assert s and s != "unknown status"
     assert fbp.fbp_status_string(12345) == "unknown status"
@@ -260,3 +260,36 @@ def test_cone_pointer_checks(lib):
     assert lib.fbp_cone_reconstruct(gp, FAKE, FAKE2, FAKE3 + 4, 1 << 20, None) == B.FBP_EINVAL
     g.angles = None
     assert lib.fbp_cone_filter(gp, FAKE, FAKE2, None) == B.FBP_EINVAL
+
+
+def test_noalloc_workspace_size_matches_the_header():
+    text = open(HEADER).read()
+    m = re.search(r"#define FBP_NOALLOC_WORKSPACE_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m, "FBP_NOALLOC_WORKSPACE_BYTES not found in fbp.h"
+    assert B.NOALLOC_WORKSPACE_BYTES == int(m.group(1)) << int(m.group(2))
+    assert "FBP_ENOTREADY = -6" in text and B.FBP_ENOTREADY == -6
+
+
+def test_noalloc_static_workspace_lives_in_device_memory_of_the_library():
+    # the static workspace is a file-scope __device__ array: it occupies no space
+    # in the shared object itself (no initialiser), only on each GPU that loads it
+    assert os.path.getsize(B.LIB_PATH) < B.NOALLOC_WORKSPACE_BYTES // 8
+
+
+def test_noalloc_validation_before_any_hip_call(lib):
+    # every refusal below comes before the entry point touches HIP (no GPU here)
+    _, g = _geom(K=4, D=7, N=5)
+    gp = ctypes.byref(g)
+    f = lib.fbp_reconstruct_noalloc
+    assert f(gp, 0, None, None, 0, None) == B.FBP_OK
+    assert f(gp, -1, FAKE, FAKE2, 0, None) == B.FBP_EINVAL
+    assert f(gp, 1, None, FAKE2, 0, None) == B.FBP_EINVAL
+    assert f(gp, 1, FAKE, None, 0, None) == B.FBP_EINVAL
+    assert f(gp, 1, FAKE + 2, FAKE2, 0, None) == B.FBP_EINVAL       # misaligned
+    assert f(gp, 1, FAKE, FAKE + 4, 0, None) == B.FBP_EINVAL        # overlap
+    assert f(gp, 1, FAKE, FAKE2, 7, None) == B.FBP_EINVAL           # unknown precision
+    assert f(None, 1, FAKE, FAKE2, 0, None) == B.FBP_EINVAL
+    # filtered rows beyond the static workspace: n * K * D * 4 > 64 MiB
+    _, big = _geom(K=720, D=725, N=512)
+    n = B.NOALLOC_WORKSPACE_BYTES // (720 * 725 * 4)
+    assert f(ctypes.byref(big), n + 1, FAKE, 1 << 40, 0, None) == B.FBP_EWORKSPACE
