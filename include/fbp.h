@@ -107,8 +107,9 @@ typedef enum {
  *   the detector line through the centre along (-sin b_k, cos b_k).  R must
  *   exceed N / sqrt(2) (the source stays outside the image); weighting must be
  *   FBP_WEIGHT_UNIFORM.  Fan geometries run through fbp_filter, fbp_backproject,
- *   fbp_reconstruct and fbp_reconstruct_batch; fbp_autotune has nothing to tune
- *   for them (FBP_OK, tile id -1); the other entry points return FBP_EUNSUPPORTED.
+ *   fbp_reconstruct, fbp_reconstruct_noalloc and fbp_reconstruct_batch;
+ *   fbp_autotune has nothing to tune for them (FBP_OK, tile id -1); the other
+ *   entry points return FBP_EUNSUPPORTED.
  */
 typedef struct {
     int32_t n_angles;        /* K >= 1 */

@@ -327,8 +327,9 @@ struct GemmListArgs {
 hipError_t launch_gemm_list(int prec, bool full, const GemmListArgs* args, int grid, size_t lds_bytes,
                             hipStream_t stream);
 // LDS of a filter workgroup; full: the kernel has even taps too (their copies
-// double the tap area); nb: FP32 tiles of 32 nb output bins (0: the default 64).
-int gemm_lds_bytes(int prec, int Dh, bool full, int nb = 0);
+// double the tap area); nb: FP32 tiles of 32 nb output bins (0: the default 64);
+// cpb: FP32 chunks staged per panel barrier (1 or 2).
+int gemm_lds_bytes(int prec, int Dh, bool full, int nb = 0, int cpb = 1);
 int gemm_occupancy(int prec, bool full, size_t lds_bytes);
 
 // Device address and size of fbp_reconstruct_noalloc's static workspace on the

@@ -22,7 +22,8 @@
 // 16x16 MFMA block per 16 bins of that parity).
 // A ring of register buffers keeps several chunks of sinogram rows in flight
 // while the current one is multiplied; the LDS panel they are staged into is
-// double-buffered, so each chunk needs one barrier.
+// double-buffered, so each barrier step needs one barrier (FP32 two-group tiles
+// stage two chunks per step, the others one).
 //   FP32:       v_mfma_f32_16x16x4_f32, 32 inputs per parity per chunk.
 //   BF16/FP16:  v_mfma_f32_16x16x32_{bf16,f16}, 64 per parity per chunk; the rows
 //               are rounded to 16 bits (RNE) as they are staged, and the tap slice
@@ -162,16 +163,17 @@ __host__ __device__ constexpr int copy_stride32(int mpad, int hn) {
 // chunk on the shared panel, and group 1 hands its sums to group 0 through LDS.
 // Every accumulator sees the same MFMAs in the same order either way, so the two
 // forms give the same bits and the host may pick either per launch.
-template <bool FULL, bool CW, int NB, int G>
+template <bool FULL, bool CW, int NB, int G, int CPB>
 __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt, char* smem) {
     static_assert(G == 1 || G == 2, "groups");
+    static_assert(CPB == 1 || CPB == 2, "chunks per barrier");
     constexpr int HN = 16 * NB;                          // output bins per parity of the tile
     constexpr int NT = 256 * G;                          // threads
     constexpr int KS = kK32 / 4;                         // k-steps per chunk
     constexpr int NS = 2 / G;                            // accumulator sets per group
     constexpr int KG = KS / 2;                           // k-steps per set
-    float* As = reinterpret_cast<float*>(smem);          // [2 buffers][2 parity planes][32 rows][kAS32]
-    float* Tc = As + 2 * kABuf32;                        // 4 copies of the odd taps, then of the even taps
+    float* As = reinterpret_cast<float*>(smem);          // [2 buffers][CPB chunks][2 parity planes][32 rows][kAS32]
+    float* Tc = As + 2 * CPB * kABuf32;                  // 4 copies of the odd taps, then of the even taps
     const int tid = threadIdx.x;
     const int grp = G == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 8);
     const int t = tid & 255;                             // thread within its group
@@ -192,7 +194,8 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
     // with column weights (CW), that column's weight
     constexpr int EL = 2048 / NT;
     constexpr int RE = CW ? EL + 1 : EL;
-    float pf[kPD][RE];
+    constexpr int RP = CPB == 1 ? kPD : 3 * CPB;         // ring entries (chunks)
+    float pf[RP][RE];
     const __amdgpu_buffer_rsrc_t prow = tile_rows(P, m0, min(kTM, R - m0), D);
     const __amdgpu_buffer_rsrc_t wcol = col_weights(job);
     auto load = [&](float (&r)[RE], int c0) {   // columns c0 .. c0+63 of rows m0 .. m0+31
@@ -215,7 +218,7 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
     // the first chunks, the centre-tap inputs and the taps are all requested before
     // the first wait, so their memory latencies overlap
 #pragma unroll
-    for (int c = 0; c < kPD - 1; ++c) load(pf[c], c * 2 * kK32);
+    for (int c = 0; c < RP - CPB; ++c) load(pf[c], c * 2 * kK32);
     float pre[NB][4];
     if constexpr (!FULL) {
         if (grp == 0) {
@@ -262,45 +265,53 @@ __device__ __forceinline__ void gemm_tile_f32(const GemmJob& job, int mt, int nt
     const float* __restrict__ Ble = Te + cse * cstride + (xle - cse) + k0;
     const int nch = (D + 2 * kK32 - 1) / (2 * kK32);
     // every chunk load is issued unconditionally (chunks past the end read zeros),
-    // so the wait before a chunk's store covers only that chunk
-    for (int cb = 0; cb < nch; cb += kPD) {
+    // so the wait before a chunk's store covers only that chunk.  CPB chunks are
+    // stored per barrier; the ring holds RP - CPB chunks ahead of the ones stored.
+    for (int cb = 0; cb < nch; cb += RP) {
 #pragma unroll
-        for (int u = 0; u < kPD; ++u) {
+        for (int u = 0; u < RP; u += CPB) {
             const int c = cb + u;
-            load(pf[(u + kPD - 1) % kPD], (c + kPD - 1) * 2 * kK32);
-            // double-buffered panel: every wave finished chunk c - 2 (same buffer)
-            // before it passed the barrier of chunk c - 1, so one barrier suffices
-            const int ab = (c & 1) * kABuf32;
-            store(pf[u], As + ab);
+#pragma unroll
+            for (int i = 0; i < CPB; ++i) load(pf[(u + RP - CPB + i) % RP], (c + RP - CPB + i) * 2 * kK32);
+            // double-buffered panel: every wave finished the chunks of the step before
+            // the last (same buffer) before it passed the last step's barrier, so one
+            // barrier per step suffices
+            const int ab0 = ((c / CPB) & 1) * CPB * kABuf32;
+#pragma unroll
+            for (int i = 0; i < CPB; ++i) store(pf[u + i], As + ab0 + i * kABuf32);
             __syncthreads();
-            if (c < nch) {
-                const int mh0 = c * kK32;
-                // this group's k-steps of the chunk: A and B fragments (four floats each
-                // per set), then the MFMAs, the sets interleaved
-                auto product = [&](const float* arow_p, const float* brow_p) {
-                    float a[NS][KG], b[NS][NB][KG];
 #pragma unroll
-                    for (int h = 0; h < NS; ++h) {
-                        const float4 av = *reinterpret_cast<const float4*>(arow_p + ab + KG * h);
-                        a[h][0] = av.x; a[h][1] = av.y; a[h][2] = av.z; a[h][3] = av.w;
+            for (int i = 0; i < CPB; ++i) {
+                if (c + i < nch) {
+                    const int ab = ab0 + i * kABuf32;
+                    const int mh0 = (c + i) * kK32;
+                    // this group's k-steps of the chunk: A and B fragments (four floats each
+                    // per set), then the MFMAs, the sets interleaved
+                    auto product = [&](const float* arow_p, const float* brow_p) {
+                        float a[NS][KG], b[NS][NB][KG];
 #pragma unroll
-                        for (int j = 0; j < NB; ++j) {
-                            const float4 bv = *reinterpret_cast<const float4*>(brow_p + mh0 - 16 * j + KG * h);
-                            b[h][j][0] = bv.x; b[h][j][1] = bv.y; b[h][j][2] = bv.z; b[h][j][3] = bv.w;
+                        for (int h = 0; h < NS; ++h) {
+                            const float4 av = *reinterpret_cast<const float4*>(arow_p + ab + KG * h);
+                            a[h][0] = av.x; a[h][1] = av.y; a[h][2] = av.z; a[h][3] = av.w;
+#pragma unroll
+                            for (int j = 0; j < NB; ++j) {
+                                const float4 bv = *reinterpret_cast<const float4*>(brow_p + mh0 - 16 * j + KG * h);
+                                b[h][j][0] = bv.x; b[h][j][1] = bv.y; b[h][j][2] = bv.z; b[h][j][3] = bv.w;
+                            }
                         }
-                    }
-                    __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the MFMAs
+                        __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the MFMAs
 #pragma unroll
-                    for (int k = 0; k < KG; ++k)
+                        for (int k = 0; k < KG; ++k)
 #pragma unroll
-                        for (int h = 0; h < NS; ++h)
+                            for (int h = 0; h < NS; ++h)
 #pragma unroll
-                            for (int j = 0; j < NB; ++j)
-                                acc[h][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[h][k], b[h][j][k], acc[h][j], 0, 0, 0);
-                };
-                static_assert(KG == 4, "four k-steps per set");
-                product(Arow, Bl);
-                if constexpr (FULL) product(ArowS, Ble);
+                                for (int j = 0; j < NB; ++j)
+                                    acc[h][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[h][k], b[h][j][k], acc[h][j], 0, 0, 0);
+                    };
+                    static_assert(KG == 4, "four k-steps per set");
+                    product(Arow, Bl);
+                    if constexpr (FULL) product(ArowS, Ble);
+                }
             }
         }
     }
@@ -478,10 +489,10 @@ __device__ __forceinline__ void gemm_tile_16(const GemmJob& job, int mt, int nt,
 
 // One instantiation per (operand precision, kernel with or without even taps), so
 // the Ram-Lak path keeps its register budget.
-template <int PREC, bool FULL, bool CW = false, int NB = kNB, int G = 1>
+template <int PREC, bool FULL, bool CW = false, int NB = kNB, int G = 1, int CPB = 1>
 __device__ __forceinline__ void gemm_tile(const GemmJob& job, int mt, int nt, char* smem) {
     if constexpr (PREC == kFP32)
-        gemm_tile_f32<FULL, CW, NB, G>(job, mt, nt, smem);
+        gemm_tile_f32<FULL, CW, NB, G, CPB>(job, mt, nt, smem);
     else
         gemm_tile_16<PREC, FULL, CW>(job, mt, nt, smem);
 }
@@ -490,14 +501,15 @@ __device__ __forceinline__ void gemm_tile(const GemmJob& job, int mt, int nt, ch
 // unweighted filter's ring and stores as they were
 // NB: 16-wide MFMA blocks per wave and parity (2: 64-bin tiles; FP32 also 1: 32-bin, 3: 96-bin)
 // G: groups of four waves (FP32: 1 or 2)
-template <int PREC, bool FULL, bool CW, int NB, int G>
+// CPB: chunks staged per panel barrier (FP32: 1 or 2; the same bits)
+template <int PREC, bool FULL, bool CW, int NB, int G, int CPB>
 __global__ __launch_bounds__(kBpThreads * G) void gemm_grid_kernel(GemmJob job) {
     extern __shared__ float4 smem4[];
     // logical tile: column tiles fastest, so the tiles of one row block (which all read
     // that block's rows) run on one XCD and share its L2
     const int b = xcd_logical(blockIdx.x, gridDim.x);
     const int mt = b / job.tiles_n, nt = b - mt * job.tiles_n;
-    gemm_tile<PREC, FULL, CW, NB, G>(job, mt, nt, reinterpret_cast<char*>(smem4));
+    gemm_tile<PREC, FULL, CW, NB, G, CPB>(job, mt, nt, reinterpret_cast<char*>(smem4));
 }
 
 template <int PREC, bool FULL>
@@ -545,26 +557,42 @@ constexpr int gemm_key(int prec, bool full) { return prec * 2 + (full ? 1 : 0); 
 
 }  // namespace
 
-int gemm_lds_bytes(int prec, int Dh, bool full, int nb) {
+int gemm_lds_bytes(int prec, int Dh, bool full, int nb, int cpb) {
     const int tables = full ? 2 : 1;   // odd taps, and even taps for kernels that have them
     if (prec == kFP32) {
         const int mpad = (Dh + kK32 - 1) / kK32 * kK32;
-        // panel, four copies of each tap table
-        return (2 * kABuf32 + tables * 4 * copy_stride32(mpad, nb > 0 ? 16 * nb : kHalfN)) * 4;
+        // panel (two buffers of the cpb chunks of one barrier step), four copies of each tap table
+        return (2 * cpb * kABuf32 + tables * 4 * copy_stride32(mpad, nb > 0 ? 16 * nb : kHalfN)) * 4;
     }
     const int mpad = (Dh + kK16 - 1) / kK16 * kK16;
     return (2 * kABuf16 + tables * 8 * ((mpad + kHalfN + 8 + 7 + 7) & ~7)) * 2;
 }
 
-// FP32 grid launch with the tile width (NB) and group count (G) as template arguments.
-template <int NB, int G>
+constexpr size_t kMaxLdsBytes = 160 * 1024;   // LDS of one gfx950 CU
+
+// FP32 grid launch with the tile width (NB), group count (G) and chunks per barrier
+// (CPB) as template arguments.
+template <int NB, int G, int CPB>
 hipError_t launch_f32(const GemmJob& job, dim3 g, size_t lds, hipStream_t stream) {
     const dim3 b(kBpThreads * G);
     if (job.full)
-        return job.colw ? launch_kernel(gemm_grid_kernel<kFP32, true, true, NB, G>, g, b, lds, stream, job)
-                        : launch_kernel(gemm_grid_kernel<kFP32, true, false, NB, G>, g, b, lds, stream, job);
-    return job.colw ? launch_kernel(gemm_grid_kernel<kFP32, false, true, NB, G>, g, b, lds, stream, job)
-                    : launch_kernel(gemm_grid_kernel<kFP32, false, false, NB, G>, g, b, lds, stream, job);
+        return job.colw ? launch_kernel(gemm_grid_kernel<kFP32, true, true, NB, G, CPB>, g, b, lds, stream, job)
+                        : launch_kernel(gemm_grid_kernel<kFP32, true, false, NB, G, CPB>, g, b, lds, stream, job);
+    return job.colw ? launch_kernel(gemm_grid_kernel<kFP32, false, true, NB, G, CPB>, g, b, lds, stream, job)
+                    : launch_kernel(gemm_grid_kernel<kFP32, false, false, NB, G, CPB>, g, b, lds, stream, job);
+}
+
+// Two-group tiles (small grids) stage two chunks per barrier where that panel still
+// fits the CU's LDS with the tap copies (long detectors with even taps do not).
+template <int NB>
+hipError_t launch_f32_groups(const GemmJob& job, dim3 g, hipStream_t stream) {
+    const bool full = job.full != 0;
+    if (job.groups == 2) {
+        const size_t lds2 = (size_t)gemm_lds_bytes(kFP32, job.Dh, full, job.nb, 2);
+        if (lds2 <= kMaxLdsBytes) return launch_f32<NB, 2, 2>(job, g, lds2, stream);
+        return launch_f32<NB, 2, 1>(job, g, (size_t)gemm_lds_bytes(kFP32, job.Dh, full, job.nb, 1), stream);
+    }
+    return launch_f32<NB, 1, 1>(job, g, (size_t)gemm_lds_bytes(kFP32, job.Dh, full, job.nb, 1), stream);
 }
 
 hipError_t launch_gemm_grid(int prec, const GemmJob& job, hipStream_t stream) {
@@ -574,20 +602,19 @@ hipError_t launch_gemm_grid(int prec, const GemmJob& job, hipStream_t stream) {
     if (nb != kNB && (prec != kFP32 || nb > 3 || job.tiles_n != (job.D + 32 * nb - 1) / (32 * nb)))
         return hipErrorInvalidValue;
     if (job.groups != 1 && (prec != kFP32 || job.groups != 2)) return hipErrorInvalidValue;
-    const size_t lds = (size_t)gemm_lds_bytes(prec, job.Dh, job.full != 0, job.nb);
     const dim3 g(grid);
     if (prec == kFP32) {
-        const bool g2 = job.groups == 2;
-        if (nb == 1) return g2 ? launch_f32<1, 2>(job, g, lds, stream) : launch_f32<1, 1>(job, g, lds, stream);
-        if (nb == 3) return g2 ? launch_f32<3, 2>(job, g, lds, stream) : launch_f32<3, 1>(job, g, lds, stream);
-        return g2 ? launch_f32<kNB, 2>(job, g, lds, stream) : launch_f32<kNB, 1>(job, g, lds, stream);
+        if (nb == 1) return launch_f32_groups<1>(job, g, stream);
+        if (nb == 3) return launch_f32_groups<3>(job, g, stream);
+        return launch_f32_groups<kNB>(job, g, stream);
     }
+    const size_t lds = (size_t)gemm_lds_bytes(prec, job.Dh, job.full != 0, job.nb);
     const dim3 b(kBpThreads);
     switch (gemm_key(prec, job.full != 0)) {
 #define X(p, f)                                                                                              \
         case gemm_key(p, f):                                                                                     \
-            return job.colw ? launch_kernel(gemm_grid_kernel<p, f, true, kNB, 1>, g, b, lds, stream, job) \
-                            : launch_kernel(gemm_grid_kernel<p, f, false, kNB, 1>, g, b, lds, stream, job);
+            return job.colw ? launch_kernel(gemm_grid_kernel<p, f, true, kNB, 1, 1>, g, b, lds, stream, job) \
+                            : launch_kernel(gemm_grid_kernel<p, f, false, kNB, 1, 1>, g, b, lds, stream, job);
         FBP_FOR_EACH_GEMM16(X)
 #undef X
         default: return hipErrorInvalidValue;
