@@ -122,3 +122,31 @@ def test_refusals_queue_nothing():
     assert e.value.status == fbp.FBP_EWORKSPACE
     torch.cuda.synchronize()
     assert float(out.abs().max()) == 0.0 and float(ob.abs().max()) == 0.0
+
+
+def test_replays_of_a_captured_graph_match_eager_calls():
+    # the callers this entry point is for: work captured into a HIP graph, where no
+    # allocation may happen.  Each replay, with eager work and synchronisations in
+    # between, must give the eager images bit for bit.
+    g = fbp.Geometry(360, 365, 256, 1.0)
+    s = dev(_stack(76, 2, 256, 360, 365))
+    ref = _alone(g, s, "fp32")
+    out = torch.zeros_like(ref)
+    fbp.fbp_reconstruct_noalloc(g, s, out)     # first call on the device outside the capture
+    torch.cuda.synchronize()
+    assert _bitwise(out, ref)
+    side = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        out.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=side):
+            fbp.fbp_reconstruct_noalloc(g, s, out)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out.fill_(float(rep + 1))
+        _ = _alone(g, s, "fp32")               # eager work between the replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert _bitwise(out, ref), f"replay {rep}"
