@@ -303,17 +303,32 @@ def fbp_reconstruct_noalloc(geom: Geometry, sino, out, precision="fp32", stream=
 
 
 def _jobs_array(jobs):
-    """jobs: sequence of (Geometry, sino[K][D] tensor, image[N][N] tensor)."""
+    """jobs: sequence of (Geometry, sino[K][D] tensor, image[N][N] tensor).  Jobs that
+    share a Geometry object share its C struct (and so its angle array)."""
+    import torch
     arr = (c_job * max(len(jobs), 1))()
     keep = []
+    per_geom = {}
+    f32 = torch.float32
     for i, (geom, sino, img) in enumerate(jobs):
-        _check_tensor(sino, (geom.n_angles, geom.n_det), f"jobs[{i}].sino")
-        _check_tensor(img, (geom.image_size, geom.image_size), f"jobs[{i}].image")
-        g = geom.as_c()
-        keep.append(g)
-        arr[i].geom = g
-        arr[i].sino = sino.data_ptr()
-        arr[i].image = img.data_ptr()
+        ent = per_geom.get(id(geom))
+        if ent is None:
+            g = geom.as_c()
+            ent = (g, (geom.n_angles, geom.n_det), (geom.image_size, geom.image_size))
+            per_geom[id(geom)] = ent
+            keep.append((geom, g))
+        g, sshape, ishape = ent
+        # the checks of _check_tensor, inlined; the named error comes from it
+        if not (isinstance(sino, torch.Tensor) and sino.dtype == f32 and sino.is_cuda and sino.is_contiguous()
+                and sino.shape == sshape):
+            _check_tensor(sino, sshape, f"jobs[{i}].sino")
+        if not (isinstance(img, torch.Tensor) and img.dtype == f32 and img.is_cuda and img.is_contiguous()
+                and img.shape == ishape):
+            _check_tensor(img, ishape, f"jobs[{i}].image")
+        job = arr[i]
+        job.geom = g
+        job.sino = sino.data_ptr()
+        job.image = img.data_ptr()
     return arr, keep
 
 

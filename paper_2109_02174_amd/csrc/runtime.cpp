@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -1106,12 +1107,30 @@ BatchLayout batch_layout(const fbp_job* jobs, int32_t n) {
     return L;
 }
 
+// Index of the first of jobs[0 .. n) with each distinct geometry struct (bytewise:
+// the same fields and the same angle array), so that a batch checks each geometry
+// and looks up its plan once; first[i] = i for the first job of a geometry.
+std::vector<int32_t> first_of_geometry(const fbp_job* jobs, int32_t n) {
+    using Bytes = std::array<unsigned char, sizeof(fbp_geom)>;
+    std::map<Bytes, int32_t> seen;
+    std::vector<int32_t> first((size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        Bytes b;
+        std::memcpy(b.data(), &jobs[i].geom, sizeof(fbp_geom));
+        first[(size_t)i] = seen.emplace(b, i).first->second;
+    }
+    return first;
+}
+
 int check_jobs(const fbp_job* jobs, int32_t n) {
     if (n < 0) return FBP_EINVAL;
     if (n > 0 && !jobs) return FBP_EINVAL;
+    const std::vector<int32_t> first = first_of_geometry(jobs, n);
     for (int32_t i = 0; i < n; ++i) {
-        const int rc = check_geom(&jobs[i].geom);
-        if (rc != FBP_OK) return rc;
+        if (first[(size_t)i] == i) {
+            const int rc = check_geom(&jobs[i].geom);
+            if (rc != FBP_OK) return rc;
+        }
         if (!jobs[i].sino || !jobs[i].image) return FBP_EINVAL;
         if (!aligned4(jobs[i].sino) || !aligned4(jobs[i].image)) return FBP_EINVAL;
         if (overlaps(jobs[i].sino, sino_bytes(&jobs[i].geom, 1), jobs[i].image,
@@ -1270,7 +1289,13 @@ int reconstruct_batch_parallel(const fbp_job* jobs, int32_t n, const BatchLayout
                                hipStream_t s) {
     int rc = FBP_OK;
     std::vector<Plan*> plans((size_t)n);
+    const std::vector<int32_t> first = first_of_geometry(jobs, n);
     for (int32_t i = 0; i < n; ++i) {
+        const int32_t f = first[(size_t)i];
+        if (f < i) {   // the same geometry struct as an earlier job: its plan
+            plans[(size_t)i] = plans[(size_t)f];
+            continue;
+        }
         rc = get_plan(&jobs[i].geom, &plans[(size_t)i]);
         if (rc == FBP_OK) rc = ensure_taps(plans[(size_t)i], prec);
         if (rc != FBP_OK) return rc;
@@ -1428,14 +1453,20 @@ int reconstruct_batch(const fbp_job* jobs, int32_t n, void* ws, size_t ws_bytes,
     const BatchLayout L = batch_layout(jobs, n);
     if (!ws || ws_bytes < L.total) return FBP_EWORKSPACE;
     if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return FBP_EINVAL;
+    std::vector<std::pair<uintptr_t, size_t>> imgs((size_t)n);
     for (int32_t i = 0; i < n; ++i) {
         if (overlaps(ws, L.total, jobs[i].sino, sino_bytes(&jobs[i].geom, 1)) ||
             overlaps(ws, L.total, jobs[i].image, image_bytes(&jobs[i].geom, 1)))
             return FBP_EINVAL;
-        for (int32_t j = 0; j < i; ++j)   // images must not overlap each other
-            if (overlaps(jobs[i].image, image_bytes(&jobs[i].geom, 1), jobs[j].image,
-                         image_bytes(&jobs[j].geom, 1)))
-                return FBP_EINVAL;
+        imgs[(size_t)i] = {reinterpret_cast<uintptr_t>(jobs[i].image), image_bytes(&jobs[i].geom, 1)};
+    }
+    // images must not overlap each other: in address order each starts at or past
+    // the furthest end of those before it
+    std::sort(imgs.begin(), imgs.end());
+    uintptr_t end = 0;
+    for (const auto& iv : imgs) {
+        if (iv.first < end) return FBP_EINVAL;
+        end = std::max(end, iv.first + iv.second);
     }
     std::vector<fbp_job> par;
     std::vector<int32_t> fan;
@@ -1899,8 +1930,9 @@ size_t fbp_workspace_bytes(const fbp_geom* geom, int32_t n_slices, int32_t preci
 
 size_t fbp_batch_workspace_bytes(const fbp_job* jobs, int32_t n_jobs, int32_t precision) {
     if (check_prec(precision) != FBP_OK || precision == kFFT32 || n_jobs < 0 || (n_jobs > 0 && !jobs)) return 0;
+    const std::vector<int32_t> first = first_of_geometry(jobs, n_jobs);
     for (int32_t i = 0; i < n_jobs; ++i)
-        if (check_geom(&jobs[i].geom) != FBP_OK) return 0;
+        if (first[(size_t)i] == i && check_geom(&jobs[i].geom) != FBP_OK) return 0;
     return batch_layout(jobs, n_jobs).total;
 }
 

@@ -163,6 +163,38 @@ def test_batch_validation(lib):
     assert lib.fbp_reconstruct_batch(jobs, 2, 0x400000, need, 0, None) == B.FBP_EINVAL
 
 
+def test_batch_validation_over_many_jobs(lib):
+    # 64 jobs sharing two geometry structs: every refusal still comes before any HIP
+    # call, whichever job carries the fault and wherever in the list it sits
+    ang = np.zeros(4)
+    angp = ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    n = 64
+    jobs = (B.c_job * n)()
+    img_bytes = 5 * 5 * 4
+    for i, j in enumerate(jobs):
+        j.geom = B.c_geom(4, 7, 5, 1.0 if i % 2 else 2.0, angp)
+        j.sino = 0x1000000 + 256 * i
+        j.image = 0x2000000 + 256 * i          # 100-byte images, 256 bytes apart
+    need = lib.fbp_batch_workspace_bytes(jobs, n, 0)
+    assert need > 0
+    ws = 0x4000000
+    # an overlap between two jobs far apart in the list (not neighbours in input order)
+    jobs[50].image = jobs[10].image + img_bytes - 4
+    assert lib.fbp_reconstruct_batch(jobs, n, ws, need, 0, None) == B.FBP_EINVAL
+    jobs[50].image = jobs[10].image + img_bytes   # touching is not overlapping
+    jobs[11].image = 0x3000000
+    # one job of a repeated geometry made invalid (a struct of its own): still refused
+    bad = B.c_geom(4, 7, 5, float("nan"), angp)
+    jobs[33].geom = bad
+    assert lib.fbp_batch_workspace_bytes(jobs, n, 0) == 0
+    assert lib.fbp_reconstruct_batch(jobs, n, ws, need, 0, None) == B.FBP_EINVAL
+    jobs[33].geom = B.c_geom(4, 7, 5, 1.0, angp)
+    # non-finite angle in the array every job shares
+    ang[2] = float("inf")
+    assert lib.fbp_reconstruct_batch(jobs, n, ws, need, 0, None) == B.FBP_EINVAL
+    ang[2] = 0.0
+
+
 def test_autotune_and_plan_validation(lib):
     assert lib.fbp_autotune(None, None, None) == B.FBP_EINVAL
     assert lib.fbp_plan_config(None) == B.FBP_EINVAL
