@@ -107,9 +107,9 @@ typedef enum {
  *   the detector line through the centre along (-sin b_k, cos b_k).  R must
  *   exceed N / sqrt(2) (the source stays outside the image); weighting must be
  *   FBP_WEIGHT_UNIFORM.  Fan geometries run through fbp_filter, fbp_backproject,
- *   fbp_reconstruct, fbp_reconstruct_noalloc and fbp_reconstruct_batch;
- *   fbp_autotune has nothing to tune for them (FBP_OK, tile id -1); the other
- *   entry points return FBP_EUNSUPPORTED.
+ *   fbp_reconstruct, fbp_reconstruct_noalloc, fbp_reconstruct_batch and
+ *   fbp_project; fbp_autotune has nothing to tune for them (FBP_OK, tile id -1);
+ *   the other entry points return FBP_EUNSUPPORTED.
  */
 typedef struct {
     int32_t n_angles;        /* K >= 1 */
@@ -212,6 +212,11 @@ int fbp_reconstruct_noalloc(const fbp_geom* geom, int32_t n_slices, const float*
  * geom->weighting.  d_image is [n_slices][N][N], d_sino [n_slices][K][D]; no
  * overlap.  Gather-only (one lane per detector bin), no atomics, deterministic;
  * <fbp_project(x), y> = <x, fbp_backproject(y)> up to FP32 rounding.
+ * Fan beam: the adjoint of the fan-beam fbp_backproject,
+ *   d_sino[b][k][j] = (2 pi / K) sum_X d_image[b](X) (R/L_k)^2 max(0, 1 - |s_k(X)/dt + (D-1)/2 - j|),
+ * with L_k and s_k as there; FBP_EUNSUPPORTED when the detector reaches the
+ * source distance ((D-1) dt / 2 >= R) or the source is too close to the image for
+ * the projector's window bound.
  */
 int fbp_project(const fbp_geom* geom, int32_t n_slices, const float* d_image, float* d_sino,
                 void* hip_stream);

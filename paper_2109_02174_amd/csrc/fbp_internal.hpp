@@ -190,11 +190,42 @@ struct ProjLayout {
     bool fast3 = false;
     int pad = 0, pitch = 0;
     size_t slice_floats = 0;   // floats of the two padded planes of one slice
+    double margin = 0.0;       // fan beam: the margin its window bound holds on
 };
 ProjLayout project_layout(const double* cs, int K, int N);
 hipError_t launch_project(const ProjJob& job, int n_slices, hipStream_t stream);
 // Padded row and column copies of n N x N slices into out (n * slice_floats floats).
 hipError_t launch_pad(const float* img, float* out, int N, int pad, int pitch, int n_slices, hipStream_t stream);
+
+// Fan-beam forward projector (the adjoint of the fan-beam backprojector), reading
+// the same padded copies.
+struct FanProjJob {
+    const float* pimg;    // padded copies, [n][2][N+1][pitch] (launch_pad)
+    float* sino;          // [n][K][D]
+    const double* cs;     // [K][2]: cos b, sin b (FP64)
+    double R, ds;         // source distance, bin width
+    double half_pix;      // (N-1)/2
+    double centre_det;    // (D-1)/2
+    double margin;        // m: window half-widths are bounded over each line grown by m pixels
+    int32_t N, K, D;
+    int32_t pad, pitch;
+    float scale;          // 2 pi / K
+};
+// Half-width (pixels along image line lc, a row when `rows`, else a column)
+// bounding 1 / |du/dq|, the spacing of neighbouring rays of view (cb, sb) along
+// the line, over the line's pixels and `margin` pixels beyond both ends:
+//     rows:    1/|du/dx| = ds L^2 / (R |y - R sb|),  columns: ds L^2 / (R |R cb - x|),
+// L = R - x cb - y sb largest at the far end of the grown line.  Inflated by
+// 2^-12 (relative and absolute) so that FP32 evaluation still bounds it; the same
+// function sizes the layout on the host and the windows in the kernel.
+template <typename F>
+__host__ __device__ inline F fan_line_half_width(F cb, F sb, F R, F ds, F half_pix, F margin, F lc, bool rows) {
+    const F ext = half_pix + F(0.5) + margin;
+    const F across = rows ? fabs(lc - R * sb) : fabs(R * cb - lc);
+    const F Lmax = rows ? R + ext * fabs(cb) - lc * sb : R + ext * fabs(sb) - lc * cb;
+    return ds * Lmax * Lmax / (R * across) * F(1.000244140625) + F(0.000244140625);
+}
+hipError_t launch_fan_project(const FanProjJob& job, int n_slices, hipStream_t stream);
 
 // ------------------------------------------------------------------ fan beam
 

@@ -181,6 +181,70 @@ __global__ __launch_bounds__(kProjThreads) void project_kernel(ProjJob job) {
     }
 }
 
+// Fan-beam forward projector: the adjoint of the fan-beam backprojection
+//     img(X) = (2 pi / K) sum_k (R / L_k)^2 Q~_k(u_k(X)),  L_k = R - (x cos b_k + y sin b_k),
+//     u_k(X) = R (-x sin b_k + y cos b_k) / (L_k ds) + (D-1)/2
+// (Kak & Slaney 1988, ch. 3), i.e.
+//     sino[k][j] = (2 pi / K) sum_X img(X) (R / L_k)^2 max(0, 1 - |u_k(X) - j|).
+// One lane per (view, bin), walking image lines across the rays (rows when
+// |sin b| >= |cos b|, else columns) in the padded copies.  On a line u - j = E / L
+// with E and L linear in the position q along the line, so the bin's ray crosses
+// the line at q* = -E(0) / E'.  Every pixel with a nonzero weight lies within r of
+// q*, r bounding the ray spacing 1 / |du/dq| on the line grown by a margin m >= r
+// (fan_line_half_width; the same for the whole block, one view and one line):
+// T = floor(2r) + 1 taps from floor(q* - r) + 1.  Each tap's weight comes from the
+// exact E and L at that pixel (FP64 at the line's first tap, FP32 steps after
+// it), so pixels the window takes in beyond the neighbouring rays weigh zero.
+// Each bin is written once by its lane, summed line by line in a fixed order; no
+// atomics.
+__global__ __launch_bounds__(kProjThreads) void fan_project_kernel(FanProjJob job) {
+    const int nbj = (job.D + kProjThreads - 1) / kProjThreads;
+    const int rest = blockIdx.x / nbj;
+    const int k = rest % job.K;                     // view
+    const int s = rest / job.K;                     // slice
+    const int j = (blockIdx.x - rest * nbj) * kProjThreads + threadIdx.x;
+    if (j >= job.D) return;                         // no barrier follows
+    const int N = job.N;
+    const double cb = job.cs[2 * k], sb = job.cs[2 * k + 1];
+    const double R = job.R, hp = job.half_pix;
+    const bool rows = fabs(sb) >= fabs(cb);
+    // u - j = E / L, E = Ea + Ex x + Ey y
+    const double g = job.centre_det - (double)j;
+    const double Ea = g * R;
+    const double Ex = -R * sb / job.ds - g * cb, Ey = R * cb / job.ds - g * sb;
+    const double Eq = rows ? Ex : Ey, El = rows ? Ey : Ex;      // along the line, across lines
+    const double Lq = rows ? -cb : -sb, Ll = rows ? -sb : -cb;
+    const double inv_Eq = 1.0 / Eq;
+    const double q_off = (double)job.pad + hp;      // padded index of line coordinate 0
+    const size_t plane = (size_t)(N + 1) * job.pitch;
+    const float* __restrict__ line = job.pimg + (size_t)s * 2 * plane + (rows ? 0 : plane);
+    const float Eq32 = (float)Eq, Lq32 = (float)Lq, R32 = (float)R;
+    const float cb32 = (float)cb, sb32 = (float)sb, ds32 = (float)job.ds, hp32 = (float)hp,
+                m32 = (float)job.margin;
+    float acc = 0.0f;
+    for (int l = 0; l < N; ++l, line += job.pitch) {
+        const double lc = (double)l - hp;
+        const float r = fan_line_half_width<float>(cb32, sb32, R32, ds32, hp32, m32, (float)lc, rows);
+        const int T = (int)(2.0f * r) + 1;          // floor(2r) + 1 (r > 0)
+        const double qs = -(Ea + El * lc) * inv_Eq;
+        // first tap, clamped into the padded line: a window that leaves the line lies
+        // wholly in its zero padding (pad >= T), which the clamped window reads instead
+        const int st = (int)fmin(fmax(floor(qs + q_off - (double)r) + 1.0, 0.0), (double)(job.pitch - T));
+        const double q0 = (double)st - q_off;
+        const float E0 = (float)(Ea + Eq * q0 + El * lc);
+        const float L0 = (float)(R + Lq * q0 + Ll * lc);
+        const float* __restrict__ px = line + st;
+        for (int m = 0; m < T; ++m) {
+            const float E = fmaf((float)m, Eq32, E0);
+            const float inv = __builtin_amdgcn_rcpf(fmaf((float)m, Lq32, L0));
+            const float w = fmaxf(0.0f, 1.0f - fabsf(E * inv));
+            const float rl = R32 * inv;
+            acc = fmaf(w * rl * rl, px[m], acc);
+        }
+    }
+    job.sino[((size_t)s * job.K + k) * job.D + j] = acc * job.scale;
+}
+
 // Padded copies of n slices: per slice, plane 0 holds the rows and plane 1 the
 // columns (transposed), each of N+1 lines of `pitch` floats: line l < N holds
 // pixel p of the line at index pad + p, zeros elsewhere; line N is all zeros.
@@ -262,6 +326,14 @@ hipError_t launch_project(const ProjJob& job, int n_slices, hipStream_t stream) 
         case 4: return launch_kernel(project_kernel<4, false>, grid, block, 0, stream, job);
         default: return launch_kernel(project_kernel<0, false>, grid, block, 0, stream, job);
     }
+}
+
+hipError_t launch_fan_project(const FanProjJob& job, int n_slices, hipStream_t stream) {
+    if (n_slices <= 0) return hipSuccess;
+    if (job.pad < 1 || job.pitch < job.N + 2 * job.pad) return hipErrorInvalidValue;
+    const int64_t blocks = (int64_t)((job.D + kProjThreads - 1) / kProjThreads) * job.K * n_slices;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    return launch_kernel(fan_project_kernel, dim3((unsigned)blocks), dim3(kProjThreads), 0, stream, job);
 }
 
 hipError_t launch_pad(const float* img, float* out, int N, int pad, int pitch, int n_slices, hipStream_t stream) {

@@ -564,6 +564,45 @@ int make_fan_plan(Plan* p) {
     return FBP_OK;
 }
 
+// Padded-copy layout of the fan-beam projector: the bound r on every line's ray
+// spacing must hold on the line grown by a margin m >= r (so a bin whose ray
+// crosses the grown line outside it has no pixel of the image in its window); m
+// is raised until it does.  T = 0: unsupported (a detector reaching R or beyond,
+// whose outer rays can run along the walked lines, or a source so close to the
+// image that no margin works).
+ProjLayout fan_project_layout(const Plan& p) {
+    ProjLayout L;
+    if (!(0.5 * (double)(p.D - 1) * p.dt < p.R)) return L;
+    const double hp = 0.5 * (double)(p.N - 1);
+    double m = 2.0, r_max = -1.0;
+    for (int it = 0; it < 12 && r_max < 0.0; ++it) {
+        double r_all = 0.0;
+        for (double b : p.angles) {
+            const double cb = std::cos(b), sb = std::sin(b);
+            const bool rows = std::fabs(sb) >= std::fabs(cb);
+            const double ext = hp + 0.5 + m;
+            for (int l = 0; l < p.N; ++l) {
+                const double lc = (double)l - hp;
+                // the source stays beyond the grown line (L > 0 all along it)
+                const double Lmin = rows ? p.R - ext * std::fabs(cb) - lc * sb : p.R - ext * std::fabs(sb) - lc * cb;
+                if (!(Lmin > 0.0)) return L;
+                r_all = std::max(r_all, fan_line_half_width<double>(cb, sb, p.R, p.dt, hp, m, lc, rows));
+            }
+        }
+        if (!(r_all < 1024.0)) return L;
+        if (r_all <= m) r_max = r_all;
+        else m = std::ceil(r_all) + 1.0;
+    }
+    if (!(r_max > 0.0)) return L;
+    const int T = (int)std::floor(2.0 * r_max) + 1;
+    L.T = T;
+    L.margin = m;
+    L.pad = T + 2;                       // >= every line's tap count, whatever its rounding
+    L.pitch = p.N + 2 * L.pad;
+    L.slice_floats = (size_t)2 * (size_t)(p.N + 1) * (size_t)L.pitch;
+    return L;
+}
+
 // Look up or create the plan of a validated geometry on the current device.
 int get_plan(const fbp_geom* g, Plan** out) {
     int device = 0;
@@ -2024,17 +2063,17 @@ int fbp_project(const fbp_geom* geom, int32_t n_slices, const float* d_image, fl
     int rc = check_geom(geom);
     if (rc == FBP_OK) rc = check_slices(geom, n_slices);
     if (rc != FBP_OK) return rc;
-    if (is_fan(geom)) return FBP_EUNSUPPORTED;
     if (n_slices == 0) return FBP_OK;
     if (!d_image || !d_sino || !aligned4(d_image) || !aligned4(d_sino)) return FBP_EINVAL;
     if (overlaps(d_image, image_bytes(geom, n_slices), d_sino, sino_bytes(geom, n_slices))) return FBP_EINVAL;
     Plan* p = nullptr;
     rc = get_plan(geom, &p);
     if (rc != FBP_OK) return rc;
+    const bool fan = p->R > 0.0;
     ProjScratch& ps = p->proj;
     std::lock_guard<std::mutex> lock(ps.mu);
     if (!ps.ptr) {
-        ps.layout = project_layout(p->cs.data(), p->K, p->N);
+        ps.layout = fan ? fan_project_layout(*p) : project_layout(p->cs.data(), p->K, p->N);
         if (ps.layout.T == 0) return FBP_EUNSUPPORTED;
         const size_t slice_bytes = sizeof(float) * ps.layout.slice_floats;
         const int slices = (int)std::max<size_t>(1, std::min<size_t>(16, ((size_t)256 << 20) / slice_bytes));
@@ -2050,28 +2089,55 @@ int fbp_project(const fbp_geom* geom, int32_t n_slices, const float* d_image, fl
     const hipStream_t s = (hipStream_t)hip_stream;
     const ProjLayout& L = ps.layout;
     ProjJob j{};
-    j.pimg = ps.ptr;
-    j.cs = p->d_cs;
-    j.wscale = p->d_wscale;
-    j.half_pix = 0.5 * (double)(p->N - 1);
-    j.centre_det = 0.5 * (double)(p->D - 1);
-    j.N = p->N;
-    j.K = p->K;
-    j.D = p->D;
-    j.scale = (float)(kPi / (double)p->K);
-    j.T = L.T;
-    j.fast3 = L.fast3 ? 1 : 0;
-    j.pad = L.pad;
-    j.pitch = L.pitch;
+    FanProjJob fj{};
+    if (fan) {
+        fj.pimg = ps.ptr;
+        fj.cs = p->d_fcs;
+        fj.R = p->R;
+        fj.ds = p->dt;
+        fj.half_pix = 0.5 * (double)(p->N - 1);
+        fj.centre_det = 0.5 * (double)(p->D - 1);
+        fj.margin = L.margin;
+        fj.N = p->N;
+        fj.K = p->K;
+        fj.D = p->D;
+        fj.pad = L.pad;
+        fj.pitch = L.pitch;
+        fj.scale = (float)(2.0 * kPi / (double)p->K);
+    } else {
+        j.pimg = ps.ptr;
+        j.cs = p->d_cs;
+        j.wscale = p->d_wscale;
+        j.half_pix = 0.5 * (double)(p->N - 1);
+        j.centre_det = 0.5 * (double)(p->D - 1);
+        j.N = p->N;
+        j.K = p->K;
+        j.D = p->D;
+        j.scale = (float)(kPi / (double)p->K);
+        j.T = L.T;
+        j.fast3 = L.fast3 ? 1 : 0;
+        j.pad = L.pad;
+        j.pitch = L.pitch;
+    }
     const size_t is = (size_t)p->N * p->N, qs = (size_t)p->K * p->D;
     if (ps.recorded) FBP_TRY_HIP(hipStreamWaitEvent(s, ps.free_ev, 0));
     for (int32_t i0 = 0; i0 < n_slices; i0 += ps.slices) {
         const int n = std::min<int32_t>(ps.slices, n_slices - i0);
-        j.sino = d_sino + (size_t)i0 * qs;
         hipError_t e = launch_pad(d_image + (size_t)i0 * is, ps.ptr, p->N, L.pad, L.pitch, n, s);
-        if (e == hipSuccess) e = launch_project(j, n, s);
-        if (e != hipSuccess)
-            return e == hipErrorInvalidValue ? FBP_EUNSUPPORTED : hip_status(e, "projector kernel launch");
+        if (e == hipSuccess) {
+            if (fan) {
+                fj.sino = d_sino + (size_t)i0 * qs;
+                e = launch_fan_project(fj, n, s);
+            } else {
+                j.sino = d_sino + (size_t)i0 * qs;
+                e = launch_project(j, n, s);
+            }
+        }
+        if (e != hipSuccess) {
+            const int frc = e == hipErrorInvalidValue ? FBP_EUNSUPPORTED : hip_status(e, "projector kernel launch");
+            // work queued by earlier rounds still reads the copies: later users wait for it
+            return i0 > 0 ? fail_after_queued(frc, ps.free_ev, &ps.recorded, s) : frc;
+        }
     }
     FBP_TRY_HIP(hipEventRecord(ps.free_ev, s));
     ps.recorded = true;

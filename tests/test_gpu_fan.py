@@ -155,12 +155,15 @@ def test_fan_scratch_is_ordered_across_streams():
             assert np.array_equal(outs[i].cpu().numpy(), ref[i]), (rep, i)
 
 
-def test_fan_geometry_is_refused_where_unsupported():
-    g = fbp.Geometry(30, 41, 24, 1.0, source_distance=40.0)
-    x = torch.zeros((1, 24, 24), device="cuda")
-    with pytest.raises(fbp.FbpError) as e:
-        fbp.fbp_project(g, x)
-    assert e.value.status == fbp.FBP_EUNSUPPORTED
+def test_fan_projector_refuses_what_its_window_bound_cannot_cover():
+    # a detector reaching the source distance ((D-1) dt / 2 >= R), and a source so
+    # close to the image that no margin bounds the ray spacing
+    for K, D, N, R in ((30, 81, 24, 40.0), (8, 61, 64, 46.0)):
+        g = fbp.Geometry(K, D, N, 1.0, source_distance=R)
+        x = torch.zeros((1, N, N), device="cuda")
+        with pytest.raises(fbp.FbpError) as e:
+            fbp.fbp_project(g, x)
+        assert e.value.status == fbp.FBP_EUNSUPPORTED
 
 
 def test_fan_jobs_in_a_mixed_batch():

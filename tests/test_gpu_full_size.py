@@ -1,15 +1,17 @@
 """GPU parity at the full workload sizes, on sampled slices the oracle recomputes.
 
 * 256-slice stack of 512^2 / 720 angles / 725 bins (the precision sweep), one
-  fbp_reconstruct call per precision: eight slices spread over the stack vs the
-  FP64 oracle (FP32 gated at the stated tolerance; BF16 and FP16 at floors a few
-  dB under their measured errors, which are printed).
+  fbp_reconstruct call per precision: every slice of the stack vs the FP64
+  oracle (FP32 gated at the stated tolerance; BF16 and FP16 at floors a few dB
+  under their measured errors; the worst slice of each mode is printed).
 * The 1000-slice mixed batch (one fbp_reconstruct_batch call, as the batch
-  benchmark runs it): one slice of every distinct geometry (side x angle count)
-  vs the oracle.
+  benchmark runs it): three slices of every distinct geometry (side x angle
+  count; its first, middle and last slice) vs the oracle.
 Sinograms are generated in HBM in FP64 by the input generator; the oracle gets
 the same FP64 values copied to the host.
 """
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 import torch
@@ -23,22 +25,33 @@ from paper_2109_02174_amd.batch_bench import build_jobs
 pytestmark = pytest.mark.gpu
 
 
-SAMPLE = (0, 37, 74, 97, 150, 201, 230, 255)
 MIN_PSNR = {"bf16": 45.0, "fp16": 60.0}
-_refs = {}
+CHUNK = 32   # slices per oracle call (host memory: 32 FP64 sinograms at a time)
 
 
 def _stack(n=256):
+    """The stack on the GPU (FP32), and per slice the FP64 oracle image and the
+    phantom's value range R."""
     g = configs.C3["geom"]
     geo = fbp.Geometry(g.K, g.D, g.N, g.dt, ph.uniform_angles(g.K))
-    sl, host = [], {}
-    for i in range(n):
-        ells = ph.draw_ellipses(ph.rng_for(3, i), 20)
-        s64 = ph.ellipse_sinogram_device(ells, g.N, g.D, g.dt, geo.angles)
-        if i in SAMPLE:
-            host[i] = (s64.cpu().numpy(), ph.rasterise(ells, g.N))
-        sl.append(s64.to(torch.float32))
-    return geo, torch.stack(sl).contiguous(), host
+    ells = [ph.draw_ellipses(ph.rng_for(3, i), 20) for i in range(n)]
+
+    def value_range(e):
+        raster = ph.rasterise(e, g.N)
+        return float(raster.max() - raster.min())
+
+    with ThreadPoolExecutor(max_workers=8) as pool:   # rasters beside the oracle calls
+        ranges = pool.map(value_range, ells)
+        sl, refs = [], []
+        for c0 in range(0, n, CHUNK):
+            host = []
+            for i in range(c0, min(n, c0 + CHUNK)):
+                s64 = ph.ellipse_sinogram_device(ells[i], g.N, g.D, g.dt, geo.angles)
+                host.append(s64.cpu().numpy())
+                sl.append(s64.to(torch.float32))
+            refs.extend(oracle.fbp(np.stack(host), geo.image_size, geo.det_spacing, geo.angles))
+        ranges = list(ranges)
+    return geo, torch.stack(sl).contiguous(), refs, ranges
 
 
 @pytest.fixture(scope="module")
@@ -47,31 +60,31 @@ def stack():
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
-def test_precision_sweep_stack_sampled_slices(stack, prec):
-    geo, sino, host = stack
-    out = fbp.fbp_reconstruct(geo, sino, precision=prec)
-    torch.cuda.synchronize()
-    for i, (s64, raster) in host.items():
-        if i not in _refs:
-            _refs[i] = oracle.fbp(s64, geo.image_size, geo.det_spacing, geo.angles)
-        R = float(raster.max() - raster.min())
-        m = metrics.compare(out[i].cpu().numpy(), _refs[i], R)
-        print(prec, i, m)
+def test_precision_sweep_stack_every_slice(stack, prec):
+    geo, sino, refs, ranges = stack
+    out = fbp.fbp_reconstruct(geo, sino, precision=prec).cpu().numpy()
+    worst = None
+    for i, (ref, R) in enumerate(zip(refs, ranges)):
+        m = metrics.compare(out[i], ref, R)
+        if worst is None or m["psnr_db"] < worst[1]["psnr_db"]:
+            worst = (i, m)
         if prec == "fp32":
-            assert m["max_abs_rel"] <= 2e-4 and m["rmse_rel"] <= 2e-5 and m["psnr_db"] >= 94
+            assert m["max_abs_rel"] <= 2e-4 and m["rmse_rel"] <= 2e-5 and m["psnr_db"] >= 94, (i, m)
             # regression gate: about three times the largest measured (5.0e-6 / 1.1e-6)
-            assert m["max_abs_rel"] <= 1.5e-5 and m["rmse_rel"] <= 3.3e-6, m
+            assert m["max_abs_rel"] <= 1.5e-5 and m["rmse_rel"] <= 3.3e-6, (i, m)
         else:
-            assert m["psnr_db"] >= MIN_PSNR[prec]
+            assert m["psnr_db"] >= MIN_PSNR[prec], (i, m)
+    print(prec, "worst slice", worst)
 
 
-def test_mixed_batch_full_size_one_slice_per_geometry():
+def test_mixed_batch_full_size_three_slices_per_geometry():
     geoms = configs.c4_geometries(1000)
-    first = {}
+    by_geom = {}
     for i, g in enumerate(geoms):
-        first.setdefault((g.N, g.K), i)
-    sample = set(first.values())
-    assert len(sample) == 12
+        by_geom.setdefault((g.N, g.K), []).append(i)
+    assert len(by_geom) == 12
+    sample = {ix[j] for ix in by_geom.values() for j in (0, len(ix) // 2, -1)}
+    assert len(sample) == 36
     jobs, _, host = build_jobs(1000, keep_host=sample)
     fbp.fbp_reconstruct_batch(jobs)
     torch.cuda.synchronize()

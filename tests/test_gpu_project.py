@@ -136,3 +136,86 @@ def test_stream_ordering_and_empty_call():
     assert np.array_equal(out.cpu().numpy(), ref)
     empty = fbp.fbp_project(g, torch.empty((0, 24, 24), device="cuda"))
     assert empty.shape == (0, 30, 41)
+
+
+# ---------------------------------------------------------------- fan beam
+
+def _fan_tol(x, N, K, R, T=9):
+    """Each term w x carries (R/L)^2 and a hat weight rounded a few times in FP32
+    (and an FP32 coordinate good to a few ulps of the window's extent); a lane adds
+    at most N * T terms in a fixed order.  256 FP32 ulps of the largest term each."""
+    wmax = (R / (R - math.sqrt(2.0) * 0.5 * N)) ** 2
+    return (2.0 * math.pi / K) * N * T * wmax * 256 * 2.0 ** -24 * float(np.max(np.abs(x))) + 1e-30
+
+
+def _fan_views(K, kind, seed):
+    if kind == "uniform":
+        return np.arange(K, dtype=np.float64) * (2.0 * math.pi / K)
+    return np.sort(ph.rng_for(1510, seed).uniform(0.0, 2.0 * math.pi, K))
+
+
+@pytest.mark.parametrize("K,D,N,dt,R,B,kind", [
+    (96, 61, 40, 1.0, 80.0, 1, "uniform"),
+    (40, 41, 33, 1.3, 45.0, 2, "random"),     # odd side, coarse bins, source close to the image
+    (64, 49, 32, 1.0, 60.0, 1, "uniform"),    # views on every octant boundary (rows/columns switch)
+    (25, 31, 17, 0.7, 30.0, 1, "random"),     # fine bins
+    (12, 13, 9, 1.0, 20.0, 3, "random"),
+    (5, 3, 1, 1.0, 4.0, 1, "random"),         # one pixel
+    (9, 1, 40, 1.0, 80.0, 1, "random"),       # one bin
+    (3, 300, 40, 0.25, 80.0, 1, "uniform"),   # more than one block of bins
+])
+def test_fan_projector_matches_oracle(K, D, N, dt, R, B, kind):
+    b = _fan_views(K, kind, K * D + N)
+    g = fbp.Geometry(K, D, N, dt, b, source_distance=R)
+    x = ph.rng_for(1511, K + N).normal(size=(B, N, N)).astype(np.float32)
+    got = fbp.fbp_project(g, torch.tensor(x, device="cuda")).cpu().numpy()
+    ref = oracle.fan_splat(x.astype(np.float64), K, D, dt, R, b)
+    assert got.shape == ref.shape
+    err = np.max(np.abs(got - ref))
+    assert err <= _fan_tol(x, N, K, R), err
+
+
+@pytest.mark.parametrize("K,D,N,R,B", [(720, 801, 512, 1024.0, 1), (360, 401, 256, 400.0, 2)])
+def test_fan_adjoint_identity_with_the_backprojector(K, D, N, R, B):
+    """<P x, y> = <x, P^T y> with the fan-beam projector and backprojector on the GPU."""
+    g = fbp.Geometry(K, D, N, 1.0, source_distance=R)
+    rng = ph.rng_for(1512, N)
+    x = torch.tensor(rng.normal(size=(B, N, N)).astype(np.float32), device="cuda")
+    y = torch.tensor(rng.normal(size=(B, K, D)).astype(np.float32), device="cuda")
+    px = fbp.fbp_project(g, x).double()
+    bty = fbp.fbp_backproject(g, y).double()
+    for bb in range(B):
+        lhs = float(torch.sum(px[bb] * y[bb].double()))
+        rhs = float(torch.sum(x[bb].double() * bty[bb]))
+        scale = float(torch.sum(torch.abs(px[bb]) * torch.abs(y[bb].double())))
+        assert abs(lhs - rhs) <= 1e-5 * scale, (bb, lhs, rhs)
+
+
+def test_fan_full_size_sampled_views_match_oracle():
+    """512x512 image, 720 views over a full turn, 801 bins, R = 1024: a sample of
+    views near every octant boundary, each computed by the oracle as a one-view
+    projection (its weight 2 pi / 1 rescaled to 2 pi / 720)."""
+    K, D, N, R = 720, 801, 512, 1024.0
+    b = _fan_views(K, "uniform", 0)
+    g = fbp.Geometry(K, D, N, 1.0, b, source_distance=R)
+    sl = ph.ellipse_slice(1513, 0, N, 8, 725, 1.0, n_ellipses=20)
+    x = sl.phantom.astype(np.float32)[None]
+    got = fbp.fbp_project(g, torch.tensor(x, device="cuda")).cpu().numpy()[0]
+    for k in (0, 1, 89, 90, 91, 180, 269, 270, 450, 719):
+        ref = oracle.fan_splat(x[0].astype(np.float64), 1, D, 1.0, R, b[k:k + 1])[0] / K
+        assert np.max(np.abs(got[k] - ref)) <= _fan_tol(x, N, K, R), k
+
+
+def test_fan_projection_repeats_bitwise_and_orders_across_streams():
+    K, D, N, R = 90, 101, 64, 120.0
+    g = fbp.Geometry(K, D, N, 1.0, source_distance=R)
+    x = torch.tensor(ph.rng_for(1514, 0).normal(size=(3, N, N)).astype(np.float32), device="cuda")
+    ref = fbp.fbp_project(g, x).cpu().numpy()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for i, st in enumerate((s1, s2, s1)):
+        with torch.cuda.stream(st):
+            outs.append(fbp.fbp_project(g, x[i:i + 1].contiguous(), stream=st))
+    torch.cuda.synchronize()
+    for i in range(3):
+        assert np.array_equal(outs[i].cpu().numpy()[0], ref[i]), i
