@@ -240,7 +240,9 @@ def test_fan_beam_entry_points(lib):
     ang = (ctypes.c_double * 4)(0.0, 1.5, 3.0, 4.5)
     g = B.c_geom(4, 9, 5, 1.0, ang, 0, 0, 10.0)
     gp = ctypes.byref(g)
-    assert lib.fbp_project(gp, 1, FAKE, FAKE2, None) == B.FBP_EUNSUPPORTED
+    # the projector takes fan geometries (its refusals need the plan, made on a GPU)
+    assert lib.fbp_project(gp, 0, None, None, None) == B.FBP_OK
+    assert lib.fbp_project(gp, 1, FAKE, FAKE + 4, None) == B.FBP_EINVAL
     assert lib.fbp_plan_config(gp) == B.FBP_EUNSUPPORTED
     assert lib.fbp_plan_stack_config(gp) == B.FBP_EUNSUPPORTED
     assert lib.fbp_backproject_with_config(gp, 1, FAKE, FAKE2, 0, None) == B.FBP_EUNSUPPORTED
