@@ -200,6 +200,8 @@ int fbp_reconstruct(const fbp_geom* geom, int32_t n_slices, const float* d_sino,
  * Every call on one GPU uses that GPU's one array and leaves its contents
  * there: calls whose work can overlap on the device (unordered streams, other
  * threads) race on it and give wrong images.  Order them on one stream.
+ * The first call on each GPU looks up the array's device address
+ * (hipGetSymbolAddress, no allocation); make that call before capturing a graph.
  */
 int fbp_reconstruct_noalloc(const fbp_geom* geom, int32_t n_slices, const float* d_sino, float* d_image,
                             int32_t precision, void* hip_stream);
