@@ -130,16 +130,18 @@ class Geometry:
 
     def as_c(self) -> c_geom:
         """The C struct (cached; the angle array is kept alive with it)."""
-        key = (int(self.n_angles), int(self.n_det), int(self.image_size), float(self.det_spacing),
-               self.angles.ctypes.data, self.filter, self.weighting, float(self.source_distance))
+        # keyed by the angle array object: the cached struct keeps a reference to it,
+        # so numpy refuses to reallocate its buffer in place while the cache holds it
+        key = (self.n_angles, self.n_det, self.image_size, self.det_spacing, id(self.angles), self.filter,
+               self.weighting, self.source_distance)
         cached = getattr(self, "_c_cache", None)
         if cached is not None and cached[0] == key:
             return cached[1]
-        g = c_geom(key[0], key[1], key[2], key[3],
+        g = c_geom(int(key[0]), int(key[1]), int(key[2]), float(key[3]),
                    self.angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                    FILTERS.get(self.filter, -1) if isinstance(self.filter, str) else int(self.filter),
                    WEIGHTINGS.get(self.weighting, -1) if isinstance(self.weighting, str) else int(self.weighting),
-                   key[7])
+                   float(key[7]))
         g._keep = self.angles
         self._c_cache = (key, g)
         return g

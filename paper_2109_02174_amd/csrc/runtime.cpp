@@ -603,10 +603,36 @@ ProjLayout fan_project_layout(const Plan& p) {
     return L;
 }
 
+bool plan_matches(const Plan& p, const fbp_geom* g) {
+    return p.K == g->n_angles && p.D == g->n_det && p.N == g->image_size && angles_equal(p, g);
+}
+
+// The plan this thread found last, on its device: found again without hashing the
+// angle list when the next call passes the same geometry (every field and every
+// angle compared).  Plans live until process exit, so the pointer stays valid.
+struct LastPlan {
+    int device = -1;
+    Plan* plan = nullptr;
+};
+thread_local LastPlan t_last_plan;
+
+int get_plan_slow(int device, const fbp_geom* g, Plan** out);
+
 // Look up or create the plan of a validated geometry on the current device.
 int get_plan(const fbp_geom* g, Plan** out) {
     int device = 0;
     FBP_TRY_HIP(hipGetDevice(&device));
+    if (t_last_plan.plan && t_last_plan.device == device && plan_matches(*t_last_plan.plan, g)) {
+        *out = t_last_plan.plan;
+        return FBP_OK;
+    }
+    const int rc = get_plan_slow(device, g, out);
+    if (rc == FBP_OK) t_last_plan = LastPlan{device, *out};
+    return rc;
+}
+
+// Look up or create the plan (registry under its lock).
+int get_plan_slow(int device, const fbp_geom* g, Plan** out) {
     const GeomKey key = make_key(device, g);
     Registry& R = registry();
     std::lock_guard<std::mutex> lock(R.mu);
