@@ -86,16 +86,20 @@ def recorded_traffic(kernel: str):
 def time_launches(fn, stream, n: int) -> float:
     """Average device duration (ms) of n back-to-back launches of fn on `stream`.
 
-    A long blocker kernel is queued first so that all n launches are enqueued before
-    the first one starts: the events then see device time, not host launch gaps.
+    Blocker GEMMs are queued first, enough to outlast the host's enqueueing of all n
+    launches (about 20 us of host time each, and a 4096^3 GEMM takes about 0.9 ms),
+    so that every launch is queued before the first one starts: the events then see
+    device time, not host launch gaps, also for kernels shorter than a launch's
+    host time.
     """
     import torch
     blocker = torch.empty((4096, 4096), device="cuda")
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    n_block = max(2, math.ceil(n * 20e-6 / 0.8e-3))
     with torch.cuda.stream(stream):
-        for _ in range(2):
-            blocker = blocker @ blocker.T   # ~ms of work ahead of the timed launches
+        for _ in range(n_block):
+            blocker = blocker @ blocker.T   # device work ahead of the timed launches
         e0.record(stream)
         for _ in range(n):
             fn()
