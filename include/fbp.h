@@ -42,8 +42,10 @@
  *
  * Determinism: every output value is written once, by one GPU thread (no
  * atomics), and every call is bitwise reproducible.  For parallel-beam
- * geometries with even N whose angles come in quarter-turn pairs
- * (theta_{k+K/2} = theta_k + pi/2, as every uniform list with even K) the tile
+ * geometries with N >= 2 whose angles come in quarter-turn pairs
+ * (theta_{k+K/2} = theta_k + pi/2, as every uniform list with even K) and whose
+ * detector spacing is above about 0.36 pixel (a 16 x 16 tile's ray window
+ * within 64 bins) the tile
  * shape and the summation order depend on the geometry alone: a slice
  * reconstructed alone, in a stack or inside a batch gives bitwise-equal images,
  * whatever the autotuner chose.  Other geometries may run single slices, stacks

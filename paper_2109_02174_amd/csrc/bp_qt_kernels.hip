@@ -2,12 +2,14 @@
 //
 // Computes Eq. 2 of arXiv 2109.02174 (section "Computed tomography") with the
 // pi/K weight (or per-angle weights) and linear interpolation, for angle lists
-// closed under +pi/2 (theta_{k+K/2} = theta_k + pi/2) and even N:
+// closed under +pi/2 (theta_{k+K/2} = theta_k + pi/2) and N >= 2:
 //     img[r][c] = w * sum_k Q~_k(u_k),  u_k = (x_c cos th_k + y_r sin th_k)/dt + (D-1)/2.
 //
 // Design:
 //  * A workgroup of 16 waves owns a 16 x 16 tile T of the top-left image quadrant
-//    and its three 90-degree turns (1024 pixels).  Rotating a pixel by +90 degrees
+//    and its three 90-degree turns (1024 pixels).  The quadrant is rows [0, N/2)
+//    by columns [0, (N+1)/2): for odd N a pinwheel piece, whose four turns cover
+//    every pixel but the centre, which the slice's first tile adds on its own.  Rotating a pixel by +90 degrees
 //    and its angle by +pi/2 leaves the ray coordinate unchanged, so for an angle
 //    pair (theta, theta + pi/2) the four turned copies of a pixel need two local
 //    coordinates, U (the tile) and V (its turn), for eight updates.
@@ -390,14 +392,34 @@ __device__ __forceinline__ void qt_run(Next next, char* smem) {
         float sum = 0.0f;
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) sum += src[w * 4 * kTileH * kPartPitch];
-        const int r = cur.tl.r0 + ty, c = cur.tl.c0 + tx, half = N >> 1;
-        if (e < kTile * kTileH && r < half && c < half) {
+        // the base region: rows [0, N/2), columns [0, (N+1)/2) (for odd N a pinwheel
+        // quadrant: its four turns cover every pixel but the centre)
+        const int r = cur.tl.r0 + ty, c = cur.tl.c0 + tx;
+        if (e < kTile * kTileH && r < (N >> 1) && c < ((N + 1) >> 1)) {
             size_t o;
             if (turn == 0) o = (size_t)r * N + c;
             else if (turn == 1) o = (size_t)c * N + (N - 1 - r);
             else if (turn == 2) o = (size_t)(N - 1 - r) * N + (N - 1 - c);
             else o = (size_t)(N - 1 - c) * N + r;
             cur.tl.img[o] = sum * cur.tl.scale;
+        }
+        // odd N: the centre pixel (x = y = 0, so u = (D-1)/2 on every angle), summed by
+        // wave 0 of the workgroup that owns the slice's first tile over all K angles in
+        // a fixed order (lane l takes angles l, l + 64, ...; then a fixed butterfly)
+        if ((N & 1) && cur.tl.r0 == 0 && cur.tl.c0 == 0 && wave == 0) {
+            const int D = cur.tl.D, K = cur.tl.K, jc = (D - 1) >> 1;
+            const bool between = (D & 1) == 0;          // (D-1)/2 midway between bins jc and jc + 1
+            const float* __restrict__ wsc = cur.tl.wscale;
+            float csum = 0.0f;
+            for (int k = lane; k < K; k += 64) {
+                const float* __restrict__ row = cur.tl.q + (size_t)k * D;
+                float v = between ? 0.5f * (row[jc] + row[jc + 1]) : row[jc];
+                if (WSM != 0 && wsc) v *= wsc[k];
+                csum += v;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) csum += __shfl_xor(csum, o);
+            if (lane == 0) cur.tl.img[(size_t)(N >> 1) * N + (N >> 1)] = csum * cur.tl.scale;
         }
         if (!more) break;
         cur = nxt;

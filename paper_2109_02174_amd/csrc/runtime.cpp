@@ -288,10 +288,11 @@ bool shape_params(int cfg, const std::vector<double>& cs, const std::vector<doub
     sp->KBm = 0;
     const int waves = kGroupThreads * s.s / 64;
     if (s.rot == 2) {
-        // chunked quarter-turn shape: even N, angles in quarter-turn pairs, and a
-        // window that fits this id's pitch (one bin short of it: the staging pairs
-        // each bin with the next lane's)
-        if ((N & 1) || !quarter_turn_symmetric(angles)) return false;
+        // chunked quarter-turn shape: N >= 2 (odd N: pinwheel quadrants and the
+        // centre pixel), angles in quarter-turn pairs, and a window that fits this
+        // id's pitch (one bin short of it: the staging pairs each bin with the next
+        // lane's)
+        if (N < 2 || !quarter_turn_symmetric(angles)) return false;
         double span = 0.0;   // the tile and its turn: (W-1)|c| + (H-1)|s| and (W-1)|s| + (H-1)|c|
         for (size_t k = 0; 2 * k + 1 < cs.size(); ++k) {
             const double c = std::fabs(cs[2 * k]), sn = std::fabs(cs[2 * k + 1]);
@@ -304,9 +305,8 @@ bool shape_params(int cfg, const std::vector<double>& cs, const std::vector<doub
         sp->WL = pitch;
         sp->KB = qt_block_pairs(pitch);
         sp->seg_shift = 0;
-        const int half = N / 2;
-        sp->tiles_x = (half + kQtTile - 1) / kQtTile;
-        sp->tiles_y = (half + kQtTileH - 1) / kQtTileH;
+        sp->tiles_x = ((N + 1) / 2 + kQtTile - 1) / kQtTile;     // base region: (N+1)/2 columns,
+        sp->tiles_y = (N / 2 + kQtTileH - 1) / kQtTileH;         // N/2 rows
         return true;
     }
     if (s.rot) {
@@ -371,16 +371,16 @@ bool shape_params(int cfg, const std::vector<double>& cs, const std::vector<doub
 }
 
 // Shape of a single slice without tuning (measured on MI355X): the one-group
-// shapes split their angles over workgroups; the quarter-turn ones need even N
-// and angles closed under +pi/2.
+// shapes split their angles over workgroups; the chunked quarter-turn ones need
+// N >= 2 and angles closed under +pi/2.
 int default_config(int N, bool quarter_turn) {
-    if (quarter_turn && (N & 1) == 0) return kQtCfg32;
+    if (quarter_turn && N >= 2) return kQtCfg32;
     if (N >= 1024) return 2;
     if (N >= 192) return 4;
     return 7;
 }
 int default_stack_config(int N, bool quarter_turn) {
-    if (quarter_turn && (N & 1) == 0) return kQtCfg32;
+    if (quarter_turn && N >= 2) return kQtCfg32;
     return N >= 256 ? 2 : 5;
 }
 

@@ -18,7 +18,7 @@ long queue waits for bounded batches rather than for one batch holding
 everything admitted before it; up to n_streams bounded batches run at once.
 
 Every image equals the image the same request gets alone: bitwise for
-quarter-turn geometries (even N, angles closed under +pi/2), whose tile shape
+quarter-turn geometries (N >= 2, angles closed under +pi/2), whose tile shape
 and summation order depend on the geometry alone, and within the FP32 tolerance
 otherwise, where a geometry with 4 or more slices in a batch takes its stack
 shape and a shorter run its single-slice shape (see include/fbp.h).

@@ -54,6 +54,9 @@ GEOMS = [
     (2, 3, 2, 1.0, "uniform", 1),         # smallest quarter-turn case
     (4, 7, 2, 1.0, "uniform", 1),         # quarter-turn, one pixel per quadrant, two angle pairs
     (8, 33, 34, 1.0, "uniform", 2),       # quarter-turn, quadrant of 17 (one full and one 1-wide tile)
+    (90, 101, 71, 1.0, "uniform", 2),     # quarter-turn, odd N: pinwheel quadrants and the centre pixel
+    (4, 7, 3, 1.0, "uniform", 1),         # quarter-turn, odd N, a 1 x 2 base region
+    (4, 5, 1, 1.0, "uniform", 1),         # quarter-turn angles, one pixel (no quarter-turn shape)
     (50, 101, 70, 1.0, "random", 9),      # stacks: two 4-slice groups and one single slice
     (24, 230, 48, 0.35, "uniform", 5),    # stacks with windows over 63 bins (two staging segments)
 ]
@@ -80,7 +83,8 @@ def test_backprojection_matches_oracle_every_tile_shape(geom):
         try:
             fbp.fbp_backproject_with_config(g, q, cfg, out=out)
         except fbp.FbpError as e:
-            # quadrant-rotation shapes need even N and quarter-turn symmetric angles
+            # quadrant-rotation shapes need quarter-turn symmetric angles (and, but
+            # for the chunked ones, even N)
             assert e.status == fbp.FBP_EUNSUPPORTED and "rotations" in fbp.fbp_tile_config_name(cfg)
             continue
         ran.append(cfg)
@@ -88,9 +92,12 @@ def test_backprojection_matches_oracle_every_tile_shape(geom):
         assert np.all(np.isfinite(got)), f"tile {cfg}: pixel left unwritten"
         err = np.max(np.abs(got - ref))
         assert err <= tol, f"tile {cfg}: max err {err:.3e} > {tol:.3e}"
-    rot_ok = N % 2 == 0 and kind == "uniform" and K % 2 == 0
-    n_rot = sum("rotations" in fbp.fbp_tile_config_name(c) for c in ran)
-    assert (n_rot > 0) == rot_ok
+    qt_angles = kind == "uniform" and K % 2 == 0
+    names = [fbp.fbp_tile_config_name(c) for c in ran]
+    n_rot = sum("rotations" in n and "angle chunks" not in n for n in names)
+    assert (n_rot > 0) == (qt_angles and N % 2 == 0)
+    if qt_angles and N >= 2 and int(15 * math.sqrt(2.0) / dt) + 5 <= 31:
+        assert any("angle chunks" in n for n in names)   # odd N included
     out = fbp.fbp_backproject(g, q)
     assert np.max(np.abs(host(out) - ref)) <= tol
 

@@ -45,6 +45,12 @@ def pitch_for(K, N, dt, angles):
     return 0
 
 
+def tile_grid(N):
+    """Quadrant tiles across and down: the base region is rows [0, N/2) by columns
+    [0, (N+1)/2) (a pinwheel piece for odd N)."""
+    return ((N + 1) // 2 + TILE - 1) // TILE, (N // 2 + TILE - 1) // TILE
+
+
 def replay(K, D, N, dt, angles, WP=None):
     """Pitch, and the smallest and largest bin read over every tile, pair and pixel."""
     WP = pitch_for(K, N, dt, angles) if WP is None else WP
@@ -52,11 +58,9 @@ def replay(K, D, N, dt, angles, WP=None):
     KH = K // 2
     cd = np.cos(angles[:KH]) / dt
     sd = np.sin(angles[:KH]) / dt
-    half = N // 2
-    tiles = (half + TILE - 1) // TILE
+    tiles_x, tiles_y = tile_grid(N)
     hp, cdet = 0.5 * (N - 1), 0.5 * (D - 1)
-    t0 = np.arange(tiles) * TILE
-    c0, r0 = [a.ravel() for a in np.meshgrid(t0, t0, indexing="xy")]
+    c0, r0 = [a.ravel() for a in np.meshgrid(np.arange(tiles_x) * TILE, np.arange(tiles_y) * TILE, indexing="xy")]
     x0 = (c0 - hp)[:, None]
     y0 = (r0 - hp)[:, None]
     uo = x0 * cd + y0 * sd + cdet
@@ -91,10 +95,17 @@ def _uniform(K):
     (2, 3, 2, 1.0), (90, 101, 70, 1.0), (180, 183, 128, 1.0), (40, 75, 50, 0.7), (4, 9, 100, 1.0),
     (720, 725, 512, 1.0), (360, 365, 256, 1.0), (1440, 546, 384, 1.0), (720, 1451, 1024, 1.0),
     (30, 101, 64, 0.36),
+    # odd sides: pinwheel quadrants
+    (2, 3, 3, 1.0), (90, 101, 71, 1.0), (180, 183, 127, 1.0), (720, 725, 511, 1.0), (40, 75, 49, 0.7),
+    (4, 7, 35, 1.3),
 ])
 def test_qt_reads_stay_in_the_staged_window(K, D, N, dt):
     WP, lo, hi = replay(K, D, N, dt, _uniform(K))
-    assert lo >= 1          # the window starts one bin below the tile's smallest coordinate
+    # the window starts one bin below the tile's smallest coordinate, so exact
+    # coordinates are >= 1; where that coordinate is an integer (pixel centres on
+    # whole offsets, as for odd sides) FP32 rounding can leave it just below 1,
+    # and bin 0 (staged) is read
+    assert lo >= 0
     assert hi <= WP - 2
     # the host's bound leaves two bins of margin above the largest bin read
     assert hi <= WP - 4
@@ -183,3 +194,59 @@ def test_list_kernel_visits_every_tile_once():
                     seen.append(it)
                     it += G
             assert sorted(seen) == list(range(total))
+
+
+def epilogue_writes(N):
+    """Image offsets the epilogue writes for every tile of one slice: thread t of
+    1024 takes turn t / 256 and tile element t % 256 (rows along tiles for turns 0
+    and 2, columns for 1 and 3), writes when its base pixel lies in the base region,
+    and for odd N the first tile's wave 0 also writes the centre pixel."""
+    tiles_x, tiles_y = tile_grid(N)
+    out = []
+    for ty_t in range(tiles_y):
+        for tx_t in range(tiles_x):
+            r0, c0 = ty_t * TILE, tx_t * TILE
+            for t in range(1024):
+                turn, e = t >> 8, t & 255
+                ty = (e % TILE) if (turn & 1) else (e // TILE)
+                tx = (e // TILE) if (turn & 1) else (e % TILE)
+                r, c = r0 + ty, c0 + tx
+                if r < (N >> 1) and c < ((N + 1) >> 1):
+                    if turn == 0:
+                        o = r * N + c
+                    elif turn == 1:
+                        o = c * N + (N - 1 - r)
+                    elif turn == 2:
+                        o = (N - 1 - r) * N + (N - 1 - c)
+                    else:
+                        o = (N - 1 - c) * N + r
+                    out.append(o)
+            if (N & 1) and r0 == 0 and c0 == 0:
+                out.append((N >> 1) * N + (N >> 1))
+    return out
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 16, 17, 31, 32, 33, 34, 35, 63, 64, 71, 127, 128, 255])
+def test_every_pixel_written_exactly_once(N):
+    """The four turns of the base region (a pinwheel piece for odd N) plus, for odd
+    N, the centre pixel written by the first tile, cover the N x N image once."""
+    writes = epilogue_writes(N)
+    assert sorted(writes) == list(range(N * N))
+
+
+def test_turn_of_a_pixel_keeps_its_ray_coordinate():
+    """Turning a pixel by +90 degrees about the centre (x, y) -> (-y, x), as the
+    epilogue's index map does for (r, c) -> (c, N-1-r), with its angle turned by
+    pi/2 leaves u unchanged: the identity the kernel builds on, for odd N too."""
+    rng = np.random.default_rng(7)
+    for N in (5, 6, 33):
+        h = 0.5 * (N - 1)
+        for _ in range(50):
+            r, c = int(rng.integers(0, N)), int(rng.integers(0, N))
+            th = rng.uniform(0, math.pi)
+            x, y = c - h, r - h
+            r1, c1 = c, N - 1 - r                     # turned pixel's row and column
+            x1, y1 = c1 - h, r1 - h
+            u0 = x * math.cos(th) + y * math.sin(th)
+            u1 = x1 * math.cos(th + math.pi / 2) + y1 * math.sin(th + math.pi / 2)
+            assert abs(u0 - u1) < 1e-9
