@@ -188,31 +188,36 @@ __global__ __launch_bounds__(kFanThreads) void fan_bp_kernel(FanJob job) {
 // Quarter-turn views (K = 4 K4, b_{k + i K4} = b_k + i pi/2): turning a pixel by
 // +pi/2 about the centre, (x, y) -> (-y, x), and its view by +pi/2 leaves the
 // depth L and the detector coordinate s unchanged.  A workgroup owns a 16 x 16
-// tile of the top-left quadrant and its three turned copies R_j (j = 1..3).  Per
+// tile of the base region (rows [0, N/2), columns [0, (N+1)/2): the top-left
+// quadrant, or for odd N a pinwheel piece whose four turns cover every pixel but
+// the centre) and its three turned copies R_j (j = 1..3).  Per
 // base view k < K4 a lane makes its pixel's maps at the four views k + m K4
 // (m = 0..3) and applies map m to R_j X at view k + ((m + j) mod 4) K4 for every
 // j: sixteen updates per four maps.  The four windows of map m (one per j, all
 // at map m's origin) are interleaved two pairs per float4 plane, so 2M reads at
 // the map's window index fetch the pairs of the four turned pixels (times M
 // slices).  Each output pixel sums its views in a fixed order (base views
-// ascending, then m).
+// ascending, then m).  Odd N: the centre pixel has depth R and detector
+// coordinate (D-1)/2 on every view (weight 1); the workgroup of the first tile
+// sums it from the filtered rows after its tile (lanes over views, then a fixed
+// butterfly).
 template <int M>
 __global__ __launch_bounds__(kFanThreads) void fan_rot_kernel(FanJob job) {
     extern __shared__ __align__(16) char smem[];
     const int KB = job.KB, WL = job.WL, N = job.N, K = job.K, D = job.D;
-    const int K4 = K / 4, H = N / 2;
+    const int K4 = K / 4, H = N / 2, Wc = (N + 1) / 2;   // base region: H rows, Wc columns
     float* coef = reinterpret_cast<float*>(smem);                      // [KB][4 maps][8]
     int* org = reinterpret_cast<int*>(coef + 32 * KB);                 // [KB][4 maps] window origins
     // [KB][4 maps][2M planes][WL] float4: plane h holds pairs 2h, 2h+1 of the
     // (turn j, slice) list j M + slice, so lanes at consecutive bins read 16-byte strides
     float4* win = reinterpret_cast<float4*>(org + 4 * KB);
-    const int tiles = job.tiles_x * job.tiles_x;                       // quadrant tiles
+    const int tiles = job.tiles_x * ((H + kFanTile - 1) / kFanTile);   // base-region tiles
     const int g = blockIdx.x / tiles;                                  // group of M slices, or view part
     const int tile = blockIdx.x - g * tiles;
     const int c0 = (tile % job.tiles_x) * kFanTile, r0 = (tile / job.tiles_x) * kFanTile;
     const int dx = threadIdx.x & (kFanTile - 1), dy = threadIdx.x / kFanTile;
-    const bool inside = c0 + dx < H && r0 + dy < H;
-    const int cw = min(kFanTile, H - c0), rh = min(kFanTile, H - r0);   // pixels of the tile in the quadrant
+    const bool inside = c0 + dx < Wc && r0 + dy < H;
+    const int cw = min(kFanTile, Wc - c0), rh = min(kFanTile, H - r0);  // pixels of the tile in the base region
     const float fdx = (float)dx, fdy = (float)dy;
     const size_t qstride = (size_t)K * D;
     // split > 1 (one slice, M = 1): this workgroup sums the base views of part g only
@@ -349,6 +354,26 @@ __global__ __launch_bounds__(kFanThreads) void fan_rot_kernel(FanJob job) {
             }
         }
     }
+    if ((N & 1) && tile == 0 && threadIdx.x < 64) {
+        const int lane = threadIdx.x, jc = (D - 1) >> 1, nv = 4 * (kend - kbeg);
+        const bool between = (D & 1) == 0;            // (D-1)/2 midway between bins jc and jc + 1
+        const size_t pix = (size_t)(N >> 1) * N + (N >> 1);
+#pragma unroll
+        for (int mm = 0; mm < M; ++mm) {
+            const float* __restrict__ qm = qs + mm * qstride;
+            float csum = 0.0f;
+            for (int t = lane; t < nv; t += 64) {     // view kbeg + t / 4 + (t % 4) K4
+                const float* __restrict__ row = qm + (size_t)(kbeg + (t >> 2) + (t & 3) * K4) * D;
+                csum += between ? 0.5f * (row[jc] + row[jc + 1]) : row[jc];
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) csum += __shfl_xor(csum, o);
+            if (lane == 0) {
+                if (job.split > 1) job.part[(size_t)g * N * N + pix] = csum;
+                else job.img[((size_t)g * M + mm) * N * N + pix] = csum * job.scale;
+            }
+        }
+    }
 }
 
 }  // namespace
@@ -369,16 +394,16 @@ size_t fan_rot_lds_bytes(int KB, int WL, int M) {
            sizeof(float) * 2 * 16 * (size_t)M * (size_t)KB * (size_t)WL;
 }
 
-// Quarter-turn form (even N, K = 4 K4 with the views in quarter turns, K D 4 bytes
+// Quarter-turn form (N >= 2, K = 4 K4 with the views in quarter turns, K D 4 bytes
 // addressable by a buffer resource): groups of M slices, the rest one slice per
 // workgroup; a single slice may split its base views over job.split parts.
 hipError_t launch_fan_rot(const FanJob& job, int n_slices, int M, int KBm, hipStream_t stream) {
     if (n_slices <= 0) return hipSuccess;
-    if ((job.N & 1) || (job.K & 3) || job.K < 4 || job.KB < 1 || 4 * job.KB > kFanThreads || job.WL < 2 ||
+    if (job.N < 2 || (job.K & 3) || job.K < 4 || job.KB < 1 || 4 * job.KB > kFanThreads || job.WL < 2 ||
         (M != 1 && M != 2 && M != 4) || (M > 1 && (KBm < 1 || 4 * KBm > kFanThreads)) ||
-        !fan_rot_addressable(job.K, job.D, job.WL) || job.tiles_x != (job.N / 2 + kFanTile - 1) / kFanTile)
+        !fan_rot_addressable(job.K, job.D, job.WL) || job.tiles_x != ((job.N + 1) / 2 + kFanTile - 1) / kFanTile)
         return hipErrorInvalidValue;
-    const int64_t tiles = (int64_t)job.tiles_x * job.tiles_x;
+    const int64_t tiles = (int64_t)job.tiles_x * ((job.N / 2 + kFanTile - 1) / kFanTile);
     const int grouped = (M > 1) ? n_slices - n_slices % M : 0;
     if (grouped > 0) {
         FanJob j = job;

@@ -243,7 +243,7 @@ struct FanJob {
     int32_t N, K, D;
     int32_t WL;           // window pairs staged per view (bound over tiles and views)
     int32_t KB;           // views per staged block
-    int32_t tiles_x;      // ceil(N / kFanTile); quarter-turn form: ceil(N/2 / kFanTile)
+    int32_t tiles_x;      // ceil(N / kFanTile); quarter-turn form: ceil(((N+1)/2) / kFanTile)
     float scale;          // 2 pi / K
     float* part;          // split > 1: [split][N][N] partial sums (one slice, M = 1)
     int32_t split;        // view parts of a single slice (1: none)
@@ -254,9 +254,11 @@ size_t fan_lds_bytes(int KB, int WL, int M);
 // n_slices through the M-slice kernel (M = 2 or 4, KBm views per block) in groups,
 // the remainder (and everything when M = 1) one slice per workgroup.
 hipError_t launch_fan_bp(const FanJob& job, int n_slices, int M, int KBm, hipStream_t stream);
-// Quarter-turn form (even N; K = 4 K4 with view k + i K4 at angle b_k + i pi/2):
-// a workgroup owns a tile of the top-left quadrant (tiles_x = ceil(N/2 / kFanTile))
-// and its three turned copies; KB (KBm for the M-slice groups) base views per block.
+// Quarter-turn form (N >= 2; K = 4 K4 with view k + i K4 at angle b_k + i pi/2):
+// a workgroup owns a tile of the base region, rows [0, N/2) by columns [0, (N+1)/2)
+// (tiles_x = ceil(((N+1)/2) / kFanTile), ceil((N/2) / kFanTile) tiles down), and its
+// three turned copies, plus, for odd N, the first tile the centre pixel; KB (KBm for
+// the M-slice groups) base views per block.
 bool fan_rot_addressable(int K, int D, int WL);
 size_t fan_rot_lds_bytes(int KB, int WL, int M);
 hipError_t launch_fan_rot(const FanJob& job, int n_slices, int M, int KBm, hipStream_t stream);

@@ -505,9 +505,9 @@ int make_fan_plan(Plan* p) {
     p->fan_KB = (int)std::min<size_t>(64, (kFanLdsBudget - 64 * 36) / (8 * (size_t)p->fan_WL));
     if (p->fan_KB < 1) return FBP_EUNSUPPORTED;
     p->fan_KB4 = (int)std::min<size_t>(16, (kFanLdsBudget - 64 * 36) / (4 * 8 * (size_t)p->fan_WL));
-    // quarter-turn form when the views come in quarter turns (N even): base views
+    // quarter-turn form when the views come in quarter turns (N >= 2): base views
     // per block for one slice, and the largest stack group whose block fits
-    p->fan_rot = (p->N % 2 == 0) && fan_quarter_turns(p->angles) && fan_rot_addressable(p->K, p->D, p->fan_WL);
+    p->fan_rot = p->N >= 2 && fan_quarter_turns(p->angles) && fan_rot_addressable(p->K, p->D, p->fan_WL);
     if (p->fan_rot) {
         p->fan_rot_KB = (int)std::min<size_t>(64, kFanRotLds / fan_rot_lds_bytes(1, p->fan_WL, 1));
         p->fan_rot = p->fan_rot_KB >= 1;
@@ -522,8 +522,9 @@ int make_fan_plan(Plan* p) {
     }
     // single slices: views (base views) split over enough parts for about 16
     // workgroups per CU, partial sums in planes owned by the plan (images up to 2048^2)
-    const int tx = p->fan_rot ? (p->N / 2 + kFanTile - 1) / kFanTile : (p->N + kFanTile - 1) / kFanTile;
-    const int tiles = tx * tx;
+    const int tx = p->fan_rot ? ((p->N + 1) / 2 + kFanTile - 1) / kFanTile : (p->N + kFanTile - 1) / kFanTile;
+    const int ty = p->fan_rot ? (p->N / 2 + kFanTile - 1) / kFanTile : tx;
+    const int tiles = tx * ty;
     const int cus = cu_count(p->device);
     const int per_cu = p->fan_rot ? kFanRotWgsPerCu : 16;
     p->fan_split = std::max(1, std::min({kMaxSplit, p->fan_rot ? p->K / 4 : p->K, (per_cu * cus + tiles / 2) / tiles}));
@@ -1030,7 +1031,7 @@ int run_fan_backproject(Plan& p, int32_t n, const float* filt, float* img, hipSt
     j.D = p.D;
     j.WL = p.fan_WL;
     j.KB = p.fan_KB;
-    j.tiles_x = p.fan_rot ? (p.N / 2 + kFanTile - 1) / kFanTile : (p.N + kFanTile - 1) / kFanTile;
+    j.tiles_x = p.fan_rot ? ((p.N + 1) / 2 + kFanTile - 1) / kFanTile : (p.N + kFanTile - 1) / kFanTile;
     j.scale = (float)(2.0 * kPi / (double)p.K);
     j.part = nullptr;
     j.split = 1;

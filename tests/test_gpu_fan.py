@@ -59,6 +59,9 @@ def test_fan_filter_matches_oracle(kind, K, D, dt, R, B):
     (120, 129, 70, 1.0, 1.6, 1, "turn"),        # quarter turns: quadrant tiles and their turns, ragged quadrant
     (84, 161, 46, 0.8, 1.3, 6, "turn"),         # quarter turns, stack: a group of slices per workgroup and two single
     (8, 95, 34, 1.0, 2.0, 3, "turn"),           # quarter turns, two base views, three slices one by one
+    (120, 129, 71, 1.0, 1.6, 1, "turn"),        # quarter turns, odd side: pinwheel tiles and the centre pixel
+    (84, 160, 45, 0.8, 1.3, 6, "turn"),         # odd side, stack groups and single slices, even D
+    (8, 95, 35, 1.0, 2.0, 3, "turn"),           # odd side, two base views
 ])
 def test_fan_backprojection_matches_oracle(K, D, N, dt, Rf, B, kind):
     R = Rf * N / math.sqrt(2.0)
@@ -218,12 +221,13 @@ def test_fan_quarter_turn_form_matches_general_form():
 
 def test_fan_degenerate_sizes():
     """Zero slices are a no-op; the smallest images (one pixel; two pixels, the
-    smallest quarter-turn quadrant) and a one-bin detector agree with the oracle."""
+    smallest quarter-turn quadrant; three pixels, the smallest odd pinwheel) and a
+    one-bin detector agree with the oracle."""
     g = fbp.Geometry(8, 5, 4, 1.0, source_distance=6.0)
     for fn, shape in ((fbp.fbp_filter, (0, 8, 5)), (fbp.fbp_backproject, (0, 4, 4)), (fbp.fbp_reconstruct, (0, 4, 4))):
         assert fn(g, torch.zeros((0, 8, 5), device="cuda")).shape == shape
     for K, D, N, kind in ((4, 3, 1, "turn"), (4, 5, 2, "turn"), (8, 5, 2, "turn"), (12, 1, 2, "turn"),
-                          (5, 4, 2, "random")):
+                          (5, 4, 2, "random"), (4, 3, 3, "turn"), (8, 4, 3, "turn"), (12, 1, 5, "turn")):
         R = 3.0 + N
         b = _views(K, kind, K + D + N)
         g = fbp.Geometry(K, D, N, 1.0, b, source_distance=R)

@@ -250,3 +250,34 @@ def test_turn_of_a_pixel_keeps_its_ray_coordinate():
             u0 = x * math.cos(th) + y * math.sin(th)
             u1 = x1 * math.cos(th + math.pi / 2) + y1 * math.sin(th + math.pi / 2)
             assert abs(u0 - u1) < 1e-9
+
+
+def fan_turn_writes(N, split=1):
+    """Image offsets (and partial planes) the fan-beam quarter-turn kernel writes:
+    a 256-thread workgroup per (part, base-region tile), thread (dx, dy) of the
+    tile writing its pixel's four turns when the pixel lies in rows [0, N/2) and
+    columns [0, (N+1)/2); for odd N the first tile also writes the centre."""
+    TF = 16
+    tiles_x, tiles_y = ((N + 1) // 2 + TF - 1) // TF, (N // 2 + TF - 1) // TF
+    tiles = tiles_x * tiles_y
+    out = []
+    for b in range(tiles * split):
+        g, tile = divmod(b, tiles)
+        c0, r0 = (tile % tiles_x) * TF, (tile // tiles_x) * TF
+        for t in range(256):
+            dx, dy = t & 15, t >> 4
+            c, r = c0 + dx, r0 + dy
+            if c < (N + 1) // 2 and r < N // 2:
+                for rj, cj in ((r, c), (c, N - 1 - r), (N - 1 - r, N - 1 - c), (N - 1 - c, r)):
+                    out.append(g * N * N + rj * N + cj)
+        if (N & 1) and tile == 0:
+            out.append(g * N * N + (N // 2) * N + N // 2)
+    return out
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 17, 33, 34, 45, 70, 71, 255])
+@pytest.mark.parametrize("split", [1, 3])
+def test_fan_turn_kernel_writes_every_pixel_once(N, split):
+    """Every pixel of every partial plane (or of the image) is written exactly once
+    by the fan-beam quarter-turn kernel's epilogue and centre step."""
+    assert sorted(fan_turn_writes(N, split)) == list(range(split * N * N))
